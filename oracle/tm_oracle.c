@@ -1,0 +1,522 @@
+/*
+ * tm_oracle.c -- plain, slow CPU FP64 oracle for the truncated-solver-method
+ * (TSM) evaluation of disconnected quark loops with twisted-mass Wilson
+ * fermions (Alexandrou et al., "Evaluation of disconnected contributions
+ * using GPUs", Lattice 2012, arXiv:1211.0126).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header, table or constant with the
+ * GPU library.  Every routine is the plain definition written out: full 4x4
+ * gamma matrices, full 3x3 links, direct phase sums, serial reductions.  The
+ * only parallelism is an OpenMP loop over sites in the hopping term, where
+ * every site is written by exactly one thread, so results do not depend on
+ * the thread count.
+ *
+ * Conventions (readings of points the paper leaves open):
+ *  - site = x + Lx*(y + Ly*(z + Lz*t)); direction mu = 0..3 is x, y, z, t.
+ *  - spinor component index 3*spin + colour, complex128 interleaved.
+ *  - link U_mu(x) is stored at [site][mu][row][col]; it multiplies psi(x+mu).
+ *  - time boundary: a hop across t = Lt-1 <-> 0 carries the factor t_bc
+ *    (-1 antiperiodic); space is periodic.
+ *  - Euclidean chiral gamma basis, gamma_5 = gamma_1 gamma_2 gamma_3 gamma_4
+ *    = diag(1, 1, -1, -1); Gamma_n = g1^b0 g2^b1 g3^b2 g4^b3 for
+ *    n = b0 + 2 b1 + 4 b2 + 8 b3 (Gamma_0 = 1, Gamma_15 = gamma_5).
+ *  - hopping normalisation: M = 1 - kappa*H + 2i*kappa*mu*gamma_5 with
+ *    H psi(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu)
+ *                    + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu).
+ *    This is 2*kappa times the physical M_u = D_W + i*mu*a*gamma_5 of the
+ *    flavour identity M_u - M_d = 2i*mu*a*gamma_5 (section 2.3).
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define NSPIN 4
+#define NCOL 3
+#define NCOMP 12
+
+/* ------------------------------------------------------------------ */
+/* threads                                                             */
+/* ------------------------------------------------------------------ */
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_get_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* geometry                                                            */
+/* ------------------------------------------------------------------ */
+
+static long volume(const int *L) { return (long)L[0] * L[1] * L[2] * L[3]; }
+
+static void site_coords(const int *L, long s, int c[4])
+{
+    c[0] = (int)(s % L[0]); s /= L[0];
+    c[1] = (int)(s % L[1]); s /= L[1];
+    c[2] = (int)(s % L[2]); s /= L[2];
+    c[3] = (int)s;
+}
+
+static long site_of(const int *L, const int c[4])
+{
+    return c[0] + (long)L[0] * (c[1] + (long)L[1] * (c[2] + (long)L[2] * c[3]));
+}
+
+/* neighbour of s one step in direction mu, forward (dir=+1) or backward
+   (dir=-1); *phase receives t_bc when the hop wraps in time, else 1 */
+static long neighbour(const int *L, int t_bc, long s, int mu, int dir, double *phase)
+{
+    int c[4];
+    site_coords(L, s, c);
+    *phase = 1.0;
+    c[mu] += dir;
+    if (c[mu] == L[mu]) { c[mu] = 0; if (mu == 3) *phase = (double)t_bc; }
+    if (c[mu] < 0) { c[mu] = L[mu] - 1; if (mu == 3) *phase = (double)t_bc; }
+    return site_of(L, c);
+}
+
+/* ------------------------------------------------------------------ */
+/* gamma matrices                                                      */
+/* ------------------------------------------------------------------ */
+
+/* Euclidean chiral basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]],
+   gamma_4 = [[0, 1], [1, 0]] in 2x2 blocks. */
+static void gamma_mu(int mu, cplx g[4][4])
+{
+    memset(g, 0, sizeof(cplx) * 16);
+    switch (mu) {
+    case 0: g[0][3] = -I; g[1][2] = -I; g[2][1] = I; g[3][0] = I; break;
+    case 1: g[0][3] = -1; g[1][2] = 1; g[2][1] = 1; g[3][0] = -1; break;
+    case 2: g[0][2] = -I; g[1][3] = I; g[2][0] = I; g[3][1] = -I; break;
+    default: g[0][2] = 1; g[1][3] = 1; g[2][0] = 1; g[3][1] = 1; break;
+    }
+}
+
+static void matmul4(const cplx a[4][4], const cplx b[4][4], cplx c[4][4])
+{
+    cplx t[4][4];
+    for (int i = 0; i < 4; i++)
+        for (int j = 0; j < 4; j++) {
+            cplx acc = 0;
+            for (int k = 0; k < 4; k++) acc += a[i][k] * b[k][j];
+            t[i][j] = acc;
+        }
+    memcpy(c, t, sizeof(t));
+}
+
+/* Gamma_n = g1^b0 g2^b1 g3^b2 g4^b3, written into out[16] (row-major 4x4) */
+void orc_gamma(int n, double *out)
+{
+    cplx r[4][4], g[4][4];
+    memset(r, 0, sizeof(r));
+    for (int i = 0; i < 4; i++) r[i][i] = 1;
+    for (int mu = 0; mu < 4; mu++)
+        if ((n >> mu) & 1) { gamma_mu(mu, g); matmul4(r, g, r); }
+    memcpy(out, r, sizeof(r));
+}
+
+/* gamma_mu for mu = 0..3 and gamma_5 for mu = 4 */
+void orc_gamma_mu(int mu, double *out)
+{
+    cplx g[4][4];
+    if (mu < 4) gamma_mu(mu, g);
+    else orc_gamma(15, (double *)g);
+    memcpy(out, g, sizeof(g));
+}
+
+static void gamma5(cplx g[4][4]) { orc_gamma(15, (double *)g); }
+
+/* ------------------------------------------------------------------ */
+/* Z4 noise (Eq. 1): counter-based splitmix64                          */
+/* ------------------------------------------------------------------ */
+
+/* splitmix64 output function (Steele, Lea & Flood, OOPSLA 2014) */
+static uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* sequential splitmix64: advance the state by the golden-ratio increment and
+   return the mixed state; exported so tests can pin it to published values */
+uint64_t orc_splitmix64_next(uint64_t *state)
+{
+    *state += 0x9E3779B97F4A7C15ULL;
+    return mix64(*state);
+}
+
+/* 64-bit hash for source id j at site s: output number 1 + j*V + s of a
+   splitmix64 stream started at state mix64(seed) */
+uint64_t orc_noise_hash(uint64_t seed, uint64_t j, uint64_t vol, uint64_t s)
+{
+    uint64_t z = mix64(seed) + 0x9E3779B97F4A7C15ULL * (1 + j * vol + s);
+    return mix64(z);
+}
+
+/* Z4 codes k_c in {0,1,2,3} for every component: eta = i^k */
+void orc_noise_codes(const int *L, uint64_t seed, uint64_t j, uint8_t *codes)
+{
+    long V = volume(L);
+    for (long s = 0; s < V; s++) {
+        uint64_t h = orc_noise_hash(seed, j, (uint64_t)V, (uint64_t)s);
+        for (int c = 0; c < NCOMP; c++) codes[s * NCOMP + c] = (uint8_t)((h >> (2 * c)) & 3);
+    }
+}
+
+/* the Z4 source eta_j itself, complex128 [V][4][3] */
+void orc_noise_z4(const int *L, uint64_t seed, uint64_t j, double *eta_out)
+{
+    static const cplx z4[4] = {1.0, I, -1.0, -I};
+    cplx *eta = (cplx *)eta_out;
+    long V = volume(L);
+    for (long s = 0; s < V; s++) {
+        uint64_t h = orc_noise_hash(seed, j, (uint64_t)V, (uint64_t)s);
+        for (int c = 0; c < NCOMP; c++) eta[s * NCOMP + c] = z4[(h >> (2 * c)) & 3];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* the operator                                                        */
+/* ------------------------------------------------------------------ */
+
+/* H (dagger = 0) or its adjoint H^dag (dagger = 1).  The adjoint follows
+   from transposing the hop: (1 + g_mu) U_mu(x) psi(x+mu) +
+   (1 - g_mu) U_mu(x-mu)^dag psi(x-mu). */
+static void hop(const int *L, int t_bc, const cplx *U, const cplx *in, cplx *out, int dagger)
+{
+    long V = volume(L);
+    cplx gm[4][4][4];
+    for (int mu = 0; mu < 4; mu++) gamma_mu(mu, gm[mu]);
+
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        cplx acc[NSPIN][NCOL];
+        memset(acc, 0, sizeof(acc));
+        for (int mu = 0; mu < 4; mu++) {
+            for (int dir = -1; dir <= 1; dir += 2) {
+                double ph;
+                long y = neighbour(L, t_bc, s, mu, dir, &ph);
+                /* colour-transported neighbour, per spin */
+                cplx v[NSPIN][NCOL];
+                for (int a = 0; a < NSPIN; a++)
+                    for (int i = 0; i < NCOL; i++) {
+                        cplx t = 0;
+                        for (int k = 0; k < NCOL; k++) {
+                            cplx u;
+                            if (dir > 0) u = U[((s * 4 + mu) * 3 + i) * 3 + k];
+                            else u = conj(U[((y * 4 + mu) * 3 + k) * 3 + i]);
+                            t += u * in[y * NCOMP + a * NCOL + k];
+                        }
+                        v[a][i] = ph * t;
+                    }
+                /* spin projector 1 - sgn*gamma_mu, sgn = +1 for the forward
+                   hop of H and the backward hop of H^dag */
+                double sgn = (dir > 0) ? 1.0 : -1.0;
+                if (dagger) sgn = -sgn;
+                for (int a = 0; a < NSPIN; a++)
+                    for (int b = 0; b < NSPIN; b++) {
+                        cplx p = (a == b ? 1.0 : 0.0) - sgn * gm[mu][a][b];
+                        if (p == 0) continue;
+                        for (int i = 0; i < NCOL; i++) acc[a][i] += p * v[b][i];
+                    }
+            }
+        }
+        for (int a = 0; a < NSPIN; a++)
+            for (int i = 0; i < NCOL; i++) out[s * NCOMP + a * NCOL + i] = acc[a][i];
+    }
+}
+
+/* M (op 0), M^dag (op 1), M^dag M (op 2), H (op 3) */
+enum { ORC_M = 0, ORC_MDAG = 1, ORC_MDAGM = 2, ORC_HOP = 3 };
+
+static void apply_m(const int *L, int t_bc, double kappa, double mu, const cplx *U,
+                    const cplx *in, cplx *out, int dagger)
+{
+    long V = volume(L);
+    cplx g5[4][4];
+    gamma5(g5);
+    hop(L, t_bc, U, in, out, dagger);
+    /* twisted mass term +2i kappa mu gamma_5 (its adjoint has the minus sign) */
+    cplx tm = (dagger ? -1.0 : 1.0) * 2.0 * I * kappa * mu;
+    for (long s = 0; s < V; s++)
+        for (int a = 0; a < NSPIN; a++)
+            for (int i = 0; i < NCOL; i++) {
+                cplx g5psi = 0;
+                for (int b = 0; b < NSPIN; b++) g5psi += g5[a][b] * in[s * NCOMP + b * NCOL + i];
+                long k = s * NCOMP + a * NCOL + i;
+                out[k] = in[k] - kappa * out[k] + tm * g5psi;
+            }
+}
+
+void orc_apply(const int *L, int t_bc, double kappa, double mu, int op,
+               const double *U_, const double *in_, double *out_)
+{
+    const cplx *U = (const cplx *)U_;
+    const cplx *in = (const cplx *)in_;
+    cplx *out = (cplx *)out_;
+    long n = volume(L) * NCOMP;
+    switch (op) {
+    case ORC_M: apply_m(L, t_bc, kappa, mu, U, in, out, 0); break;
+    case ORC_MDAG: apply_m(L, t_bc, kappa, mu, U, in, out, 1); break;
+    case ORC_MDAGM: {
+        cplx *tmp = malloc(sizeof(cplx) * n);
+        apply_m(L, t_bc, kappa, mu, U, in, tmp, 0);
+        apply_m(L, t_bc, kappa, mu, U, tmp, out, 1);
+        free(tmp);
+        break;
+    }
+    default: hop(L, t_bc, U, in, out, 0); break;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* CG on the normal equations (the inverter of section 2.2)           */
+/* ------------------------------------------------------------------ */
+
+static double norm2(const cplx *a, long n)
+{
+    double s = 0;
+    for (long i = 0; i < n; i++) s += creal(a[i]) * creal(a[i]) + cimag(a[i]) * cimag(a[i]);
+    return s;
+}
+
+enum { ORC_STOP_NORMAL = 0, ORC_STOP_TRUE = 1 };
+
+/*
+ * Solve M s = eta through M^dag M s = M^dag eta by conjugate gradients from
+ * s = 0.  Stop (checked before every iteration) when the relative residual
+ * is <= tol or when maxit iterations are done (maxit < 0: no cap).  The
+ * residual is that of the normal equations (stop = 0) or the recursively
+ * tracked residual eta - M s of the original system (stop = 1).  These are
+ * the two truncation criteria of section 2.2 (a residual or a fixed number
+ * of iterations).
+ *
+ * stats[0] iterations, [1] final normal-equation relative residual,
+ * [2] true relative residual |eta - M s|/|eta| computed directly,
+ * [3] 1 if stopped by the tolerance, [4] 1 if stopped by the iteration cap.
+ */
+int orc_cgnr(const int *L, int t_bc, double kappa, double mu, const double *U_,
+             const double *eta_, double tol, int maxit, int stop,
+             double *x_, double *stats)
+{
+    const cplx *U = (const cplx *)U_;
+    const cplx *eta = (const cplx *)eta_;
+    cplx *x = (cplx *)x_;
+    long n = volume(L) * NCOMP;
+    cplx *b = malloc(sizeof(cplx) * n), *r = malloc(sizeof(cplx) * n);
+    cplx *p = malloc(sizeof(cplx) * n), *t = malloc(sizeof(cplx) * n);
+    cplx *q = malloc(sizeof(cplx) * n), *rho = malloc(sizeof(cplx) * n);
+
+    apply_m(L, t_bc, kappa, mu, U, eta, b, 1);
+    for (long i = 0; i < n; i++) { x[i] = 0; r[i] = b[i]; p[i] = b[i]; rho[i] = eta[i]; }
+    double rr = norm2(r, n), bb = rr, ee = norm2(eta, n), rhorho = ee;
+    int it = 0, conv = 0, trunc = 0;
+    for (;;) {
+        double rel = (stop == ORC_STOP_TRUE) ? sqrt(rhorho / ee) : sqrt(rr / bb);
+        if (rel <= tol) { conv = 1; break; }
+        if (maxit >= 0 && it >= maxit) { trunc = 1; break; }
+        apply_m(L, t_bc, kappa, mu, U, p, t, 0);
+        double tt = norm2(t, n);
+        double alpha = rr / tt;
+        for (long i = 0; i < n; i++) x[i] += alpha * p[i];
+        if (stop == ORC_STOP_TRUE) {
+            for (long i = 0; i < n; i++) rho[i] -= alpha * t[i];
+            rhorho = norm2(rho, n);
+        }
+        apply_m(L, t_bc, kappa, mu, U, t, q, 1);
+        for (long i = 0; i < n; i++) r[i] -= alpha * q[i];
+        double rr_new = norm2(r, n);
+        double beta = rr_new / rr;
+        for (long i = 0; i < n; i++) p[i] = r[i] + beta * p[i];
+        rr = rr_new;
+        it++;
+    }
+    if (stats) {
+        apply_m(L, t_bc, kappa, mu, U, x, t, 0);
+        for (long i = 0; i < n; i++) t[i] = eta[i] - t[i];
+        stats[0] = it;
+        stats[1] = sqrt(rr / bb);
+        stats[2] = sqrt(norm2(t, n) / ee);
+        stats[3] = conv;
+        stats[4] = trunc;
+    }
+    free(b); free(r); free(p); free(t); free(q); free(rho);
+    return it;
+}
+
+/* ------------------------------------------------------------------ */
+/* loops: <eta^dag Gamma s> per timeslice and momentum (section 2.3)   */
+/* ------------------------------------------------------------------ */
+
+/*
+ * out[n][m][t] += sum over sites x with time t of
+ *     exp(-i p_m . x) * sum_{a,b,c} conj(eta(x)_{a c}) Gamma_n[a][b] s(x)_{b c}
+ * with p_m = 2 pi (mom[m][0]/Lx, mom[m][1]/Ly, mom[m][2]/Lz).  The sum runs
+ * over all sites of each timeslice (the Fourier transform of the paper is
+ * this sum at the chosen momenta).  out is complex128 [16][n_mom][Lt] and is
+ * accumulated into, not cleared.
+ */
+void orc_loops(const int *L, const double *eta_, const double *s_, int n_mom,
+               const int *mom, double *out_)
+{
+    const cplx *eta = (const cplx *)eta_;
+    const cplx *sv = (const cplx *)s_;
+    cplx *out = (cplx *)out_;
+    long V = volume(L);
+    int Lt = L[3];
+    cplx G[16][4][4];
+    for (int n = 0; n < 16; n++) orc_gamma(n, (double *)G[n]);
+    const double twopi = 2.0 * acos(-1.0);
+    for (long s = 0; s < V; s++) {
+        int c[4];
+        site_coords(L, s, c);
+        cplx tr[16];
+        for (int n = 0; n < 16; n++) {
+            cplx acc = 0;
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) {
+                    if (G[n][a][b] == 0) continue;
+                    for (int k = 0; k < NCOL; k++)
+                        acc += conj(eta[s * NCOMP + a * NCOL + k]) * G[n][a][b] * sv[s * NCOMP + b * NCOL + k];
+                }
+            tr[n] = acc;
+        }
+        for (int m = 0; m < n_mom; m++) {
+            double arg = twopi * ((double)mom[3 * m] * c[0] / L[0] + (double)mom[3 * m + 1] * c[1] / L[1] +
+                                  (double)mom[3 * m + 2] * c[2] / L[2]);
+            cplx ph = cexp(-I * arg);
+            for (int n = 0; n < 16; n++) out[((long)n * n_mom + m) * Lt + c[3]] += ph * tr[n];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* TSM estimator (Eq. 4)                                               */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Eq. 4 applied to the loops:
+ *   C = (1/N_HP) sum_{j in HP} [L(s_j^HP) - L(s_j^LP)]    (correction)
+ *   B = (1/N_LP) sum_{j in LP} L(s_j^LP)                  (biased estimate)
+ *   T = C + B
+ * HP ids are 0..n_hp-1 and LP ids n_hp..n_hp+n_lp-1 (disjoint sets, n_lp of
+ * them: the paper's count of N_HP + N_LP low-precision inversions).  The LP
+ * solves of the HP set use exactly the LP solver settings.  An empty set
+ * contributes zero.
+ *
+ * out: complex128 [3][16][n_mom][Lt] (C, B, T).
+ * err (nullable): same shape; re/im hold the standard errors of the real and
+ *   imaginary parts from the per-source spread (sample variance / N; a set
+ *   with a single source contributes zero).  err_T^2 = err_C^2 + err_B^2.
+ * per_src (nullable): complex128 [n_hp+n_lp][2][16][n_mom][Lt]: slot 0 the
+ *   LP loops, slot 1 the HP loops (zero for LP ids).
+ * src_stats (nullable): double [n_hp+n_lp][2][5] CG stats (slot 0 LP, 1 HP).
+ */
+int orc_tsm(const int *L, int t_bc, double kappa, double mu, const double *U,
+            uint64_t seed, int n_hp, int n_lp,
+            double lp_tol, int lp_maxit, int lp_stop,
+            double hp_tol, int hp_maxit, int hp_stop,
+            int n_mom, const int *mom,
+            double *out_, double *err_, double *per_src_, double *src_stats)
+{
+    long V = volume(L);
+    long n = V * NCOMP;
+    int Lt = L[3];
+    long nl = 16L * n_mom * Lt;
+    cplx *out = (cplx *)out_;
+    cplx *err = (cplx *)err_;
+    cplx *per_src = (cplx *)per_src_;
+    cplx *eta = malloc(sizeof(cplx) * n), *s = malloc(sizeof(cplx) * n);
+    cplx *l_lp = malloc(sizeof(cplx) * nl), *l_hp = malloc(sizeof(cplx) * nl);
+    cplx *sumC = calloc(nl, sizeof(cplx)), *sumB = calloc(nl, sizeof(cplx));
+    /* per-source values kept for the spread */
+    cplx *dC = calloc((size_t)(n_hp > 0 ? n_hp : 1) * nl, sizeof(cplx));
+    cplx *dB = calloc((size_t)(n_lp > 0 ? n_lp : 1) * nl, sizeof(cplx));
+    double st[5];
+
+    for (int j = 0; j < n_hp + n_lp; j++) {
+        int is_hp = j < n_hp;
+        orc_noise_z4(L, seed, (uint64_t)j, (double *)eta);
+        orc_cgnr(L, t_bc, kappa, mu, U, (double *)eta, lp_tol, lp_maxit, lp_stop, (double *)s, st);
+        if (src_stats) memcpy(src_stats + (j * 2 + 0) * 5, st, sizeof(st));
+        memset(l_lp, 0, sizeof(cplx) * nl);
+        orc_loops(L, (double *)eta, (double *)s, n_mom, mom, (double *)l_lp);
+        memset(l_hp, 0, sizeof(cplx) * nl);
+        if (is_hp) {
+            orc_cgnr(L, t_bc, kappa, mu, U, (double *)eta, hp_tol, hp_maxit, hp_stop, (double *)s, st);
+            if (src_stats) memcpy(src_stats + (j * 2 + 1) * 5, st, sizeof(st));
+            orc_loops(L, (double *)eta, (double *)s, n_mom, mom, (double *)l_hp);
+            for (long k = 0; k < nl; k++) {
+                cplx d = l_hp[k] - l_lp[k];
+                sumC[k] += d;
+                dC[(long)j * nl + k] = d;
+            }
+        } else {
+            if (src_stats) memset(src_stats + (j * 2 + 1) * 5, 0, sizeof(st));
+            for (long k = 0; k < nl; k++) {
+                sumB[k] += l_lp[k];
+                dB[(long)(j - n_hp) * nl + k] = l_lp[k];
+            }
+        }
+        if (per_src) {
+            memcpy(per_src + ((long)j * 2 + 0) * nl, l_lp, sizeof(cplx) * nl);
+            memcpy(per_src + ((long)j * 2 + 1) * nl, l_hp, sizeof(cplx) * nl);
+        }
+    }
+    for (long k = 0; k < nl; k++) {
+        cplx C = n_hp > 0 ? sumC[k] / n_hp : 0;
+        cplx B = n_lp > 0 ? sumB[k] / n_lp : 0;
+        out[k] = C;
+        out[nl + k] = B;
+        out[2 * nl + k] = C + B;
+        if (err) {
+            double vcr = 0, vci = 0, vbr = 0, vbi = 0;
+            if (n_hp > 1) {
+                for (int j = 0; j < n_hp; j++) {
+                    cplx d = dC[(long)j * nl + k] - C;
+                    vcr += creal(d) * creal(d);
+                    vci += cimag(d) * cimag(d);
+                }
+                vcr /= (double)(n_hp - 1) * n_hp;
+                vci /= (double)(n_hp - 1) * n_hp;
+            }
+            if (n_lp > 1) {
+                for (int j = 0; j < n_lp; j++) {
+                    cplx d = dB[(long)j * nl + k] - B;
+                    vbr += creal(d) * creal(d);
+                    vbi += cimag(d) * cimag(d);
+                }
+                vbr /= (double)(n_lp - 1) * n_lp;
+                vbi /= (double)(n_lp - 1) * n_lp;
+            }
+            err[k] = sqrt(vcr) + I * sqrt(vci);
+            err[nl + k] = sqrt(vbr) + I * sqrt(vbi);
+            err[2 * nl + k] = sqrt(vcr + vbr) + I * sqrt(vci + vbi);
+        }
+    }
+    free(eta); free(s); free(l_lp); free(l_hp); free(sumC); free(sumB); free(dC); free(dB);
+    return 0;
+}
