@@ -1,0 +1,273 @@
+/*
+ * tmqcd.h -- C ABI of the MI355X (gfx950) library for the truncated solver
+ * method (TSM) evaluation of disconnected quark loops with twisted-mass
+ * Wilson fermions, after C. Alexandrou et al., "Evaluation of disconnected
+ * contributions using GPUs", Lattice 2012 (arXiv:1211.0126).
+ *
+ * The problem statement follows the paper: the operator M with kappa and
+ * mu (section 2.2, the twisted-mass lower bound; section 2.3, the flavour
+ * identity M_u - M_d = 2 i mu a gamma_5), N_HP and N_LP Z4 noise sources
+ * (Eq. 1, Eq. 4), truncation of the low-precision solves by a residual or a
+ * fixed number of iterations (section 2.2), and loops Tr(M^{-1} X) estimated
+ * as averages of <eta^dag X s> (section 2.3) for all 16 Dirac structures,
+ * per timeslice and momentum (section 3: loops for all insertion times,
+ * Fourier transformed).
+ *
+ * Conventions
+ *  - lattice dims[4] = (Lx, Ly, Lz, Lt), each >= 2; site index
+ *    x + Lx*(y + Ly*(z + Lz*t)); direction mu = 0..3 is x, y, z, t.
+ *  - spinor component index 3*spin + colour; canonical spinor layout
+ *    [rhs][site][spin][colour] complex, real and imaginary parts interleaved.
+ *  - canonical gauge layout complex128 [site][mu][row][col]; U_mu(x)
+ *    multiplies psi(x + mu).  No boundary sign is stored in the links.
+ *  - time boundary factor t_bc (-1 antiperiodic, +1 periodic) on hops across
+ *    t = Lt-1 <-> 0; space is periodic.
+ *  - Euclidean chiral gamma basis, gamma_5 = gamma_1 gamma_2 gamma_3 gamma_4
+ *    = diag(1, 1, -1, -1); Gamma_n = g1^b0 g2^b1 g3^b2 g4^b3 for
+ *    n = b0 + 2 b1 + 4 b2 + 8 b3.
+ *  - hopping normalisation: M = 1 - kappa H + 2 i kappa mu gamma_5, with
+ *    H psi(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu)
+ *                    + (1 + g_mu) U_mu(x-mu)^dag psi(x-mu);
+ *    M is 2 kappa times the physical M_u.  M^dag = 1 - kappa H^dag
+ *    - 2 i kappa mu gamma_5.
+ *  - noise: Z4 components eta = i^k, k = bits (2c, 2c+1) of
+ *    splitmix64mix(splitmix64mix(seed) + 0x9E3779B97F4A7C15 * (1 + id*V + site))
+ *    for component c; regenerated on the fly, never stored (section 3).
+ *  - loops: L_n(t, p) = sum_{x in timeslice t} exp(-i p.x)
+ *    sum_{a,b,c} conj(eta(x)_{a c}) Gamma_n[a][b] s(x)_{b c},
+ *    p = 2 pi (nx/Lx, ny/Ly, nz/Lz); layout [16][n_mom][Lt] complex128.
+ *
+ * Memory and threading
+ *  - "_dev" pointers are device memory owned by the caller (16-byte
+ *    aligned); "_host" pointers are host memory owned by the caller.  The
+ *    library keeps its own device workspace (gauge copies, solver vectors),
+ *    allocated on first use and released by tm_destroy.
+ *  - all work is enqueued on the HIP stream given to tm_create.  Calls that
+ *    return host results synchronise that stream; tm_dslash does not.
+ *  - a context is not thread-safe: one host thread per context.
+ *
+ * Errors
+ *  - every entry point returns tm_status: 0 success, > 0 warning, < 0 error.
+ *    Nothing throws or aborts across the ABI.  Outputs are undefined after an
+ *    error; tm_last_error gives the text.  TM_EDEVICE is sticky: destroy the
+ *    context.  Truncation of an LP solve by the iteration cap is not an error.
+ */
+#ifndef TMQCD_H
+#define TMQCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TM_ABI_VERSION 1
+
+typedef int32_t tm_status;
+enum {
+    TM_OK = 0,
+    TM_WARN_NOT_CONVERGED = 1, /* a solve with no iteration cap missed its tolerance */
+    TM_WARN_FALLBACK = 2,      /* the learned preconditioner fell back to plain CG */
+    TM_EINVAL = -1,            /* invalid argument */
+    TM_ENOMEM = -2,            /* device allocation failed */
+    TM_EDEVICE = -3,           /* HIP runtime error (sticky) */
+    TM_ESTATE = -4,            /* call out of order (e.g. no gauge field loaded) */
+    TM_ENOTSUP = -5            /* combination not supported */
+};
+
+/* storage precision of spinor fields; arithmetic is FP64 for TM_PREC_F64
+   and FP32 otherwise, inner products and norms are accumulated in FP64 */
+typedef enum { TM_PREC_F64 = 0, TM_PREC_F32 = 1, TM_PREC_F16 = 2, TM_PREC_BF16 = 3 } tm_prec;
+
+typedef enum {
+    TM_OP_M = 0,     /* M */
+    TM_OP_MDAG = 1,  /* M^dag */
+    TM_OP_MDAGM = 2, /* M^dag M */
+    TM_OP_HOP = 3    /* H (hopping term alone) */
+} tm_op;
+
+typedef enum {
+    TM_LAYOUT_CANONICAL = 0, /* [rhs][site][spin][colour] complex of the storage precision */
+    TM_LAYOUT_NATIVE = 1     /* the library's internal layout (opaque), see tm_field_bytes */
+} tm_layout;
+
+typedef enum {
+    TM_STOP_NORMAL = 0, /* |M^dag eta - M^dag M s| / |M^dag eta| <= tol (CG's own residual) */
+    TM_STOP_TRUE = 1    /* recursively tracked |eta - M s| / |eta| <= tol */
+} tm_stop;
+
+typedef enum {
+    TM_SOLVER_CG = 0,          /* conjugate gradients on M^dag M */
+    TM_SOLVER_FCG_LEARNED = 1  /* flexible CG preconditioned by the learned network */
+} tm_solver;
+
+typedef struct {
+    int32_t dims[4]; /* Lx, Ly, Lz, Lt, each >= 2 */
+    double kappa;    /* hopping parameter */
+    double mu;       /* twisted mass a*mu; the operator uses 2*kappa*mu */
+    int32_t t_bc;    /* -1 antiperiodic, +1 periodic in time */
+} tm_lattice;
+
+typedef struct tm_ctx tm_ctx;
+
+/* One solve configuration (the inverter of section 2.2). */
+typedef struct {
+    int32_t prec;       /* tm_prec: storage of the Krylov vectors */
+    int32_t solver;     /* tm_solver */
+    double tol;         /* relative residual target; 0 = run to max_iter */
+    int32_t max_iter;   /* iteration cap, -1 = none; 0 returns s = 0 */
+    int32_t stop;       /* tm_stop */
+    int32_t reliable;   /* 1: FP32 iterations with FP64 reliable updates (prec must be F32) */
+    double delta;       /* reliable-update trigger: |r| < delta * max |r| since the last update */
+    int32_t rhs_block;  /* sources per launch, 1..32; 0 = library default */
+    int32_t true_resid; /* 1: compute the FP64 true residual of every solve (one FP64 M) */
+} tsm_solve_params;
+
+/* Per-source solve record. */
+typedef struct {
+    int32_t iters;          /* CG iterations done */
+    int32_t converged;      /* 1 if stopped by the tolerance */
+    int32_t truncated;      /* 1 if stopped by the iteration cap */
+    int32_t fell_back;      /* 1 if the learned preconditioner was dropped */
+    double resid_iterated;  /* final relative residual of the stop criterion */
+    double resid_true;      /* FP64 |eta - M s| / |eta| */
+} tsm_solve_stats;
+
+typedef struct {
+    uint64_t seed;          /* noise seed; source ids are 0..n_hp+n_lp-1 */
+    int32_t n_hp;           /* sources solved to high and low precision (ids 0..n_hp-1) */
+    int32_t n_lp;           /* further sources solved to low precision only */
+    tsm_solve_params lp;    /* the LP solver, used for every LP solve of both sets */
+    tsm_solve_params hp;    /* the HP solver */
+    int32_t n_mom;          /* number of momenta (>= 1) */
+    const int32_t* mom_host;/* [n_mom][3] integer momenta n, p = 2 pi n / L */
+} tsm_params;
+
+typedef struct {
+    double ms_hp_phase;     /* wall time of the HP set (LP + HP solves, contractions) */
+    double ms_lp_phase;     /* wall time of the LP set */
+    int64_t lp_iters;       /* total LP CG iterations (both sets) */
+    int64_t hp_iters;       /* total HP CG iterations */
+    double max_lp_resid_true; /* largest FP64 true residual of an LP solve */
+    double max_hp_resid_true; /* largest FP64 true residual of an HP solve */
+    int32_t hp_not_converged; /* HP solves that missed their tolerance */
+    int32_t reserved;
+} tsm_run_stats;
+
+/* ---- lifecycle ---------------------------------------------------------- */
+
+/* ABI version (TM_ABI_VERSION). */
+int32_t tm_abi_version(void);
+
+/* Create a context for one lattice on the current HIP device.  hip_stream is
+   a hipStream_t (NULL: the null stream).  TM_EINVAL for dims < 2 or
+   lattices of 2^26 sites or more. */
+tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out);
+
+/* Release every device buffer and the context. */
+tm_status tm_destroy(tm_ctx* ctx);
+
+/* Text of the last error on this context (never NULL). */
+const char* tm_last_error(const tm_ctx* ctx);
+
+/* ---- gauge field -------------------------------------------------------- */
+
+/* Load the links (canonical complex128 [V][4][3][3], host, SU(3)).  The
+   library keeps an FP64 copy (full links) and an FP32 copy (two rows; the
+   third is rebuilt from unitarity).  Synchronous; the caller may free its
+   buffer on return.  Section 3 of the paper: one gauge configuration at a
+   time. */
+tm_status tm_gauge_load(tm_ctx* ctx, const double* links_host);
+
+/* ---- operator ----------------------------------------------------------- */
+
+/* Bytes of one field of nrhs spinors in the given precision and layout. */
+size_t tm_field_bytes(const tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t layout);
+
+/* Convert nrhs spinors between the canonical and native layouts of the same
+   precision (to_native = 1: canonical -> native).  Asynchronous. */
+tm_status tm_field_convert(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t to_native,
+                           const void* in_dev, void* out_dev);
+
+/* Apply op (tm_op) to nrhs spinors: out = op(in).  in/out are device
+   buffers in the given layout and storage precision (canonical complex128
+   for F64, complex64 for F32, pairs of binary16 / bfloat16 for F16 / BF16);
+   they must not overlap.  Arithmetic: FP64 for F64, FP32 otherwise.  The
+   operator is the one defined under Conventions (section 2.2/2.3).
+   Asynchronous. */
+tm_status tm_dslash(tm_ctx* ctx, int32_t op, int32_t prec, int32_t nrhs, int32_t layout,
+                    const void* in_dev, void* out_dev);
+
+/* ---- noise -------------------------------------------------------------- */
+
+/* Write the Z4 sources (Eq. 1) of the given ids as canonical complex128
+   [nsrc][V][4][3] into out_dev.  ids_host: nsrc source ids.  Asynchronous. */
+tm_status tm_noise_z4(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* ids_host, double* out_dev);
+
+/* ---- solves ------------------------------------------------------------- */
+
+/* Solve M s_j = eta_j (section 2.2) for the Z4 sources of the given ids with
+   CG on M^dag M from s = 0.  sol_dev (nullable) receives the solutions as
+   canonical complex128 [nsrc][V][4][3]; stats_host receives nsrc records.
+   Synchronous.  Returns TM_WARN_NOT_CONVERGED if a solve with max_iter = -1
+   stopped without reaching tol (cannot happen with an iteration cap). */
+tm_status tsm_solve_batch(tm_ctx* ctx, const tsm_solve_params* params, uint64_t seed, int32_t nsrc,
+                          const uint64_t* ids_host, double* sol_dev, tsm_solve_stats* stats_host);
+
+/* ---- loops -------------------------------------------------------------- */
+
+/* Contract given solutions with the regenerated sources of the given ids
+   (section 2.3, per timeslice and momentum).  sol_dev: canonical complex128
+   [nsrc][V][4][3] (device).  loops_host: complex128 [nsrc][16][n_mom][Lt].
+   Synchronous. */
+tm_status tsm_contract(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* ids_host,
+                       const double* sol_dev, int32_t n_mom, const int32_t* mom_host, double* loops_host);
+
+/* The whole TSM estimate of Eq. 4 for the loops:
+     C = (1/N_HP) sum_{j < N_HP} [L(s_j^HP) - L(s_j^LP)],
+     B = (1/N_LP) sum_{N_HP <= j < N_HP+N_LP} L(s_j^LP),   T = C + B,
+   with every LP solve (of both sets) done by params->lp and the HP solves by
+   params->hp.  An empty set contributes zero.
+   loops_host: complex128 [3][16][n_mom][Lt] (C, B, T).
+   err_host (nullable): same shape; real and imaginary parts are the
+     standard errors of the real and imaginary parts from the per-source
+     spread (sample variance / N; zero for a set of one source),
+     err_T^2 = err_C^2 + err_B^2.
+   per_source_host (nullable): complex128 [N_HP+N_LP][2][16][n_mom][Lt];
+     slot 0 the LP loops, slot 1 the HP loops (zero for LP-only ids).
+   stats_host (nullable): tsm_solve_stats [N_HP+N_LP][2] (slot 0 LP, 1 HP).
+   run_stats (nullable): timings and totals.
+   Synchronous.  Returns TM_WARN_NOT_CONVERGED if an HP solve missed its
+   tolerance. */
+tm_status tsm_loops(tm_ctx* ctx, const tsm_params* params, double* loops_host, double* err_host,
+                    double* per_source_host, tsm_solve_stats* stats_host, tsm_run_stats* run_stats);
+
+/* ---- instrumentation ---------------------------------------------------- */
+
+/* Kernel classes timed with HIP events on the context stream when profiling
+   is enabled. */
+enum {
+    TM_KC_DSLASH = 0,     /* t = M p (+ |t|^2): the CG operator application */
+    TM_KC_DSLASH_UPD = 1, /* q = M^dag t fused with x, r updates (+ |r|^2) */
+    TM_KC_BLAS = 2,       /* p = r + beta p */
+    TM_KC_CONTRACT = 3,   /* loop contraction */
+    TM_KC_OTHER = 4,      /* noise, initialisation, reliable updates, residuals */
+    TM_KC_APPLY = 5,      /* tm_dslash applications */
+    TM_KC_COUNT = 6
+};
+
+/* Enable (1) or disable (0) per-launch event timing; enabling clears the
+   accumulated figures. */
+tm_status tm_profile_enable(tm_ctx* ctx, int32_t on);
+
+/* Synchronise and read, per kernel class, the number of launches, the total
+   milliseconds and the total algorithmic bytes moved (array length
+   TM_KC_COUNT each; any pointer may be NULL). */
+tm_status tm_profile_read(tm_ctx* ctx, int64_t* launches, double* ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TMQCD_H */

@@ -1,0 +1,41 @@
+"""MI355X (gfx950) implementation of the truncated-solver-method evaluation
+of disconnected quark loops with twisted-mass Wilson fermions
+(Alexandrou et al., arXiv:1211.0126).
+
+The computation lives in the HIP library libtmqcd.so (C ABI in
+include/tmqcd.h); this package holds its sources (csrc/), the build script
+and a thin ctypes binding with the same entry-point names.
+"""
+
+from .binding import (  # noqa: F401
+    Context,
+    TmError,
+    load_library,
+    solve_params,
+    tm_abi_version,
+    tm_create,
+    tm_gauge_load,
+    tm_dslash,
+    tm_field_bytes,
+    tm_field_convert,
+    tm_noise_z4,
+    tsm_solve_batch,
+    tsm_contract,
+    tsm_loops,
+    tm_profile_enable,
+    tm_profile_read,
+    EXPORTS,
+    LIB_PATH,
+    PREC_F64,
+    PREC_F32,
+    PREC_F16,
+    PREC_BF16,
+    OP_M,
+    OP_MDAG,
+    OP_MDAGM,
+    OP_HOP,
+    LAYOUT_CANONICAL,
+    LAYOUT_NATIVE,
+    STOP_NORMAL,
+    STOP_TRUE,
+)

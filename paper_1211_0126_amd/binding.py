@@ -1,0 +1,276 @@
+"""Thin ctypes binding of libtmqcd.so (the C ABI in include/tmqcd.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  torch supplies device memory and the stream.  There is no CPU
+fallback: if the library is not built, loading it raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtmqcd.so")
+
+TM_OK, TM_WARN_NOT_CONVERGED, TM_WARN_FALLBACK = 0, 1, 2
+TM_EINVAL, TM_ENOMEM, TM_EDEVICE, TM_ESTATE, TM_ENOTSUP = -1, -2, -3, -4, -5
+PREC_F64, PREC_F32, PREC_F16, PREC_BF16 = 0, 1, 2, 3
+OP_M, OP_MDAG, OP_MDAGM, OP_HOP = 0, 1, 2, 3
+LAYOUT_CANONICAL, LAYOUT_NATIVE = 0, 1
+STOP_NORMAL, STOP_TRUE = 0, 1
+SOLVER_CG, SOLVER_FCG_LEARNED = 0, 1
+KC_NAMES = ["dslash", "dslash_upd", "blas", "contract", "other", "apply"]
+
+
+class TmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("tmqcd error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("kappa", ctypes.c_double), ("mu", ctypes.c_double),
+                ("t_bc", ctypes.c_int32)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("solver", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("stop", ctypes.c_int32), ("reliable", ctypes.c_int32),
+                ("delta", ctypes.c_double), ("rhs_block", ctypes.c_int32), ("true_resid", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("truncated", ctypes.c_int32),
+                ("fell_back", ctypes.c_int32), ("resid_iterated", ctypes.c_double), ("resid_true", ctypes.c_double)]
+
+
+class TsmParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n_hp", ctypes.c_int32), ("n_lp", ctypes.c_int32),
+                ("lp", SolveParams), ("hp", SolveParams), ("n_mom", ctypes.c_int32),
+                ("mom_host", ctypes.POINTER(ctypes.c_int32))]
+
+
+class RunStats(ctypes.Structure):
+    _fields_ = [("ms_hp_phase", ctypes.c_double), ("ms_lp_phase", ctypes.c_double), ("lp_iters", ctypes.c_int64),
+                ("hp_iters", ctypes.c_int64), ("max_lp_resid_true", ctypes.c_double),
+                ("max_hp_resid_true", ctypes.c_double), ("hp_not_converged", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+EXPORTS = [
+    "tm_abi_version", "tm_create", "tm_destroy", "tm_last_error", "tm_gauge_load", "tm_field_bytes",
+    "tm_field_convert", "tm_dslash", "tm_noise_z4", "tsm_solve_batch", "tsm_contract", "tsm_loops",
+    "tm_profile_enable", "tm_profile_read",
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtmqcd.so; raises if it is not built (no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libtmqcd.so is not built (%s); run __graft_entry__.build()" % path)
+    lib = ctypes.CDLL(path)
+    P, i32, u64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
+    lib.tm_abi_version.restype = i32
+    lib.tm_create.argtypes = [ctypes.POINTER(Lattice), P, ctypes.POINTER(P)]
+    lib.tm_destroy.argtypes = [P]
+    lib.tm_last_error.argtypes = [P]
+    lib.tm_last_error.restype = ctypes.c_char_p
+    lib.tm_gauge_load.argtypes = [P, P]
+    lib.tm_field_bytes.argtypes = [P, i32, i32, i32]
+    lib.tm_field_bytes.restype = ctypes.c_size_t
+    lib.tm_field_convert.argtypes = [P, i32, i32, i32, P, P]
+    lib.tm_dslash.argtypes = [P, i32, i32, i32, i32, P, P]
+    lib.tm_noise_z4.argtypes = [P, u64, i32, P, P]
+    lib.tsm_solve_batch.argtypes = [P, ctypes.POINTER(SolveParams), u64, i32, P, P, P]
+    lib.tsm_contract.argtypes = [P, u64, i32, P, P, i32, P, P]
+    lib.tsm_loops.argtypes = [P, ctypes.POINTER(TsmParams), P, P, P, P, ctypes.POINTER(RunStats)]
+    lib.tm_profile_enable.argtypes = [P, i32]
+    lib.tm_profile_read.argtypes = [P, P, P, P]
+    for name in EXPORTS:
+        if name != "tm_abi_version" and name != "tm_last_error" and name != "tm_field_bytes":
+            getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def solve_params(prec=PREC_F64, tol=1e-10, max_iter=-1, stop=STOP_NORMAL, reliable=0, delta=0.1, rhs_block=0,
+                 true_resid=1, solver=SOLVER_CG) -> SolveParams:
+    return SolveParams(prec, solver, tol, max_iter, stop, reliable, delta, rhs_block, true_resid)
+
+
+class Context:
+    """One lattice on the current device; wraps a tm_ctx*."""
+
+    def __init__(self, dims, kappa, mu, t_bc=-1, stream=None):
+        import torch
+        self.lib = load_library()
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        lat = Lattice((ctypes.c_int32 * 4)(*self.dims), float(kappa), float(mu), int(t_bc))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = self.lib.tm_create(ctypes.byref(lat), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        if rc != TM_OK:
+            raise TmError(rc, "tm_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, rc, allow_warn=True):
+        if rc < 0 or (rc > 0 and not allow_warn):
+            raise TmError(rc, self.lib.tm_last_error(self.h).decode())
+        return rc
+
+
+def tm_abi_version() -> int:
+    return int(load_library().tm_abi_version())
+
+
+def tm_create(dims, kappa, mu, t_bc=-1, stream=None) -> Context:
+    return Context(dims, kappa, mu, t_bc, stream)
+
+
+def tm_gauge_load(ctx: Context, links: np.ndarray) -> None:
+    links = np.ascontiguousarray(links, dtype=np.complex128)
+    assert links.shape == (ctx.V, 4, 3, 3)
+    ctx.check(ctx.lib.tm_gauge_load(ctx.h, _ptr(links)))
+
+
+def _canon_dtype(prec):
+    import torch
+    return {PREC_F64: torch.complex128, PREC_F32: torch.complex64, PREC_F16: torch.float16,
+            PREC_BF16: torch.bfloat16}[prec]
+
+
+def canonical_shape(ctx: Context, prec, nrhs):
+    if prec in (PREC_F16, PREC_BF16):
+        return (nrhs, ctx.V, 4, 3, 2)
+    return (nrhs, ctx.V, 4, 3)
+
+
+def tm_field_bytes(ctx: Context, prec, nrhs, layout) -> int:
+    return int(ctx.lib.tm_field_bytes(ctx.h, prec, nrhs, layout))
+
+
+def tm_field_convert(ctx: Context, prec, nrhs, to_native, x, out):
+    ctx.check(ctx.lib.tm_field_convert(ctx.h, prec, nrhs, int(to_native), ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def tm_dslash(ctx: Context, op, prec, x, out=None, layout=LAYOUT_CANONICAL, nrhs=None):
+    """out = op(x) for canonical tensors [nrhs][V][4][3] (complex) or
+    [nrhs][V][4][3][2] (F16/BF16 pairs), or native uint8 buffers."""
+    import torch
+    if layout == LAYOUT_CANONICAL:
+        nrhs = x.shape[0]
+        assert tuple(x.shape) == canonical_shape(ctx, prec, nrhs) and x.dtype == _canon_dtype(prec)
+        assert x.is_cuda and x.is_contiguous()
+        if out is None:
+            out = torch.empty_like(x)
+    else:
+        assert nrhs is not None and out is not None
+    ctx.check(ctx.lib.tm_dslash(ctx.h, op, prec, nrhs, layout, ctypes.c_void_p(x.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def tm_noise_z4(ctx: Context, seed, ids):
+    import torch
+    ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64))
+    out = torch.empty((len(ids), ctx.V, 4, 3), dtype=torch.complex128, device="cuda")
+    ctx.check(ctx.lib.tm_noise_z4(ctx.h, int(seed), len(ids), _ptr(ids), ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def _stats_list(st):
+    return [{"iters": s.iters, "converged": bool(s.converged), "truncated": bool(s.truncated),
+             "fell_back": bool(s.fell_back), "resid_iterated": s.resid_iterated, "resid_true": s.resid_true}
+            for s in st]
+
+
+def tsm_solve_batch(ctx: Context, params: SolveParams, seed, ids, want_solutions=True):
+    """Returns (solutions complex128 [n][V][4][3] on the device or None, stats list, status)."""
+    import torch
+    ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64))
+    n = len(ids)
+    sol = torch.empty((n, ctx.V, 4, 3), dtype=torch.complex128, device="cuda") if want_solutions else None
+    st = (SolveStats * max(n, 1))()
+    rc = ctx.lib.tsm_solve_batch(ctx.h, ctypes.byref(params), int(seed), n, _ptr(ids),
+                                 ctypes.c_void_p(sol.data_ptr()) if sol is not None else None, st)
+    ctx.check(rc)
+    return sol, _stats_list(st[:n]), rc
+
+
+def tsm_contract(ctx: Context, seed, ids, sol, mom):
+    """Loops of given solutions, complex128 [n][16][n_mom][Lt] (host)."""
+    ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64))
+    mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros((len(ids), 16, mom.shape[0], ctx.dims[3]), dtype=np.complex128)
+    assert sol.is_cuda and sol.is_contiguous() and tuple(sol.shape) == (len(ids), ctx.V, 4, 3)
+    ctx.check(ctx.lib.tsm_contract(ctx.h, int(seed), len(ids), _ptr(ids), ctypes.c_void_p(sol.data_ptr()),
+                                   mom.shape[0], _ptr(mom), _ptr(out)))
+    return out
+
+
+def tsm_loops(ctx: Context, seed, n_hp, n_lp, lp: SolveParams, hp: SolveParams, mom, per_source=False,
+              stats=True):
+    """The TSM estimate (Eq. 4).  Returns dict with 'loops' [3][16][n_mom][Lt]
+    (C, B, T), 'err', optional 'per_source' [N][2][16][n_mom][Lt], 'stats'
+    (list of [LP, HP] records), 'run' and the status code."""
+    mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+    nm, lt = mom.shape[0], ctx.dims[3]
+    N = n_hp + n_lp
+    P = TsmParams(int(seed), int(n_hp), int(n_lp), lp, hp, nm, mom.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    loops = np.zeros((3, 16, nm, lt), dtype=np.complex128)
+    err = np.zeros_like(loops)
+    ps = np.zeros((max(N, 1), 2, 16, nm, lt), dtype=np.complex128) if per_source else None
+    st = (SolveStats * (2 * max(N, 1)))() if stats else None
+    run = RunStats()
+    rc = ctx.lib.tsm_loops(ctx.h, ctypes.byref(P), _ptr(loops), _ptr(err), _ptr(ps) if ps is not None else None,
+                           st, ctypes.byref(run))
+    ctx.check(rc)
+    res = {"loops": loops, "err": err, "status": rc,
+           "run": {f: getattr(run, f) for f, _ in RunStats._fields_}}
+    if ps is not None:
+        res["per_source"] = ps[:N]
+    if st is not None:
+        sl = _stats_list(st[:2 * N])
+        res["stats"] = [[sl[2 * j], sl[2 * j + 1]] for j in range(N)]
+    return res
+
+
+def tm_profile_enable(ctx: Context, on=True):
+    ctx.check(ctx.lib.tm_profile_enable(ctx.h, 1 if on else 0))
+
+
+def tm_profile_read(ctx: Context):
+    n = len(KC_NAMES)
+    la = np.zeros(n, dtype=np.int64)
+    ms = np.zeros(n, dtype=np.float64)
+    by = np.zeros(n, dtype=np.float64)
+    ctx.check(ctx.lib.tm_profile_read(ctx.h, _ptr(la), _ptr(ms), _ptr(by)))
+    return {KC_NAMES[k]: {"launches": int(la[k]), "ms": float(ms[k]), "bytes": float(by[k])} for k in range(n)}

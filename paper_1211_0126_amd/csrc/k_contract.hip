@@ -1,0 +1,236 @@
+// Loop contraction and the TSM combination (gfx950).
+//
+// For one source the loop is (section 2.3 of the paper, for all insertion
+// times as in section 3)
+//   L_n(t, p) = sum_{x in t} exp(-i p.x) Tr[Gamma_n S(x)],
+//   S_{ba}(x) = sum_c s_{bc}(x) conj(eta_{ac}(x)),
+// with eta regenerated from the noise hash.  The Fourier sum is separable,
+// so it is done one axis at a time over the distinct per-axis momentum
+// components (3 each for the 27 momenta with |n_i| <= 1):
+//   A: per (x, z, t) row, sum over y with the y phases   (reads s once)
+//   B: sum over x with the x phases
+//   C: sum over z with the z phases and the Gamma traces (each Gamma_n is
+//      a phase-signed permutation: 4 terms)
+// All sums are in FP64 and in a fixed order (bitwise reproducible).
+
+#include "tm_device.h"
+#include "tm_kernels.h"
+
+namespace tmq {
+
+// load the six components of spin rows 2h, 2h+1
+template <class S>
+__device__ __forceinline__ void load_half_spinor(const void* base, long Vs, uint32_t s, int h, cx<double> p[6]);
+
+template <>
+__device__ __forceinline__ void load_half_spinor<SF64>(const void* base, long Vs, uint32_t s, int h, cx<double> p[6]) {
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        double2 v = ld_plane<double2>(base, Vs, 6 * h + k, s);
+        p[k] = {v.x, v.y};
+    }
+}
+template <>
+__device__ __forceinline__ void load_half_spinor<SF32>(const void* base, long Vs, uint32_t s, int h, cx<double> p[6]) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        float4 v = ld_plane<float4>(base, Vs, 3 * h + k, s);
+        p[2 * k] = {(double)v.x, (double)v.y};
+        p[2 * k + 1] = {(double)v.z, (double)v.w};
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
+    const Geom& g = a.geo;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+    const long nrow = (long)Lx * Lz * Lt;
+    const long tid = (long)blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (tid >= 2 * nrow) return;
+    const int h = tid >= nrow ? 1 : 0;
+    const long q = tid - h * nrow;
+    const int x = (int)(q % Lx);
+    const long q2 = q / Lx;
+    const int z = (int)(q2 % Lz);
+    const int t = (int)(q2 / Lz);
+    const int npy = a.npy;
+    const void* sol = field_rhs<S>(a.sol, g.Vs, r);
+    const uint64_t id = a.ids[r];
+    cx<double> acc[3][8];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int e = 0; e < 8; e++) acc[i][e] = {0.0, 0.0};
+    for (int y = 0; y < Ly; y++) {
+        const uint32_t s = x + Lx * (y + Ly * (z + Lz * t));
+        cx<double> p[6];
+        load_half_spinor<S>(sol, g.Vs, s, h, p);
+        const uint64_t bits = noise_bits(a.seed_mixed, id, (uint64_t)g.V, (uint64_t)s);
+        cx<double> S8[8];
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int al = 0; al < 4; al++) {
+                cx<double> v = {0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    cx<double> e = z4_value<double>((uint32_t)(bits >> (2 * (3 * al + c))) & 3u);
+                    v = v + cmulc(e, p[3 * b + c]);
+                }
+                S8[4 * b + al] = v;
+            }
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            if (i >= npy) break;
+            const double2 ph = a.phy[i * Ly + y];
+            const cx<double> w = {ph.x, ph.y};
+#pragma unroll
+            for (int e = 0; e < 8; e++) acc[i][e] = acc[i][e] + w * S8[e];
+        }
+    }
+    for (int i = 0; i < npy; i++) {
+        double2* o = a.A + (((((size_t)r * Lt + t) * Lz + z) * npy + i) * Lx + x) * 16 + 8 * h;
+#pragma unroll
+        for (int e = 0; e < 8; e++) o[e] = make_double2(acc[i][e].re, acc[i][e].im);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_contract_b(ContractArgs a) {
+    const Geom& g = a.geo;
+    const int Lx = g.L[0], Lz = g.L[2], Lt = g.L[3];
+    const int npy = a.npy, npx = a.npx;
+    const long n = 16L * npy * Lz * Lt;
+    const long tid = (long)blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (tid >= n) return;
+    const int e = (int)(tid % 16);
+    long q = tid / 16;
+    const int iy = (int)(q % npy);
+    q /= npy;
+    const int z = (int)(q % Lz);
+    const int t = (int)(q / Lz);
+    cx<double> acc[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) acc[i] = {0.0, 0.0};
+    const double2* in = a.A + ((((size_t)r * Lt + t) * Lz + z) * npy + iy) * Lx * 16 + e;
+    for (int x = 0; x < Lx; x++) {
+        const double2 v = in[(size_t)x * 16];
+        const cx<double> vv = {v.x, v.y};
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            if (i >= npx) break;
+            const double2 ph = a.phx[i * Lx + x];
+            acc[i] = acc[i] + cx<double>{ph.x, ph.y} * vv;
+        }
+    }
+    for (int i = 0; i < npx; i++)
+        a.B[(((((size_t)r * Lt + t) * Lz + z) * npx + i) * npy + iy) * 16 + e] = make_double2(acc[i].re, acc[i].im);
+}
+
+__global__ __launch_bounds__(256) void k_contract_c(ContractArgs a) {
+    const Geom& g = a.geo;
+    const int Lz = g.L[2], Lt = g.L[3];
+    const int npx = a.npx, npy = a.npy;
+    const long n = 16L * a.n_mom * Lt;
+    const long tid = (long)blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (tid >= n) return;
+    const int gn = (int)(tid % 16);
+    long q = tid / 16;
+    const int m = (int)(q % a.n_mom);
+    const int t = (int)(q / a.n_mom);
+    const int ix = a.mom_idx[3 * m], iy = a.mom_idx[3 * m + 1], iz = a.mom_idx[3 * m + 2];
+    cx<double> acc = {0.0, 0.0};
+    for (int z = 0; z < Lz; z++) {
+        const double2* bz = a.B + (((((size_t)r * Lt + t) * Lz + z) * npx + ix) * npy + iy) * 16;
+        cx<double> tr = {0.0, 0.0};
+#pragma unroll
+        for (int al = 0; al < 4; al++) {
+            const int be = a.gam_col[gn * 4 + al];
+            const double2 v = bz[be * 4 + al];
+            const cx<double> ph = z4_value<double>((uint32_t)a.gam_ph[gn * 4 + al]);
+            tr = tr + ph * cx<double>{v.x, v.y};
+        }
+        const double2 pz = a.phz[iz * Lz + z];
+        acc = acc + cx<double>{pz.x, pz.y} * tr;
+    }
+    double2* o = a.out + (size_t)a.out_slot[r] * a.out_stride;
+    o[((size_t)gn * a.n_mom + m) * Lt + t] = make_double2(acc.re, acc.im);
+}
+
+void launch_contract(hipStream_t st, const ContractArgs& a, int xprec) {
+    const Geom& g = a.geo;
+    const long nrow = 2L * g.L[0] * g.L[2] * g.L[3];
+    dim3 ga((unsigned)((nrow + 255) / 256), (unsigned)a.nrhs);
+    if (xprec == P_F64)
+        hipLaunchKernelGGL((k_contract_a<SF64>), ga, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_contract_a<SF32>), ga, dim3(256), 0, st, a);
+    const long nb = 16L * a.npy * g.L[2] * g.L[3];
+    hipLaunchKernelGGL(k_contract_b, dim3((unsigned)((nb + 255) / 256), (unsigned)a.nrhs), dim3(256), 0, st, a);
+    const long nc = 16L * a.n_mom * g.L[3];
+    hipLaunchKernelGGL(k_contract_c, dim3((unsigned)((nc + 255) / 256), (unsigned)a.nrhs), dim3(256), 0, st, a);
+}
+
+// TSM combination of Eq. 4 from the per-source loops ps[j][slot][k]
+// (slot 0 LP, 1 HP), k over nl = 16 * n_mom * Lt elements.  Two passes in
+// source order: means, then the spread.  out/err: [3][nl] (C, B, T).
+__global__ __launch_bounds__(256) void k_tsm_final(const double2* ps, long nl, int n_hp, int n_lp, double2* out,
+                                                   double2* err) {
+    const long k = (long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nl) return;
+    double cr = 0, ci = 0, br = 0, bi = 0;
+    for (int j = 0; j < n_hp; j++) {
+        double2 lp = ps[((size_t)j * 2 + 0) * nl + k], hp = ps[((size_t)j * 2 + 1) * nl + k];
+        cr += hp.x - lp.x;
+        ci += hp.y - lp.y;
+    }
+    for (int j = n_hp; j < n_hp + n_lp; j++) {
+        double2 lp = ps[((size_t)j * 2 + 0) * nl + k];
+        br += lp.x;
+        bi += lp.y;
+    }
+    if (n_hp > 0) {
+        cr /= n_hp;
+        ci /= n_hp;
+    }
+    if (n_lp > 0) {
+        br /= n_lp;
+        bi /= n_lp;
+    }
+    double vcr = 0, vci = 0, vbr = 0, vbi = 0;
+    if (n_hp > 1) {
+        for (int j = 0; j < n_hp; j++) {
+            double2 lp = ps[((size_t)j * 2 + 0) * nl + k], hp = ps[((size_t)j * 2 + 1) * nl + k];
+            double dr = (hp.x - lp.x) - cr, di = (hp.y - lp.y) - ci;
+            vcr += dr * dr;
+            vci += di * di;
+        }
+        vcr /= (double)(n_hp - 1) * n_hp;
+        vci /= (double)(n_hp - 1) * n_hp;
+    }
+    if (n_lp > 1) {
+        for (int j = n_hp; j < n_hp + n_lp; j++) {
+            double2 lp = ps[((size_t)j * 2 + 0) * nl + k];
+            double dr = lp.x - br, di = lp.y - bi;
+            vbr += dr * dr;
+            vbi += di * di;
+        }
+        vbr /= (double)(n_lp - 1) * n_lp;
+        vbi /= (double)(n_lp - 1) * n_lp;
+    }
+    out[k] = make_double2(cr, ci);
+    out[nl + k] = make_double2(br, bi);
+    out[2 * nl + k] = make_double2(cr + br, ci + bi);
+    err[k] = make_double2(sqrt(vcr), sqrt(vci));
+    err[nl + k] = make_double2(sqrt(vbr), sqrt(vbi));
+    err[2 * nl + k] = make_double2(sqrt(vcr + vbr), sqrt(vci + vbi));
+}
+
+void launch_tsm_final(hipStream_t st, const double* ps, long nl, int n_hp, int n_lp, double* out, double* err) {
+    hipLaunchKernelGGL(k_tsm_final, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, (const double2*)ps, nl, n_hp,
+                       n_lp, (double2*)out, (double2*)err);
+}
+
+}  // namespace tmq

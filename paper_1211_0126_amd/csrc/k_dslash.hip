@@ -1,0 +1,865 @@
+// Twisted-mass Wilson-Dirac operator and the fused CG kernels (gfx950).
+//
+// M = 1 - kappa H + 2 i kappa mu gamma_5 in the hopping normalisation, with
+// H psi(x) = sum_mu (1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^dag
+// psi(x-mu) and the adjoint H^dag obtained by swapping the two projectors.
+// (Flavour identities of section 2.3 of the paper; the twisted mass bounds
+// M^dag M from below, section 2.2.)
+//
+// One lane per lattice site and NR right-hand sides: every link is loaded
+// once per lane and applied to NR spinors.  Spin projection to two-spinor
+// halves (the chiral basis makes every projector a signed permutation), so a
+// hop costs two SU(3) matrix-vector products.  Sites are dealt to blocks of
+// 256 with an XCD-aware block order.
+//
+// The CG iteration on M^dag M is three launches per step:
+//   K1  t = M p,          |t|^2 -> alpha = |r|^2/|t|^2       (last block)
+//   K2  q = M^dag t,  r -= alpha q,  x += alpha p,  |r|^2 -> beta, stop test
+//   K3  p = r + beta p
+// with the scalars of every right-hand side kept on the device.
+
+#include "tm_device.h"
+#include "tm_kernels.h"
+
+// Compiler-only barrier: memory operations are not moved across it.
+#define TM_MEM_FENCE() asm volatile("" ::: "memory")
+
+namespace tmq {
+
+// ---------------------------------------------------------------------------
+// spin projection for the hop in direction MU with projector 1 - SG g_MU.
+// With g_MU = [[0, B], [B^dag, 0]] (2x2 spin blocks) the projected spinor is
+// (h, -SG B^dag h) with h = u - SG B d, u and d the upper and lower halves.
+// ---------------------------------------------------------------------------
+template <int MU, int SG, typename R>
+__device__ __forceinline__ void proj(const cx<R> p[12], cx<R> h[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        cx<R> u0 = p[c], u1 = p[3 + c], d0 = p[6 + c], d1 = p[9 + c];
+        cx<R> b0, b1;
+        if (MU == 0) {        // B = -i sigma_1
+            b0 = times_mi(d1);
+            b1 = times_mi(d0);
+        } else if (MU == 1) { // B = -i sigma_2
+            b0 = {-d1.re, -d1.im};
+            b1 = d0;
+        } else if (MU == 2) { // B = -i sigma_3
+            b0 = times_mi(d0);
+            b1 = times_i(d1);
+        } else {              // B = 1
+            b0 = d0;
+            b1 = d1;
+        }
+        if (SG > 0) {
+            h[c] = u0 - b0;
+            h[3 + c] = u1 - b1;
+        } else {
+            h[c] = u0 + b0;
+            h[3 + c] = u1 + b1;
+        }
+    }
+}
+
+template <int MU, int SG, typename R>
+__device__ __forceinline__ void recon(const cx<R> g[6], cx<R> acc[12]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        cx<R> g0 = g[c], g1 = g[3 + c];
+        cx<R> e0, e1;  // B^dag g
+        if (MU == 0) {
+            e0 = times_i(g1);
+            e1 = times_i(g0);
+        } else if (MU == 1) {
+            e0 = g1;
+            e1 = {-g0.re, -g0.im};
+        } else if (MU == 2) {
+            e0 = times_i(g0);
+            e1 = times_mi(g1);
+        } else {
+            e0 = g0;
+            e1 = g1;
+        }
+        acc[c] = acc[c] + g0;
+        acc[3 + c] = acc[3 + c] + g1;
+        if (SG > 0) {
+            acc[6 + c] = acc[6 + c] - e0;
+            acc[9 + c] = acc[9 + c] - e1;
+        } else {
+            acc[6 + c] = acc[6 + c] + e0;
+            acc[9 + c] = acc[9 + c] + e1;
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void su3_mul(const cx<R> U[3][3], const cx<R> h[6], cx<R> g[6]) {
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int i = 0; i < 3; i++) g[3 * a + i] = U[i][0] * h[3 * a] + U[i][1] * h[3 * a + 1] + U[i][2] * h[3 * a + 2];
+}
+template <typename R>
+__device__ __forceinline__ void su3_dag_mul(const cx<R> U[3][3], const cx<R> h[6], cx<R> g[6]) {
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+            g[3 * a + i] = cmulc(U[0][i], h[3 * a]) + cmulc(U[1][i], h[3 * a + 1]) + cmulc(U[2][i], h[3 * a + 2]);
+}
+
+template <typename R>
+__device__ __forceinline__ void negate6(cx<R> h[6]) {
+#pragma unroll
+    for (int k = 0; k < 6; k++) h[k] = {-h[k].re, -h[k].im};
+}
+
+// Materialise the accumulators here: the arithmetic of one direction then
+// completes before the next direction's loads are issued.
+template <typename R, int NR>
+__device__ __forceinline__ void pin_acc(cx<R> (&acc)[NR][12]) {
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+#pragma unroll
+        for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[r][k].re), "+v"(acc[r][k].im));
+}
+
+// Both hops in direction MU for NR spinors (rhs r at field_rhs(in, r)).
+template <int MU, bool DAG, typename R, class S, class G, int NR>
+__device__ __forceinline__ void hop_mu(const Geom& geo, const void* gauge, const void* in, uint32_t s, const Site& c,
+                                       cx<R> (&acc)[NR][12]) {
+    constexpr int SF = DAG ? -1 : 1;
+    const long Vs = geo.Vs;
+    {
+        const uint32_t y = nb_fwd(geo, s, c, MU);
+        const bool flip = (MU == 3) && (c.t + 1 == geo.L[3]) && (geo.t_bc < 0);
+        cx<R> U[3][3];
+        load_link<G, R>(gauge, Vs, MU, s, U);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<R> p[12], h[6], g[6];
+            load_spinor<S, R>(field_rhs<S>(in, Vs, r), Vs, y, p);
+            proj<MU, SF>(p, h);
+            if (flip) negate6(h);
+            su3_mul(U, h, g);
+            recon<MU, SF>(g, acc[r]);
+        }
+    }
+    if (sizeof(R) == 8) {
+        pin_acc<R, NR>(acc);
+        TM_MEM_FENCE();
+    }
+    {
+        const uint32_t y = nb_bwd(geo, s, c, MU);
+        const bool flip = (MU == 3) && (c.t == 0) && (geo.t_bc < 0);
+        cx<R> U[3][3];
+        load_link<G, R>(gauge, Vs, MU, y, U);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<R> p[12], h[6], g[6];
+            load_spinor<S, R>(field_rhs<S>(in, Vs, r), Vs, y, p);
+            proj<MU, -SF>(p, h);
+            if (flip) negate6(h);
+            su3_dag_mul(U, h, g);
+            recon<MU, -SF>(g, acc[r]);
+        }
+    }
+}
+
+template <bool DAG, typename R, class S, class G, int NR>
+__device__ __forceinline__ void hop_all(const Geom& geo, const void* gauge, const void* in, uint32_t s, const Site& c,
+                                        cx<R> (&acc)[NR][12]) {
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[r][k] = {(R)0, (R)0};
+    // compiler barriers keep one direction's loads in flight at a time, so
+    // the register budget of the occupancy target is not spent on hoisting
+    hop_mu<0, DAG, R, S, G, NR>(geo, gauge, in, s, c, acc);
+    pin_acc<R, NR>(acc);
+    TM_MEM_FENCE();
+    hop_mu<1, DAG, R, S, G, NR>(geo, gauge, in, s, c, acc);
+    pin_acc<R, NR>(acc);
+    TM_MEM_FENCE();
+    hop_mu<2, DAG, R, S, G, NR>(geo, gauge, in, s, c, acc);
+    pin_acc<R, NR>(acc);
+    TM_MEM_FENCE();
+    hop_mu<3, DAG, R, S, G, NR>(geo, gauge, in, s, c, acc);
+}
+
+// out = p - kappa acc + i tw gamma_5 p   (tw = +2 kappa mu for M, -2 kappa mu for M^dag)
+template <typename R>
+__device__ __forceinline__ void diag_combine(const cx<R> p[12], const cx<R> acc[12], R kappa, R tw, cx<R> out[12]) {
+#pragma unroll
+    for (int k = 0; k < 6; k++)
+        out[k] = {p[k].re - kappa * acc[k].re - tw * p[k].im, p[k].im - kappa * acc[k].im + tw * p[k].re};
+#pragma unroll
+    for (int k = 6; k < 12; k++)
+        out[k] = {p[k].re - kappa * acc[k].re + tw * p[k].im, p[k].im - kappa * acc[k].im - tw * p[k].re};
+}
+
+template <typename R>
+__device__ __forceinline__ double spinor_norm2(const cx<R> v[12]) {
+    double s = 0;
+#pragma unroll
+    for (int k = 0; k < 12; k++) s += (double)v[k].re * (double)v[k].re + (double)v[k].im * (double)v[k].im;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// plain application: out = op(in), op 0 = M, 1 = M^dag, 3 = H
+// gate (nullable): apply only to right-hand sides whose reliable flag is set
+// ---------------------------------------------------------------------------
+template <int OP, typename R, class Si, class So, class G, int NR>
+__global__ TM_STENCIL_R(NR, R) void k_apply(Geom geo, const void* gauge, R kappa, R twist, int nrhs,
+                                               const void* in, void* out, const CgScal* gate) {
+    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t s = b * 256u + threadIdx.x;
+    const int r0 = blockIdx.y * NR;
+    if (s >= geo.V) return;
+    if (gate != nullptr && !gate[r0].rflag) return;  // gated launches use NR = 1
+    const Site c = site_coords(geo, s);
+    const void* in0 = field_rhs<Si>(in, geo.Vs, r0);
+    cx<R> acc[NR][12];
+    hop_all<OP == 1, R, Si, G, NR>(geo, gauge, in0, s, c, acc);
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        cx<R> o[12];
+        if (OP == 3) {
+#pragma unroll
+            for (int k = 0; k < 12; k++) o[k] = acc[r][k];
+        } else {
+            cx<R> pc[12];
+            load_spinor<Si, R>(field_rhs<Si>(in0, geo.Vs, r), geo.Vs, s, pc);
+            diag_combine(pc, acc[r], kappa, OP == 0 ? twist : -twist, o);
+        }
+        store_spinor<So, R>(field_rhs<So>(out, geo.Vs, r0 + r), geo.Vs, s, o);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CG kernels
+// ---------------------------------------------------------------------------
+
+// End of one CG step for one right-hand side (single thread).
+__device__ inline void cg_finish_step(CgScal& q, double rrn, double rhon) {
+    q.iters += 1;
+    if (!(rrn == rrn) || !(q.alpha == q.alpha) || rrn > 1e300) {  // NaN or overflow: breakdown
+        q.status = 3;
+        q.active = 0;
+        q.rflag = 0;
+        return;
+    }
+    if (q.stop == 1) q.rho2 = rhon;
+    if (q.reliable) {
+        if (rrn > q.maxrr) q.maxrr = rrn;
+        if (rrn <= q.tol2 * q.bb || rrn < q.delta2 * q.maxrr) {
+            q.rflag = 1;  // the reliable-update kernels finish this step
+            return;
+        }
+        q.beta = rrn / q.rr;
+        q.rr = rrn;
+        if (q.maxit >= 0 && q.iters >= q.maxit) {
+            q.status = 2;
+            q.active = 0;
+        }
+        return;
+    }
+    q.beta = rrn / q.rr;
+    q.rr = rrn;
+    const double rel2 = (q.stop == 1) ? q.rho2 / q.ee : rrn / q.bb;
+    if (rel2 <= q.tol2) {
+        q.status = 1;
+        q.active = 0;
+    } else if (q.maxit >= 0 && q.iters >= q.maxit) {
+        q.status = 2;
+        q.active = 0;
+    }
+}
+
+// K1: t = M p and alpha
+template <typename R, class S, class G, int NR>
+__global__ TM_STENCIL_R(NR, R) void k_cg_mp(CgArgs a) {
+    __shared__ double sh[4];
+    __shared__ int sflag;
+    const uint32_t nb = gridDim.x;
+    const uint32_t b = xcd_block(blockIdx.x, nb);
+    const uint32_t s = b * 256u + threadIdx.x;
+    const int r0 = blockIdx.y * NR;
+    const long Vs = a.geo.Vs;
+    bool act[NR];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        act[r] = a.scal[r0 + r].active != 0;
+        any |= act[r];
+    }
+    if (!any) return;  // uniform over all blocks of this rhs chunk
+    double part[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) part[r] = 0;
+    if (s < a.geo.V) {
+        const Site c = site_coords(a.geo, s);
+        const void* p0 = field_rhs<S>(a.p, Vs, r0);
+        cx<R> acc[NR][12];
+        hop_all<false, R, S, G, NR>(a.geo, a.gauge, p0, s, c, acc);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (!act[r]) continue;
+            cx<R> pc[12], t[12];
+            load_spinor<S, R>(field_rhs<S>(p0, Vs, r), Vs, s, pc);
+            diag_combine(pc, acc[r], (R)a.kappa, (R)a.twist, t);
+            round_storage<S, R>(t);
+            store_spinor<S, R>(field_rhs<S>(a.t, Vs, r0 + r), Vs, s, t);
+            part[r] = spinor_norm2(t);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        double v = block_sum256(part[r], sh);
+        if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * nb + blockIdx.x] = v;
+    }
+    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (!act[r]) continue;
+            double tt = sum_partials(a.partials + (size_t)(r0 + r) * nb, nb, sh);
+            if (threadIdx.x == 0) {
+                CgScal& q = a.scal[r0 + r];
+                q.tt = tt;
+                q.alpha = tt > 0 ? q.rr / tt : 0.0;
+            }
+        }
+        if (threadIdx.x == 0) a.counters[blockIdx.y] = 0;
+    }
+}
+
+// K2: q = M^dag t, r -= alpha q, x += alpha p (x of storage X), |r|^2,
+// optionally rho -= alpha t (recursive true residual)
+template <typename R, class S, class G, class X, typename RX, int NR, bool TRACK>
+__global__ TM_STENCIL_R(NR, R) void k_cg_upd(CgArgs a) {
+    __shared__ double sh[4];
+    __shared__ int sflag;
+    const uint32_t nb = gridDim.x;
+    const uint32_t b = xcd_block(blockIdx.x, nb);
+    const uint32_t s = b * 256u + threadIdx.x;
+    const int r0 = blockIdx.y * NR;
+    const long Vs = a.geo.Vs;
+    bool act[NR];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        act[r] = a.scal[r0 + r].active != 0;
+        any |= act[r];
+    }
+    if (!any) return;
+    double prr[NR], prho[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) prr[r] = prho[r] = 0;
+    if (s < a.geo.V) {
+        const Site c = site_coords(a.geo, s);
+        const void* t0 = field_rhs<S>(a.t, Vs, r0);
+        cx<R> acc[NR][12];
+        hop_all<true, R, S, G, NR>(a.geo, a.gauge, t0, s, c, acc);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (!act[r]) continue;
+            const double alpha = a.scal[r0 + r].alpha;
+            cx<R> tc[12], q[12], rv[12], pv[12];
+            load_spinor<S, R>(field_rhs<S>(t0, Vs, r), Vs, s, tc);
+            diag_combine(tc, acc[r], (R)a.kappa, (R)(-a.twist), q);
+            void* rp = field_rhs<S>(a.r, Vs, r0 + r);
+            load_spinor<S, R>(rp, Vs, s, rv);
+            const R al = (R)alpha;
+#pragma unroll
+            for (int k = 0; k < 12; k++) rv[k] = rv[k] - al * q[k];
+            round_storage<S, R>(rv);
+            store_spinor<S, R>(rp, Vs, s, rv);
+            prr[r] = spinor_norm2(rv);
+            load_spinor<S, R>(field_rhs<S>(a.p, Vs, r0 + r), Vs, s, pv);
+            cx<RX> xv[12];
+            void* xp = field_rhs<X>(a.x, Vs, r0 + r);
+            load_spinor<X, RX>(xp, Vs, s, xv);
+            const RX alx = (RX)alpha;
+#pragma unroll
+            for (int k = 0; k < 12; k++) xv[k] = {xv[k].re + alx * (RX)pv[k].re, xv[k].im + alx * (RX)pv[k].im};
+            store_spinor<X, RX>(xp, Vs, s, xv);
+            if (TRACK) {
+                cx<R> rh[12];
+                void* hp = field_rhs<S>(a.rho, Vs, r0 + r);
+                load_spinor<S, R>(hp, Vs, s, rh);
+#pragma unroll
+                for (int k = 0; k < 12; k++) rh[k] = rh[k] - al * tc[k];
+                round_storage<S, R>(rh);
+                store_spinor<S, R>(hp, Vs, s, rh);
+                prho[r] = spinor_norm2(rh);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        double v = block_sum256(prr[r], sh);
+        if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * nb + blockIdx.x] = v;
+        if (TRACK) {
+            double w = block_sum256(prho[r], sh);
+            if (threadIdx.x == 0) a.partials2[(size_t)(r0 + r) * nb + blockIdx.x] = w;
+        }
+    }
+    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (!act[r]) continue;
+            double rrn = sum_partials(a.partials + (size_t)(r0 + r) * nb, nb, sh);
+            double rhon = TRACK ? sum_partials(a.partials2 + (size_t)(r0 + r) * nb, nb, sh) : 0.0;
+            if (threadIdx.x == 0) cg_finish_step(a.scal[r0 + r], rrn, rhon);
+        }
+        if (threadIdx.x == 0) a.counters[blockIdx.y] = 0;
+    }
+}
+
+// K3: p = r + beta p (one lane per site and right-hand side)
+template <typename R, class S>
+__global__ __launch_bounds__(256) void k_cg_p(CgArgs a) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= a.geo.V) return;
+    const CgScal& q = a.scal[r];
+    if (!q.active) return;
+    const R beta = (R)q.beta;
+    cx<R> rv[12], pv[12];
+    load_spinor<S, R>(field_rhs<S>(a.r, a.geo.Vs, r), a.geo.Vs, s, rv);
+    void* pp = field_rhs<S>(a.p, a.geo.Vs, r);
+    load_spinor<S, R>(pp, a.geo.Vs, s, pv);
+#pragma unroll
+    for (int k = 0; k < 12; k++) pv[k] = rv[k] + beta * pv[k];
+    store_spinor<S, R>(pp, a.geo.Vs, s, pv);
+}
+
+// Initialisation: r holds b = M^dag eta.  p = r, x = 0, (rho = eta),
+// |b|^2 and |eta|^2, first stop test.
+template <typename R, class S, class X, typename RX, bool TRACK>
+__global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const void* eta) {
+    __shared__ double sh[4];
+    __shared__ int sflag;
+    const uint32_t nb = gridDim.x;
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    const long Vs = a.geo.Vs;
+    double pb = 0, pe = 0;
+    if (s < a.geo.V) {
+        cx<R> rv[12], ev[12];
+        load_spinor<S, R>(field_rhs<S>(a.r, Vs, r), Vs, s, rv);
+        store_spinor<S, R>(field_rhs<S>(a.p, Vs, r), Vs, s, rv);
+        cx<RX> z[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) z[k] = {(RX)0, (RX)0};
+        store_spinor<X, RX>(field_rhs<X>(a.x, Vs, r), Vs, s, z);
+        pb = spinor_norm2(rv);
+        load_spinor<S, R>(field_rhs<S>(eta, Vs, r), Vs, s, ev);
+        pe = spinor_norm2(ev);
+        if (TRACK) store_spinor<S, R>(field_rhs<S>(a.rho, Vs, r), Vs, s, ev);
+    }
+    double v = block_sum256(pb, sh);
+    if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
+    double w = block_sum256(pe, sh);
+    if (threadIdx.x == 0) a.partials2[(size_t)r * nb + blockIdx.x] = w;
+    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
+        double bb = sum_partials(a.partials + (size_t)r * nb, nb, sh);
+        double ee = sum_partials(a.partials2 + (size_t)r * nb, nb, sh);
+        if (threadIdx.x == 0) {
+            CgScal& q = a.scal[r];
+            q.bb = q.rr = q.maxrr = bb;
+            q.ee = q.rho2 = ee;
+            q.iters = 0;
+            q.rflag = 0;
+            q.n_reliable = 0;
+            q.alpha = q.beta = 0;
+            if (bb <= 0 || 1.0 <= q.tol2) {
+                q.status = 1;
+            } else if (q.maxit == 0) {
+                q.status = 2;
+            } else {
+                q.status = 0;
+            }
+            q.active = q.status == 0;
+            a.counters[blockIdx.y] = 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reliable updates (FP32 iterations, FP64 solution and true residual)
+// ---------------------------------------------------------------------------
+
+// init: r32 = b64, p32 = r32, x32 = 0, x64 = 0, |b64|^2
+__global__ __launch_bounds__(256) void k_rel_init(CgArgs a, const void* b64, void* x64) {
+    __shared__ double sh[4];
+    __shared__ int sflag;
+    const uint32_t nb = gridDim.x;
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    const long Vs = a.geo.Vs;
+    double pb = 0;
+    if (s < a.geo.V) {
+        cx<double> bv[12], z[12];
+        load_spinor<SF64, double>(field_rhs<SF64>(b64, Vs, r), Vs, s, bv);
+        pb = spinor_norm2(bv);
+        cx<float> rf[12], zf[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            rf[k] = {(float)bv[k].re, (float)bv[k].im};
+            zf[k] = {0.f, 0.f};
+            z[k] = {0.0, 0.0};
+        }
+        store_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r), Vs, s, rf);
+        store_spinor<SF32, float>(field_rhs<SF32>(a.p, Vs, r), Vs, s, rf);
+        store_spinor<SF32, float>(field_rhs<SF32>(a.x, Vs, r), Vs, s, zf);
+        store_spinor<SF64, double>(field_rhs<SF64>(x64, Vs, r), Vs, s, z);
+    }
+    double v = block_sum256(pb, sh);
+    if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
+    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
+        double bb = sum_partials(a.partials + (size_t)r * nb, nb, sh);
+        if (threadIdx.x == 0) {
+            CgScal& q = a.scal[r];
+            q.bb = q.rr = q.maxrr = bb;
+            q.ee = q.rho2 = (double)a.geo.V * 12.0;  // |eta|^2 of a Z4 source
+            q.iters = 0;
+            q.rflag = 0;
+            q.n_reliable = 0;
+            q.alpha = q.beta = 0;
+            q.status = (bb <= 0 || 1.0 <= q.tol2) ? 1 : (q.maxit == 0 ? 2 : 0);
+            q.active = q.status == 0;
+            a.counters[blockIdx.y] = 0;
+        }
+    }
+}
+
+// x64 += x32, x32 = 0 (where the reliable flag is set, or always if force)
+__global__ __launch_bounds__(256) void k_rel_flush(CgArgs a, void* x64, int force) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= a.geo.V) return;
+    if (!force && !a.scal[r].rflag) return;
+    const long Vs = a.geo.Vs;
+    cx<double> xd[12], xs[12];
+    cx<float> z[12];
+    void* xdp = field_rhs<SF64>(x64, Vs, r);
+    void* xsp = field_rhs<SF32>(a.x, Vs, r);
+    load_spinor<SF64, double>(xdp, Vs, s, xd);
+    load_spinor<SF32, double>(xsp, Vs, s, xs);
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        xd[k] = xd[k] + xs[k];
+        z[k] = {0.f, 0.f};
+    }
+    store_spinor<SF64, double>(xdp, Vs, s, xd);
+    store_spinor<SF32, float>(xsp, Vs, s, z);
+}
+
+// r64 = b64 - M^dag t64 (t64 = M x64), r32 = r64, |r64|^2 -> finish the step
+__global__ TM_STENCIL_R(1, double) void k_rel_resid(CgArgs a, const void* gauge64, const void* b64, const void* t64) {
+    __shared__ double sh[4];
+    __shared__ int sflag;
+    const uint32_t nb = gridDim.x;
+    const uint32_t b = xcd_block(blockIdx.x, nb);
+    const uint32_t s = b * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    const long Vs = a.geo.Vs;
+    if (!a.scal[r].rflag) return;
+    double pr = 0;
+    if (s < a.geo.V) {
+        const Site c = site_coords(a.geo, s);
+        const void* t0 = field_rhs<SF64>(t64, Vs, r);
+        cx<double> acc[1][12];
+        hop_all<true, double, SF64, GF64, 1>(a.geo, gauge64, t0, s, c, acc);
+        cx<double> tc[12], q[12], bv[12];
+        load_spinor<SF64, double>(t0, Vs, s, tc);
+        diag_combine(tc, acc[0], a.kappa, -a.twist, q);
+        load_spinor<SF64, double>(field_rhs<SF64>(b64, Vs, r), Vs, s, bv);
+        cx<float> rf[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            bv[k] = bv[k] - q[k];
+            rf[k] = {(float)bv[k].re, (float)bv[k].im};
+        }
+        store_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r), Vs, s, rf);
+        pr = spinor_norm2(bv);
+    }
+    double v = block_sum256(pr, sh);
+    if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
+    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
+        double rrn = sum_partials(a.partials + (size_t)r * nb, nb, sh);
+        if (threadIdx.x == 0) {
+            CgScal& q = a.scal[r];
+            q.beta = rrn / q.rr;
+            q.rr = rrn;
+            q.maxrr = rrn;
+            q.rflag = 0;
+            q.n_reliable += 1;
+            if (rrn <= q.tol2 * q.bb) {
+                q.status = 1;
+                q.active = 0;
+            } else if (q.maxit >= 0 && q.iters >= q.maxit) {
+                q.status = 2;
+                q.active = 0;
+            }
+            a.counters[blockIdx.y] = 0;
+        }
+    }
+}
+
+// FP64 true residual |eta - M x| / |eta| with eta regenerated from the hash
+template <class X, typename RXin>
+__global__ TM_STENCIL_R(1, double) void k_true_resid(CgArgs a, const void* gauge64, uint64_t seed_mixed,
+                                                    const uint64_t* ids) {
+    __shared__ double sh[4];
+    __shared__ int sflag;
+    const uint32_t nb = gridDim.x;
+    const uint32_t b = xcd_block(blockIdx.x, nb);
+    const uint32_t s = b * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    const long Vs = a.geo.Vs;
+    double pr = 0, pe = 0;
+    if (s < a.geo.V) {
+        const Site c = site_coords(a.geo, s);
+        const void* x0 = field_rhs<X>(a.x, Vs, r);
+        cx<double> acc[1][12];
+        hop_all<false, double, X, GF64, 1>(a.geo, gauge64, x0, s, c, acc);
+        cx<double> xc[12], mx[12];
+        load_spinor<X, double>(x0, Vs, s, xc);
+        diag_combine(xc, acc[0], a.kappa, a.twist, mx);
+        const uint64_t h = noise_bits(seed_mixed, ids[r], (uint64_t)a.geo.V, (uint64_t)s);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            cx<double> e = z4_value<double>((uint32_t)(h >> (2 * k)) & 3u);
+            cx<double> d = e - mx[k];
+            pr += norm2(d);
+            pe += norm2(e);
+        }
+    }
+    double v = block_sum256(pr, sh);
+    if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
+    double w = block_sum256(pe, sh);
+    if (threadIdx.x == 0) a.partials2[(size_t)r * nb + blockIdx.x] = w;
+    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
+        double rr = sum_partials(a.partials + (size_t)r * nb, nb, sh);
+        double ee = sum_partials(a.partials2 + (size_t)r * nb, nb, sh);
+        if (threadIdx.x == 0) {
+            a.scal[r].resid_true = sqrt(rr / ee);
+            a.counters[blockIdx.y] = 0;
+        }
+    }
+}
+
+// per-right-hand-side solver settings
+__global__ void k_scal_init(CgScal* sc, int n, double tol2, int maxit, int stop, int reliable, double delta2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    CgScal q = {};
+    q.tol2 = tol2;
+    q.maxit = maxit;
+    q.stop = stop;
+    q.reliable = reliable;
+    q.delta2 = delta2;
+    q.resid_true = -1.0;
+    sc[i] = q;
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline dim3 site_grid(const Geom& g, int ychunks) {
+    return dim3((unsigned)((g.V + 255) / 256), (unsigned)ychunks, 1);
+}
+
+template <int OP, typename R, class Si, class So, class G>
+static void apply_nr(hipStream_t st, const Geom& g, const void* gauge, double kappa, double twist, int nrhs,
+                     const void* in, void* out, int nr, const CgScal* gate) {
+    if constexpr (sizeof(R) == 8) {
+        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 1>), site_grid(g, nrhs), dim3(256), 0, st, g, gauge, (R)kappa,
+                           (R)twist, nrhs, in, out, gate);
+        return;
+    }
+    switch (nr) {
+    case 4:
+        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 4>), site_grid(g, nrhs / 4), dim3(256), 0, st, g, gauge, (R)kappa,
+                           (R)twist, nrhs, in, out, gate);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 2>), site_grid(g, nrhs / 2), dim3(256), 0, st, g, gauge, (R)kappa,
+                           (R)twist, nrhs, in, out, gate);
+        break;
+    default:
+        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 1>), site_grid(g, nrhs), dim3(256), 0, st, g, gauge, (R)kappa,
+                           (R)twist, nrhs, in, out, gate);
+        break;
+    }
+}
+
+template <int OP>
+static void apply_prec(hipStream_t st, const Geom& g, int prec, const void* gauge, double kappa, double twist,
+                       int nrhs, const void* in, void* out, int nr, const CgScal* gate) {
+    switch (prec) {
+    case P_F64:
+        apply_nr<OP, double, SF64, SF64, GF64>(st, g, gauge, kappa, twist, nrhs, in, out, 1, gate);
+        break;
+    case P_F32:
+        apply_nr<OP, float, SF32, SF32, GF32>(st, g, gauge, kappa, twist, nrhs, in, out, nr, gate);
+        break;
+    case P_F16:
+        apply_nr<OP, float, SF16, SF16, GF32>(st, g, gauge, kappa, twist, nrhs, in, out, nr, gate);
+        break;
+    default:
+        apply_nr<OP, float, SBF16, SBF16, GF32>(st, g, gauge, kappa, twist, nrhs, in, out, nr, gate);
+        break;
+    }
+}
+
+void launch_apply(hipStream_t st, const Geom& g, int prec, const void* gauge, double kappa, double twist, int op,
+                  int nrhs, const void* in, void* out, int nr, const CgScal* gate) {
+    if (op == 0)
+        apply_prec<0>(st, g, prec, gauge, kappa, twist, nrhs, in, out, nr, gate);
+    else if (op == 1)
+        apply_prec<1>(st, g, prec, gauge, kappa, twist, nrhs, in, out, nr, gate);
+    else
+        apply_prec<3>(st, g, prec, gauge, kappa, twist, nrhs, in, out, nr, gate);
+}
+
+void launch_apply_f32in_f64(hipStream_t st, const Geom& g, const void* gauge64, double kappa, double twist, int op,
+                            int nrhs, const void* in32, void* out64, const CgScal* gate) {
+    if (op == 0)
+        apply_nr<0, double, SF32, SF64, GF64>(st, g, gauge64, kappa, twist, nrhs, in32, out64, 1, gate);
+    else
+        apply_nr<1, double, SF32, SF64, GF64>(st, g, gauge64, kappa, twist, nrhs, in32, out64, 1, gate);
+}
+
+template <typename R, class S, class G>
+static void cg_mp_typed(hipStream_t st, const CgArgs& a, int nr) {
+    const Geom& g = a.geo;
+    if constexpr (sizeof(R) == 8) {
+        hipLaunchKernelGGL((k_cg_mp<R, S, G, 1>), site_grid(g, a.nrhs), dim3(256), 0, st, a);
+        return;
+    }
+    switch (nr) {
+    case 4:
+        hipLaunchKernelGGL((k_cg_mp<R, S, G, 4>), site_grid(g, a.nrhs / 4), dim3(256), 0, st, a);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_cg_mp<R, S, G, 2>), site_grid(g, a.nrhs / 2), dim3(256), 0, st, a);
+        break;
+    default:
+        hipLaunchKernelGGL((k_cg_mp<R, S, G, 1>), site_grid(g, a.nrhs), dim3(256), 0, st, a);
+        break;
+    }
+}
+
+template <typename R, class S, class G, class X, typename RX>
+static void cg_upd_typed(hipStream_t st, const CgArgs& a, int nr, bool track) {
+    const Geom& g = a.geo;
+    if (track) {
+        hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 1, true>), site_grid(g, a.nrhs), dim3(256), 0, st, a);
+    } else if constexpr (sizeof(R) == 8) {
+        hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 1, false>), site_grid(g, a.nrhs), dim3(256), 0, st, a);
+    } else {
+        switch (nr) {
+        case 4:
+            hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 4, false>), site_grid(g, a.nrhs / 4), dim3(256), 0, st, a);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 2, false>), site_grid(g, a.nrhs / 2), dim3(256), 0, st, a);
+            break;
+        default:
+            hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 1, false>), site_grid(g, a.nrhs), dim3(256), 0, st, a);
+            break;
+        }
+    }
+}
+
+template <typename R, class S>
+static void cg_p_typed(hipStream_t st, const CgArgs& a) {
+    hipLaunchKernelGGL((k_cg_p<R, S>), site_grid(a.geo, a.nrhs), dim3(256), 0, st, a);
+}
+
+void launch_cg_mp(hipStream_t st, const CgArgs& a, int prec, int nr) {
+    switch (prec) {
+    case P_F64: cg_mp_typed<double, SF64, GF64>(st, a, 1); break;
+    case P_F32: cg_mp_typed<float, SF32, GF32>(st, a, nr); break;
+    case P_F16: cg_mp_typed<float, SF16, GF32>(st, a, nr); break;
+    default: cg_mp_typed<float, SBF16, GF32>(st, a, nr); break;
+    }
+}
+
+void launch_cg_upd(hipStream_t st, const CgArgs& a, int prec, int nr, bool track) {
+    switch (prec) {
+    case P_F64: cg_upd_typed<double, SF64, GF64, SF64, double>(st, a, 1, track); break;
+    case P_F32: cg_upd_typed<float, SF32, GF32, SF32, float>(st, a, nr, track); break;
+    case P_F16: cg_upd_typed<float, SF16, GF32, SF32, float>(st, a, nr, track); break;
+    default: cg_upd_typed<float, SBF16, GF32, SF32, float>(st, a, nr, track); break;
+    }
+}
+
+void launch_cg_p(hipStream_t st, const CgArgs& a, int prec) {
+    switch (prec) {
+    case P_F64: cg_p_typed<double, SF64>(st, a); break;
+    case P_F32: cg_p_typed<float, SF32>(st, a); break;
+    case P_F16: cg_p_typed<float, SF16>(st, a); break;
+    default: cg_p_typed<float, SBF16>(st, a); break;
+    }
+}
+
+void launch_cg_init(hipStream_t st, const CgArgs& a, int prec, bool track, const void* eta) {
+    dim3 grid = site_grid(a.geo, a.nrhs);
+    switch (prec) {
+    case P_F64:
+        if (track)
+            hipLaunchKernelGGL((k_cg_init<double, SF64, SF64, double, true>), grid, dim3(256), 0, st, a, eta);
+        else
+            hipLaunchKernelGGL((k_cg_init<double, SF64, SF64, double, false>), grid, dim3(256), 0, st, a, eta);
+        break;
+    case P_F32:
+        if (track)
+            hipLaunchKernelGGL((k_cg_init<float, SF32, SF32, float, true>), grid, dim3(256), 0, st, a, eta);
+        else
+            hipLaunchKernelGGL((k_cg_init<float, SF32, SF32, float, false>), grid, dim3(256), 0, st, a, eta);
+        break;
+    case P_F16:
+        if (track)
+            hipLaunchKernelGGL((k_cg_init<float, SF16, SF32, float, true>), grid, dim3(256), 0, st, a, eta);
+        else
+            hipLaunchKernelGGL((k_cg_init<float, SF16, SF32, float, false>), grid, dim3(256), 0, st, a, eta);
+        break;
+    default:
+        if (track)
+            hipLaunchKernelGGL((k_cg_init<float, SBF16, SF32, float, true>), grid, dim3(256), 0, st, a, eta);
+        else
+            hipLaunchKernelGGL((k_cg_init<float, SBF16, SF32, float, false>), grid, dim3(256), 0, st, a, eta);
+        break;
+    }
+}
+
+void launch_scal_init(hipStream_t st, CgScal* sc, int n, double tol2, int maxit, int stop, int reliable,
+                      double delta2) {
+    hipLaunchKernelGGL(k_scal_init, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, sc, n, tol2, maxit, stop, reliable,
+                       delta2);
+}
+
+void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64) {
+    hipLaunchKernelGGL(k_rel_init, site_grid(a.geo, a.nrhs), dim3(256), 0, st, a, b64, x64);
+}
+void launch_rel_flush(hipStream_t st, const CgArgs& a, void* x64, int force) {
+    hipLaunchKernelGGL(k_rel_flush, site_grid(a.geo, a.nrhs), dim3(256), 0, st, a, x64, force);
+}
+void launch_rel_resid(hipStream_t st, const CgArgs& a, const void* gauge64, const void* b64, const void* t64) {
+    hipLaunchKernelGGL(k_rel_resid, site_grid(a.geo, a.nrhs), dim3(256), 0, st, a, gauge64, b64, t64);
+}
+
+void launch_true_resid(hipStream_t st, const CgArgs& a, int xprec, const void* gauge64, uint64_t seed_mixed,
+                       const uint64_t* ids) {
+    dim3 grid = site_grid(a.geo, a.nrhs);
+    if (xprec == P_F64)
+        hipLaunchKernelGGL((k_true_resid<SF64, double>), grid, dim3(256), 0, st, a, gauge64, seed_mixed, ids);
+    else
+        hipLaunchKernelGGL((k_true_resid<SF32, float>), grid, dim3(256), 0, st, a, gauge64, seed_mixed, ids);
+}
+
+}  // namespace tmq

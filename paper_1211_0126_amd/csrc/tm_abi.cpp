@@ -1,0 +1,335 @@
+// C ABI: lifecycle, gauge load, operator application, noise, instrumentation.
+
+#include <cmath>
+#include <cstring>
+#include <complex>
+
+#include "tm_ctx.h"
+
+namespace tmq {
+
+tm_status set_error(tm_ctx* ctx, tm_status code, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+tm_status dev_error(tm_ctx* ctx, hipError_t e, const char* what) {
+    if (ctx) {
+        ctx->sticky = 1;
+        ctx->err = std::string("HIP error ") + hipGetErrorString(e) + " in " + what;
+    }
+    return TM_EDEVICE;
+}
+
+void* ws_get(tm_ctx* ctx, const std::string& name, size_t bytes, tm_status* st) {
+    auto& b = ctx->ws[name];
+    if (b.bytes >= bytes && b.p) return b.p;
+    if (b.p) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            *st = dev_error(ctx, e, "hipStreamSynchronize");
+            return nullptr;
+        }
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *st = set_error(ctx, TM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes for " + name +
+                                            " failed");
+        return nullptr;
+    }
+    e = hipMemsetAsync(p, 0, bytes, ctx->stream);
+    if (e != hipSuccess) {
+        *st = dev_error(ctx, e, "hipMemsetAsync");
+        return nullptr;
+    }
+    b.p = p;
+    b.bytes = bytes;
+    return p;
+}
+
+size_t field_bytes(const Geom& g, int prec, int nrhs) {
+    const int nv = prec == P_F64 ? 12 : (prec == P_F32 ? 6 : 3);
+    return (size_t)nrhs * nv * 16 * (size_t)g.Vs;
+}
+
+// splitmix64 output mix (Steele, Lea & Flood 2014), host side
+uint64_t seed_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+void prof_begin(tm_ctx* ctx, int kc) {
+    if (!ctx->prof) return;
+    while (ctx->ev_used + 2 > ctx->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+            ctx->prof = false;
+            return;
+        }
+        ctx->ev_pool.push_back(e);
+    }
+    hipEvent_t a = ctx->ev_pool[ctx->ev_used++];
+    hipEvent_t b = ctx->ev_pool[ctx->ev_used++];
+    (void)hipEventRecord(a, ctx->stream);
+    ctx->recs.push_back({kc, a, b, 0.0});
+}
+
+void prof_end(tm_ctx* ctx, int kc, double bytes) {
+    if (!ctx->prof || ctx->recs.empty()) return;
+    auto& r = ctx->recs.back();
+    (void)kc;
+    r.bytes = bytes;
+    (void)hipEventRecord(r.b, ctx->stream);
+}
+
+// Gamma_n = g1^b0 g2^b1 g3^b2 g4^b3 of the Euclidean chiral basis
+// (gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = [[0, 1], [1, 0]]),
+// as the column and phase i^k of the one nonzero entry of each row.
+static void gamma_tables(int col[16][4], int ph[16][4]) {
+    using C = std::complex<double>;
+    const C I(0, 1);
+    C g[4][4][4] = {};
+    // gamma_1
+    g[0][0][3] = -I; g[0][1][2] = -I; g[0][2][1] = I; g[0][3][0] = I;
+    // gamma_2
+    g[1][0][3] = -1.0; g[1][1][2] = 1.0; g[1][2][1] = 1.0; g[1][3][0] = -1.0;
+    // gamma_3
+    g[2][0][2] = -I; g[2][1][3] = I; g[2][2][0] = I; g[2][3][1] = -I;
+    // gamma_4
+    g[3][0][2] = 1.0; g[3][1][3] = 1.0; g[3][2][0] = 1.0; g[3][3][1] = 1.0;
+    for (int n = 0; n < 16; n++) {
+        C m[4][4] = {};
+        for (int i = 0; i < 4; i++) m[i][i] = 1.0;
+        for (int mu = 0; mu < 4; mu++) {
+            if (!((n >> mu) & 1)) continue;
+            C t[4][4] = {};
+            for (int i = 0; i < 4; i++)
+                for (int j = 0; j < 4; j++)
+                    for (int k = 0; k < 4; k++) t[i][j] += m[i][k] * g[mu][k][j];
+            std::memcpy(m, t, sizeof(t));
+        }
+        for (int a = 0; a < 4; a++) {
+            for (int b = 0; b < 4; b++) {
+                if (std::abs(m[a][b]) < 0.5) continue;
+                col[n][a] = b;
+                C v = m[a][b];
+                ph[n][a] = v.real() > 0.5 ? 0 : (v.imag() > 0.5 ? 1 : (v.real() < -0.5 ? 2 : 3));
+            }
+        }
+    }
+}
+
+}  // namespace tmq
+
+using namespace tmq;
+
+extern "C" {
+
+int32_t tm_abi_version(void) { return TM_ABI_VERSION; }
+
+tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
+    if (!lat || !out) return TM_EINVAL;
+    *out = nullptr;
+    long V = 1;
+    for (int d = 0; d < 4; d++) {
+        if (lat->dims[d] < 2 || lat->dims[d] > 4096) return TM_EINVAL;
+        V *= lat->dims[d];
+    }
+    if (V >= (1L << 26)) return TM_EINVAL;
+    if (lat->t_bc != 1 && lat->t_bc != -1) return TM_EINVAL;
+    if (!std::isfinite(lat->kappa) || !std::isfinite(lat->mu)) return TM_EINVAL;
+    tm_ctx* ctx = new tm_ctx();
+    ctx->lat = *lat;
+    ctx->stream = (hipStream_t)hip_stream;
+    Geom& g = ctx->geo;
+    for (int d = 0; d < 4; d++) g.L[d] = lat->dims[d];
+    g.t_bc = lat->t_bc;
+    g.V = V;
+    g.Vs = (V + 255) / 256 * 256;
+    for (int d = 0; d < 3; d++) {
+        uint64_t dd = (uint64_t)g.L[d];
+        uint64_t m = ((1ULL << 32) + dd - 1) / dd;
+        // exactness of floor(n * m / 2^32) = n / d for every n < V
+        uint64_t e = m * dd - (1ULL << 32);
+        if ((uint64_t)V * e >= (1ULL << 32)) {
+            delete ctx;
+            return TM_EINVAL;
+        }
+        g.m[d] = (uint32_t)m;
+    }
+    ctx->twist = 2.0 * lat->kappa * lat->mu;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return TM_EDEVICE;
+    }
+    int col[16][4], ph[16][4];
+    gamma_tables(col, ph);
+    int tab[128];
+    std::memcpy(tab, col, sizeof(col));
+    std::memcpy(tab + 64, ph, sizeof(ph));
+    if (hipMalloc(&ctx->gam_dev, sizeof(tab)) != hipSuccess ||
+        hipMemcpy(ctx->gam_dev, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return TM_EDEVICE;
+    }
+    *out = ctx;
+    return TM_OK;
+}
+
+tm_status tm_destroy(tm_ctx* ctx) {
+    if (!ctx) return TM_EINVAL;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->ws)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    if (ctx->gauge64) (void)hipFree(ctx->gauge64);
+    if (ctx->gauge32) (void)hipFree(ctx->gauge32);
+    if (ctx->gam_dev) (void)hipFree(ctx->gam_dev);
+    if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    delete ctx;
+    return TM_OK;
+}
+
+const char* tm_last_error(const tm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+tm_status tm_gauge_load(tm_ctx* ctx, const double* links_host) {
+    if (!ctx || !links_host) return set_error(ctx, TM_EINVAL, "null argument");
+    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    const Geom& g = ctx->geo;
+    const size_t canon_bytes = (size_t)g.V * 4 * 9 * 16;
+    if (!ctx->gauge64) TM_HIP(hipMalloc(&ctx->gauge64, (size_t)4 * 9 * 16 * g.Vs));
+    if (!ctx->gauge32) TM_HIP(hipMalloc(&ctx->gauge32, (size_t)4 * 3 * 16 * g.Vs));
+    void* tmp = nullptr;
+    TM_HIP(hipMalloc(&tmp, canon_bytes));
+    hipError_t e = hipMemcpyAsync(tmp, links_host, canon_bytes, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) {
+        launch_gauge_convert(ctx->stream, g, (const double*)tmp, ctx->gauge64, ctx->gauge32);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return dev_error(ctx, e, "gauge load");
+    ctx->gauge_loaded = true;
+    return TM_OK;
+}
+
+size_t tm_field_bytes(const tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t layout) {
+    if (!ctx || prec < 0 || prec > 3 || nrhs < 0) return 0;
+    if (layout == TM_LAYOUT_NATIVE) return field_bytes(ctx->geo, prec, nrhs);
+    const size_t e = prec == TM_PREC_F64 ? 16 : (prec == TM_PREC_F32 ? 8 : 4);
+    return (size_t)nrhs * ctx->geo.V * 12 * e;
+}
+
+tm_status tm_field_convert(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t to_native, const void* in_dev,
+                           void* out_dev) {
+    if (!ctx) return TM_EINVAL;
+    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    if (prec < 0 || prec > 3 || nrhs < 1 || nrhs > 65535 || !in_dev || !out_dev || in_dev == out_dev)
+        return set_error(ctx, TM_EINVAL, "tm_field_convert: bad argument");
+    launch_field_convert(ctx->stream, ctx->geo, prec, nrhs, to_native != 0, in_dev, out_dev);
+    TM_HIP(hipGetLastError());
+    return TM_OK;
+}
+
+tm_status tm_dslash(tm_ctx* ctx, int32_t op, int32_t prec, int32_t nrhs, int32_t layout, const void* in_dev,
+                    void* out_dev) {
+    if (!ctx) return TM_EINVAL;
+    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tm_dslash: no gauge field loaded");
+    if (op < 0 || op > 3 || prec < 0 || prec > 3 || nrhs < 1 || nrhs > 65535 || !in_dev || !out_dev ||
+        in_dev == out_dev || (layout != TM_LAYOUT_CANONICAL && layout != TM_LAYOUT_NATIVE))
+        return set_error(ctx, TM_EINVAL, "tm_dslash: bad argument");
+    const Geom& g = ctx->geo;
+    const void* gauge = prec == TM_PREC_F64 ? ctx->gauge64 : ctx->gauge32;
+    const int nr = (prec == TM_PREC_F64) ? 1 : (nrhs % 4 == 0 ? 4 : (nrhs % 2 == 0 ? 2 : 1));
+    const size_t fb = field_bytes(g, prec, nrhs);
+    const void* in = in_dev;
+    void* out = out_dev;
+    tm_status st = TM_OK;
+    if (layout == TM_LAYOUT_CANONICAL) {
+        void* a = ws_get(ctx, "dslash_in", fb, &st);
+        if (!a) return st;
+        void* b = ws_get(ctx, "dslash_out", fb, &st);
+        if (!b) return st;
+        launch_field_convert(ctx->stream, g, prec, nrhs, true, in_dev, a);
+        in = a;
+        out = b;
+    }
+    const double bs = prec == TM_PREC_F64 ? 8 : (prec == TM_PREC_F32 ? 4 : 2);
+    const double gb = prec == TM_PREC_F64 ? 4 * 18 * 8 : 4 * 12 * 4;
+    const double bytes_one = (double)g.V * (nrhs * 48.0 * bs + gb);
+    if (op == TM_OP_MDAGM) {
+        void* tmp = ws_get(ctx, "dslash_tmp", fb, &st);
+        if (!tmp) return st;
+        prof_begin(ctx, TM_KC_APPLY);
+        launch_apply(ctx->stream, g, prec, gauge, ctx->lat.kappa, ctx->twist, 0, nrhs, in, tmp, nr, nullptr);
+        prof_end(ctx, TM_KC_APPLY, bytes_one);
+        prof_begin(ctx, TM_KC_APPLY);
+        launch_apply(ctx->stream, g, prec, gauge, ctx->lat.kappa, ctx->twist, 1, nrhs, tmp, out, nr, nullptr);
+        prof_end(ctx, TM_KC_APPLY, bytes_one);
+    } else {
+        prof_begin(ctx, TM_KC_APPLY);
+        launch_apply(ctx->stream, g, prec, gauge, ctx->lat.kappa, ctx->twist, op, nrhs, in, out, nr, nullptr);
+        prof_end(ctx, TM_KC_APPLY, bytes_one);
+    }
+    if (layout == TM_LAYOUT_CANONICAL) launch_field_convert(ctx->stream, g, prec, nrhs, false, out, out_dev);
+    TM_HIP(hipGetLastError());
+    return TM_OK;
+}
+
+tm_status tm_noise_z4(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* ids_host, double* out_dev) {
+    if (!ctx) return TM_EINVAL;
+    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    if (nsrc < 1 || nsrc > 65535 || !ids_host || !out_dev) return set_error(ctx, TM_EINVAL, "tm_noise_z4: bad argument");
+    tm_status st = TM_OK;
+    uint64_t* ids = (uint64_t*)ws_get(ctx, "noise_ids", sizeof(uint64_t) * nsrc, &st);
+    if (!ids) return st;
+    TM_HIP(hipMemcpyAsync(ids, ids_host, sizeof(uint64_t) * nsrc, hipMemcpyHostToDevice, ctx->stream));
+    launch_noise_c128(ctx->stream, ctx->geo, seed_mix(seed), ids, nsrc, out_dev);
+    TM_HIP(hipGetLastError());
+    TM_HIP(hipStreamSynchronize(ctx->stream));  // ids_host may be released on return
+    return TM_OK;
+}
+
+tm_status tm_profile_enable(tm_ctx* ctx, int32_t on) {
+    if (!ctx) return TM_EINVAL;
+    TM_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->prof = on != 0;
+    ctx->recs.clear();
+    ctx->ev_used = 0;
+    for (int k = 0; k < TM_KC_COUNT; k++) {
+        ctx->prof_launches[k] = 0;
+        ctx->prof_ms[k] = 0;
+        ctx->prof_bytes[k] = 0;
+    }
+    return TM_OK;
+}
+
+tm_status tm_profile_read(tm_ctx* ctx, int64_t* launches, double* ms, double* bytes) {
+    if (!ctx) return TM_EINVAL;
+    TM_HIP(hipStreamSynchronize(ctx->stream));
+    for (auto& r : ctx->recs) {
+        float t = 0;
+        TM_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        ctx->prof_launches[r.kc] += 1;
+        ctx->prof_ms[r.kc] += t;
+        ctx->prof_bytes[r.kc] += r.bytes;
+    }
+    ctx->recs.clear();
+    ctx->ev_used = 0;
+    for (int k = 0; k < TM_KC_COUNT; k++) {
+        if (launches) launches[k] = ctx->prof_launches[k];
+        if (ms) ms[k] = ctx->prof_ms[k];
+        if (bytes) bytes[k] = ctx->prof_bytes[k];
+    }
+    return TM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Host-side context of the library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/tmqcd.h"
+#include "tm_kernels.h"
+#include "tm_types.h"
+
+struct tm_ctx {
+    tm_lattice lat;
+    tmq::Geom geo;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double twist = 0;  // 2 kappa mu
+
+    void* gauge64 = nullptr;  // double2 [4][9][Vs]
+    void* gauge32 = nullptr;  // float4  [4][3][Vs]
+    bool gauge_loaded = false;
+
+    struct Buf {
+        void* p = nullptr;
+        size_t bytes = 0;
+    };
+    std::map<std::string, Buf> ws;  // grow-only named device workspace
+
+    tmq::CgScal* scal_host = nullptr;  // pinned mirror for stop checks
+    int scal_host_n = 0;
+
+    // Gamma_n tables on the device (row a -> column, phase i^k)
+    int* gam_dev = nullptr;
+
+    std::string err;
+    int sticky = 0;
+
+    // instrumentation
+    bool prof = false;
+    struct Rec {
+        int kc;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    int64_t prof_launches[TM_KC_COUNT] = {0};
+    double prof_ms[TM_KC_COUNT] = {0};
+    double prof_bytes[TM_KC_COUNT] = {0};
+};
+
+namespace tmq {
+
+tm_status set_error(tm_ctx* ctx, tm_status code, const std::string& msg);
+tm_status dev_error(tm_ctx* ctx, hipError_t e, const char* what);
+void* ws_get(tm_ctx* ctx, const std::string& name, size_t bytes, tm_status* st);
+size_t field_bytes(const Geom& g, int prec, int nrhs);
+uint64_t seed_mix(uint64_t seed);
+
+// instrumentation around a launch of kernel class kc moving `bytes`
+void prof_begin(tm_ctx* ctx, int kc);
+void prof_end(tm_ctx* ctx, int kc, double bytes);
+
+}  // namespace tmq
+
+#define TM_HIP(call)                                             \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return tmq::dev_error(ctx, e_, #call); \
+    } while (0)

@@ -1,0 +1,81 @@
+// Host-visible launchers of the gfx950 kernels and their argument blocks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tm_types.h"
+
+namespace tmq {
+
+struct CgArgs {
+    Geom geo;
+    const void* gauge;  // native gauge of the iteration precision
+    double kappa;
+    double twist;       // 2 kappa mu
+    void* p;
+    void* t;
+    void* r;
+    void* x;
+    void* rho;          // recursive true residual (stop on |eta - M x|)
+    CgScal* scal;
+    double* partials;   // [nrhs][nblocks]
+    double* partials2;  // [nrhs][nblocks]
+    unsigned int* counters;  // [nrhs], zero between launches
+    int nrhs;
+};
+
+struct ContractArgs {
+    Geom geo;
+    uint64_t seed_mixed;
+    const uint64_t* ids;  // [nrhs] source ids (device)
+    const void* sol;      // native solutions (F64 or F32 storage)
+    int nrhs;
+    int npx, npy, npz;    // distinct momentum components per axis (<= 3)
+    const double2* phx;   // [npx][Lx] exp(-2 pi i n x / Lx)
+    const double2* phy;   // [npy][Ly]
+    const double2* phz;   // [npz][Lz]
+    int n_mom;
+    const int* mom_idx;   // [n_mom][3] indices into the per-axis lists
+    const int* gam_col;   // [16][4] column of the nonzero of row a of Gamma_n
+    const int* gam_ph;    // [16][4] its value i^k as k
+    double2* A;           // scratch [nrhs][Lt][Lz][npy][Lx][16]
+    double2* B;           // scratch [nrhs][Lt][Lz][npx][npy][16]
+    double2* out;         // loops, [slot][16][n_mom][Lt]
+    const int* out_slot;  // [nrhs] output slot of each right-hand side (device)
+    long out_stride;      // complex elements between slots
+};
+
+// operator
+void launch_apply(hipStream_t st, const Geom& g, int prec, const void* gauge, double kappa, double twist, int op,
+                  int nrhs, const void* in, void* out, int nr, const CgScal* gate);
+void launch_apply_f32in_f64(hipStream_t st, const Geom& g, const void* gauge64, double kappa, double twist, int op,
+                            int nrhs, const void* in32, void* out64, const CgScal* gate);
+
+// CG
+void launch_scal_init(hipStream_t st, CgScal* sc, int n, double tol2, int maxit, int stop, int reliable,
+                      double delta2);
+void launch_cg_init(hipStream_t st, const CgArgs& a, int prec, bool track, const void* eta);
+void launch_cg_mp(hipStream_t st, const CgArgs& a, int prec, int nr);
+void launch_cg_upd(hipStream_t st, const CgArgs& a, int prec, int nr, bool track);
+void launch_cg_p(hipStream_t st, const CgArgs& a, int prec);
+void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64);
+void launch_rel_flush(hipStream_t st, const CgArgs& a, void* x64, int force);
+void launch_rel_resid(hipStream_t st, const CgArgs& a, const void* gauge64, const void* b64, const void* t64);
+void launch_true_resid(hipStream_t st, const CgArgs& a, int xprec, const void* gauge64, uint64_t seed_mixed,
+                       const uint64_t* ids);
+
+// layout and noise
+void launch_field_convert(hipStream_t st, const Geom& g, int prec, int nrhs, bool to_native, const void* in,
+                          void* out);
+void launch_native_to_c128(hipStream_t st, const Geom& g, int prec, int nrhs, const void* in, double* out);
+void launch_gauge_convert(hipStream_t st, const Geom& g, const double* canon, void* g64, void* g32);
+void launch_noise_native(hipStream_t st, const Geom& g, int prec, uint64_t seed_mixed, const uint64_t* ids, int nrhs,
+                         void* out);
+void launch_noise_c128(hipStream_t st, const Geom& g, uint64_t seed_mixed, const uint64_t* ids, int nrhs, double* out);
+
+// loops
+void launch_contract(hipStream_t st, const ContractArgs& a, int xprec);
+void launch_tsm_final(hipStream_t st, const double* ps, long nl, int n_hp, int n_lp, double* out, double* err);
+
+}  // namespace tmq

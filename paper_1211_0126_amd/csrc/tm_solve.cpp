@@ -1,0 +1,497 @@
+// Solver and TSM drivers: tsm_solve_batch, tsm_contract, tsm_loops.
+//
+// A block of right-hand sides is solved together: all vectors and all
+// per-source scalars live on the device, every CG step is three kernel
+// launches, and the host only polls the per-source stop flags once per
+// chunk of steps.  Each source's arithmetic is independent of the others in
+// its block (per-source scalars, masks and reductions in a fixed order), so
+// the LP solution of a source does not depend on how the sources are
+// batched: the HP-minus-LP correction of Eq. 4 sees one fixed LP map.
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "tm_ctx.h"
+
+namespace tmq {
+
+static const int kMaxBlock = 32;
+static const int kIterCap = 20000;  // safety cap for max_iter = -1
+
+static tm_status check_solve_params(tm_ctx* ctx, const tsm_solve_params* p) {
+    if (!p) return set_error(ctx, TM_EINVAL, "null solve parameters");
+    if (p->prec < 0 || p->prec > 3) return set_error(ctx, TM_EINVAL, "solve: bad precision");
+    if (p->solver != TM_SOLVER_CG) return set_error(ctx, TM_ENOTSUP, "solve: only TM_SOLVER_CG is available here");
+    if (!(p->tol >= 0) || !std::isfinite(p->tol)) return set_error(ctx, TM_EINVAL, "solve: bad tolerance");
+    if (p->max_iter < -1) return set_error(ctx, TM_EINVAL, "solve: bad max_iter");
+    if (p->stop != TM_STOP_NORMAL && p->stop != TM_STOP_TRUE) return set_error(ctx, TM_EINVAL, "solve: bad stop");
+    if (p->reliable != 0 && p->reliable != 1) return set_error(ctx, TM_EINVAL, "solve: bad reliable flag");
+    if (p->reliable) {
+        if (p->prec != TM_PREC_F32)
+            return set_error(ctx, TM_ENOTSUP, "solve: reliable updates need FP32 iterations");
+        if (p->stop != TM_STOP_NORMAL)
+            return set_error(ctx, TM_ENOTSUP, "solve: reliable updates stop on the normal-equation residual");
+        if (!(p->delta > 0 && p->delta < 1)) return set_error(ctx, TM_EINVAL, "solve: delta must be in (0, 1)");
+    }
+    if (p->rhs_block < 0 || p->rhs_block > kMaxBlock) return set_error(ctx, TM_EINVAL, "solve: rhs_block in 0..32");
+    return TM_OK;
+}
+
+static int default_block(const tsm_solve_params* p) {
+    if (p->rhs_block > 0) return p->rhs_block;
+    if (p->prec == TM_PREC_F64) return 4;
+    return p->reliable ? 8 : 16;
+}
+
+// right-hand sides per lane in the stencil kernels
+static int lane_rhs(const tsm_solve_params* p, int block) {
+    if (p->prec == TM_PREC_F64 || p->stop == TM_STOP_TRUE) return 1;
+    if (block % 4 == 0) return 4;
+    if (block % 2 == 0) return 2;
+    return 1;
+}
+
+static tm_status ensure_scal_host(tm_ctx* ctx, int n) {
+    if (ctx->scal_host_n >= n) return TM_OK;
+    if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
+    ctx->scal_host = nullptr;
+    ctx->scal_host_n = 0;
+    TM_HIP(hipHostMalloc((void**)&ctx->scal_host, sizeof(CgScal) * kMaxBlock * 2));
+    ctx->scal_host_n = kMaxBlock * 2;
+    return TM_OK;
+}
+
+// bytes of the CG kernels per launch (algorithmic: each field touched once,
+// each link once per site)
+struct CgBytes {
+    double k1, k2, k3;
+};
+static CgBytes cg_bytes(const Geom& g, int prec, int nrhs, bool reliable_x64, bool track) {
+    const double bs = prec == P_F64 ? 8 : (prec == P_F32 ? 4 : 2);
+    const double bx = prec == P_F64 ? 8 : 4;
+    const double gb = prec == P_F64 ? 4 * 18 * 8 : 4 * 12 * 4;
+    (void)reliable_x64;
+    CgBytes b;
+    b.k1 = (double)g.V * (nrhs * 48.0 * bs + gb);
+    b.k2 = (double)g.V * (nrhs * (24.0 * bs + 48.0 * bs + 24.0 * bs + 48.0 * bx + (track ? 48.0 * bs : 0.0)) + gb);
+    b.k3 = (double)g.V * nrhs * 72.0 * bs;
+    return b;
+}
+
+struct BlockResult {
+    void* x;
+    int xprec;
+};
+
+// Solve nrhs sources (ids on the device) with the given settings.  On
+// return the stream is synchronised, ctx->scal_host[0..nrhs) holds the final
+// per-source state and res the native solutions.
+static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t seed_mixed, const uint64_t* ids_dev,
+                             int nrhs, int nr, const std::string& tag, BlockResult* res) {
+    const Geom& g = ctx->geo;
+    hipStream_t st = ctx->stream;
+    tm_status s = TM_OK;
+    const int prec = p->prec;
+    const bool rel = p->reliable != 0;
+    const bool track = p->stop == TM_STOP_TRUE;
+    const size_t nblk = (size_t)((g.V + 255) / 256);
+    const size_t fb = field_bytes(g, prec, nrhs);
+    const size_t fx = field_bytes(g, prec == P_F64 ? P_F64 : P_F32, nrhs);
+    const size_t f64 = field_bytes(g, P_F64, nrhs);
+
+    CgArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geo = g;
+    a.gauge = prec == P_F64 ? ctx->gauge64 : ctx->gauge32;
+    a.kappa = ctx->lat.kappa;
+    a.twist = ctx->twist;
+    a.nrhs = nrhs;
+    a.p = ws_get(ctx, tag + "_p", fb, &s);
+    a.t = ws_get(ctx, tag + "_t", fb, &s);
+    a.r = ws_get(ctx, tag + "_r", fb, &s);
+    a.x = ws_get(ctx, tag + "_x", fx, &s);
+    a.scal = (CgScal*)ws_get(ctx, tag + "_scal", sizeof(CgScal) * kMaxBlock, &s);
+    a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * nblk * kMaxBlock, &s);
+    a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * nblk * kMaxBlock, &s);
+    a.counters = (unsigned int*)ws_get(ctx, "counters", sizeof(unsigned int) * kMaxBlock, &s);
+    if (track) a.rho = ws_get(ctx, tag + "_rho", fb, &s);
+    void* eta = nullptr;
+    void *b64 = nullptr, *x64 = nullptr, *t64 = nullptr;
+    if (rel) {
+        eta = ws_get(ctx, tag + "_eta64", f64, &s);
+        b64 = ws_get(ctx, tag + "_b64", f64, &s);
+        x64 = ws_get(ctx, tag + "_x64", f64, &s);
+        t64 = ws_get(ctx, tag + "_t64", f64, &s);
+    } else {
+        eta = ws_get(ctx, tag + "_eta", fb, &s);
+    }
+    if (s != TM_OK) return s;
+    if ((s = ensure_scal_host(ctx, nrhs)) != TM_OK) return s;
+
+    const double tol2 = p->tol * p->tol;
+    const double delta2 = rel ? p->delta * p->delta : 0.0;
+    launch_scal_init(st, a.scal, nrhs, tol2, p->max_iter, p->stop, rel ? 1 : 0, delta2);
+
+    const CgBytes by = cg_bytes(g, prec, nrhs, rel, track);
+    const double gb64 = 4 * 18 * 8.0;
+
+    // sources and right-hand side b = M^dag eta
+    prof_begin(ctx, TM_KC_OTHER);
+    if (rel) {
+        launch_noise_native(st, g, P_F64, seed_mixed, ids_dev, nrhs, eta);
+        launch_apply(st, g, P_F64, ctx->gauge64, ctx->lat.kappa, ctx->twist, 1, nrhs, eta, b64, 1, nullptr);
+        launch_rel_init(st, a, b64, x64);
+    } else {
+        launch_noise_native(st, g, prec, seed_mixed, ids_dev, nrhs, eta);
+        launch_apply(st, g, prec, a.gauge, ctx->lat.kappa, ctx->twist, 1, nrhs, eta, a.r, nr, nullptr);
+        launch_cg_init(st, a, prec, track, eta);
+    }
+    prof_end(ctx, TM_KC_OTHER, 0.0);
+    TM_HIP(hipGetLastError());
+
+    const int chunk = rel ? 16 : 8;
+    int done = 0;
+    for (;;) {
+        int k = chunk;
+        if (p->max_iter >= 0) k = std::max(1, std::min(chunk, p->max_iter - done));
+        for (int i = 0; i < k; i++) {
+            prof_begin(ctx, TM_KC_DSLASH);
+            launch_cg_mp(st, a, prec, nr);
+            prof_end(ctx, TM_KC_DSLASH, by.k1);
+            prof_begin(ctx, TM_KC_DSLASH_UPD);
+            launch_cg_upd(st, a, prec, nr, track);
+            prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
+            if (rel) {
+                prof_begin(ctx, TM_KC_OTHER);
+                launch_rel_flush(st, a, x64, 0);
+                launch_apply(st, g, P_F64, ctx->gauge64, ctx->lat.kappa, ctx->twist, 0, nrhs, x64, t64, 1, a.scal);
+                launch_rel_resid(st, a, ctx->gauge64, b64, t64);
+                prof_end(ctx, TM_KC_OTHER, 0.0);
+            }
+            prof_begin(ctx, TM_KC_BLAS);
+            launch_cg_p(st, a, prec);
+            prof_end(ctx, TM_KC_BLAS, by.k3);
+        }
+        TM_HIP(hipGetLastError());
+        done += k;
+        TM_HIP(hipMemcpyAsync(ctx->scal_host, a.scal, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        bool any = false;
+        for (int r = 0; r < nrhs; r++) any |= ctx->scal_host[r].active != 0;
+        if (!any) break;
+        if (done >= kIterCap) break;
+    }
+    if (rel) {
+        launch_rel_flush(st, a, x64, 1);
+        res->x = x64;
+        res->xprec = P_F64;
+    } else {
+        res->x = a.x;
+        res->xprec = prec == P_F64 ? P_F64 : P_F32;
+    }
+    if (p->true_resid) {
+        CgArgs at = a;
+        at.x = res->x;
+        prof_begin(ctx, TM_KC_OTHER);
+        launch_true_resid(st, at, res->xprec, ctx->gauge64, seed_mixed, ids_dev);
+        prof_end(ctx, TM_KC_OTHER, (double)g.V * (nrhs * 24.0 * (res->xprec == P_F64 ? 8 : 4) + gb64));
+    }
+    TM_HIP(hipGetLastError());
+    TM_HIP(hipMemcpyAsync(ctx->scal_host, a.scal, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    return TM_OK;
+}
+
+static void fill_stats(const CgScal& q, tsm_solve_stats* o) {
+    o->iters = q.iters;
+    o->converged = q.status == 1;
+    o->truncated = q.status == 2;
+    o->fell_back = 0;
+    if (q.stop == 1)
+        o->resid_iterated = q.ee > 0 ? std::sqrt(q.rho2 / q.ee) : 0.0;
+    else
+        o->resid_iterated = q.bb > 0 ? std::sqrt(q.rr / q.bb) : 0.0;
+    o->resid_true = q.resid_true;
+}
+
+// ---------------------------------------------------------------------------
+// contraction set-up
+// ---------------------------------------------------------------------------
+struct MomPlan {
+    int np[3];
+    std::vector<int> vals[3];
+    std::vector<int> idx;  // [n_mom][3]
+};
+
+static tm_status plan_momenta(tm_ctx* ctx, int n_mom, const int32_t* mom, MomPlan* mp) {
+    if (n_mom < 1 || !mom) return set_error(ctx, TM_EINVAL, "need at least one momentum");
+    for (int d = 0; d < 3; d++) {
+        mp->vals[d].clear();
+        for (int m = 0; m < n_mom; m++) {
+            int v = mom[3 * m + d];
+            if (std::find(mp->vals[d].begin(), mp->vals[d].end(), v) == mp->vals[d].end()) mp->vals[d].push_back(v);
+        }
+        if (mp->vals[d].size() > 3)
+            return set_error(ctx, TM_ENOTSUP, "more than 3 distinct momentum components on one axis");
+        mp->np[d] = (int)mp->vals[d].size();
+    }
+    mp->idx.resize(3 * n_mom);
+    for (int m = 0; m < n_mom; m++)
+        for (int d = 0; d < 3; d++)
+            mp->idx[3 * m + d] =
+                (int)(std::find(mp->vals[d].begin(), mp->vals[d].end(), mom[3 * m + d]) - mp->vals[d].begin());
+    return TM_OK;
+}
+
+struct Contractor {
+    ContractArgs a;
+};
+
+// Upload phase tables and indices; scratch sized for `maxr` sources.
+static tm_status setup_contract(tm_ctx* ctx, const MomPlan& mp, int n_mom, int maxr, uint64_t seed_mixed,
+                                Contractor* c) {
+    const Geom& g = ctx->geo;
+    tm_status s = TM_OK;
+    std::memset(&c->a, 0, sizeof(c->a));
+    ContractArgs& a = c->a;
+    a.geo = g;
+    a.seed_mixed = seed_mixed;
+    a.npx = mp.np[0];
+    a.npy = mp.np[1];
+    a.npz = mp.np[2];
+    a.n_mom = n_mom;
+    // host table: phases then indices
+    const int L0 = g.L[0], L1 = g.L[1], L2 = g.L[2];
+    std::vector<double> ph(2 * (a.npx * L0 + a.npy * L1 + a.npz * L2));
+    size_t o = 0;
+    const double twopi = 2.0 * std::acos(-1.0);
+    for (int d = 0; d < 3; d++)
+        for (int i = 0; i < mp.np[d]; i++)
+            for (int x = 0; x < g.L[d]; x++) {
+                double arg = twopi * (double)mp.vals[d][i] * x / g.L[d];
+                ph[o++] = std::cos(arg);
+                ph[o++] = -std::sin(arg);
+            }
+    double* phd = (double*)ws_get(ctx, "c_phase", sizeof(double) * ph.size(), &s);
+    int* idd = (int*)ws_get(ctx, "c_momidx", sizeof(int) * mp.idx.size(), &s);
+    if (s != TM_OK) return s;
+    TM_HIP(hipMemcpy(phd, ph.data(), sizeof(double) * ph.size(), hipMemcpyHostToDevice));
+    TM_HIP(hipMemcpy(idd, mp.idx.data(), sizeof(int) * mp.idx.size(), hipMemcpyHostToDevice));
+    a.phx = (const double2*)phd;
+    a.phy = a.phx + a.npx * L0;
+    a.phz = a.phy + a.npy * L1;
+    a.mom_idx = idd;
+    a.gam_col = ctx->gam_dev;
+    a.gam_ph = ctx->gam_dev + 64;
+    const size_t A = (size_t)maxr * g.L[3] * g.L[2] * a.npy * g.L[0] * 16 * 16;
+    const size_t B = (size_t)maxr * g.L[3] * g.L[2] * a.npx * a.npy * 16 * 16;
+    a.A = (double2*)ws_get(ctx, "c_A", A, &s);
+    a.B = (double2*)ws_get(ctx, "c_B", B, &s);
+    if (s != TM_OK) return s;
+    return TM_OK;
+}
+
+static void contract_block(tm_ctx* ctx, Contractor* c, const uint64_t* ids_dev, const void* x, int xprec, int nrhs,
+                           double2* out, const int* slots_dev, long out_stride) {
+    ContractArgs a = c->a;
+    a.ids = ids_dev;
+    a.sol = x;
+    a.nrhs = nrhs;
+    a.out = out;
+    a.out_slot = slots_dev;
+    a.out_stride = out_stride;
+    prof_begin(ctx, TM_KC_CONTRACT);
+    launch_contract(ctx->stream, a, xprec);
+    prof_end(ctx, TM_KC_CONTRACT, (double)ctx->geo.V * nrhs * 24.0 * (xprec == P_F64 ? 8 : 4));
+}
+
+}  // namespace tmq
+
+using namespace tmq;
+
+extern "C" {
+
+tm_status tsm_solve_batch(tm_ctx* ctx, const tsm_solve_params* params, uint64_t seed, int32_t nsrc,
+                          const uint64_t* ids_host, double* sol_dev, tsm_solve_stats* stats_host) {
+    if (!ctx) return TM_EINVAL;
+    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tsm_solve_batch: no gauge field loaded");
+    tm_status s = check_solve_params(ctx, params);
+    if (s != TM_OK) return s;
+    if (nsrc < 0 || (nsrc > 0 && (!ids_host || !stats_host)))
+        return set_error(ctx, TM_EINVAL, "tsm_solve_batch: bad source list");
+    if (nsrc == 0) return TM_OK;
+    const Geom& g = ctx->geo;
+    const int blk = default_block(params);
+    const int nr = lane_rhs(params, blk);
+    // ids padded to a multiple of the lane width with repeats of the last id
+    const int npad = (nsrc + nr - 1) / nr * nr;
+    std::vector<uint64_t> ids(ids_host, ids_host + nsrc);
+    ids.resize(npad, ids_host[nsrc - 1]);
+    uint64_t* ids_dev = (uint64_t*)ws_get(ctx, "solve_ids", sizeof(uint64_t) * npad, &s);
+    if (!ids_dev) return s;
+    TM_HIP(hipMemcpy(ids_dev, ids.data(), sizeof(uint64_t) * npad, hipMemcpyHostToDevice));
+    const uint64_t sm = seed_mix(seed);
+    bool warn = false;
+    for (int j0 = 0; j0 < nsrc; j0 += blk) {
+        const int nb = std::min(blk, nsrc - j0);
+        const int nbp = (nb + nr - 1) / nr * nr;
+        BlockResult res;
+        s = solve_block(ctx, params, sm, ids_dev + j0, nbp, nr, "sb", &res);
+        if (s != TM_OK) return s;
+        for (int r = 0; r < nb; r++) {
+            fill_stats(ctx->scal_host[r], stats_host + j0 + r);
+            if (params->max_iter < 0 && ctx->scal_host[r].status != 1) warn = true;
+        }
+        if (sol_dev) {
+            launch_native_to_c128(ctx->stream, g, res.xprec, nb, res.x, sol_dev + (size_t)j0 * g.V * 24);
+            TM_HIP(hipGetLastError());
+        }
+    }
+    TM_HIP(hipStreamSynchronize(ctx->stream));
+    return warn ? TM_WARN_NOT_CONVERGED : TM_OK;
+}
+
+tm_status tsm_contract(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* ids_host, const double* sol_dev,
+                       int32_t n_mom, const int32_t* mom_host, double* loops_host) {
+    if (!ctx) return TM_EINVAL;
+    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    if (nsrc < 1 || !ids_host || !sol_dev || !loops_host) return set_error(ctx, TM_EINVAL, "tsm_contract: bad argument");
+    const Geom& g = ctx->geo;
+    MomPlan mp;
+    tm_status s = plan_momenta(ctx, n_mom, mom_host, &mp);
+    if (s != TM_OK) return s;
+    const int blk = std::min(nsrc, kMaxBlock);
+    Contractor c;
+    if ((s = setup_contract(ctx, mp, n_mom, blk, seed_mix(seed), &c)) != TM_OK) return s;
+    const long nl = 16L * n_mom * g.L[3];
+    uint64_t* ids_dev = (uint64_t*)ws_get(ctx, "contract_ids", sizeof(uint64_t) * nsrc, &s);
+    int* slots = (int*)ws_get(ctx, "contract_slots", sizeof(int) * nsrc, &s);
+    void* nat = ws_get(ctx, "contract_nat", field_bytes(g, P_F64, blk), &s);
+    double* out = (double*)ws_get(ctx, "contract_out", sizeof(double) * 2 * nl * nsrc, &s);
+    if (s != TM_OK) return s;
+    std::vector<int> sl(nsrc);
+    for (int i = 0; i < nsrc; i++) sl[i] = i;
+    TM_HIP(hipMemcpy(ids_dev, ids_host, sizeof(uint64_t) * nsrc, hipMemcpyHostToDevice));
+    TM_HIP(hipMemcpy(slots, sl.data(), sizeof(int) * nsrc, hipMemcpyHostToDevice));
+    for (int j0 = 0; j0 < nsrc; j0 += blk) {
+        const int nb = std::min(blk, nsrc - j0);
+        launch_field_convert(ctx->stream, g, P_F64, nb, true, sol_dev + (size_t)j0 * g.V * 24, nat);
+        contract_block(ctx, &c, ids_dev + j0, nat, P_F64, nb, (double2*)out, slots + j0, nl);
+        TM_HIP(hipGetLastError());
+    }
+    TM_HIP(hipMemcpyAsync(loops_host, out, sizeof(double) * 2 * nl * nsrc, hipMemcpyDeviceToHost, ctx->stream));
+    TM_HIP(hipStreamSynchronize(ctx->stream));
+    return TM_OK;
+}
+
+tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double* err_host, double* per_source_host,
+                    tsm_solve_stats* stats_host, tsm_run_stats* run_stats) {
+    using clk = std::chrono::steady_clock;
+    if (!ctx) return TM_EINVAL;
+    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tsm_loops: no gauge field loaded");
+    if (!P || !loops_host) return set_error(ctx, TM_EINVAL, "tsm_loops: null argument");
+    if (P->n_hp < 0 || P->n_lp < 0) return set_error(ctx, TM_EINVAL, "tsm_loops: negative source count");
+    tm_status s = check_solve_params(ctx, &P->lp);
+    if (s != TM_OK) return s;
+    if ((s = check_solve_params(ctx, &P->hp)) != TM_OK) return s;
+    const Geom& g = ctx->geo;
+    MomPlan mp;
+    if ((s = plan_momenta(ctx, P->n_mom, P->mom_host, &mp)) != TM_OK) return s;
+    const int N = P->n_hp + P->n_lp;
+    const long nl = 16L * P->n_mom * g.L[3];
+    hipStream_t st = ctx->stream;
+    const uint64_t sm = seed_mix(P->seed);
+
+    const int blp = default_block(&P->lp), bhp = default_block(&P->hp);
+    const int nr_lp = lane_rhs(&P->lp, blp), nr_hp = lane_rhs(&P->hp, bhp);
+    Contractor c;
+    if ((s = setup_contract(ctx, mp, P->n_mom, std::max(blp, bhp) + 4, sm, &c)) != TM_OK) return s;
+
+    // per-source loops [N][2][nl], source ids, output slots (ids padded at the end)
+    const int Npad = N + 8;
+    double* ps = (double*)ws_get(ctx, "tsm_ps", sizeof(double) * 2 * 2 * nl * std::max(N, 1), &s);
+    uint64_t* ids_dev = (uint64_t*)ws_get(ctx, "tsm_ids", sizeof(uint64_t) * Npad, &s);
+    int* slots_dev = (int*)ws_get(ctx, "tsm_slots", sizeof(int) * 2 * Npad, &s);
+    double* fin = (double*)ws_get(ctx, "tsm_fin", sizeof(double) * 2 * 2 * 3 * nl, &s);
+    if (s != TM_OK) return s;
+    std::vector<uint64_t> ids(Npad);
+    std::vector<int> slots(2 * Npad);
+    for (int j = 0; j < Npad; j++) {
+        ids[j] = (uint64_t)std::min(j, std::max(N - 1, 0));
+        slots[j] = 2 * std::min(j, std::max(N - 1, 0));              // LP slot
+        slots[Npad + j] = 2 * std::min(j, std::max(N - 1, 0)) + 1;   // HP slot
+    }
+    TM_HIP(hipMemcpy(ids_dev, ids.data(), sizeof(uint64_t) * Npad, hipMemcpyHostToDevice));
+    TM_HIP(hipMemcpy(slots_dev, slots.data(), sizeof(int) * 2 * Npad, hipMemcpyHostToDevice));
+    TM_HIP(hipMemsetAsync(ps, 0, sizeof(double) * 2 * 2 * nl * std::max(N, 1), st));
+
+    tsm_run_stats rs;
+    std::memset(&rs, 0, sizeof(rs));
+    bool warn = false;
+    auto record = [&](int j0, int nb, int slot, bool hp) {
+        for (int r = 0; r < nb; r++) {
+            const CgScal& q = ctx->scal_host[r];
+            if (stats_host) fill_stats(q, stats_host + 2 * (j0 + r) + slot);
+            if (hp) {
+                rs.hp_iters += q.iters;
+                rs.max_hp_resid_true = std::max(rs.max_hp_resid_true, q.resid_true);
+                if (q.status != 1) {
+                    rs.hp_not_converged++;
+                    if (P->hp.max_iter < 0) warn = true;
+                }
+            } else {
+                rs.lp_iters += q.iters;
+                rs.max_lp_resid_true = std::max(rs.max_lp_resid_true, q.resid_true);
+            }
+        }
+    };
+    if (stats_host) std::memset(stats_host, 0, sizeof(tsm_solve_stats) * 2 * N);
+
+    auto t0 = clk::now();
+    // HP set: LP and HP solves of ids 0..n_hp-1
+    const int bh = std::min(blp, bhp);
+    for (int j0 = 0; j0 < P->n_hp; j0 += bh) {
+        const int nb = std::min(bh, P->n_hp - j0);
+        BlockResult res;
+        const int nbl = (nb + nr_lp - 1) / nr_lp * nr_lp;
+        if ((s = solve_block(ctx, &P->lp, sm, ids_dev + j0, nbl, nr_lp, "lp", &res)) != TM_OK) return s;
+        record(j0, nb, 0, false);
+        contract_block(ctx, &c, ids_dev + j0, res.x, res.xprec, nb, (double2*)ps, slots_dev + j0, nl);
+        const int nbh = (nb + nr_hp - 1) / nr_hp * nr_hp;
+        if ((s = solve_block(ctx, &P->hp, sm, ids_dev + j0, nbh, nr_hp, "hp", &res)) != TM_OK) return s;
+        record(j0, nb, 1, true);
+        contract_block(ctx, &c, ids_dev + j0, res.x, res.xprec, nb, (double2*)ps, slots_dev + Npad + j0, nl);
+        TM_HIP(hipGetLastError());
+    }
+    TM_HIP(hipStreamSynchronize(st));
+    auto t1 = clk::now();
+    // LP set: ids n_hp..N-1
+    for (int j0 = P->n_hp; j0 < N; j0 += blp) {
+        const int nb = std::min(blp, N - j0);
+        const int nbl = (nb + nr_lp - 1) / nr_lp * nr_lp;
+        BlockResult res;
+        if ((s = solve_block(ctx, &P->lp, sm, ids_dev + j0, nbl, nr_lp, "lp", &res)) != TM_OK) return s;
+        record(j0, nb, 0, false);
+        contract_block(ctx, &c, ids_dev + j0, res.x, res.xprec, nb, (double2*)ps, slots_dev + j0, nl);
+        TM_HIP(hipGetLastError());
+    }
+    launch_tsm_final(st, ps, nl, P->n_hp, P->n_lp, fin, fin + 2 * 3 * nl);
+    TM_HIP(hipGetLastError());
+    TM_HIP(hipStreamSynchronize(st));
+    auto t2 = clk::now();
+    TM_HIP(hipMemcpy(loops_host, fin, sizeof(double) * 2 * 3 * nl, hipMemcpyDeviceToHost));
+    if (err_host) TM_HIP(hipMemcpy(err_host, fin + 2 * 3 * nl, sizeof(double) * 2 * 3 * nl, hipMemcpyDeviceToHost));
+    if (per_source_host && N > 0)
+        TM_HIP(hipMemcpy(per_source_host, ps, sizeof(double) * 2 * 2 * nl * N, hipMemcpyDeviceToHost));
+    rs.ms_hp_phase = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    rs.ms_lp_phase = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    if (run_stats) *run_stats = rs;
+    return warn ? TM_WARN_NOT_CONVERGED : TM_OK;
+}
+
+}  // extern "C"
