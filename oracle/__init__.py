@@ -25,4 +25,10 @@ from .oracle import (  # noqa: F401
     OP_HOP,
     STOP_NORMAL,
     STOP_TRUE,
+    layer_weight_count,
+    net_weight_count,
+    pt_layer,
+    pt_net,
+    pt_loss_grad,
+    fcg,
 )

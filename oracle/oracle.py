@@ -60,6 +60,13 @@ def load_oracle():
     lib.orc_tsm.argtypes = [P, i32, f64, f64, P, u64, i32, i32, f64, i32, i32, f64, i32, i32,
                             i32, P, P, P, P, P]
     lib.orc_tsm.restype = i32
+    lib.orc_pt_layer.argtypes = [P, i32, P, i32, i32, P, P, P]
+    lib.orc_pt_layer_adj.argtypes = [P, i32, P, i32, i32, P, P, P]
+    lib.orc_pt_net.argtypes = [P, i32, P, i32, P, P, P, P, i32]
+    lib.orc_pt_loss_grad.argtypes = [P, i32, P, i32, P, P, i32, P, P, P]
+    lib.orc_pt_loss_grad.restype = f64
+    lib.orc_fcg.argtypes = [P, i32, f64, f64, P, i32, P, P, P, f64, i32, P, P]
+    lib.orc_fcg.restype = i32
     _lib = lib
     return lib
 
@@ -175,3 +182,62 @@ def tsm(dims, t_bc, kappa, mu, U, seed, n_hp, n_lp, lp_tol, lp_maxit, hp_tol, hp
     if ps is not None:
         res["per_source"] = ps[:n]
     return res
+
+
+# ---- gauge-covariant parallel-transport network -------------------------
+
+def layer_weight_count(cin: int, cout: int) -> int:
+    """complex weights of one layer: [9][cout][cin][4][4]"""
+    return 9 * cout * cin * 16
+
+
+def net_weight_count(widths) -> int:
+    return sum(layer_weight_count(widths[l], widths[l + 1]) for l in range(len(widths) - 1))
+
+
+def pt_layer(dims, t_bc, U, cin, cout, W, x, adjoint=False):
+    """x: [cin][V][4][3] (or [cout][V][4][3] for the adjoint)."""
+    d = _dims(dims)
+    v = int(np.prod(d))
+    W = _c128(W)
+    x = _c128(x)
+    out = np.zeros((cin if adjoint else cout, v, 4, 3), dtype=np.complex128)
+    fn = load_oracle().orc_pt_layer_adj if adjoint else load_oracle().orc_pt_layer
+    fn(_ptr(d), int(t_bc), _ptr(_c128(U)), int(cin), int(cout), _ptr(W), _ptr(x), _ptr(out))
+    return out
+
+
+def pt_net(dims, t_bc, U, widths, W, x, adjoint=False):
+    d = _dims(dims)
+    v = int(np.prod(d))
+    wd = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
+    nout = wd[0] if adjoint else wd[-1]
+    out = np.zeros((nout, v, 4, 3), dtype=np.complex128)
+    load_oracle().orc_pt_net(_ptr(d), int(t_bc), _ptr(_c128(U)), len(wd) - 1, _ptr(wd), _ptr(_c128(W)),
+                             _ptr(_c128(x)), _ptr(out), 1 if adjoint else 0)
+    return out
+
+
+def pt_loss_grad(dims, t_bc, U, widths, W, r, e):
+    """Loss mean |N r - e|^2/|e|^2 and its Wirtinger gradient d/d conj(W)."""
+    d = _dims(dims)
+    wd = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
+    W = _c128(W)
+    r = _c128(r)
+    e = _c128(e)
+    grad = np.zeros_like(W)
+    loss = load_oracle().orc_pt_loss_grad(_ptr(d), int(t_bc), _ptr(_c128(U)), len(wd) - 1, _ptr(wd), _ptr(W),
+                                          int(r.shape[0]), _ptr(r), _ptr(e), _ptr(grad))
+    return float(loss), grad
+
+
+def fcg(dims, t_bc, kappa, mu, U, widths, W, eta, tol, maxit=-1):
+    d = _dims(dims)
+    wd = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
+    eta = _c128(eta)
+    x = np.zeros_like(eta)
+    st = np.zeros(6, dtype=np.float64)
+    load_oracle().orc_fcg(_ptr(d), int(t_bc), float(kappa), float(mu), _ptr(_c128(U)), len(wd) - 1, _ptr(wd),
+                          _ptr(_c128(W)), _ptr(eta), float(tol), int(maxit), _ptr(x), _ptr(st))
+    return x, {"iters": int(st[0]), "resid_normal": st[1], "resid_true": st[2], "converged": bool(st[3]),
+               "truncated": bool(st[4]), "fell_back": bool(st[5])}

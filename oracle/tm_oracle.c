@@ -520,3 +520,307 @@ int orc_tsm(const int *L, int t_bc, double kappa, double mu, const double *U,
     free(eta); free(s); free(l_lp); free(l_hp); free(sumC); free(sumB); free(dC); free(dB);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* gauge-covariant parallel-transport network (learned preconditioner) */
+/* ------------------------------------------------------------------ */
+
+/*
+ * A layer maps cin spinor fields phi_b to cout fields
+ *     psi_a(x) = sum_b sum_p W[p][a][b] (T_p phi_b)(x),
+ * where W[p][a][b] is a complex 4x4 matrix acting on spin (identity on
+ * colour) and T_p runs over nine paths: p = 0 the identity, p = 1 + 2 mu
+ * the transport from x + mu, U_mu(x) phi(x + mu), and p = 2 + 2 mu the
+ * transport from x - mu, U_mu(x - mu)^dag phi(x - mu), both with the
+ * time-boundary factor of the operator.  Transports commute with gauge
+ * transformations, so the layer is gauge covariant; with
+ * W[0] = 1 + 2i kappa mu gamma_5, W[1+2mu] = -kappa (1 - gamma_mu),
+ * W[2+2mu] = -kappa (1 + gamma_mu) a single 1 -> 1 layer is exactly M.
+ *
+ * Weights of a layer: complex [9][cout][cin][4][4]; a net of nl layers
+ * with widths w[0..nl] stores its layers back to back.  Fields: complex
+ * [channel][V][4][3].  The net is linear (no bias, no activation), so its
+ * adjoint is the reversed chain of adjoint layers, with T_{+mu}^dag =
+ * T_{-mu}.
+ */
+
+static void transport(const int *L, int t_bc, const cplx *U, int p, const cplx *in, cplx *out)
+{
+    long V = volume(L);
+    if (p == 0) {
+        memcpy(out, in, sizeof(cplx) * V * NCOMP);
+        return;
+    }
+    int mu = (p - 1) / 2;
+    int dir = (p % 2 == 1) ? 1 : -1;
+#pragma omp parallel for schedule(static)
+    for (long s = 0; s < V; s++) {
+        double ph;
+        long y = neighbour(L, t_bc, s, mu, dir, &ph);
+        for (int a = 0; a < NSPIN; a++)
+            for (int i = 0; i < NCOL; i++) {
+                cplx t = 0;
+                for (int k = 0; k < NCOL; k++) {
+                    cplx u = dir > 0 ? U[((s * 4 + mu) * 3 + i) * 3 + k] : conj(U[((y * 4 + mu) * 3 + k) * 3 + i]);
+                    t += u * in[y * NCOMP + a * NCOL + k];
+                }
+                out[s * NCOMP + a * NCOL + i] = ph * t;
+            }
+    }
+}
+
+static long layer_weights(int cin, int cout) { return 9L * cout * cin * 16; }
+
+/* out (cout fields) = layer(in (cin fields)) */
+void orc_pt_layer(const int *L, int t_bc, const double *U_, int cin, int cout, const double *W_,
+                  const double *in_, double *out_)
+{
+    const cplx *U = (const cplx *)U_, *W = (const cplx *)W_, *in = (const cplx *)in_;
+    cplx *out = (cplx *)out_;
+    long V = volume(L), n = V * NCOMP;
+    cplx *tp = malloc(sizeof(cplx) * n);
+    memset(out, 0, sizeof(cplx) * n * cout);
+    for (int b = 0; b < cin; b++)
+        for (int p = 0; p < 9; p++) {
+            transport(L, t_bc, U, p, in + (long)b * n, tp);
+            for (int a = 0; a < cout; a++) {
+                const cplx *w = W + (((long)p * cout + a) * cin + b) * 16;
+                cplx *o = out + (long)a * n;
+                for (long s = 0; s < V; s++)
+                    for (int so = 0; so < 4; so++)
+                        for (int si = 0; si < 4; si++) {
+                            cplx ww = w[so * 4 + si];
+                            if (ww == 0) continue;
+                            for (int c = 0; c < NCOL; c++) o[s * NCOMP + so * NCOL + c] += ww * tp[s * NCOMP + si * NCOL + c];
+                        }
+            }
+        }
+    free(tp);
+}
+
+/* out (cin fields) = layer^dag(in (cout fields)):
+   out_b = sum_a sum_p T_p^dag (W[p][a][b]^dag in_a), T_{1+2mu}^dag = T_{2+2mu} */
+void orc_pt_layer_adj(const int *L, int t_bc, const double *U_, int cin, int cout, const double *W_,
+                      const double *in_, double *out_)
+{
+    const cplx *U = (const cplx *)U_, *W = (const cplx *)W_, *in = (const cplx *)in_;
+    cplx *out = (cplx *)out_;
+    long V = volume(L), n = V * NCOMP;
+    cplx *tmp = malloc(sizeof(cplx) * n), *tp = malloc(sizeof(cplx) * n);
+    memset(out, 0, sizeof(cplx) * n * cin);
+    for (int b = 0; b < cin; b++)
+        for (int p = 0; p < 9; p++) {
+            memset(tmp, 0, sizeof(cplx) * n);
+            for (int a = 0; a < cout; a++) {
+                const cplx *w = W + (((long)p * cout + a) * cin + b) * 16;
+                const cplx *x = in + (long)a * n;
+                for (long s = 0; s < V; s++)
+                    for (int si = 0; si < 4; si++)
+                        for (int so = 0; so < 4; so++) {
+                            cplx ww = conj(w[so * 4 + si]);
+                            if (ww == 0) continue;
+                            for (int c = 0; c < NCOL; c++) tmp[s * NCOMP + si * NCOL + c] += ww * x[s * NCOMP + so * NCOL + c];
+                        }
+            }
+            int padj = p == 0 ? 0 : (p % 2 == 1 ? p + 1 : p - 1);
+            transport(L, t_bc, U, padj, tmp, tp);
+            for (long k = 0; k < n; k++) out[(long)b * n + k] += tp[k];
+        }
+    free(tmp);
+    free(tp);
+}
+
+/* y = net(x) (adjoint = 0) or net^dag(x) (adjoint = 1); widths[0..nl] */
+void orc_pt_net(const int *L, int t_bc, const double *U, int nl, const int *widths, const double *W_,
+                const double *x_, double *y_, int adjoint)
+{
+    const cplx *W = (const cplx *)W_;
+    long n = volume(L) * NCOMP;
+    int wmax = 0;
+    for (int l = 0; l <= nl; l++) if (widths[l] > wmax) wmax = widths[l];
+    cplx *a = malloc(sizeof(cplx) * n * wmax), *b = malloc(sizeof(cplx) * n * wmax);
+    long off[64];
+    off[0] = 0;
+    for (int l = 0; l < nl; l++) off[l + 1] = off[l] + layer_weights(widths[l], widths[l + 1]);
+    if (!adjoint) {
+        memcpy(a, x_, sizeof(cplx) * n * widths[0]);
+        for (int l = 0; l < nl; l++) {
+            orc_pt_layer(L, t_bc, U, widths[l], widths[l + 1], (const double *)(W + off[l]), (double *)a, (double *)b);
+            cplx *t = a; a = b; b = t;
+        }
+        memcpy(y_, a, sizeof(cplx) * n * widths[nl]);
+    } else {
+        memcpy(a, x_, sizeof(cplx) * n * widths[nl]);
+        for (int l = nl - 1; l >= 0; l--) {
+            orc_pt_layer_adj(L, t_bc, U, widths[l], widths[l + 1], (const double *)(W + off[l]), (double *)a,
+                             (double *)b);
+            cplx *t = a; a = b; b = t;
+        }
+        memcpy(y_, a, sizeof(cplx) * n * widths[0]);
+    }
+    free(a);
+    free(b);
+}
+
+/*
+ * Loss (1/npairs) sum_i |net(r_i) - e_i|^2 / |e_i|^2 over pairs of single
+ * spinor fields (widths[0] = widths[nl] = 1), and its gradient with
+ * respect to conj(W) (Wirtinger): the derivative of the loss with respect
+ * to Re W is 2 Re(grad), with respect to Im W is 2 Im(grad).  Back
+ * propagation through the linear layers: the upstream gradient of a layer's
+ * input is the adjoint layer applied to that of its output, and
+ *   dW[p][a][b][so][si] = sum_{x,c} g_a(x)_{so c} conj((T_p phi_b)(x)_{si c}).
+ */
+double orc_pt_loss_grad(const int *L, int t_bc, const double *U_, int nl, const int *widths, const double *W_,
+                        int npairs, const double *r_, const double *e_, double *grad_)
+{
+    const cplx *U = (const cplx *)U_, *W = (const cplx *)W_, *r = (const cplx *)r_, *e = (const cplx *)e_;
+    cplx *grad = (cplx *)grad_;
+    long n = volume(L) * NCOMP, V = volume(L);
+    long off[64];
+    off[0] = 0;
+    for (int l = 0; l < nl; l++) off[l + 1] = off[l] + layer_weights(widths[l], widths[l + 1]);
+    memset(grad, 0, sizeof(cplx) * off[nl]);
+    cplx **act = malloc(sizeof(cplx *) * (nl + 1));
+    for (int l = 0; l <= nl; l++) act[l] = malloc(sizeof(cplx) * n * widths[l]);
+    int wmax = 0;
+    for (int l = 0; l <= nl; l++) if (widths[l] > wmax) wmax = widths[l];
+    cplx *g = malloc(sizeof(cplx) * n * wmax), *g2 = malloc(sizeof(cplx) * n * wmax);
+    cplx *tp = malloc(sizeof(cplx) * n);
+    double loss = 0;
+    for (int i = 0; i < npairs; i++) {
+        memcpy(act[0], r + (long)i * n, sizeof(cplx) * n);
+        for (int l = 0; l < nl; l++)
+            orc_pt_layer(L, t_bc, U_, widths[l], widths[l + 1], (const double *)(W + off[l]), (double *)act[l],
+                         (double *)act[l + 1]);
+        const cplx *ei = e + (long)i * n;
+        double ee = norm2(ei, n), d2 = 0;
+        for (long k = 0; k < n; k++) {
+            cplx d = act[nl][k] - ei[k];
+            d2 += creal(d) * creal(d) + cimag(d) * cimag(d);
+            g[k] = d / (ee * npairs);
+        }
+        loss += d2 / ee / npairs;
+        for (int l = nl - 1; l >= 0; l--) {
+            int cin = widths[l], cout = widths[l + 1];
+            for (int b = 0; b < cin; b++)
+                for (int p = 0; p < 9; p++) {
+                    transport(L, t_bc, U, p, act[l] + (long)b * n, tp);
+                    for (int a = 0; a < cout; a++) {
+                        cplx *dw = grad + off[l] + (((long)p * cout + a) * cin + b) * 16;
+                        const cplx *ga = g + (long)a * n;
+                        for (long s = 0; s < V; s++)
+                            for (int so = 0; so < 4; so++)
+                                for (int si = 0; si < 4; si++) {
+                                    cplx acc = 0;
+                                    for (int c = 0; c < NCOL; c++)
+                                        acc += ga[s * NCOMP + so * NCOL + c] * conj(tp[s * NCOMP + si * NCOL + c]);
+                                    dw[so * 4 + si] += acc;
+                                }
+                    }
+                }
+            if (l > 0) {
+                orc_pt_layer_adj(L, t_bc, U_, cin, cout, (const double *)(W + off[l]), (double *)g, (double *)g2);
+                cplx *t = g; g = g2; g2 = t;
+            }
+        }
+    }
+    for (int l = 0; l <= nl; l++) free(act[l]);
+    free(act);
+    free(g);
+    free(g2);
+    free(tp);
+    return loss;
+}
+
+static cplx cdot(const cplx *a, const cplx *b, long n)
+{
+    cplx s = 0;
+    for (long i = 0; i < n; i++) s += conj(a[i]) * b[i];
+    return s;
+}
+
+/*
+ * Flexible CG on M^dag M (Notay 2000; Golub & Ye 1999) with the variable
+ * preconditioner z = N(N^dag(r)) of the network N, Polak-Ribiere
+ * direction update beta = <z_new, r_new - r> / <z, r>.  Falls back to plain
+ * CG (from the current iterate, directions restarted) when Re<z, r> <= 0,
+ * on a non-finite scalar, or when the residual norm has not dropped below
+ * its value five iterations earlier.  stats as orc_cgnr plus stats[5] = 1
+ * if the fallback happened.
+ */
+int orc_fcg(const int *L, int t_bc, double kappa, double mu, const double *U_, int nl, const int *widths,
+            const double *W, const double *eta_, double tol, int maxit, double *x_, double *stats)
+{
+    const cplx *U = (const cplx *)U_, *eta = (const cplx *)eta_;
+    cplx *x = (cplx *)x_;
+    long n = volume(L) * NCOMP;
+    cplx *b = malloc(sizeof(cplx) * n), *r = malloc(sizeof(cplx) * n), *z = malloc(sizeof(cplx) * n);
+    cplx *p = malloc(sizeof(cplx) * n), *t = malloc(sizeof(cplx) * n), *q = malloc(sizeof(cplx) * n);
+    cplx *rold = malloc(sizeof(cplx) * n), *tmp = malloc(sizeof(cplx) * n);
+    apply_m(L, t_bc, kappa, mu, U, eta, b, 1);
+    for (long i = 0; i < n; i++) { x[i] = 0; r[i] = b[i]; }
+    double bb = norm2(b, n), rr = bb;
+    double hist[5] = {rr, rr, rr, rr, rr};
+    int it = 0, conv = 0, trunc = 0, fell = 0;
+    orc_pt_net(L, t_bc, U_, nl, widths, W, (double *)r, (double *)tmp, 1);
+    orc_pt_net(L, t_bc, U_, nl, widths, W, (double *)tmp, (double *)z, 0);
+    cplx zr = cdot(z, r, n);
+    if (!(creal(zr) > 0) || !isfinite(creal(zr)) || !isfinite(cimag(zr))) fell = 1;
+    if (fell) { memcpy(z, r, sizeof(cplx) * n); zr = rr; }
+    memcpy(p, z, sizeof(cplx) * n);
+    for (;;) {
+        if (sqrt(rr / bb) <= tol) { conv = 1; break; }
+        if (maxit >= 0 && it >= maxit) { trunc = 1; break; }
+        apply_m(L, t_bc, kappa, mu, U, p, t, 0);
+        apply_m(L, t_bc, kappa, mu, U, t, q, 1);
+        cplx pq = cdot(p, q, n);
+        cplx alpha = zr / pq;
+        memcpy(rold, r, sizeof(cplx) * n);
+        for (long i = 0; i < n; i++) { x[i] += alpha * p[i]; r[i] -= alpha * q[i]; }
+        double rr_new = norm2(r, n);
+        it++;
+        cplx zr_new, beta;
+        int drop_fail = it >= 5 && !(rr_new < hist[it % 5]);
+        hist[it % 5] = rr_new;
+        if (!fell && drop_fail) fell = 2;
+        if (!fell) {
+            orc_pt_net(L, t_bc, U_, nl, widths, W, (double *)r, (double *)tmp, 1);
+            orc_pt_net(L, t_bc, U_, nl, widths, W, (double *)tmp, (double *)z, 0);
+            zr_new = cdot(z, r, n);
+            if (!(creal(zr_new) > 0) || !isfinite(creal(zr_new)) || !isfinite(cimag(zr_new))) fell = 2;
+        }
+        if (fell == 2) {
+            /* drop the network: plain CG restarted from the current iterate */
+            fell = 1;
+            memcpy(z, r, sizeof(cplx) * n);
+            memcpy(p, r, sizeof(cplx) * n);
+            zr = rr_new;
+            rr = rr_new;
+            continue;
+        }
+        if (fell) {
+            memcpy(z, r, sizeof(cplx) * n);
+            zr_new = rr_new;
+            beta = zr_new / zr;
+        } else {
+            for (long i = 0; i < n; i++) tmp[i] = r[i] - rold[i];
+            beta = cdot(z, tmp, n) / zr;
+        }
+        for (long i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+        zr = zr_new;
+        rr = rr_new;
+    }
+    if (stats) {
+        apply_m(L, t_bc, kappa, mu, U, x, t, 0);
+        for (long i = 0; i < n; i++) t[i] = eta[i] - t[i];
+        stats[0] = it;
+        stats[1] = sqrt(rr / bb);
+        stats[2] = sqrt(norm2(t, n) / norm2(eta, n));
+        stats[3] = conv;
+        stats[4] = trunc;
+        stats[5] = fell ? 1 : 0;
+    }
+    free(b); free(r); free(z); free(p); free(t); free(q); free(rold); free(tmp);
+    return it;
+}
