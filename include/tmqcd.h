@@ -243,6 +243,77 @@ tm_status tsm_contract(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t*
 tm_status tsm_loops(tm_ctx* ctx, const tsm_params* params, double* loops_host, double* err_host,
                     double* per_source_host, tsm_solve_stats* stats_host, tsm_run_stats* run_stats);
 
+/* ---- learned preconditioner --------------------------------------------- */
+
+/* A gauge-covariant network of linear parallel-transport layers.  Layer l
+   maps widths[l] spinor fields phi_b to widths[l+1] fields
+     psi_a(x) = sum_b sum_p W[p][a][b] (T_p phi_b)(x),
+   over nine paths p: 0 the identity, 1 + 2 mu the transport from x + mu,
+   U_mu(x) phi(x + mu), 2 + 2 mu the transport from x - mu,
+   U_mu(x - mu)^dag phi(x - mu) (time-boundary sign included); W[p][a][b] is
+   a complex 4x4 spin matrix (identity on colour).  Weights of a layer:
+   complex128 [9][widths[l+1]][widths[l]][4][4], layers back to back.
+   widths[0] = widths[n_layers] = 1 and 1 <= widths[l] <= 2.  The network N
+   approximates M^{-1}; flexible CG on M^dag M uses z = N(N^dag(r)).
+   Mixing runs on the matrix cores in bfloat16 with FP32 accumulation. */
+#define TM_NET_MAX_LAYERS 8
+typedef struct {
+    int32_t n_layers;
+    int32_t widths[TM_NET_MAX_LAYERS + 1];
+} tm_net_shape;
+
+/* Number of complex weights of a network shape (0 if invalid). */
+size_t tm_precond_weight_count(const tm_net_shape* shape);
+
+/* Install a network (weights_host: complex128, tm_precond_weight_count of
+   them).  TM_ENOTSUP for widths outside 1..2. */
+tm_status tm_precond_set(tm_ctx* ctx, const tm_net_shape* shape, const double* weights_host);
+
+/* Read back the installed shape and weights (weights_host may be NULL). */
+tm_status tm_precond_get(tm_ctx* ctx, tm_net_shape* shape_out, double* weights_host);
+
+/* out = N(in) (adjoint = 0) or N^dag(in) (adjoint = 1) for nrhs single
+   spinor fields, canonical complex128 [nrhs][V][4][3] (device).  FP32
+   activations, bfloat16 mixing.  Asynchronous. */
+tm_status tm_precond_apply(tm_ctx* ctx, int32_t adjoint, int32_t nrhs, const double* in_dev, double* out_dev);
+
+/* Training loss (1/npairs) sum_i |N(r_i) - e_i|^2 / |e_i|^2 over pairs given
+   as canonical complex128 [npairs][V][4][3] (device), and its gradient with
+   respect to conj(W) (complex128, weight layout; d loss / d Re W = 2 Re,
+   d loss / d Im W = 2 Im).  Synchronous. */
+tm_status tm_precond_loss_grad(tm_ctx* ctx, int32_t npairs, const double* r_dev, const double* e_dev,
+                               double* loss_host, double* grad_host);
+
+typedef struct {
+    uint64_t seed;        /* noise seed of the training sources (use one disjoint from the estimator's) */
+    int32_t n_sources;    /* training sources solved to hp_tol */
+    int32_t n_pairs;      /* (residual, error) pairs harvested from their iterates */
+    int32_t epochs;
+    int32_t batch;        /* pairs per Adam step */
+    double lr;            /* Adam step size */
+    double hp_tol;        /* tolerance of the training solves */
+    double min_rel_err;   /* harvest only iterates with |e_k| / |x*| above this */
+    uint64_t init_seed;   /* seed of the initial weights (identity on channel 0 plus noise) */
+    double init_scale;    /* size of that noise */
+} tm_train_params;
+
+typedef struct {
+    double loss_first;    /* mean loss of the first epoch */
+    double loss_last;     /* mean loss of the last epoch */
+    double ms_generate;   /* time to harvest the pairs */
+    double ms_train;      /* time of the Adam epochs */
+    int32_t pairs;        /* pairs used */
+    int32_t steps;        /* Adam steps */
+} tm_train_stats;
+
+/* Harvest (r_k = eta - M x_k, e_k = x* - x_k) pairs from CG solves of
+   training sources, store them in bfloat16, and train the installed network
+   (or the default 1 -> 2 -> 2 -> 1 shape if none is installed) with Adam on
+   the loss of tm_precond_loss_grad, using the library's forward, adjoint and
+   weight-gradient kernels.  The trained weights stay installed.
+   Synchronous. */
+tm_status tm_precond_train(tm_ctx* ctx, const tm_train_params* params, tm_train_stats* stats);
+
 /* ---- instrumentation ---------------------------------------------------- */
 
 /* Kernel classes timed with HIP events on the context stream when profiling

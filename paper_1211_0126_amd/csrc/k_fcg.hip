@@ -1,0 +1,364 @@
+// Flexible CG on M^dag M with the network preconditioner z = N(N^dag(r))
+// (Notay 2000; Golub & Ye 1999), FP32 vectors, FP64 complex scalars.
+//   F1  t = M p, |t|^2                         -> alpha = <z,r> / |t|^2
+//   F2  q = M^dag t (kept), x += alpha p, r -= alpha q, |r|^2 -> stop tests,
+//       stagnation test (|r| not below its value five steps earlier)
+//   net z = N(N^dag(r))                        (transport layers)
+//   F3  <z,q>, <z,r>                           -> beta = -alpha <z,q> / <z,r>_old
+//       (Polak-Ribiere, since r_new - r_old = -alpha q), or fallback
+//   F4  p = z + beta p   | p = r + beta p (plain CG after fallback) | p = r (restart)
+// A source falls back to plain CG (directions restarted from its current
+// iterate) when Re<z,r> <= 0, a scalar is not finite, or it stagnates.
+
+#include "tm_device.h"
+#include "tm_kernels.h"
+
+namespace tmq {
+
+// reuse the stencil helpers of k_dslash.hip through a small local copy of the
+// single-right-hand-side FP32 operator
+template <int MU, int SG>
+__device__ __forceinline__ void fproj(const cx<float> p[12], cx<float> h[6]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        cx<float> u0 = p[c], u1 = p[3 + c], d0 = p[6 + c], d1 = p[9 + c], b0, b1;
+        if (MU == 0) { b0 = times_mi(d1); b1 = times_mi(d0); }
+        else if (MU == 1) { b0 = {-d1.re, -d1.im}; b1 = d0; }
+        else if (MU == 2) { b0 = times_mi(d0); b1 = times_i(d1); }
+        else { b0 = d0; b1 = d1; }
+        if (SG > 0) { h[c] = u0 - b0; h[3 + c] = u1 - b1; }
+        else { h[c] = u0 + b0; h[3 + c] = u1 + b1; }
+    }
+}
+template <int MU, int SG>
+__device__ __forceinline__ void frecon(const cx<float> g[6], cx<float> acc[12]) {
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        cx<float> g0 = g[c], g1 = g[3 + c], e0, e1;
+        if (MU == 0) { e0 = times_i(g1); e1 = times_i(g0); }
+        else if (MU == 1) { e0 = g1; e1 = {-g0.re, -g0.im}; }
+        else if (MU == 2) { e0 = times_i(g0); e1 = times_mi(g1); }
+        else { e0 = g0; e1 = g1; }
+        acc[c] = acc[c] + g0;
+        acc[3 + c] = acc[3 + c] + g1;
+        if (SG > 0) { acc[6 + c] = acc[6 + c] - e0; acc[9 + c] = acc[9 + c] - e1; }
+        else { acc[6 + c] = acc[6 + c] + e0; acc[9 + c] = acc[9 + c] + e1; }
+    }
+}
+template <int MU, bool DAG>
+__device__ __forceinline__ void fhop(const Geom& geo, const void* gauge, const void* in, uint32_t s, const Site& c,
+                                     cx<float> acc[12]) {
+    constexpr int SF = DAG ? -1 : 1;
+    {
+        const uint32_t y = nb_fwd(geo, s, c, MU);
+        const bool flip = (MU == 3) && (c.t + 1 == geo.L[3]) && (geo.t_bc < 0);
+        cx<float> U[3][3], p[12], h[6], g[6];
+        load_link<GF32, float>(gauge, geo.Vs, MU, s, U);
+        load_spinor<SF32, float>(in, geo.Vs, y, p);
+        fproj<MU, SF>(p, h);
+        if (flip)
+#pragma unroll
+            for (int k = 0; k < 6; k++) h[k] = {-h[k].re, -h[k].im};
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int i = 0; i < 3; i++) g[3 * a + i] = U[i][0] * h[3 * a] + U[i][1] * h[3 * a + 1] + U[i][2] * h[3 * a + 2];
+        frecon<MU, SF>(g, acc);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im));
+    asm volatile("" ::: "memory");
+    {
+        const uint32_t y = nb_bwd(geo, s, c, MU);
+        const bool flip = (MU == 3) && (c.t == 0) && (geo.t_bc < 0);
+        cx<float> U[3][3], p[12], h[6], g[6];
+        load_link<GF32, float>(gauge, geo.Vs, MU, y, U);
+        load_spinor<SF32, float>(in, geo.Vs, y, p);
+        fproj<MU, -SF>(p, h);
+        if (flip)
+#pragma unroll
+            for (int k = 0; k < 6; k++) h[k] = {-h[k].re, -h[k].im};
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+                g[3 * a + i] = cmulc(U[0][i], h[3 * a]) + cmulc(U[1][i], h[3 * a + 1]) + cmulc(U[2][i], h[3 * a + 2]);
+        frecon<MU, -SF>(g, acc);
+    }
+#pragma unroll
+    for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im));
+    asm volatile("" ::: "memory");
+}
+// out = in - kappa H in + i tw gamma_5 in (DAG: H^dag and -tw)
+template <bool DAG>
+__device__ __forceinline__ void fop(const Geom& geo, const void* gauge, float kappa, float tw, const void* in,
+                                    uint32_t s, cx<float> out[12]) {
+    const Site c = site_coords(geo, s);
+    cx<float> acc[12], p[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) acc[k] = {0.f, 0.f};
+    fhop<0, DAG>(geo, gauge, in, s, c, acc);
+    fhop<1, DAG>(geo, gauge, in, s, c, acc);
+    fhop<2, DAG>(geo, gauge, in, s, c, acc);
+    fhop<3, DAG>(geo, gauge, in, s, c, acc);
+    load_spinor<SF32, float>(in, geo.Vs, s, p);
+    const float t = DAG ? -tw : tw;
+#pragma unroll
+    for (int k = 0; k < 6; k++) out[k] = {p[k].re - kappa * acc[k].re - t * p[k].im, p[k].im - kappa * acc[k].im + t * p[k].re};
+#pragma unroll
+    for (int k = 6; k < 12; k++) out[k] = {p[k].re - kappa * acc[k].re + t * p[k].im, p[k].im - kappa * acc[k].im - t * p[k].re};
+}
+
+__device__ __forceinline__ bool finite_d(double v) { return v == v && v < 1e300 && v > -1e300; }
+
+// F1: t = M p, alpha = <z,r> / |t|^2
+__global__ TM_STENCIL(1) void k_fcg_mp(FcgArgs a) {
+    __shared__ double sh[4];
+    __shared__ int sflag;
+    const uint32_t nb = gridDim.x, b = xcd_block(blockIdx.x, nb);
+    const uint32_t s = b * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (!a.scal[r].active) return;
+    const long Vs = a.geo.Vs;
+    double part = 0;
+    if (s < a.geo.V) {
+        cx<float> t[12];
+        fop<false>(a.geo, a.gauge, (float)a.kappa, (float)a.twist, field_rhs<SF32>(a.p, Vs, r), s, t);
+        store_spinor<SF32, float>(field_rhs<SF32>(a.t, Vs, r), Vs, s, t);
+#pragma unroll
+        for (int k = 0; k < 12; k++) part += (double)t[k].re * t[k].re + (double)t[k].im * t[k].im;
+    }
+    double v = block_sum256(part, sh);
+    if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
+    if (take_last_ticket(a.counters + r, nb, &sflag)) {
+        double tt = sum_partials(a.partials + (size_t)r * nb, nb, sh);
+        if (threadIdx.x == 0) {
+            FcgScal& q = a.scal[r];
+            q.tt = tt;
+            q.alpha_re = tt > 0 ? q.zr_re / tt : 0.0;
+            q.alpha_im = tt > 0 ? q.zr_im / tt : 0.0;
+            a.counters[r] = 0;
+        }
+    }
+}
+
+// F2: q = M^dag t, x += alpha p, r -= alpha q, |r|^2, stop and stagnation tests
+__global__ TM_STENCIL(1) void k_fcg_upd(FcgArgs a) {
+    __shared__ double sh[4];
+    __shared__ int sflag;
+    const uint32_t nb = gridDim.x, b = xcd_block(blockIdx.x, nb);
+    const uint32_t s = b * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (!a.scal[r].active) return;
+    const long Vs = a.geo.Vs;
+    double part = 0;
+    if (s < a.geo.V) {
+        const float ar = (float)a.scal[r].alpha_re, ai = (float)a.scal[r].alpha_im;
+        cx<float> q[12], rv[12], pv[12], xv[12];
+        fop<true>(a.geo, a.gauge, (float)a.kappa, (float)a.twist, field_rhs<SF32>(a.t, Vs, r), s, q);
+        store_spinor<SF32, float>(field_rhs<SF32>(a.q, Vs, r), Vs, s, q);
+        void* rp = field_rhs<SF32>(a.r, Vs, r);
+        void* xp = field_rhs<SF32>(a.x, Vs, r);
+        load_spinor<SF32, float>(rp, Vs, s, rv);
+        load_spinor<SF32, float>(field_rhs<SF32>(a.p, Vs, r), Vs, s, pv);
+        load_spinor<SF32, float>(xp, Vs, s, xv);
+        const cx<float> al = {ar, ai};
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            xv[k] = xv[k] + al * pv[k];
+            rv[k] = rv[k] - al * q[k];
+            part += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
+        }
+        store_spinor<SF32, float>(rp, Vs, s, rv);
+        store_spinor<SF32, float>(xp, Vs, s, xv);
+    }
+    double v = block_sum256(part, sh);
+    if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
+    if (take_last_ticket(a.counters + r, nb, &sflag)) {
+        double rrn = sum_partials(a.partials + (size_t)r * nb, nb, sh);
+        if (threadIdx.x == 0) {
+            FcgScal& q = a.scal[r];
+            q.iters += 1;
+            q.rr_prev = q.rr;
+            q.rr = rrn;
+            const int slot = q.iters % 5;
+            q.stagnant = (q.iters >= 5 && !(rrn < q.hist[slot])) ? 1 : 0;
+            q.hist[slot] = rrn;
+            if (!finite_d(rrn) || !finite_d(q.alpha_re) || !finite_d(q.alpha_im)) {
+                q.status = 3;
+                q.active = 0;
+            } else if (rrn <= q.tol2 * q.bb) {
+                q.status = 1;
+                q.active = 0;
+            } else if (q.maxit >= 0 && q.iters >= q.maxit) {
+                q.status = 2;
+                q.active = 0;
+            }
+            a.counters[r] = 0;
+        }
+    }
+}
+
+// F3 (and the initial step, init = 1): <z,q>, <z,r>; choose the direction mode
+__global__ __launch_bounds__(256) void k_fcg_dot(FcgArgs a, int init) {
+    __shared__ double sh[4];
+    __shared__ int sflag;
+    const uint32_t nb = gridDim.x;
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (!a.scal[r].active) return;
+    const long Vs = a.geo.Vs;
+    double zq_re = 0, zq_im = 0, zr_re = 0, zr_im = 0;
+    if (s < a.geo.V) {
+        cx<float> z[12], q[12], rv[12];
+        load_spinor<SF32, float>(field_rhs<SF32>(a.z, Vs, r), Vs, s, z);
+        load_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r), Vs, s, rv);
+        if (!init) load_spinor<SF32, float>(field_rhs<SF32>(a.q, Vs, r), Vs, s, q);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            zr_re += (double)z[k].re * rv[k].re + (double)z[k].im * rv[k].im;
+            zr_im += (double)z[k].re * rv[k].im - (double)z[k].im * rv[k].re;
+            if (!init) {
+                zq_re += (double)z[k].re * q[k].re + (double)z[k].im * q[k].im;
+                zq_im += (double)z[k].re * q[k].im - (double)z[k].im * q[k].re;
+            }
+        }
+    }
+    double* P = a.partials + (size_t)r * nb * 4;
+    double v0 = block_sum256(zr_re, sh);
+    double v1 = block_sum256(zr_im, sh);
+    double v2 = block_sum256(zq_re, sh);
+    double v3 = block_sum256(zq_im, sh);
+    if (threadIdx.x == 0) {
+        P[blockIdx.x] = v0;
+        P[nb + blockIdx.x] = v1;
+        P[2 * nb + blockIdx.x] = v2;
+        P[3 * nb + blockIdx.x] = v3;
+    }
+    if (take_last_ticket(a.counters + r, nb, &sflag)) {
+        double zrr = sum_partials(P, nb, sh);
+        double zri = sum_partials(P + nb, nb, sh);
+        double zqr = sum_partials(P + 2 * nb, nb, sh);
+        double zqi = sum_partials(P + 3 * nb, nb, sh);
+        if (threadIdx.x == 0) {
+            FcgScal& q = a.scal[r];
+            const bool bad = !(zrr > 0) || !finite_d(zrr) || !finite_d(zri) || !finite_d(zqr) || !finite_d(zqi);
+            if (init) {
+                if (q.fell || bad) {
+                    q.fell = 1;
+                    q.mode = 2;  // p = r
+                    q.zr_re = q.rr;
+                    q.zr_im = 0;
+                } else {
+                    q.mode = 3;  // p = z
+                    q.zr_re = zrr;
+                    q.zr_im = zri;
+                }
+            } else if (q.fell) {
+                // plain CG: beta = |r_new|^2 / |r_old|^2
+                q.mode = 1;
+                q.beta_re = q.rr / q.zr_re;
+                q.beta_im = 0;
+                q.zr_re = q.rr;
+                q.zr_im = 0;
+            } else if (q.stagnant || bad) {
+                q.fell = 1;
+                q.mode = 2;  // restart: p = r
+                q.zr_re = q.rr;
+                q.zr_im = 0;
+            } else {
+                // beta = -alpha <z,q> / zr_old
+                const double nr = -(q.alpha_re * zqr - q.alpha_im * zqi);
+                const double ni = -(q.alpha_re * zqi + q.alpha_im * zqr);
+                const double den = q.zr_re * q.zr_re + q.zr_im * q.zr_im;
+                q.beta_re = (nr * q.zr_re + ni * q.zr_im) / den;
+                q.beta_im = (ni * q.zr_re - nr * q.zr_im) / den;
+                q.mode = 0;
+                q.zr_re = zrr;
+                q.zr_im = zri;
+            }
+            a.counters[r] = 0;
+        }
+    }
+}
+
+// F4: p = z + beta p (mode 0), r + beta p (1), r (2), z (3)
+__global__ __launch_bounds__(256) void k_fcg_p(FcgArgs a) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= a.geo.V) return;
+    const FcgScal& q = a.scal[r];
+    if (!q.active) return;
+    const long Vs = a.geo.Vs;
+    cx<float> src[12], pv[12];
+    load_spinor<SF32, float>(field_rhs<SF32>((q.mode == 0 || q.mode == 3) ? a.z : a.r, Vs, r), Vs, s, src);
+    void* pp = field_rhs<SF32>(a.p, Vs, r);
+    if (q.mode <= 1) {
+        const cx<float> be = {(float)q.beta_re, (float)q.beta_im};
+        load_spinor<SF32, float>(pp, Vs, s, pv);
+#pragma unroll
+        for (int k = 0; k < 12; k++) pv[k] = src[k] + be * pv[k];
+        store_spinor<SF32, float>(pp, Vs, s, pv);
+    } else {
+        store_spinor<SF32, float>(pp, Vs, s, src);
+    }
+}
+
+// init: x = 0, |b|^2 (r holds b = M^dag eta), scalars
+__global__ __launch_bounds__(256) void k_fcg_init(FcgArgs a, double tol2, int maxit, int fell) {
+    __shared__ double sh[4];
+    __shared__ int sflag;
+    const uint32_t nb = gridDim.x;
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    const long Vs = a.geo.Vs;
+    double part = 0;
+    if (s < a.geo.V) {
+        cx<float> rv[12], z[12];
+        load_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r), Vs, s, rv);
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            part += (double)rv[k].re * rv[k].re + (double)rv[k].im * rv[k].im;
+            z[k] = {0.f, 0.f};
+        }
+        store_spinor<SF32, float>(field_rhs<SF32>(a.x, Vs, r), Vs, s, z);
+    }
+    double v = block_sum256(part, sh);
+    if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
+    if (take_last_ticket(a.counters + r, nb, &sflag)) {
+        double bb = sum_partials(a.partials + (size_t)r * nb, nb, sh);
+        if (threadIdx.x == 0) {
+            FcgScal q = {};
+            q.bb = q.rr = q.rr_prev = bb;
+            for (int k = 0; k < 5; k++) q.hist[k] = bb;
+            q.tol2 = tol2;
+            q.maxit = maxit;
+            q.fell = fell;
+            q.resid_true = -1.0;
+            q.status = (bb <= 0 || 1.0 <= tol2) ? 1 : (maxit == 0 ? 2 : 0);
+            q.active = q.status == 0;
+            a.scal[r] = q;
+            a.counters[r] = 0;
+        }
+    }
+}
+
+static inline dim3 fgrid(const Geom& g, int n) { return dim3((unsigned)((g.V + 255) / 256), (unsigned)n); }
+
+void launch_fcg_init(hipStream_t st, const FcgArgs& a, double tol2, int maxit, int fell) {
+    hipLaunchKernelGGL(k_fcg_init, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a, tol2, maxit, fell);
+}
+void launch_fcg_mp(hipStream_t st, const FcgArgs& a) {
+    hipLaunchKernelGGL(k_fcg_mp, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a);
+}
+void launch_fcg_upd(hipStream_t st, const FcgArgs& a) {
+    hipLaunchKernelGGL(k_fcg_upd, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a);
+}
+void launch_fcg_dot(hipStream_t st, const FcgArgs& a, int init) {
+    hipLaunchKernelGGL(k_fcg_dot, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a, init);
+}
+void launch_fcg_p(hipStream_t st, const FcgArgs& a) {
+    hipLaunchKernelGGL(k_fcg_p, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a);
+}
+
+}  // namespace tmq

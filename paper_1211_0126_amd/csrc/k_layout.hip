@@ -88,6 +88,29 @@ void launch_native_to_c128(hipStream_t st, const Geom& g, int prec, int nrhs, co
         hipLaunchKernelGGL((k_native_to_c128<SF32>), grid, dim3(256), 0, st, g, nrhs, in, out);
 }
 
+// canonical complex128 -> native storage S (values rounded to S)
+template <class S, typename R>
+__global__ __launch_bounds__(256) void k_c128_to_native(Geom geo, int nrhs, const double* in, void* out) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= geo.V) return;
+    const double2* c = (const double2*)in + ((size_t)r * geo.V + s) * 12;
+    cx<R> p[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) p[k] = {(R)c[k].x, (R)c[k].y};
+    store_spinor<S, R>(field_rhs<S>(out, geo.Vs, r), geo.Vs, s, p);
+}
+
+void launch_c128_to_native(hipStream_t st, const Geom& g, int prec, int nrhs, const double* in, void* out) {
+    dim3 grid((unsigned)((g.V + 255) / 256), (unsigned)nrhs);
+    switch (prec) {
+    case P_F64: hipLaunchKernelGGL((k_c128_to_native<SF64, double>), grid, dim3(256), 0, st, g, nrhs, in, out); break;
+    case P_F32: hipLaunchKernelGGL((k_c128_to_native<SF32, float>), grid, dim3(256), 0, st, g, nrhs, in, out); break;
+    case P_F16: hipLaunchKernelGGL((k_c128_to_native<SF16, float>), grid, dim3(256), 0, st, g, nrhs, in, out); break;
+    default: hipLaunchKernelGGL((k_c128_to_native<SBF16, float>), grid, dim3(256), 0, st, g, nrhs, in, out); break;
+    }
+}
+
 // canonical complex128 (device) -> native F64 (full links) and F32 (rows 0, 1)
 __global__ __launch_bounds__(256) void k_gauge_convert(Geom geo, const double2* canon, double2* g64, float4* g32) {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;

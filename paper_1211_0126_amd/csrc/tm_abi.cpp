@@ -5,6 +5,7 @@
 #include <complex>
 
 #include "tm_ctx.h"
+#include "tm_learn.h"
 
 namespace tmq {
 
@@ -192,6 +193,7 @@ tm_status tm_destroy(tm_ctx* ctx) {
     if (ctx->gauge32) (void)hipFree(ctx->gauge32);
     if (ctx->gam_dev) (void)hipFree(ctx->gam_dev);
     if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
+    net_release(ctx);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     delete ctx;
     return TM_OK;

@@ -34,6 +34,9 @@ struct tm_ctx {
     // Gamma_n tables on the device (row a -> column, phase i^k)
     int* gam_dev = nullptr;
 
+    // learned preconditioner (weights and their bfloat16 fragments)
+    struct NetState* net = nullptr;
+
     std::string err;
     int sticky = 0;
 

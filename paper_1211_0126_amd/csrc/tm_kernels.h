@@ -46,6 +46,44 @@ struct ContractArgs {
     long out_stride;      // complex elements between slots
 };
 
+struct FcgArgs {
+    Geom geo;
+    const void* gauge;  // FP32 native links
+    double kappa, twist;
+    void *p, *t, *q, *r, *x, *z;  // FP32 native fields, nrhs each
+    FcgScal* scal;
+    double* partials;   // [nrhs][4][nblocks]
+    unsigned int* counters;
+    int nrhs;
+};
+
+void launch_fcg_init(hipStream_t st, const FcgArgs& a, double tol2, int maxit, int fell);
+void launch_fcg_mp(hipStream_t st, const FcgArgs& a);
+void launch_fcg_upd(hipStream_t st, const FcgArgs& a);
+void launch_fcg_dot(hipStream_t st, const FcgArgs& a, int init);
+void launch_fcg_p(hipStream_t st, const FcgArgs& a);
+
+// One transport layer of the learned preconditioner (cin, cout <= 2).
+struct PtArgs {
+    Geom geo;
+    const void* gauge;     // FP32 native links
+    int cin, cout;
+    int kpad;              // 72 * cin rounded up to 16
+    const void* in;        // cin fields (per right-hand side: cin consecutive fields)
+    void* out;             // cout FP32 fields (per right-hand side)
+    const short* wfrag;    // weight fragments [kpad/16][64 lanes][4] bfloat16
+    const void* g;         // weight gradient: upstream gradient (cout FP32 fields)
+    float* partials;       // weight gradient: [blocks][16][kpad]
+};
+
+void launch_pt_layer(hipStream_t st, const PtArgs& a, int in_prec, int nrhs);
+void launch_pt_wgrad(hipStream_t st, const PtArgs& a, int in_prec, const double* scale, double* grad);
+void launch_pt_loss(hipStream_t st, const Geom& g, const void* y, const void* e, int e_prec, void* gout,
+                    double* partials, unsigned int* counter, double* scal, int npairs);
+int pt_blocks(const Geom& g);
+void launch_make_pair(hipStream_t st, const Geom& g, uint64_t seed_mixed, const uint64_t* id, const void* xk,
+                      const void* xstar, const void* mxk, void* r_out, void* e_out);
+
 // operator
 void launch_apply(hipStream_t st, const Geom& g, int prec, const void* gauge, double kappa, double twist, int op,
                   int nrhs, const void* in, void* out, int nr, const CgScal* gate);
@@ -69,6 +107,7 @@ void launch_true_resid(hipStream_t st, const CgArgs& a, int xprec, const void* g
 void launch_field_convert(hipStream_t st, const Geom& g, int prec, int nrhs, bool to_native, const void* in,
                           void* out);
 void launch_native_to_c128(hipStream_t st, const Geom& g, int prec, int nrhs, const void* in, double* out);
+void launch_c128_to_native(hipStream_t st, const Geom& g, int prec, int nrhs, const double* in, void* out);
 void launch_gauge_convert(hipStream_t st, const Geom& g, const double* canon, void* g64, void* g32);
 void launch_noise_native(hipStream_t st, const Geom& g, int prec, uint64_t seed_mixed, const uint64_t* ids, int nrhs,
                          void* out);

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "tm_ctx.h"
+#include "tm_learn.h"
 
 namespace tmq {
 
@@ -24,7 +25,13 @@ static const int kIterCap = 20000;  // safety cap for max_iter = -1
 static tm_status check_solve_params(tm_ctx* ctx, const tsm_solve_params* p) {
     if (!p) return set_error(ctx, TM_EINVAL, "null solve parameters");
     if (p->prec < 0 || p->prec > 3) return set_error(ctx, TM_EINVAL, "solve: bad precision");
-    if (p->solver != TM_SOLVER_CG) return set_error(ctx, TM_ENOTSUP, "solve: only TM_SOLVER_CG is available here");
+    if (p->solver != TM_SOLVER_CG && p->solver != TM_SOLVER_FCG_LEARNED)
+        return set_error(ctx, TM_EINVAL, "solve: unknown solver");
+    if (p->solver == TM_SOLVER_FCG_LEARNED) {
+        if (p->prec != TM_PREC_F32 || p->reliable || p->stop != TM_STOP_NORMAL)
+            return set_error(ctx, TM_ENOTSUP, "solve: flexible CG runs FP32 vectors, normal-equation stop, no reliable updates");
+        if (!net_installed(ctx)) return set_error(ctx, TM_ESTATE, "solve: no network installed (tm_precond_set/train)");
+    }
     if (!(p->tol >= 0) || !std::isfinite(p->tol)) return set_error(ctx, TM_EINVAL, "solve: bad tolerance");
     if (p->max_iter < -1) return set_error(ctx, TM_EINVAL, "solve: bad max_iter");
     if (p->stop != TM_STOP_NORMAL && p->stop != TM_STOP_TRUE) return set_error(ctx, TM_EINVAL, "solve: bad stop");
@@ -86,11 +93,174 @@ struct BlockResult {
     int xprec;
 };
 
+// Flexible CG with the network preconditioner for a block of sources; the
+// final state is written into ctx->scal_host in CgScal form.
+static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_t seed_mixed,
+                                 const uint64_t* ids_dev, int nrhs, const std::string& tag, BlockResult* res) {
+    const Geom& g = ctx->geo;
+    hipStream_t st = ctx->stream;
+    tm_status s = TM_OK;
+    const size_t nblk = (size_t)((g.V + 255) / 256);
+    const size_t fb = field_bytes(g, P_F32, nrhs);
+    FcgArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geo = g;
+    a.gauge = ctx->gauge32;
+    a.kappa = ctx->lat.kappa;
+    a.twist = ctx->twist;
+    a.nrhs = nrhs;
+    a.p = ws_get(ctx, tag + "_fp", fb, &s);
+    a.t = ws_get(ctx, tag + "_ft", fb, &s);
+    a.q = ws_get(ctx, tag + "_fq", fb, &s);
+    a.r = ws_get(ctx, tag + "_fr", fb, &s);
+    a.x = ws_get(ctx, tag + "_fx", fb, &s);
+    a.z = ws_get(ctx, tag + "_fz", fb, &s);
+    void* eta = ws_get(ctx, tag + "_feta", fb, &s);
+    a.scal = (FcgScal*)ws_get(ctx, tag + "_fscal", sizeof(FcgScal) * kMaxBlock, &s);
+    a.partials = (double*)ws_get(ctx, "fpartials", sizeof(double) * nblk * kMaxBlock * 4, &s);
+    a.counters = (unsigned int*)ws_get(ctx, "counters", sizeof(unsigned int) * kMaxBlock, &s);
+    CgScal* tscal = (CgScal*)ws_get(ctx, tag + "_ftscal", sizeof(CgScal) * kMaxBlock, &s);
+    double* part1 = (double*)ws_get(ctx, "partials", sizeof(double) * nblk * kMaxBlock, &s);
+    double* part2 = (double*)ws_get(ctx, "partials2", sizeof(double) * nblk * kMaxBlock, &s);
+    if (s != TM_OK) return s;
+    if ((s = ensure_scal_host(ctx, nrhs)) != TM_OK) return s;
+
+    prof_begin(ctx, TM_KC_OTHER);
+    launch_noise_native(st, g, P_F32, seed_mixed, ids_dev, nrhs, eta);
+    launch_apply(st, g, P_F32, ctx->gauge32, ctx->lat.kappa, ctx->twist, 1, nrhs, eta, a.r, 1, nullptr);
+    launch_fcg_init(st, a, p->tol * p->tol, p->max_iter, 0);
+    prof_end(ctx, TM_KC_OTHER, 0.0);
+    if ((s = net_precondition(ctx, nrhs, a.r, a.z)) != TM_OK) return s;
+    launch_fcg_dot(st, a, 1);
+    launch_fcg_p(st, a);
+    TM_HIP(hipGetLastError());
+    const CgBytes by = cg_bytes(g, P_F32, nrhs, false, false);
+    std::vector<FcgScal> fs(nrhs);
+    int done = 0;
+    for (;;) {
+        int k = 8;
+        if (p->max_iter >= 0) k = std::max(1, std::min(8, p->max_iter - done));
+        for (int i = 0; i < k; i++) {
+            prof_begin(ctx, TM_KC_DSLASH);
+            launch_fcg_mp(st, a);
+            prof_end(ctx, TM_KC_DSLASH, by.k1);
+            prof_begin(ctx, TM_KC_DSLASH_UPD);
+            launch_fcg_upd(st, a);
+            prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
+            if ((s = net_precondition(ctx, nrhs, a.r, a.z)) != TM_OK) return s;
+            launch_fcg_dot(st, a, 0);
+            prof_begin(ctx, TM_KC_BLAS);
+            launch_fcg_p(st, a);
+            prof_end(ctx, TM_KC_BLAS, by.k3);
+        }
+        TM_HIP(hipGetLastError());
+        done += k;
+        TM_HIP(hipMemcpyAsync(fs.data(), a.scal, sizeof(FcgScal) * nrhs, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        bool any = false;
+        for (int r = 0; r < nrhs; r++) any |= fs[r].active != 0;
+        if (!any || done >= kIterCap) break;
+    }
+    res->x = a.x;
+    res->xprec = P_F32;
+    std::vector<CgScal> ts(nrhs);
+    std::memset(ts.data(), 0, sizeof(CgScal) * nrhs);
+    if (p->true_resid) {
+        CgArgs at;
+        std::memset(&at, 0, sizeof(at));
+        at.geo = g;
+        at.x = a.x;
+        at.scal = tscal;
+        at.partials = part1;
+        at.partials2 = part2;
+        at.counters = a.counters;
+        at.nrhs = nrhs;
+        launch_true_resid(st, at, P_F32, ctx->gauge64, seed_mixed, ids_dev);
+        TM_HIP(hipGetLastError());
+        TM_HIP(hipMemcpyAsync(ts.data(), tscal, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st));
+    }
+    TM_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < nrhs; r++) {
+        CgScal q;
+        std::memset(&q, 0, sizeof(q));
+        q.iters = fs[r].iters;
+        q.status = fs[r].status;
+        q.rr = fs[r].rr;
+        q.bb = fs[r].bb;
+        q.resid_true = p->true_resid ? ts[r].resid_true : -1.0;
+        q.fell_back = fs[r].fell;
+        ctx->scal_host[r] = q;
+    }
+    return TM_OK;
+}
+
+tm_status solve_f64_history(tm_ctx* ctx, uint64_t seed_mixed, const uint64_t* id_dev, double tol, int maxit,
+                            std::vector<double>* hist, void* xstar_out, PairSink* sink) {
+    const Geom& g = ctx->geo;
+    hipStream_t st = ctx->stream;
+    tm_status s = TM_OK;
+    const size_t nblk = (size_t)((g.V + 255) / 256);
+    const size_t fb = field_bytes(g, P_F64, 1);
+    CgArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geo = g;
+    a.gauge = ctx->gauge64;
+    a.kappa = ctx->lat.kappa;
+    a.twist = ctx->twist;
+    a.nrhs = 1;
+    a.p = ws_get(ctx, "h_p", fb, &s);
+    a.t = ws_get(ctx, "h_t", fb, &s);
+    a.r = ws_get(ctx, "h_r", fb, &s);
+    a.x = ws_get(ctx, "h_x", fb, &s);
+    void* eta = ws_get(ctx, "h_eta", fb, &s);
+    void* mx = ws_get(ctx, "h_mx", fb, &s);
+    a.scal = (CgScal*)ws_get(ctx, "h_scal", sizeof(CgScal) * kMaxBlock, &s);
+    a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * nblk * kMaxBlock, &s);
+    a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * nblk * kMaxBlock, &s);
+    a.counters = (unsigned int*)ws_get(ctx, "counters", sizeof(unsigned int) * kMaxBlock, &s);
+    if (s != TM_OK) return s;
+    launch_scal_init(st, a.scal, 1, tol * tol, maxit, 0, 0, 0.0);
+    launch_noise_native(st, g, P_F64, seed_mixed, id_dev, 1, eta);
+    launch_apply(st, g, P_F64, ctx->gauge64, ctx->lat.kappa, ctx->twist, 1, 1, eta, a.r, 1, nullptr);
+    launch_cg_init(st, a, P_F64, false, eta);
+    TM_HIP(hipGetLastError());
+    size_t cut = 0;
+    auto maybe_cut = [&](int it) -> tm_status {
+        if (!sink || cut >= sink->ks.size() || sink->ks[cut] != it) return TM_OK;
+        launch_apply(st, g, P_F64, ctx->gauge64, ctx->lat.kappa, ctx->twist, 0, 1, a.x, mx, 1, nullptr);
+        launch_make_pair(st, g, seed_mixed, id_dev, a.x, sink->xstar, mx, (char*)sink->R + sink->next * sink->fb,
+                         (char*)sink->E + sink->next * sink->fb);
+        TM_HIP(hipGetLastError());
+        sink->next++;
+        cut++;
+        return TM_OK;
+    };
+    CgScal q;
+    TM_HIP(hipMemcpyAsync(&q, a.scal, sizeof(CgScal), hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    if (hist) hist->push_back(q.rr / q.bb);
+    if ((s = maybe_cut(0)) != TM_OK) return s;
+    while (q.active && q.iters < kIterCap) {
+        launch_cg_mp(st, a, P_F64, 1);
+        launch_cg_upd(st, a, P_F64, 1, false);
+        launch_cg_p(st, a, P_F64);
+        TM_HIP(hipGetLastError());
+        TM_HIP(hipMemcpyAsync(&q, a.scal, sizeof(CgScal), hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        if (hist) hist->push_back(q.rr / q.bb);
+        if ((s = maybe_cut(q.iters)) != TM_OK) return s;
+    }
+    if (xstar_out) TM_HIP(hipMemcpyAsync(xstar_out, a.x, fb, hipMemcpyDeviceToDevice, st));
+    TM_HIP(hipStreamSynchronize(st));
+    return TM_OK;
+}
+
 // Solve nrhs sources (ids on the device) with the given settings.  On
 // return the stream is synchronised, ctx->scal_host[0..nrhs) holds the final
 // per-source state and res the native solutions.
 static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t seed_mixed, const uint64_t* ids_dev,
                              int nrhs, int nr, const std::string& tag, BlockResult* res) {
+    if (p->solver == TM_SOLVER_FCG_LEARNED) return solve_block_fcg(ctx, p, seed_mixed, ids_dev, nrhs, tag, res);
     const Geom& g = ctx->geo;
     hipStream_t st = ctx->stream;
     tm_status s = TM_OK;
@@ -209,7 +379,7 @@ static void fill_stats(const CgScal& q, tsm_solve_stats* o) {
     o->iters = q.iters;
     o->converged = q.status == 1;
     o->truncated = q.status == 2;
-    o->fell_back = 0;
+    o->fell_back = q.fell_back;
     if (q.stop == 1)
         o->resid_iterated = q.ee > 0 ? std::sqrt(q.rho2 / q.ee) : 0.0;
     else

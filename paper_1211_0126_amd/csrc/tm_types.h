@@ -28,6 +28,21 @@ struct CgScal {
     int32_t n_reliable;
     int32_t stop;       // 0 normal-equation residual, 1 tracked true residual
     int32_t reliable;   // 1: reliable-update mode
+    int32_t fell_back;  // flexible CG only: 1 if it fell back to plain CG
+    int32_t pad;
+};
+
+// Per-right-hand-side state of flexible CG (complex step scalars).
+struct FcgScal {
+    double zr_re, zr_im;        // <z, r>
+    double alpha_re, alpha_im;
+    double beta_re, beta_im;
+    double rr, rr_prev, bb, tt, tol2, resid_true;
+    double hist[5];             // |r|^2 of the last five steps
+    int32_t maxit, iters, active, status;
+    int32_t fell;               // 1 after the fallback to plain CG
+    int32_t mode;               // direction update: 0 z+beta p, 1 r+beta p, 2 r, 3 z
+    int32_t stagnant, pad;
 };
 
 // Lattice geometry as the kernels see it.
