@@ -24,6 +24,14 @@ from .binding import (  # noqa: F401
     tsm_loops,
     tm_profile_enable,
     tm_profile_read,
+    tm_precond_weight_count,
+    tm_precond_set,
+    tm_precond_get,
+    tm_precond_apply,
+    tm_precond_loss_grad,
+    tm_precond_train,
+    SOLVER_CG,
+    SOLVER_FCG_LEARNED,
     EXPORTS,
     LIB_PATH,
     PREC_F64,

@@ -76,6 +76,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libtmqcd.so is not built (%s); run __graft_entry__.build()" % path)
+    # torch ships its own HIP/HSA runtime libraries; load them first so that
+    # the library binds to the same runtime (two runtimes in one process do
+    # not see the device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, i32, u64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
     lib.tm_abi_version.restype = i32
@@ -125,7 +129,7 @@ class Context:
         h = ctypes.c_void_p()
         rc = self.lib.tm_create(ctypes.byref(lat), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
         if rc != TM_OK:
-            raise TmError(rc, "tm_create failed")
+            raise TmError(rc, self.lib.tm_last_error(None).decode())
         self.h = h
 
     def close(self):
@@ -274,3 +278,104 @@ def tm_profile_read(ctx: Context):
     by = np.zeros(n, dtype=np.float64)
     ctx.check(ctx.lib.tm_profile_read(ctx.h, _ptr(la), _ptr(ms), _ptr(by)))
     return {KC_NAMES[k]: {"launches": int(la[k]), "ms": float(ms[k]), "bytes": float(by[k])} for k in range(n)}
+
+
+# ---- learned preconditioner ------------------------------------------------
+
+NET_MAX_LAYERS = 8
+
+
+class NetShape(ctypes.Structure):
+    _fields_ = [("n_layers", ctypes.c_int32), ("widths", ctypes.c_int32 * (NET_MAX_LAYERS + 1))]
+
+
+class TrainParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("n_sources", ctypes.c_int32), ("n_pairs", ctypes.c_int32),
+                ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("hp_tol", ctypes.c_double), ("min_rel_err", ctypes.c_double), ("init_seed", ctypes.c_uint64),
+                ("init_scale", ctypes.c_double)]
+
+
+class TrainStats(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double), ("ms_generate", ctypes.c_double),
+                ("ms_train", ctypes.c_double), ("pairs", ctypes.c_int32), ("steps", ctypes.c_int32)]
+
+
+def _net_shape(widths) -> NetShape:
+    w = list(widths) + [0] * (NET_MAX_LAYERS + 1 - len(widths))
+    return NetShape(len(widths) - 1, (ctypes.c_int32 * (NET_MAX_LAYERS + 1))(*w))
+
+
+def _learn_sigs(lib):
+    P, i32 = ctypes.c_void_p, ctypes.c_int32
+    lib.tm_precond_weight_count.argtypes = [ctypes.POINTER(NetShape)]
+    lib.tm_precond_weight_count.restype = ctypes.c_size_t
+    lib.tm_precond_set.argtypes = [P, ctypes.POINTER(NetShape), P]
+    lib.tm_precond_set.restype = i32
+    lib.tm_precond_get.argtypes = [P, ctypes.POINTER(NetShape), P]
+    lib.tm_precond_get.restype = i32
+    lib.tm_precond_apply.argtypes = [P, i32, i32, P, P]
+    lib.tm_precond_apply.restype = i32
+    lib.tm_precond_loss_grad.argtypes = [P, i32, P, P, P, P]
+    lib.tm_precond_loss_grad.restype = i32
+    lib.tm_precond_train.argtypes = [P, ctypes.POINTER(TrainParams), ctypes.POINTER(TrainStats)]
+    lib.tm_precond_train.restype = i32
+
+
+EXPORTS += ["tm_precond_weight_count", "tm_precond_set", "tm_precond_get", "tm_precond_apply",
+            "tm_precond_loss_grad", "tm_precond_train"]
+
+
+def tm_precond_weight_count(widths) -> int:
+    lib = load_library()
+    _learn_sigs(lib)
+    return int(lib.tm_precond_weight_count(ctypes.byref(_net_shape(widths))))
+
+
+def tm_precond_set(ctx: Context, widths, weights: np.ndarray) -> None:
+    _learn_sigs(ctx.lib)
+    w = np.ascontiguousarray(weights, dtype=np.complex128)
+    assert w.size == tm_precond_weight_count(widths)
+    ctx.check(ctx.lib.tm_precond_set(ctx.h, ctypes.byref(_net_shape(widths)), _ptr(w)))
+
+
+def tm_precond_get(ctx: Context):
+    _learn_sigs(ctx.lib)
+    sh = NetShape()
+    ctx.check(ctx.lib.tm_precond_get(ctx.h, ctypes.byref(sh), None))
+    widths = [sh.widths[i] for i in range(sh.n_layers + 1)]
+    w = np.zeros(tm_precond_weight_count(widths), dtype=np.complex128)
+    ctx.check(ctx.lib.tm_precond_get(ctx.h, ctypes.byref(sh), _ptr(w)))
+    return widths, w
+
+
+def tm_precond_apply(ctx: Context, x, adjoint=False):
+    """N(x) or N^dag(x) for canonical complex128 [n][V][4][3] device tensors."""
+    import torch
+    _learn_sigs(ctx.lib)
+    assert x.dtype == torch.complex128 and x.is_cuda and x.is_contiguous()
+    out = torch.empty_like(x)
+    ctx.check(ctx.lib.tm_precond_apply(ctx.h, 1 if adjoint else 0, x.shape[0], ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def tm_precond_loss_grad(ctx: Context, r, e):
+    """Loss and Wirtinger gradient (d/d conj W) of pairs given as device tensors."""
+    _learn_sigs(ctx.lib)
+    widths, w = tm_precond_get(ctx)
+    loss = ctypes.c_double()
+    grad = np.zeros_like(w)
+    ctx.check(ctx.lib.tm_precond_loss_grad(ctx.h, r.shape[0], ctypes.c_void_p(r.data_ptr()),
+                                           ctypes.c_void_p(e.data_ptr()), ctypes.byref(loss), _ptr(grad)))
+    return loss.value, grad
+
+
+def tm_precond_train(ctx: Context, seed, n_sources, n_pairs, epochs, batch, lr=1e-3, hp_tol=1e-10,
+                     min_rel_err=1e-4, init_seed=1, init_scale=1e-2):
+    _learn_sigs(ctx.lib)
+    p = TrainParams(int(seed), int(n_sources), int(n_pairs), int(epochs), int(batch), float(lr), float(hp_tol),
+                    float(min_rel_err), int(init_seed), float(init_scale))
+    st = TrainStats()
+    ctx.check(ctx.lib.tm_precond_train(ctx.h, ctypes.byref(p), ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in TrainStats._fields_}

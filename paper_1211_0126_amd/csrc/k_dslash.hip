@@ -212,9 +212,9 @@ __device__ __forceinline__ double spinor_norm2(const cx<R> v[12]) {
 template <int OP, typename R, class Si, class So, class G, int NR>
 __global__ TM_STENCIL_R(NR, R) void k_apply(Geom geo, const void* gauge, R kappa, R twist, int nrhs,
                                                const void* in, void* out, const CgScal* gate) {
-    const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t s = b * 256u + threadIdx.x;
-    const int r0 = blockIdx.y * NR;
+    const BlockMap bm = stencil_block((uint32_t)(nrhs / NR));
+    const uint32_t s = bm.sb * 256u + threadIdx.x;
+    const int r0 = bm.ch * NR;
     if (s >= geo.V) return;
     if (gate != nullptr && !gate[r0].rflag) return;  // gated launches use NR = 1
     const Site c = site_coords(geo, s);
@@ -281,10 +281,10 @@ template <typename R, class S, class G, int NR>
 __global__ TM_STENCIL_R(NR, R) void k_cg_mp(CgArgs a) {
     __shared__ double sh[4];
     __shared__ int sflag;
-    const uint32_t nb = gridDim.x;
-    const uint32_t b = xcd_block(blockIdx.x, nb);
-    const uint32_t s = b * 256u + threadIdx.x;
-    const int r0 = blockIdx.y * NR;
+    const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
+    const uint32_t nb = bm.nsb;
+    const uint32_t s = bm.sb * 256u + threadIdx.x;
+    const int r0 = bm.ch * NR;
     const long Vs = a.geo.Vs;
     bool act[NR];
     bool any = false;
@@ -316,9 +316,9 @@ __global__ TM_STENCIL_R(NR, R) void k_cg_mp(CgArgs a) {
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         double v = block_sum256(part[r], sh);
-        if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * nb + blockIdx.x] = v;
+        if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * nb + bm.sb] = v;
     }
-    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
+    if (take_last_ticket(a.counters + bm.ch, nb, &sflag)) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             if (!act[r]) continue;
@@ -329,7 +329,7 @@ __global__ TM_STENCIL_R(NR, R) void k_cg_mp(CgArgs a) {
                 q.alpha = tt > 0 ? q.rr / tt : 0.0;
             }
         }
-        if (threadIdx.x == 0) a.counters[blockIdx.y] = 0;
+        if (threadIdx.x == 0) a.counters[bm.ch] = 0;
     }
 }
 
@@ -339,10 +339,10 @@ template <typename R, class S, class G, class X, typename RX, int NR, bool TRACK
 __global__ TM_STENCIL_R(NR, R) void k_cg_upd(CgArgs a) {
     __shared__ double sh[4];
     __shared__ int sflag;
-    const uint32_t nb = gridDim.x;
-    const uint32_t b = xcd_block(blockIdx.x, nb);
-    const uint32_t s = b * 256u + threadIdx.x;
-    const int r0 = blockIdx.y * NR;
+    const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
+    const uint32_t nb = bm.nsb;
+    const uint32_t s = bm.sb * 256u + threadIdx.x;
+    const int r0 = bm.ch * NR;
     const long Vs = a.geo.Vs;
     bool act[NR];
     bool any = false;
@@ -398,13 +398,13 @@ __global__ TM_STENCIL_R(NR, R) void k_cg_upd(CgArgs a) {
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         double v = block_sum256(prr[r], sh);
-        if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * nb + blockIdx.x] = v;
+        if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * nb + bm.sb] = v;
         if (TRACK) {
             double w = block_sum256(prho[r], sh);
-            if (threadIdx.x == 0) a.partials2[(size_t)(r0 + r) * nb + blockIdx.x] = w;
+            if (threadIdx.x == 0) a.partials2[(size_t)(r0 + r) * nb + bm.sb] = w;
         }
     }
-    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
+    if (take_last_ticket(a.counters + bm.ch, nb, &sflag)) {
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             if (!act[r]) continue;
@@ -412,7 +412,7 @@ __global__ TM_STENCIL_R(NR, R) void k_cg_upd(CgArgs a) {
             double rhon = TRACK ? sum_partials(a.partials2 + (size_t)(r0 + r) * nb, nb, sh) : 0.0;
             if (threadIdx.x == 0) cg_finish_step(a.scal[r0 + r], rrn, rhon);
         }
-        if (threadIdx.x == 0) a.counters[blockIdx.y] = 0;
+        if (threadIdx.x == 0) a.counters[bm.ch] = 0;
     }
 }
 
@@ -560,10 +560,10 @@ __global__ __launch_bounds__(256) void k_rel_flush(CgArgs a, void* x64, int forc
 __global__ TM_STENCIL_R(1, double) void k_rel_resid(CgArgs a, const void* gauge64, const void* b64, const void* t64) {
     __shared__ double sh[4];
     __shared__ int sflag;
-    const uint32_t nb = gridDim.x;
-    const uint32_t b = xcd_block(blockIdx.x, nb);
-    const uint32_t s = b * 256u + threadIdx.x;
-    const int r = blockIdx.y;
+    const BlockMap bm = stencil_block((uint32_t)a.nrhs);
+    const uint32_t nb = bm.nsb;
+    const uint32_t s = bm.sb * 256u + threadIdx.x;
+    const int r = bm.ch;
     const long Vs = a.geo.Vs;
     if (!a.scal[r].rflag) return;
     double pr = 0;
@@ -586,8 +586,8 @@ __global__ TM_STENCIL_R(1, double) void k_rel_resid(CgArgs a, const void* gauge6
         pr = spinor_norm2(bv);
     }
     double v = block_sum256(pr, sh);
-    if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
-    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
+    if (threadIdx.x == 0) a.partials[(size_t)r * nb + bm.sb] = v;
+    if (take_last_ticket(a.counters + bm.ch, nb, &sflag)) {
         double rrn = sum_partials(a.partials + (size_t)r * nb, nb, sh);
         if (threadIdx.x == 0) {
             CgScal& q = a.scal[r];
@@ -603,7 +603,7 @@ __global__ TM_STENCIL_R(1, double) void k_rel_resid(CgArgs a, const void* gauge6
                 q.status = 2;
                 q.active = 0;
             }
-            a.counters[blockIdx.y] = 0;
+            a.counters[bm.ch] = 0;
         }
     }
 }
@@ -614,10 +614,10 @@ __global__ TM_STENCIL_R(1, double) void k_true_resid(CgArgs a, const void* gauge
                                                     const uint64_t* ids) {
     __shared__ double sh[4];
     __shared__ int sflag;
-    const uint32_t nb = gridDim.x;
-    const uint32_t b = xcd_block(blockIdx.x, nb);
-    const uint32_t s = b * 256u + threadIdx.x;
-    const int r = blockIdx.y;
+    const BlockMap bm = stencil_block((uint32_t)a.nrhs);
+    const uint32_t nb = bm.nsb;
+    const uint32_t s = bm.sb * 256u + threadIdx.x;
+    const int r = bm.ch;
     const long Vs = a.geo.Vs;
     double pr = 0, pe = 0;
     if (s < a.geo.V) {
@@ -638,15 +638,15 @@ __global__ TM_STENCIL_R(1, double) void k_true_resid(CgArgs a, const void* gauge
         }
     }
     double v = block_sum256(pr, sh);
-    if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
+    if (threadIdx.x == 0) a.partials[(size_t)r * nb + bm.sb] = v;
     double w = block_sum256(pe, sh);
-    if (threadIdx.x == 0) a.partials2[(size_t)r * nb + blockIdx.x] = w;
-    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
+    if (threadIdx.x == 0) a.partials2[(size_t)r * nb + bm.sb] = w;
+    if (take_last_ticket(a.counters + bm.ch, nb, &sflag)) {
         double rr = sum_partials(a.partials + (size_t)r * nb, nb, sh);
         double ee = sum_partials(a.partials2 + (size_t)r * nb, nb, sh);
         if (threadIdx.x == 0) {
             a.scal[r].resid_true = sqrt(rr / ee);
-            a.counters[blockIdx.y] = 0;
+            a.counters[bm.ch] = 0;
         }
     }
 }
@@ -668,6 +668,11 @@ __global__ void k_scal_init(CgScal* sc, int n, double tol2, int maxit, int stop,
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+// 1-D grid of site blocks x right-hand-side chunks (see stencil_block)
+static inline dim3 stencil_grid(const Geom& g, int nch) {
+    return dim3((unsigned)(((g.V + 255) / 256) * nch), 1, 1);
+}
+
 static inline dim3 site_grid(const Geom& g, int ychunks) {
     return dim3((unsigned)((g.V + 255) / 256), (unsigned)ychunks, 1);
 }
@@ -676,21 +681,21 @@ template <int OP, typename R, class Si, class So, class G>
 static void apply_nr(hipStream_t st, const Geom& g, const void* gauge, double kappa, double twist, int nrhs,
                      const void* in, void* out, int nr, const CgScal* gate) {
     if constexpr (sizeof(R) == 8) {
-        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 1>), site_grid(g, nrhs), dim3(256), 0, st, g, gauge, (R)kappa,
+        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 1>), stencil_grid(g, nrhs), dim3(256), 0, st, g, gauge, (R)kappa,
                            (R)twist, nrhs, in, out, gate);
         return;
     }
     switch (nr) {
     case 4:
-        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 4>), site_grid(g, nrhs / 4), dim3(256), 0, st, g, gauge, (R)kappa,
+        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 4>), stencil_grid(g, nrhs / 4), dim3(256), 0, st, g, gauge, (R)kappa,
                            (R)twist, nrhs, in, out, gate);
         break;
     case 2:
-        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 2>), site_grid(g, nrhs / 2), dim3(256), 0, st, g, gauge, (R)kappa,
+        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 2>), stencil_grid(g, nrhs / 2), dim3(256), 0, st, g, gauge, (R)kappa,
                            (R)twist, nrhs, in, out, gate);
         break;
     default:
-        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 1>), site_grid(g, nrhs), dim3(256), 0, st, g, gauge, (R)kappa,
+        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 1>), stencil_grid(g, nrhs), dim3(256), 0, st, g, gauge, (R)kappa,
                            (R)twist, nrhs, in, out, gate);
         break;
     }
@@ -737,18 +742,18 @@ template <typename R, class S, class G>
 static void cg_mp_typed(hipStream_t st, const CgArgs& a, int nr) {
     const Geom& g = a.geo;
     if constexpr (sizeof(R) == 8) {
-        hipLaunchKernelGGL((k_cg_mp<R, S, G, 1>), site_grid(g, a.nrhs), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_cg_mp<R, S, G, 1>), stencil_grid(g, a.nrhs), dim3(256), 0, st, a);
         return;
     }
     switch (nr) {
     case 4:
-        hipLaunchKernelGGL((k_cg_mp<R, S, G, 4>), site_grid(g, a.nrhs / 4), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_cg_mp<R, S, G, 4>), stencil_grid(g, a.nrhs / 4), dim3(256), 0, st, a);
         break;
     case 2:
-        hipLaunchKernelGGL((k_cg_mp<R, S, G, 2>), site_grid(g, a.nrhs / 2), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_cg_mp<R, S, G, 2>), stencil_grid(g, a.nrhs / 2), dim3(256), 0, st, a);
         break;
     default:
-        hipLaunchKernelGGL((k_cg_mp<R, S, G, 1>), site_grid(g, a.nrhs), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_cg_mp<R, S, G, 1>), stencil_grid(g, a.nrhs), dim3(256), 0, st, a);
         break;
     }
 }
@@ -757,19 +762,19 @@ template <typename R, class S, class G, class X, typename RX>
 static void cg_upd_typed(hipStream_t st, const CgArgs& a, int nr, bool track) {
     const Geom& g = a.geo;
     if (track) {
-        hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 1, true>), site_grid(g, a.nrhs), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 1, true>), stencil_grid(g, a.nrhs), dim3(256), 0, st, a);
     } else if constexpr (sizeof(R) == 8) {
-        hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 1, false>), site_grid(g, a.nrhs), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 1, false>), stencil_grid(g, a.nrhs), dim3(256), 0, st, a);
     } else {
         switch (nr) {
         case 4:
-            hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 4, false>), site_grid(g, a.nrhs / 4), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 4, false>), stencil_grid(g, a.nrhs / 4), dim3(256), 0, st, a);
             break;
         case 2:
-            hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 2, false>), site_grid(g, a.nrhs / 2), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 2, false>), stencil_grid(g, a.nrhs / 2), dim3(256), 0, st, a);
             break;
         default:
-            hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 1, false>), site_grid(g, a.nrhs), dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_cg_upd<R, S, G, X, RX, 1, false>), stencil_grid(g, a.nrhs), dim3(256), 0, st, a);
             break;
         }
     }
@@ -850,12 +855,12 @@ void launch_rel_flush(hipStream_t st, const CgArgs& a, void* x64, int force) {
     hipLaunchKernelGGL(k_rel_flush, site_grid(a.geo, a.nrhs), dim3(256), 0, st, a, x64, force);
 }
 void launch_rel_resid(hipStream_t st, const CgArgs& a, const void* gauge64, const void* b64, const void* t64) {
-    hipLaunchKernelGGL(k_rel_resid, site_grid(a.geo, a.nrhs), dim3(256), 0, st, a, gauge64, b64, t64);
+    hipLaunchKernelGGL(k_rel_resid, stencil_grid(a.geo, a.nrhs), dim3(256), 0, st, a, gauge64, b64, t64);
 }
 
 void launch_true_resid(hipStream_t st, const CgArgs& a, int xprec, const void* gauge64, uint64_t seed_mixed,
                        const uint64_t* ids) {
-    dim3 grid = site_grid(a.geo, a.nrhs);
+    dim3 grid = stencil_grid(a.geo, a.nrhs);
     if (xprec == P_F64)
         hipLaunchKernelGGL((k_true_resid<SF64, double>), grid, dim3(256), 0, st, a, gauge64, seed_mixed, ids);
     else

@@ -9,6 +9,9 @@
 
 namespace tmq {
 
+// error text of the last failed tm_create on this thread (tm_last_error(NULL))
+static thread_local std::string g_create_error = "no error";
+
 tm_status set_error(tm_ctx* ctx, tm_status code, const std::string& msg) {
     if (ctx) ctx->err = msg;
     return code;
@@ -165,7 +168,9 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
         g.m[d] = (uint32_t)m;
     }
     ctx->twist = 2.0 * lat->kappa * lat->mu;
-    if (hipGetDevice(&ctx->device) != hipSuccess) {
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("tm_create: hipGetDevice: ") + hipGetErrorString(e);
         delete ctx;
         return TM_EDEVICE;
     }
@@ -174,8 +179,10 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
     int tab[128];
     std::memcpy(tab, col, sizeof(col));
     std::memcpy(tab + 64, ph, sizeof(ph));
-    if (hipMalloc(&ctx->gam_dev, sizeof(tab)) != hipSuccess ||
-        hipMemcpy(ctx->gam_dev, tab, sizeof(tab), hipMemcpyHostToDevice) != hipSuccess) {
+    e = hipMalloc(&ctx->gam_dev, sizeof(tab));
+    if (e == hipSuccess) e = hipMemcpy(ctx->gam_dev, tab, sizeof(tab), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        g_create_error = std::string("tm_create: device set-up: ") + hipGetErrorString(e);
         (void)hipGetLastError();
         delete ctx;
         return TM_EDEVICE;
@@ -199,7 +206,7 @@ tm_status tm_destroy(tm_ctx* ctx) {
     return TM_OK;
 }
 
-const char* tm_last_error(const tm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* tm_last_error(const tm_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
 tm_status tm_gauge_load(tm_ctx* ctx, const double* links_host) {
     if (!ctx || !links_host) return set_error(ctx, TM_EINVAL, "null argument");

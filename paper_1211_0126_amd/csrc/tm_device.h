@@ -335,6 +335,25 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
     return (b & 7u) * (full >> 3) + (b >> 3);
 }
 
+// Stencil launches are 1-D grids of nsb site blocks x nch right-hand-side
+// chunks.  After the XCD remap, consecutive logical blocks are the chunks of
+// one site block, so every chunk of a site block runs back to back on the same
+// XCD (its links and neighbours are served from that XCD's L2), and each XCD
+// sweeps one contiguous range of sites.
+struct BlockMap {
+    uint32_t sb;   // site block
+    uint32_t ch;   // right-hand-side chunk
+    uint32_t nsb;  // number of site blocks
+};
+__device__ __forceinline__ BlockMap stencil_block(uint32_t nch) {
+    const uint32_t L = xcd_block(blockIdx.x, gridDim.x);
+    BlockMap m;
+    m.nsb = gridDim.x / nch;
+    m.sb = L / nch;
+    m.ch = L - m.sb * nch;
+    return m;
+}
+
 // ---------------------------------------------------------------------------
 // Z4 noise: splitmix64 output mix (Steele, Lea & Flood 2014) applied to the
 // counter 1 + j*V + site of a stream started at mix(seed); component c takes

@@ -169,6 +169,8 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
         CgArgs at;
         std::memset(&at, 0, sizeof(at));
         at.geo = g;
+        at.kappa = ctx->lat.kappa;
+        at.twist = ctx->twist;
         at.x = a.x;
         at.scal = tscal;
         at.partials = part1;
