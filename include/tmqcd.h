@@ -314,6 +314,26 @@ typedef struct {
    Synchronous. */
 tm_status tm_precond_train(tm_ctx* ctx, const tm_train_params* params, tm_train_stats* stats);
 
+/* ---- tuning ------------------------------------------------------------- */
+
+/* Autotuner: time the operator M on nrhs fields (native layout) of storage
+   precision prec with 1, 2 and 4 right-hand sides per lane (those that
+   divide nrhs; FP64 runs 1), keep the fastest for later solves in that
+   precision, and report it in *best_nr and the mean milliseconds per
+   application of each candidate in ms_host[3] (negative where not run).
+   Needs a loaded gauge field.  Synchronous. */
+tm_status tm_autotune(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_nr, double* ms_host);
+
+/* Set (nr = 1, 2 or 4) or reset to the built-in choice (nr = 0) the
+   right-hand sides per lane used by solves in storage precision prec. */
+tm_status tm_set_lane_rhs(tm_ctx* ctx, int32_t prec, int32_t nr);
+
+/* CG iteration chunks are captured once into HIP graphs and replayed (on a
+   non-null stream, while per-launch profiling is off).  on = 1 enables (the
+   default), 0 disables, -1 leaves the setting; *replays (nullable) receives
+   the number of graph replays so far. */
+tm_status tm_set_graphs(tm_ctx* ctx, int32_t on, int64_t* replays);
+
 /* ---- instrumentation ---------------------------------------------------- */
 
 /* Kernel classes timed with HIP events on the context stream when profiling

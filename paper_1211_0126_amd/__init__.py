@@ -7,6 +7,7 @@ include/tmqcd.h); this package holds its sources (csrc/), the build script
 and a thin ctypes binding with the same entry-point names.
 """
 
+from .binding_tuning import tm_set_graphs  # noqa: F401
 from .binding import (  # noqa: F401
     Context,
     TmError,
@@ -30,6 +31,8 @@ from .binding import (  # noqa: F401
     tm_precond_apply,
     tm_precond_loss_grad,
     tm_precond_train,
+    tm_autotune,
+    tm_set_lane_rhs,
     SOLVER_CG,
     SOLVER_FCG_LEARNED,
     EXPORTS,

@@ -379,3 +379,25 @@ def tm_precond_train(ctx: Context, seed, n_sources, n_pairs, epochs, batch, lr=1
     st = TrainStats()
     ctx.check(ctx.lib.tm_precond_train(ctx.h, ctypes.byref(p), ctypes.byref(st)))
     return {f: getattr(st, f) for f, _ in TrainStats._fields_}
+
+
+# ---- tuning ------------------------------------------------------------------
+
+EXPORTS += ["tm_autotune", "tm_set_lane_rhs"]
+
+
+def tm_autotune(ctx: Context, prec, nrhs):
+    """Returns (best right-hand sides per lane, ms per application for 1, 2, 4)."""
+    ctx.lib.tm_autotune.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]
+    ctx.lib.tm_autotune.restype = ctypes.c_int32
+    best = ctypes.c_int32()
+    ms = np.zeros(3, dtype=np.float64)
+    ctx.check(ctx.lib.tm_autotune(ctx.h, int(prec), int(nrhs), ctypes.byref(best), _ptr(ms)))
+    return int(best.value), ms
+
+
+def tm_set_lane_rhs(ctx: Context, prec, nr):
+    ctx.lib.tm_set_lane_rhs.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+    ctx.lib.tm_set_lane_rhs.restype = ctypes.c_int32
+    ctx.check(ctx.lib.tm_set_lane_rhs(ctx.h, int(prec), int(nr)))

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <complex>
+#include <vector>
 
 #include "tm_ctx.h"
 #include "tm_learn.h"
@@ -202,6 +203,7 @@ tm_status tm_destroy(tm_ctx* ctx) {
     if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
     net_release(ctx);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
     delete ctx;
     return TM_OK;
 }
@@ -304,6 +306,76 @@ tm_status tm_noise_z4(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* 
     launch_noise_c128(ctx->stream, ctx->geo, seed_mix(seed), ids, nsrc, out_dev);
     TM_HIP(hipGetLastError());
     TM_HIP(hipStreamSynchronize(ctx->stream));  // ids_host may be released on return
+    return TM_OK;
+}
+
+tm_status tm_set_graphs(tm_ctx* ctx, int32_t on, int64_t* replays) {
+    if (!ctx) return TM_EINVAL;
+    if (on >= 0) ctx->use_graphs = on != 0;
+    if (replays) *replays = ctx->graph_launches;
+    return TM_OK;
+}
+
+tm_status tm_set_lane_rhs(tm_ctx* ctx, int32_t prec, int32_t nr) {
+    if (!ctx || prec < 0 || prec > 3 || !(nr == 0 || nr == 1 || nr == 2 || nr == 4))
+        return set_error(ctx, TM_EINVAL, "tm_set_lane_rhs: bad argument");
+    ctx->lane_rhs[prec] = prec == TM_PREC_F64 ? (nr ? 1 : 0) : nr;
+    return TM_OK;
+}
+
+tm_status tm_autotune(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_nr, double* ms_host) {
+    if (!ctx || prec < 0 || prec > 3 || nrhs < 1 || nrhs > 32 || !best_nr)
+        return set_error(ctx, TM_EINVAL, "tm_autotune: bad argument");
+    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tm_autotune: no gauge field loaded");
+    const Geom& g = ctx->geo;
+    tm_status s = TM_OK;
+    const size_t fb = field_bytes(g, prec, nrhs);
+    void* in = ws_get(ctx, "tune_in", fb, &s);
+    void* out = ws_get(ctx, "tune_out", fb, &s);
+    uint64_t* ids = (uint64_t*)ws_get(ctx, "tune_ids", sizeof(uint64_t) * nrhs, &s);
+    if (s != TM_OK) return s;
+    std::vector<uint64_t> idh(nrhs);
+    for (int i = 0; i < nrhs; i++) idh[i] = (uint64_t)i;
+    TM_HIP(hipMemcpy(ids, idh.data(), sizeof(uint64_t) * nrhs, hipMemcpyHostToDevice));
+    launch_noise_native(ctx->stream, g, prec, seed_mix(12345), ids, nrhs, in);
+    const void* gauge = prec == TM_PREC_F64 ? ctx->gauge64 : ctx->gauge32;
+    hipEvent_t e0, e1;
+    TM_HIP(hipEventCreate(&e0));
+    TM_HIP(hipEventCreate(&e1));
+    const int cand[3] = {1, 2, 4};
+    double best = 1e300;
+    int bnr = 1;
+    for (int c = 0; c < 3; c++) {
+        const int nr = cand[c];
+        if (ms_host) ms_host[c] = -1.0;
+        if (nrhs % nr != 0 || (prec == TM_PREC_F64 && nr != 1)) continue;
+        for (int w = 0; w < 2; w++)
+            launch_apply(ctx->stream, g, prec, gauge, ctx->lat.kappa, ctx->twist, 0, nrhs, in, out, nr, nullptr);
+        const int reps = 10;
+        (void)hipEventRecord(e0, ctx->stream);
+        for (int i = 0; i < reps; i++)
+            launch_apply(ctx->stream, g, prec, gauge, ctx->lat.kappa, ctx->twist, 0, nrhs, in, out, nr, nullptr);
+        (void)hipEventRecord(e1, ctx->stream);
+        hipError_t e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return dev_error(ctx, e, "tm_autotune timing");
+        }
+        const double per = ms / reps;
+        if (ms_host) ms_host[c] = per;
+        if (per < best) {
+            best = per;
+            bnr = nr;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->lane_rhs[prec] = bnr;
+    *best_nr = bnr;
     return TM_OK;
 }
 

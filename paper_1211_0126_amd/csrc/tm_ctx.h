@@ -37,6 +37,16 @@ struct tm_ctx {
     // learned preconditioner (weights and their bfloat16 fragments)
     struct NetState* net = nullptr;
 
+    // right-hand sides per lane chosen by tm_autotune / tm_set_lane_rhs, per
+    // storage precision (0: built-in default)
+    int lane_rhs[4] = {0, 0, 0, 0};
+
+    // captured CG chunks (replayed with hipGraphLaunch), keyed by buffers and
+    // launch configuration; used on a non-null stream when profiling is off
+    bool use_graphs = true;
+    std::map<std::string, hipGraphExec_t> graphs;
+    int64_t graph_launches = 0;
+
     std::string err;
     int sticky = 0;
 

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -53,9 +54,12 @@ static int default_block(const tsm_solve_params* p) {
     return p->reliable ? 8 : 16;
 }
 
-// right-hand sides per lane in the stencil kernels
-static int lane_rhs(const tsm_solve_params* p, int block) {
+// right-hand sides per lane in the stencil kernels: the tuned choice when it
+// divides the block, else the largest of 4, 2, 1 that does
+static int lane_rhs(const tm_ctx* ctx, const tsm_solve_params* p, int block) {
     if (p->prec == TM_PREC_F64 || p->stop == TM_STOP_TRUE) return 1;
+    const int t = ctx->lane_rhs[p->prec];
+    if (t > 0 && block % t == 0) return t;
     if (block % 4 == 0) return 4;
     if (block % 2 == 0) return 2;
     return 1;
@@ -329,23 +333,51 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
     for (;;) {
         int k = chunk;
         if (p->max_iter >= 0) k = std::max(1, std::min(chunk, p->max_iter - done));
-        for (int i = 0; i < k; i++) {
-            prof_begin(ctx, TM_KC_DSLASH);
-            launch_cg_mp(st, a, prec, nr);
-            prof_end(ctx, TM_KC_DSLASH, by.k1);
-            prof_begin(ctx, TM_KC_DSLASH_UPD);
-            launch_cg_upd(st, a, prec, nr, track);
-            prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
-            if (rel) {
-                prof_begin(ctx, TM_KC_OTHER);
-                launch_rel_flush(st, a, x64, 0);
-                launch_apply(st, g, P_F64, ctx->gauge64, ctx->lat.kappa, ctx->twist, 0, nrhs, x64, t64, 1, a.scal);
-                launch_rel_resid(st, a, ctx->gauge64, b64, t64);
-                prof_end(ctx, TM_KC_OTHER, 0.0);
+        auto steps = [&](int n) {
+            for (int i = 0; i < n; i++) {
+                prof_begin(ctx, TM_KC_DSLASH);
+                launch_cg_mp(st, a, prec, nr);
+                prof_end(ctx, TM_KC_DSLASH, by.k1);
+                prof_begin(ctx, TM_KC_DSLASH_UPD);
+                launch_cg_upd(st, a, prec, nr, track);
+                prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
+                if (rel) {
+                    prof_begin(ctx, TM_KC_OTHER);
+                    launch_rel_flush(st, a, x64, 0);
+                    launch_apply(st, g, P_F64, ctx->gauge64, ctx->lat.kappa, ctx->twist, 0, nrhs, x64, t64, 1,
+                                 a.scal);
+                    launch_rel_resid(st, a, ctx->gauge64, b64, t64);
+                    prof_end(ctx, TM_KC_OTHER, 0.0);
+                }
+                prof_begin(ctx, TM_KC_BLAS);
+                launch_cg_p(st, a, prec);
+                prof_end(ctx, TM_KC_BLAS, by.k3);
             }
-            prof_begin(ctx, TM_KC_BLAS);
-            launch_cg_p(st, a, prec);
-            prof_end(ctx, TM_KC_BLAS, by.k3);
+        };
+        if (ctx->use_graphs && !ctx->prof && st != nullptr) {
+            // the chunk's launches depend only on the buffers and the launch
+            // configuration, so one captured graph serves every chunk
+            char key[512];
+            std::snprintf(key, sizeof(key), "cg|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%d", a.p, a.t, a.r,
+                          a.x, a.rho, (void*)a.scal, (void*)a.partials, (void*)a.partials2, x64, t64, b64, prec, nr,
+                          (int)track, (int)rel, nrhs, k);
+            auto it = ctx->graphs.find(key);
+            if (it == ctx->graphs.end()) {
+                hipGraph_t graph;
+                TM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                steps(k);
+                hipError_t ce = hipStreamEndCapture(st, &graph);
+                if (ce != hipSuccess) return dev_error(ctx, ce, "hipStreamEndCapture");
+                hipGraphExec_t exec;
+                ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ce != hipSuccess) return dev_error(ctx, ce, "hipGraphInstantiate");
+                it = ctx->graphs.emplace(key, exec).first;
+            }
+            TM_HIP(hipGraphLaunch(it->second, st));
+            ctx->graph_launches++;
+        } else {
+            steps(k);
         }
         TM_HIP(hipGetLastError());
         done += k;
@@ -498,7 +530,7 @@ tm_status tsm_solve_batch(tm_ctx* ctx, const tsm_solve_params* params, uint64_t 
     if (nsrc == 0) return TM_OK;
     const Geom& g = ctx->geo;
     const int blk = default_block(params);
-    const int nr = lane_rhs(params, blk);
+    const int nr = lane_rhs(ctx, params, blk);
     // ids padded to a multiple of the lane width with repeats of the last id
     const int npad = (nsrc + nr - 1) / nr * nr;
     std::vector<uint64_t> ids(ids_host, ids_host + nsrc);
@@ -580,7 +612,7 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double
     const uint64_t sm = seed_mix(P->seed);
 
     const int blp = default_block(&P->lp), bhp = default_block(&P->hp);
-    const int nr_lp = lane_rhs(&P->lp, blp), nr_hp = lane_rhs(&P->hp, bhp);
+    const int nr_lp = lane_rhs(ctx, &P->lp, blp), nr_hp = lane_rhs(ctx, &P->hp, bhp);
     Contractor c;
     if ((s = setup_contract(ctx, mp, P->n_mom, std::max(blp, bhp) + 4, sm, &c)) != TM_OK) return s;
 
