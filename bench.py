@@ -8,7 +8,12 @@ field, by default the 32^3x64 workload (N_HP = 32, N_LP = 2048).
 value = N_LP / (wall time of the whole step): LP TSM sources per second,
 HP correction included.  Per-kernel durations come from HIP events recorded
 on the library's stream around every launch during the timed steps; the
-roofline entry is for the kernel class with the largest total time.
+roofline entry is the kernel class with the largest total time.
+
+After the timed steps (not part of them): plain FP32 single-RHS CG on the
+same GPU, and the LP configuration of the step (and, with --learned, flexible
+CG with the trained network) calibrated to the same median FP64 true
+residual, timed on the same sources.
 
 Prints one JSON line.
 """
@@ -16,7 +21,6 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,6 +34,8 @@ sys.path.insert(0, ROOT)
 METRIC = "LP TSM sources/s + Dslash HBM GB/s, learned/mixed vs plain CG at equal residual"
 HBM_PEAK_GBS = 8000.0
 PREC_NAMES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+KERNEL_OF = {"dslash": "k_cg_mp", "dslash_upd": "k_cg_upd", "blas": "k_cg_p", "contract": "k_contract",
+             "other": "init/residual", "apply": "k_apply"}
 
 
 def parse():
@@ -43,21 +49,63 @@ def parse():
     ap.add_argument("--hp-block", type=int, default=8)
     ap.add_argument("--n-lp", type=int, default=None, help="override N_LP (default: the workload's)")
     ap.add_argument("--n-hp", type=int, default=None)
+    ap.add_argument("--compare-sources", type=int, default=64)
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--learned", action="store_true", help="train the network and time flexible CG with it")
+    ap.add_argument("--train-pairs", type=int, default=200)
+    ap.add_argument("--train-sources", type=int, default=10)
+    ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32-reference", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     return ap.parse_args()
+
+
+def kname(v):
+    k = KERNEL_OF[v["kc"]]
+    return k.replace("k_cg_", "k_fcg_") if v.get("solver") == 1 else k
 
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def median_true(st):
+    return float(np.median([s["resid_true"] for s in st]))
+
+
+def timed_solve(tq, torch, ctx, params, seed, ids):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st, _ = tq.tsm_solve_batch(ctx, params, seed, ids, want_solutions=False)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, st
+
+
+def calibrate(tq, ctx, make, seed, ids, target, tol0):
+    """Bisect the stop tolerance (log scale) until the median true residual of
+    `ids` is within 5% of `target`; returns (tol, stats)."""
+    lo, hi = tol0 / 8, tol0 * 8
+    tol = tol0
+    best = None
+    for _ in range(10):
+        _, st, _ = tq.tsm_solve_batch(ctx, make(tol), seed, ids, want_solutions=False)
+        m = median_true(st)
+        best = (tol, st)
+        if abs(m / target - 1) <= 0.05:
+            break
+        if m > target:
+            hi = tol
+        else:
+            lo = tol
+        tol = float(np.sqrt(lo * hi))
+    return best
+
+
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (--gpus 1); the path shards by source, see the design notes",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only (--gpus 1): the estimator shards by source, so N GPUs would each run "
+              "this step on their own source range", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -72,10 +120,19 @@ def main():
     t0 = time.time()
     U = make_gauge(wl.dims, wl.eps, wl.gauge_seed)
     log("gauge generated in %.1f s" % (time.time() - t0))
-    ctx = tq.tm_create(wl.dims, wl.kappa, wl.mu, wl.t_bc)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = tq.tm_create(wl.dims, wl.kappa, wl.mu, wl.t_bc, stream=stream)
     tq.tm_gauge_load(ctx, U)
+    del U
     mom = wl.momenta()
     lp_prec = PREC_NAMES[args.lp_prec]
+    tune = {}
+    for prec, blk in ((lp_prec, args.lp_block), (tq.PREC_F32, args.hp_block)):
+        best, ms = tq.tm_autotune(ctx, prec, blk)
+        tune[[k for k, v in PREC_NAMES.items() if v == prec][0]] = {"lane_rhs": best, "ms_per_apply": ms.tolist(),
+                                                                     "rhs": blk}
+    log("autotune: %s" % tune)
     lp = tq.solve_params(prec=lp_prec, tol=wl.lp_tol, max_iter=wl.lp_maxit, rhs_block=args.lp_block, true_resid=1)
     hp = tq.solve_params(prec=tq.PREC_F32, tol=wl.hp_tol, max_iter=-1, reliable=1, delta=0.1,
                          rhs_block=args.hp_block, true_resid=1)
@@ -99,19 +156,23 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = tq.tm_profile_read(ctx)
+    variants = tq.tm_profile_entries(ctx)
     tq.tm_profile_enable(ctx, False)
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     value = n_lp / (ms_per_step / 1e3)
 
-    # dominant kernel class
-    dom = max(prof, key=lambda k: prof[k]["ms"])
-    d = prof[dom]
+    # dominant kernel: the variant (class, storage, RHS per lane, solver) with
+    # the largest total time; it is one compiled kernel in the rocprofv3 trace
+    d = max((v for v in variants if v["bytes"] > 0), key=lambda v: v["ms"])
     avg_ms = d["ms"] / max(d["launches"], 1)
     avg_bytes = d["bytes"] / max(d["launches"], 1)
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
+    prec_name = {v: k for k, v in PREC_NAMES.items()}
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
-                "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": avg_bytes}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "%s %s NR=%d" % (kname(d), prec_name[d["prec"]], d["lane_rhs"]),
+                "launches": d["launches"], "avg_launch_us": round(avg_ms * 1e3, 2),
+                "algorithmic_bytes_per_launch": avg_bytes}
     per_class = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / max(v["launches"], 1), 2),
                      "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1) if v["bytes"] > 0 else None,
                      "total_ms": round(v["ms"], 1)} for k, v in prof.items()}
@@ -121,7 +182,6 @@ def main():
     lp_iters = [s[0]["iters"] for s in st]
     hp_iters = [s[1]["iters"] for s in st[:n_hp]]
     run = res["run"]
-
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -144,6 +204,7 @@ def main():
             "n_hp": n_hp, "n_lp": n_lp, "lp_storage": args.lp_prec, "lp_rhs_block": args.lp_block,
             "hp_rhs_block": args.hp_block,
         },
+        "autotune": tune,
         "lp_phase_sources_per_s": round(n_lp / (run["ms_lp_phase"] / 1e3), 2),
         "hp_phase_ms": round(run["ms_hp_phase"], 1),
         "lp_iters_mean": round(float(np.mean(lp_iters)), 2),
@@ -152,49 +213,74 @@ def main():
         "lp_true_resid_max": float(np.max(lp_true)),
         "hp_true_resid_max": run["max_hp_resid_true"],
         "kernels": per_class,
+        "kernel_variants": [{"kernel": kname(v), "prec": v["prec"], "lane_rhs": v["lane_rhs"],
+                             "launches": v["launches"], "avg_us": round(1e3 * v["ms"] / max(v["launches"], 1), 2),
+                             "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1) if v["bytes"] > 0 else None}
+                            for v in variants if v["prec"] >= 0],
         "roofline": roofline,
     }
 
-    # plain FP32 single-RHS CG on the same GPU, same sources, same stop
-    if not args.no_fp32_reference:
-        ns = 64
-        ids = list(range(n_hp, n_hp + ns))
-        ref_p = tq.solve_params(prec=tq.PREC_F32, tol=wl.lp_tol, max_iter=wl.lp_maxit, rhs_block=1, true_resid=1)
-        cand_p = tq.solve_params(prec=lp_prec, tol=wl.lp_tol, max_iter=wl.lp_maxit, rhs_block=args.lp_block,
-                                 true_resid=1)
-        tq.tsm_solve_batch(ctx, ref_p, wl.noise_seed, ids[:4], want_solutions=False)  # warm
-        torch.cuda.synchronize()
-        ta = time.perf_counter()
-        _, st_ref, _ = tq.tsm_solve_batch(ctx, ref_p, wl.noise_seed, ids, want_solutions=False)
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        _, st_c, _ = tq.tsm_solve_batch(ctx, cand_p, wl.noise_seed, ids, want_solutions=False)
-        torch.cuda.synchronize()
-        tc = time.perf_counter()
-        out["fp32_1rhs_reference"] = {
-            "sources": ns,
-            "solve_sources_per_s": round(ns / (tb - ta), 2),
-            "true_resid_median": float(np.median([s["resid_true"] for s in st_ref])),
-            "iters_mean": float(np.mean([s["iters"] for s in st_ref])),
-            "candidate_solve_sources_per_s": round(ns / (tc - tb), 2),
-            "candidate_true_resid_median": float(np.median([s["resid_true"] for s in st_c])),
-            "speedup": round((tb - ta) / (tc - tb), 3),
-        }
-        log("fp32 1-rhs reference: %s" % out["fp32_1rhs_reference"])
+    if not args.no_compare:
+        out["equal_residual"] = compare(args, tq, torch, ctx, wl, n_hp, lp_prec)
 
     ctx.close()
-
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, U, args.cpu_threads)
-
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_threads)
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(wl, U, threads):
+def compare(args, tq, torch, ctx, wl, n_hp, lp_prec):
+    """Plain FP32 single-RHS CG vs the batched reduced-precision LP solver
+    (and optionally learned flexible CG) at equal median true residual."""
+    ns = args.compare_sources
+    ids = list(range(n_hp, n_hp + ns))
+    cal_ids = ids[:16]
+    ref_p = tq.solve_params(prec=tq.PREC_F32, tol=wl.lp_tol, max_iter=-1, rhs_block=1, true_resid=1)
+    tq.tsm_solve_batch(ctx, ref_p, wl.noise_seed, ids[:2], want_solutions=False)  # warm
+    t_ref, st_ref = timed_solve(tq, torch, ctx, ref_p, wl.noise_seed, ids)
+    target = median_true(st_ref)
+    res = {"sources": ns, "target_true_resid": target,
+           "plain_fp32_1rhs": {"tol": wl.lp_tol, "sources_per_s": round(ns / t_ref, 2),
+                               "iters_mean": float(np.mean([s["iters"] for s in st_ref])),
+                               "true_resid_median": target}}
+    log("plain FP32 1-RHS CG: %.2f sources/s, true residual %.4g" % (ns / t_ref, target))
+
+    def mk_batched(tol):
+        return tq.solve_params(prec=lp_prec, tol=tol, max_iter=-1, rhs_block=args.lp_block, true_resid=1)
+    tol_b, _ = calibrate(tq, ctx, mk_batched, wl.noise_seed, cal_ids, target, wl.lp_tol)
+    t_b, st_b = timed_solve(tq, torch, ctx, mk_batched(tol_b), wl.noise_seed, ids)
+    res["batched_mixed"] = {"storage": args.lp_prec, "rhs_block": args.lp_block, "tol": tol_b,
+                            "sources_per_s": round(ns / t_b, 2),
+                            "iters_mean": float(np.mean([s["iters"] for s in st_b])),
+                            "true_resid_median": median_true(st_b), "speedup": round(t_ref / t_b, 3)}
+    log("batched %s: %s" % (args.lp_prec, res["batched_mixed"]))
+
+    if args.learned:
+        tr = tq.tm_precond_train(ctx, seed=0x5EED0000 + wl.noise_seed, n_sources=args.train_sources,
+                                 n_pairs=args.train_pairs, epochs=args.train_epochs, batch=8, lr=2e-3,
+                                 hp_tol=wl.hp_tol, min_rel_err=1e-3, init_seed=7, init_scale=1e-2)
+        log("trained: %s" % tr)
+
+        def mk_fcg(tol):
+            return tq.solve_params(prec=tq.PREC_F32, tol=tol, max_iter=-1, rhs_block=args.lp_block, true_resid=1,
+                                   solver=tq.SOLVER_FCG_LEARNED)
+        tol_f, _ = calibrate(tq, ctx, mk_fcg, wl.noise_seed, cal_ids, target, wl.lp_tol)
+        t_f, st_f = timed_solve(tq, torch, ctx, mk_fcg(tol_f), wl.noise_seed, ids)
+        res["learned_fcg"] = {"train": tr, "tol": tol_f, "sources_per_s": round(ns / t_f, 2),
+                              "iters_mean": float(np.mean([s["iters"] for s in st_f])),
+                              "fell_back": int(sum(s["fell_back"] for s in st_f)),
+                              "true_resid_median": median_true(st_f), "speedup": round(t_ref / t_f, 3)}
+        log("learned FCG: %s" % res["learned_fcg"])
+    return res
+
+
+def cpu_baseline(wl, threads):
     """The FP64 oracle on the host cores: one LP source (CG to the LP
     tolerance on the normal equations) plus its loop contraction on the
     same lattice, scaled to LP sources/s."""
     import oracle
+    from lattice_inputs import make_gauge
+    U = make_gauge(wl.dims, wl.eps, wl.gauge_seed)
     n = threads or min(16, os.cpu_count() or 1)
     oracle.set_threads(n)
     used = oracle.get_threads()

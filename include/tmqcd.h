@@ -357,6 +357,24 @@ tm_status tm_profile_enable(tm_ctx* ctx, int32_t on);
    TM_KC_COUNT each; any pointer may be NULL). */
 tm_status tm_profile_read(tm_ctx* ctx, int64_t* launches, double* ms, double* bytes);
 
+/* The same figures split by kernel variant: one entry per (kernel class,
+   storage precision, right-hand sides per lane, solver) seen since the last
+   tm_profile_enable, so that an entry corresponds to one compiled kernel.
+   Launches that carry no variant (initialisation, residuals, contraction,
+   tm_dslash) have prec = lane_rhs = solver = -1.  Writes at most `cap`
+   entries to `out` (host array) and their number to *n; TM_EINVAL if a
+   pointer is NULL or cap < 0. */
+typedef struct {
+    int32_t kc;       /* TM_KC_* */
+    int32_t prec;     /* tm_prec of the stored fields, or -1 */
+    int32_t lane_rhs; /* right-hand sides per lane, or -1 */
+    int32_t solver;   /* tm_solver, or -1 */
+    int64_t launches;
+    double ms;
+    double bytes;
+} tm_profile_entry;
+tm_status tm_profile_entries(tm_ctx* ctx, tm_profile_entry* out, int32_t cap, int32_t* n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,7 +69,7 @@ uint64_t seed_mix(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-void prof_begin(tm_ctx* ctx, int kc) {
+void prof_begin(tm_ctx* ctx, int kc, int tag) {
     if (!ctx->prof) return;
     while (ctx->ev_used + 2 > ctx->ev_pool.size()) {
         hipEvent_t e;
@@ -82,7 +82,7 @@ void prof_begin(tm_ctx* ctx, int kc) {
     hipEvent_t a = ctx->ev_pool[ctx->ev_used++];
     hipEvent_t b = ctx->ev_pool[ctx->ev_used++];
     (void)hipEventRecord(a, ctx->stream);
-    ctx->recs.push_back({kc, a, b, 0.0});
+    ctx->recs.push_back({kc, tag, a, b, 0.0});
 }
 
 void prof_end(tm_ctx* ctx, int kc, double bytes) {
@@ -156,7 +156,15 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
     for (int d = 0; d < 4; d++) g.L[d] = lat->dims[d];
     g.t_bc = lat->t_bc;
     g.V = V;
+    // Plane stride: a multiple of 256 sites, made an odd multiple so that the
+    // byte distance between planes (16 * Vs) is an odd multiple of 4 KiB.  A
+    // power-of-two distance (every even lattice with 2^k sites) puts the same
+    // site of all planes, and of all right-hand sides, on the same memory
+    // channel.
     g.Vs = (V + 255) / 256 * 256;
+#ifndef TM_POW2_PLANES
+    if ((g.Vs / 256) % 2 == 0) g.Vs += 256;
+#endif
     for (int d = 0; d < 3; d++) {
         uint64_t dd = (uint64_t)g.L[d];
         uint64_t m = ((1ULL << 32) + dd - 1) / dd;
@@ -385,6 +393,7 @@ tm_status tm_profile_enable(tm_ctx* ctx, int32_t on) {
     ctx->prof = on != 0;
     ctx->recs.clear();
     ctx->ev_used = 0;
+    ctx->prof_variants.clear();
     for (int k = 0; k < TM_KC_COUNT; k++) {
         ctx->prof_launches[k] = 0;
         ctx->prof_ms[k] = 0;
@@ -393,8 +402,8 @@ tm_status tm_profile_enable(tm_ctx* ctx, int32_t on) {
     return TM_OK;
 }
 
-tm_status tm_profile_read(tm_ctx* ctx, int64_t* launches, double* ms, double* bytes) {
-    if (!ctx) return TM_EINVAL;
+// fold the recorded launches into the per-class and per-variant sums
+static tm_status prof_drain(tm_ctx* ctx) {
     TM_HIP(hipStreamSynchronize(ctx->stream));
     for (auto& r : ctx->recs) {
         float t = 0;
@@ -402,9 +411,42 @@ tm_status tm_profile_read(tm_ctx* ctx, int64_t* launches, double* ms, double* by
         ctx->prof_launches[r.kc] += 1;
         ctx->prof_ms[r.kc] += t;
         ctx->prof_bytes[r.kc] += r.bytes;
+        auto& v = ctx->prof_variants[{r.kc, r.tag}];
+        v.launches += 1;
+        v.ms += t;
+        v.bytes += r.bytes;
     }
     ctx->recs.clear();
     ctx->ev_used = 0;
+    return TM_OK;
+}
+
+tm_status tm_profile_entries(tm_ctx* ctx, tm_profile_entry* out, int32_t cap, int32_t* n) {
+    if (!ctx || !out || !n || cap < 0) return ctx ? set_error(ctx, TM_EINVAL, "tm_profile_entries: bad arguments")
+                                                  : TM_EINVAL;
+    tm_status s = prof_drain(ctx);
+    if (s != TM_OK) return s;
+    int32_t k = 0;
+    for (auto& kv : ctx->prof_variants) {
+        if (k >= cap) break;
+        const int tag = kv.first.second;
+        tm_profile_entry& e = out[k++];
+        e.kc = kv.first.first;
+        e.prec = tag < 0 ? -1 : (tag & 15);
+        e.lane_rhs = tag < 0 ? -1 : ((tag >> 4) & 255);
+        e.solver = tag < 0 ? -1 : (tag >> 12);
+        e.launches = kv.second.launches;
+        e.ms = kv.second.ms;
+        e.bytes = kv.second.bytes;
+    }
+    *n = k;
+    return TM_OK;
+}
+
+tm_status tm_profile_read(tm_ctx* ctx, int64_t* launches, double* ms, double* bytes) {
+    if (!ctx) return TM_EINVAL;
+    tm_status s = prof_drain(ctx);
+    if (s != TM_OK) return s;
     for (int k = 0; k < TM_KC_COUNT; k++) {
         if (launches) launches[k] = ctx->prof_launches[k];
         if (ms) ms[k] = ctx->prof_ms[k];

@@ -54,9 +54,15 @@ struct tm_ctx {
     bool prof = false;
     struct Rec {
         int kc;
+        int tag;  // prof_tag() of the launch, -1 if none
         hipEvent_t a, b;
         double bytes;
     };
+    struct Acc {
+        int64_t launches = 0;
+        double ms = 0, bytes = 0;
+    };
+    std::map<std::pair<int, int>, Acc> prof_variants;  // (kc, tag)
     std::vector<Rec> recs;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
@@ -74,7 +80,9 @@ size_t field_bytes(const Geom& g, int prec, int nrhs);
 uint64_t seed_mix(uint64_t seed);
 
 // instrumentation around a launch of kernel class kc moving `bytes`
-void prof_begin(tm_ctx* ctx, int kc);
+// tag: prof_tag(prec, lane_rhs, solver) of the launched kernel, -1 if none
+void prof_begin(tm_ctx* ctx, int kc, int tag = -1);
+inline int prof_tag(int prec, int lane_rhs, int solver) { return prec | (lane_rhs << 4) | (solver << 12); }
 void prof_end(tm_ctx* ctx, int kc, double bytes);
 
 }  // namespace tmq

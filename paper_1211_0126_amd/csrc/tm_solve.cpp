@@ -145,15 +145,15 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
         int k = 8;
         if (p->max_iter >= 0) k = std::max(1, std::min(8, p->max_iter - done));
         for (int i = 0; i < k; i++) {
-            prof_begin(ctx, TM_KC_DSLASH);
+            prof_begin(ctx, TM_KC_DSLASH, prof_tag(P_F32, 1, TM_SOLVER_FCG_LEARNED));
             launch_fcg_mp(st, a);
             prof_end(ctx, TM_KC_DSLASH, by.k1);
-            prof_begin(ctx, TM_KC_DSLASH_UPD);
+            prof_begin(ctx, TM_KC_DSLASH_UPD, prof_tag(P_F32, 1, TM_SOLVER_FCG_LEARNED));
             launch_fcg_upd(st, a);
             prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
             if ((s = net_precondition(ctx, nrhs, a.r, a.z)) != TM_OK) return s;
             launch_fcg_dot(st, a, 0);
-            prof_begin(ctx, TM_KC_BLAS);
+            prof_begin(ctx, TM_KC_BLAS, prof_tag(P_F32, 1, TM_SOLVER_FCG_LEARNED));
             launch_fcg_p(st, a);
             prof_end(ctx, TM_KC_BLAS, by.k3);
         }
@@ -329,16 +329,17 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
     TM_HIP(hipGetLastError());
 
     const int chunk = rel ? 16 : 8;
+    const int vtag = prof_tag(prec, prec == P_F64 ? 1 : nr, TM_SOLVER_CG);
     int done = 0;
     for (;;) {
         int k = chunk;
         if (p->max_iter >= 0) k = std::max(1, std::min(chunk, p->max_iter - done));
         auto steps = [&](int n) {
             for (int i = 0; i < n; i++) {
-                prof_begin(ctx, TM_KC_DSLASH);
+                prof_begin(ctx, TM_KC_DSLASH, vtag);
                 launch_cg_mp(st, a, prec, nr);
                 prof_end(ctx, TM_KC_DSLASH, by.k1);
-                prof_begin(ctx, TM_KC_DSLASH_UPD);
+                prof_begin(ctx, TM_KC_DSLASH_UPD, track ? prof_tag(prec, 1, TM_SOLVER_CG) : vtag);
                 launch_cg_upd(st, a, prec, nr, track);
                 prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
                 if (rel) {
@@ -349,7 +350,7 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
                     launch_rel_resid(st, a, ctx->gauge64, b64, t64);
                     prof_end(ctx, TM_KC_OTHER, 0.0);
                 }
-                prof_begin(ctx, TM_KC_BLAS);
+                prof_begin(ctx, TM_KC_BLAS, prof_tag(prec, 1, TM_SOLVER_CG));
                 launch_cg_p(st, a, prec);
                 prof_end(ctx, TM_KC_BLAS, by.k3);
             }
