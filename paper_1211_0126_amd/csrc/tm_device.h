@@ -51,6 +51,18 @@ __device__ __forceinline__ uint32_t f32_to_bf16(float f) {
     return u >> 16;
 }
 __device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+#ifdef TM_F16_ASM_CVT
+__device__ __forceinline__ uint32_t f32_to_f16(float f) {
+    uint32_t h;
+    asm volatile("v_cvt_f16_f32 %0, %1" : "=v"(h) : "v"(f));
+    return h & 0xFFFFu;
+}
+__device__ __forceinline__ float f16_to_f32(uint32_t h) {
+    float f;
+    asm volatile("v_cvt_f32_f16 %0, %1" : "=v"(f) : "v"(h & 0xFFFFu));
+    return f;
+}
+#else
 __device__ __forceinline__ uint32_t f32_to_f16(float f) {
     _Float16 h = (_Float16)f;
     return (uint32_t)__builtin_bit_cast(uint16_t, h);
@@ -58,6 +70,7 @@ __device__ __forceinline__ uint32_t f32_to_f16(float f) {
 __device__ __forceinline__ float f16_to_f32(uint32_t h) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(h & 0xFFFFu));
 }
+#endif
 
 // ---------------------------------------------------------------------------
 // native spinor storage: component planes of 16-byte vectors, stride Vs
@@ -99,11 +112,19 @@ __device__ __forceinline__ T ld_plane(const void* base, long Vs, int k, uint32_t
     auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc_of(base), s << 4, (uint32_t)((size_t)k * Vs * 16), 0);
     return __builtin_bit_cast(T, v);
 }
+// A 128-bit store reads its data registers after it issues; the compiler's
+// hazard model adds wait states before those registers are rewritten only
+// when the store's scalar offset is not a register, which it is here.  The
+// guard below takes the data as operands of a few wait states placed after
+// the store, so no instruction can overwrite them earlier.  (Without it,
+// stores issued under memory pressure intermittently wrote the next values
+// of the data registers for some lanes.)
 template <typename T>
 __device__ __forceinline__ void st_plane(void* base, long Vs, int k, uint32_t s, T val) {
     using V4 = unsigned int __attribute__((ext_vector_type(4)));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, val), rsrc_of(base), s << 4,
-                                           (uint32_t)((size_t)k * Vs * 16), 0);
+    const V4 v = __builtin_bit_cast(V4, val);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rsrc_of(base), s << 4, (uint32_t)((size_t)k * Vs * 16), 0);
+    asm volatile("s_nop 4" ::"v"(v) : "memory");
 }
 
 template <class S, typename R>

@@ -1,0 +1,61 @@
+"""Reduced-precision storage on a lattice large enough to load the memory
+system (16^3 x 32): the operator is deterministic and accurate to the
+storage rounding at every site, and LP solves with FP16 / BF16 storage take
+the iterations of FP32 storage.  Regression test for stores whose data
+registers were rewritten before the store had read them, which corrupted
+some lanes intermittently and only under memory pressure."""
+
+import pytest
+import torch
+
+from lattice_inputs import make_gauge
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (16, 16, 16, 32)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1211_0126_amd as tq
+    U = make_gauge(DIMS, 0.25, 1001)
+    c = tq.tm_create(DIMS, 0.1632, 0.004, -1)
+    tq.tm_gauge_load(c, U)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("nrhs", [1, 2, 4])
+def test_half_storage_operator_deterministic_and_sitewise_accurate(ctx, prec, nrhs):
+    import paper_1211_0126_amd as tq
+    g = torch.Generator(device="cuda").manual_seed(11 + nrhs)
+    x = torch.randn((nrhs, ctx.V, 4, 3), dtype=torch.complex64, device="cuda", generator=g)
+    dt = torch.float16 if prec == 2 else torch.bfloat16
+    xh = torch.view_as_real(x).to(dt).contiguous()
+    xr = torch.view_as_complex(xh.float().contiguous()).contiguous()  # the stored values, exactly
+    ref = tq.tm_dslash(ctx, tq.OP_M, tq.PREC_F32, xr)
+    ys = [tq.tm_dslash(ctx, tq.OP_M, prec, xh) for _ in range(4)]
+    for y in ys[1:]:
+        assert torch.equal(y, ys[0])
+    y = torch.view_as_complex(ys[0].float().contiguous())
+    # output rounding only: 2^-11 (FP16) or 2^-8 (BF16) of each component
+    # (the arithmetic is FP32); bound per site against the global scale
+    err = (y - ref).abs().amax(dim=(2, 3)) / ref.abs().amax()
+    bound = 1e-3 if prec == 2 else 8e-3
+    assert err.max().item() < bound, err.max().item()
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("blk", [1, 4, 8])
+def test_half_storage_lp_solves_match_fp32_iterations(ctx, prec, blk):
+    import paper_1211_0126_amd as tq
+    ids = list(range(8))
+    ref = tq.solve_params(prec=tq.PREC_F32, tol=1e-2, max_iter=400, rhs_block=blk)
+    _, st32, _ = tq.tsm_solve_batch(ctx, ref, 2001, ids, want_solutions=False)
+    p = tq.solve_params(prec=prec, tol=1e-2, max_iter=400, rhs_block=blk)
+    for _ in range(2):
+        _, st, _ = tq.tsm_solve_batch(ctx, p, 2001, ids, want_solutions=False)
+        for a, b in zip(st, st32):
+            assert a["converged"] and abs(a["iters"] - b["iters"]) <= 1, (a, b)
+            assert a["resid_true"] < 1.1 * b["resid_true"] + 1e-3, (a, b)
