@@ -343,7 +343,7 @@ enum {
     TM_KC_DSLASH_UPD = 1, /* q = M^dag t fused with x, r updates (+ |r|^2) */
     TM_KC_BLAS = 2,       /* p = r + beta p */
     TM_KC_CONTRACT = 3,   /* loop contraction */
-    TM_KC_OTHER = 4,      /* noise, initialisation, reliable updates, residuals */
+    TM_KC_OTHER = 4,      /* noise, initialisation, CG scalar reductions, reliable updates, residuals */
     TM_KC_APPLY = 5,      /* tm_dslash applications */
     TM_KC_COUNT = 6
 };

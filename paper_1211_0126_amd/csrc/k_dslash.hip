@@ -12,11 +12,16 @@
 // hop costs two SU(3) matrix-vector products.  Sites are dealt to blocks of
 // 256 with an XCD-aware block order.
 //
-// The CG iteration on M^dag M is three launches per step:
-//   K1  t = M p,          |t|^2 -> alpha = |r|^2/|t|^2       (last block)
-//   K2  q = M^dag t,  r -= alpha q,  x += alpha p,  |r|^2 -> beta, stop test
+// The CG iteration on M^dag M is five launches per step:
+//   K1  t = M p,                               block partials of |t|^2
+//   R1  alpha = |r|^2/|t|^2                    (one block per right-hand side)
+//   K2  q = M^dag t,  r -= alpha q,  x += alpha p,  block partials of |r|^2
+//   R2  beta, stop test                        (one block per right-hand side)
 //   K3  p = r + beta p
-// with the scalars of every right-hand side kept on the device.
+// with the scalars of every right-hand side kept on the device.  The
+// reductions are separate launches because a last-block-finalises pattern
+// needs a device-scope release per block, which on a multi-XCD part writes
+// back the XCD's L2 and costs more than the stencil itself.
 
 #include "tm_device.h"
 #include "tm_kernels.h"
@@ -280,7 +285,6 @@ __device__ inline void cg_finish_step(CgScal& q, double rrn, double rhon) {
 template <typename R, class S, class G, int NR>
 __global__ TM_STENCIL_R(NR, R) void k_cg_mp(CgArgs a) {
     __shared__ double sh[4];
-    __shared__ int sflag;
     const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
     const uint32_t nb = bm.nsb;
     const uint32_t s = bm.sb * 256u + threadIdx.x;
@@ -318,19 +322,39 @@ __global__ TM_STENCIL_R(NR, R) void k_cg_mp(CgArgs a) {
         double v = block_sum256(part[r], sh);
         if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * nb + bm.sb] = v;
     }
-    if (take_last_ticket(a.counters + bm.ch, nb, &sflag)) {
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            if (!act[r]) continue;
-            double tt = sum_partials(a.partials + (size_t)(r0 + r) * nb, nb, sh);
-            if (threadIdx.x == 0) {
-                CgScal& q = a.scal[r0 + r];
-                q.tt = tt;
-                q.alpha = tt > 0 ? q.rr / tt : 0.0;
-            }
-        }
-        if (threadIdx.x == 0) a.counters[bm.ch] = 0;
+}
+
+// Block partials of one right-hand side in a fixed order (the stencil
+// launch that wrote them has completed); valid in thread 0.
+__device__ __forceinline__ double sum_block_partials(const double* p, uint32_t n, double* sh) {
+    double v = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += 256) v += p[i];
+    return block_sum256(v, sh);
+}
+
+// after K1, one block per right-hand side: alpha = |r|^2 / |t|^2
+__global__ __launch_bounds__(256) void k_cg_alpha(CgArgs a, uint32_t nb) {
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
+    if (!a.scal[r].active) return;
+    const double tt = sum_block_partials(a.partials + (size_t)r * nb, nb, sh);
+    if (threadIdx.x == 0) {
+        CgScal& q = a.scal[r];
+        q.tt = tt;
+        q.alpha = tt > 0 ? q.rr / tt : 0.0;
     }
+}
+
+// after K2, one block per right-hand side: |r|^2 (and |rho|^2), beta and the
+// stop test
+template <bool TRACK>
+__global__ __launch_bounds__(256) void k_cg_beta(CgArgs a, uint32_t nb) {
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
+    if (!a.scal[r].active) return;
+    const double rrn = sum_block_partials(a.partials + (size_t)r * nb, nb, sh);
+    const double rhon = TRACK ? sum_block_partials(a.partials2 + (size_t)r * nb, nb, sh) : 0.0;
+    if (threadIdx.x == 0) cg_finish_step(a.scal[r], rrn, rhon);
 }
 
 // K2: q = M^dag t, r -= alpha q, x += alpha p (x of storage X), |r|^2,
@@ -338,7 +362,6 @@ __global__ TM_STENCIL_R(NR, R) void k_cg_mp(CgArgs a) {
 template <typename R, class S, class G, class X, typename RX, int NR, bool TRACK>
 __global__ TM_STENCIL_R(NR, R) void k_cg_upd(CgArgs a) {
     __shared__ double sh[4];
-    __shared__ int sflag;
     const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
     const uint32_t nb = bm.nsb;
     const uint32_t s = bm.sb * 256u + threadIdx.x;
@@ -403,16 +426,6 @@ __global__ TM_STENCIL_R(NR, R) void k_cg_upd(CgArgs a) {
             double w = block_sum256(prho[r], sh);
             if (threadIdx.x == 0) a.partials2[(size_t)(r0 + r) * nb + bm.sb] = w;
         }
-    }
-    if (take_last_ticket(a.counters + bm.ch, nb, &sflag)) {
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            if (!act[r]) continue;
-            double rrn = sum_partials(a.partials + (size_t)(r0 + r) * nb, nb, sh);
-            double rhon = TRACK ? sum_partials(a.partials2 + (size_t)(r0 + r) * nb, nb, sh) : 0.0;
-            if (threadIdx.x == 0) cg_finish_step(a.scal[r0 + r], rrn, rhon);
-        }
-        if (threadIdx.x == 0) a.counters[bm.ch] = 0;
     }
 }
 
@@ -801,6 +814,18 @@ void launch_cg_upd(hipStream_t st, const CgArgs& a, int prec, int nr, bool track
     case P_F16: cg_upd_typed<float, SF16, GF32, SF32, float>(st, a, nr, track); break;
     default: cg_upd_typed<float, SBF16, GF32, SF32, float>(st, a, nr, track); break;
     }
+}
+
+void launch_cg_alpha(hipStream_t st, const CgArgs& a) {
+    hipLaunchKernelGGL(k_cg_alpha, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, (uint32_t)((a.geo.V + 255) / 256));
+}
+
+void launch_cg_beta(hipStream_t st, const CgArgs& a, bool track) {
+    const uint32_t nb = (uint32_t)((a.geo.V + 255) / 256);
+    if (track)
+        hipLaunchKernelGGL(k_cg_beta<true>, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, nb);
+    else
+        hipLaunchKernelGGL(k_cg_beta<false>, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, nb);
 }
 
 void launch_cg_p(hipStream_t st, const CgArgs& a, int prec) {

@@ -96,6 +96,8 @@ void launch_scal_init(hipStream_t st, CgScal* sc, int n, double tol2, int maxit,
 void launch_cg_init(hipStream_t st, const CgArgs& a, int prec, bool track, const void* eta);
 void launch_cg_mp(hipStream_t st, const CgArgs& a, int prec, int nr);
 void launch_cg_upd(hipStream_t st, const CgArgs& a, int prec, int nr, bool track);
+void launch_cg_alpha(hipStream_t st, const CgArgs& a);              // after launch_cg_mp
+void launch_cg_beta(hipStream_t st, const CgArgs& a, bool track);   // after launch_cg_upd
 void launch_cg_p(hipStream_t st, const CgArgs& a, int prec);
 void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64);
 void launch_rel_flush(hipStream_t st, const CgArgs& a, void* x64, int force);

@@ -248,7 +248,9 @@ tm_status solve_f64_history(tm_ctx* ctx, uint64_t seed_mixed, const uint64_t* id
     if ((s = maybe_cut(0)) != TM_OK) return s;
     while (q.active && q.iters < kIterCap) {
         launch_cg_mp(st, a, P_F64, 1);
+        launch_cg_alpha(st, a);
         launch_cg_upd(st, a, P_F64, 1, false);
+        launch_cg_beta(st, a, false);
         launch_cg_p(st, a, P_F64);
         TM_HIP(hipGetLastError());
         TM_HIP(hipMemcpyAsync(&q, a.scal, sizeof(CgScal), hipMemcpyDeviceToHost, st));
@@ -339,9 +341,15 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
                 prof_begin(ctx, TM_KC_DSLASH, vtag);
                 launch_cg_mp(st, a, prec, nr);
                 prof_end(ctx, TM_KC_DSLASH, by.k1);
+                prof_begin(ctx, TM_KC_OTHER);
+                launch_cg_alpha(st, a);
+                prof_end(ctx, TM_KC_OTHER, 0.0);
                 prof_begin(ctx, TM_KC_DSLASH_UPD, track ? prof_tag(prec, 1, TM_SOLVER_CG) : vtag);
                 launch_cg_upd(st, a, prec, nr, track);
                 prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
+                prof_begin(ctx, TM_KC_OTHER);
+                launch_cg_beta(st, a, track);
+                prof_end(ctx, TM_KC_OTHER, 0.0);
                 if (rel) {
                     prof_begin(ctx, TM_KC_OTHER);
                     launch_rel_flush(st, a, x64, 0);
