@@ -218,26 +218,30 @@ template <int OP, typename R, class Si, class So, class G, int NR>
 __global__ TM_STENCIL_R(NR, R) void k_apply(Geom geo, const void* gauge, R kappa, R twist, int nrhs,
                                                const void* in, void* out, const CgScal* gate) {
     const BlockMap bm = stencil_block((uint32_t)(nrhs / NR));
-    const uint32_t s = bm.sb * 256u + threadIdx.x;
     const int r0 = bm.ch * NR;
-    if (s >= geo.V) return;
     if (gate != nullptr && !gate[r0].rflag) return;  // gated launches use NR = 1
-    const Site c = site_coords(geo, s);
     const void* in0 = field_rhs<Si>(in, geo.Vs, r0);
-    cx<R> acc[NR][12];
-    hop_all<OP == 1, R, Si, G, NR>(geo, gauge, in0, s, c, acc);
+    // gated launches use a small grid that strides over the site blocks
+    const uint32_t nsb_all = (uint32_t)((geo.V + 255) / 256);
+    for (uint32_t sb = bm.sb; sb < nsb_all; sb += bm.nsb) {
+        const uint32_t s = sb * 256u + threadIdx.x;
+        if (s >= geo.V) continue;
+        const Site c = site_coords(geo, s);
+        cx<R> acc[NR][12];
+        hop_all<OP == 1, R, Si, G, NR>(geo, gauge, in0, s, c, acc);
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        cx<R> o[12];
-        if (OP == 3) {
+        for (int r = 0; r < NR; r++) {
+            cx<R> o[12];
+            if (OP == 3) {
 #pragma unroll
-            for (int k = 0; k < 12; k++) o[k] = acc[r][k];
-        } else {
-            cx<R> pc[12];
-            load_spinor<Si, R>(field_rhs<Si>(in0, geo.Vs, r), geo.Vs, s, pc);
-            diag_combine(pc, acc[r], kappa, OP == 0 ? twist : -twist, o);
+                for (int k = 0; k < 12; k++) o[k] = acc[r][k];
+            } else {
+                cx<R> pc[12];
+                load_spinor<Si, R>(field_rhs<Si>(in0, geo.Vs, r), geo.Vs, s, pc);
+                diag_combine(pc, acc[r], kappa, OP == 0 ? twist : -twist, o);
+            }
+            store_spinor<So, R>(field_rhs<So>(out, geo.Vs, r0 + r), geo.Vs, s, o);
         }
-        store_spinor<So, R>(field_rhs<So>(out, geo.Vs, r0 + r), geo.Vs, s, o);
     }
 }
 
@@ -447,12 +451,11 @@ __global__ __launch_bounds__(256) void k_cg_p(CgArgs a) {
     store_spinor<S, R>(pp, a.geo.Vs, s, pv);
 }
 
-// Initialisation: r holds b = M^dag eta.  p = r, x = 0, (rho = eta),
-// |b|^2 and |eta|^2, first stop test.
+// Initialisation: r holds b = M^dag eta.  p = r, x = 0, (rho = eta), block
+// partials of |b|^2 and |eta|^2 (k_cg_init_fin finishes).
 template <typename R, class S, class X, typename RX, bool TRACK>
 __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const void* eta) {
     __shared__ double sh[4];
-    __shared__ int sflag;
     const uint32_t nb = gridDim.x;
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     const int r = blockIdx.y;
@@ -475,38 +478,42 @@ __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const void* eta) {
     if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
     double w = block_sum256(pe, sh);
     if (threadIdx.x == 0) a.partials2[(size_t)r * nb + blockIdx.x] = w;
-    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
-        double bb = sum_partials(a.partials + (size_t)r * nb, nb, sh);
-        double ee = sum_partials(a.partials2 + (size_t)r * nb, nb, sh);
-        if (threadIdx.x == 0) {
-            CgScal& q = a.scal[r];
-            q.bb = q.rr = q.maxrr = bb;
-            q.ee = q.rho2 = ee;
-            q.iters = 0;
-            q.rflag = 0;
-            q.n_reliable = 0;
-            q.alpha = q.beta = 0;
-            if (bb <= 0 || 1.0 <= q.tol2) {
-                q.status = 1;
-            } else if (q.maxit == 0) {
-                q.status = 2;
-            } else {
-                q.status = 0;
-            }
-            q.active = q.status == 0;
-            a.counters[blockIdx.y] = 0;
-        }
+}
+
+// Per-source state at the start of CG given |b|^2 and |eta|^2.
+__device__ inline void cg_start(CgScal& q, double bb, double ee) {
+    q.bb = q.rr = q.maxrr = bb;
+    q.ee = q.rho2 = ee;
+    q.iters = 0;
+    q.rflag = 0;
+    q.n_reliable = 0;
+    q.alpha = q.beta = 0;
+    if (bb <= 0 || 1.0 <= q.tol2) {
+        q.status = 1;
+    } else if (q.maxit == 0) {
+        q.status = 2;
+    } else {
+        q.status = 0;
     }
+    q.active = q.status == 0;
+}
+
+// one block per right-hand side; with_ee = 0: |eta|^2 of a Z4 source (12 V)
+__global__ __launch_bounds__(256) void k_cg_init_fin(CgArgs a, uint32_t nb, int with_ee) {
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
+    const double bb = sum_block_partials(a.partials + (size_t)r * nb, nb, sh);
+    const double ee = with_ee ? sum_block_partials(a.partials2 + (size_t)r * nb, nb, sh) : (double)a.geo.V * 12.0;
+    if (threadIdx.x == 0) cg_start(a.scal[r], bb, ee);
 }
 
 // ---------------------------------------------------------------------------
 // reliable updates (FP32 iterations, FP64 solution and true residual)
 // ---------------------------------------------------------------------------
 
-// init: r32 = b64, p32 = r32, x32 = 0, x64 = 0, |b64|^2
+// init: r32 = b64, p32 = r32, x32 = 0, x64 = 0, block partials of |b64|^2
 __global__ __launch_bounds__(256) void k_rel_init(CgArgs a, const void* b64, void* x64) {
     __shared__ double sh[4];
-    __shared__ int sflag;
     const uint32_t nb = gridDim.x;
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     const int r = blockIdx.y;
@@ -530,59 +537,52 @@ __global__ __launch_bounds__(256) void k_rel_init(CgArgs a, const void* b64, voi
     }
     double v = block_sum256(pb, sh);
     if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
-    if (take_last_ticket(a.counters + blockIdx.y, nb, &sflag)) {
-        double bb = sum_partials(a.partials + (size_t)r * nb, nb, sh);
-        if (threadIdx.x == 0) {
-            CgScal& q = a.scal[r];
-            q.bb = q.rr = q.maxrr = bb;
-            q.ee = q.rho2 = (double)a.geo.V * 12.0;  // |eta|^2 of a Z4 source
-            q.iters = 0;
-            q.rflag = 0;
-            q.n_reliable = 0;
-            q.alpha = q.beta = 0;
-            q.status = (bb <= 0 || 1.0 <= q.tol2) ? 1 : (q.maxit == 0 ? 2 : 0);
-            q.active = q.status == 0;
-            a.counters[blockIdx.y] = 0;
-        }
-    }
 }
+
+// The kernels below run every iteration but act only on sources whose
+// reliable flag is set, which is rare; they use a small grid that strides
+// over the site blocks, so that an idle launch costs little.
+constexpr uint32_t kGatedBlocks = 512;
 
 // x64 += x32, x32 = 0 (where the reliable flag is set, or always if force)
 __global__ __launch_bounds__(256) void k_rel_flush(CgArgs a, void* x64, int force) {
-    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     const int r = blockIdx.y;
-    if (s >= a.geo.V) return;
     if (!force && !a.scal[r].rflag) return;
     const long Vs = a.geo.Vs;
-    cx<double> xd[12], xs[12];
-    cx<float> z[12];
+    const uint32_t nsb = (uint32_t)((a.geo.V + 255) / 256);
     void* xdp = field_rhs<SF64>(x64, Vs, r);
     void* xsp = field_rhs<SF32>(a.x, Vs, r);
-    load_spinor<SF64, double>(xdp, Vs, s, xd);
-    load_spinor<SF32, double>(xsp, Vs, s, xs);
+    for (uint32_t sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
+        const uint32_t s = sb * 256u + threadIdx.x;
+        if (s >= a.geo.V) continue;
+        cx<double> xd[12], xs[12];
+        cx<float> z[12];
+        load_spinor<SF64, double>(xdp, Vs, s, xd);
+        load_spinor<SF32, double>(xsp, Vs, s, xs);
 #pragma unroll
-    for (int k = 0; k < 12; k++) {
-        xd[k] = xd[k] + xs[k];
-        z[k] = {0.f, 0.f};
+        for (int k = 0; k < 12; k++) {
+            xd[k] = xd[k] + xs[k];
+            z[k] = {0.f, 0.f};
+        }
+        store_spinor<SF64, double>(xdp, Vs, s, xd);
+        store_spinor<SF32, float>(xsp, Vs, s, z);
     }
-    store_spinor<SF64, double>(xdp, Vs, s, xd);
-    store_spinor<SF32, float>(xsp, Vs, s, z);
 }
 
-// r64 = b64 - M^dag t64 (t64 = M x64), r32 = r64, |r64|^2 -> finish the step
+// r64 = b64 - M^dag t64 (t64 = M x64), r32 = r64, block partials of |r64|^2
+// (grid: kGatedBlocks x nrhs, striding over site blocks)
 __global__ TM_STENCIL_R(1, double) void k_rel_resid(CgArgs a, const void* gauge64, const void* b64, const void* t64) {
     __shared__ double sh[4];
-    __shared__ int sflag;
-    const BlockMap bm = stencil_block((uint32_t)a.nrhs);
-    const uint32_t nb = bm.nsb;
-    const uint32_t s = bm.sb * 256u + threadIdx.x;
-    const int r = bm.ch;
-    const long Vs = a.geo.Vs;
+    const int r = blockIdx.y;
     if (!a.scal[r].rflag) return;
+    const long Vs = a.geo.Vs;
+    const uint32_t nsb = (uint32_t)((a.geo.V + 255) / 256);
+    const void* t0 = field_rhs<SF64>(t64, Vs, r);
     double pr = 0;
-    if (s < a.geo.V) {
+    for (uint32_t sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
+        const uint32_t s = sb * 256u + threadIdx.x;
+        if (s >= a.geo.V) continue;
         const Site c = site_coords(a.geo, s);
-        const void* t0 = field_rhs<SF64>(t64, Vs, r);
         cx<double> acc[1][12];
         hop_all<true, double, SF64, GF64, 1>(a.geo, gauge64, t0, s, c, acc);
         cx<double> tc[12], q[12], bv[12];
@@ -596,37 +596,42 @@ __global__ TM_STENCIL_R(1, double) void k_rel_resid(CgArgs a, const void* gauge6
             rf[k] = {(float)bv[k].re, (float)bv[k].im};
         }
         store_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r), Vs, s, rf);
-        pr = spinor_norm2(bv);
+        pr += spinor_norm2(bv);
     }
     double v = block_sum256(pr, sh);
-    if (threadIdx.x == 0) a.partials[(size_t)r * nb + bm.sb] = v;
-    if (take_last_ticket(a.counters + bm.ch, nb, &sflag)) {
-        double rrn = sum_partials(a.partials + (size_t)r * nb, nb, sh);
-        if (threadIdx.x == 0) {
-            CgScal& q = a.scal[r];
-            q.beta = rrn / q.rr;
-            q.rr = rrn;
-            q.maxrr = rrn;
-            q.rflag = 0;
-            q.n_reliable += 1;
-            if (rrn <= q.tol2 * q.bb) {
-                q.status = 1;
-                q.active = 0;
-            } else if (q.maxit >= 0 && q.iters >= q.maxit) {
-                q.status = 2;
-                q.active = 0;
-            }
-            a.counters[bm.ch] = 0;
+    if (threadIdx.x == 0) a.partials[(size_t)r * gridDim.x + blockIdx.x] = v;
+}
+
+// one block per right-hand side with the reliable flag set: restart the
+// recursion from the recomputed residual, stop test on it
+__global__ __launch_bounds__(256) void k_rel_fin(CgArgs a, uint32_t nb) {
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
+    if (!a.scal[r].rflag) return;
+    const double rrn = sum_block_partials(a.partials + (size_t)r * nb, nb, sh);
+    if (threadIdx.x == 0) {
+        CgScal& q = a.scal[r];
+        q.beta = rrn / q.rr;
+        q.rr = rrn;
+        q.maxrr = rrn;
+        q.rflag = 0;
+        q.n_reliable += 1;
+        if (rrn <= q.tol2 * q.bb) {
+            q.status = 1;
+            q.active = 0;
+        } else if (q.maxit >= 0 && q.iters >= q.maxit) {
+            q.status = 2;
+            q.active = 0;
         }
     }
 }
 
-// FP64 true residual |eta - M x| / |eta| with eta regenerated from the hash
+// FP64 true residual |eta - M x| / |eta| with eta regenerated from the hash:
+// block partials of |eta - M x|^2 and |eta|^2 (k_true_resid_fin finishes)
 template <class X, typename RXin>
 __global__ TM_STENCIL_R(1, double) void k_true_resid(CgArgs a, const void* gauge64, uint64_t seed_mixed,
                                                     const uint64_t* ids) {
     __shared__ double sh[4];
-    __shared__ int sflag;
     const BlockMap bm = stencil_block((uint32_t)a.nrhs);
     const uint32_t nb = bm.nsb;
     const uint32_t s = bm.sb * 256u + threadIdx.x;
@@ -654,14 +659,14 @@ __global__ TM_STENCIL_R(1, double) void k_true_resid(CgArgs a, const void* gauge
     if (threadIdx.x == 0) a.partials[(size_t)r * nb + bm.sb] = v;
     double w = block_sum256(pe, sh);
     if (threadIdx.x == 0) a.partials2[(size_t)r * nb + bm.sb] = w;
-    if (take_last_ticket(a.counters + bm.ch, nb, &sflag)) {
-        double rr = sum_partials(a.partials + (size_t)r * nb, nb, sh);
-        double ee = sum_partials(a.partials2 + (size_t)r * nb, nb, sh);
-        if (threadIdx.x == 0) {
-            a.scal[r].resid_true = sqrt(rr / ee);
-            a.counters[bm.ch] = 0;
-        }
-    }
+}
+
+__global__ __launch_bounds__(256) void k_true_resid_fin(CgArgs a, uint32_t nb) {
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
+    const double rr = sum_block_partials(a.partials + (size_t)r * nb, nb, sh);
+    const double ee = sum_block_partials(a.partials2 + (size_t)r * nb, nb, sh);
+    if (threadIdx.x == 0) a.scal[r].resid_true = sqrt(rr / ee);
 }
 
 // per-right-hand-side solver settings
@@ -686,6 +691,9 @@ static inline dim3 stencil_grid(const Geom& g, int nch) {
     return dim3((unsigned)(((g.V + 255) / 256) * nch), 1, 1);
 }
 
+static inline uint32_t site_blocks(const Geom& g) { return (uint32_t)((g.V + 255) / 256); }
+static inline uint32_t gated_blocks(const Geom& g) { return std::min(site_blocks(g), kGatedBlocks); }
+
 static inline dim3 site_grid(const Geom& g, int ychunks) {
     return dim3((unsigned)((g.V + 255) / 256), (unsigned)ychunks, 1);
 }
@@ -693,6 +701,11 @@ static inline dim3 site_grid(const Geom& g, int ychunks) {
 template <int OP, typename R, class Si, class So, class G>
 static void apply_nr(hipStream_t st, const Geom& g, const void* gauge, double kappa, double twist, int nrhs,
                      const void* in, void* out, int nr, const CgScal* gate) {
+    if (gate != nullptr) {
+        hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 1>), dim3(gated_blocks(g) * (unsigned)nrhs), dim3(256), 0, st, g,
+                           gauge, (R)kappa, (R)twist, nrhs, in, out, gate);
+        return;
+    }
     if constexpr (sizeof(R) == 8) {
         hipLaunchKernelGGL((k_apply<OP, R, Si, So, G, 1>), stencil_grid(g, nrhs), dim3(256), 0, st, g, gauge, (R)kappa,
                            (R)twist, nrhs, in, out, gate);
@@ -865,6 +878,7 @@ void launch_cg_init(hipStream_t st, const CgArgs& a, int prec, bool track, const
             hipLaunchKernelGGL((k_cg_init<float, SBF16, SF32, float, false>), grid, dim3(256), 0, st, a, eta);
         break;
     }
+    hipLaunchKernelGGL(k_cg_init_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, site_blocks(a.geo), 1);
 }
 
 void launch_scal_init(hipStream_t st, CgScal* sc, int n, double tol2, int maxit, int stop, int reliable,
@@ -875,12 +889,15 @@ void launch_scal_init(hipStream_t st, CgScal* sc, int n, double tol2, int maxit,
 
 void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64) {
     hipLaunchKernelGGL(k_rel_init, site_grid(a.geo, a.nrhs), dim3(256), 0, st, a, b64, x64);
+    hipLaunchKernelGGL(k_cg_init_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, site_blocks(a.geo), 0);
 }
 void launch_rel_flush(hipStream_t st, const CgArgs& a, void* x64, int force) {
-    hipLaunchKernelGGL(k_rel_flush, site_grid(a.geo, a.nrhs), dim3(256), 0, st, a, x64, force);
+    hipLaunchKernelGGL(k_rel_flush, dim3(gated_blocks(a.geo), (unsigned)a.nrhs), dim3(256), 0, st, a, x64, force);
 }
 void launch_rel_resid(hipStream_t st, const CgArgs& a, const void* gauge64, const void* b64, const void* t64) {
-    hipLaunchKernelGGL(k_rel_resid, stencil_grid(a.geo, a.nrhs), dim3(256), 0, st, a, gauge64, b64, t64);
+    const uint32_t nb = gated_blocks(a.geo);
+    hipLaunchKernelGGL(k_rel_resid, dim3(nb, (unsigned)a.nrhs), dim3(256), 0, st, a, gauge64, b64, t64);
+    hipLaunchKernelGGL(k_rel_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, nb);
 }
 
 void launch_true_resid(hipStream_t st, const CgArgs& a, int xprec, const void* gauge64, uint64_t seed_mixed,
@@ -890,6 +907,7 @@ void launch_true_resid(hipStream_t st, const CgArgs& a, int xprec, const void* g
         hipLaunchKernelGGL((k_true_resid<SF64, double>), grid, dim3(256), 0, st, a, gauge64, seed_mixed, ids);
     else
         hipLaunchKernelGGL((k_true_resid<SF32, float>), grid, dim3(256), 0, st, a, gauge64, seed_mixed, ids);
+    hipLaunchKernelGGL(k_true_resid_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, site_blocks(a.geo));
 }
 
 }  // namespace tmq
