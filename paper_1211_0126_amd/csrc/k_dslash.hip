@@ -31,6 +31,19 @@
 
 namespace tmq {
 
+// Cache policies of the streamed accesses (see ld_plane): K2's centre-site
+// fields, K1's output, K3's inputs.
+#ifndef TM_CP_K2
+#define TM_CP_K2 kStream
+#endif
+#ifndef TM_CP_K1T
+#define TM_CP_K1T kStream
+#endif
+#ifndef TM_CP_K3
+#define TM_CP_K3 kStream
+#endif
+
+
 // ---------------------------------------------------------------------------
 // spin projection for the hop in direction MU with projector 1 - SG g_MU.
 // With g_MU = [[0, B], [B^dag, 0]] (2x2 spin blocks) the projected spinor is
@@ -317,7 +330,7 @@ __global__ TM_STENCIL_R(NR, R) void k_cg_mp(CgArgs a) {
             load_spinor<S, R>(field_rhs<S>(p0, Vs, r), Vs, s, pc);
             diag_combine(pc, acc[r], (R)a.kappa, (R)a.twist, t);
             round_storage<S, R>(t);
-            store_spinor<S, R>(field_rhs<S>(a.t, Vs, r0 + r), Vs, s, t);
+            store_spinor_cp<S, R, TM_CP_K1T>(field_rhs<S>(a.t, Vs, r0 + r), Vs, s, t);
             part[r] = spinor_norm2(t);
         }
     }
@@ -395,29 +408,29 @@ __global__ TM_STENCIL_R(NR, R) void k_cg_upd(CgArgs a) {
             load_spinor<S, R>(field_rhs<S>(t0, Vs, r), Vs, s, tc);
             diag_combine(tc, acc[r], (R)a.kappa, (R)(-a.twist), q);
             void* rp = field_rhs<S>(a.r, Vs, r0 + r);
-            load_spinor<S, R>(rp, Vs, s, rv);
+            load_spinor_cp<S, R, TM_CP_K2>(rp, Vs, s, rv);
             const R al = (R)alpha;
 #pragma unroll
             for (int k = 0; k < 12; k++) rv[k] = rv[k] - al * q[k];
             round_storage<S, R>(rv);
-            store_spinor<S, R>(rp, Vs, s, rv);
+            store_spinor_cp<S, R, TM_CP_K2>(rp, Vs, s, rv);
             prr[r] = spinor_norm2(rv);
-            load_spinor<S, R>(field_rhs<S>(a.p, Vs, r0 + r), Vs, s, pv);
+            load_spinor_cp<S, R, TM_CP_K2>(field_rhs<S>(a.p, Vs, r0 + r), Vs, s, pv);
             cx<RX> xv[12];
             void* xp = field_rhs<X>(a.x, Vs, r0 + r);
-            load_spinor<X, RX>(xp, Vs, s, xv);
+            load_spinor_cp<X, RX, TM_CP_K2>(xp, Vs, s, xv);
             const RX alx = (RX)alpha;
 #pragma unroll
             for (int k = 0; k < 12; k++) xv[k] = {xv[k].re + alx * (RX)pv[k].re, xv[k].im + alx * (RX)pv[k].im};
-            store_spinor<X, RX>(xp, Vs, s, xv);
+            store_spinor_cp<X, RX, TM_CP_K2>(xp, Vs, s, xv);
             if (TRACK) {
                 cx<R> rh[12];
                 void* hp = field_rhs<S>(a.rho, Vs, r0 + r);
-                load_spinor<S, R>(hp, Vs, s, rh);
+                load_spinor_cp<S, R, TM_CP_K2>(hp, Vs, s, rh);
 #pragma unroll
                 for (int k = 0; k < 12; k++) rh[k] = rh[k] - al * tc[k];
                 round_storage<S, R>(rh);
-                store_spinor<S, R>(hp, Vs, s, rh);
+                store_spinor_cp<S, R, TM_CP_K2>(hp, Vs, s, rh);
                 prho[r] = spinor_norm2(rh);
             }
         }
@@ -443,9 +456,9 @@ __global__ __launch_bounds__(256) void k_cg_p(CgArgs a) {
     if (!q.active) return;
     const R beta = (R)q.beta;
     cx<R> rv[12], pv[12];
-    load_spinor<S, R>(field_rhs<S>(a.r, a.geo.Vs, r), a.geo.Vs, s, rv);
+    load_spinor_cp<S, R, TM_CP_K3>(field_rhs<S>(a.r, a.geo.Vs, r), a.geo.Vs, s, rv);
     void* pp = field_rhs<S>(a.p, a.geo.Vs, r);
-    load_spinor<S, R>(pp, a.geo.Vs, s, pv);
+    load_spinor_cp<S, R, TM_CP_K3>(pp, a.geo.Vs, s, pv);
 #pragma unroll
     for (int k = 0; k < 12; k++) pv[k] = rv[k] + beta * pv[k];
     store_spinor<S, R>(pp, a.geo.Vs, s, pv);

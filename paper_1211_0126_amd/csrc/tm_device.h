@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 #include "tm_types.h"
@@ -107,9 +108,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* base) {
     // raw buffer, no stride; dword3 = 0x00020000 is the gfx9-family format word
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
 }
-template <typename T>
+// CP: cache-policy bits of the buffer instruction (0: default, kStream:
+// non-temporal, for fields that are streamed once and would otherwise evict
+// the stencil's neighbour data from L2)
+constexpr int kStream = 2;
+template <typename T, int CP = 0>
 __device__ __forceinline__ T ld_plane(const void* base, long Vs, int k, uint32_t s) {
-    auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc_of(base), s << 4, (uint32_t)((size_t)k * Vs * 16), 0);
+    auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc_of(base), s << 4, (uint32_t)((size_t)k * Vs * 16), CP);
     return __builtin_bit_cast(T, v);
 }
 // A 128-bit store reads its data registers after it issues; the compiler's
@@ -119,11 +124,11 @@ __device__ __forceinline__ T ld_plane(const void* base, long Vs, int k, uint32_t
 // the store, so no instruction can overwrite them earlier.  (Without it,
 // stores issued under memory pressure intermittently wrote the next values
 // of the data registers for some lanes.)
-template <typename T>
+template <typename T, int CP = 0>
 __device__ __forceinline__ void st_plane(void* base, long Vs, int k, uint32_t s, T val) {
     using V4 = unsigned int __attribute__((ext_vector_type(4)));
     const V4 v = __builtin_bit_cast(V4, val);
-    __builtin_amdgcn_raw_buffer_store_b128(v, rsrc_of(base), s << 4, (uint32_t)((size_t)k * Vs * 16), 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rsrc_of(base), s << 4, (uint32_t)((size_t)k * Vs * 16), CP);
     asm volatile("s_nop 4" ::"v"(v) : "memory");
 }
 
@@ -145,11 +150,11 @@ __device__ __forceinline__ void store_spinor<SF64, double>(void* base, long Vs, 
 #pragma unroll
     for (int k = 0; k < 12; k++) st_plane(base, Vs, k, s, make_double2(p[k].re, p[k].im));
 }
-template <typename R>
+template <typename R, int CP = 0>
 __device__ __forceinline__ void load_f32_planes(const void* base, long Vs, uint32_t s, cx<R> p[12]) {
 #pragma unroll
     for (int k = 0; k < 6; k++) {
-        float4 v = ld_plane<float4>(base, Vs, k, s);
+        float4 v = ld_plane<float4, CP>(base, Vs, k, s);
         p[2 * k] = {(R)v.x, (R)v.y};
         p[2 * k + 1] = {(R)v.z, (R)v.w};
     }
@@ -176,11 +181,11 @@ __device__ __forceinline__ void store_spinor<SF32, double>(void* base, long Vs, 
                  make_float4((float)p[2 * k].re, (float)p[2 * k].im, (float)p[2 * k + 1].re, (float)p[2 * k + 1].im));
 }
 
-template <bool BF, typename R>
+template <bool BF, typename R, int CP = 0>
 __device__ __forceinline__ void load_half_planes(const void* base, long Vs, uint32_t s, cx<R> p[12]) {
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        uint4 v = ld_plane<uint4>(base, Vs, k, s);
+        uint4 v = ld_plane<uint4, CP>(base, Vs, k, s);
         uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int j = 0; j < 4; j++) {
@@ -190,7 +195,7 @@ __device__ __forceinline__ void load_half_planes(const void* base, long Vs, uint
         }
     }
 }
-template <bool BF>
+template <bool BF, int CP = 0>
 __device__ __forceinline__ void store_half_planes(void* base, long Vs, uint32_t s, const cx<float> p[12]) {
 #pragma unroll
     for (int k = 0; k < 3; k++) {
@@ -201,7 +206,7 @@ __device__ __forceinline__ void store_half_planes(void* base, long Vs, uint32_t 
             uint32_t hi = BF ? f32_to_bf16(p[4 * k + j].im) : f32_to_f16(p[4 * k + j].im);
             w[j] = lo | (hi << 16);
         }
-        st_plane(base, Vs, k, s, make_uint4(w[0], w[1], w[2], w[3]));
+        st_plane<uint4, CP>(base, Vs, k, s, make_uint4(w[0], w[1], w[2], w[3]));
     }
 }
 template <>
@@ -251,6 +256,38 @@ template <>
 __device__ __forceinline__ void round_storage<SBF16, float>(cx<float>* p) {
 #pragma unroll
     for (int k = 0; k < 12; k++) p[k] = {bf16_to_f32(f32_to_bf16(p[k].re)), bf16_to_f32(f32_to_bf16(p[k].im))};
+}
+
+// Spinor load / store with a cache policy (see ld_plane).
+template <class S, typename R, int CP>
+__device__ __forceinline__ void load_spinor_cp(const void* base, long Vs, uint32_t s, cx<R> p[12]) {
+    if constexpr (std::is_same<S, SF64>::value) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            double2 v = ld_plane<double2, CP>(base, Vs, k, s);
+            p[k] = {(R)v.x, (R)v.y};
+        }
+    } else if constexpr (std::is_same<S, SF32>::value) {
+        load_f32_planes<R, CP>(base, Vs, s, p);
+    } else {
+        load_half_planes<std::is_same<S, SBF16>::value, R, CP>(base, Vs, s, p);
+    }
+}
+template <class S, typename R, int CP>
+__device__ __forceinline__ void store_spinor_cp(void* base, long Vs, uint32_t s, const cx<R> p[12]) {
+    if constexpr (std::is_same<S, SF64>::value) {
+#pragma unroll
+        for (int k = 0; k < 12; k++) st_plane<double2, CP>(base, Vs, k, s, make_double2(p[k].re, p[k].im));
+    } else if constexpr (std::is_same<S, SF32>::value) {
+#pragma unroll
+        for (int k = 0; k < 6; k++)
+            st_plane<float4, CP>(base, Vs, k, s,
+                                 make_float4((float)p[2 * k].re, (float)p[2 * k].im, (float)p[2 * k + 1].re,
+                                             (float)p[2 * k + 1].im));
+    } else {
+        static_assert(sizeof(R) == 4, "half storage is written from FP32");
+        store_half_planes<std::is_same<S, SBF16>::value, CP>(base, Vs, s, p);
+    }
 }
 
 template <class S>
