@@ -36,6 +36,7 @@ HBM_PEAK_GBS = 8000.0
 PREC_NAMES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 KERNEL_OF = {"dslash": "k_cg_mp", "dslash_upd": "k_cg_upd", "blas": "k_cg_p", "contract": "k_contract",
              "other": "init/residual", "apply": "k_apply"}
+MARCH_OF = {"k_cg_mp": "k_tm_mp", "k_cg_upd": "k_tm_upd"}
 
 
 def parse():
@@ -95,7 +96,9 @@ def recorded_traffic(kernel, workload):
 
 def kname(v):
     k = KERNEL_OF[v["kc"]]
-    return k.replace("k_cg_", "k_fcg_") if v.get("solver") == 1 else k
+    if v.get("solver") == 1:
+        return k.replace("k_cg_", "k_fcg_")
+    return MARCH_OF.get(k, k) if v.get("tseg", 0) > 0 else k
 
 
 def log(msg):
@@ -171,9 +174,10 @@ def main():
     lp_prec = PREC_NAMES[args.lp_prec]
     tune = {}
     for prec, blk in ((lp_prec, args.lp_block), (tq.PREC_F32, args.hp_block)):
-        best, ms = tq.tm_autotune(ctx, prec, blk)
-        tune[[k for k, v in PREC_NAMES.items() if v == prec][0]] = {"lane_rhs": best, "ms_per_apply": ms.tolist(),
-                                                                     "rhs": blk}
+        nr, ts, ms = tq.tm_autotune_cg(ctx, prec, blk)
+        tune[[k for k, v in PREC_NAMES.items() if v == prec][0]] = {
+            "rhs_block": blk, "lane_rhs": nr, "tseg": ts,
+            "ms_per_cg_iteration": {"%d,%d" % c: round(m, 4) for c, m in ms.items()}}
     log("autotune: %s" % tune)
     # The LP true residual is a diagnostic outside the method (the estimator
     # uses the truncated solutions as they are); it is measured on the same
@@ -214,7 +218,7 @@ def main():
     avg_bytes = d["bytes"] / max(d["launches"], 1)
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     prec_name = {v: k for k, v in PREC_NAMES.items()}
-    dom_name = "%s %s NR=%d" % (kname(d), prec_name[d["prec"]], d["lane_rhs"])
+    dom_name = "%s %s NR=%d tseg=%d" % (kname(d), prec_name[d["prec"]], d["lane_rhs"], d["tseg"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dom_name, wl.name),
                 "kernel": dom_name,
@@ -260,7 +264,7 @@ def main():
         "lp_true_resid_max": float(np.max(lp_true)) if lp_true else None,
         "hp_true_resid_max": run["max_hp_resid_true"],
         "kernels": per_class,
-        "kernel_variants": [{"kernel": kname(v), "prec": v["prec"], "lane_rhs": v["lane_rhs"],
+        "kernel_variants": [{"kernel": kname(v), "prec": v["prec"], "lane_rhs": v["lane_rhs"], "tseg": v["tseg"],
                              "launches": v["launches"], "avg_us": round(1e3 * v["ms"] / max(v["launches"], 1), 2),
                              "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1) if v["bytes"] > 0 else None}
                             for v in variants if v["prec"] >= 0],

@@ -324,9 +324,32 @@ tm_status tm_precond_train(tm_ctx* ctx, const tm_train_params* params, tm_train_
    Needs a loaded gauge field.  Synchronous. */
 tm_status tm_autotune(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_nr, double* ms_host);
 
+/* Autotuner for the CG kernels of storage precision prec on blocks of nrhs
+   sources (1..32): times truncated CG iterations (operator, reductions and
+   updates) on synthetic sources for each candidate traversal, keeps the
+   fastest for later solves in that precision (as tm_set_lane_rhs and
+   tm_set_march would) and reports it.  Candidates, in this order, as
+   (right-hand sides per lane, time slices per lane): (1,0) (2,0) (4,0)
+   (1,4) (1,8) (1,16) (2,4) (2,8); those whose lane width does not divide
+   nrhs are skipped (and FP64 runs lane width 1 only).  ms_host (nullable)
+   receives 8 per-iteration milliseconds, negative where skipped.  Needs a
+   loaded gauge field; synchronous; uses the context's workspace. */
+tm_status tm_autotune_cg(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_nr, int32_t* best_tseg,
+                         double* ms_host);
+
 /* Set (nr = 1, 2 or 4) or reset to the built-in choice (nr = 0) the
    right-hand sides per lane used by solves in storage precision prec. */
 tm_status tm_set_lane_rhs(tm_ctx* ctx, int32_t prec, int32_t nr);
+
+/* Stencil traversal of the CG kernels in storage precision prec: tseg = 0
+   gives one lane per lattice site; tseg > 0 makes each lane walk tseg time
+   slices of one spatial site (time-direction hops carried between slices,
+   so the time neighbours are loaded once), used with 1 or 2 right-hand
+   sides per lane.  Values above the time extent act as the time extent.
+   Results agree with the one-lane-per-site kernels up to rounding (the
+   terms of a site are summed in another order).  TM_EINVAL for prec
+   outside 0..3 or tseg outside 0..65535. */
+tm_status tm_set_march(tm_ctx* ctx, int32_t prec, int32_t tseg);
 
 /* CG iteration chunks are captured once into HIP graphs and replayed (on a
    non-null stream, while per-launch profiling is off).  on = 1 enables (the
@@ -369,6 +392,9 @@ typedef struct {
     int32_t prec;     /* tm_prec of the stored fields, or -1 */
     int32_t lane_rhs; /* right-hand sides per lane, or -1 */
     int32_t solver;   /* tm_solver, or -1 */
+    int32_t tseg;     /* time slices per lane of a time-marching kernel, 0 if
+                         one lane per site, -1 if not a CG stencil */
+    int32_t reserved;
     int64_t launches;
     double ms;
     double bytes;

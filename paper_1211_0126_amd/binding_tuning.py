@@ -23,8 +23,8 @@ def tm_set_graphs(ctx: Context, on=None):
 
 class ProfileEntry(ctypes.Structure):
     _fields_ = [("kc", ctypes.c_int32), ("prec", ctypes.c_int32), ("lane_rhs", ctypes.c_int32),
-                ("solver", ctypes.c_int32), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
-                ("bytes", ctypes.c_double)]
+                ("solver", ctypes.c_int32), ("tseg", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 EXPORTS += ["tm_profile_entries"]
@@ -40,5 +40,34 @@ def tm_profile_entries(ctx: Context, cap=256):
     buf = (ProfileEntry * cap)()
     n = ctypes.c_int32()
     ctx.check(ctx.lib.tm_profile_entries(ctx.h, buf, int(cap), ctypes.byref(n)))
-    return [{"kc": KC_NAMES[e.kc], "prec": e.prec, "lane_rhs": e.lane_rhs, "solver": e.solver,
+    return [{"kc": KC_NAMES[e.kc], "prec": e.prec, "lane_rhs": e.lane_rhs, "solver": e.solver, "tseg": e.tseg,
              "launches": int(e.launches), "ms": float(e.ms), "bytes": float(e.bytes)} for e in buf[:n.value]]
+
+
+EXPORTS += ["tm_set_march"]
+
+
+def tm_set_march(ctx: Context, prec, tseg):
+    """Time slices per lane of the CG stencils in storage precision prec
+    (0: one lane per site)."""
+    ctx.lib.tm_set_march.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+    ctx.lib.tm_set_march.restype = ctypes.c_int32
+    ctx.check(ctx.lib.tm_set_march(ctx.h, int(prec), int(tseg)))
+
+
+EXPORTS += ["tm_autotune_cg"]
+TUNE_CANDIDATES = [(1, 0), (2, 0), (4, 0), (1, 4), (1, 8), (1, 16), (2, 4), (2, 8)]
+
+
+def tm_autotune_cg(ctx: Context, prec, nrhs):
+    """Returns (right-hand sides per lane, time slices per lane, {candidate:
+    ms per CG iteration}) and keeps the choice for later solves."""
+    import numpy as np
+    ctx.lib.tm_autotune_cg.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]
+    ctx.lib.tm_autotune_cg.restype = ctypes.c_int32
+    nr, ts = ctypes.c_int32(), ctypes.c_int32()
+    ms = np.zeros(len(TUNE_CANDIDATES), dtype=np.float64)
+    ctx.check(ctx.lib.tm_autotune_cg(ctx.h, int(prec), int(nrhs), ctypes.byref(nr), ctypes.byref(ts),
+                                     ms.ctypes.data_as(ctypes.c_void_p)))
+    return int(nr.value), int(ts.value), {c: float(m) for c, m in zip(TUNE_CANDIDATES, ms) if m >= 0}

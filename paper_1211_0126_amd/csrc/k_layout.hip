@@ -120,9 +120,10 @@ __global__ __launch_bounds__(256) void k_gauge_convert(Geom geo, const double2* 
     const size_t Vs = geo.Vs;
 #pragma unroll
     for (int k = 0; k < 9; k++) g64[((size_t)mu * 9 + k) * Vs + s] = u[k];
-    g32[((size_t)mu * 3 + 0) * Vs + s] = make_float4((float)u[0].x, (float)u[0].y, (float)u[1].x, (float)u[1].y);
-    g32[((size_t)mu * 3 + 1) * Vs + s] = make_float4((float)u[2].x, (float)u[2].y, (float)u[3].x, (float)u[3].y);
-    g32[((size_t)mu * 3 + 2) * Vs + s] = make_float4((float)u[4].x, (float)u[4].y, (float)u[5].x, (float)u[5].y);
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+        g32[((size_t)mu * 3 + k) * Vs + s] =
+            make_float4((float)u[2 * k].x, (float)u[2 * k].y, (float)u[2 * k + 1].x, (float)u[2 * k + 1].y);
 }
 
 void launch_gauge_convert(hipStream_t st, const Geom& g, const double* canon, void* g64, void* g32) {

@@ -324,6 +324,13 @@ tm_status tm_set_graphs(tm_ctx* ctx, int32_t on, int64_t* replays) {
     return TM_OK;
 }
 
+tm_status tm_set_march(tm_ctx* ctx, int32_t prec, int32_t tseg) {
+    if (!ctx || prec < 0 || prec > 3 || tseg < 0 || tseg > 65535)
+        return ctx ? set_error(ctx, TM_EINVAL, "tm_set_march: bad argument") : TM_EINVAL;
+    ctx->march[prec] = tseg;
+    return TM_OK;
+}
+
 tm_status tm_set_lane_rhs(tm_ctx* ctx, int32_t prec, int32_t nr) {
     if (!ctx || prec < 0 || prec > 3 || !(nr == 0 || nr == 1 || nr == 2 || nr == 4))
         return set_error(ctx, TM_EINVAL, "tm_set_lane_rhs: bad argument");
@@ -433,8 +440,10 @@ tm_status tm_profile_entries(tm_ctx* ctx, tm_profile_entry* out, int32_t cap, in
         tm_profile_entry& e = out[k++];
         e.kc = kv.first.first;
         e.prec = tag < 0 ? -1 : (tag & 15);
-        e.lane_rhs = tag < 0 ? -1 : ((tag >> 4) & 255);
-        e.solver = tag < 0 ? -1 : (tag >> 12);
+        e.lane_rhs = tag < 0 ? -1 : ((tag >> 4) & 15);
+        e.solver = tag < 0 ? -1 : ((tag >> 8) & 15);
+        e.tseg = tag < 0 ? -1 : (tag >> 12);
+        e.reserved = 0;
         e.launches = kv.second.launches;
         e.ms = kv.second.ms;
         e.bytes = kv.second.bytes;

@@ -40,6 +40,9 @@ struct tm_ctx {
     // right-hand sides per lane chosen by tm_autotune / tm_set_lane_rhs, per
     // storage precision (0: built-in default)
     int lane_rhs[4] = {0, 0, 0, 0};
+    // time slices per lane of the time-marching CG stencils, per storage
+    // precision (0: one lane per site)
+    int march[4] = {0, 0, 0, 0};
 
     // captured CG chunks (replayed with hipGraphLaunch), keyed by buffers and
     // launch configuration; used on a non-null stream when profiling is off
@@ -82,7 +85,9 @@ uint64_t seed_mix(uint64_t seed);
 // instrumentation around a launch of kernel class kc moving `bytes`
 // tag: prof_tag(prec, lane_rhs, solver) of the launched kernel, -1 if none
 void prof_begin(tm_ctx* ctx, int kc, int tag = -1);
-inline int prof_tag(int prec, int lane_rhs, int solver) { return prec | (lane_rhs << 4) | (solver << 12); }
+inline int prof_tag(int prec, int lane_rhs, int solver, int tseg = 0) {
+    return prec | (lane_rhs << 4) | (solver << 8) | (tseg << 12);
+}
 void prof_end(tm_ctx* ctx, int kc, double bytes);
 
 }  // namespace tmq

@@ -23,6 +23,8 @@ struct CgArgs {
     double* partials2;  // [nrhs][nblocks]
     unsigned int* counters;  // [nrhs], zero between launches
     int nrhs;
+    uint32_t npart;     // block partials per right-hand side written by K1 / K2
+    int tseg;           // time slices per lane of the time-marching K1 / K2
 };
 
 struct ContractArgs {
@@ -96,6 +98,11 @@ void launch_scal_init(hipStream_t st, CgScal* sc, int n, double tol2, int maxit,
 void launch_cg_init(hipStream_t st, const CgArgs& a, int prec, bool track, const void* eta);
 void launch_cg_mp(hipStream_t st, const CgArgs& a, int prec, int nr);
 void launch_cg_upd(hipStream_t st, const CgArgs& a, int prec, int nr, bool track);
+// time-marching K1 / K2 (a.tseg time slices per lane); they write
+// march_partials(geo, tseg) partials per right-hand side
+uint32_t march_partials(const Geom& g, int tseg);
+void launch_tm_mp(hipStream_t st, const CgArgs& a, int prec, int nr);
+void launch_tm_upd(hipStream_t st, const CgArgs& a, int prec, int nr, bool track);
 void launch_cg_alpha(hipStream_t st, const CgArgs& a);              // after launch_cg_mp
 void launch_cg_beta(hipStream_t st, const CgArgs& a, bool track);   // after launch_cg_upd
 void launch_cg_p(hipStream_t st, const CgArgs& a, int prec);

@@ -65,6 +65,18 @@ static int lane_rhs(const tm_ctx* ctx, const tsm_solve_params* p, int block) {
     return 1;
 }
 
+// time slices per lane of the time-marching K1 / K2 (0: lane per site)
+// autotuner candidates (right-hand sides per lane, time slices per lane)
+constexpr int kTuneCandidates = 8;
+constexpr int kTuneNr[kTuneCandidates] = {1, 2, 4, 1, 1, 1, 2, 2};
+constexpr int kTuneTseg[kTuneCandidates] = {0, 0, 0, 4, 8, 16, 4, 8};
+
+static int march_tseg(const tm_ctx* ctx, const tsm_solve_params* p, int nr) {
+    const int t = ctx->march[p->prec];
+    if (t <= 0 || nr > 2) return 0;
+    return std::min(t, ctx->geo.L[3]);
+}
+
 static tm_status ensure_scal_host(tm_ctx* ctx, int n) {
     if (ctx->scal_host_n >= n) return TM_OK;
     if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
@@ -214,6 +226,7 @@ tm_status solve_f64_history(tm_ctx* ctx, uint64_t seed_mixed, const uint64_t* id
     a.kappa = ctx->lat.kappa;
     a.twist = ctx->twist;
     a.nrhs = 1;
+    a.npart = (uint32_t)nblk;
     a.p = ws_get(ctx, "h_p", fb, &s);
     a.t = ws_get(ctx, "h_t", fb, &s);
     a.r = ws_get(ctx, "h_r", fb, &s);
@@ -287,13 +300,17 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
     a.kappa = ctx->lat.kappa;
     a.twist = ctx->twist;
     a.nrhs = nrhs;
+    // time-marching K1 / K2 when a segment length is set for this precision
+    a.tseg = march_tseg(ctx, p, nr);
+    a.npart = a.tseg > 0 ? march_partials(g, a.tseg) : (uint32_t)nblk;
+    const size_t npart_max = std::max<size_t>(nblk, a.npart);
     a.p = ws_get(ctx, tag + "_p", fb, &s);
     a.t = ws_get(ctx, tag + "_t", fb, &s);
     a.r = ws_get(ctx, tag + "_r", fb, &s);
     a.x = ws_get(ctx, tag + "_x", fx, &s);
     a.scal = (CgScal*)ws_get(ctx, tag + "_scal", sizeof(CgScal) * kMaxBlock, &s);
-    a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * nblk * kMaxBlock, &s);
-    a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * nblk * kMaxBlock, &s);
+    a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * npart_max * kMaxBlock, &s);
+    a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * npart_max * kMaxBlock, &s);
     a.counters = (unsigned int*)ws_get(ctx, "counters", sizeof(unsigned int) * kMaxBlock, &s);
     if (track) a.rho = ws_get(ctx, tag + "_rho", fb, &s);
     void* eta = nullptr;
@@ -331,7 +348,7 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
     TM_HIP(hipGetLastError());
 
     const int chunk = rel ? 16 : 8;
-    const int vtag = prof_tag(prec, prec == P_F64 ? 1 : nr, TM_SOLVER_CG);
+    const int vtag = prof_tag(prec, prec == P_F64 ? 1 : nr, TM_SOLVER_CG, a.tseg);
     int done = 0;
     for (;;) {
         int k = chunk;
@@ -339,13 +356,19 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
         auto steps = [&](int n) {
             for (int i = 0; i < n; i++) {
                 prof_begin(ctx, TM_KC_DSLASH, vtag);
-                launch_cg_mp(st, a, prec, nr);
+                if (a.tseg > 0)
+                    launch_tm_mp(st, a, prec, nr);
+                else
+                    launch_cg_mp(st, a, prec, nr);
                 prof_end(ctx, TM_KC_DSLASH, by.k1);
                 prof_begin(ctx, TM_KC_OTHER);
                 launch_cg_alpha(st, a);
                 prof_end(ctx, TM_KC_OTHER, 0.0);
-                prof_begin(ctx, TM_KC_DSLASH_UPD, track ? prof_tag(prec, 1, TM_SOLVER_CG) : vtag);
-                launch_cg_upd(st, a, prec, nr, track);
+                prof_begin(ctx, TM_KC_DSLASH_UPD, track ? prof_tag(prec, 1, TM_SOLVER_CG, a.tseg) : vtag);
+                if (a.tseg > 0)
+                    launch_tm_upd(st, a, prec, nr, track);
+                else
+                    launch_cg_upd(st, a, prec, nr, track);
                 prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
                 prof_begin(ctx, TM_KC_OTHER);
                 launch_cg_beta(st, a, track);
@@ -367,9 +390,9 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
             // the chunk's launches depend only on the buffers and the launch
             // configuration, so one captured graph serves every chunk
             char key[512];
-            std::snprintf(key, sizeof(key), "cg|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%d", a.p, a.t, a.r,
+            std::snprintf(key, sizeof(key), "cg|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%d|%d", a.p, a.t, a.r,
                           a.x, a.rho, (void*)a.scal, (void*)a.partials, (void*)a.partials2, x64, t64, b64, prec, nr,
-                          (int)track, (int)rel, nrhs, k);
+                          a.tseg, (int)track, (int)rel, nrhs, k);
             auto it = ctx->graphs.find(key);
             if (it == ctx->graphs.end()) {
                 hipGraph_t graph;
@@ -705,6 +728,72 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double
     rs.ms_lp_phase = std::chrono::duration<double, std::milli>(t2 - t1).count();
     if (run_stats) *run_stats = rs;
     return warn ? TM_WARN_NOT_CONVERGED : TM_OK;
+}
+
+tm_status tm_autotune_cg(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_nr, int32_t* best_tseg,
+                         double* ms_host) {
+    if (!ctx || prec < 0 || prec > 3 || nrhs < 1 || nrhs > kMaxBlock || !best_nr || !best_tseg)
+        return ctx ? set_error(ctx, TM_EINVAL, "tm_autotune_cg: bad argument") : TM_EINVAL;
+    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tm_autotune_cg: no gauge field loaded");
+    tm_status s = TM_OK;
+    uint64_t* ids = (uint64_t*)ws_get(ctx, "tune_ids", sizeof(uint64_t) * nrhs, &s);
+    if (!ids) return s;
+    std::vector<uint64_t> idh(nrhs);
+    for (int i = 0; i < nrhs; i++) idh[i] = (uint64_t)i;
+    TM_HIP(hipMemcpy(ids, idh.data(), sizeof(uint64_t) * nrhs, hipMemcpyHostToDevice));
+    const int keep_nr = ctx->lane_rhs[prec], keep_ts = ctx->march[prec];
+    tsm_solve_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.prec = prec;
+    p.solver = TM_SOLVER_CG;
+    p.tol = 0.0;  // never converges: runs max_iter steps
+    p.stop = TM_STOP_NORMAL;
+    p.rhs_block = nrhs;
+    p.true_resid = 0;
+    double best = 1e300;
+    int bnr = 1, bts = 0;
+    for (int c = 0; c < kTuneCandidates; c++) {
+        const int nr = kTuneNr[c], ts = kTuneTseg[c];
+        if (ms_host) ms_host[c] = -1.0;
+        if (nrhs % nr != 0 || (prec == TM_PREC_F64 && nr != 1)) continue;
+        ctx->lane_rhs[prec] = nr;
+        ctx->march[prec] = ts;
+        // per-iteration time: difference of a long and a short truncated
+        // solve (initialisation cancels), best of two
+        double per = 1e300;
+        for (int rep = 0; rep < 3; rep++) {
+            double t[2];
+            for (int j = 0; j < 2; j++) {
+                p.max_iter = j == 0 ? 2 : 10;
+                BlockResult res;
+                const auto t0 = std::chrono::steady_clock::now();
+                s = solve_block(ctx, &p, seed_mix(12345), ids, nrhs, nr, "tune", &res);
+                const auto t1 = std::chrono::steady_clock::now();
+                if (s != TM_OK) break;
+                t[j] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            }
+            if (s != TM_OK) break;
+            if (rep > 0) per = std::min(per, (t[1] - t[0]) / 8.0);  // the first pass warms up
+        }
+        if (s != TM_OK) break;
+        if (ms_host) ms_host[c] = per;
+        if (per < best) {
+            best = per;
+            bnr = nr;
+            bts = ts;
+        }
+    }
+    if (s != TM_OK) {
+        ctx->lane_rhs[prec] = keep_nr;
+        ctx->march[prec] = keep_ts;
+        return s;
+    }
+    ctx->lane_rhs[prec] = bnr;
+    ctx->march[prec] = bts;
+    *best_nr = bnr;
+    *best_tseg = bts;
+    return TM_OK;
 }
 
 }  // extern "C"

@@ -58,4 +58,7 @@ def test_half_storage_lp_solves_match_fp32_iterations(ctx, prec, blk):
         _, st, _ = tq.tsm_solve_batch(ctx, p, 2001, ids, want_solutions=False)
         for a, b in zip(st, st32):
             assert a["converged"] and abs(a["iters"] - b["iters"]) <= 1, (a, b)
-            assert a["resid_true"] < 1.1 * b["resid_true"] + 1e-3, (a, b)
+            # one iteration fewer (the iterated residual crossing the stop
+            # just earlier) leaves the true residual of that step
+            f = 1.1 if a["iters"] == b["iters"] else 1.4
+            assert a["resid_true"] < f * b["resid_true"] + 1e-3, (a, b)
