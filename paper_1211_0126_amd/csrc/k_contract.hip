@@ -40,6 +40,16 @@ __device__ __forceinline__ void load_half_spinor<SF32>(const void* base, long Vs
     }
 }
 
+// conj(i^k) p for a Z4 noise component i^k: a permutation and signs
+__device__ __forceinline__ cx<double> z4_conj_times(uint32_t k, cx<double> p) {
+    const double re = (k & 1u) ? p.im : p.re;
+    const double im = (k & 1u) ? p.re : p.im;
+    // k = 0: (re, im); 1: (im, -re); 2: (-re, -im); 3: (-im, re)
+    const double sr = (k == 2u || k == 3u) ? -1.0 : 1.0;
+    const double si = (k == 1u || k == 2u) ? -1.0 : 1.0;
+    return {sr * re, si * im};
+}
+
 template <class S>
 __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
     const Geom& g = a.geo;
@@ -74,25 +84,31 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
             for (int al = 0; al < 4; al++) {
                 cx<double> v = {0.0, 0.0};
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    cx<double> e = z4_value<double>((uint32_t)(bits >> (2 * (3 * al + c))) & 3u);
-                    v = v + cmulc(e, p[3 * b + c]);
-                }
+                for (int c = 0; c < 3; c++)
+                    v = v + z4_conj_times((uint32_t)(bits >> (2 * (3 * al + c))) & 3u, p[3 * b + c]);
                 S8[4 * b + al] = v;
             }
+        // fully unrolled with predicates: a runtime bound on i would index
+        // acc dynamically and move it to scratch memory
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-            if (i >= npy) break;
-            const double2 ph = a.phy[i * Ly + y];
-            const cx<double> w = {ph.x, ph.y};
+            if (i < npy) {
+                const double2 ph = a.phy[i * Ly + y];
+                const cx<double> w = {ph.x, ph.y};
 #pragma unroll
-            for (int e = 0; e < 8; e++) acc[i][e] = acc[i][e] + w * S8[e];
+                for (int e = 0; e < 8; e++) acc[i][e] = acc[i][e] + w * S8[e];
+            }
         }
     }
-    for (int i = 0; i < npy; i++) {
-        double2* o = a.A + (((((size_t)r * Lt + t) * Lz + z) * npy + i) * Lx + x) * 16 + 8 * h;
+    // A[r][t][z][iy][entry][x]: lanes of consecutive x write consecutive
+    // elements
 #pragma unroll
-        for (int e = 0; e < 8; e++) o[e] = make_double2(acc[i][e].re, acc[i][e].im);
+    for (int i = 0; i < 3; i++) {
+        if (i < npy) {
+            double2* o = a.A + ((((((size_t)r * Lt + t) * Lz + z) * npy + i) * 16 + 8 * h) * Lx + x);
+#pragma unroll
+            for (int e = 0; e < 8; e++) o[(size_t)e * Lx] = make_double2(acc[i][e].re, acc[i][e].im);
+        }
     }
 }
 
@@ -113,19 +129,23 @@ __global__ __launch_bounds__(256) void k_contract_b(ContractArgs a) {
     cx<double> acc[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) acc[i] = {0.0, 0.0};
-    const double2* in = a.A + ((((size_t)r * Lt + t) * Lz + z) * npy + iy) * Lx * 16 + e;
+    const double2* in = a.A + (((((size_t)r * Lt + t) * Lz + z) * npy + iy) * 16 + e) * Lx;
     for (int x = 0; x < Lx; x++) {
-        const double2 v = in[(size_t)x * 16];
+        const double2 v = in[x];
         const cx<double> vv = {v.x, v.y};
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-            if (i >= npx) break;
-            const double2 ph = a.phx[i * Lx + x];
-            acc[i] = acc[i] + cx<double>{ph.x, ph.y} * vv;
+            if (i < npx) {
+                const double2 ph = a.phx[i * Lx + x];
+                acc[i] = acc[i] + cx<double>{ph.x, ph.y} * vv;
+            }
         }
     }
-    for (int i = 0; i < npx; i++)
-        a.B[(((((size_t)r * Lt + t) * Lz + z) * npx + i) * npy + iy) * 16 + e] = make_double2(acc[i].re, acc[i].im);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+        if (i < npx)
+            a.B[(((((size_t)r * Lt + t) * Lz + z) * npx + i) * npy + iy) * 16 + e] =
+                make_double2(acc[i].re, acc[i].im);
 }
 
 __global__ __launch_bounds__(256) void k_contract_c(ContractArgs a) {
