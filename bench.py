@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--lp-true-resid", action="store_true",
                     help="also compute the FP64 true residual of every LP solve inside the timed step")
+    ap.add_argument("--lp-config", default=None, metavar="NR,TSEG",
+                    help="fix the LP kernels' right-hand sides per lane and time slices per lane (default: autotune)")
+    ap.add_argument("--hp-config", default=None, metavar="NR,TSEG", help="same for the HP kernels")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory once (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -173,11 +176,17 @@ def main():
     mom = wl.momenta()
     lp_prec = PREC_NAMES[args.lp_prec]
     tune = {}
-    for prec, blk in ((lp_prec, args.lp_block), (tq.PREC_F32, args.hp_block)):
+    for prec, blk, fixed in ((lp_prec, args.lp_block, args.lp_config), (tq.PREC_F32, args.hp_block, args.hp_config)):
+        name = [k for k, v in PREC_NAMES.items() if v == prec][0]
+        if fixed:
+            nr, ts = (int(v) for v in fixed.split(","))
+            tq.tm_set_lane_rhs(ctx, prec, nr)
+            tq.tm_set_march(ctx, prec, ts)
+            tune[name] = {"rhs_block": blk, "lane_rhs": nr, "tseg": ts, "fixed": True}
+            continue
         nr, ts, ms = tq.tm_autotune_cg(ctx, prec, blk)
-        tune[[k for k, v in PREC_NAMES.items() if v == prec][0]] = {
-            "rhs_block": blk, "lane_rhs": nr, "tseg": ts,
-            "ms_per_cg_iteration": {"%d,%d" % c: round(m, 4) for c, m in ms.items()}}
+        tune[name] = {"rhs_block": blk, "lane_rhs": nr, "tseg": ts,
+                      "ms_per_cg_iteration": {"%d,%d" % c: round(m, 4) for c, m in ms.items()}}
     log("autotune: %s" % tune)
     # The LP true residual is a diagnostic outside the method (the estimator
     # uses the truncated solutions as they are); it is measured on the same
