@@ -293,8 +293,15 @@ typedef struct {
     double lr;            /* Adam step size */
     double hp_tol;        /* tolerance of the training solves */
     double min_rel_err;   /* harvest only iterates with |e_k| / |x*| above this */
-    uint64_t init_seed;   /* seed of the initial weights (identity on channel 0 plus noise) */
+    uint64_t init_seed;   /* seed of the noise added to the initial weights */
     double init_scale;    /* size of that noise */
+    int32_t init_mode;    /* initial network: 0 identity on channel 0; 1 the third-order
+                             Neumann series of M^{-1} = sum_k A^k with A = 1 - M, built as
+                             psi + A (psi + A (psi + A psi)) with channel 0 carrying psi
+                             (needs the default 1 -> 2 -> 2 -> 1 shape) */
+    int32_t loss_mode;    /* 0: |N(r) - e|^2 / |e|^2 (the loss of tm_precond_loss_grad);
+                             1: |M N(r) - r|^2 / |r|^2, the residual of the preconditioned
+                             operator, which weights all modes alike */
 } tm_train_params;
 
 typedef struct {
@@ -308,10 +315,11 @@ typedef struct {
 
 /* Harvest (r_k = eta - M x_k, e_k = x* - x_k) pairs from CG solves of
    training sources, store them in bfloat16, and train the installed network
-   (or the default 1 -> 2 -> 2 -> 1 shape if none is installed) with Adam on
-   the loss of tm_precond_loss_grad, using the library's forward, adjoint and
-   weight-gradient kernels.  The trained weights stay installed.
-   Synchronous. */
+   (or a new 1 -> 2 -> 2 -> 1 network initialised as init_mode says if none
+   is installed) with Adam on the loss of tm_precond_loss_grad, using the
+   library's forward, adjoint and weight-gradient kernels.  The trained
+   weights stay installed.  n_pairs = epochs = 0 only installs the initial
+   network.  Synchronous. */
 tm_status tm_precond_train(tm_ctx* ctx, const tm_train_params* params, tm_train_stats* stats);
 
 /* ---- tuning ------------------------------------------------------------- */

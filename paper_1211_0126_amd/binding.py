@@ -293,7 +293,7 @@ class TrainParams(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("n_sources", ctypes.c_int32), ("n_pairs", ctypes.c_int32),
                 ("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
                 ("hp_tol", ctypes.c_double), ("min_rel_err", ctypes.c_double), ("init_seed", ctypes.c_uint64),
-                ("init_scale", ctypes.c_double)]
+                ("init_scale", ctypes.c_double), ("init_mode", ctypes.c_int32), ("loss_mode", ctypes.c_int32)]
 
 
 class TrainStats(ctypes.Structure):
@@ -372,10 +372,13 @@ def tm_precond_loss_grad(ctx: Context, r, e):
 
 
 def tm_precond_train(ctx: Context, seed, n_sources, n_pairs, epochs, batch, lr=1e-3, hp_tol=1e-10,
-                     min_rel_err=1e-4, init_seed=1, init_scale=1e-2):
+                     min_rel_err=1e-4, init_seed=1, init_scale=1e-2, init_mode=1, loss_mode=1):
+    """init_mode 0: identity start; 1: third-order Neumann series of M^{-1}.
+    loss_mode 0: error loss; 1: residual loss.  n_pairs = epochs = 0
+    installs the initial network only."""
     _learn_sigs(ctx.lib)
     p = TrainParams(int(seed), int(n_sources), int(n_pairs), int(epochs), int(batch), float(lr), float(hp_tol),
-                    float(min_rel_err), int(init_seed), float(init_scale))
+                    float(min_rel_err), int(init_seed), float(init_scale), int(init_mode), int(loss_mode))
     st = TrainStats()
     ctx.check(ctx.lib.tm_precond_train(ctx.h, ctypes.byref(p), ctypes.byref(st)))
     return {f: getattr(st, f) for f, _ in TrainStats._fields_}

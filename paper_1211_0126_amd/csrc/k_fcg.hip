@@ -10,103 +10,20 @@
 // A source falls back to plain CG (directions restarted from its current
 // iterate) when Re<z,r> <= 0, a scalar is not finite, or it stagnates.
 
-#include "tm_device.h"
 #include "tm_kernels.h"
+#include "tm_stencil.h"
 
 namespace tmq {
 
-// reuse the stencil helpers of k_dslash.hip through a small local copy of the
-// single-right-hand-side FP32 operator
-template <int MU, int SG>
-__device__ __forceinline__ void fproj(const cx<float> p[12], cx<float> h[6]) {
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        cx<float> u0 = p[c], u1 = p[3 + c], d0 = p[6 + c], d1 = p[9 + c], b0, b1;
-        if (MU == 0) { b0 = times_mi(d1); b1 = times_mi(d0); }
-        else if (MU == 1) { b0 = {-d1.re, -d1.im}; b1 = d0; }
-        else if (MU == 2) { b0 = times_mi(d0); b1 = times_i(d1); }
-        else { b0 = d0; b1 = d1; }
-        if (SG > 0) { h[c] = u0 - b0; h[3 + c] = u1 - b1; }
-        else { h[c] = u0 + b0; h[3 + c] = u1 + b1; }
-    }
-}
-template <int MU, int SG>
-__device__ __forceinline__ void frecon(const cx<float> g[6], cx<float> acc[12]) {
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        cx<float> g0 = g[c], g1 = g[3 + c], e0, e1;
-        if (MU == 0) { e0 = times_i(g1); e1 = times_i(g0); }
-        else if (MU == 1) { e0 = g1; e1 = {-g0.re, -g0.im}; }
-        else if (MU == 2) { e0 = times_i(g0); e1 = times_mi(g1); }
-        else { e0 = g0; e1 = g1; }
-        acc[c] = acc[c] + g0;
-        acc[3 + c] = acc[3 + c] + g1;
-        if (SG > 0) { acc[6 + c] = acc[6 + c] - e0; acc[9 + c] = acc[9 + c] - e1; }
-        else { acc[6 + c] = acc[6 + c] + e0; acc[9 + c] = acc[9 + c] + e1; }
-    }
-}
-template <int MU, bool DAG>
-__device__ __forceinline__ void fhop(const Geom& geo, const void* gauge, const void* in, uint32_t s, const Site& c,
-                                     cx<float> acc[12]) {
-    constexpr int SF = DAG ? -1 : 1;
-    {
-        const uint32_t y = nb_fwd(geo, s, c, MU);
-        const bool flip = (MU == 3) && (c.t + 1 == geo.L[3]) && (geo.t_bc < 0);
-        cx<float> U[3][3], p[12], h[6], g[6];
-        load_link<GF32, float>(gauge, geo.Vs, MU, s, U);
-        load_spinor<SF32, float>(in, geo.Vs, y, p);
-        fproj<MU, SF>(p, h);
-        if (flip)
-#pragma unroll
-            for (int k = 0; k < 6; k++) h[k] = {-h[k].re, -h[k].im};
-#pragma unroll
-        for (int a = 0; a < 2; a++)
-#pragma unroll
-            for (int i = 0; i < 3; i++) g[3 * a + i] = U[i][0] * h[3 * a] + U[i][1] * h[3 * a + 1] + U[i][2] * h[3 * a + 2];
-        frecon<MU, SF>(g, acc);
-    }
-#pragma unroll
-    for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im));
-    asm volatile("" ::: "memory");
-    {
-        const uint32_t y = nb_bwd(geo, s, c, MU);
-        const bool flip = (MU == 3) && (c.t == 0) && (geo.t_bc < 0);
-        cx<float> U[3][3], p[12], h[6], g[6];
-        load_link<GF32, float>(gauge, geo.Vs, MU, y, U);
-        load_spinor<SF32, float>(in, geo.Vs, y, p);
-        fproj<MU, -SF>(p, h);
-        if (flip)
-#pragma unroll
-            for (int k = 0; k < 6; k++) h[k] = {-h[k].re, -h[k].im};
-#pragma unroll
-        for (int a = 0; a < 2; a++)
-#pragma unroll
-            for (int i = 0; i < 3; i++)
-                g[3 * a + i] = cmulc(U[0][i], h[3 * a]) + cmulc(U[1][i], h[3 * a + 1]) + cmulc(U[2][i], h[3 * a + 2]);
-        frecon<MU, -SF>(g, acc);
-    }
-#pragma unroll
-    for (int k = 0; k < 12; k++) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im));
-    asm volatile("" ::: "memory");
-}
-// out = in - kappa H in + i tw gamma_5 in (DAG: H^dag and -tw)
+// out = M in (DAG: M^dag in), single right-hand side, FP32
 template <bool DAG>
 __device__ __forceinline__ void fop(const Geom& geo, const void* gauge, float kappa, float tw, const void* in,
                                     uint32_t s, cx<float> out[12]) {
     const Site c = site_coords(geo, s);
-    cx<float> acc[12], p[12];
-#pragma unroll
-    for (int k = 0; k < 12; k++) acc[k] = {0.f, 0.f};
-    fhop<0, DAG>(geo, gauge, in, s, c, acc);
-    fhop<1, DAG>(geo, gauge, in, s, c, acc);
-    fhop<2, DAG>(geo, gauge, in, s, c, acc);
-    fhop<3, DAG>(geo, gauge, in, s, c, acc);
+    cx<float> acc[1][12], p[12];
+    hop_all<DAG, float, SF32, GF32, 1>(geo, gauge, in, s, c, acc);
     load_spinor<SF32, float>(in, geo.Vs, s, p);
-    const float t = DAG ? -tw : tw;
-#pragma unroll
-    for (int k = 0; k < 6; k++) out[k] = {p[k].re - kappa * acc[k].re - t * p[k].im, p[k].im - kappa * acc[k].im + t * p[k].re};
-#pragma unroll
-    for (int k = 6; k < 12; k++) out[k] = {p[k].re - kappa * acc[k].re + t * p[k].im, p[k].im - kappa * acc[k].im - t * p[k].re};
+    diag_combine(p, acc[0], kappa, DAG ? -tw : tw, out);
 }
 
 __device__ __forceinline__ bool finite_d(double v) { return v == v && v < 1e300 && v > -1e300; }
@@ -114,7 +31,6 @@ __device__ __forceinline__ bool finite_d(double v) { return v == v && v < 1e300 
 // F1: t = M p, alpha = <z,r> / |t|^2
 __global__ TM_STENCIL(1) void k_fcg_mp(FcgArgs a) {
     __shared__ double sh[4];
-    __shared__ int sflag;
     const uint32_t nb = gridDim.x, b = xcd_block(blockIdx.x, nb);
     const uint32_t s = b * 256u + threadIdx.x;
     const int r = blockIdx.y;
@@ -130,22 +46,32 @@ __global__ TM_STENCIL(1) void k_fcg_mp(FcgArgs a) {
     }
     double v = block_sum256(part, sh);
     if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
-    if (take_last_ticket(a.counters + r, nb, &sflag)) {
-        double tt = sum_partials(a.partials + (size_t)r * nb, nb, sh);
-        if (threadIdx.x == 0) {
-            FcgScal& q = a.scal[r];
-            q.tt = tt;
-            q.alpha_re = tt > 0 ? q.zr_re / tt : 0.0;
-            q.alpha_im = tt > 0 ? q.zr_im / tt : 0.0;
-            a.counters[r] = 0;
-        }
+}
+
+// Block partials of one source in a fixed order; valid in thread 0.
+__device__ __forceinline__ double fsum(const double* p, uint32_t n, double* sh) {
+    double v = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += 256) v += p[i];
+    return block_sum256(v, sh);
+}
+
+// after F1, one block per source: alpha = <z,r> / |t|^2
+__global__ __launch_bounds__(256) void k_fcg_mp_fin(FcgArgs a, uint32_t nb) {
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
+    if (!a.scal[r].active) return;
+    const double tt = fsum(a.partials + (size_t)r * nb, nb, sh);
+    if (threadIdx.x == 0) {
+        FcgScal& q = a.scal[r];
+        q.tt = tt;
+        q.alpha_re = tt > 0 ? q.zr_re / tt : 0.0;
+        q.alpha_im = tt > 0 ? q.zr_im / tt : 0.0;
     }
 }
 
 // F2: q = M^dag t, x += alpha p, r -= alpha q, |r|^2, stop and stagnation tests
 __global__ TM_STENCIL(1) void k_fcg_upd(FcgArgs a) {
     __shared__ double sh[4];
-    __shared__ int sflag;
     const uint32_t nb = gridDim.x, b = xcd_block(blockIdx.x, nb);
     const uint32_t s = b * 256u + threadIdx.x;
     const int r = blockIdx.y;
@@ -174,8 +100,15 @@ __global__ TM_STENCIL(1) void k_fcg_upd(FcgArgs a) {
     }
     double v = block_sum256(part, sh);
     if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
-    if (take_last_ticket(a.counters + r, nb, &sflag)) {
-        double rrn = sum_partials(a.partials + (size_t)r * nb, nb, sh);
+}
+
+// after F2, one block per source: stop and stagnation tests
+__global__ __launch_bounds__(256) void k_fcg_upd_fin(FcgArgs a, uint32_t nb) {
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
+    if (!a.scal[r].active) return;
+    {
+        double rrn = fsum(a.partials + (size_t)r * nb, nb, sh);
         if (threadIdx.x == 0) {
             FcgScal& q = a.scal[r];
             q.iters += 1;
@@ -194,7 +127,6 @@ __global__ TM_STENCIL(1) void k_fcg_upd(FcgArgs a) {
                 q.status = 2;
                 q.active = 0;
             }
-            a.counters[r] = 0;
         }
     }
 }
@@ -202,7 +134,6 @@ __global__ TM_STENCIL(1) void k_fcg_upd(FcgArgs a) {
 // F3 (and the initial step, init = 1): <z,q>, <z,r>; choose the direction mode
 __global__ __launch_bounds__(256) void k_fcg_dot(FcgArgs a, int init) {
     __shared__ double sh[4];
-    __shared__ int sflag;
     const uint32_t nb = gridDim.x;
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     const int r = blockIdx.y;
@@ -235,11 +166,19 @@ __global__ __launch_bounds__(256) void k_fcg_dot(FcgArgs a, int init) {
         P[2 * nb + blockIdx.x] = v2;
         P[3 * nb + blockIdx.x] = v3;
     }
-    if (take_last_ticket(a.counters + r, nb, &sflag)) {
-        double zrr = sum_partials(P, nb, sh);
-        double zri = sum_partials(P + nb, nb, sh);
-        double zqr = sum_partials(P + 2 * nb, nb, sh);
-        double zqi = sum_partials(P + 3 * nb, nb, sh);
+}
+
+// after F3, one block per source: beta and the direction mode, or fallback
+__global__ __launch_bounds__(256) void k_fcg_dot_fin(FcgArgs a, uint32_t nb, int init) {
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
+    if (!a.scal[r].active) return;
+    const double* P = a.partials + (size_t)r * nb * 4;
+    {
+        double zrr = fsum(P, nb, sh);
+        double zri = fsum(P + nb, nb, sh);
+        double zqr = fsum(P + 2 * nb, nb, sh);
+        double zqi = fsum(P + 3 * nb, nb, sh);
         if (threadIdx.x == 0) {
             FcgScal& q = a.scal[r];
             const bool bad = !(zrr > 0) || !finite_d(zrr) || !finite_d(zri) || !finite_d(zqr) || !finite_d(zqi);
@@ -277,7 +216,6 @@ __global__ __launch_bounds__(256) void k_fcg_dot(FcgArgs a, int init) {
                 q.zr_re = zrr;
                 q.zr_im = zri;
             }
-            a.counters[r] = 0;
         }
     }
 }
@@ -305,9 +243,8 @@ __global__ __launch_bounds__(256) void k_fcg_p(FcgArgs a) {
 }
 
 // init: x = 0, |b|^2 (r holds b = M^dag eta), scalars
-__global__ __launch_bounds__(256) void k_fcg_init(FcgArgs a, double tol2, int maxit, int fell) {
+__global__ __launch_bounds__(256) void k_fcg_init(FcgArgs a) {
     __shared__ double sh[4];
-    __shared__ int sflag;
     const uint32_t nb = gridDim.x;
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     const int r = blockIdx.y;
@@ -325,8 +262,13 @@ __global__ __launch_bounds__(256) void k_fcg_init(FcgArgs a, double tol2, int ma
     }
     double v = block_sum256(part, sh);
     if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
-    if (take_last_ticket(a.counters + r, nb, &sflag)) {
-        double bb = sum_partials(a.partials + (size_t)r * nb, nb, sh);
+}
+
+__global__ __launch_bounds__(256) void k_fcg_init_fin(FcgArgs a, uint32_t nb, double tol2, int maxit, int fell) {
+    __shared__ double sh[4];
+    const int r = blockIdx.x;
+    {
+        double bb = fsum(a.partials + (size_t)r * nb, nb, sh);
         if (threadIdx.x == 0) {
             FcgScal q = {};
             q.bb = q.rr = q.rr_prev = bb;
@@ -338,24 +280,31 @@ __global__ __launch_bounds__(256) void k_fcg_init(FcgArgs a, double tol2, int ma
             q.status = (bb <= 0 || 1.0 <= tol2) ? 1 : (maxit == 0 ? 2 : 0);
             q.active = q.status == 0;
             a.scal[r] = q;
-            a.counters[r] = 0;
         }
     }
 }
 
 static inline dim3 fgrid(const Geom& g, int n) { return dim3((unsigned)((g.V + 255) / 256), (unsigned)n); }
 
+static inline uint32_t fblocks(const Geom& g) { return (uint32_t)((g.V + 255) / 256); }
+
+// each partial-writing kernel is followed by its one-block-per-source
+// finaliser (no device-scope release per block; see the CG kernels)
 void launch_fcg_init(hipStream_t st, const FcgArgs& a, double tol2, int maxit, int fell) {
-    hipLaunchKernelGGL(k_fcg_init, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a, tol2, maxit, fell);
+    hipLaunchKernelGGL(k_fcg_init, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_fcg_init_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, fblocks(a.geo), tol2, maxit, fell);
 }
 void launch_fcg_mp(hipStream_t st, const FcgArgs& a) {
     hipLaunchKernelGGL(k_fcg_mp, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_fcg_mp_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, fblocks(a.geo));
 }
 void launch_fcg_upd(hipStream_t st, const FcgArgs& a) {
     hipLaunchKernelGGL(k_fcg_upd, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_fcg_upd_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, fblocks(a.geo));
 }
 void launch_fcg_dot(hipStream_t st, const FcgArgs& a, int init) {
     hipLaunchKernelGGL(k_fcg_dot, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a, init);
+    hipLaunchKernelGGL(k_fcg_dot_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, fblocks(a.geo), init);
 }
 void launch_fcg_p(hipStream_t st, const FcgArgs& a) {
     hipLaunchKernelGGL(k_fcg_p, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a);

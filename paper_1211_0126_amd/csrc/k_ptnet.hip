@@ -5,18 +5,18 @@
 //     psi_a(x) = sum_b sum_p W[p][a][b] (T_p phi_b)(x),
 // p over nine paths (identity, U_mu(x) phi(x+mu), U_mu(x-mu)^dag phi(x-mu),
 // with the time-boundary sign), W[p][a][b] a complex 4x4 spin matrix,
-// identity on colour.  Per block of 64 sites:
+// identity on colour.  Per block of PT_TS sites:
 //   1. gather: every (site, path, channel) transport is computed once with
 //      the FP32 links and written as bfloat16 into an LDS tile A whose rows
 //      are (colour, site) and columns (path, channel, spin, re/im);
-//   2. mix: the dense channel/spin mixing is a real GEMM A(192 x K) B(K x 16)
+//   2. mix: the dense channel/spin mixing is a real GEMM A(3 PT_TS x K) B(K x 16)
 //      on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation),
 //      B the real form of the complex weights, K = 72 cin padded to 16;
-//   3. the 192 x 16 FP32 result is staged in LDS and written as spinors.
+//   3. the 3 PT_TS x 16 FP32 result is staged in LDS and written as spinors.
 // The adjoint layer is the same kernel with weights W'[p*][b][a] = W[p][a][b]^dag
 // (p* the reversed path), prepared on the host.
 // The weight gradient dW = sum_{x,c} g (T_p phi)^dag is the GEMM
-// G^T (16 x 192) A (192 x K) per block, FP32 block partials reduced in a
+// G^T (16 x 3 PT_TS) A (3 PT_TS x K) per block, FP32 block partials reduced in a
 // fixed order.
 
 #include "tm_device.h"
@@ -27,8 +27,11 @@ namespace tmq {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-constexpr int PT_TS = 64;             // sites per block
+// 32 sites per block keep the bfloat16 A tile at 28 KB of LDS, so five
+// blocks (20 waves) share a compute unit to hide the gather's load latency
+constexpr int PT_TS = 32;             // sites per block
 constexpr int PT_ROWS = 3 * PT_TS;    // (colour, site) rows
+constexpr int PT_NT = PT_ROWS / 16;   // 16-row MFMA tiles, dealt to the 4 waves
 constexpr int PT_KMAX = 144;          // 72 * cin for cin <= 2
 constexpr int PT_KP = PT_KMAX + 4;    // LDS row stride (bf16), padded against bank conflicts
 constexpr int PT_GP = 16 + 4;         // LDS row stride of the gradient tile
@@ -126,11 +129,14 @@ __global__ __launch_bounds__(256) void k_pt_layer(PtArgs a) {
     __syncthreads();
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    v4f acc[3];
+    constexpr int TPW = (PT_NT + 3) / 4;  // row tiles per wave
+    v4f acc[TPW];
 #pragma unroll
-    for (int t = 0; t < 3; t++) {
+    for (int t = 0; t < TPW; t++) {
         acc[t] = (v4f){0.f, 0.f, 0.f, 0.f};
-        const int row = (3 * w + t) * 16 + (lane & 15);
+        const int tile = w + 4 * t;
+        if (tile >= PT_NT) continue;
+        const int row = tile * 16 + (lane & 15);
         for (int ks = 0; ks < kpad / 16; ks++) {
             const v4s af = *(const v4s*)(As + row * PT_KP + ks * 16 + 4 * (lane >> 4));
             const v4s bf = ((const v4s*)a.wfrag)[ks * 64 + lane];
@@ -138,11 +144,14 @@ __global__ __launch_bounds__(256) void k_pt_layer(PtArgs a) {
         }
     }
     __syncthreads();
-    float* Os = (float*)As;  // reuse: 192 x 16 floats
+    float* Os = (float*)As;  // reuse: PT_ROWS x 16 floats
 #pragma unroll
-    for (int t = 0; t < 3; t++)
+    for (int t = 0; t < TPW; t++) {
+        const int tile = w + 4 * t;
+        if (tile >= PT_NT) continue;
 #pragma unroll
-        for (int j = 0; j < 4; j++) Os[((3 * w + t) * 16 + 4 * (lane >> 4) + j) * 16 + (lane & 15)] = acc[t][j];
+        for (int j = 0; j < 4; j++) Os[(tile * 16 + 4 * (lane >> 4) + j) * 16 + (lane & 15)] = acc[t][j];
+    }
     __syncthreads();
     for (int item = threadIdx.x; item < PT_TS * a.cout; item += 256) {
         const int i = item % PT_TS, ch = item / PT_TS;

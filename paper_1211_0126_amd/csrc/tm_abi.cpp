@@ -69,6 +69,13 @@ uint64_t seed_mix(uint64_t z) {
     return z ^ (z >> 31);
 }
 
+tm_status copy_sync(tm_ctx* ctx, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return dev_error(ctx, e, "copy");
+    return TM_OK;
+}
+
 void prof_begin(tm_ctx* ctx, int kc, int tag) {
     if (!ctx->prof) return;
     while (ctx->ev_used + 2 > ctx->ev_pool.size()) {
@@ -352,7 +359,7 @@ tm_status tm_autotune(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_nr,
     if (s != TM_OK) return s;
     std::vector<uint64_t> idh(nrhs);
     for (int i = 0; i < nrhs; i++) idh[i] = (uint64_t)i;
-    TM_HIP(hipMemcpy(ids, idh.data(), sizeof(uint64_t) * nrhs, hipMemcpyHostToDevice));
+    if ((s = copy_sync(ctx, ids, idh.data(), sizeof(uint64_t) * nrhs, hipMemcpyHostToDevice)) != TM_OK) return s;
     launch_noise_native(ctx->stream, g, prec, seed_mix(12345), ids, nrhs, in);
     const void* gauge = prec == TM_PREC_F64 ? ctx->gauge64 : ctx->gauge32;
     hipEvent_t e0, e1;

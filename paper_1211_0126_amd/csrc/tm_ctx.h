@@ -82,6 +82,16 @@ void* ws_get(tm_ctx* ctx, const std::string& name, size_t bytes, tm_status* st);
 size_t field_bytes(const Geom& g, int prec, int nrhs);
 uint64_t seed_mix(uint64_t seed);
 
+// Copy on the context's stream and wait for it (and for all work queued
+// before it).  A plain hipMemcpy runs on the null stream, which does not
+// wait for a non-blocking stream such as the caller's.
+tm_status copy_sync(tm_ctx* ctx, void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
+#define TM_COPY(dst, src, bytes, kind)                                          \
+    do {                                                                        \
+        const tm_status cs_ = ::tmq::copy_sync(ctx, (dst), (src), (bytes), (kind)); \
+        if (cs_ != TM_OK) return cs_;                                           \
+    } while (0)
+
 // instrumentation around a launch of kernel class kc moving `bytes`
 // tag: prof_tag(prec, lane_rhs, solver) of the launched kernel, -1 if none
 void prof_begin(tm_ctx* ctx, int kc, int tag = -1);

@@ -186,9 +186,12 @@ void net_release(tm_ctx* ctx) {
 // Loss and accumulated gradient of a list of pairs (native fields, r in
 // r_prec, e in e_prec), into per-layer device gradients [16][kpad] double.
 // scal[2] accumulates the loss.  grads must be zeroed by the caller.
+// mode 0: error loss |N(r) - e|^2 / |e|^2; mode 1: residual loss
+// |M N(r) - r|^2 / |r|^2 (e unused), whose gradient with respect to N(r) is
+// M^dag (M N(r) - r).
 static tm_status loss_grad_pairs(tm_ctx* ctx, int npairs, const void* r, int r_prec, const void* e, int e_prec,
                                  size_t pair_stride_r, size_t pair_stride_e, std::vector<double*>& grads,
-                                 double* scal) {
+                                 double* scal, int mode = 0) {
     NetState* ns = ctx->net;
     const Geom& g = ctx->geo;
     tm_status s = TM_OK;
@@ -201,6 +204,8 @@ static tm_status loss_grad_pairs(tm_ctx* ctx, int npairs, const void* r, int r_p
     float* partials = (float*)ws_get(ctx, "lg_partials", sizeof(float) * (size_t)nb * 16 * 144, &s);
     double* lpart = (double*)ws_get(ctx, "lg_lpart", sizeof(double) * 2 * ((g.V + 255) / 256), &s);
     unsigned int* counter = (unsigned int*)ws_get(ctx, "lg_counter", sizeof(unsigned int), &s);
+    void* mw = mode == 1 ? ws_get(ctx, "lg_mw", f2, &s) : nullptr;
+    void* gd = mode == 1 ? ws_get(ctx, "lg_gd", f2, &s) : nullptr;
     if (s != TM_OK) return s;
     for (int i = 0; i < npairs; i++) {
         const void* ri = (const char*)r + i * pair_stride_r;
@@ -213,7 +218,14 @@ static tm_status loss_grad_pairs(tm_ctx* ctx, int npairs, const void* r, int r_p
             cur = act[l + 1];
             cur_prec = P_F32;
         }
-        launch_pt_loss(ctx->stream, g, act[ns->nl], ei, e_prec, g0, lpart, counter, scal, npairs);
+        if (mode == 1) {
+            launch_apply(ctx->stream, g, P_F32, ctx->gauge32, ctx->lat.kappa, ctx->twist, 0, 1, act[ns->nl], mw, 1,
+                         nullptr);
+            launch_pt_loss(ctx->stream, g, mw, ri, r_prec, gd, lpart, counter, scal, npairs);
+            launch_apply(ctx->stream, g, P_F32, ctx->gauge32, ctx->lat.kappa, ctx->twist, 1, 1, gd, g0, 1, nullptr);
+        } else {
+            launch_pt_loss(ctx->stream, g, act[ns->nl], ei, e_prec, g0, lpart, counter, scal, npairs);
+        }
         // backward
         void* gcur = g0;
         void* gnext = g1;
@@ -271,7 +283,7 @@ static tm_status read_grads(tm_ctx* ctx, std::vector<double*>& grads, std::vecto
     G.assign(ns->W.size(), cplx(0, 0));
     for (int l = 0; l < ns->nl; l++) {
         std::vector<double> C((size_t)16 * ns->kpad_fwd[l]);
-        TM_HIP(hipMemcpy(C.data(), grads[l], sizeof(double) * C.size(), hipMemcpyDeviceToHost));
+        TM_COPY(C.data(), grads[l], sizeof(double) * C.size(), hipMemcpyDeviceToHost);
         layer_grad_to_complex(C.data(), ns->widths[l], ns->widths[l + 1], ns->kpad_fwd[l], G.data() + ns->off[l]);
     }
     return TM_OK;
@@ -338,7 +350,7 @@ tm_status tm_precond_loss_grad(tm_ctx* ctx, int32_t npairs, const double* r_dev,
     if ((s = alloc_grads(ctx, grads)) != TM_OK) return s;
     if ((s = loss_grad_pairs(ctx, npairs, r, P_F32, e, P_F32, f1, f1, grads, scal)) != TM_OK) return s;
     double sc[4];
-    TM_HIP(hipMemcpy(sc, scal, sizeof(sc), hipMemcpyDeviceToHost));
+    TM_COPY(sc, scal, sizeof(sc), hipMemcpyDeviceToHost);
     *loss_host = sc[2];
     std::vector<cplx> G;
     if ((s = read_grads(ctx, grads, G)) != TM_OK) return s;
@@ -346,17 +358,87 @@ tm_status tm_precond_loss_grad(tm_ctx* ctx, int32_t npairs, const double* r_dev,
     return TM_OK;
 }
 
+// Euclidean chiral gammas (gamma_k = [[0, -i s_k], [i s_k, 0]], gamma_4 =
+// [[0, 1], [1, 0]], gamma_5 = diag(1, 1, -1, -1)), g[mu][row][col] with
+// mu = 0..3 for gamma_1..gamma_4 and mu = 4 for gamma_5.
+static void chiral_gammas(cplx g[5][4][4]) {
+    const cplx I(0, 1);
+    for (int m = 0; m < 5; m++)
+        for (int a = 0; a < 4; a++)
+            for (int b = 0; b < 4; b++) g[m][a][b] = 0;
+    const cplx sig[3][2][2] = {{{0, 1}, {1, 0}}, {{0, -I}, {I, 0}}, {{1, 0}, {0, -1}}};
+    for (int k = 0; k < 3; k++)
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++) {
+                g[k][a][2 + b] = -I * sig[k][a][b];
+                g[k][2 + a][b] = I * sig[k][a][b];
+            }
+    for (int a = 0; a < 2; a++) {
+        g[3][a][2 + a] = 1;
+        g[3][2 + a][a] = 1;
+    }
+    for (int a = 0; a < 4; a++) g[4][a][a] = a < 2 ? 1 : -1;
+}
+
+// Layer l of the third-order Neumann series of M^{-1}: with A = 1 - M (path
+// 0: -2 i kappa mu g5; path +mu: kappa (1 - g_mu); path -mu: kappa (1 + g_mu))
+//   layer 0 (1 -> 2): c0 = psi,  c1 = psi + A psi
+//   layer 1 (2 -> 2): c0 = c0,   c1 = c0 + A c1
+//   layer 2 (2 -> 1): out = c0 + A c1
+// so out = psi + A psi + A^2 psi + A^3 psi.  W is added to (layout
+// [p][cout][cin][4][4]).
+static void neumann_layer(const tm_ctx* ctx, int l, int cin, int cout, cplx* W) {
+    cplx g[5][4][4];
+    chiral_gammas(g);
+    const double kappa = ctx->lat.kappa, tw = ctx->twist;  // tw = 2 kappa mu
+    auto at = [&](int p, int a, int b) { return W + (((size_t)p * cout + a) * cin + b) * 16; };
+    auto add_identity = [&](cplx* w) {
+        for (int i = 0; i < 4; i++) w[i * 4 + i] += 1.0;
+    };
+    auto add_a = [&](int a, int b) {  // A from channel b into channel a
+        cplx* w0 = at(0, a, b);
+        for (int i = 0; i < 4; i++)
+            for (int j = 0; j < 4; j++) w0[i * 4 + j] += cplx(0, -tw) * g[4][i][j];
+        for (int m = 0; m < 4; m++) {
+            cplx* wf = at(1 + 2 * m, a, b);
+            cplx* wb = at(2 + 2 * m, a, b);
+            for (int i = 0; i < 4; i++)
+                for (int j = 0; j < 4; j++) {
+                    const cplx d = i == j ? 1.0 : 0.0;
+                    wf[i * 4 + j] += kappa * (d - g[m][i][j]);
+                    wb[i * 4 + j] += kappa * (d + g[m][i][j]);
+                }
+        }
+    };
+    if (l == 0) {  // 1 -> 2
+        add_identity(at(0, 0, 0));
+        add_identity(at(0, 1, 0));
+        add_a(1, 0);
+    } else if (l == 1) {  // 2 -> 2
+        add_identity(at(0, 0, 0));
+        add_identity(at(0, 1, 0));
+        add_a(1, 1);
+    } else {  // 2 -> 1
+        add_identity(at(0, 0, 0));
+        add_a(0, 1);
+    }
+}
+
 tm_status tm_precond_train(tm_ctx* ctx, const tm_train_params* P, tm_train_stats* stats) {
     using clk = std::chrono::steady_clock;
     if (!ctx || !P) return set_error(ctx, TM_EINVAL, "tm_precond_train: null argument");
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
     if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tm_precond_train: no gauge field loaded");
-    if (P->n_sources < 1 || P->n_pairs < 1 || P->epochs < 0 || P->batch < 1 || !(P->lr > 0) || !(P->hp_tol > 0))
+    const bool init_only = P->n_pairs == 0 && P->epochs == 0;
+    if ((!init_only && (P->n_sources < 1 || P->n_pairs < 1 || P->epochs < 0 || P->batch < 1 || !(P->lr > 0) ||
+                        !(P->hp_tol > 0))) ||
+        P->init_mode < 0 || P->init_mode > 1 || P->loss_mode < 0 || P->loss_mode > 1)
         return set_error(ctx, TM_EINVAL, "tm_precond_train: bad parameters");
     const Geom& g = ctx->geo;
     tm_status s = TM_OK;
-    // initial network: identity on channel 0 of every layer plus noise
-    if (!ctx->net) {
+    // initial network (init_mode) plus noise; a network already installed
+    // is trained from where it is, unless only the initial one is asked for
+    if (!ctx->net || init_only) {
         tm_net_shape sh;
         std::memset(&sh, 0, sizeof(sh));
         sh.n_layers = 3;
@@ -372,10 +454,18 @@ tm_status tm_precond_train(tm_ctx* ctx, const tm_train_params* P, tm_train_stats
             const int cin = sh.widths[l], cout = sh.widths[l + 1];
             for (size_t k = 0; k < (size_t)9 * cin * cout * 16; k++)
                 W[off + k] = P->init_scale * cplx(nd(rng), nd(rng));
-            for (int si = 0; si < 4; si++) W[off + (size_t)si * 4 + si] += 1.0;  // p = 0, a = 0, b = 0
+            if (P->init_mode == 0) {
+                for (int si = 0; si < 4; si++) W[off + (size_t)si * 4 + si] += 1.0;  // p = 0, a = 0, b = 0
+            } else {
+                neumann_layer(ctx, l, cin, cout, W.data() + off);
+            }
             off += (size_t)9 * cin * cout * 16;
         }
         if ((s = install(ctx, &sh, W.data())) != TM_OK) return s;
+    }
+    if (init_only) {
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        return TM_OK;
     }
     NetState* ns = ctx->net;
     auto t0 = clk::now();
@@ -390,7 +480,7 @@ tm_status tm_precond_train(tm_ctx* ctx, const tm_train_params* P, tm_train_stats
     if (s != TM_OK) return s;
     std::vector<uint64_t> idh(P->n_sources);
     for (int j = 0; j < P->n_sources; j++) idh[j] = (uint64_t)j;
-    TM_HIP(hipMemcpy(ids, idh.data(), sizeof(uint64_t) * P->n_sources, hipMemcpyHostToDevice));
+    TM_COPY(ids, idh.data(), sizeof(uint64_t) * P->n_sources, hipMemcpyHostToDevice);
     const uint64_t sm = seed_mix(P->seed);
     const int per_src = (npairs_max + P->n_sources - 1) / P->n_sources;
     int npairs = 0;
@@ -437,11 +527,11 @@ tm_status tm_precond_train(tm_ctx* ctx, const tm_train_params* P, tm_train_stats
             for (int i = 0; i < bsz; i++) {
                 const int pi = order[b0 + i];
                 if ((s = loss_grad_pairs(ctx, 1, (const char*)R + pi * fbf, P_BF16, (const char*)E + pi * fbf, P_BF16,
-                                         fbf, fbf, grads, scal)) != TM_OK)
+                                         fbf, fbf, grads, scal, P->loss_mode)) != TM_OK)
                     return s;
             }
             double sc[4];
-            TM_HIP(hipMemcpy(sc, scal, sizeof(sc), hipMemcpyDeviceToHost));
+            TM_COPY(sc, scal, sizeof(sc), hipMemcpyDeviceToHost);
             ep_loss += sc[2] / bsz;
             nsteps++;
             std::vector<cplx> G;

@@ -514,8 +514,8 @@ static tm_status setup_contract(tm_ctx* ctx, const MomPlan& mp, int n_mom, int m
     double* phd = (double*)ws_get(ctx, "c_phase", sizeof(double) * ph.size(), &s);
     int* idd = (int*)ws_get(ctx, "c_momidx", sizeof(int) * mp.idx.size(), &s);
     if (s != TM_OK) return s;
-    TM_HIP(hipMemcpy(phd, ph.data(), sizeof(double) * ph.size(), hipMemcpyHostToDevice));
-    TM_HIP(hipMemcpy(idd, mp.idx.data(), sizeof(int) * mp.idx.size(), hipMemcpyHostToDevice));
+    TM_COPY(phd, ph.data(), sizeof(double) * ph.size(), hipMemcpyHostToDevice);
+    TM_COPY(idd, mp.idx.data(), sizeof(int) * mp.idx.size(), hipMemcpyHostToDevice);
     a.phx = (const double2*)phd;
     a.phy = a.phx + a.npx * L0;
     a.phz = a.phy + a.npy * L1;
@@ -569,7 +569,7 @@ tm_status tsm_solve_batch(tm_ctx* ctx, const tsm_solve_params* params, uint64_t 
     ids.resize(npad, ids_host[nsrc - 1]);
     uint64_t* ids_dev = (uint64_t*)ws_get(ctx, "solve_ids", sizeof(uint64_t) * npad, &s);
     if (!ids_dev) return s;
-    TM_HIP(hipMemcpy(ids_dev, ids.data(), sizeof(uint64_t) * npad, hipMemcpyHostToDevice));
+    TM_COPY(ids_dev, ids.data(), sizeof(uint64_t) * npad, hipMemcpyHostToDevice);
     const uint64_t sm = seed_mix(seed);
     bool warn = false;
     for (int j0 = 0; j0 < nsrc; j0 += blk) {
@@ -611,8 +611,8 @@ tm_status tsm_contract(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t*
     if (s != TM_OK) return s;
     std::vector<int> sl(nsrc);
     for (int i = 0; i < nsrc; i++) sl[i] = i;
-    TM_HIP(hipMemcpy(ids_dev, ids_host, sizeof(uint64_t) * nsrc, hipMemcpyHostToDevice));
-    TM_HIP(hipMemcpy(slots, sl.data(), sizeof(int) * nsrc, hipMemcpyHostToDevice));
+    TM_COPY(ids_dev, ids_host, sizeof(uint64_t) * nsrc, hipMemcpyHostToDevice);
+    TM_COPY(slots, sl.data(), sizeof(int) * nsrc, hipMemcpyHostToDevice);
     for (int j0 = 0; j0 < nsrc; j0 += blk) {
         const int nb = std::min(blk, nsrc - j0);
         launch_field_convert(ctx->stream, g, P_F64, nb, true, sol_dev + (size_t)j0 * g.V * 24, nat);
@@ -662,8 +662,8 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double
         slots[j] = 2 * std::min(j, std::max(N - 1, 0));              // LP slot
         slots[Npad + j] = 2 * std::min(j, std::max(N - 1, 0)) + 1;   // HP slot
     }
-    TM_HIP(hipMemcpy(ids_dev, ids.data(), sizeof(uint64_t) * Npad, hipMemcpyHostToDevice));
-    TM_HIP(hipMemcpy(slots_dev, slots.data(), sizeof(int) * 2 * Npad, hipMemcpyHostToDevice));
+    TM_COPY(ids_dev, ids.data(), sizeof(uint64_t) * Npad, hipMemcpyHostToDevice);
+    TM_COPY(slots_dev, slots.data(), sizeof(int) * 2 * Npad, hipMemcpyHostToDevice);
     TM_HIP(hipMemsetAsync(ps, 0, sizeof(double) * 2 * 2 * nl * std::max(N, 1), st));
 
     tsm_run_stats rs;
@@ -720,10 +720,10 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double
     TM_HIP(hipGetLastError());
     TM_HIP(hipStreamSynchronize(st));
     auto t2 = clk::now();
-    TM_HIP(hipMemcpy(loops_host, fin, sizeof(double) * 2 * 3 * nl, hipMemcpyDeviceToHost));
-    if (err_host) TM_HIP(hipMemcpy(err_host, fin + 2 * 3 * nl, sizeof(double) * 2 * 3 * nl, hipMemcpyDeviceToHost));
+    TM_COPY(loops_host, fin, sizeof(double) * 2 * 3 * nl, hipMemcpyDeviceToHost);
+    if (err_host) TM_COPY(err_host, fin + 2 * 3 * nl, sizeof(double) * 2 * 3 * nl, hipMemcpyDeviceToHost);
     if (per_source_host && N > 0)
-        TM_HIP(hipMemcpy(per_source_host, ps, sizeof(double) * 2 * 2 * nl * N, hipMemcpyDeviceToHost));
+        TM_COPY(per_source_host, ps, sizeof(double) * 2 * 2 * nl * N, hipMemcpyDeviceToHost);
     rs.ms_hp_phase = std::chrono::duration<double, std::milli>(t1 - t0).count();
     rs.ms_lp_phase = std::chrono::duration<double, std::milli>(t2 - t1).count();
     if (run_stats) *run_stats = rs;
@@ -741,7 +741,7 @@ tm_status tm_autotune_cg(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_
     if (!ids) return s;
     std::vector<uint64_t> idh(nrhs);
     for (int i = 0; i < nrhs; i++) idh[i] = (uint64_t)i;
-    TM_HIP(hipMemcpy(ids, idh.data(), sizeof(uint64_t) * nrhs, hipMemcpyHostToDevice));
+    TM_COPY(ids, idh.data(), sizeof(uint64_t) * nrhs, hipMemcpyHostToDevice);
     const int keep_nr = ctx->lane_rhs[prec], keep_ts = ctx->march[prec];
     tsm_solve_params p;
     std::memset(&p, 0, sizeof(p));
