@@ -52,10 +52,11 @@ def parse():
     ap.add_argument("--n-hp", type=int, default=None)
     ap.add_argument("--compare-sources", type=int, default=64)
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--learned", action="store_true", help="train the network and time flexible CG with it")
-    ap.add_argument("--train-pairs", type=int, default=200)
-    ap.add_argument("--train-sources", type=int, default=10)
-    ap.add_argument("--train-epochs", type=int, default=4)
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-preconditioner leg of the equal-residual comparison")
+    ap.add_argument("--train-pairs", type=int, default=256)
+    ap.add_argument("--train-sources", type=int, default=16)
+    ap.add_argument("--train-epochs", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--lp-true-resid", action="store_true",
@@ -315,14 +316,18 @@ def compare(args, tq, torch, ctx, wl, n_hp, lp_prec):
                             "true_resid_median": median_true(st_b), "speedup": round(t_ref / t_b, 3)}
     log("batched %s: %s" % (args.lp_prec, res["batched_mixed"]))
 
-    if args.learned:
+    if not args.no_learned:
+        # network: third-order Neumann series of M^{-1} as the starting point,
+        # trained on (residual, error) pairs from the early iterates of HP
+        # solves of training sources disjoint from the estimator's
         tr = tq.tm_precond_train(ctx, seed=0x5EED0000 + wl.noise_seed, n_sources=args.train_sources,
-                                 n_pairs=args.train_pairs, epochs=args.train_epochs, batch=8, lr=2e-3,
-                                 hp_tol=wl.hp_tol, min_rel_err=1e-3, init_seed=7, init_scale=1e-2)
+                                 n_pairs=args.train_pairs, epochs=args.train_epochs, batch=8, lr=1e-4,
+                                 hp_tol=wl.hp_tol, min_rel_err=0.3, init_seed=7, init_scale=0.0, init_mode=1,
+                                 loss_mode=0)
         log("trained: %s" % tr)
 
         def mk_fcg(tol):
-            return tq.solve_params(prec=tq.PREC_F32, tol=tol, max_iter=-1, rhs_block=args.lp_block, true_resid=1,
+            return tq.solve_params(prec=tq.PREC_F32, tol=tol, max_iter=-1, rhs_block=8, true_resid=1,
                                    solver=tq.SOLVER_FCG_LEARNED)
         tol_f, _ = calibrate(tq, ctx, mk_fcg, wl.noise_seed, cal_ids, target, wl.lp_tol)
         t_f, st_f = timed_solve(tq, torch, ctx, mk_fcg(tol_f), wl.noise_seed, ids)
