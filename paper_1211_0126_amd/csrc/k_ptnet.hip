@@ -5,19 +5,19 @@
 //     psi_a(x) = sum_b sum_p W[p][a][b] (T_p phi_b)(x),
 // p over nine paths (identity, U_mu(x) phi(x+mu), U_mu(x-mu)^dag phi(x-mu),
 // with the time-boundary sign), W[p][a][b] a complex 4x4 spin matrix,
-// identity on colour.  Per block of PT_TS sites:
+// identity on colour.  Both kernels below follow the same three steps:
 //   1. gather: every (site, path, channel) transport is computed once with
 //      the FP32 links and written as bfloat16 into an LDS tile A whose rows
 //      are (colour, site) and columns (path, channel, spin, re/im);
-//   2. mix: the dense channel/spin mixing is a real GEMM A(3 PT_TS x K) B(K x 16)
+//   2. mix: the dense channel/spin mixing is a real GEMM A(rows x K) B(K x 16)
 //      on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation),
 //      B the real form of the complex weights, K = 72 cin padded to 16;
-//   3. the 3 PT_TS x 16 FP32 result is staged in LDS and written as spinors.
+//   3. the FP32 result is staged in LDS and written as spinor planes.
 // The adjoint layer is the same kernel with weights W'[p*][b][a] = W[p][a][b]^dag
 // (p* the reversed path), prepared on the host.
 // The weight gradient dW = sum_{x,c} g (T_p phi)^dag is the GEMM
-// G^T (16 x 3 PT_TS) A (3 PT_TS x K) per block, FP32 block partials reduced in a
-// fixed order.
+// G^T (16 x rows) A (rows x K) per block of PT_TS sites, FP32 block partials
+// reduced in a fixed order.
 
 #include "tm_device.h"
 #include "tm_kernels.h"
@@ -27,8 +27,7 @@ namespace tmq {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// 32 sites per block keep the bfloat16 A tile at 28 KB of LDS, so five
-// blocks (20 waves) share a compute unit to hide the gather's load latency
+// weight gradient: 32 sites per block (a 28 KB bfloat16 A tile)
 constexpr int PT_TS = 32;             // sites per block
 constexpr int PT_ROWS = 3 * PT_TS;    // (colour, site) rows
 constexpr int PT_NT = PT_ROWS / 16;   // 16-row MFMA tiles, dealt to the 4 waves
@@ -76,7 +75,7 @@ __device__ __forceinline__ void transport_site(const Geom& geo, const void* gaug
         }
 }
 
-// Fill the A tile: rows (colour c, site i) = c*64 + i, columns
+// Fill the gradient's A tile: rows (colour c, site i) = c*PT_TS + i, columns
 // k = ((p*cin + b)*4 + spin)*2 + re/im, zero-padded to kpad.
 template <class Si>
 __device__ __forceinline__ void gather_tile(const PtArgs& a, uint32_t site0, uint16_t* As, int kpad) {
@@ -116,56 +115,224 @@ __device__ __forceinline__ void gather_tile(const PtArgs& a, uint32_t site0, uin
     }
 }
 
-template <class Si, class So>
-__global__ __launch_bounds__(256) void k_pt_layer(PtArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[PT_ROWS * PT_KP];
-    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const uint32_t site0 = blk * PT_TS;
-    const int kpad = a.kpad;
-    PtArgs ar = a;
-    const int r = blockIdx.y;  // right-hand side: channel blocks of cin / cout fields
-    ar.in = field_rhs<Si>(a.in, a.geo.Vs, r * a.cin);
-    gather_tile<Si>(ar, site0, As, kpad);
-    __syncthreads();
+// ---------------------------------------------------------------------------
+// Layer application.  A block owns 64 consecutive sites and loops over the
+// right-hand sides; it runs nine waves, wave p handling path p with one lane
+// per site.  The wave's effective link (sign and adjoint folded in) is loaded
+// once and kept in registers for all right-hand sides, and the input planes
+// of the next right-hand side are loaded while the current one is
+// transported, mixed and stored.  Per right-hand side:
+//   gather: the lane's CIN transports, packed to bfloat16, one 16-byte LDS
+//           store per colour into the tile (rows (colour, site), columns
+//           (path, channel, spin, re/im), row stride kpad + 8 bfloat16 so the
+//           16-byte stores and the 8-byte MFMA operand reads are conflict-free);
+//   mix:    the twelve 16-row MFMA tiles dealt to the waves, the FP32 result
+//           staged in its own LDS array;
+//   store:  one (channel, plane) of 16-byte elements per wave and pass.
+// The barriers wait for LDS traffic only, so the prefetched global loads
+// stay in flight across them.
+// ---------------------------------------------------------------------------
+constexpr int LY_TS = 64;
+constexpr int LY_ROWS = 3 * LY_TS;
+constexpr int LY_THREADS = 9 * 64;
+constexpr int LY_OS = 20;  // staging row stride (floats): conflict-free MFMA result writes
 
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    constexpr int TPW = (PT_NT + 3) / 4;  // row tiles per wave
-    v4f acc[TPW];
+template <int CIN>
+struct LyShape {
+    static constexpr int KP = (72 * CIN + 15) / 16 * 16;  // 80 or 144
+    static constexpr int KS = KP + 8;                      // LDS row stride (bfloat16)
+};
+
+// LDS-only workgroup barrier: outstanding global loads are not waited for.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// raw storage planes of one spinor
+template <class S>
+struct RawSpinor {
+    typename S::V v[S::NV];
+};
+template <class S>
+__device__ __forceinline__ void raw_load(const void* base, long Vs, uint32_t s, RawSpinor<S>& q) {
 #pragma unroll
-    for (int t = 0; t < TPW; t++) {
-        acc[t] = (v4f){0.f, 0.f, 0.f, 0.f};
-        const int tile = w + 4 * t;
-        if (tile >= PT_NT) continue;
-        const int row = tile * 16 + (lane & 15);
-        for (int ks = 0; ks < kpad / 16; ks++) {
-            const v4s af = *(const v4s*)(As + row * PT_KP + ks * 16 + 4 * (lane >> 4));
-            const v4s bf = ((const v4s*)a.wfrag)[ks * 64 + lane];
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf, acc[t], 0, 0, 0);
-        }
+    for (int k = 0; k < S::NV; k++) q.v[k] = ld_plane<typename S::V>(base, Vs, k, s);
+}
+// the spinor as twelve bfloat16 (re, im) pairs, the order of the half planes
+__device__ __forceinline__ void raw_pairs(const RawSpinor<SF32>& q, uint32_t p[12]) {
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        p[2 * k] = pack2_bf16(q.v[k].x, q.v[k].y);
+        p[2 * k + 1] = pack2_bf16(q.v[k].z, q.v[k].w);
     }
-    __syncthreads();
-    float* Os = (float*)As;  // reuse: PT_ROWS x 16 floats
+}
+__device__ __forceinline__ void raw_pairs(const RawSpinor<SBF16>& q, uint32_t p[12]) {
 #pragma unroll
-    for (int t = 0; t < TPW; t++) {
-        const int tile = w + 4 * t;
-        if (tile >= PT_NT) continue;
-#pragma unroll
-        for (int j = 0; j < 4; j++) Os[(tile * 16 + 4 * (lane >> 4) + j) * 16 + (lane & 15)] = acc[t][j];
+    for (int k = 0; k < 3; k++) {
+        p[4 * k] = q.v[k].x;
+        p[4 * k + 1] = q.v[k].y;
+        p[4 * k + 2] = q.v[k].z;
+        p[4 * k + 3] = q.v[k].w;
     }
-    __syncthreads();
-    for (int item = threadIdx.x; item < PT_TS * a.cout; item += 256) {
-        const int i = item % PT_TS, ch = item / PT_TS;
-        const uint32_t s = site0 + i;
-        if (s >= a.geo.V) continue;
-        cx<float> o[12];
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// acc + a.lo b.lo + a.hi b.hi, bfloat16 pairs, FP32 accumulation (v_dot2_f32_bf16)
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float acc) {
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b), acc, false);
+}
+
+template <int P, class Si, class So, int CIN, int COUT>
+__device__ __forceinline__ void ly_run(const PtArgs& a, uint32_t nrhs, uint32_t site0, int lane, uint16_t* As,
+                                       float* Os) {
+    constexpr int KP = LyShape<CIN>::KP, KS = LyShape<CIN>::KS;
+    constexpr int MU = (P - 1) >> 1;
+    constexpr bool FWD = (P & 1) != 0;
+    constexpr int NT = LY_ROWS / 16;  // MFMA row tiles
+    constexpr int NP = So::NV;        // output planes per field
+    constexpr int CPP = 12 / NP;      // complex components per output plane
+    const Geom& geo = a.geo;
+    const long Vs = geo.Vs;
+    const uint32_t s = site0 + lane;
+    const bool valid = s < geo.V;
+
+    // effective link L = sign * U_mu(x), or sign * U_mu(x-mu)^dag, as bfloat16
+    // pairs: (Re t, Im t) += (psi . LA, psi . LB) with LA = (Re L, -Im L),
+    // LB = (Im L, Re L) for psi = (Re psi, Im psi); zero past the lattice
+    uint32_t LA[3][3], LB[3][3];
 #pragma unroll
-        for (int so = 0; so < 4; so++)
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) LA[i][k] = LB[i][k] = 0u;
+    uint32_t y = s;
+    if (P > 0 && valid) {
+        const Site c = site_coords(geo, s);
+        y = FWD ? nb_fwd(geo, s, c, MU) : nb_bwd(geo, s, c, MU);
+        cx<float> U[3][3];
+        load_link<GF32, float>(a.gauge, Vs, MU, FWD ? s : y, U);
+        const bool flip = MU == 3 && geo.t_bc < 0 && (FWD ? (c.t + 1 == geo.L[3]) : (c.t == 0));
+        const float sg = flip ? -1.f : 1.f;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const cx<float> m = FWD ? cx<float>{sg * U[i][k].re, sg * U[i][k].im}
+                                        : cx<float>{sg * U[k][i].re, -sg * U[k][i].im};
+                LA[i][k] = pack2_bf16(m.re, -m.im);
+                LB[i][k] = pack2_bf16(m.im, m.re);
+            }
+    }
+    // input planes of the current right-hand side; those of the next one are
+    // loaded into the same registers once the current ones are unpacked
+    // (lanes past the lattice keep zeros)
+    RawSpinor<Si> nxt[CIN];
+#pragma unroll
+    for (int b = 0; b < CIN; b++)
+#pragma unroll
+        for (int k = 0; k < Si::NV; k++) nxt[b].v[k] = typename Si::V{};
+    if (valid) {
+#pragma unroll
+        for (int b = 0; b < CIN; b++) raw_load(field_rhs<Si>(a.in, Vs, b), Vs, y, nxt[b]);
+    }
+
+    for (uint32_t r = 0; r < nrhs; r++) {
+        // gather
+#pragma unroll
+        for (int b = 0; b < CIN; b++) {
+            uint32_t psi[12];
+            raw_pairs(nxt[b], psi);
+            if (valid && r + 1 < nrhs) raw_load(field_rhs<Si>(a.in, Vs, (int)((r + 1) * CIN + b)), Vs, y, nxt[b]);
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                const float* src = Os + (c * PT_TS + i) * 16 + (ch * 4 + so) * 2;
-                o[3 * so + c] = {src[0], src[1]};
+                uint32_t q[4];
+#pragma unroll
+                for (int sp = 0; sp < 4; sp++) {
+                    if (P == 0) {
+                        q[sp] = psi[3 * sp + c];
+                    } else {
+                        float tr = 0.f, ti = 0.f;
+#pragma unroll
+                        for (int k = 0; k < 3; k++) {
+                            tr = dot2(psi[3 * sp + k], LA[c][k], tr);
+                            ti = dot2(psi[3 * sp + k], LB[c][k], ti);
+                        }
+                        q[sp] = pack2_bf16(tr, ti);
+                    }
+                }
+                *(uint4*)(As + (c * LY_TS + lane) * KS + (P * CIN + b) * 8) = make_uint4(q[0], q[1], q[2], q[3]);
             }
-        store_spinor<So, float>(field_rhs<So>(a.out, a.geo.Vs, r * a.cout + ch), a.geo.Vs, s, o);
+        }
+        if (KP > 72 * CIN && P == 0 && r == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) *(uint4*)(As + (c * LY_TS + lane) * KS + 72 * CIN) = make_uint4(0, 0, 0, 0);
+        }
+        lds_barrier();
+
+        // mix
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int tt = P + 9 * j;
+            if (tt >= NT) continue;
+            v4f acc = (v4f){0.f, 0.f, 0.f, 0.f};
+            const int row = tt * 16 + (lane & 15);
+#pragma unroll
+            for (int ks = 0; ks < KP / 16; ks++) {
+                const v4s af = *(const v4s*)(As + row * KS + ks * 16 + 4 * (lane >> 4));
+                const v4s bf = ((const v4s*)a.wfrag)[ks * 64 + lane];
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; e++) Os[(tt * 16 + 4 * (lane >> 4) + e) * LY_OS + (lane & 15)] = acc[e];
+        }
+        lds_barrier();
+
+        // store
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int u = P + 9 * j;
+            if (u >= COUT * NP || !valid) continue;
+            const int ch = u / NP, k = u - ch * NP;
+            float val[2 * CPP];
+#pragma unroll
+            for (int q = 0; q < CPP; q++) {
+                const int comp = k * CPP + q, sp = comp / 3, col = comp - 3 * sp;
+                const float* src = Os + (col * LY_TS + lane) * LY_OS + (ch * 4 + sp) * 2;
+                val[2 * q] = src[0];
+                val[2 * q + 1] = src[1];
+            }
+            void* dst = field_rhs<So>(a.out, Vs, (int)(r * COUT + ch));
+            if constexpr (NP == 6) {
+                st_plane(dst, Vs, k, s, make_float4(val[0], val[1], val[2], val[3]));
+            } else {
+                st_plane(dst, Vs, k, s,
+                         make_uint4(pack2_bf16(val[0], val[1]), pack2_bf16(val[2], val[3]),
+                                    pack2_bf16(val[4], val[5]), pack2_bf16(val[6], val[7])));
+            }
+        }
+    }
+}
+
+// Two blocks (18 waves) per compute unit need at most 96 registers per lane,
+// which the bfloat16-input kernels meet without spilling; the FP32-input
+// two-channel kernels (training activations) run one block per unit.
+template <class Si, int CIN>
+constexpr int ly_min_waves() { return (std::is_same<Si, SF32>::value && CIN == 2) ? 1 : 5; }
+
+template <class Si, class So, int CIN, int COUT>
+__global__ __launch_bounds__(LY_THREADS, (ly_min_waves<Si, CIN>())) void k_pt_layer(PtArgs a, uint32_t nrhs) {
+    constexpr int KS = LyShape<CIN>::KS;
+    __shared__ __attribute__((aligned(16))) uint16_t As[LY_ROWS * KS];
+    __shared__ __attribute__((aligned(16))) float Os[LY_ROWS * LY_OS];
+    const uint32_t site0 = xcd_block(blockIdx.x, gridDim.x) * LY_TS;
+    const int lane = threadIdx.x & 63;
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: ly_run<0, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
+    case 1: ly_run<1, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
+    case 2: ly_run<2, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
+    case 3: ly_run<3, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
+    case 4: ly_run<4, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
+    case 5: ly_run<5, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
+    case 6: ly_run<6, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
+    case 7: ly_run<7, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
+    default: ly_run<8, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
     }
 }
 
@@ -266,12 +433,22 @@ __global__ __launch_bounds__(256) void k_pt_loss(Geom geo, const void* y, const 
     }
 }
 
-void launch_pt_layer(hipStream_t st, const PtArgs& a, int in_prec, int nrhs) {
-    dim3 grid((unsigned)((a.geo.V + PT_TS - 1) / PT_TS), (unsigned)nrhs);
-    if (in_prec == P_BF16)
-        hipLaunchKernelGGL((k_pt_layer<SBF16, SF32>), grid, dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_pt_layer<SF32, SF32>), grid, dim3(256), 0, st, a);
+template <class Si, class So>
+static void launch_pt_layer_t(hipStream_t st, const PtArgs& a, int nrhs) {
+    const dim3 grid((unsigned)((a.geo.V + LY_TS - 1) / LY_TS)), blk(LY_THREADS);
+    const uint32_t n = (uint32_t)nrhs;
+    if (a.cin == 1 && a.cout == 1) hipLaunchKernelGGL((k_pt_layer<Si, So, 1, 1>), grid, blk, 0, st, a, n);
+    else if (a.cin == 1) hipLaunchKernelGGL((k_pt_layer<Si, So, 1, 2>), grid, blk, 0, st, a, n);
+    else if (a.cout == 1) hipLaunchKernelGGL((k_pt_layer<Si, So, 2, 1>), grid, blk, 0, st, a, n);
+    else hipLaunchKernelGGL((k_pt_layer<Si, So, 2, 2>), grid, blk, 0, st, a, n);
+}
+
+void launch_pt_layer(hipStream_t st, const PtArgs& a, int in_prec, int out_prec, int nrhs) {
+    const bool ib = in_prec == P_BF16, ob = out_prec == P_BF16;
+    if (ib && ob) launch_pt_layer_t<SBF16, SBF16>(st, a, nrhs);
+    else if (ib) launch_pt_layer_t<SBF16, SF32>(st, a, nrhs);
+    else if (ob) launch_pt_layer_t<SF32, SBF16>(st, a, nrhs);
+    else launch_pt_layer_t<SF32, SF32>(st, a, nrhs);
 }
 
 void launch_pt_wgrad(hipStream_t st, const PtArgs& a, int in_prec, const double* scale, double* grad) {

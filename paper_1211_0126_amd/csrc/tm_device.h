@@ -52,6 +52,17 @@ __device__ __forceinline__ uint32_t f32_to_bf16(float f) {
     return u >> 16;
 }
 __device__ __forceinline__ float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
+// Two floats to a packed pair, low half first, rounded to nearest even: one
+// v_cvt_pk_bf16_f32 / v_cvt_pk_f16_f32 on gfx950.
+typedef float tm_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 tm_bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 tm_f16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack2_bf16(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((tm_f32x2){lo, hi}, tm_bf16x2));
+}
+__device__ __forceinline__ uint32_t pack2_f16(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((tm_f32x2){lo, hi}, tm_f16x2));
+}
 #ifdef TM_F16_ASM_CVT
 __device__ __forceinline__ uint32_t f32_to_f16(float f) {
     uint32_t h;
@@ -201,11 +212,8 @@ __device__ __forceinline__ void store_half_planes(void* base, long Vs, uint32_t 
     for (int k = 0; k < 3; k++) {
         uint32_t w[4];
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            uint32_t lo = BF ? f32_to_bf16(p[4 * k + j].re) : f32_to_f16(p[4 * k + j].re);
-            uint32_t hi = BF ? f32_to_bf16(p[4 * k + j].im) : f32_to_f16(p[4 * k + j].im);
-            w[j] = lo | (hi << 16);
-        }
+        for (int j = 0; j < 4; j++)
+            w[j] = BF ? pack2_bf16(p[4 * k + j].re, p[4 * k + j].im) : pack2_f16(p[4 * k + j].re, p[4 * k + j].im);
         st_plane<uint4, CP>(base, Vs, k, s, make_uint4(w[0], w[1], w[2], w[3]));
     }
 }

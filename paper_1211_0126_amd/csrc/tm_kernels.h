@@ -72,13 +72,13 @@ struct PtArgs {
     int cin, cout;
     int kpad;              // 72 * cin rounded up to 16
     const void* in;        // cin fields (per right-hand side: cin consecutive fields)
-    void* out;             // cout FP32 fields (per right-hand side)
+    void* out;             // cout fields (per right-hand side), FP32 or bfloat16
     const short* wfrag;    // weight fragments [kpad/16][64 lanes][4] bfloat16
     const void* g;         // weight gradient: upstream gradient (cout FP32 fields)
     float* partials;       // weight gradient: [blocks][16][kpad]
 };
 
-void launch_pt_layer(hipStream_t st, const PtArgs& a, int in_prec, int nrhs);
+void launch_pt_layer(hipStream_t st, const PtArgs& a, int in_prec, int out_prec, int nrhs);
 void launch_pt_wgrad(hipStream_t st, const PtArgs& a, int in_prec, const double* scale, double* grad);
 void launch_pt_loss(hipStream_t st, const Geom& g, const void* y, const void* e, int e_prec, void* gout,
                     double* partials, unsigned int* counter, double* scal, int npairs);

@@ -130,8 +130,10 @@ static tm_status install(tm_ctx* ctx, const tm_net_shape* shape, const cplx* W) 
     return upload_fragments(ctx);
 }
 
-// one layer: in (cin fields per rhs, storage in_prec) -> out (cout FP32 fields per rhs)
-static void layer_launch(tm_ctx* ctx, int l, bool adjoint, const void* in, int in_prec, void* out, int nrhs) {
+// one layer: in (cin fields per rhs, storage in_prec) -> out (cout fields per
+// rhs, storage out_prec: FP32 or bfloat16)
+static void layer_launch(tm_ctx* ctx, int l, bool adjoint, const void* in, int in_prec, void* out, int nrhs,
+                         int out_prec = P_F32) {
     NetState* ns = ctx->net;
     PtArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -143,14 +145,16 @@ static void layer_launch(tm_ctx* ctx, int l, bool adjoint, const void* in, int i
     a.in = in;
     a.out = out;
     a.wfrag = adjoint ? ns->frag_adj[l] : ns->frag_fwd[l];
-    launch_pt_layer(ctx->stream, a, in_prec, nrhs);
+    launch_pt_layer(ctx->stream, a, in_prec, out_prec, nrhs);
 }
 
-// out = N(in) or N^dag(in); single fields, nrhs of them; out FP32 native
-tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_prec, void* out) {
+// out = N(in) or N^dag(in); single fields, nrhs of them.  The hidden
+// activations are stored as bfloat16 (the precision the mixing GEMM reads
+// them in); out is written in out_prec.
+tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_prec, void* out, int out_prec) {
     NetState* ns = ctx->net;
     tm_status s = TM_OK;
-    const size_t fb = field_bytes(ctx->geo, P_F32, 2 * nrhs);
+    const size_t fb = field_bytes(ctx->geo, P_BF16, 2 * nrhs);
     void* A = ws_get(ctx, "net_a", fb, &s);
     void* B = ws_get(ctx, "net_b", fb, &s);
     if (s != TM_OK) return s;
@@ -158,23 +162,26 @@ tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_
     int cur_prec = in_prec;
     for (int i = 0; i < ns->nl; i++) {
         const int l = adjoint ? ns->nl - 1 - i : i;
-        void* dst = (i == ns->nl - 1) ? out : ((i % 2 == 0) ? A : B);
+        const bool last = i == ns->nl - 1;
+        void* dst = last ? out : ((i % 2 == 0) ? A : B);
+        const int dst_prec = last ? out_prec : P_BF16;
         prof_begin(ctx, TM_KC_OTHER);
-        layer_launch(ctx, l, adjoint, cur, cur_prec, dst, nrhs);
+        layer_launch(ctx, l, adjoint, cur, cur_prec, dst, nrhs, dst_prec);
         prof_end(ctx, TM_KC_OTHER, 0.0);
         cur = dst;
-        cur_prec = P_F32;
+        cur_prec = dst_prec;
     }
     TM_HIP(hipGetLastError());
     return TM_OK;
 }
 
+// z = N(N^dag(r)), r and z FP32, the middle field bfloat16
 tm_status net_precondition(tm_ctx* ctx, int nrhs, const void* r, void* z) {
     tm_status s = TM_OK;
-    void* tmp = ws_get(ctx, "net_mid", field_bytes(ctx->geo, P_F32, nrhs), &s);
+    void* tmp = ws_get(ctx, "net_mid", field_bytes(ctx->geo, P_BF16, nrhs), &s);
     if (s != TM_OK) return s;
-    if ((s = net_apply(ctx, true, nrhs, r, P_F32, tmp)) != TM_OK) return s;
-    return net_apply(ctx, false, nrhs, tmp, P_F32, z);
+    if ((s = net_apply(ctx, true, nrhs, r, P_F32, tmp, P_BF16)) != TM_OK) return s;
+    return net_apply(ctx, false, nrhs, tmp, P_BF16, z, P_F32);
 }
 
 bool net_installed(const tm_ctx* ctx) { return ctx->net != nullptr; }
@@ -324,7 +331,7 @@ tm_status tm_precond_apply(tm_ctx* ctx, int32_t adjoint, int32_t nrhs, const dou
     void* b = ws_get(ctx, "pa_out", fb, &s);
     if (s != TM_OK) return s;
     launch_c128_to_native(ctx->stream, ctx->geo, P_F32, nrhs, in_dev, a);
-    if ((s = net_apply(ctx, adjoint != 0, nrhs, a, P_F32, b)) != TM_OK) return s;
+    if ((s = net_apply(ctx, adjoint != 0, nrhs, a, P_F32, b, P_F32)) != TM_OK) return s;
     launch_native_to_c128(ctx->stream, ctx->geo, P_F32, nrhs, b, out_dev);
     TM_HIP(hipGetLastError());
     return TM_OK;
