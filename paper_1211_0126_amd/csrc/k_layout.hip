@@ -112,7 +112,8 @@ void launch_c128_to_native(hipStream_t st, const Geom& g, int prec, int nrhs, co
 }
 
 // canonical complex128 (device) -> native F64 (full links) and F32 (rows 0, 1)
-__global__ __launch_bounds__(256) void k_gauge_convert(Geom geo, const double2* canon, double2* g64, float4* g32) {
+__global__ __launch_bounds__(256) void k_gauge_convert(Geom geo, const double2* canon, double2* g64, float4* g32,
+                                                       uint4* gbf) {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     const int mu = blockIdx.y;
     if (s >= geo.V) return;
@@ -124,11 +125,19 @@ __global__ __launch_bounds__(256) void k_gauge_convert(Geom geo, const double2* 
     for (int k = 0; k < 3; k++)
         g32[((size_t)mu * 3 + k) * Vs + s] =
             make_float4((float)u[2 * k].x, (float)u[2 * k].y, (float)u[2 * k + 1].x, (float)u[2 * k + 1].y);
+    // bfloat16 pairs: entries 0-3, 4-7 and 8 (the rest of the last plane zero)
+    uint32_t w[12];
+#pragma unroll
+    for (int k = 0; k < 12; k++) w[k] = k < 9 ? pack2_bf16((float)u[k].x, (float)u[k].y) : 0u;
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+        gbf[((size_t)mu * 3 + k) * Vs + s] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
 }
 
-void launch_gauge_convert(hipStream_t st, const Geom& g, const double* canon, void* g64, void* g32) {
+void launch_gauge_convert(hipStream_t st, const Geom& g, const double* canon, void* g64, void* g32, void* gbf) {
     dim3 grid((unsigned)((g.V + 255) / 256), 4);
-    hipLaunchKernelGGL(k_gauge_convert, grid, dim3(256), 0, st, g, (const double2*)canon, (double2*)g64, (float4*)g32);
+    hipLaunchKernelGGL(k_gauge_convert, grid, dim3(256), 0, st, g, (const double2*)canon, (double2*)g64, (float4*)g32,
+                       (uint4*)gbf);
 }
 
 // Z4 sources (Eq. 1) in native storage S, one per id

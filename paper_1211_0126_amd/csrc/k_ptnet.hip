@@ -116,62 +116,44 @@ __device__ __forceinline__ void gather_tile(const PtArgs& a, uint32_t site0, uin
 }
 
 // ---------------------------------------------------------------------------
-// Layer application.  A block owns 64 consecutive sites and loops over the
-// right-hand sides; it runs nine waves, wave p handling path p with one lane
-// per site.  The wave's effective link (sign and adjoint folded in) is loaded
-// once and kept in registers for all right-hand sides, and the input planes
-// of the next right-hand side are loaded while the current one is
-// transported, mixed and stored.  Per right-hand side:
-//   gather: the lane's CIN transports, packed to bfloat16, one 16-byte LDS
-//           store per colour into the tile (rows (colour, site), columns
-//           (path, channel, spin, re/im), row stride kpad + 8 bfloat16 so the
-//           16-byte stores and the 8-byte MFMA operand reads are conflict-free);
-//   mix:    the twelve 16-row MFMA tiles dealt to the waves, the FP32 result
-//           staged in its own LDS array;
-//   store:  one (channel, plane) of 16-byte elements per wave and pass.
-// The barriers wait for LDS traffic only, so the prefetched global loads
-// stay in flight across them.
+// Layer application.  Every wave is independent: it owns 16 consecutive
+// sites and loops over the right-hand sides.  The mixing is computed with the
+// sites on the N side of the matrix cores,
+//     D[out][site] += Wt[out][k] T[k][site]   (v_mfma_f32_16x16x16_bf16),
+// one product per colour, so the transports T go from registers straight into
+// the B operand: lane l = 16 g + i holds, for site i, the four k = 4g..4g+3 of
+// the current k-step, i.e. one (path, channel) and the spin pair 2(g&1),
+// 2(g&1)+1.  Each lane therefore transports a half spinor per k-step (18
+// complex multiply-adds as bfloat16 dot2 with FP32 accumulation); the link
+// comes from a bfloat16-pair copy of the gauge field.  The D layout gives
+// lane l the output channel g>>1 and the same spin pair, which it writes as
+// its half of the output spinor.  No LDS and no barriers.
+// K-steps: for two input channels step ks is path ks (lane channel g>>1); for
+// one channel step ks covers paths 2ks and 2ks+1 (lane path 2ks + (g>>1)),
+// the tenth "path" being zero padding.
 // ---------------------------------------------------------------------------
-constexpr int LY_TS = 64;
-constexpr int LY_ROWS = 3 * LY_TS;
-constexpr int LY_THREADS = 9 * 64;
-constexpr int LY_OS = 20;  // staging row stride (floats): conflict-free MFMA result writes
+constexpr int LY_TS = 64;         // sites per block: four waves of 16
+constexpr int LY_THREADS = 256;
 
-template <int CIN>
-struct LyShape {
-    static constexpr int KP = (72 * CIN + 15) / 16 * 16;  // 80 or 144
-    static constexpr int KS = KP + 8;                      // LDS row stride (bfloat16)
-};
-
-// LDS-only workgroup barrier: outstanding global loads are not waited for.
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
-// raw storage planes of one spinor
-template <class S>
-struct RawSpinor {
-    typename S::V v[S::NV];
-};
-template <class S>
-__device__ __forceinline__ void raw_load(const void* base, long Vs, uint32_t s, RawSpinor<S>& q) {
-#pragma unroll
-    for (int k = 0; k < S::NV; k++) q.v[k] = ld_plane<typename S::V>(base, Vs, k, s);
+__device__ __forceinline__ uint4 ldv128(const void* base, uint32_t voff) {
+    return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rsrc_of(base), voff, 0, 0));
 }
-// the spinor as twelve bfloat16 (re, im) pairs, the order of the half planes
-__device__ __forceinline__ void raw_pairs(const RawSpinor<SF32>& q, uint32_t p[12]) {
-#pragma unroll
-    for (int k = 0; k < 6; k++) {
-        p[2 * k] = pack2_bf16(q.v[k].x, q.v[k].y);
-        p[2 * k + 1] = pack2_bf16(q.v[k].z, q.v[k].w);
-    }
+__device__ __forceinline__ uint2 ldv64(const void* base, uint32_t voff) {
+    return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rsrc_of(base), voff, 0, 0));
 }
-__device__ __forceinline__ void raw_pairs(const RawSpinor<SBF16>& q, uint32_t p[12]) {
-#pragma unroll
-    for (int k = 0; k < 3; k++) {
-        p[4 * k] = q.v[k].x;
-        p[4 * k + 1] = q.v[k].y;
-        p[4 * k + 2] = q.v[k].z;
-        p[4 * k + 3] = q.v[k].w;
-    }
+__device__ __forceinline__ uint32_t ldv32(const void* base, uint32_t voff) {
+    return __builtin_amdgcn_raw_buffer_load_b32(rsrc_of(base), voff, 0, 0);
+}
+// (see st_plane for the wait states after a 128-bit store)
+__device__ __forceinline__ void stv128(void* base, uint32_t voff, uint4 val) {
+    using V4 = unsigned int __attribute__((ext_vector_type(4)));
+    const V4 v = __builtin_bit_cast(V4, val);
+    __builtin_amdgcn_raw_buffer_store_b128(v, rsrc_of(base), voff, 0, 0);
+    asm volatile("s_nop 4" ::"v"(v) : "memory");
+}
+__device__ __forceinline__ void stv64(void* base, uint32_t voff, uint2 val) {
+    using V2 = unsigned int __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, val), rsrc_of(base), voff, 0, 0);
 }
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -179,160 +161,247 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float acc) {
     return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b), acc, false);
 }
+__device__ __forceinline__ uint32_t swap16(uint32_t x) { return __builtin_amdgcn_alignbit(x, x, 16); }
 
-template <int P, class Si, class So, int CIN, int COUT>
-__device__ __forceinline__ void ly_run(const PtArgs& a, uint32_t nrhs, uint32_t site0, int lane, uint16_t* As,
-                                       float* Os) {
-    constexpr int KP = LyShape<CIN>::KP, KS = LyShape<CIN>::KS;
-    constexpr int MU = (P - 1) >> 1;
-    constexpr bool FWD = (P & 1) != 0;
-    constexpr int NT = LY_ROWS / 16;  // MFMA row tiles
-    constexpr int NP = So::NV;        // output planes per field
-    constexpr int CPP = 12 / NP;      // complex components per output plane
-    const Geom& geo = a.geo;
-    const long Vs = geo.Vs;
-    const uint32_t s = site0 + lane;
-    const bool valid = s < geo.V;
-
-    // effective link L = sign * U_mu(x), or sign * U_mu(x-mu)^dag, as bfloat16
-    // pairs: (Re t, Im t) += (psi . LA, psi . LB) with LA = (Re L, -Im L),
-    // LB = (Im L, Re L) for psi = (Re psi, Im psi); zero past the lattice
-    uint32_t LA[3][3], LB[3][3];
+// The lane's half spinor (components 6h .. 6h+5, spins 2h and 2h+1) of
+// channel b at site y, as bfloat16 (re, im) pairs.
+__device__ __forceinline__ void half_spinor(const void* f, uint32_t PB, int b, uint32_t y, int h, uint32_t q[6],
+                                            SBF16) {
+    // planes of 4 components: h = 0 -> plane 0 + low half of plane 1; h = 1 -> high half of plane 1 + plane 2
+    const uint32_t base = (y << 4) + (uint32_t)b * 3u * PB;
+    const uint4 full = ldv128(f, base + (h ? 2u * PB : 0u));
+    const uint2 half = ldv64(f, base + PB + (h ? 8u : 0u));
+    q[0] = h ? half.x : full.x;
+    q[1] = h ? half.y : full.y;
+    q[2] = h ? full.x : full.z;
+    q[3] = h ? full.y : full.w;
+    q[4] = h ? full.z : half.x;
+    q[5] = h ? full.w : half.y;
+}
+__device__ __forceinline__ void half_spinor(const void* f, uint32_t PB, int b, uint32_t y, int h, uint32_t q[6],
+                                            SF32) {
+    // planes of 2 components: planes 3h, 3h+1, 3h+2
+    const uint32_t base = (y << 4) + (uint32_t)b * 6u * PB + (uint32_t)h * 3u * PB;
 #pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int k = 0; k < 3; k++) LA[i][k] = LB[i][k] = 0u;
-    uint32_t y = s;
-    if (P > 0 && valid) {
-        const Site c = site_coords(geo, s);
-        y = FWD ? nb_fwd(geo, s, c, MU) : nb_bwd(geo, s, c, MU);
-        cx<float> U[3][3];
-        load_link<GF32, float>(a.gauge, Vs, MU, FWD ? s : y, U);
-        const bool flip = MU == 3 && geo.t_bc < 0 && (FWD ? (c.t + 1 == geo.L[3]) : (c.t == 0));
-        const float sg = flip ? -1.f : 1.f;
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                const cx<float> m = FWD ? cx<float>{sg * U[i][k].re, sg * U[i][k].im}
-                                        : cx<float>{sg * U[k][i].re, -sg * U[k][i].im};
-                LA[i][k] = pack2_bf16(m.re, -m.im);
-                LB[i][k] = pack2_bf16(m.im, m.re);
-            }
-    }
-    // input planes of the current right-hand side; those of the next one are
-    // loaded into the same registers once the current ones are unpacked
-    // (lanes past the lattice keep zeros)
-    RawSpinor<Si> nxt[CIN];
-#pragma unroll
-    for (int b = 0; b < CIN; b++)
-#pragma unroll
-        for (int k = 0; k < Si::NV; k++) nxt[b].v[k] = typename Si::V{};
-    if (valid) {
-#pragma unroll
-        for (int b = 0; b < CIN; b++) raw_load(field_rhs<Si>(a.in, Vs, b), Vs, y, nxt[b]);
-    }
-
-    for (uint32_t r = 0; r < nrhs; r++) {
-        // gather
-#pragma unroll
-        for (int b = 0; b < CIN; b++) {
-            uint32_t psi[12];
-            raw_pairs(nxt[b], psi);
-            if (valid && r + 1 < nrhs) raw_load(field_rhs<Si>(a.in, Vs, (int)((r + 1) * CIN + b)), Vs, y, nxt[b]);
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                uint32_t q[4];
-#pragma unroll
-                for (int sp = 0; sp < 4; sp++) {
-                    if (P == 0) {
-                        q[sp] = psi[3 * sp + c];
-                    } else {
-                        float tr = 0.f, ti = 0.f;
-#pragma unroll
-                        for (int k = 0; k < 3; k++) {
-                            tr = dot2(psi[3 * sp + k], LA[c][k], tr);
-                            ti = dot2(psi[3 * sp + k], LB[c][k], ti);
-                        }
-                        q[sp] = pack2_bf16(tr, ti);
-                    }
-                }
-                *(uint4*)(As + (c * LY_TS + lane) * KS + (P * CIN + b) * 8) = make_uint4(q[0], q[1], q[2], q[3]);
-            }
-        }
-        if (KP > 72 * CIN && P == 0 && r == 0) {
-#pragma unroll
-            for (int c = 0; c < 3; c++) *(uint4*)(As + (c * LY_TS + lane) * KS + 72 * CIN) = make_uint4(0, 0, 0, 0);
-        }
-        lds_barrier();
-
-        // mix
-#pragma unroll
-        for (int j = 0; j < 2; j++) {
-            const int tt = P + 9 * j;
-            if (tt >= NT) continue;
-            v4f acc = (v4f){0.f, 0.f, 0.f, 0.f};
-            const int row = tt * 16 + (lane & 15);
-#pragma unroll
-            for (int ks = 0; ks < KP / 16; ks++) {
-                const v4s af = *(const v4s*)(As + row * KS + ks * 16 + 4 * (lane >> 4));
-                const v4s bf = ((const v4s*)a.wfrag)[ks * 64 + lane];
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf, acc, 0, 0, 0);
-            }
-#pragma unroll
-            for (int e = 0; e < 4; e++) Os[(tt * 16 + 4 * (lane >> 4) + e) * LY_OS + (lane & 15)] = acc[e];
-        }
-        lds_barrier();
-
-        // store
-#pragma unroll
-        for (int j = 0; j < 2; j++) {
-            const int u = P + 9 * j;
-            if (u >= COUT * NP || !valid) continue;
-            const int ch = u / NP, k = u - ch * NP;
-            float val[2 * CPP];
-#pragma unroll
-            for (int q = 0; q < CPP; q++) {
-                const int comp = k * CPP + q, sp = comp / 3, col = comp - 3 * sp;
-                const float* src = Os + (col * LY_TS + lane) * LY_OS + (ch * 4 + sp) * 2;
-                val[2 * q] = src[0];
-                val[2 * q + 1] = src[1];
-            }
-            void* dst = field_rhs<So>(a.out, Vs, (int)(r * COUT + ch));
-            if constexpr (NP == 6) {
-                st_plane(dst, Vs, k, s, make_float4(val[0], val[1], val[2], val[3]));
-            } else {
-                st_plane(dst, Vs, k, s,
-                         make_uint4(pack2_bf16(val[0], val[1]), pack2_bf16(val[2], val[3]),
-                                    pack2_bf16(val[4], val[5]), pack2_bf16(val[6], val[7])));
-            }
-        }
+    for (int j = 0; j < 3; j++) {
+        const float4 v = __builtin_bit_cast(float4, ldv128(f, base + (uint32_t)j * PB));
+        q[2 * j] = pack2_bf16(v.x, v.y);
+        q[2 * j + 1] = pack2_bf16(v.z, v.w);
     }
 }
 
-// Two blocks (18 waves) per compute unit need at most 96 registers per lane,
-// which the bfloat16-input kernels meet without spilling; the FP32-input
-// two-channel kernels (training activations) run one block per unit.
-template <class Si, int CIN>
-constexpr int ly_min_waves() { return (std::is_same<Si, SF32>::value && CIN == 2) ? 1 : 5; }
+// Per-lane description of the (path, channel) of one k-step.
+struct LyPath {
+    uint32_t y;      // neighbour site
+    uint32_t lsite;  // site of the link
+    uint32_t lplane; // byte offset of the link's first plane
+    uint32_t flip;   // 0x80008000 where the time-boundary sign applies
+    bool fwd, ident, pad;
+};
+
+template <int P>
+__device__ __forceinline__ LyPath ly_path(const uint32_t ys[9], uint32_t s, uint32_t flip_f, uint32_t flip_b,
+                                          uint32_t PB) {
+    LyPath d;
+    d.pad = P >= 9;
+    d.ident = P == 0;
+    d.y = (P >= 1 && P <= 8) ? ys[P] : s;
+    d.fwd = (P & 1) != 0;
+    const int mu = (P >= 1 && P <= 8) ? (P - 1) >> 1 : 0;  // identity and padding read direction 0's link
+    d.lsite = d.fwd || P == 0 ? s : d.y;
+    d.lplane = (uint32_t)(mu * 3) * PB;
+    d.flip = (P == 7) ? flip_f : (P == 8) ? flip_b : 0u;
+    return d;
+}
+__device__ __forceinline__ LyPath ly_select(bool hi, const LyPath& a, const LyPath& b) {
+    LyPath d;
+    d.y = hi ? b.y : a.y;
+    d.lsite = hi ? b.lsite : a.lsite;
+    d.lplane = hi ? b.lplane : a.lplane;
+    d.flip = hi ? b.flip : a.flip;
+    d.fwd = hi ? b.fwd : a.fwd;
+    d.ident = hi ? b.ident : a.ident;
+    d.pad = hi ? b.pad : a.pad;
+    return d;
+}
+
+// The link of a k-step, oriented and as bfloat16 pairs: m[c][k] = U[c][k]
+// (forward) or U[k][c] (backward, to be used with the conjugating operand
+// signs below).
+__device__ __forceinline__ void ly_link(const PtArgs& a, uint32_t PB, const LyPath& d, uint32_t m[9]) {
+    const uint32_t lb = (d.lsite << 4) + d.lplane;
+    const uint4 u0 = ldv128(a.gaugebf, lb);
+    const uint4 u1 = ldv128(a.gaugebf, lb + PB);
+    const uint32_t u8 = ldv32(a.gaugebf, lb + 2u * PB);
+    const uint32_t u[9] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w, u8};
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) m[3 * c + k] = d.fwd ? u[3 * c + k] : u[3 * k + c];
+}
+
+// B operand of one k-step and one right-hand side for the three colours: the
+// lane's two spins of the transported (or, for the identity path, the plain)
+// half spinor.
+//   forward:  Re t = (Re, -Im) psi . U,   Im t = (Im, Re) psi . U
+//   backward: Re t = psi . U^T,           Im t = (Im, -Re) psi . U^T
+template <class Si>
+__device__ __forceinline__ void ly_operand(const void* in, uint32_t PB, int h, int b, const LyPath& d,
+                                           const uint32_t m[9], uint32_t B[3][2]) {
+    uint32_t q[6];
+    half_spinor(in, PB, b, d.y, h, q, Si{});
+    const uint32_t s1 = d.fwd ? 0x80000000u : 0u, s2 = d.fwd ? 0u : 0x80000000u;
+    uint32_t a1[6], a2[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        a1[j] = q[j] ^ s1;
+        a2[j] = swap16(q[j]) ^ s2;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            float tr = dot2(a1[3 * t], m[3 * c], 0.f), ti = dot2(a2[3 * t], m[3 * c], 0.f);
+            tr = dot2(a1[3 * t + 1], m[3 * c + 1], tr);
+            ti = dot2(a2[3 * t + 1], m[3 * c + 1], ti);
+            tr = dot2(a1[3 * t + 2], m[3 * c + 2], tr);
+            ti = dot2(a2[3 * t + 2], m[3 * c + 2], ti);
+            const uint32_t tv = pack2_bf16(tr, ti) ^ d.flip;
+            B[c][t] = d.pad ? 0u : d.ident ? q[3 * t + c] : tv;
+        }
+}
+
+// Right-hand sides are processed in chunks of LY_RC: each k-step's link is
+// loaded once and applied to all of the chunk's right-hand sides, whose MFMA
+// accumulators stay live.  A block handles TM_LY_CHUNKS_RC right-hand sides of
+// its tile, and the grid runs chunk-major, so the lattice is swept once per
+// group of right-hand sides and the time neighbours of a sweep stay in cache.
+// (Measured on 24^3 x 48 with 8 right-hand sides: chunks of 2 and 2 per block
+// are 5-15% faster than 1, 4 or all right-hand sides per block.)
+#ifndef TM_LY_RC
+#define TM_LY_RC 2
+#endif
+constexpr int LY_RC = TM_LY_RC;
+#ifndef TM_LY_CHUNKS_RC
+#define TM_LY_CHUNKS_RC 2
+#endif
 
 template <class Si, class So, int CIN, int COUT>
-__global__ __launch_bounds__(LY_THREADS, (ly_min_waves<Si, CIN>())) void k_pt_layer(PtArgs a, uint32_t nrhs) {
-    constexpr int KS = LyShape<CIN>::KS;
-    __shared__ __attribute__((aligned(16))) uint16_t As[LY_ROWS * KS];
-    __shared__ __attribute__((aligned(16))) float Os[LY_ROWS * LY_OS];
-    const uint32_t site0 = xcd_block(blockIdx.x, gridDim.x) * LY_TS;
-    const int lane = threadIdx.x & 63;
-    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
-    case 0: ly_run<0, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
-    case 1: ly_run<1, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
-    case 2: ly_run<2, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
-    case 3: ly_run<3, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
-    case 4: ly_run<4, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
-    case 5: ly_run<5, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
-    case 6: ly_run<6, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
-    case 7: ly_run<7, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
-    default: ly_run<8, Si, So, CIN, COUT>(a, nrhs, site0, lane, As, Os); break;
+__global__ __launch_bounds__(LY_THREADS) void k_pt_layer(PtArgs a, uint32_t nrhs) {
+    constexpr int NKS = (9 * CIN + 1) / 2;  // k-steps of 16
+    const Geom& geo = a.geo;
+    const long Vs = geo.Vs;
+    const uint32_t PB = (uint32_t)Vs * 16u;  // plane bytes
+    const int lane = threadIdx.x & 63, g = lane >> 4, h = g & 1;
+    // blocks: (right-hand-side chunk, site tile), chunk slowest
+    const uint32_t ntile = (geo.V + LY_TS - 1) / LY_TS;
+    const uint32_t L = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t chunk = L / ntile, tile = L - chunk * ntile;
+    const uint32_t s0 = tile * LY_TS + (threadIdx.x >> 6) * 16 + (lane & 15);
+    const bool valid = s0 < geo.V;
+    const uint32_t s = valid ? s0 : 0u;  // lanes past the lattice compute site 0 and store nothing
+
+    uint32_t ys[9];
+    uint32_t flip_f = 0, flip_b = 0;
+    {
+        const Site c = site_coords(geo, s);
+        ys[0] = s;
+#pragma unroll
+        for (int mu = 0; mu < 4; mu++) {
+            ys[1 + 2 * mu] = nb_fwd(geo, s, c, mu);
+            ys[2 + 2 * mu] = nb_bwd(geo, s, c, mu);
+        }
+        if (geo.t_bc < 0) {
+            flip_f = (c.t + 1 == geo.L[3]) ? 0x80008000u : 0u;
+            flip_b = (c.t == 0) ? 0x80008000u : 0u;
+        }
+    }
+    v4s wf[NKS];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ks++) wf[ks] = ((const v4s*)a.wfrag)[ks * 64 + lane];
+
+    const uint32_t r_end = (chunk + 1) * (uint32_t)TM_LY_CHUNKS_RC < nrhs ? (chunk + 1) * (uint32_t)TM_LY_CHUNKS_RC : nrhs;
+    for (uint32_t r0 = chunk * (uint32_t)TM_LY_CHUNKS_RC; r0 < r_end; r0 += LY_RC) {
+        const uint32_t nrhs_left = r_end;
+        const uint32_t nr = nrhs_left - r0 < (uint32_t)LY_RC ? nrhs_left - r0 : (uint32_t)LY_RC;
+        v4f D[LY_RC][3];
+#pragma unroll
+        for (int j = 0; j < LY_RC; j++)
+#pragma unroll
+            for (int c = 0; c < 3; c++) D[j][c] = (v4f){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < NKS; ks++) {
+            LyPath d;
+            int b;
+            if constexpr (CIN == 2) {
+                d = ks == 0 ? ly_path<0>(ys, s, flip_f, flip_b, PB)
+                  : ks == 1 ? ly_path<1>(ys, s, flip_f, flip_b, PB)
+                  : ks == 2 ? ly_path<2>(ys, s, flip_f, flip_b, PB)
+                  : ks == 3 ? ly_path<3>(ys, s, flip_f, flip_b, PB)
+                  : ks == 4 ? ly_path<4>(ys, s, flip_f, flip_b, PB)
+                  : ks == 5 ? ly_path<5>(ys, s, flip_f, flip_b, PB)
+                  : ks == 6 ? ly_path<6>(ys, s, flip_f, flip_b, PB)
+                  : ks == 7 ? ly_path<7>(ys, s, flip_f, flip_b, PB)
+                            : ly_path<8>(ys, s, flip_f, flip_b, PB);
+                b = g >> 1;
+            } else {
+                const bool hi = (g >> 1) != 0;
+                d = ks == 0 ? ly_select(hi, ly_path<0>(ys, s, flip_f, flip_b, PB), ly_path<1>(ys, s, flip_f, flip_b, PB))
+                  : ks == 1 ? ly_select(hi, ly_path<2>(ys, s, flip_f, flip_b, PB), ly_path<3>(ys, s, flip_f, flip_b, PB))
+                  : ks == 2 ? ly_select(hi, ly_path<4>(ys, s, flip_f, flip_b, PB), ly_path<5>(ys, s, flip_f, flip_b, PB))
+                  : ks == 3 ? ly_select(hi, ly_path<6>(ys, s, flip_f, flip_b, PB), ly_path<7>(ys, s, flip_f, flip_b, PB))
+                            : ly_select(hi, ly_path<8>(ys, s, flip_f, flip_b, PB), ly_path<9>(ys, s, flip_f, flip_b, PB));
+                b = 0;
+            }
+            uint32_t m[9];
+            ly_link(a, PB, d, m);
+#pragma unroll
+            for (int j = 0; j < LY_RC; j++) {
+                if ((uint32_t)j >= nr) break;
+                uint32_t B[3][2];
+                ly_operand<Si>(field_rhs<Si>(a.in, Vs, (int)((r0 + j) * CIN)), PB, h, b, d, m, B);
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const v4s bo = __builtin_bit_cast(v4s, make_uint2(B[c][0], B[c][1]));
+                    D[j][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[ks], bo, D[j][c], 0, 0, 0);
+                }
+            }
+        }
+        // lane holds channel g>>1, spins 2h and 2h+1: component 6h + 3t + c is
+        // (D[c][2t], D[c][2t + 1])
+        const int ch = g >> 1;
+        if (!valid || ch >= COUT) continue;
+#pragma unroll
+        for (int j = 0; j < LY_RC; j++) {
+            if ((uint32_t)j >= nr) break;
+            void* out = field_rhs<So>(a.out, Vs, (int)((r0 + j) * COUT));
+            float o[12];
+#pragma unroll
+            for (int t = 0; t < 2; t++)
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    o[2 * (3 * t + c)] = D[j][c][2 * t];
+                    o[2 * (3 * t + c) + 1] = D[j][c][2 * t + 1];
+                }
+            if constexpr (std::is_same<So, SF32>::value) {
+                const uint32_t base = (s << 4) + (uint32_t)ch * 6u * PB + (uint32_t)h * 3u * PB;
+#pragma unroll
+                for (int q = 0; q < 3; q++)
+                    stv128(out, base + (uint32_t)q * PB,
+                           make_uint4(__float_as_uint(o[4 * q]), __float_as_uint(o[4 * q + 1]),
+                                      __float_as_uint(o[4 * q + 2]), __float_as_uint(o[4 * q + 3])));
+            } else {
+                uint32_t w[6];
+#pragma unroll
+                for (int q = 0; q < 6; q++) w[q] = pack2_bf16(o[2 * q], o[2 * q + 1]);
+                const uint32_t base = (s << 4) + (uint32_t)ch * 3u * PB;
+                // h = 0: components 0-3 -> plane 0, 4-5 -> low half of plane 1
+                // h = 1: components 6-7 -> high half of plane 1, 8-11 -> plane 2
+                stv128(out, base + (h ? 2u * PB : 0u),
+                       h ? make_uint4(w[2], w[3], w[4], w[5]) : make_uint4(w[0], w[1], w[2], w[3]));
+                stv64(out, base + PB + (h ? 8u : 0u), h ? make_uint2(w[0], w[1]) : make_uint2(w[4], w[5]));
+            }
+        }
     }
 }
 
@@ -435,7 +504,8 @@ __global__ __launch_bounds__(256) void k_pt_loss(Geom geo, const void* y, const 
 
 template <class Si, class So>
 static void launch_pt_layer_t(hipStream_t st, const PtArgs& a, int nrhs) {
-    const dim3 grid((unsigned)((a.geo.V + LY_TS - 1) / LY_TS)), blk(LY_THREADS);
+    const unsigned nchunk = (unsigned)((nrhs + TM_LY_CHUNKS_RC - 1) / TM_LY_CHUNKS_RC);
+    const dim3 grid((unsigned)((a.geo.V + LY_TS - 1) / LY_TS) * nchunk), blk(LY_THREADS);
     const uint32_t n = (uint32_t)nrhs;
     if (a.cin == 1 && a.cout == 1) hipLaunchKernelGGL((k_pt_layer<Si, So, 1, 1>), grid, blk, 0, st, a, n);
     else if (a.cin == 1) hipLaunchKernelGGL((k_pt_layer<Si, So, 1, 2>), grid, blk, 0, st, a, n);

@@ -214,6 +214,7 @@ tm_status tm_destroy(tm_ctx* ctx) {
         if (kv.second.p) (void)hipFree(kv.second.p);
     if (ctx->gauge64) (void)hipFree(ctx->gauge64);
     if (ctx->gauge32) (void)hipFree(ctx->gauge32);
+    if (ctx->gaugebf) (void)hipFree(ctx->gaugebf);
     if (ctx->gam_dev) (void)hipFree(ctx->gam_dev);
     if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
     net_release(ctx);
@@ -232,11 +233,12 @@ tm_status tm_gauge_load(tm_ctx* ctx, const double* links_host) {
     const size_t canon_bytes = (size_t)g.V * 4 * 9 * 16;
     if (!ctx->gauge64) TM_HIP(hipMalloc(&ctx->gauge64, (size_t)4 * 9 * 16 * g.Vs));
     if (!ctx->gauge32) TM_HIP(hipMalloc(&ctx->gauge32, (size_t)4 * 3 * 16 * g.Vs));
+    if (!ctx->gaugebf) TM_HIP(hipMalloc(&ctx->gaugebf, (size_t)4 * 3 * 16 * g.Vs));
     void* tmp = nullptr;
     TM_HIP(hipMalloc(&tmp, canon_bytes));
     hipError_t e = hipMemcpyAsync(tmp, links_host, canon_bytes, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) {
-        launch_gauge_convert(ctx->stream, g, (const double*)tmp, ctx->gauge64, ctx->gauge32);
+        launch_gauge_convert(ctx->stream, g, (const double*)tmp, ctx->gauge64, ctx->gauge32, ctx->gaugebf);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);

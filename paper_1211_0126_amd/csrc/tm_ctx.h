@@ -20,6 +20,7 @@ struct tm_ctx {
 
     void* gauge64 = nullptr;  // double2 [4][9][Vs]
     void* gauge32 = nullptr;  // float4  [4][3][Vs]
+    void* gaugebf = nullptr;  // uint4   [4][3][Vs]: bfloat16 (re, im) pairs of the 9 entries, for the network
     bool gauge_loaded = false;
 
     struct Buf {

@@ -68,7 +68,8 @@ void launch_fcg_p(hipStream_t st, const FcgArgs& a);
 // One transport layer of the learned preconditioner (cin, cout <= 2).
 struct PtArgs {
     Geom geo;
-    const void* gauge;     // FP32 native links
+    const void* gauge;     // FP32 native links (weight gradient)
+    const void* gaugebf;   // bfloat16-pair links (layer application)
     int cin, cout;
     int kpad;              // 72 * cin rounded up to 16
     const void* in;        // cin fields (per right-hand side: cin consecutive fields)
@@ -117,7 +118,7 @@ void launch_field_convert(hipStream_t st, const Geom& g, int prec, int nrhs, boo
                           void* out);
 void launch_native_to_c128(hipStream_t st, const Geom& g, int prec, int nrhs, const void* in, double* out);
 void launch_c128_to_native(hipStream_t st, const Geom& g, int prec, int nrhs, const double* in, void* out);
-void launch_gauge_convert(hipStream_t st, const Geom& g, const double* canon, void* g64, void* g32);
+void launch_gauge_convert(hipStream_t st, const Geom& g, const double* canon, void* g64, void* g32, void* gbf);
 void launch_noise_native(hipStream_t st, const Geom& g, int prec, uint64_t seed_mixed, const uint64_t* ids, int nrhs,
                          void* out);
 void launch_noise_c128(hipStream_t st, const Geom& g, uint64_t seed_mixed, const uint64_t* ids, int nrhs, double* out);

@@ -139,6 +139,7 @@ static void layer_launch(tm_ctx* ctx, int l, bool adjoint, const void* in, int i
     std::memset(&a, 0, sizeof(a));
     a.geo = ctx->geo;
     a.gauge = ctx->gauge32;
+    a.gaugebf = ctx->gaugebf;
     a.cin = adjoint ? ns->widths[l + 1] : ns->widths[l];
     a.cout = adjoint ? ns->widths[l] : ns->widths[l + 1];
     a.kpad = adjoint ? ns->kpad_adj[l] : ns->kpad_fwd[l];
