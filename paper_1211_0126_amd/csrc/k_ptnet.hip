@@ -297,6 +297,13 @@ __global__ __launch_bounds__(LY_THREADS) void k_pt_layer(PtArgs a, uint32_t nrhs
     const uint32_t ntile = (geo.V + LY_TS - 1) / LY_TS;
     const uint32_t L = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t chunk = L / ntile, tile = L - chunk * ntile;
+    const uint32_t r_beg = chunk * (uint32_t)TM_LY_CHUNKS_RC;
+    const uint32_t r_end = r_beg + (uint32_t)TM_LY_CHUNKS_RC < nrhs ? r_beg + (uint32_t)TM_LY_CHUNKS_RC : nrhs;
+    if (a.gate) {  // flexible CG: nothing to do for converged or fallen-back right-hand sides
+        bool any = false;
+        for (uint32_t r = r_beg; r < r_end; r++) any |= a.gate[r].active != 0 && a.gate[r].fell == 0;
+        if (!any) return;
+    }
     const uint32_t s0 = tile * LY_TS + (threadIdx.x >> 6) * 16 + (lane & 15);
     const bool valid = s0 < geo.V;
     const uint32_t s = valid ? s0 : 0u;  // lanes past the lattice compute site 0 and store nothing
@@ -320,8 +327,7 @@ __global__ __launch_bounds__(LY_THREADS) void k_pt_layer(PtArgs a, uint32_t nrhs
 #pragma unroll
     for (int ks = 0; ks < NKS; ks++) wf[ks] = ((const v4s*)a.wfrag)[ks * 64 + lane];
 
-    const uint32_t r_end = (chunk + 1) * (uint32_t)TM_LY_CHUNKS_RC < nrhs ? (chunk + 1) * (uint32_t)TM_LY_CHUNKS_RC : nrhs;
-    for (uint32_t r0 = chunk * (uint32_t)TM_LY_CHUNKS_RC; r0 < r_end; r0 += LY_RC) {
+    for (uint32_t r0 = r_beg; r0 < r_end; r0 += LY_RC) {
         const uint32_t nrhs_left = r_end;
         const uint32_t nr = nrhs_left - r0 < (uint32_t)LY_RC ? nrhs_left - r0 : (uint32_t)LY_RC;
         v4f D[LY_RC][3];

@@ -75,6 +75,8 @@ struct PtArgs {
     const void* in;        // cin fields (per right-hand side: cin consecutive fields)
     void* out;             // cout fields (per right-hand side), FP32 or bfloat16
     const short* wfrag;    // weight fragments [kpad/16][64 lanes][4] bfloat16
+    const FcgScal* gate;   // layer application: right-hand side r is skipped unless gate[r]
+                           // is active and has not fallen back (nullptr: all)
     const void* g;         // weight gradient: upstream gradient (cout FP32 fields)
     float* partials;       // weight gradient: [blocks][16][kpad]
 };

@@ -133,7 +133,7 @@ static tm_status install(tm_ctx* ctx, const tm_net_shape* shape, const cplx* W) 
 // one layer: in (cin fields per rhs, storage in_prec) -> out (cout fields per
 // rhs, storage out_prec: FP32 or bfloat16)
 static void layer_launch(tm_ctx* ctx, int l, bool adjoint, const void* in, int in_prec, void* out, int nrhs,
-                         int out_prec = P_F32) {
+                         int out_prec = P_F32, const FcgScal* gate = nullptr) {
     NetState* ns = ctx->net;
     PtArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -146,13 +146,15 @@ static void layer_launch(tm_ctx* ctx, int l, bool adjoint, const void* in, int i
     a.in = in;
     a.out = out;
     a.wfrag = adjoint ? ns->frag_adj[l] : ns->frag_fwd[l];
+    a.gate = gate;
     launch_pt_layer(ctx->stream, a, in_prec, out_prec, nrhs);
 }
 
 // out = N(in) or N^dag(in); single fields, nrhs of them.  The hidden
 // activations are stored as bfloat16 (the precision the mixing GEMM reads
 // them in); out is written in out_prec.
-tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_prec, void* out, int out_prec) {
+tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_prec, void* out, int out_prec,
+                    const FcgScal* gate) {
     NetState* ns = ctx->net;
     tm_status s = TM_OK;
     const size_t fb = field_bytes(ctx->geo, P_BF16, 2 * nrhs);
@@ -167,7 +169,7 @@ tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_
         void* dst = last ? out : ((i % 2 == 0) ? A : B);
         const int dst_prec = last ? out_prec : P_BF16;
         prof_begin(ctx, TM_KC_OTHER);
-        layer_launch(ctx, l, adjoint, cur, cur_prec, dst, nrhs, dst_prec);
+        layer_launch(ctx, l, adjoint, cur, cur_prec, dst, nrhs, dst_prec, gate);
         prof_end(ctx, TM_KC_OTHER, 0.0);
         cur = dst;
         cur_prec = dst_prec;
@@ -176,13 +178,14 @@ tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_
     return TM_OK;
 }
 
-// z = N(N^dag(r)), r and z FP32, the middle field bfloat16
-tm_status net_precondition(tm_ctx* ctx, int nrhs, const void* r, void* z) {
+// z = N(N^dag(r)), r and z FP32, the middle field bfloat16; right-hand sides
+// that gate marks converged or fallen back are skipped (z keeps its values)
+tm_status net_precondition(tm_ctx* ctx, int nrhs, const void* r, void* z, const FcgScal* gate) {
     tm_status s = TM_OK;
     void* tmp = ws_get(ctx, "net_mid", field_bytes(ctx->geo, P_BF16, nrhs), &s);
     if (s != TM_OK) return s;
-    if ((s = net_apply(ctx, true, nrhs, r, P_F32, tmp, P_BF16)) != TM_OK) return s;
-    return net_apply(ctx, false, nrhs, tmp, P_BF16, z, P_F32);
+    if ((s = net_apply(ctx, true, nrhs, r, P_F32, tmp, P_BF16, gate)) != TM_OK) return s;
+    return net_apply(ctx, false, nrhs, tmp, P_BF16, z, P_F32, gate);
 }
 
 bool net_installed(const tm_ctx* ctx) { return ctx->net != nullptr; }
@@ -332,7 +335,7 @@ tm_status tm_precond_apply(tm_ctx* ctx, int32_t adjoint, int32_t nrhs, const dou
     void* b = ws_get(ctx, "pa_out", fb, &s);
     if (s != TM_OK) return s;
     launch_c128_to_native(ctx->stream, ctx->geo, P_F32, nrhs, in_dev, a);
-    if ((s = net_apply(ctx, adjoint != 0, nrhs, a, P_F32, b, P_F32)) != TM_OK) return s;
+    if ((s = net_apply(ctx, adjoint != 0, nrhs, a, P_F32, b, P_F32, nullptr)) != TM_OK) return s;
     launch_native_to_c128(ctx->stream, ctx->geo, P_F32, nrhs, b, out_dev);
     TM_HIP(hipGetLastError());
     return TM_OK;

@@ -26,8 +26,9 @@ struct PairSink {
 tm_status solve_f64_history(tm_ctx* ctx, uint64_t seed_mixed, const uint64_t* id_dev, double tol, int maxit,
                             std::vector<double>* hist, void* xstar_out, PairSink* sink);
 
-tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_prec, void* out, int out_prec);
-tm_status net_precondition(tm_ctx* ctx, int nrhs, const void* r, void* z);
+tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_prec, void* out, int out_prec,
+                    const FcgScal* gate);
+tm_status net_precondition(tm_ctx* ctx, int nrhs, const void* r, void* z, const FcgScal* gate);
 bool net_installed(const tm_ctx* ctx);
 void net_release(tm_ctx* ctx);
 

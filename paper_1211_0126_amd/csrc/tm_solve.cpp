@@ -146,7 +146,7 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
     launch_apply(st, g, P_F32, ctx->gauge32, ctx->lat.kappa, ctx->twist, 1, nrhs, eta, a.r, 1, nullptr);
     launch_fcg_init(st, a, p->tol * p->tol, p->max_iter, 0);
     prof_end(ctx, TM_KC_OTHER, 0.0);
-    if ((s = net_precondition(ctx, nrhs, a.r, a.z)) != TM_OK) return s;
+    if ((s = net_precondition(ctx, nrhs, a.r, a.z, nullptr)) != TM_OK) return s;
     launch_fcg_dot(st, a, 1);
     launch_fcg_p(st, a);
     TM_HIP(hipGetLastError());
@@ -154,8 +154,10 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
     std::vector<FcgScal> fs(nrhs);
     int done = 0;
     for (;;) {
-        int k = 8;
-        if (p->max_iter >= 0) k = std::max(1, std::min(8, p->max_iter - done));
+        // iterations between host checks: the network skips finished
+        // right-hand sides, so an iteration past convergence costs launches only
+        int k = 2;
+        if (p->max_iter >= 0) k = std::max(1, std::min(k, p->max_iter - done));
         for (int i = 0; i < k; i++) {
             prof_begin(ctx, TM_KC_DSLASH, prof_tag(P_F32, 1, TM_SOLVER_FCG_LEARNED));
             launch_fcg_mp(st, a);
@@ -163,7 +165,7 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
             prof_begin(ctx, TM_KC_DSLASH_UPD, prof_tag(P_F32, 1, TM_SOLVER_FCG_LEARNED));
             launch_fcg_upd(st, a);
             prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
-            if ((s = net_precondition(ctx, nrhs, a.r, a.z)) != TM_OK) return s;
+            if ((s = net_precondition(ctx, nrhs, a.r, a.z, a.scal)) != TM_OK) return s;
             launch_fcg_dot(st, a, 0);
             prof_begin(ctx, TM_KC_BLAS, prof_tag(P_F32, 1, TM_SOLVER_FCG_LEARNED));
             launch_fcg_p(st, a);
