@@ -341,13 +341,22 @@ __device__ __forceinline__ void load_link<GF32, float>(const void* g, long Vs, i
     U[1][0] = {a1.z, a1.w};
     U[1][1] = {a2.x, a2.y};
     U[1][2] = {a2.z, a2.w};
-    // row2 = conj(row0 x row1)
-    U[2][0] = {U[0][1].re * U[1][2].re - U[0][1].im * U[1][2].im - U[0][2].re * U[1][1].re + U[0][2].im * U[1][1].im,
-               -(U[0][1].re * U[1][2].im + U[0][1].im * U[1][2].re - U[0][2].re * U[1][1].im - U[0][2].im * U[1][1].re)};
-    U[2][1] = {U[0][2].re * U[1][0].re - U[0][2].im * U[1][0].im - U[0][0].re * U[1][2].re + U[0][0].im * U[1][2].im,
-               -(U[0][2].re * U[1][0].im + U[0][2].im * U[1][0].re - U[0][0].re * U[1][2].im - U[0][0].im * U[1][2].re)};
-    U[2][2] = {U[0][0].re * U[1][1].re - U[0][0].im * U[1][1].im - U[0][1].re * U[1][0].re + U[0][1].im * U[1][0].im,
-               -(U[0][0].re * U[1][1].im + U[0][0].im * U[1][1].re - U[0][1].re * U[1][0].im - U[0][1].im * U[1][0].re)};
+    // row2 = conj(row0 x row1): U[2][k] = conj(a b - c d) with (a, b, c, d)
+    // the entries of the 2x2 cofactor, as FMA chains
+    auto cof = [](cx<float> a, cx<float> b, cx<float> c, cx<float> d) -> cx<float> {
+        float re = a.re * b.re;
+        re = fmaf(-a.im, b.im, re);
+        re = fmaf(-c.re, d.re, re);
+        re = fmaf(c.im, d.im, re);
+        float im = a.re * b.im;
+        im = fmaf(a.im, b.re, im);
+        im = fmaf(-c.re, d.im, im);
+        im = fmaf(-c.im, d.re, im);
+        return {re, -im};
+    };
+    U[2][0] = cof(U[0][1], U[1][2], U[0][2], U[1][1]);
+    U[2][1] = cof(U[0][2], U[1][0], U[0][0], U[1][2]);
+    U[2][2] = cof(U[0][0], U[1][1], U[0][1], U[1][0]);
 }
 
 // ---------------------------------------------------------------------------

@@ -93,20 +93,56 @@ __device__ __forceinline__ void recon(const cx<R> g[6], cx<R> acc[12]) {
     }
 }
 
+// SU(3) times the two colour vectors of a half spinor, as chains of fused
+// multiply-adds (a complex multiply-add is four FMAs; written out because the
+// compiler may not fuse across the complex products without reassociating)
+template <typename R>
+__device__ __forceinline__ cx<R> cmul_f(cx<R> a, cx<R> b) {
+    return {fma(-a.im, b.im, a.re * b.re), fma(a.im, b.re, a.re * b.im)};
+}
+template <typename R>
+__device__ __forceinline__ void cmac_f(cx<R>& t, cx<R> a, cx<R> b) {
+    t.re = fma(a.re, b.re, t.re);
+    t.re = fma(-a.im, b.im, t.re);
+    t.im = fma(a.re, b.im, t.im);
+    t.im = fma(a.im, b.re, t.im);
+}
+// conj(a) * b, and t += conj(a) * b
+template <typename R>
+__device__ __forceinline__ cx<R> cmulc_f(cx<R> a, cx<R> b) {
+    return {fma(a.im, b.im, a.re * b.re), fma(-a.im, b.re, a.re * b.im)};
+}
+template <typename R>
+__device__ __forceinline__ void cmacc_f(cx<R>& t, cx<R> a, cx<R> b) {
+    t.re = fma(a.re, b.re, t.re);
+    t.re = fma(a.im, b.im, t.re);
+    t.im = fma(a.re, b.im, t.im);
+    t.im = fma(-a.im, b.re, t.im);
+}
+
 template <typename R>
 __device__ __forceinline__ void su3_mul(const cx<R> U[3][3], const cx<R> h[6], cx<R> g[6]) {
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
-        for (int i = 0; i < 3; i++) g[3 * a + i] = U[i][0] * h[3 * a] + U[i][1] * h[3 * a + 1] + U[i][2] * h[3 * a + 2];
+        for (int i = 0; i < 3; i++) {
+            cx<R> t = cmul_f(U[i][0], h[3 * a]);
+            cmac_f(t, U[i][1], h[3 * a + 1]);
+            cmac_f(t, U[i][2], h[3 * a + 2]);
+            g[3 * a + i] = t;
+        }
 }
 template <typename R>
 __device__ __forceinline__ void su3_dag_mul(const cx<R> U[3][3], const cx<R> h[6], cx<R> g[6]) {
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
-        for (int i = 0; i < 3; i++)
-            g[3 * a + i] = cmulc(U[0][i], h[3 * a]) + cmulc(U[1][i], h[3 * a + 1]) + cmulc(U[2][i], h[3 * a + 2]);
+        for (int i = 0; i < 3; i++) {
+            cx<R> t = cmulc_f(U[0][i], h[3 * a]);
+            cmacc_f(t, U[1][i], h[3 * a + 1]);
+            cmacc_f(t, U[2][i], h[3 * a + 2]);
+            g[3 * a + i] = t;
+        }
 }
 
 template <typename R>
