@@ -460,12 +460,24 @@ __global__ __launch_bounds__(256) void k_pt_wgrad(PtArgs a) {
     }
 }
 
-// grad[m][k] += scale * sum over blocks of partials (fixed order), FP64
-__global__ void k_pt_wgrad_reduce(const float* partials, int nblocks, int kpad, const double* scale, double* grad) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 16 * kpad) return;
+// grad[m][k] += scale * sum over blocks of partials, FP64, in two coalesced
+// stages with a fixed order: chunk sums of WG_CH block partials, then the sum
+// of the chunk sums.
+constexpr int WG_CH = 256;
+__global__ __launch_bounds__(256) void k_pt_wgrad_sum1(const float* partials, int nblocks, int ne, double* part2) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
+    const int b0 = blockIdx.y * WG_CH, b1 = min(b0 + WG_CH, nblocks);
     double s = 0;
-    for (int b = 0; b < nblocks; b++) s += (double)partials[(size_t)b * 16 * kpad + e];
+    for (int b = b0; b < b1; b++) s += (double)partials[(size_t)b * ne + e];
+    part2[(size_t)blockIdx.y * ne + e] = s;
+}
+__global__ __launch_bounds__(256) void k_pt_wgrad_sum2(const double* part2, int nchunk, int ne, const double* scale,
+                                                       double* grad) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= ne) return;
+    double s = 0;
+    for (int c = 0; c < nchunk; c++) s += part2[(size_t)c * ne + e];
     grad[e] += (*scale) * s;
 }
 
@@ -533,8 +545,9 @@ void launch_pt_wgrad(hipStream_t st, const PtArgs& a, int in_prec, const double*
         hipLaunchKernelGGL((k_pt_wgrad<SBF16, SF32>), dim3(nb), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((k_pt_wgrad<SF32, SF32>), dim3(nb), dim3(256), 0, st, a);
-    const int n = 16 * a.kpad;
-    hipLaunchKernelGGL(k_pt_wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, st, a.partials, nb, a.kpad, scale, grad);
+    const int ne = 16 * a.kpad, nchunk = (nb + WG_CH - 1) / WG_CH;
+    hipLaunchKernelGGL(k_pt_wgrad_sum1, dim3((ne + 255) / 256, nchunk), dim3(256), 0, st, a.partials, nb, ne, a.partials2);
+    hipLaunchKernelGGL(k_pt_wgrad_sum2, dim3((ne + 255) / 256), dim3(256), 0, st, a.partials2, nchunk, ne, scale, grad);
 }
 
 void launch_pt_loss(hipStream_t st, const Geom& g, const void* y, const void* e, int e_prec, void* gout,
@@ -547,6 +560,7 @@ void launch_pt_loss(hipStream_t st, const Geom& g, const void* y, const void* e,
 }
 
 int pt_blocks(const Geom& g) { return (int)((g.V + PT_TS - 1) / PT_TS); }
+int pt_chunks(const Geom& g) { return (pt_blocks(g) + WG_CH - 1) / WG_CH; }
 
 // Training pair from an iterate x_k: r = eta - M x_k, e = x* - x_k (FP64
 // arithmetic, stored as bfloat16); eta regenerated from the hash.

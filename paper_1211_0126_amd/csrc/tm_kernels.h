@@ -79,6 +79,7 @@ struct PtArgs {
                            // is active and has not fallen back (nullptr: all)
     const void* g;         // weight gradient: upstream gradient (cout FP32 fields)
     float* partials;       // weight gradient: [blocks][16][kpad]
+    double* partials2;     // weight gradient: [pt_chunks][16][kpad]
 };
 
 void launch_pt_layer(hipStream_t st, const PtArgs& a, int in_prec, int out_prec, int nrhs);
@@ -86,6 +87,7 @@ void launch_pt_wgrad(hipStream_t st, const PtArgs& a, int in_prec, const double*
 void launch_pt_loss(hipStream_t st, const Geom& g, const void* y, const void* e, int e_prec, void* gout,
                     double* partials, unsigned int* counter, double* scal, int npairs);
 int pt_blocks(const Geom& g);
+int pt_chunks(const Geom& g);
 void launch_make_pair(hipStream_t st, const Geom& g, uint64_t seed_mixed, const uint64_t* id, const void* xk,
                       const void* xstar, const void* mxk, void* r_out, void* e_out);
 

@@ -213,6 +213,7 @@ static tm_status loss_grad_pairs(tm_ctx* ctx, int npairs, const void* r, int r_p
     void* g1 = ws_get(ctx, "lg_g1", f2, &s);
     const int nb = pt_blocks(g);
     float* partials = (float*)ws_get(ctx, "lg_partials", sizeof(float) * (size_t)nb * 16 * 144, &s);
+    double* partials2 = (double*)ws_get(ctx, "lg_partials2", sizeof(double) * (size_t)pt_chunks(g) * 16 * 144, &s);
     double* lpart = (double*)ws_get(ctx, "lg_lpart", sizeof(double) * 2 * ((g.V + 255) / 256), &s);
     unsigned int* counter = (unsigned int*)ws_get(ctx, "lg_counter", sizeof(unsigned int), &s);
     void* mw = mode == 1 ? ws_get(ctx, "lg_mw", f2, &s) : nullptr;
@@ -251,6 +252,7 @@ static tm_status loss_grad_pairs(tm_ctx* ctx, int npairs, const void* r, int r_p
             a.in = l == 0 ? ri : act[l];
             a.g = gcur;
             a.partials = partials;
+            a.partials2 = partials2;
             launch_pt_wgrad(ctx->stream, a, l == 0 ? r_prec : P_F32, scal, grads[l]);
             if (l > 0) {
                 layer_launch(ctx, l, true, gcur, P_F32, gnext, 1);
