@@ -144,6 +144,26 @@ def test_fcg_with_network_matches_oracle(orc, U):
     ctx.close()
 
 
+def test_fcg_sources_independent_of_block(orc, U):
+    """Per-source arithmetic of flexible CG does not depend on the other
+    sources of a block: a block of five (layers in chunks of two, the last
+    chunk partial, finished sources skipped) gives bit for bit what five
+    one-source blocks give."""
+    import paper_1211_0126_amd as tq
+    ctx = _ctx(DIMS, U)
+    tq.tm_precond_set(ctx, WIDTHS, _net(orc, 3, scale=0.02))
+    ids = [0, 1, 2, 3, 4]
+    p5 = tq.solve_params(prec=tq.PREC_F32, tol=1e-7, max_iter=-1, solver=tq.SOLVER_FCG_LEARNED, rhs_block=5)
+    p1 = tq.solve_params(prec=tq.PREC_F32, tol=1e-7, max_iter=-1, solver=tq.SOLVER_FCG_LEARNED, rhs_block=1)
+    s5, st5, _ = tq.tsm_solve_batch(ctx, p5, 12, ids)
+    s1, st1, _ = tq.tsm_solve_batch(ctx, p1, 12, ids)
+    assert [a["iters"] for a in st5] == [b["iters"] for b in st1]
+    assert all(a["converged"] for a in st5)
+    assert bool((s5 == s1).all())
+    print("fcg iterations per source", [a["iters"] for a in st5])
+    ctx.close()
+
+
 def test_training_reduces_loss_and_solves(orc):
     """Training on harvested pairs lowers the loss; the trained network
     preconditions flexible CG to the same solution as plain CG."""
