@@ -255,7 +255,10 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* params, double* loops_host, d
    complex128 [9][widths[l+1]][widths[l]][4][4], layers back to back.
    widths[0] = widths[n_layers] = 1 and 1 <= widths[l] <= 2.  The network N
    approximates M^{-1}; flexible CG on M^dag M uses z = N(N^dag(r)).
-   Mixing runs on the matrix cores in bfloat16 with FP32 accumulation. */
+   Transports use bfloat16 (re, im) pairs of the input and of a bfloat16
+   copy of the links with FP32 accumulation; the mixing runs on the matrix
+   cores in bfloat16 with FP32 accumulation; hidden activations are stored
+   as bfloat16. */
 #define TM_NET_MAX_LAYERS 8
 typedef struct {
     int32_t n_layers;
@@ -274,7 +277,7 @@ tm_status tm_precond_get(tm_ctx* ctx, tm_net_shape* shape_out, double* weights_h
 
 /* out = N(in) (adjoint = 0) or N^dag(in) (adjoint = 1) for nrhs single
    spinor fields, canonical complex128 [nrhs][V][4][3] (device).  FP32
-   activations, bfloat16 mixing.  Asynchronous. */
+   input and output, bfloat16 hidden activations and mixing.  Asynchronous. */
 tm_status tm_precond_apply(tm_ctx* ctx, int32_t adjoint, int32_t nrhs, const double* in_dev, double* out_dev);
 
 /* Training loss (1/npairs) sum_i |N(r_i) - e_i|^2 / |e_i|^2 over pairs given
