@@ -46,8 +46,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--lp-prec", default="f16", choices=list(PREC_NAMES))
-    ap.add_argument("--lp-block", type=int, default=16)
-    ap.add_argument("--hp-block", type=int, default=8)
+    ap.add_argument("--lp-block", type=int, default=0,
+                    help="LP sources per solver block (default: autotune over 8, 16, 32)")
+    ap.add_argument("--hp-block", type=int, default=0,
+                    help="HP sources per solver block (default: autotune over 8, 16)")
     ap.add_argument("--n-lp", type=int, default=None, help="override N_LP (default: the workload's)")
     ap.add_argument("--n-hp", type=int, default=None)
     ap.add_argument("--compare-sources", type=int, default=64)
@@ -177,17 +179,37 @@ def main():
     mom = wl.momenta()
     lp_prec = PREC_NAMES[args.lp_prec]
     tune = {}
-    for prec, blk, fixed in ((lp_prec, args.lp_block, args.lp_config), (tq.PREC_F32, args.hp_block, args.hp_config)):
+    n_lp0 = args.n_lp if args.n_lp is not None else wl.n_lp
+    n_hp0 = args.n_hp if args.n_hp is not None else wl.n_hp
+    # block candidates and the block used with a fixed kernel configuration
+    for role, prec, blk, fixed, cands, dflt, nsrc in (
+            ("lp", lp_prec, args.lp_block, args.lp_config, (8, 16, 32), 16, n_lp0),
+            ("hp", tq.PREC_F32, args.hp_block, args.hp_config, (8, 16), 8, n_hp0)):
         name = [k for k, v in PREC_NAMES.items() if v == prec][0]
+        blocks = [blk] if blk else ([b for b in cands if b <= max(nsrc, 1)] or [cands[0]])
         if fixed:
             nr, ts = (int(v) for v in fixed.split(","))
             tq.tm_set_lane_rhs(ctx, prec, nr)
             tq.tm_set_march(ctx, prec, ts)
-            tune[name] = {"rhs_block": blk, "lane_rhs": nr, "tseg": ts, "fixed": True}
+            tune[role] = {"storage": name, "rhs_block": blk or dflt, "lane_rhs": nr, "tseg": ts, "fixed": True}
             continue
-        nr, ts, ms = tq.tm_autotune_cg(ctx, prec, blk)
-        tune[name] = {"rhs_block": blk, "lane_rhs": nr, "tseg": ts,
-                      "ms_per_cg_iteration": {"%d,%d" % c: round(m, 4) for c, m in ms.items()}}
+        # per block size: the best (right-hand sides per lane, time slices
+        # per lane); keep the block with the lowest time per source-iteration
+        best = None
+        per_block = {}
+        for b in blocks:
+            nr, ts, ms = tq.tm_autotune_cg(ctx, prec, b)
+            per_source = ms[(nr, ts)] / b
+            per_block[b] = {"lane_rhs": nr, "tseg": ts, "ms_per_source_iteration": round(per_source, 5),
+                            "ms_per_cg_iteration": {"%d,%d" % c: round(m, 4) for c, m in ms.items()}}
+            if best is None or per_source < best[3]:
+                best = (b, nr, ts, per_source)
+        b, nr, ts, _ = best
+        tq.tm_set_lane_rhs(ctx, prec, nr)
+        tq.tm_set_march(ctx, prec, ts)
+        tune[role] = {"storage": name, "rhs_block": b, "lane_rhs": nr, "tseg": ts, "candidates": per_block}
+    args.lp_block = tune["lp"]["rhs_block"]
+    args.hp_block = tune["hp"]["rhs_block"]
     log("autotune: %s" % tune)
     # The LP true residual is a diagnostic outside the method (the estimator
     # uses the truncated solutions as they are); it is measured on the same
