@@ -161,8 +161,11 @@ typedef struct {
 int32_t tm_abi_version(void);
 
 /* Create a context for one lattice on the current HIP device.  hip_stream is
-   a hipStream_t (NULL: the null stream).  TM_EINVAL for dims < 2 or
-   lattices of 2^26 sites or more. */
+   a hipStream_t (NULL: the null stream).  TM_EINVAL for dims < 2 or for
+   lattices whose volume, padded to the plane stride (an odd multiple of
+   256), exceeds 7,456,512 sites (planes are addressed with 32-bit byte
+   offsets: 48^3 x 64 fits, 48^3 x 96 does not); tm_last_error(NULL) says
+   why. */
 tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out);
 
 /* Release every device buffer and the context. */

@@ -153,7 +153,10 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
         if (lat->dims[d] < 2 || lat->dims[d] > 4096) return TM_EINVAL;
         V *= lat->dims[d];
     }
-    if (V >= (1L << 26)) return TM_EINVAL;
+    if (V >= (1L << 26)) {
+        g_create_error = "lattice too large";
+        return TM_EINVAL;
+    }
     if (lat->t_bc != 1 && lat->t_bc != -1) return TM_EINVAL;
     if (!std::isfinite(lat->kappa) || !std::isfinite(lat->mu)) return TM_EINVAL;
     tm_ctx* ctx = new tm_ctx();
@@ -172,6 +175,14 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
 #ifndef TM_POW2_PLANES
     if ((g.Vs / 256) % 2 == 0) g.Vs += 256;
 #endif
+    // Buffer instructions address a field's planes with 32-bit byte offsets
+    // from one base; the most planes behind one base are the FP64 links'
+    // 4 x 9, so 36 planes of 16 Vs bytes must stay below 4 GiB.
+    if (g.Vs * 16 * 36 > 0xFFFFFFFFL) {
+        g_create_error = "lattice too large: 576 * (volume padded to 256) must stay below 2^32 bytes";
+        delete ctx;
+        return TM_EINVAL;
+    }
     for (int d = 0; d < 3; d++) {
         uint64_t dd = (uint64_t)g.L[d];
         uint64_t m = ((1ULL << 32) + dd - 1) / dd;

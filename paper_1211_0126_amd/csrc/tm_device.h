@@ -113,8 +113,8 @@ struct SBF16 {
 // buffer instructions: the field's base address lives in a descriptor in
 // scalar registers, the plane offset k*Vs*16 is a scalar offset, and the
 // only per-lane address is the 32-bit byte offset 16*site, shared by all
-// planes of all fields.  (Offsets stay below 4 GiB: lattices have < 2^26
-// sites and at most 36 planes per field.)
+// planes of all fields.  (Offsets stay below 4 GiB: at most 36 planes sit
+// behind one base, and tm_create rejects lattices with 576 * Vs >= 2^32.)
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void* base) {
     // raw buffer, no stride; dword3 = 0x00020000 is the gfx9-family format word
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);

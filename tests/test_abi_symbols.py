@@ -68,3 +68,19 @@ def test_missing_library_fails_loudly(tmp_path):
             binding.load_library(str(tmp_path / "libtmqcd.so"))
     finally:
         binding._lib = saved
+
+
+def test_too_large_lattices_are_rejected_before_any_device_call(lib):
+    """tm_create refuses volumes whose 36 planes of FP64 links would need
+    byte offsets of 2^32 or more (checked before any HIP call)."""
+    from paper_1211_0126_amd.binding import Lattice
+    lib.tm_create.argtypes = [ctypes.POINTER(Lattice), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    lib.tm_create.restype = ctypes.c_int32
+    lib.tm_last_error.argtypes = [ctypes.c_void_p]
+    lib.tm_last_error.restype = ctypes.c_char_p
+    for dims in ((48, 48, 48, 96), (64, 64, 64, 64), (256, 256, 256, 16)):
+        lat = Lattice((ctypes.c_int32 * 4)(*dims), 0.16, 0.01, -1)
+        out = ctypes.c_void_p()
+        assert lib.tm_create(ctypes.byref(lat), None, ctypes.byref(out)) == -1, dims
+        assert not out.value
+        assert b"too large" in lib.tm_last_error(None)
