@@ -481,14 +481,12 @@ __global__ __launch_bounds__(256) void k_pt_wgrad_sum2(const double* part2, int 
     grad[e] += (*scale) * s;
 }
 
-// Output error of a training pair: g = y - e (FP32 field), |y - e|^2 and
-// |e|^2, and (last block) the pair's loss share and gradient scale
-// 1 / (|e|^2 npairs); loss accumulates into scal[2].
+// Output error of a training pair: g = y - e (FP32 field), block partials of
+// |y - e|^2 and |e|^2; k_pt_loss_fin turns them into the pair's loss share
+// and gradient scale.
 template <class Se>
-__global__ __launch_bounds__(256) void k_pt_loss(Geom geo, const void* y, const void* e, void* g, double* partials,
-                                                 unsigned int* counter, double* scal, int npairs) {
+__global__ __launch_bounds__(256) void k_pt_loss(Geom geo, const void* y, const void* e, void* g, double* partials) {
     __shared__ double sh[4];
-    __shared__ int sflag;
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     double pd = 0, pe = 0;
     if (s < geo.V) {
@@ -508,15 +506,23 @@ __global__ __launch_bounds__(256) void k_pt_loss(Geom geo, const void* y, const 
     if (threadIdx.x == 0) partials[blockIdx.x] = v;
     double u = block_sum256(pe, sh);
     if (threadIdx.x == 0) partials[nb + blockIdx.x] = u;
-    if (take_last_ticket(counter, nb, &sflag)) {
-        double d2 = sum_partials(partials, nb, sh);
-        double e2 = sum_partials(partials + nb, nb, sh);
-        if (threadIdx.x == 0) {
-            scal[0] = 1.0 / (e2 * npairs);      // gradient scale of this pair
-            scal[1] = d2 / e2;                   // this pair's relative error
-            scal[2] += d2 / e2 / npairs;         // running loss
-            *counter = 0;
-        }
+}
+
+// one block: the pair's gradient scale 1 / (|e|^2 npairs) into scal[0], its
+// relative error into scal[1], and its loss share added to scal[2]
+__global__ __launch_bounds__(256) void k_pt_loss_fin(const double* partials, uint32_t nb, double* scal, int npairs) {
+    __shared__ double sh[4];
+    double d = 0, e = 0;
+    for (uint32_t i = threadIdx.x; i < nb; i += 256) {
+        d += partials[i];
+        e += partials[nb + i];
+    }
+    const double d2 = block_sum256(d, sh);
+    const double e2 = block_sum256(e, sh);
+    if (threadIdx.x == 0) {
+        scal[0] = 1.0 / (e2 * npairs);
+        scal[1] = d2 / e2;
+        scal[2] += d2 / e2 / npairs;
     }
 }
 
@@ -551,12 +557,13 @@ void launch_pt_wgrad(hipStream_t st, const PtArgs& a, int in_prec, const double*
 }
 
 void launch_pt_loss(hipStream_t st, const Geom& g, const void* y, const void* e, int e_prec, void* gout,
-                    double* partials, unsigned int* counter, double* scal, int npairs) {
-    dim3 grid((unsigned)((g.V + 255) / 256));
+                    double* partials, double* scal, int npairs) {
+    const unsigned nb = (unsigned)((g.V + 255) / 256);
     if (e_prec == P_BF16)
-        hipLaunchKernelGGL((k_pt_loss<SBF16>), grid, dim3(256), 0, st, g, y, e, gout, partials, counter, scal, npairs);
+        hipLaunchKernelGGL((k_pt_loss<SBF16>), dim3(nb), dim3(256), 0, st, g, y, e, gout, partials);
     else
-        hipLaunchKernelGGL((k_pt_loss<SF32>), grid, dim3(256), 0, st, g, y, e, gout, partials, counter, scal, npairs);
+        hipLaunchKernelGGL((k_pt_loss<SF32>), dim3(nb), dim3(256), 0, st, g, y, e, gout, partials);
+    hipLaunchKernelGGL(k_pt_loss_fin, dim3(1), dim3(256), 0, st, partials, nb, scal, npairs);
 }
 
 int pt_blocks(const Geom& g) { return (int)((g.V + PT_TS - 1) / PT_TS); }

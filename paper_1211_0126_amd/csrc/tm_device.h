@@ -468,29 +468,6 @@ __device__ __forceinline__ double block_sum256(double v, double* sh /*[4]*/) {
     return r;
 }
 
-// Completion ticket for the "last block finalises" pattern.  Every block
-// publishes its partial, then takes a ticket; the block that draws the last
-// ticket sees all partials (release/acquire at agent scope) and resets the
-// counter for the next launch.
-__device__ __forceinline__ bool take_last_ticket(unsigned int* counter, unsigned int nblocks, int* sh_flag) {
-    if (threadIdx.x == 0) {
-        __threadfence();
-        unsigned int t = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        *sh_flag = (t == nblocks - 1);
-    }
-    __syncthreads();
-    bool last = *sh_flag != 0;
-    if (last) __threadfence();
-    return last;
-}
-
-// Fixed-order sum of n partials by a 256-thread block; valid in thread 0.
-__device__ __forceinline__ double sum_partials(const double* p, int n, double* sh) {
-    double v = 0;
-    for (int i = threadIdx.x; i < n; i += 256) v += __hip_atomic_load(p + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return block_sum256(v, sh);
-}
-
 // Occupancy target of the stencil kernels (waves per SIMD) for NR
 // right-hand sides per lane; caps the registers the scheduler may spend on
 // hoisting neighbour loads.

@@ -21,7 +21,6 @@ struct CgArgs {
     CgScal* scal;
     double* partials;   // [nrhs][nblocks]
     double* partials2;  // [nrhs][nblocks]
-    unsigned int* counters;  // [nrhs], zero between launches
     int nrhs;
     uint32_t npart;     // block partials per right-hand side written by K1 / K2
     int tseg;           // time slices per lane of the time-marching K1 / K2
@@ -55,7 +54,6 @@ struct FcgArgs {
     void *p, *t, *q, *r, *x, *z;  // FP32 native fields, nrhs each
     FcgScal* scal;
     double* partials;   // [nrhs][4][nblocks]
-    unsigned int* counters;
     int nrhs;
 };
 
@@ -85,7 +83,7 @@ struct PtArgs {
 void launch_pt_layer(hipStream_t st, const PtArgs& a, int in_prec, int out_prec, int nrhs);
 void launch_pt_wgrad(hipStream_t st, const PtArgs& a, int in_prec, const double* scale, double* grad);
 void launch_pt_loss(hipStream_t st, const Geom& g, const void* y, const void* e, int e_prec, void* gout,
-                    double* partials, unsigned int* counter, double* scal, int npairs);
+                    double* partials, double* scal, int npairs);
 int pt_blocks(const Geom& g);
 int pt_chunks(const Geom& g);
 void launch_make_pair(hipStream_t st, const Geom& g, uint64_t seed_mixed, const uint64_t* id, const void* xk,

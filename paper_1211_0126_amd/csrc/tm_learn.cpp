@@ -215,7 +215,6 @@ static tm_status loss_grad_pairs(tm_ctx* ctx, int npairs, const void* r, int r_p
     float* partials = (float*)ws_get(ctx, "lg_partials", sizeof(float) * (size_t)nb * 16 * 144, &s);
     double* partials2 = (double*)ws_get(ctx, "lg_partials2", sizeof(double) * (size_t)pt_chunks(g) * 16 * 144, &s);
     double* lpart = (double*)ws_get(ctx, "lg_lpart", sizeof(double) * 2 * ((g.V + 255) / 256), &s);
-    unsigned int* counter = (unsigned int*)ws_get(ctx, "lg_counter", sizeof(unsigned int), &s);
     void* mw = mode == 1 ? ws_get(ctx, "lg_mw", f2, &s) : nullptr;
     void* gd = mode == 1 ? ws_get(ctx, "lg_gd", f2, &s) : nullptr;
     if (s != TM_OK) return s;
@@ -233,10 +232,10 @@ static tm_status loss_grad_pairs(tm_ctx* ctx, int npairs, const void* r, int r_p
         if (mode == 1) {
             launch_apply(ctx->stream, g, P_F32, ctx->gauge32, ctx->lat.kappa, ctx->twist, 0, 1, act[ns->nl], mw, 1,
                          nullptr);
-            launch_pt_loss(ctx->stream, g, mw, ri, r_prec, gd, lpart, counter, scal, npairs);
+            launch_pt_loss(ctx->stream, g, mw, ri, r_prec, gd, lpart, scal, npairs);
             launch_apply(ctx->stream, g, P_F32, ctx->gauge32, ctx->lat.kappa, ctx->twist, 1, 1, gd, g0, 1, nullptr);
         } else {
-            launch_pt_loss(ctx->stream, g, act[ns->nl], ei, e_prec, g0, lpart, counter, scal, npairs);
+            launch_pt_loss(ctx->stream, g, act[ns->nl], ei, e_prec, g0, lpart, scal, npairs);
         }
         // backward
         void* gcur = g0;

@@ -134,7 +134,6 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
     void* eta = ws_get(ctx, tag + "_feta", fb, &s);
     a.scal = (FcgScal*)ws_get(ctx, tag + "_fscal", sizeof(FcgScal) * kMaxBlock, &s);
     a.partials = (double*)ws_get(ctx, "fpartials", sizeof(double) * nblk * kMaxBlock * 4, &s);
-    a.counters = (unsigned int*)ws_get(ctx, "counters", sizeof(unsigned int) * kMaxBlock, &s);
     CgScal* tscal = (CgScal*)ws_get(ctx, tag + "_ftscal", sizeof(CgScal) * kMaxBlock, &s);
     double* part1 = (double*)ws_get(ctx, "partials", sizeof(double) * nblk * kMaxBlock, &s);
     double* part2 = (double*)ws_get(ctx, "partials2", sizeof(double) * nblk * kMaxBlock, &s);
@@ -193,7 +192,6 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
         at.scal = tscal;
         at.partials = part1;
         at.partials2 = part2;
-        at.counters = a.counters;
         at.nrhs = nrhs;
         launch_true_resid(st, at, P_F32, ctx->gauge64, seed_mixed, ids_dev);
         TM_HIP(hipGetLastError());
@@ -238,7 +236,6 @@ tm_status solve_f64_history(tm_ctx* ctx, uint64_t seed_mixed, const uint64_t* id
     a.scal = (CgScal*)ws_get(ctx, "h_scal", sizeof(CgScal) * kMaxBlock, &s);
     a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * nblk * kMaxBlock, &s);
     a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * nblk * kMaxBlock, &s);
-    a.counters = (unsigned int*)ws_get(ctx, "counters", sizeof(unsigned int) * kMaxBlock, &s);
     if (s != TM_OK) return s;
     launch_scal_init(st, a.scal, 1, tol * tol, maxit, 0, 0, 0.0);
     launch_noise_native(st, g, P_F64, seed_mixed, id_dev, 1, eta);
@@ -313,7 +310,6 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
     a.scal = (CgScal*)ws_get(ctx, tag + "_scal", sizeof(CgScal) * kMaxBlock, &s);
     a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * npart_max * kMaxBlock, &s);
     a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * npart_max * kMaxBlock, &s);
-    a.counters = (unsigned int*)ws_get(ctx, "counters", sizeof(unsigned int) * kMaxBlock, &s);
     if (track) a.rho = ws_get(ctx, tag + "_rho", fb, &s);
     void* eta = nullptr;
     void *b64 = nullptr, *x64 = nullptr, *t64 = nullptr;
