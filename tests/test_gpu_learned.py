@@ -234,3 +234,23 @@ def test_learned_preconditioner_gain():
             assert a["converged"] and not a["fell_back"]
             assert a["resid_true"] <= 1.05 * b["resid_true"] + 1e-12
     ctx.close()
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_network_on_a_large_lattice(orc, adjoint):
+    """16^3 x 32 (2^17 sites, plane offsets of several MB) with five right-hand
+    sides, so the layers run several right-hand-side chunks, the last one
+    partial: the whole output against the FP64 oracle."""
+    import torch
+    import paper_1211_0126_amd as tq
+    dims = (16, 16, 16, 32)
+    U = make_gauge(dims, 0.25, 1001)
+    ctx = _ctx(dims, U)
+    W = _net(orc, 4)
+    tq.tm_precond_set(ctx, WIDTHS, W)
+    x = random_spinor(dims, 9, 5)
+    out = tq.tm_precond_apply(ctx, torch.from_numpy(x).cuda(), adjoint=adjoint).cpu().numpy()
+    for r in range(5):
+        ref = orc.pt_net(dims, -1, U, WIDTHS, W, x[r][None], adjoint=adjoint)[0]
+        assert _rel(out[r], ref) < 2e-2, (r, _rel(out[r], ref))
+    ctx.close()
