@@ -302,6 +302,12 @@ void launch_fcg_upd(hipStream_t st, const FcgArgs& a) {
     hipLaunchKernelGGL(k_fcg_upd, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_fcg_upd_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, fblocks(a.geo));
 }
+void launch_fcg_mp_fin(hipStream_t st, const FcgArgs& a, uint32_t nb) {
+    hipLaunchKernelGGL(k_fcg_mp_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, nb);
+}
+void launch_fcg_upd_fin(hipStream_t st, const FcgArgs& a, uint32_t nb) {
+    hipLaunchKernelGGL(k_fcg_upd_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, nb);
+}
 void launch_fcg_dot(hipStream_t st, const FcgArgs& a, int init) {
     hipLaunchKernelGGL(k_fcg_dot, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a, init);
     hipLaunchKernelGGL(k_fcg_dot_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, fblocks(a.geo), init);

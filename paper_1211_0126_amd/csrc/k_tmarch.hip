@@ -264,6 +264,109 @@ __global__ TM_MARCH_R(NR, R) void k_tm_upd(CgArgs a) {
     }
 }
 
+// Flexible CG with the marching stencils (FP32 fields, complex alpha):
+// F1 t = M p with block partials of |t|^2; F2 q = M^dag t (kept for the
+// direction update), x += alpha p, r -= alpha q, block partials of |r|^2.
+template <int NR>
+__global__ TM_MARCH_R(NR, float) void k_fcg_tm_mp(FcgArgs a, int tseg, uint32_t npart) {
+    __shared__ double sh[4];
+    const Geom& g = a.geo;
+    const int Lt = g.L[3];
+    const uint32_t V3 = (uint32_t)(g.V / Lt);
+    const MarchMap m = march_block((uint32_t)(a.nrhs / NR), (V3 + 255) / 256);
+    const int r0 = m.ch * NR;
+    bool act[NR];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        act[r] = a.scal[r0 + r].active != 0;
+        any |= act[r];
+    }
+    if (!any) return;
+    double part[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) part[r] = 0;
+    const uint32_t s3 = m.tile * 256u + threadIdx.x;
+    const int t0 = (int)m.seg * tseg;
+    const int t1 = min(t0 + tseg, Lt);
+    if (s3 < V3) {
+        const long Vs = g.Vs;
+        march<false, float, SF32, GF32, NR>(g, a.gauge, field_rhs<SF32>(a.p, Vs, r0), a.kappa, a.twist, s3, V3, t0,
+                                            t1, [&](int, uint32_t s, cx<float> (&out)[NR][12]) {
+#pragma unroll
+                                                for (int r = 0; r < NR; r++) {
+                                                    if (!act[r]) continue;
+                                                    store_spinor<SF32, float>(field_rhs<SF32>(a.t, Vs, r0 + r), Vs, s,
+                                                                              out[r]);
+                                                    part[r] += spinor_norm2(out[r]);
+                                                }
+                                            });
+    }
+    const uint32_t blk = m.tile + m.ntile * m.seg;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        double v = block_sum256(part[r], sh);
+        if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * npart + blk] = v;
+    }
+}
+
+template <int NR>
+__global__ TM_MARCH_R(NR, float) void k_fcg_tm_upd(FcgArgs a, int tseg, uint32_t npart) {
+    __shared__ double sh[4];
+    const Geom& g = a.geo;
+    const int Lt = g.L[3];
+    const uint32_t V3 = (uint32_t)(g.V / Lt);
+    const MarchMap m = march_block((uint32_t)(a.nrhs / NR), (V3 + 255) / 256);
+    const int r0 = m.ch * NR;
+    bool act[NR];
+    bool any = false;
+    cx<float> al[NR];
+    double prr[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        act[r] = a.scal[r0 + r].active != 0;
+        any |= act[r];
+        al[r] = {(float)a.scal[r0 + r].alpha_re, (float)a.scal[r0 + r].alpha_im};
+        prr[r] = 0;
+    }
+    if (!any) return;
+    const uint32_t s3 = m.tile * 256u + threadIdx.x;
+    const int t0 = (int)m.seg * tseg;
+    const int t1 = min(t0 + tseg, Lt);
+    if (s3 < V3) {
+        const long Vs = g.Vs;
+        march<true, float, SF32, GF32, NR>(
+            g, a.gauge, field_rhs<SF32>(a.t, Vs, r0), a.kappa, a.twist, s3, V3, t0, t1,
+            [&](int, uint32_t s, cx<float> (&q)[NR][12]) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    if (!act[r]) continue;
+                    store_spinor<SF32, float>(field_rhs<SF32>(a.q, Vs, r0 + r), Vs, s, q[r]);
+                    void* rp = field_rhs<SF32>(a.r, Vs, r0 + r);
+                    cx<float> rv[12];
+                    load_spinor_cp<SF32, float, TM_CP_K2>(rp, Vs, s, rv);
+#pragma unroll
+                    for (int k = 0; k < 12; k++) rv[k] = rv[k] - al[r] * q[r][k];
+                    store_spinor_cp<SF32, float, TM_CP_K2>(rp, Vs, s, rv);
+                    prr[r] += spinor_norm2(rv);
+                    void* xp = field_rhs<SF32>(a.x, Vs, r0 + r);
+                    cx<float> pv[12], xv[12];
+                    load_spinor_cp<SF32, float, TM_CP_K2>(field_rhs<SF32>(a.p, Vs, r0 + r), Vs, s, pv);
+                    load_spinor_cp<SF32, float, TM_CP_K2>(xp, Vs, s, xv);
+#pragma unroll
+                    for (int k = 0; k < 12; k++) xv[k] = xv[k] + al[r] * pv[k];
+                    store_spinor_cp<SF32, float, TM_CP_K2>(xp, Vs, s, xv);
+                }
+            });
+    }
+    const uint32_t blk = m.tile + m.ntile * m.seg;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        double v = block_sum256(prr[r], sh);
+        if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * npart + blk] = v;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -277,12 +380,12 @@ static void tm_mp_typed(hipStream_t st, const CgArgs& a, int nr) {
     const unsigned nb = march_partials(a.geo, a.tseg);
     if constexpr (sizeof(R) == 8) {
         hipLaunchKernelGGL((k_tm_mp<R, S, G, 1>), dim3(nb * a.nrhs), dim3(256), 0, st, a);
-        return;
+    } else {
+        if (nr == 2)
+            hipLaunchKernelGGL((k_tm_mp<R, S, G, 2>), dim3(nb * (a.nrhs / 2)), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_tm_mp<R, S, G, 1>), dim3(nb * a.nrhs), dim3(256), 0, st, a);
     }
-    if (nr == 2)
-        hipLaunchKernelGGL((k_tm_mp<R, S, G, 2>), dim3(nb * (a.nrhs / 2)), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL((k_tm_mp<R, S, G, 1>), dim3(nb * a.nrhs), dim3(256), 0, st, a);
 }
 
 template <typename R, class S, class G, class X, typename RX>
@@ -294,12 +397,29 @@ static void tm_upd_typed(hipStream_t st, const CgArgs& a, int nr, bool track) {
     }
     if constexpr (sizeof(R) == 8) {
         hipLaunchKernelGGL((k_tm_upd<R, S, G, X, RX, 1, false>), dim3(nb * a.nrhs), dim3(256), 0, st, a);
-        return;
+    } else {
+        if (nr == 2)
+            hipLaunchKernelGGL((k_tm_upd<R, S, G, X, RX, 2, false>), dim3(nb * (a.nrhs / 2)), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_tm_upd<R, S, G, X, RX, 1, false>), dim3(nb * a.nrhs), dim3(256), 0, st, a);
     }
+}
+
+void launch_fcg_tm_mp(hipStream_t st, const FcgArgs& a, int nr, int tseg) {
+    const uint32_t np = march_partials(a.geo, tseg);
     if (nr == 2)
-        hipLaunchKernelGGL((k_tm_upd<R, S, G, X, RX, 2, false>), dim3(nb * (a.nrhs / 2)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_fcg_tm_mp<2>, dim3(np * (unsigned)(a.nrhs / 2)), dim3(256), 0, st, a, tseg, np);
     else
-        hipLaunchKernelGGL((k_tm_upd<R, S, G, X, RX, 1, false>), dim3(nb * a.nrhs), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_fcg_tm_mp<1>, dim3(np * (unsigned)a.nrhs), dim3(256), 0, st, a, tseg, np);
+    launch_fcg_mp_fin(st, a, np);
+}
+void launch_fcg_tm_upd(hipStream_t st, const FcgArgs& a, int nr, int tseg) {
+    const uint32_t np = march_partials(a.geo, tseg);
+    if (nr == 2)
+        hipLaunchKernelGGL(k_fcg_tm_upd<2>, dim3(np * (unsigned)(a.nrhs / 2)), dim3(256), 0, st, a, tseg, np);
+    else
+        hipLaunchKernelGGL(k_fcg_tm_upd<1>, dim3(np * (unsigned)a.nrhs), dim3(256), 0, st, a, tseg, np);
+    launch_fcg_upd_fin(st, a, np);
 }
 
 void launch_tm_mp(hipStream_t st, const CgArgs& a, int prec, int nr) {

@@ -62,6 +62,12 @@ void launch_fcg_mp(hipStream_t st, const FcgArgs& a);
 void launch_fcg_upd(hipStream_t st, const FcgArgs& a);
 void launch_fcg_dot(hipStream_t st, const FcgArgs& a, int init);
 void launch_fcg_p(hipStream_t st, const FcgArgs& a);
+// finalisers of F1 / F2 over nb block partials per source
+void launch_fcg_mp_fin(hipStream_t st, const FcgArgs& a, uint32_t nb);
+void launch_fcg_upd_fin(hipStream_t st, const FcgArgs& a, uint32_t nb);
+// time-marching F1 / F2 (nr right-hand sides per lane, tseg slices per lane)
+void launch_fcg_tm_mp(hipStream_t st, const FcgArgs& a, int nr, int tseg);
+void launch_fcg_tm_upd(hipStream_t st, const FcgArgs& a, int nr, int tseg);
 
 // One transport layer of the learned preconditioner (cin, cout <= 2).
 struct PtArgs {

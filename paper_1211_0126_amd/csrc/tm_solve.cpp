@@ -112,7 +112,8 @@ struct BlockResult {
 // Flexible CG with the network preconditioner for a block of sources; the
 // final state is written into ctx->scal_host in CgScal form.
 static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_t seed_mixed,
-                                 const uint64_t* ids_dev, int nrhs, const std::string& tag, BlockResult* res) {
+                                 const uint64_t* ids_dev, int nrhs, int nr, const std::string& tag,
+                                 BlockResult* res) {
     const Geom& g = ctx->geo;
     hipStream_t st = ctx->stream;
     tm_status s = TM_OK;
@@ -152,17 +153,26 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
     const CgBytes by = cg_bytes(g, P_F32, nrhs, false, false);
     std::vector<FcgScal> fs(nrhs);
     int done = 0;
+    // the stencil steps march in time when a segment length is set for FP32
+    // (nr right-hand sides per lane, 1 or 2), else one lane per site
+    const int tseg = march_tseg(ctx, p, nr);
     for (;;) {
         // iterations between host checks: the network skips finished
         // right-hand sides, so an iteration past convergence costs launches only
         int k = 2;
         if (p->max_iter >= 0) k = std::max(1, std::min(k, p->max_iter - done));
         for (int i = 0; i < k; i++) {
-            prof_begin(ctx, TM_KC_DSLASH, prof_tag(P_F32, 1, TM_SOLVER_FCG_LEARNED));
-            launch_fcg_mp(st, a);
+            prof_begin(ctx, TM_KC_DSLASH, prof_tag(P_F32, tseg > 0 ? nr : 1, TM_SOLVER_FCG_LEARNED, tseg));
+            if (tseg > 0)
+                launch_fcg_tm_mp(st, a, nr, tseg);
+            else
+                launch_fcg_mp(st, a);
             prof_end(ctx, TM_KC_DSLASH, by.k1);
-            prof_begin(ctx, TM_KC_DSLASH_UPD, prof_tag(P_F32, 1, TM_SOLVER_FCG_LEARNED));
-            launch_fcg_upd(st, a);
+            prof_begin(ctx, TM_KC_DSLASH_UPD, prof_tag(P_F32, tseg > 0 ? nr : 1, TM_SOLVER_FCG_LEARNED, tseg));
+            if (tseg > 0)
+                launch_fcg_tm_upd(st, a, nr, tseg);
+            else
+                launch_fcg_upd(st, a);
             prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
             if ((s = net_precondition(ctx, nrhs, a.r, a.z, a.scal)) != TM_OK) return s;
             launch_fcg_dot(st, a, 0);
@@ -280,7 +290,7 @@ tm_status solve_f64_history(tm_ctx* ctx, uint64_t seed_mixed, const uint64_t* id
 // per-source state and res the native solutions.
 static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t seed_mixed, const uint64_t* ids_dev,
                              int nrhs, int nr, const std::string& tag, BlockResult* res) {
-    if (p->solver == TM_SOLVER_FCG_LEARNED) return solve_block_fcg(ctx, p, seed_mixed, ids_dev, nrhs, tag, res);
+    if (p->solver == TM_SOLVER_FCG_LEARNED) return solve_block_fcg(ctx, p, seed_mixed, ids_dev, nrhs, nr, tag, res);
     const Geom& g = ctx->geo;
     hipStream_t st = ctx->stream;
     tm_status s = TM_OK;

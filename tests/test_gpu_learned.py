@@ -164,6 +164,27 @@ def test_fcg_sources_independent_of_block(orc, U):
     ctx.close()
 
 
+@pytest.mark.parametrize("nr,tseg", [(1, 3), (2, 3), (2, 8)])
+def test_fcg_marching_stencils_match_lane_per_site(orc, U, nr, tseg):
+    """Flexible CG with the time-marching stencil steps (right-hand sides per
+    lane, time slices per lane; 3 does not divide Lt = 8) reaches the
+    solution of the lane-per-site steps in the same number of iterations."""
+    import paper_1211_0126_amd as tq
+    ctx = _ctx(DIMS, U)
+    tq.tm_precond_set(ctx, WIDTHS, _net(orc, 3, scale=0.02))
+    p = tq.solve_params(prec=tq.PREC_F32, tol=1e-6, max_iter=-1, solver=tq.SOLVER_FCG_LEARNED, rhs_block=4)
+    ref, st_ref, _ = tq.tsm_solve_batch(ctx, p, 21, [0, 1, 2, 3])
+    tq.tm_set_lane_rhs(ctx, tq.PREC_F32, nr)
+    tq.tm_set_march(ctx, tq.PREC_F32, tseg)
+    sol, st, _ = tq.tsm_solve_batch(ctx, p, 21, [0, 1, 2, 3])
+    for a, b in zip(st, st_ref):
+        assert a["converged"] and abs(a["iters"] - b["iters"]) <= 1, (a, b)
+    ref, sol = ref.cpu().numpy(), sol.cpu().numpy()
+    for i in range(4):
+        assert _rel(sol[i], ref[i]) < 1e-5, _rel(sol[i], ref[i])
+    ctx.close()
+
+
 def test_training_reduces_loss_and_solves(orc):
     """Training on harvested pairs lowers the loss; the trained network
     preconditions flexible CG to the same solution as plain CG."""
