@@ -161,6 +161,22 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float acc) {
     return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2, a), __builtin_bit_cast(bf16x2, b), acc, false);
 }
+// a.lo b.lo + a.hi b.hi: the three-operand form with a zero accumulator (the
+// builtin would first move a zero into a register for the two-operand form)
+__device__ __forceinline__ float dot2_0(uint32_t a, uint32_t b) {
+    float d;
+    asm("v_dot2_f32_bf16 %0, %1, %2, 0" : "=v"(d) : "v"(a), "v"(b));
+    return d;
+}
+
+// Hidden activations of the network (internal to the layers): bfloat16 pairs
+// in three 16-byte planes arranged so that each half spinor is one plane and
+// one half plane: plane 0 = components 0-3, plane 1 = 6-9, plane 2 = 4, 5 |
+// 10, 11.
+struct SBH {
+    using V = uint4;
+    static constexpr int NV = 3;
+};
 __device__ __forceinline__ uint32_t swap16(uint32_t x) { return __builtin_amdgcn_alignbit(x, x, 16); }
 
 // The lane's half spinor (components 6h .. 6h+5, spins 2h and 2h+1) of
@@ -177,6 +193,18 @@ __device__ __forceinline__ void half_spinor(const void* f, uint32_t PB, int b, u
     q[3] = h ? full.y : full.w;
     q[4] = h ? full.z : half.x;
     q[5] = h ? full.w : half.y;
+}
+__device__ __forceinline__ void half_spinor(const void* f, uint32_t PB, int b, uint32_t y, int h, uint32_t q[6],
+                                            SBH) {
+    const uint32_t base = (y << 4) + (uint32_t)b * 3u * PB;
+    const uint4 full = ldv128(f, base + (uint32_t)h * PB);
+    const uint2 half = ldv64(f, base + 2u * PB + (uint32_t)h * 8u);
+    q[0] = full.x;
+    q[1] = full.y;
+    q[2] = full.z;
+    q[3] = full.w;
+    q[4] = half.x;
+    q[5] = half.y;
 }
 __device__ __forceinline__ void half_spinor(const void* f, uint32_t PB, int b, uint32_t y, int h, uint32_t q[6],
                                             SF32) {
@@ -261,7 +289,7 @@ __device__ __forceinline__ void ly_operand(const void* in, uint32_t PB, int h, i
     for (int c = 0; c < 3; c++)
 #pragma unroll
         for (int t = 0; t < 2; t++) {
-            float tr = dot2(a1[3 * t], m[3 * c], 0.f), ti = dot2(a2[3 * t], m[3 * c], 0.f);
+            float tr = dot2_0(a1[3 * t], m[3 * c]), ti = dot2_0(a2[3 * t], m[3 * c]);
             tr = dot2(a1[3 * t + 1], m[3 * c + 1], tr);
             ti = dot2(a2[3 * t + 1], m[3 * c + 1], ti);
             tr = dot2(a1[3 * t + 2], m[3 * c + 2], tr);
@@ -389,7 +417,14 @@ __global__ __launch_bounds__(LY_THREADS) void k_pt_layer(PtArgs a, uint32_t nrhs
                     o[2 * (3 * t + c)] = D[j][c][2 * t];
                     o[2 * (3 * t + c) + 1] = D[j][c][2 * t + 1];
                 }
-            if constexpr (std::is_same<So, SF32>::value) {
+            if constexpr (std::is_same<So, SBH>::value) {
+                uint32_t w[6];
+#pragma unroll
+                for (int q = 0; q < 6; q++) w[q] = pack2_bf16(o[2 * q], o[2 * q + 1]);
+                const uint32_t base = (s << 4) + (uint32_t)ch * 3u * PB;
+                stv128(out, base + (uint32_t)h * PB, make_uint4(w[0], w[1], w[2], w[3]));
+                stv64(out, base + 2u * PB + (uint32_t)h * 8u, make_uint2(w[4], w[5]));
+            } else if constexpr (std::is_same<So, SF32>::value) {
                 const uint32_t base = (s << 4) + (uint32_t)ch * 6u * PB + (uint32_t)h * 3u * PB;
 #pragma unroll
                 for (int q = 0; q < 3; q++)
@@ -397,15 +432,7 @@ __global__ __launch_bounds__(LY_THREADS) void k_pt_layer(PtArgs a, uint32_t nrhs
                            make_uint4(__float_as_uint(o[4 * q]), __float_as_uint(o[4 * q + 1]),
                                       __float_as_uint(o[4 * q + 2]), __float_as_uint(o[4 * q + 3])));
             } else {
-                uint32_t w[6];
-#pragma unroll
-                for (int q = 0; q < 6; q++) w[q] = pack2_bf16(o[2 * q], o[2 * q + 1]);
-                const uint32_t base = (s << 4) + (uint32_t)ch * 3u * PB;
-                // h = 0: components 0-3 -> plane 0, 4-5 -> low half of plane 1
-                // h = 1: components 6-7 -> high half of plane 1, 8-11 -> plane 2
-                stv128(out, base + (h ? 2u * PB : 0u),
-                       h ? make_uint4(w[2], w[3], w[4], w[5]) : make_uint4(w[0], w[1], w[2], w[3]));
-                stv64(out, base + PB + (h ? 8u : 0u), h ? make_uint2(w[0], w[1]) : make_uint2(w[4], w[5]));
+                static_assert(std::is_same<So, SF32>::value || std::is_same<So, SBH>::value, "FP32 or SBH output");
             }
         }
     }
@@ -538,11 +565,17 @@ static void launch_pt_layer_t(hipStream_t st, const PtArgs& a, int nrhs) {
 }
 
 void launch_pt_layer(hipStream_t st, const PtArgs& a, int in_prec, int out_prec, int nrhs) {
-    const bool ib = in_prec == P_BF16, ob = out_prec == P_BF16;
-    if (ib && ob) launch_pt_layer_t<SBF16, SBF16>(st, a, nrhs);
-    else if (ib) launch_pt_layer_t<SBF16, SF32>(st, a, nrhs);
-    else if (ob) launch_pt_layer_t<SF32, SBF16>(st, a, nrhs);
-    else launch_pt_layer_t<SF32, SF32>(st, a, nrhs);
+    const bool ob = out_prec == P_BH;
+    if (in_prec == P_BH) {
+        if (ob) launch_pt_layer_t<SBH, SBH>(st, a, nrhs);
+        else launch_pt_layer_t<SBH, SF32>(st, a, nrhs);
+    } else if (in_prec == P_BF16) {
+        if (ob) launch_pt_layer_t<SBF16, SBH>(st, a, nrhs);
+        else launch_pt_layer_t<SBF16, SF32>(st, a, nrhs);
+    } else {
+        if (ob) launch_pt_layer_t<SF32, SBH>(st, a, nrhs);
+        else launch_pt_layer_t<SF32, SF32>(st, a, nrhs);
+    }
 }
 
 void launch_pt_wgrad(hipStream_t st, const PtArgs& a, int in_prec, const double* scale, double* grad) {

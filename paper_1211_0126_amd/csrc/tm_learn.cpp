@@ -152,12 +152,13 @@ static void layer_launch(tm_ctx* ctx, int l, bool adjoint, const void* in, int i
 
 // out = N(in) or N^dag(in); single fields, nrhs of them.  The hidden
 // activations are stored as bfloat16 (the precision the mixing GEMM reads
-// them in); out is written in out_prec.
+// them in) in the layers' half-split plane order (P_BH); out is written in
+// out_prec (FP32 or P_BH).
 tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_prec, void* out, int out_prec,
                     const FcgScal* gate) {
     NetState* ns = ctx->net;
     tm_status s = TM_OK;
-    const size_t fb = field_bytes(ctx->geo, P_BF16, 2 * nrhs);
+    const size_t fb = field_bytes(ctx->geo, P_BH, 2 * nrhs);
     void* A = ws_get(ctx, "net_a", fb, &s);
     void* B = ws_get(ctx, "net_b", fb, &s);
     if (s != TM_OK) return s;
@@ -167,7 +168,7 @@ tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_
         const int l = adjoint ? ns->nl - 1 - i : i;
         const bool last = i == ns->nl - 1;
         void* dst = last ? out : ((i % 2 == 0) ? A : B);
-        const int dst_prec = last ? out_prec : P_BF16;
+        const int dst_prec = last ? out_prec : P_BH;
         prof_begin(ctx, TM_KC_OTHER);
         layer_launch(ctx, l, adjoint, cur, cur_prec, dst, nrhs, dst_prec, gate);
         prof_end(ctx, TM_KC_OTHER, 0.0);
@@ -178,14 +179,14 @@ tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_
     return TM_OK;
 }
 
-// z = N(N^dag(r)), r and z FP32, the middle field bfloat16; right-hand sides
+// z = N(N^dag(r)), r and z FP32, the middle field bfloat16 (P_BH); right-hand sides
 // that gate marks converged or fallen back are skipped (z keeps its values)
 tm_status net_precondition(tm_ctx* ctx, int nrhs, const void* r, void* z, const FcgScal* gate) {
     tm_status s = TM_OK;
-    void* tmp = ws_get(ctx, "net_mid", field_bytes(ctx->geo, P_BF16, nrhs), &s);
+    void* tmp = ws_get(ctx, "net_mid", field_bytes(ctx->geo, P_BH, nrhs), &s);
     if (s != TM_OK) return s;
-    if ((s = net_apply(ctx, true, nrhs, r, P_F32, tmp, P_BF16, gate)) != TM_OK) return s;
-    return net_apply(ctx, false, nrhs, tmp, P_BF16, z, P_F32, gate);
+    if ((s = net_apply(ctx, true, nrhs, r, P_F32, tmp, P_BH, gate)) != TM_OK) return s;
+    return net_apply(ctx, false, nrhs, tmp, P_BH, z, P_F32, gate);
 }
 
 bool net_installed(const tm_ctx* ctx) { return ctx->net != nullptr; }

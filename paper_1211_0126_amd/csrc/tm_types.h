@@ -54,6 +54,6 @@ struct Geom {
     uint32_t m[3];  // ceil(2^32 / L[d]) for exact division of site indices
 };
 
-enum SPrec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3 };
+enum SPrec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3, P_BH = 4 /* network-internal bfloat16, half-split planes */ };
 
 }  // namespace tmq
