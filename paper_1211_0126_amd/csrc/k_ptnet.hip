@@ -5,19 +5,19 @@
 //     psi_a(x) = sum_b sum_p W[p][a][b] (T_p phi_b)(x),
 // p over nine paths (identity, U_mu(x) phi(x+mu), U_mu(x-mu)^dag phi(x-mu),
 // with the time-boundary sign), W[p][a][b] a complex 4x4 spin matrix,
-// identity on colour.  Both kernels below follow the same three steps:
-//   1. gather: every (site, path, channel) transport is computed once with
-//      the FP32 links and written as bfloat16 into an LDS tile A whose rows
-//      are (colour, site) and columns (path, channel, spin, re/im);
-//   2. mix: the dense channel/spin mixing is a real GEMM A(rows x K) B(K x 16)
-//      on the matrix cores (v_mfma_f32_16x16x16_bf16, FP32 accumulation),
-//      B the real form of the complex weights, K = 72 cin padded to 16;
-//   3. the FP32 result is staged in LDS and written as spinor planes.
+// identity on colour.  The channel/spin mixing is a real GEMM over
+// K = 72 cin (path, channel, spin, re/im; padded to 16) on the matrix cores
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation) with the real form of the
+// complex weights:
+//   * layer application (k_pt_layer): the sites are the GEMM's N side and the
+//     transports are computed in registers straight into its B operand (see
+//     the comment at the kernel);
+//   * weight gradient (k_pt_wgrad): dW = sum_{x,c} g (T_p phi)^dag as the GEMM
+//     G^T (16 x rows) A (rows x K) per block of PT_TS sites, A the transports
+//     gathered into an LDS tile with rows (colour, site), FP32 block partials
+//     reduced in a fixed order.
 // The adjoint layer is the same kernel with weights W'[p*][b][a] = W[p][a][b]^dag
 // (p* the reversed path), prepared on the host.
-// The weight gradient dW = sum_{x,c} g (T_p phi)^dag is the GEMM
-// G^T (16 x rows) A (rows x K) per block of PT_TS sites, FP32 block partials
-// reduced in a fixed order.
 
 #include "tm_device.h"
 #include "tm_kernels.h"
