@@ -16,6 +16,7 @@ from .oracle import (  # noqa: F401
     apply_op,
     cgnr,
     loops,
+    loops_est,
     tsm,
     set_threads,
     get_threads,
@@ -25,6 +26,9 @@ from .oracle import (  # noqa: F401
     OP_HOP,
     STOP_NORMAL,
     STOP_TRUE,
+    LOOP_STD,
+    LOOP_ONEEND_VV,
+    LOOP_ONEEND_GEN,
     layer_weight_count,
     net_weight_count,
     pt_layer,

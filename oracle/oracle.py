@@ -19,6 +19,7 @@ _LIB = os.path.join(_HERE, "libtmoracle.so")
 
 OP_M, OP_MDAG, OP_MDAGM, OP_HOP = 0, 1, 2, 3
 STOP_NORMAL, STOP_TRUE = 0, 1
+LOOP_STD, LOOP_ONEEND_VV, LOOP_ONEEND_GEN = 0, 1, 2
 
 _lib = None
 
@@ -57,8 +58,9 @@ def load_oracle():
     lib.orc_cgnr.argtypes = [P, i32, f64, f64, P, P, f64, i32, i32, P, P]
     lib.orc_cgnr.restype = i32
     lib.orc_loops.argtypes = [P, P, P, i32, P, P]
+    lib.orc_loops_est.argtypes = [P, i32, f64, f64, P, i32, P, P, i32, P, P]
     lib.orc_tsm.argtypes = [P, i32, f64, f64, P, u64, i32, i32, f64, i32, i32, f64, i32, i32,
-                            i32, P, P, P, P, P]
+                            i32, P, i32, P, P, P, P]
     lib.orc_tsm.restype = i32
     lib.orc_pt_layer.argtypes = [P, i32, P, i32, i32, P, P, P]
     lib.orc_pt_layer_adj.argtypes = [P, i32, P, i32, i32, P, P, P]
@@ -161,8 +163,24 @@ def loops(dims, eta, s, mom) -> np.ndarray:
     return out
 
 
+def loops_est(dims, t_bc, kappa, mu, U, est, s, mom, eta=None) -> np.ndarray:
+    """Loops of estimator est (LOOP_STD needs eta; the one-end estimators of
+    section 2.3, Eqs. 5 and 6, use the solution alone): complex128
+    [16][n_mom][Lt]."""
+    d = _dims(dims)
+    mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros((16, mom.shape[0], int(d[3])), dtype=np.complex128)
+    if est == LOOP_STD and eta is None:
+        raise ValueError("the standard loop needs the source")
+    e = _c128(eta) if eta is not None else None
+    load_oracle().orc_loops_est(_ptr(d), int(t_bc), float(kappa), float(mu), _ptr(_c128(U)), int(est),
+                                _ptr(e) if e is not None else None, _ptr(_c128(s)), mom.shape[0], _ptr(mom),
+                                _ptr(out))
+    return out
+
+
 def tsm(dims, t_bc, kappa, mu, U, seed, n_hp, n_lp, lp_tol, lp_maxit, hp_tol, hp_maxit, mom,
-        lp_stop=STOP_NORMAL, hp_stop=STOP_NORMAL, per_source=False):
+        lp_stop=STOP_NORMAL, hp_stop=STOP_NORMAL, per_source=False, estimator=LOOP_STD):
     """Returns dict with 'loops' [3][16][n_mom][Lt] (C, B, T), 'err', optional
     'per_source' [N][2][16][n_mom][Lt] and 'stats' [N][2][5]."""
     d = _dims(dims)
@@ -177,7 +195,8 @@ def tsm(dims, t_bc, kappa, mu, U, seed, n_hp, n_lp, lp_tol, lp_maxit, hp_tol, hp
     st = np.zeros((max(n, 1), 2, 5), dtype=np.float64)
     load_oracle().orc_tsm(_ptr(d), int(t_bc), float(kappa), float(mu), _ptr(U), int(seed), int(n_hp), int(n_lp),
                           float(lp_tol), int(lp_maxit), int(lp_stop), float(hp_tol), int(hp_maxit), int(hp_stop),
-                          nm, _ptr(mom), _ptr(out), _ptr(err), _ptr(ps) if ps is not None else None, _ptr(st))
+                          nm, _ptr(mom), int(estimator), _ptr(out), _ptr(err), _ptr(ps) if ps is not None else None,
+                          _ptr(st))
     res = {"loops": out, "err": err, "stats": st[:n]}
     if ps is not None:
         res["per_source"] = ps[:n]

@@ -414,11 +414,89 @@ void orc_loops(const int *L, const double *eta_, const double *s_, int n_mom,
 }
 
 /* ------------------------------------------------------------------ */
+/* one-end trick loops (section 2.3, Eqs. 5 and 6)                     */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Loops that use the solution on both sides of the bilinear; the source
+ * does not appear.  With s = M_u^{-1} eta (M_u the operator above, M_d the
+ * same operator with mu -> -mu, both in hopping normalisation) and
+ * tw = 2 kappa mu:
+ *
+ *   est 1, isovector (Eq. 5):
+ *     out[n][m][t] += -2i tw sum_{x in t} exp(-i p_m.x) s(x)^dag g5 Gamma_n s(x)
+ *   whose noise average is Tr over the timeslice of
+ *   exp(-i p.x) Gamma_n (M_u^{-1} - M_d^{-1}).  The factor follows from
+ *   M_u - M_d = 2i tw g5: M_u^{-1} - M_d^{-1} = -2i tw M_u^{-1} (M_u^{-1})^dag g5
+ *   (with g5 M_u g5 = M_d^dag); the printed sign of Eq. 5 is the opposite.
+ *
+ *   est 2, generalized (Eq. 6):
+ *     out[n][m][t] += 2 sum_{x in t} exp(-i p_m.x) s(x)^dag g5 Gamma_n g5 (D s)(x)
+ *   with D = (M_u + M_d)/2 = 1 - kappa H (the operator at mu = 0), whose
+ *   noise average is the same trace of Gamma_n (M_u^{-1} + M_d^{-1}).
+ *
+ * est 0 is the standard loop of orc_loops (eta must then be given).  out is
+ * complex128 [16][n_mom][Lt], accumulated into.
+ */
+void orc_loops_est(const int *L, int t_bc, double kappa, double mu, const double *U_, int est,
+                   const double *eta_, const double *s_, int n_mom, const int *mom, double *out_)
+{
+    if (est == 0) {
+        orc_loops(L, eta_, s_, n_mom, mom, out_);
+        return;
+    }
+    const cplx *sv = (const cplx *)s_;
+    cplx *out = (cplx *)out_;
+    long V = volume(L);
+    int Lt = L[3];
+    cplx *right = malloc(sizeof(cplx) * V * NCOMP);
+    cplx G[16][4][4], g5[4][4], coef;
+    gamma5(g5);
+    for (int n = 0; n < 16; n++) {
+        cplx gn[4][4];
+        orc_gamma(n, (double *)gn);
+        matmul4(g5, gn, G[n]);
+        if (est == 2) matmul4(G[n], g5, G[n]);
+    }
+    if (est == 1) {
+        coef = -2.0 * I * (2.0 * kappa * mu);
+        memcpy(right, sv, sizeof(cplx) * V * NCOMP);
+    } else {
+        coef = 2.0;
+        apply_m(L, t_bc, kappa, 0.0, (const cplx *)U_, sv, right, 0);
+    }
+    const double twopi = 2.0 * acos(-1.0);
+    for (long s = 0; s < V; s++) {
+        int c[4];
+        site_coords(L, s, c);
+        cplx tr[16];
+        for (int n = 0; n < 16; n++) {
+            cplx acc = 0;
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) {
+                    if (G[n][a][b] == 0) continue;
+                    for (int k = 0; k < NCOL; k++)
+                        acc += conj(sv[s * NCOMP + a * NCOL + k]) * G[n][a][b] * right[s * NCOMP + b * NCOL + k];
+                }
+            tr[n] = coef * acc;
+        }
+        for (int m = 0; m < n_mom; m++) {
+            double arg = twopi * ((double)mom[3 * m] * c[0] / L[0] + (double)mom[3 * m + 1] * c[1] / L[1] +
+                                  (double)mom[3 * m + 2] * c[2] / L[2]);
+            cplx ph = cexp(-I * arg);
+            for (int n = 0; n < 16; n++) out[((long)n * n_mom + m) * Lt + c[3]] += ph * tr[n];
+        }
+    }
+    free(right);
+}
+
+/* ------------------------------------------------------------------ */
 /* TSM estimator (Eq. 4)                                               */
 /* ------------------------------------------------------------------ */
 
 /*
- * Eq. 4 applied to the loops:
+ * Eq. 4 applied to the loops of estimator est (0 standard, 1 and 2 the
+ * one-end loops of orc_loops_est):
  *   C = (1/N_HP) sum_{j in HP} [L(s_j^HP) - L(s_j^LP)]    (correction)
  *   B = (1/N_LP) sum_{j in LP} L(s_j^LP)                  (biased estimate)
  *   T = C + B
@@ -439,7 +517,7 @@ int orc_tsm(const int *L, int t_bc, double kappa, double mu, const double *U,
             uint64_t seed, int n_hp, int n_lp,
             double lp_tol, int lp_maxit, int lp_stop,
             double hp_tol, int hp_maxit, int hp_stop,
-            int n_mom, const int *mom,
+            int n_mom, const int *mom, int est,
             double *out_, double *err_, double *per_src_, double *src_stats)
 {
     long V = volume(L);
@@ -463,12 +541,12 @@ int orc_tsm(const int *L, int t_bc, double kappa, double mu, const double *U,
         orc_cgnr(L, t_bc, kappa, mu, U, (double *)eta, lp_tol, lp_maxit, lp_stop, (double *)s, st);
         if (src_stats) memcpy(src_stats + (j * 2 + 0) * 5, st, sizeof(st));
         memset(l_lp, 0, sizeof(cplx) * nl);
-        orc_loops(L, (double *)eta, (double *)s, n_mom, mom, (double *)l_lp);
+        orc_loops_est(L, t_bc, kappa, mu, U, est, (double *)eta, (double *)s, n_mom, mom, (double *)l_lp);
         memset(l_hp, 0, sizeof(cplx) * nl);
         if (is_hp) {
             orc_cgnr(L, t_bc, kappa, mu, U, (double *)eta, hp_tol, hp_maxit, hp_stop, (double *)s, st);
             if (src_stats) memcpy(src_stats + (j * 2 + 1) * 5, st, sizeof(st));
-            orc_loops(L, (double *)eta, (double *)s, n_mom, mom, (double *)l_hp);
+            orc_loops_est(L, t_bc, kappa, mu, U, est, (double *)eta, (double *)s, n_mom, mom, (double *)l_hp);
             for (long k = 0; k < nl; k++) {
                 cplx d = l_hp[k] - l_lp[k];
                 sumC[k] += d;
