@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define TM_ABI_VERSION 1
+#define TM_ABI_VERSION 2
 
 typedef int32_t tm_status;
 enum {
@@ -134,6 +134,24 @@ typedef struct {
     double resid_true;      /* FP64 |eta - M s| / |eta| */
 } tsm_solve_stats;
 
+/* The loop estimator of one source (section 2.3), all in the hopping
+   normalisation of the operator (M = 1 - kappa H + 2i kappa mu g5 = M_u;
+   M_d is the same with mu -> -mu; tw = 2 kappa mu; X = the phase-weighted
+   insertion Gamma_n on one timeslice):
+   STANDARD:           eta^dag Gamma_n s, whose noise average is Tr[X M_u^{-1}];
+   ONEEND_ISOVECTOR:   -2i tw s^dag g5 Gamma_n s (Eq. 5), noise average
+                       Tr[X M_u^{-1}] - Tr[X M_d^{-1}]; the factor follows
+                       from M_u - M_d = 2i tw g5 (Eq. 5 prints the opposite
+                       sign);
+   ONEEND_GENERALIZED: 2 s^dag g5 Gamma_n g5 D s with D = 1 - kappa H (Eq. 6),
+                       noise average Tr[X M_u^{-1}] + Tr[X M_d^{-1}]; one
+                       extra FP64 stencil application per source. */
+typedef enum {
+    TM_LOOP_STANDARD = 0,
+    TM_LOOP_ONEEND_ISOVECTOR = 1,
+    TM_LOOP_ONEEND_GENERALIZED = 2
+} tm_loop_estimator;
+
 typedef struct {
     uint64_t seed;          /* noise seed; source ids are 0..n_hp+n_lp-1 */
     int32_t n_hp;           /* sources solved to high and low precision (ids 0..n_hp-1) */
@@ -142,6 +160,8 @@ typedef struct {
     tsm_solve_params hp;    /* the HP solver */
     int32_t n_mom;          /* number of momenta (>= 1) */
     const int32_t* mom_host;/* [n_mom][3] integer momenta n, p = 2 pi n / L */
+    int32_t estimator;      /* tm_loop_estimator of every per-source loop */
+    int32_t reserved;
 } tsm_params;
 
 typedef struct {
@@ -227,7 +247,15 @@ tm_status tsm_solve_batch(tm_ctx* ctx, const tsm_solve_params* params, uint64_t 
 tm_status tsm_contract(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* ids_host,
                        const double* sol_dev, int32_t n_mom, const int32_t* mom_host, double* loops_host);
 
-/* The whole TSM estimate of Eq. 4 for the loops:
+/* tsm_contract with the loop estimator chosen (tm_loop_estimator; section
+   2.3, Eqs. 5 and 6).  The one-end estimators use the solutions alone:
+   seed and ids_host are ignored and ids_host may be NULL.  The generalized
+   one needs the gauge field (TM_ESTATE otherwise) and applies D in FP64 to
+   each solution.  TM_EINVAL for an unknown estimator.  Synchronous. */
+tm_status tsm_contract_est(tm_ctx* ctx, int32_t estimator, uint64_t seed, int32_t nsrc, const uint64_t* ids_host,
+                           const double* sol_dev, int32_t n_mom, const int32_t* mom_host, double* loops_host);
+
+/* The whole TSM estimate of Eq. 4 for the loops L of params->estimator:
      C = (1/N_HP) sum_{j < N_HP} [L(s_j^HP) - L(s_j^LP)],
      B = (1/N_LP) sum_{N_HP <= j < N_HP+N_LP} L(s_j^LP),   T = C + B,
    with every LP solve (of both sets) done by params->lp and the HP solves by
@@ -242,7 +270,7 @@ tm_status tsm_contract(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t*
    stats_host (nullable): tsm_solve_stats [N_HP+N_LP][2] (slot 0 LP, 1 HP).
    run_stats (nullable): timings and totals.
    Synchronous.  Returns TM_WARN_NOT_CONVERGED if an HP solve missed its
-   tolerance. */
+   tolerance; TM_EINVAL for an unknown params->estimator. */
 tm_status tsm_loops(tm_ctx* ctx, const tsm_params* params, double* loops_host, double* err_host,
                     double* per_source_host, tsm_solve_stats* stats_host, tsm_run_stats* run_stats);
 

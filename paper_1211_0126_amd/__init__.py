@@ -49,4 +49,7 @@ from .binding import (  # noqa: F401
     LAYOUT_NATIVE,
     STOP_NORMAL,
     STOP_TRUE,
+    LOOP_STANDARD,
+    LOOP_ONEEND_ISOVECTOR,
+    LOOP_ONEEND_GENERALIZED,
 )

@@ -22,6 +22,7 @@ OP_M, OP_MDAG, OP_MDAGM, OP_HOP = 0, 1, 2, 3
 LAYOUT_CANONICAL, LAYOUT_NATIVE = 0, 1
 STOP_NORMAL, STOP_TRUE = 0, 1
 SOLVER_CG, SOLVER_FCG_LEARNED = 0, 1
+LOOP_STANDARD, LOOP_ONEEND_ISOVECTOR, LOOP_ONEEND_GENERALIZED = 0, 1, 2
 KC_NAMES = ["dslash", "dslash_upd", "blas", "contract", "other", "apply"]
 
 
@@ -50,7 +51,8 @@ class SolveStats(ctypes.Structure):
 class TsmParams(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("n_hp", ctypes.c_int32), ("n_lp", ctypes.c_int32),
                 ("lp", SolveParams), ("hp", SolveParams), ("n_mom", ctypes.c_int32),
-                ("mom_host", ctypes.POINTER(ctypes.c_int32))]
+                ("mom_host", ctypes.POINTER(ctypes.c_int32)), ("estimator", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class RunStats(ctypes.Structure):
@@ -62,7 +64,8 @@ class RunStats(ctypes.Structure):
 
 EXPORTS = [
     "tm_abi_version", "tm_create", "tm_destroy", "tm_last_error", "tm_gauge_load", "tm_field_bytes",
-    "tm_field_convert", "tm_dslash", "tm_noise_z4", "tsm_solve_batch", "tsm_contract", "tsm_loops",
+    "tm_field_convert", "tm_dslash", "tm_noise_z4", "tsm_solve_batch", "tsm_contract", "tsm_contract_est",
+    "tsm_loops",
     "tm_profile_enable", "tm_profile_read",
 ]
 
@@ -95,6 +98,7 @@ def load_library(path: str = LIB_PATH):
     lib.tm_noise_z4.argtypes = [P, u64, i32, P, P]
     lib.tsm_solve_batch.argtypes = [P, ctypes.POINTER(SolveParams), u64, i32, P, P, P]
     lib.tsm_contract.argtypes = [P, u64, i32, P, P, i32, P, P]
+    lib.tsm_contract_est.argtypes = [P, i32, u64, i32, P, P, i32, P, P]
     lib.tsm_loops.argtypes = [P, ctypes.POINTER(TsmParams), P, P, P, P, ctypes.POINTER(RunStats)]
     lib.tm_profile_enable.argtypes = [P, i32]
     lib.tm_profile_read.argtypes = [P, P, P, P]
@@ -229,26 +233,33 @@ def tsm_solve_batch(ctx: Context, params: SolveParams, seed, ids, want_solutions
     return sol, _stats_list(st[:n]), rc
 
 
-def tsm_contract(ctx: Context, seed, ids, sol, mom):
-    """Loops of given solutions, complex128 [n][16][n_mom][Lt] (host)."""
-    ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64))
+def tsm_contract(ctx: Context, seed, ids, sol, mom, estimator=LOOP_STANDARD):
+    """Loops of given solutions, complex128 [n][16][n_mom][Lt] (host).  The
+    one-end estimators ignore seed and ids (pass ids=None and the count comes
+    from sol)."""
+    import torch
+    n = len(ids) if ids is not None else int(sol.shape[0])
+    ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64)) if ids is not None else None
     mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
-    out = np.zeros((len(ids), 16, mom.shape[0], ctx.dims[3]), dtype=np.complex128)
-    assert sol.is_cuda and sol.is_contiguous() and tuple(sol.shape) == (len(ids), ctx.V, 4, 3)
-    ctx.check(ctx.lib.tsm_contract(ctx.h, int(seed), len(ids), _ptr(ids), ctypes.c_void_p(sol.data_ptr()),
-                                   mom.shape[0], _ptr(mom), _ptr(out)))
+    out = np.zeros((n, 16, mom.shape[0], ctx.dims[3]), dtype=np.complex128)
+    assert sol.is_cuda and sol.is_contiguous() and tuple(sol.shape) == (n, ctx.V, 4, 3)
+    assert sol.dtype == torch.complex128
+    ctx.check(ctx.lib.tsm_contract_est(ctx.h, int(estimator), int(seed), n,
+                                       _ptr(ids_a) if ids_a is not None else None,
+                                       ctypes.c_void_p(sol.data_ptr()), mom.shape[0], _ptr(mom), _ptr(out)))
     return out
 
 
 def tsm_loops(ctx: Context, seed, n_hp, n_lp, lp: SolveParams, hp: SolveParams, mom, per_source=False,
-              stats=True):
+              stats=True, estimator=LOOP_STANDARD):
     """The TSM estimate (Eq. 4).  Returns dict with 'loops' [3][16][n_mom][Lt]
     (C, B, T), 'err', optional 'per_source' [N][2][16][n_mom][Lt], 'stats'
     (list of [LP, HP] records), 'run' and the status code."""
     mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
     nm, lt = mom.shape[0], ctx.dims[3]
     N = n_hp + n_lp
-    P = TsmParams(int(seed), int(n_hp), int(n_lp), lp, hp, nm, mom.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    P = TsmParams(int(seed), int(n_hp), int(n_lp), lp, hp, nm, mom.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                  int(estimator), 0)
     loops = np.zeros((3, 16, nm, lt), dtype=np.complex128)
     err = np.zeros_like(loops)
     ps = np.zeros((max(N, 1), 2, 16, nm, lt), dtype=np.complex128) if per_source else None

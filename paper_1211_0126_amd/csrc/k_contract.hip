@@ -2,9 +2,16 @@
 //
 // For one source the loop is (section 2.3 of the paper, for all insertion
 // times as in section 3)
-//   L_n(t, p) = sum_{x in t} exp(-i p.x) Tr[Gamma_n S(x)],
-//   S_{ba}(x) = sum_c s_{bc}(x) conj(eta_{ac}(x)),
-// with eta regenerated from the noise hash.  The Fourier sum is separable,
+//   L_n(t, p) = f sum_{x in t} exp(-i p.x) Tr[X_n S(x)],
+//   S_{ba}(x) = sum_c u_{bc}(x) conj(v_{ac}(x)),
+// in one of three forms:
+//   est 0 (standard):     u = s, v = eta, X_n = Gamma_n, f = 1,
+//                         eta regenerated from the noise hash;
+//   est 1 (Eq. 5):        u = v = s, X_n = g5 Gamma_n, f = -2i (2 kappa mu);
+//   est 2 (Eq. 6):        u = D s, v = s, X_n = g5 Gamma_n g5, f = 2,
+//                         D s = (1 - kappa H) s from the FP64 stencil.
+// The one-end forms estimate Tr[X (M_u^{-1} -+ M_d^{-1})] with M_d the
+// operator at -mu.  The Fourier sum is separable,
 // so it is done one axis at a time over the distinct per-axis momentum
 // components (3 each for the 27 momenta with |n_i| <= 1):
 //   A: per (x, z, t) row, sum over y with the y phases   (reads s once)
@@ -12,6 +19,8 @@
 //   C: sum over z with the z phases and the Gamma traces (each Gamma_n is
 //      a phase-signed permutation: 4 terms)
 // All sums are in FP64 and in a fixed order (bitwise reproducible).
+
+#include <type_traits>
 
 #include "tm_device.h"
 #include "tm_kernels.h"
@@ -50,7 +59,7 @@ __device__ __forceinline__ cx<double> z4_conj_times(uint32_t k, cx<double> p) {
     return {sr * re, si * im};
 }
 
-template <class S>
+template <class S, int E>
 __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
     const Geom& g = a.geo;
     const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
@@ -74,20 +83,42 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
         for (int e = 0; e < 8; e++) acc[i][e] = {0.0, 0.0};
     for (int y = 0; y < Ly; y++) {
         const uint32_t s = x + Lx * (y + Ly * (z + Lz * t));
-        cx<double> p[6];
-        load_half_spinor<S>(sol, g.Vs, s, h, p);
-        const uint64_t bits = noise_bits(a.seed_mixed, id, (uint64_t)g.V, (uint64_t)s);
         cx<double> S8[8];
+        if constexpr (E == 0) {
+            cx<double> p[6];
+            load_half_spinor<S>(sol, g.Vs, s, h, p);
+            const uint64_t bits = noise_bits(a.seed_mixed, id, (uint64_t)g.V, (uint64_t)s);
 #pragma unroll
-        for (int b = 0; b < 2; b++)
+            for (int b = 0; b < 2; b++)
 #pragma unroll
-            for (int al = 0; al < 4; al++) {
-                cx<double> v = {0.0, 0.0};
+                for (int al = 0; al < 4; al++) {
+                    cx<double> v = {0.0, 0.0};
 #pragma unroll
-                for (int c = 0; c < 3; c++)
-                    v = v + z4_conj_times((uint32_t)(bits >> (2 * (3 * al + c))) & 3u, p[3 * b + c]);
-                S8[4 * b + al] = v;
+                    for (int c = 0; c < 3; c++)
+                        v = v + z4_conj_times((uint32_t)(bits >> (2 * (3 * al + c))) & 3u, p[3 * b + c]);
+                    S8[4 * b + al] = v;
+                }
+        } else {
+            // v = s (all four spin rows); u = rows 2h, 2h+1 of s or of D s
+            cx<double> q[12], u[6];
+            load_half_spinor<S>(sol, g.Vs, s, 0, q);
+            load_half_spinor<S>(sol, g.Vs, s, 1, q + 6);
+            if constexpr (E == 1) {
+#pragma unroll
+                for (int k = 0; k < 6; k++) u[k] = h ? q[6 + k] : q[k];
+            } else {
+                load_half_spinor<SF64>(field_rhs<SF64>(a.dsol, g.Vs, r), g.Vs, s, h, u);
             }
+#pragma unroll
+            for (int b = 0; b < 2; b++)
+#pragma unroll
+                for (int al = 0; al < 4; al++) {
+                    cx<double> v = {0.0, 0.0};
+#pragma unroll
+                    for (int c = 0; c < 3; c++) v = v + cmulc(q[3 * al + c], u[3 * b + c]);
+                    S8[4 * b + al] = v;
+                }
+        }
         // fully unrolled with predicates: a runtime bound on i would index
         // acc dynamically and move it to scratch memory
 #pragma unroll
@@ -175,6 +206,7 @@ __global__ __launch_bounds__(256) void k_contract_c(ContractArgs a) {
         const double2 pz = a.phz[iz * Lz + z];
         acc = acc + cx<double>{pz.x, pz.y} * tr;
     }
+    acc = cx<double>{a.coef.x, a.coef.y} * acc;
     double2* o = a.out + (size_t)a.out_slot[r] * a.out_stride;
     o[((size_t)gn * a.n_mom + m) * Lt + t] = make_double2(acc.re, acc.im);
 }
@@ -183,10 +215,19 @@ void launch_contract(hipStream_t st, const ContractArgs& a, int xprec) {
     const Geom& g = a.geo;
     const long nrow = 2L * g.L[0] * g.L[2] * g.L[3];
     dim3 ga((unsigned)((nrow + 255) / 256), (unsigned)a.nrhs);
-    if (xprec == P_F64)
-        hipLaunchKernelGGL((k_contract_a<SF64>), ga, dim3(256), 0, st, a);
+    auto run_a = [&](auto est) {
+        constexpr int E = decltype(est)::value;
+        if (xprec == P_F64)
+            hipLaunchKernelGGL((k_contract_a<SF64, E>), ga, dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_contract_a<SF32, E>), ga, dim3(256), 0, st, a);
+    };
+    if (a.est == 1)
+        run_a(std::integral_constant<int, 1>{});
+    else if (a.est == 2)
+        run_a(std::integral_constant<int, 2>{});
     else
-        hipLaunchKernelGGL((k_contract_a<SF32>), ga, dim3(256), 0, st, a);
+        run_a(std::integral_constant<int, 0>{});
     const long nb = 16L * a.npy * g.L[2] * g.L[3];
     hipLaunchKernelGGL(k_contract_b, dim3((unsigned)((nb + 255) / 256), (unsigned)a.nrhs), dim3(256), 0, st, a);
     const long nc = 16L * a.n_mom * g.L[3];

@@ -2,6 +2,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <array>
 #include <complex>
 #include <vector>
 
@@ -102,11 +103,22 @@ void prof_end(tm_ctx* ctx, int kc, double bytes) {
 
 // Gamma_n = g1^b0 g2^b1 g3^b2 g4^b3 of the Euclidean chiral basis
 // (gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = [[0, 1], [1, 0]]),
-// as the column and phase i^k of the one nonzero entry of each row.
-static void gamma_tables(int col[16][4], int ph[16][4]) {
+// as the column and phase i^k of the one nonzero entry of each row.  Table
+// e = 0 holds Gamma_n, e = 1 g5 Gamma_n and e = 2 g5 Gamma_n g5 (the
+// matrices of the standard loop and of the two one-end loops of Eqs. 5 and
+// 6), g5 = Gamma_15; each is again a phase-signed permutation.
+static void gamma_tables(int col[3][16][4], int ph[3][16][4]) {
     using C = std::complex<double>;
+    using M4 = std::array<std::array<C, 4>, 4>;
     const C I(0, 1);
-    C g[4][4][4] = {};
+    auto mul = [](const M4& a, const M4& b) {
+        M4 t{};
+        for (int i = 0; i < 4; i++)
+            for (int j = 0; j < 4; j++)
+                for (int k = 0; k < 4; k++) t[i][j] += a[i][k] * b[k][j];
+        return t;
+    };
+    M4 g[4] = {};
     // gamma_1
     g[0][0][3] = -I; g[0][1][2] = -I; g[0][2][1] = I; g[0][3][0] = I;
     // gamma_2
@@ -115,26 +127,27 @@ static void gamma_tables(int col[16][4], int ph[16][4]) {
     g[2][0][2] = -I; g[2][1][3] = I; g[2][2][0] = I; g[2][3][1] = -I;
     // gamma_4
     g[3][0][2] = 1.0; g[3][1][3] = 1.0; g[3][2][0] = 1.0; g[3][3][1] = 1.0;
+    M4 G[16];
     for (int n = 0; n < 16; n++) {
-        C m[4][4] = {};
+        M4 m{};
         for (int i = 0; i < 4; i++) m[i][i] = 1.0;
-        for (int mu = 0; mu < 4; mu++) {
-            if (!((n >> mu) & 1)) continue;
-            C t[4][4] = {};
-            for (int i = 0; i < 4; i++)
-                for (int j = 0; j < 4; j++)
-                    for (int k = 0; k < 4; k++) t[i][j] += m[i][k] * g[mu][k][j];
-            std::memcpy(m, t, sizeof(t));
-        }
-        for (int a = 0; a < 4; a++) {
-            for (int b = 0; b < 4; b++) {
-                if (std::abs(m[a][b]) < 0.5) continue;
-                col[n][a] = b;
-                C v = m[a][b];
-                ph[n][a] = v.real() > 0.5 ? 0 : (v.imag() > 0.5 ? 1 : (v.real() < -0.5 ? 2 : 3));
-            }
-        }
+        for (int mu = 0; mu < 4; mu++)
+            if ((n >> mu) & 1) m = mul(m, g[mu]);
+        G[n] = m;
     }
+    for (int e = 0; e < 3; e++)
+        for (int n = 0; n < 16; n++) {
+            M4 m = G[n];
+            if (e >= 1) m = mul(G[15], m);
+            if (e == 2) m = mul(m, G[15]);
+            for (int a = 0; a < 4; a++)
+                for (int b = 0; b < 4; b++) {
+                    if (std::abs(m[a][b]) < 0.5) continue;
+                    col[e][n][a] = b;
+                    const C v = m[a][b];
+                    ph[e][n][a] = v.real() > 0.5 ? 0 : (v.imag() > 0.5 ? 1 : (v.real() < -0.5 ? 2 : 3));
+                }
+        }
 }
 
 }  // namespace tmq
@@ -201,11 +214,13 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
         delete ctx;
         return TM_EDEVICE;
     }
-    int col[16][4], ph[16][4];
+    int col[3][16][4], ph[3][16][4];
     gamma_tables(col, ph);
-    int tab[128];
-    std::memcpy(tab, col, sizeof(col));
-    std::memcpy(tab + 64, ph, sizeof(ph));
+    int tab[384];  // per table e: [16][4] columns, then [16][4] phases
+    for (int e = 0; e < 3; e++) {
+        std::memcpy(tab + 128 * e, col[e], sizeof(col[e]));
+        std::memcpy(tab + 128 * e + 64, ph[e], sizeof(ph[e]));
+    }
     e = hipMalloc(&ctx->gam_dev, sizeof(tab));
     if (e == hipSuccess) e = hipMemcpy(ctx->gam_dev, tab, sizeof(tab), hipMemcpyHostToDevice);
     if (e != hipSuccess) {

@@ -32,7 +32,8 @@ struct tm_ctx {
     tmq::CgScal* scal_host = nullptr;  // pinned mirror for stop checks
     int scal_host_n = 0;
 
-    // Gamma_n tables on the device (row a -> column, phase i^k)
+    // insertion tables on the device (row a -> column, phase i^k): [3][2][16][4]
+    // for Gamma_n, g5 Gamma_n, g5 Gamma_n g5
     int* gam_dev = nullptr;
 
     // learned preconditioner (weights and their bfloat16 fragments)

@@ -494,15 +494,21 @@ struct Contractor {
     ContractArgs a;
 };
 
-// Upload phase tables and indices; scratch sized for `maxr` sources.
+// Upload phase tables and indices; scratch sized for `maxr` sources.  est
+// selects the loop form: 0 the standard eta^dag Gamma s, 1 and 2 the
+// one-end loops of section 2.3 (Eqs. 5 and 6).
 static tm_status setup_contract(tm_ctx* ctx, const MomPlan& mp, int n_mom, int maxr, uint64_t seed_mixed,
-                                Contractor* c) {
+                                int est, Contractor* c) {
     const Geom& g = ctx->geo;
     tm_status s = TM_OK;
     std::memset(&c->a, 0, sizeof(c->a));
     ContractArgs& a = c->a;
     a.geo = g;
     a.seed_mixed = seed_mixed;
+    a.est = est;
+    // isovector: Tr[X (M_u^-1 - M_d^-1)] = -2i tw <s^dag g5 X s> with tw = 2 kappa mu,
+    // from M_u - M_d = 2i tw g5 (the printed sign of Eq. 5 is the opposite)
+    a.coef = est == 1 ? make_double2(0.0, -2.0 * ctx->twist) : make_double2(est == 2 ? 2.0 : 1.0, 0.0);
     a.npx = mp.np[0];
     a.npy = mp.np[1];
     a.npz = mp.np[2];
@@ -528,12 +534,13 @@ static tm_status setup_contract(tm_ctx* ctx, const MomPlan& mp, int n_mom, int m
     a.phy = a.phx + a.npx * L0;
     a.phz = a.phy + a.npy * L1;
     a.mom_idx = idd;
-    a.gam_col = ctx->gam_dev;
-    a.gam_ph = ctx->gam_dev + 64;
+    a.gam_col = ctx->gam_dev + 128 * est;
+    a.gam_ph = a.gam_col + 64;
     const size_t A = (size_t)maxr * g.L[3] * g.L[2] * a.npy * g.L[0] * 16 * 16;
     const size_t B = (size_t)maxr * g.L[3] * g.L[2] * a.npx * a.npy * 16 * 16;
     a.A = (double2*)ws_get(ctx, "c_A", A, &s);
     a.B = (double2*)ws_get(ctx, "c_B", B, &s);
+    if (est == 2) a.dsol = ws_get(ctx, "c_dsol", field_bytes(g, P_F64, maxr), &s);
     if (s != TM_OK) return s;
     return TM_OK;
 }
@@ -547,9 +554,23 @@ static void contract_block(tm_ctx* ctx, Contractor* c, const uint64_t* ids_dev, 
     a.out = out;
     a.out_slot = slots_dev;
     a.out_stride = out_stride;
+    const double sb = (double)ctx->geo.V * nrhs * 24.0 * (xprec == P_F64 ? 8 : 4);
+    if (a.est == 2) {
+        // D s = (1 - kappa H) s: the operator at zero twist, FP64 arithmetic
+        // and output on the FP64 links (FP32 solutions promote exactly)
+        const Geom& g = ctx->geo;
+        prof_begin(ctx, TM_KC_OTHER);
+        if (xprec == P_F64)
+            launch_apply(ctx->stream, g, P_F64, ctx->gauge64, ctx->lat.kappa, 0.0, 0, nrhs, x, (void*)a.dsol, 1,
+                         nullptr);
+        else
+            launch_apply_f32in_f64(ctx->stream, g, ctx->gauge64, ctx->lat.kappa, 0.0, 0, nrhs, x, (void*)a.dsol,
+                                   nullptr);
+        prof_end(ctx, TM_KC_OTHER, sb + (double)g.V * nrhs * 24.0 * 8 + (double)g.V * 144.0 * 8);
+    }
     prof_begin(ctx, TM_KC_CONTRACT);
     launch_contract(ctx->stream, a, xprec);
-    prof_end(ctx, TM_KC_CONTRACT, (double)ctx->geo.V * nrhs * 24.0 * (xprec == P_F64 ? 8 : 4));
+    prof_end(ctx, TM_KC_CONTRACT, a.est == 2 ? sb + (double)ctx->geo.V * nrhs * 24.0 * 8 : sb);
 }
 
 }  // namespace tmq
@@ -601,16 +622,26 @@ tm_status tsm_solve_batch(tm_ctx* ctx, const tsm_solve_params* params, uint64_t 
 
 tm_status tsm_contract(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* ids_host, const double* sol_dev,
                        int32_t n_mom, const int32_t* mom_host, double* loops_host) {
+    return tsm_contract_est(ctx, TM_LOOP_STANDARD, seed, nsrc, ids_host, sol_dev, n_mom, mom_host, loops_host);
+}
+
+tm_status tsm_contract_est(tm_ctx* ctx, int32_t estimator, uint64_t seed, int32_t nsrc, const uint64_t* ids_host,
+                           const double* sol_dev, int32_t n_mom, const int32_t* mom_host, double* loops_host) {
     if (!ctx) return TM_EINVAL;
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
-    if (nsrc < 1 || !ids_host || !sol_dev || !loops_host) return set_error(ctx, TM_EINVAL, "tsm_contract: bad argument");
+    if (estimator < TM_LOOP_STANDARD || estimator > TM_LOOP_ONEEND_GENERALIZED)
+        return set_error(ctx, TM_EINVAL, "tsm_contract: unknown estimator");
+    if (nsrc < 1 || !sol_dev || !loops_host || (estimator == TM_LOOP_STANDARD && !ids_host))
+        return set_error(ctx, TM_EINVAL, "tsm_contract: bad argument");
+    if (estimator == TM_LOOP_ONEEND_GENERALIZED && !ctx->gauge_loaded)
+        return set_error(ctx, TM_ESTATE, "tsm_contract: the generalized one-end loop needs the gauge field");
     const Geom& g = ctx->geo;
     MomPlan mp;
     tm_status s = plan_momenta(ctx, n_mom, mom_host, &mp);
     if (s != TM_OK) return s;
     const int blk = std::min(nsrc, kMaxBlock);
     Contractor c;
-    if ((s = setup_contract(ctx, mp, n_mom, blk, seed_mix(seed), &c)) != TM_OK) return s;
+    if ((s = setup_contract(ctx, mp, n_mom, blk, seed_mix(seed), estimator, &c)) != TM_OK) return s;
     const long nl = 16L * n_mom * g.L[3];
     uint64_t* ids_dev = (uint64_t*)ws_get(ctx, "contract_ids", sizeof(uint64_t) * nsrc, &s);
     int* slots = (int*)ws_get(ctx, "contract_slots", sizeof(int) * nsrc, &s);
@@ -619,7 +650,10 @@ tm_status tsm_contract(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t*
     if (s != TM_OK) return s;
     std::vector<int> sl(nsrc);
     for (int i = 0; i < nsrc; i++) sl[i] = i;
-    TM_COPY(ids_dev, ids_host, sizeof(uint64_t) * nsrc, hipMemcpyHostToDevice);
+    if (ids_host)
+        TM_COPY(ids_dev, ids_host, sizeof(uint64_t) * nsrc, hipMemcpyHostToDevice);
+    else
+        TM_HIP(hipMemsetAsync(ids_dev, 0, sizeof(uint64_t) * nsrc, ctx->stream));
     TM_COPY(slots, sl.data(), sizeof(int) * nsrc, hipMemcpyHostToDevice);
     for (int j0 = 0; j0 < nsrc; j0 += blk) {
         const int nb = std::min(blk, nsrc - j0);
@@ -654,7 +688,9 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double
     const int blp = default_block(&P->lp), bhp = default_block(&P->hp);
     const int nr_lp = lane_rhs(ctx, &P->lp, blp), nr_hp = lane_rhs(ctx, &P->hp, bhp);
     Contractor c;
-    if ((s = setup_contract(ctx, mp, P->n_mom, std::max(blp, bhp) + 4, sm, &c)) != TM_OK) return s;
+    if (P->estimator < TM_LOOP_STANDARD || P->estimator > TM_LOOP_ONEEND_GENERALIZED)
+        return set_error(ctx, TM_EINVAL, "tsm_loops: unknown estimator");
+    if ((s = setup_contract(ctx, mp, P->n_mom, std::max(blp, bhp) + 4, sm, P->estimator, &c)) != TM_OK) return s;
 
     // per-source loops [N][2][nl], source ids, output slots (ids padded at the end)
     const int Npad = N + 8;

@@ -46,7 +46,7 @@ def test_binding_covers_header():
 
 
 def test_abi_version(lib):
-    assert lib.tm_abi_version() == 1
+    assert lib.tm_abi_version() == 2
 
 
 def test_product_path_has_no_oracle_dependency():
@@ -84,3 +84,30 @@ def test_too_large_lattices_are_rejected_before_any_device_call(lib):
         assert lib.tm_create(ctypes.byref(lat), None, ctypes.byref(out)) == -1, dims
         assert not out.value
         assert b"too large" in lib.tm_last_error(None)
+
+
+def test_struct_layouts_match_binding(tmp_path):
+    """Sizes and field offsets of the ABI structs as the C compiler lays them
+    out from the header equal those of the ctypes binding."""
+    import subprocess
+
+    from paper_1211_0126_amd import binding as b
+    structs = {"tm_lattice": b.Lattice, "tsm_solve_params": b.SolveParams, "tsm_solve_stats": b.SolveStats,
+               "tsm_params": b.TsmParams, "tsm_run_stats": b.RunStats, "tm_net_shape": b.NetShape,
+               "tm_train_params": b.TrainParams, "tm_train_stats": b.TrainStats}
+    lines = []
+    for cname, cls in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "tmqcd.h"\nint main(void) {\n%s\nreturn 0;\n}\n'
+                   % "\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                          text=True).stdout.splitlines())
+    for cname, cls in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(cls, f).offset, (cname, f)
