@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--train-pairs", type=int, default=256)
     ap.add_argument("--train-sources", type=int, default=16)
     ap.add_argument("--train-epochs", type=int, default=6)
+    ap.add_argument("--no-one-end", action="store_true",
+                    help="skip the per-estimator step (standard and one-end loops of Eqs. 5 and 6)")
+    ap.add_argument("--one-end-lp", type=int, default=32, help="LP sources of the per-estimator step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--lp-true-resid", action="store_true",
@@ -305,11 +308,38 @@ def main():
 
     if not args.no_compare:
         out["equal_residual"] = compare(args, tq, torch, ctx, wl, n_hp, lp_prec)
+    if not args.no_one_end:
+        out["one_end"] = one_end(args, tq, torch, ctx, wl, lp, hp, mom)
 
     ctx.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_threads)
     print(json.dumps(out), flush=True)
+
+
+def one_end(args, tq, torch, ctx, wl, lp, hp, mom):
+    """The TSM step with each loop estimator (section 2.3: the standard
+    eta^dag Gamma s and the one-end loops of Eqs. 5 and 6) on a smaller
+    source sample, same solvers: LP-phase sources/s and the contraction
+    kernels' time per source (the generalized loop adds one FP64 stencil
+    application per source, counted in the 'other' class)."""
+    n_hp, n_lp = min(2, wl.n_hp), args.one_end_lp
+    res = {"sample": "N_HP %d, N_LP %d" % (n_hp, n_lp)}
+    for name, est in (("standard", tq.LOOP_STANDARD), ("isovector", tq.LOOP_ONEEND_ISOVECTOR),
+                      ("generalized", tq.LOOP_ONEEND_GENERALIZED)):
+        tq.tsm_loops(ctx, wl.noise_seed, n_hp, n_lp, lp, hp, mom, stats=False, estimator=est)  # warm
+        tq.tm_profile_enable(ctx, True)
+        r = tq.tsm_loops(ctx, wl.noise_seed, n_hp, n_lp, lp, hp, mom, stats=False, estimator=est)
+        prof = tq.tm_profile_read(ctx)
+        tq.tm_profile_enable(ctx, False)
+        c = prof["contract"]
+        n_contr = 2 * n_hp + n_lp
+        res[name] = {"lp_phase_sources_per_s": round(n_lp / (r["run"]["ms_lp_phase"] / 1e3), 2),
+                     "contract_us_per_source": round(1e3 * c["ms"] / n_contr, 1),
+                     "contract_GBps": round(c["bytes"] / max(c["ms"], 1e-9) / 1e6, 1),
+                     "other_us_per_source": round(1e3 * prof["other"]["ms"] / n_contr, 1)}
+        log("one-end %s: %s" % (name, res[name]))
+    return res
 
 
 def compare(args, tq, torch, ctx, wl, n_hp, lp_prec):
