@@ -35,4 +35,5 @@ from .oracle import (  # noqa: F401
     pt_net,
     pt_loss_grad,
     fcg,
+    fgmres,
 )

@@ -69,6 +69,8 @@ def load_oracle():
     lib.orc_pt_loss_grad.restype = f64
     lib.orc_fcg.argtypes = [P, i32, f64, f64, P, i32, P, P, P, f64, i32, P, P]
     lib.orc_fcg.restype = i32
+    lib.orc_fgmres.argtypes = [P, i32, f64, f64, P, i32, P, P, P, f64, i32, i32, P, P]
+    lib.orc_fgmres.restype = i32
     _lib = lib
     return lib
 
@@ -260,3 +262,16 @@ def fcg(dims, t_bc, kappa, mu, U, widths, W, eta, tol, maxit=-1):
                           _ptr(_c128(W)), _ptr(eta), float(tol), int(maxit), _ptr(x), _ptr(st))
     return x, {"iters": int(st[0]), "resid_normal": st[1], "resid_true": st[2], "converged": bool(st[3]),
                "truncated": bool(st[4]), "fell_back": bool(st[5])}
+
+
+def fgmres(dims, t_bc, kappa, mu, U, widths, W, eta, tol, m=16, maxit=-1):
+    """Restarted FGMRES(m) on M with the network as right preconditioner."""
+    d = _dims(dims)
+    wd = np.ascontiguousarray(np.asarray(widths, dtype=np.int32))
+    eta = _c128(eta)
+    x = np.zeros_like(eta)
+    st = np.zeros(5, dtype=np.float64)
+    load_oracle().orc_fgmres(_ptr(d), int(t_bc), float(kappa), float(mu), _ptr(_c128(U)), len(wd) - 1, _ptr(wd),
+                             _ptr(_c128(W)), _ptr(eta), float(tol), int(m), int(maxit), _ptr(x), _ptr(st))
+    return x, {"iters": int(st[0]), "resid": st[1], "resid_true": st[2], "converged": bool(st[3]),
+               "truncated": bool(st[4])}

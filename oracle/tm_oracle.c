@@ -902,3 +902,105 @@ int orc_fcg(const int *L, int t_bc, double kappa, double mu, const double *U_, i
     free(b); free(r); free(z); free(p); free(t); free(q); free(rold); free(tmp);
     return it;
 }
+
+/* ------------------------------------------------------------------ */
+/* flexible GMRES on M, right-preconditioned by the network            */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Restarted FGMRES(m) (Saad 1993) for M x = eta from x = 0, with the
+ * network N as right preconditioner (z_j = N v_j, one forward pass per
+ * iteration): Arnoldi on M z_j with modified Gram-Schmidt, the small least-
+ * squares problem by Givens rotations, x += Z y at the end of each cycle.
+ * Stops when the rotated residual |g_{j+1}| / |eta| (equal to
+ * |eta - M x| / |eta| in exact arithmetic) is <= tol, or after maxit
+ * iterations in total (maxit < 0: no cap).  A zero subdiagonal element
+ * (the Krylov space holds the solution) ends the cycle with the exact
+ * least-squares solution.  stats (nullable): iterations, final rotated
+ * residual, FP64 true residual |eta - M x| / |eta|, converged, truncated.
+ */
+int orc_fgmres(const int *L, int t_bc, double kappa, double mu, const double *U_, int nl, const int *widths,
+               const double *W, const double *eta_, double tol, int m, int maxit, double *x_, double *stats)
+{
+    const cplx *U = (const cplx *)U_, *eta = (const cplx *)eta_;
+    cplx *x = (cplx *)x_;
+    long n = volume(L) * NCOMP;
+    cplx *V = malloc(sizeof(cplx) * n * (m + 1)), *Z = malloc(sizeof(cplx) * n * m);
+    cplx *w = malloc(sizeof(cplx) * n);
+    cplx *H = calloc((size_t)(m + 1) * m, sizeof(cplx));   /* H[i*m + j] */
+    cplx *g = malloc(sizeof(cplx) * (m + 1)), *y = malloc(sizeof(cplx) * m);
+    double *cs = malloc(sizeof(double) * m);
+    cplx *sn = malloc(sizeof(cplx) * m);
+    double eta_norm = sqrt(norm2(eta, n));
+    int it = 0, conv = 0, trunc = 0;
+    double res = 1.0;
+    for (long i = 0; i < n; i++) x[i] = 0;
+    if (eta_norm == 0) conv = 1;
+    while (!conv && !trunc) {
+        /* r = eta - M x, v_0 = r / |r| */
+        apply_m(L, t_bc, kappa, mu, U, x, w, 0);
+        for (long i = 0; i < n; i++) w[i] = eta[i] - w[i];
+        double beta = sqrt(norm2(w, n));
+        res = beta / eta_norm;
+        if (res <= tol) { conv = 1; break; }
+        if (maxit >= 0 && it >= maxit) { trunc = 1; break; }
+        for (long i = 0; i < n; i++) V[i] = w[i] / beta;
+        for (int i = 0; i <= m; i++) g[i] = 0;
+        g[0] = beta;
+        int k = 0;  /* columns of this cycle */
+        for (int j = 0; j < m; j++) {
+            cplx *vj = V + (long)j * n, *zj = Z + (long)j * n;
+            orc_pt_net(L, t_bc, U_, nl, widths, W, (const double *)vj, (double *)zj, 0);
+            apply_m(L, t_bc, kappa, mu, U, zj, w, 0);
+            for (int i = 0; i <= j; i++) {
+                cplx *vi = V + (long)i * n;
+                cplx h = cdot(vi, w, n);
+                H[i * m + j] = h;
+                for (long q = 0; q < n; q++) w[q] -= h * vi[q];
+            }
+            double hn = sqrt(norm2(w, n));
+            H[(j + 1) * m + j] = hn;
+            if (hn > 0)
+                for (long q = 0; q < n; q++) V[(long)(j + 1) * n + q] = w[q] / hn;
+            /* previous rotations, then the one that zeroes H[j+1][j] */
+            for (int i = 0; i < j; i++) {
+                cplx a = H[i * m + j], b = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * b;
+                H[(i + 1) * m + j] = -conj(sn[i]) * a + cs[i] * b;
+            }
+            cplx a = H[j * m + j];
+            double bb = hn, den = sqrt(creal(a) * creal(a) + cimag(a) * cimag(a) + bb * bb);
+            if (cabs(a) == 0) { cs[j] = 0; sn[j] = 1; }
+            else { cs[j] = cabs(a) / den; sn[j] = (a / cabs(a)) * bb / den; }
+            H[j * m + j] = cs[j] * a + sn[j] * bb;
+            H[(j + 1) * m + j] = 0;
+            g[j + 1] = -conj(sn[j]) * g[j];
+            g[j] = cs[j] * g[j];
+            it++;
+            k = j + 1;
+            res = cabs(g[j + 1]) / eta_norm;
+            if (res <= tol) { conv = 1; break; }
+            if (maxit >= 0 && it >= maxit) { trunc = 1; break; }
+            if (hn == 0) break;
+        }
+        /* y = R^{-1} g (back substitution), x += Z y */
+        for (int i = k - 1; i >= 0; i--) {
+            cplx acc = g[i];
+            for (int q = i + 1; q < k; q++) acc -= H[i * m + q] * y[q];
+            y[i] = acc / H[i * m + i];
+        }
+        for (int j = 0; j < k; j++)
+            for (long q = 0; q < n; q++) x[q] += y[j] * Z[(long)j * n + q];
+    }
+    if (stats) {
+        apply_m(L, t_bc, kappa, mu, U, x, w, 0);
+        for (long i = 0; i < n; i++) w[i] = eta[i] - w[i];
+        stats[0] = it;
+        stats[1] = res;
+        stats[2] = eta_norm > 0 ? sqrt(norm2(w, n)) / eta_norm : 0.0;
+        stats[3] = conv;
+        stats[4] = trunc;
+    }
+    free(V); free(Z); free(w); free(H); free(g); free(y); free(cs); free(sn);
+    return it;
+}
