@@ -17,6 +17,7 @@ from .oracle import (  # noqa: F401
     cgnr,
     loops,
     loops_est,
+    loops_deriv,
     tsm,
     set_threads,
     get_threads,
@@ -29,6 +30,7 @@ from .oracle import (  # noqa: F401
     LOOP_STD,
     LOOP_ONEEND_VV,
     LOOP_ONEEND_GEN,
+    LOOP_DERIV,
     layer_weight_count,
     net_weight_count,
     pt_layer,

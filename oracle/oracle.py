@@ -19,7 +19,7 @@ _LIB = os.path.join(_HERE, "libtmoracle.so")
 
 OP_M, OP_MDAG, OP_MDAGM, OP_HOP = 0, 1, 2, 3
 STOP_NORMAL, STOP_TRUE = 0, 1
-LOOP_STD, LOOP_ONEEND_VV, LOOP_ONEEND_GEN = 0, 1, 2
+LOOP_STD, LOOP_ONEEND_VV, LOOP_ONEEND_GEN, LOOP_DERIV = 0, 1, 2, 3
 
 _lib = None
 
@@ -58,6 +58,7 @@ def load_oracle():
     lib.orc_cgnr.argtypes = [P, i32, f64, f64, P, P, f64, i32, i32, P, P]
     lib.orc_cgnr.restype = i32
     lib.orc_loops.argtypes = [P, P, P, i32, P, P]
+    lib.orc_loops_deriv.argtypes = [P, i32, P, P, P, i32, P, P]
     lib.orc_loops_est.argtypes = [P, i32, f64, f64, P, i32, P, P, i32, P, P]
     lib.orc_tsm.argtypes = [P, i32, f64, f64, P, u64, i32, i32, f64, i32, i32, f64, i32, i32,
                             i32, P, i32, P, P, P, P]
@@ -165,6 +166,17 @@ def loops(dims, eta, s, mom) -> np.ndarray:
     return out
 
 
+def loops_deriv(dims, t_bc, U, eta, s, mom) -> np.ndarray:
+    """One-derivative loops (symmetric covariant derivative in each
+    direction mu): complex128 [4][16][n_mom][Lt]."""
+    d = _dims(dims)
+    mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros((4, 16, mom.shape[0], int(d[3])), dtype=np.complex128)
+    load_oracle().orc_loops_deriv(_ptr(d), int(t_bc), _ptr(_c128(U)), _ptr(_c128(eta)), _ptr(_c128(s)),
+                                  mom.shape[0], _ptr(mom), _ptr(out))
+    return out
+
+
 def loops_est(dims, t_bc, kappa, mu, U, est, s, mom, eta=None) -> np.ndarray:
     """Loops of estimator est (LOOP_STD needs eta; the one-end estimators of
     section 2.3, Eqs. 5 and 6, use the solution alone): complex128
@@ -172,6 +184,8 @@ def loops_est(dims, t_bc, kappa, mu, U, est, s, mom, eta=None) -> np.ndarray:
     d = _dims(dims)
     mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
     out = np.zeros((16, mom.shape[0], int(d[3])), dtype=np.complex128)
+    if est == LOOP_DERIV:
+        return loops_deriv(dims, t_bc, U, eta, s, mom)
     if est == LOOP_STD and eta is None:
         raise ValueError("the standard loop needs the source")
     e = _c128(eta) if eta is not None else None
@@ -190,10 +204,11 @@ def tsm(dims, t_bc, kappa, mu, U, seed, n_hp, n_lp, lp_tol, lp_maxit, hp_tol, hp
     mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
     nm = mom.shape[0]
     lt = int(d[3])
-    out = np.zeros((3, 16, nm, lt), dtype=np.complex128)
+    el = (4, 16, nm, lt) if estimator == LOOP_DERIV else (16, nm, lt)
+    out = np.zeros((3,) + el, dtype=np.complex128)
     err = np.zeros_like(out)
     n = n_hp + n_lp
-    ps = np.zeros((max(n, 1), 2, 16, nm, lt), dtype=np.complex128) if per_source else None
+    ps = np.zeros((max(n, 1), 2) + el, dtype=np.complex128) if per_source else None
     st = np.zeros((max(n, 1), 2, 5), dtype=np.float64)
     load_oracle().orc_tsm(_ptr(d), int(t_bc), float(kappa), float(mu), _ptr(U), int(seed), int(n_hp), int(n_lp),
                           float(lp_tol), int(lp_maxit), int(lp_stop), float(hp_tol), int(hp_maxit), int(hp_stop),

@@ -435,14 +435,22 @@ void orc_loops(const int *L, const double *eta_, const double *s_, int n_mom,
  *   with D = (M_u + M_d)/2 = 1 - kappa H (the operator at mu = 0), whose
  *   noise average is the same trace of Gamma_n (M_u^{-1} + M_d^{-1}).
  *
- * est 0 is the standard loop of orc_loops (eta must then be given).  out is
- * complex128 [16][n_mom][Lt], accumulated into.
+ * est 0 is the standard loop of orc_loops and est 3 the one-derivative
+ * loops of orc_loops_deriv (eta must then be given).  out is complex128
+ * [16][n_mom][Lt] ([4][16][n_mom][Lt] for est 3), accumulated into.
  */
+void orc_loops_deriv(const int *L, int t_bc, const double *U_, const double *eta_, const double *s_, int n_mom,
+                     const int *mom, double *out_);
+
 void orc_loops_est(const int *L, int t_bc, double kappa, double mu, const double *U_, int est,
                    const double *eta_, const double *s_, int n_mom, const int *mom, double *out_)
 {
     if (est == 0) {
         orc_loops(L, eta_, s_, n_mom, mom, out_);
+        return;
+    }
+    if (est == 3) {
+        orc_loops_deriv(L, t_bc, U_, eta_, s_, n_mom, mom, out_);
         return;
     }
     const cplx *sv = (const cplx *)s_;
@@ -491,12 +499,83 @@ void orc_loops_est(const int *L, int t_bc, double kappa, double mu, const double
 }
 
 /* ------------------------------------------------------------------ */
+/* one-derivative loops (the operators of section 3 and Fig. 1)        */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Loops of psibar(x) Gamma_n Dsym_mu psi(x) with the symmetric covariant
+ * derivative Dsym = (Dfwd - Dbwd)/2,
+ *   Dfwd_mu psi(x)   = [U_mu(x) psi(x+mu) - U_mu(x-mu)^dag psi(x-mu)] / 2,
+ *   psibar Dbwd_mu(x) = [psibar(x+mu) U_mu(x)^dag - psibar(x-mu) U_mu(x-mu)] / 2,
+ * with the propagator estimated by s eta^dag as in the standard loop:
+ *   out[mu][n][m][t] += sum_{x in t} exp(-i p_m.x) (1/4) sum_{a,b,c}
+ *       [ conj(eta_ac(x)) Gamma_n[a][b] f_bc(x) - conj(g_ac(x)) Gamma_n[a][b] s_bc(x) ],
+ *   f = U_mu(x) s(x+mu) - U_mu(x-mu)^dag s(x-mu),
+ *   g = U_mu(x) eta(x+mu) - U_mu(x-mu)^dag eta(x-mu),
+ * hops across the time boundary carrying t_bc as in the operator.  The
+ * timeslice and phase are those of x.  out: complex128
+ * [4][16][n_mom][Lt], accumulated into.
+ */
+void orc_loops_deriv(const int *L, int t_bc, const double *U_, const double *eta_, const double *s_, int n_mom,
+                     const int *mom, double *out_)
+{
+    const cplx *U = (const cplx *)U_, *eta = (const cplx *)eta_, *sv = (const cplx *)s_;
+    cplx *out = (cplx *)out_;
+    long V = volume(L);
+    int Lt = L[3];
+    cplx G[16][4][4];
+    for (int n = 0; n < 16; n++) orc_gamma(n, (double *)G[n]);
+    const double twopi = 2.0 * acos(-1.0);
+    for (long x = 0; x < V; x++) {
+        int c[4];
+        site_coords(L, x, c);
+        for (int mu = 0; mu < 4; mu++) {
+            double php, phm;
+            long xp = neighbour(L, t_bc, x, mu, +1, &php);
+            long xm = neighbour(L, t_bc, x, mu, -1, &phm);
+            cplx f[NSPIN][NCOL], g[NSPIN][NCOL];
+            for (int a = 0; a < NSPIN; a++)
+                for (int i = 0; i < NCOL; i++) {
+                    cplx fs = 0, ge = 0;
+                    for (int k = 0; k < NCOL; k++) {
+                        cplx up = U[((x * 4 + mu) * 3 + i) * 3 + k];          /* U_mu(x)[i][k] */
+                        cplx um = conj(U[((xm * 4 + mu) * 3 + k) * 3 + i]);   /* U_mu(x-mu)^dag[i][k] */
+                        fs += php * up * sv[xp * NCOMP + a * NCOL + k] - phm * um * sv[xm * NCOMP + a * NCOL + k];
+                        ge += php * up * eta[xp * NCOMP + a * NCOL + k] - phm * um * eta[xm * NCOMP + a * NCOL + k];
+                    }
+                    f[a][i] = fs;
+                    g[a][i] = ge;
+                }
+            cplx tr[16];
+            for (int n = 0; n < 16; n++) {
+                cplx acc = 0;
+                for (int a = 0; a < 4; a++)
+                    for (int b = 0; b < 4; b++) {
+                        if (G[n][a][b] == 0) continue;
+                        for (int k = 0; k < NCOL; k++)
+                            acc += G[n][a][b] * (conj(eta[x * NCOMP + a * NCOL + k]) * f[b][k] -
+                                                 conj(g[a][k]) * sv[x * NCOMP + b * NCOL + k]);
+                    }
+                tr[n] = 0.25 * acc;
+            }
+            for (int m = 0; m < n_mom; m++) {
+                double arg = twopi * ((double)mom[3 * m] * c[0] / L[0] + (double)mom[3 * m + 1] * c[1] / L[1] +
+                                      (double)mom[3 * m + 2] * c[2] / L[2]);
+                cplx ph = cexp(-I * arg);
+                for (int n = 0; n < 16; n++) out[(((long)mu * 16 + n) * n_mom + m) * Lt + c[3]] += ph * tr[n];
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* TSM estimator (Eq. 4)                                               */
 /* ------------------------------------------------------------------ */
 
 /*
  * Eq. 4 applied to the loops of estimator est (0 standard, 1 and 2 the
- * one-end loops of orc_loops_est):
+ * one-end loops of orc_loops_est, 3 the one-derivative loops, whose
+ * elements are [4][16][n_mom][Lt] where the others have [16][n_mom][Lt]):
  *   C = (1/N_HP) sum_{j in HP} [L(s_j^HP) - L(s_j^LP)]    (correction)
  *   B = (1/N_LP) sum_{j in LP} L(s_j^LP)                  (biased estimate)
  *   T = C + B
@@ -523,7 +602,7 @@ int orc_tsm(const int *L, int t_bc, double kappa, double mu, const double *U,
     long V = volume(L);
     long n = V * NCOMP;
     int Lt = L[3];
-    long nl = 16L * n_mom * Lt;
+    long nl = (est == 3 ? 64L : 16L) * n_mom * Lt;
     cplx *out = (cplx *)out_;
     cplx *err = (cplx *)err_;
     cplx *per_src = (cplx *)per_src_;
