@@ -145,11 +145,20 @@ typedef struct {
                        sign);
    ONEEND_GENERALIZED: 2 s^dag g5 Gamma_n g5 D s with D = 1 - kappa H (Eq. 6),
                        noise average Tr[X M_u^{-1}] + Tr[X M_d^{-1}]; one
-                       extra FP64 stencil application per source. */
+                       extra FP64 stencil application per source;
+   DERIVATIVE:         the one-derivative loops psibar Gamma_n Dsym_mu psi of
+                       the operators of section 3 (Fig. 1), one set per
+                       direction mu: (1/4) [eta^dag Gamma_n f - g^dag Gamma_n s]
+                       with f = U_mu(x) s(x+mu) - U_mu(x-mu)^dag s(x-mu) and g
+                       the same of eta (symmetric covariant derivative
+                       (Dfwd - Dbwd)/2, hops across t carry t_bc); its
+                       loop elements are [4][16][n_mom][Lt] where the
+                       others have [16][n_mom][Lt]. */
 typedef enum {
     TM_LOOP_STANDARD = 0,
     TM_LOOP_ONEEND_ISOVECTOR = 1,
-    TM_LOOP_ONEEND_GENERALIZED = 2
+    TM_LOOP_ONEEND_GENERALIZED = 2,
+    TM_LOOP_DERIVATIVE = 3
 } tm_loop_estimator;
 
 typedef struct {
@@ -248,10 +257,13 @@ tm_status tsm_contract(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t*
                        const double* sol_dev, int32_t n_mom, const int32_t* mom_host, double* loops_host);
 
 /* tsm_contract with the loop estimator chosen (tm_loop_estimator; section
-   2.3, Eqs. 5 and 6).  The one-end estimators use the solutions alone:
-   seed and ids_host are ignored and ids_host may be NULL.  The generalized
-   one needs the gauge field (TM_ESTATE otherwise) and applies D in FP64 to
-   each solution.  TM_EINVAL for an unknown estimator.  Synchronous. */
+   2.3, Eqs. 5 and 6, and the derivative loops of section 3).  The one-end
+   estimators use the solutions alone: seed and ids_host are ignored and
+   ids_host may be NULL.  The generalized one-end and the derivative loops
+   need the gauge field (TM_ESTATE otherwise); the former applies D in FP64
+   to each solution.  loops_host: complex128 [nsrc][16][n_mom][Lt], for
+   TM_LOOP_DERIVATIVE [nsrc][4][16][n_mom][Lt].  TM_EINVAL for an unknown
+   estimator.  Synchronous. */
 tm_status tsm_contract_est(tm_ctx* ctx, int32_t estimator, uint64_t seed, int32_t nsrc, const uint64_t* ids_host,
                            const double* sol_dev, int32_t n_mom, const int32_t* mom_host, double* loops_host);
 
@@ -260,7 +272,9 @@ tm_status tsm_contract_est(tm_ctx* ctx, int32_t estimator, uint64_t seed, int32_
      B = (1/N_LP) sum_{N_HP <= j < N_HP+N_LP} L(s_j^LP),   T = C + B,
    with every LP solve (of both sets) done by params->lp and the HP solves by
    params->hp.  An empty set contributes zero.
-   loops_host: complex128 [3][16][n_mom][Lt] (C, B, T).
+   loops_host: complex128 [3][16][n_mom][Lt] (C, B, T); with
+     TM_LOOP_DERIVATIVE each [16][n_mom][Lt] block is [4][16][n_mom][Lt],
+     here and in err_host and per_source_host.
    err_host (nullable): same shape; real and imaginary parts are the
      standard errors of the real and imaginary parts from the per-source
      spread (sample variance / N; zero for a set of one source),

@@ -52,4 +52,5 @@ from .binding import (  # noqa: F401
     LOOP_STANDARD,
     LOOP_ONEEND_ISOVECTOR,
     LOOP_ONEEND_GENERALIZED,
+    LOOP_DERIVATIVE,
 )

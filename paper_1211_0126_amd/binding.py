@@ -22,7 +22,7 @@ OP_M, OP_MDAG, OP_MDAGM, OP_HOP = 0, 1, 2, 3
 LAYOUT_CANONICAL, LAYOUT_NATIVE = 0, 1
 STOP_NORMAL, STOP_TRUE = 0, 1
 SOLVER_CG, SOLVER_FCG_LEARNED = 0, 1
-LOOP_STANDARD, LOOP_ONEEND_ISOVECTOR, LOOP_ONEEND_GENERALIZED = 0, 1, 2
+LOOP_STANDARD, LOOP_ONEEND_ISOVECTOR, LOOP_ONEEND_GENERALIZED, LOOP_DERIVATIVE = 0, 1, 2, 3
 KC_NAMES = ["dslash", "dslash_upd", "blas", "contract", "other", "apply"]
 
 
@@ -241,7 +241,8 @@ def tsm_contract(ctx: Context, seed, ids, sol, mom, estimator=LOOP_STANDARD):
     n = len(ids) if ids is not None else int(sol.shape[0])
     ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64)) if ids is not None else None
     mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
-    out = np.zeros((n, 16, mom.shape[0], ctx.dims[3]), dtype=np.complex128)
+    el = (4, 16, mom.shape[0], ctx.dims[3]) if estimator == LOOP_DERIVATIVE else (16, mom.shape[0], ctx.dims[3])
+    out = np.zeros((n,) + el, dtype=np.complex128)
     assert sol.is_cuda and sol.is_contiguous() and tuple(sol.shape) == (n, ctx.V, 4, 3)
     assert sol.dtype == torch.complex128
     ctx.check(ctx.lib.tsm_contract_est(ctx.h, int(estimator), int(seed), n,
@@ -254,15 +255,17 @@ def tsm_loops(ctx: Context, seed, n_hp, n_lp, lp: SolveParams, hp: SolveParams, 
               stats=True, estimator=LOOP_STANDARD):
     """The TSM estimate (Eq. 4).  Returns dict with 'loops' [3][16][n_mom][Lt]
     (C, B, T), 'err', optional 'per_source' [N][2][16][n_mom][Lt], 'stats'
-    (list of [LP, HP] records), 'run' and the status code."""
+    (list of [LP, HP] records), 'run' and the status code; the derivative
+    estimator has [4][16][n_mom][Lt] in place of each [16][n_mom][Lt]."""
     mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
     nm, lt = mom.shape[0], ctx.dims[3]
     N = n_hp + n_lp
     P = TsmParams(int(seed), int(n_hp), int(n_lp), lp, hp, nm, mom.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                   int(estimator), 0)
-    loops = np.zeros((3, 16, nm, lt), dtype=np.complex128)
+    el = (4, 16, nm, lt) if estimator == LOOP_DERIVATIVE else (16, nm, lt)
+    loops = np.zeros((3,) + el, dtype=np.complex128)
     err = np.zeros_like(loops)
-    ps = np.zeros((max(N, 1), 2, 16, nm, lt), dtype=np.complex128) if per_source else None
+    ps = np.zeros((max(N, 1), 2) + el, dtype=np.complex128) if per_source else None
     st = (SolveStats * (2 * max(N, 1)))() if stats else None
     run = RunStats()
     rc = ctx.lib.tsm_loops(ctx.h, ctypes.byref(P), _ptr(loops), _ptr(err), _ptr(ps) if ps is not None else None,

@@ -11,7 +11,12 @@
 //   est 2 (Eq. 6):        u = D s, v = s, X_n = g5 Gamma_n g5, f = 2,
 //                         D s = (1 - kappa H) s from the FP64 stencil.
 // The one-end forms estimate Tr[X (M_u^{-1} -+ M_d^{-1})] with M_d the
-// operator at -mu.  The Fourier sum is separable,
+// operator at -mu.  est 3 gives the one-derivative loops of
+// psibar Gamma_n Dsym_mu psi, Dsym = (Dfwd - Dbwd)/2, one set per direction:
+//   S_{ba}(x) = (1/4) sum_c [f_{bc}(x) conj(eta_{ac}(x)) - s_{bc}(x) conj(g_{ac}(x))],
+//   f = U_mu(x) s(x+mu) - U_mu(x-mu)^dag s(x-mu), g the same of eta,
+// with the time-boundary factor on hops across t (k_contract_d).  The
+// Fourier sum is separable,
 // so it is done one axis at a time over the distinct per-axis momentum
 // components (3 each for the 27 momenta with |n_i| <= 1):
 //   A: per (x, z, t) row, sum over y with the y phases   (reads s once)
@@ -143,6 +148,130 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
     }
 }
 
+// U psi (fwd) or U^dag psi (!fwd) of one colour vector, times ph
+__device__ __forceinline__ void su3_apply_d(const cx<double> U[3][3], bool fwd, double ph, const cx<double> v[3],
+                                            cx<double> o[3]) {
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        cx<double> acc = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < 3; k++) acc = acc + (fwd ? U[i][k] * v[k] : cmulc(U[k][i], v[k]));
+        o[i] = ph * acc;
+    }
+}
+
+// One-derivative loops, stage A: one lane per (x, z, t) row, spin half h
+// and direction mu (grid z); the A slice of (source r, direction mu) is
+// r * 4 + mu.  f and g are built from the forward hop first, then the
+// backward one, so only one link is live at a time.
+template <class S>
+__global__ __launch_bounds__(256) void k_contract_d(ContractArgs a) {
+    const Geom& g = a.geo;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+    const long nrow = (long)Lx * Lz * Lt;
+    const long tid = (long)blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    const int mu = blockIdx.z;
+    if (tid >= 2 * nrow) return;
+    const int h = tid >= nrow ? 1 : 0;
+    const long q = tid - h * nrow;
+    const int x = (int)(q % Lx);
+    const long q2 = q / Lx;
+    const int z = (int)(q2 % Lz);
+    const int t = (int)(q2 / Lz);
+    const int npy = a.npy;
+    const void* sol = field_rhs<S>(a.sol, g.Vs, r);
+    const uint64_t id = a.ids[r];
+    const uint64_t V = (uint64_t)g.V;
+    cx<double> acc[3][8];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int e = 0; e < 8; e++) acc[i][e] = {0.0, 0.0};
+    for (int y = 0; y < Ly; y++) {
+        int c[4] = {x, y, z, t};
+        const uint32_t s0 = x + Lx * (y + Ly * (z + Lz * t));
+        const int cmu = c[mu], Lmu = g.L[mu];
+        const bool wrap_p = cmu + 1 == Lmu, wrap_m = cmu == 0;
+        c[mu] = wrap_p ? 0 : cmu + 1;
+        const uint32_t sp = c[0] + Lx * (c[1] + Ly * (c[2] + Lz * c[3]));
+        c[mu] = wrap_m ? Lmu - 1 : cmu - 1;
+        const uint32_t sm = c[0] + Lx * (c[1] + Ly * (c[2] + Lz * c[3]));
+        const double php = (mu == 3 && wrap_p) ? (double)g.t_bc : 1.0;
+        const double phm = (mu == 3 && wrap_m) ? (double)g.t_bc : 1.0;
+        cx<double> f[6], gg[12];
+        {
+            // forward hop: U_mu(x) applied to s(x+mu) (rows of half h) and eta(x+mu)
+            cx<double> U[3][3], p[6];
+            load_link<GF64, double>(a.gauge64, g.Vs, mu, s0, U);
+            load_half_spinor<S>(sol, g.Vs, sp, h, p);
+            su3_apply_d(U, true, php, p, f);
+            su3_apply_d(U, true, php, p + 3, f + 3);
+            const uint64_t bp = noise_bits(a.seed_mixed, id, V, (uint64_t)sp);
+#pragma unroll
+            for (int al = 0; al < 4; al++) {
+                cx<double> e[3];
+#pragma unroll
+                for (int k = 0; k < 3; k++) e[k] = z4_value<double>((uint32_t)(bp >> (2 * (3 * al + k))) & 3u);
+                su3_apply_d(U, true, php, e, gg + 3 * al);
+            }
+        }
+        {
+            // backward hop: U_mu(x-mu)^dag applied to s(x-mu) and eta(x-mu), subtracted
+            cx<double> U[3][3], p[6], o[3];
+            load_link<GF64, double>(a.gauge64, g.Vs, mu, sm, U);
+            load_half_spinor<S>(sol, g.Vs, sm, h, p);
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                su3_apply_d(U, false, phm, p + 3 * b, o);
+#pragma unroll
+                for (int k = 0; k < 3; k++) f[3 * b + k] = f[3 * b + k] - o[k];
+            }
+            const uint64_t bm = noise_bits(a.seed_mixed, id, V, (uint64_t)sm);
+#pragma unroll
+            for (int al = 0; al < 4; al++) {
+                cx<double> e[3];
+#pragma unroll
+                for (int k = 0; k < 3; k++) e[k] = z4_value<double>((uint32_t)(bm >> (2 * (3 * al + k))) & 3u);
+                su3_apply_d(U, false, phm, e, o);
+#pragma unroll
+                for (int k = 0; k < 3; k++) gg[3 * al + k] = gg[3 * al + k] - o[k];
+            }
+        }
+        cx<double> p0[6];
+        load_half_spinor<S>(sol, g.Vs, s0, h, p0);
+        const uint64_t b0 = noise_bits(a.seed_mixed, id, V, (uint64_t)s0);
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int al = 0; al < 4; al++) {
+                cx<double> v = {0.0, 0.0};
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    v = v + z4_conj_times((uint32_t)(b0 >> (2 * (3 * al + k))) & 3u, f[3 * b + k]);
+                    v = v - cmulc(gg[3 * al + k], p0[3 * b + k]);
+                }
+                v = 0.25 * v;
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    if (i < npy) {
+                        const double2 ph = a.phy[i * Ly + y];
+                        acc[i][4 * b + al] = acc[i][4 * b + al] + cx<double>{ph.x, ph.y} * v;
+                    }
+                }
+            }
+    }
+    const int rs = r * 4 + mu;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        if (i < npy) {
+            double2* o = a.A + ((((((size_t)rs * Lt + t) * Lz + z) * npy + i) * 16 + 8 * h) * Lx + x);
+#pragma unroll
+            for (int e = 0; e < 8; e++) o[(size_t)e * Lx] = make_double2(acc[i][e].re, acc[i][e].im);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_contract_b(ContractArgs a) {
     const Geom& g = a.geo;
     const int Lx = g.L[0], Lz = g.L[2], Lt = g.L[3];
@@ -207,26 +336,37 @@ __global__ __launch_bounds__(256) void k_contract_c(ContractArgs a) {
         acc = acc + cx<double>{pz.x, pz.y} * tr;
     }
     acc = cx<double>{a.coef.x, a.coef.y} * acc;
-    double2* o = a.out + (size_t)a.out_slot[r] * a.out_stride;
+    // slice r of the scratch is direction r % nmu of source r / nmu
+    double2* o = a.out + (size_t)a.out_slot[r / a.nmu] * a.out_stride + (size_t)(r % a.nmu) * 16 * a.n_mom * Lt;
     o[((size_t)gn * a.n_mom + m) * Lt + t] = make_double2(acc.re, acc.im);
 }
 
-void launch_contract(hipStream_t st, const ContractArgs& a, int xprec) {
-    const Geom& g = a.geo;
+void launch_contract(hipStream_t st, const ContractArgs& a0, int xprec) {
+    const Geom& g = a0.geo;
     const long nrow = 2L * g.L[0] * g.L[2] * g.L[3];
-    dim3 ga((unsigned)((nrow + 255) / 256), (unsigned)a.nrhs);
+    dim3 ga((unsigned)((nrow + 255) / 256), (unsigned)a0.nrhs);
+    // stages B and C see one slice per (source, direction)
+    ContractArgs a = a0;
+    a.nrhs = a0.nrhs * a0.nmu;
+    if (a0.est == 3) {
+        dim3 gd(ga.x, ga.y, 4);
+        if (xprec == P_F64)
+            hipLaunchKernelGGL((k_contract_d<SF64>), gd, dim3(256), 0, st, a0);
+        else
+            hipLaunchKernelGGL((k_contract_d<SF32>), gd, dim3(256), 0, st, a0);
+    }
     auto run_a = [&](auto est) {
         constexpr int E = decltype(est)::value;
         if (xprec == P_F64)
-            hipLaunchKernelGGL((k_contract_a<SF64, E>), ga, dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_contract_a<SF64, E>), ga, dim3(256), 0, st, a0);
         else
-            hipLaunchKernelGGL((k_contract_a<SF32, E>), ga, dim3(256), 0, st, a);
+            hipLaunchKernelGGL((k_contract_a<SF32, E>), ga, dim3(256), 0, st, a0);
     };
     if (a.est == 1)
         run_a(std::integral_constant<int, 1>{});
     else if (a.est == 2)
         run_a(std::integral_constant<int, 2>{});
-    else
+    else if (a.est == 0)
         run_a(std::integral_constant<int, 0>{});
     const long nb = 16L * a.npy * g.L[2] * g.L[3];
     hipLaunchKernelGGL(k_contract_b, dim3((unsigned)((nb + 255) / 256), (unsigned)a.nrhs), dim3(256), 0, st, a);

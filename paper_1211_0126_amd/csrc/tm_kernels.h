@@ -34,6 +34,8 @@ struct ContractArgs {
     const void* dsol;     // est 2: native FP64 D s = (1 - kappa H) s of the same sources
     int est;              // 0 eta^dag Gamma s; 1, 2 the one-end loops (Eqs. 5, 6)
     double2 coef;         // factor of every loop element (1; -2i 2 kappa mu; 2)
+    const void* gauge64;  // est 3: FP64 links (double2 [4][9][Vs])
+    int nmu;              // loop sets per source: 4 for est 3 (one per direction), else 1
     int nrhs;
     int npx, npy, npz;    // distinct momentum components per axis (<= 3)
     const double2* phx;   // [npx][Lx] exp(-2 pi i n x / Lx)
@@ -43,9 +45,9 @@ struct ContractArgs {
     const int* mom_idx;   // [n_mom][3] indices into the per-axis lists
     const int* gam_col;   // [16][4] column of the nonzero of row a of the insertion
     const int* gam_ph;    // [16][4] its value i^k as k (Gamma_n, g5 Gamma_n or g5 Gamma_n g5)
-    double2* A;           // scratch [nrhs][Lt][Lz][npy][Lx][16]
-    double2* B;           // scratch [nrhs][Lt][Lz][npx][npy][16]
-    double2* out;         // loops, [slot][16][n_mom][Lt]
+    double2* A;           // scratch [nrhs * nmu][Lt][Lz][npy][Lx][16]
+    double2* B;           // scratch [nrhs * nmu][Lt][Lz][npx][npy][16]
+    double2* out;         // loops, [slot][nmu][16][n_mom][Lt]
     const int* out_slot;  // [nrhs] output slot of each right-hand side (device)
     long out_stride;      // complex elements between slots
 };

@@ -494,9 +494,14 @@ struct Contractor {
     ContractArgs a;
 };
 
+// loop sets per source of an estimator: one per direction for the
+// one-derivative loops
+static int loop_sets(int est) { return est == TM_LOOP_DERIVATIVE ? 4 : 1; }
+
 // Upload phase tables and indices; scratch sized for `maxr` sources.  est
 // selects the loop form: 0 the standard eta^dag Gamma s, 1 and 2 the
-// one-end loops of section 2.3 (Eqs. 5 and 6).
+// one-end loops of section 2.3 (Eqs. 5 and 6), 3 the one-derivative loops
+// (four sets per source, one per direction).
 static tm_status setup_contract(tm_ctx* ctx, const MomPlan& mp, int n_mom, int maxr, uint64_t seed_mixed,
                                 int est, Contractor* c) {
     const Geom& g = ctx->geo;
@@ -509,6 +514,8 @@ static tm_status setup_contract(tm_ctx* ctx, const MomPlan& mp, int n_mom, int m
     // isovector: Tr[X (M_u^-1 - M_d^-1)] = -2i tw <s^dag g5 X s> with tw = 2 kappa mu,
     // from M_u - M_d = 2i tw g5 (the printed sign of Eq. 5 is the opposite)
     a.coef = est == 1 ? make_double2(0.0, -2.0 * ctx->twist) : make_double2(est == 2 ? 2.0 : 1.0, 0.0);
+    a.nmu = loop_sets(est);
+    a.gauge64 = ctx->gauge64;
     a.npx = mp.np[0];
     a.npy = mp.np[1];
     a.npz = mp.np[2];
@@ -534,10 +541,10 @@ static tm_status setup_contract(tm_ctx* ctx, const MomPlan& mp, int n_mom, int m
     a.phy = a.phx + a.npx * L0;
     a.phz = a.phy + a.npy * L1;
     a.mom_idx = idd;
-    a.gam_col = ctx->gam_dev + 128 * est;
+    a.gam_col = ctx->gam_dev + 128 * (est == 3 ? 0 : est);
     a.gam_ph = a.gam_col + 64;
-    const size_t A = (size_t)maxr * g.L[3] * g.L[2] * a.npy * g.L[0] * 16 * 16;
-    const size_t B = (size_t)maxr * g.L[3] * g.L[2] * a.npx * a.npy * 16 * 16;
+    const size_t A = (size_t)maxr * a.nmu * g.L[3] * g.L[2] * a.npy * g.L[0] * 16 * 16;
+    const size_t B = (size_t)maxr * a.nmu * g.L[3] * g.L[2] * a.npx * a.npy * 16 * 16;
     a.A = (double2*)ws_get(ctx, "c_A", A, &s);
     a.B = (double2*)ws_get(ctx, "c_B", B, &s);
     if (est == 2) a.dsol = ws_get(ctx, "c_dsol", field_bytes(g, P_F64, maxr), &s);
@@ -570,7 +577,11 @@ static void contract_block(tm_ctx* ctx, Contractor* c, const uint64_t* ids_dev, 
     }
     prof_begin(ctx, TM_KC_CONTRACT);
     launch_contract(ctx->stream, a, xprec);
-    prof_end(ctx, TM_KC_CONTRACT, a.est == 2 ? sb + (double)ctx->geo.V * nrhs * 24.0 * 8 : sb);
+    // est 3 reads s at x and its eight neighbours (each reused by eight
+    // sites: counted once) and the FP64 links once
+    prof_end(ctx, TM_KC_CONTRACT,
+             a.est == 2 ? sb + (double)ctx->geo.V * nrhs * 24.0 * 8
+                        : (a.est == 3 ? sb + (double)ctx->geo.V * 4 * 18 * 8 : sb));
 }
 
 }  // namespace tmq
@@ -629,12 +640,13 @@ tm_status tsm_contract_est(tm_ctx* ctx, int32_t estimator, uint64_t seed, int32_
                            const double* sol_dev, int32_t n_mom, const int32_t* mom_host, double* loops_host) {
     if (!ctx) return TM_EINVAL;
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
-    if (estimator < TM_LOOP_STANDARD || estimator > TM_LOOP_ONEEND_GENERALIZED)
+    if (estimator < TM_LOOP_STANDARD || estimator > TM_LOOP_DERIVATIVE)
         return set_error(ctx, TM_EINVAL, "tsm_contract: unknown estimator");
-    if (nsrc < 1 || !sol_dev || !loops_host || (estimator == TM_LOOP_STANDARD && !ids_host))
+    const bool needs_eta = estimator == TM_LOOP_STANDARD || estimator == TM_LOOP_DERIVATIVE;
+    if (nsrc < 1 || !sol_dev || !loops_host || (needs_eta && !ids_host))
         return set_error(ctx, TM_EINVAL, "tsm_contract: bad argument");
-    if (estimator == TM_LOOP_ONEEND_GENERALIZED && !ctx->gauge_loaded)
-        return set_error(ctx, TM_ESTATE, "tsm_contract: the generalized one-end loop needs the gauge field");
+    if ((estimator == TM_LOOP_ONEEND_GENERALIZED || estimator == TM_LOOP_DERIVATIVE) && !ctx->gauge_loaded)
+        return set_error(ctx, TM_ESTATE, "tsm_contract: this loop needs the gauge field");
     const Geom& g = ctx->geo;
     MomPlan mp;
     tm_status s = plan_momenta(ctx, n_mom, mom_host, &mp);
@@ -642,7 +654,7 @@ tm_status tsm_contract_est(tm_ctx* ctx, int32_t estimator, uint64_t seed, int32_
     const int blk = std::min(nsrc, kMaxBlock);
     Contractor c;
     if ((s = setup_contract(ctx, mp, n_mom, blk, seed_mix(seed), estimator, &c)) != TM_OK) return s;
-    const long nl = 16L * n_mom * g.L[3];
+    const long nl = 16L * loop_sets(estimator) * n_mom * g.L[3];
     uint64_t* ids_dev = (uint64_t*)ws_get(ctx, "contract_ids", sizeof(uint64_t) * nsrc, &s);
     int* slots = (int*)ws_get(ctx, "contract_slots", sizeof(int) * nsrc, &s);
     void* nat = ws_get(ctx, "contract_nat", field_bytes(g, P_F64, blk), &s);
@@ -681,15 +693,15 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double
     MomPlan mp;
     if ((s = plan_momenta(ctx, P->n_mom, P->mom_host, &mp)) != TM_OK) return s;
     const int N = P->n_hp + P->n_lp;
-    const long nl = 16L * P->n_mom * g.L[3];
+    if (P->estimator < TM_LOOP_STANDARD || P->estimator > TM_LOOP_DERIVATIVE)
+        return set_error(ctx, TM_EINVAL, "tsm_loops: unknown estimator");
+    const long nl = 16L * loop_sets(P->estimator) * P->n_mom * g.L[3];
     hipStream_t st = ctx->stream;
     const uint64_t sm = seed_mix(P->seed);
 
     const int blp = default_block(&P->lp), bhp = default_block(&P->hp);
     const int nr_lp = lane_rhs(ctx, &P->lp, blp), nr_hp = lane_rhs(ctx, &P->hp, bhp);
     Contractor c;
-    if (P->estimator < TM_LOOP_STANDARD || P->estimator > TM_LOOP_ONEEND_GENERALIZED)
-        return set_error(ctx, TM_EINVAL, "tsm_loops: unknown estimator");
     if ((s = setup_contract(ctx, mp, P->n_mom, std::max(blp, bhp) + 4, sm, P->estimator, &c)) != TM_OK) return s;
 
     // per-source loops [N][2][nl], source ids, output slots (ids padded at the end)
