@@ -59,9 +59,9 @@ def parse():
     ap.add_argument("--train-pairs", type=int, default=256)
     ap.add_argument("--train-sources", type=int, default=16)
     ap.add_argument("--train-epochs", type=int, default=6)
-    ap.add_argument("--no-one-end", action="store_true",
-                    help="skip the per-estimator step (standard and one-end loops of Eqs. 5 and 6)")
-    ap.add_argument("--one-end-lp", type=int, default=32, help="LP sources of the per-estimator step")
+    ap.add_argument("--no-estimators", action="store_true",
+                    help="skip the per-estimator steps (standard, one-end of Eqs. 5 and 6, one-derivative loops)")
+    ap.add_argument("--estimators-lp", type=int, default=32, help="LP sources of each per-estimator step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--lp-true-resid", action="store_true",
@@ -308,8 +308,8 @@ def main():
 
     if not args.no_compare:
         out["equal_residual"] = compare(args, tq, torch, ctx, wl, n_hp, lp_prec)
-    if not args.no_one_end:
-        out["one_end"] = one_end(args, tq, torch, ctx, wl, lp, hp, mom)
+    if not args.no_estimators:
+        out["estimators"] = estimators(args, tq, torch, ctx, wl, lp, hp, mom)
 
     ctx.close()
     if not args.no_cpu_baseline:
@@ -317,16 +317,17 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def one_end(args, tq, torch, ctx, wl, lp, hp, mom):
-    """The TSM step with each loop estimator (section 2.3: the standard
-    eta^dag Gamma s and the one-end loops of Eqs. 5 and 6) on a smaller
-    source sample, same solvers: LP-phase sources/s and the contraction
-    kernels' time per source (the generalized loop adds one FP64 stencil
-    application per source, counted in the 'other' class)."""
-    n_hp, n_lp = min(2, wl.n_hp), args.one_end_lp
+def estimators(args, tq, torch, ctx, wl, lp, hp, mom):
+    """The TSM step with each loop estimator (the standard eta^dag Gamma s,
+    the one-end loops of Eqs. 5 and 6, the one-derivative loops in four
+    directions) on a smaller source sample, same solvers: LP-phase
+    sources/s and the contraction kernels' time per source (the generalized
+    one-end loop adds one FP64 stencil application per source, counted in
+    the 'other' class)."""
+    n_hp, n_lp = min(2, wl.n_hp), args.estimators_lp
     res = {"sample": "N_HP %d, N_LP %d" % (n_hp, n_lp)}
     for name, est in (("standard", tq.LOOP_STANDARD), ("isovector", tq.LOOP_ONEEND_ISOVECTOR),
-                      ("generalized", tq.LOOP_ONEEND_GENERALIZED)):
+                      ("generalized", tq.LOOP_ONEEND_GENERALIZED), ("derivative", tq.LOOP_DERIVATIVE)):
         tq.tsm_loops(ctx, wl.noise_seed, n_hp, n_lp, lp, hp, mom, stats=False, estimator=est)  # warm
         tq.tm_profile_enable(ctx, True)
         r = tq.tsm_loops(ctx, wl.noise_seed, n_hp, n_lp, lp, hp, mom, stats=False, estimator=est)
@@ -338,7 +339,7 @@ def one_end(args, tq, torch, ctx, wl, lp, hp, mom):
                      "contract_us_per_source": round(1e3 * c["ms"] / n_contr, 1),
                      "contract_GBps": round(c["bytes"] / max(c["ms"], 1e-9) / 1e6, 1),
                      "other_us_per_source": round(1e3 * prof["other"]["ms"] / n_contr, 1)}
-        log("one-end %s: %s" % (name, res[name]))
+        log("estimator %s: %s" % (name, res[name]))
     return res
 
 

@@ -162,15 +162,22 @@ __device__ __forceinline__ void su3_apply_d(const cx<double> U[3][3], bool fwd, 
 
 // One-derivative loops, stage A: one lane per (x, z, t) row, spin half h
 // and direction mu (grid z); the A slice of (source r, direction mu) is
-// r * 4 + mu.  f and g are built from the forward hop first, then the
-// backward one, so only one link is live at a time.
+// r * 4 + mu.  The source-side transport is moved onto the solution,
+//   sum_c conj((U eta')_{ac}) s_{bc} = sum_k conj(eta'_{ak}) (U^dag s)_{bk},
+// so every product with the noise is a Z4 permutation:
+//   4 S_{ba} = sum_k [ f_{bk} conj(eta_{ak}(x))
+//                      - ph+ (U_mu(x)^dag s(x))_{bk} conj(eta_{ak}(x+mu))
+//                      + ph- (U_mu(x-mu) s(x))_{bk} conj(eta_{ak}(x-mu)) ],
+//   f = ph+ U_mu(x) s(x+mu) - ph- U_mu(x-mu)^dag s(x-mu).
 template <class S>
 __global__ __launch_bounds__(256) void k_contract_d(ContractArgs a) {
     const Geom& g = a.geo;
     const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
     const long nrow = (long)Lx * Lz * Lt;
-    const long tid = (long)blockIdx.x * 256 + threadIdx.x;
-    const int r = blockIdx.y;
+    // the source is the fastest grid index: the blocks of all sources on
+    // the same rows run together and share the links through L2
+    const long tid = (long)blockIdx.y * 256 + threadIdx.x;
+    const int r = blockIdx.x;
     const int mu = blockIdx.z;
     if (tid >= 2 * nrow) return;
     const int h = tid >= nrow ? 1 : 0;
@@ -189,77 +196,69 @@ __global__ __launch_bounds__(256) void k_contract_d(ContractArgs a) {
 #pragma unroll
         for (int e = 0; e < 8; e++) acc[i][e] = {0.0, 0.0};
     for (int y = 0; y < Ly; y++) {
-        int c[4] = {x, y, z, t};
+        // neighbour coordinates by selects (a coordinate array indexed by mu
+        // would live in scratch memory)
         const uint32_t s0 = x + Lx * (y + Ly * (z + Lz * t));
-        const int cmu = c[mu], Lmu = g.L[mu];
+        const int cmu = mu == 0 ? x : (mu == 1 ? y : (mu == 2 ? z : t));
+        const int Lmu = mu == 0 ? Lx : (mu == 1 ? Ly : (mu == 2 ? Lz : Lt));
         const bool wrap_p = cmu + 1 == Lmu, wrap_m = cmu == 0;
-        c[mu] = wrap_p ? 0 : cmu + 1;
-        const uint32_t sp = c[0] + Lx * (c[1] + Ly * (c[2] + Lz * c[3]));
-        c[mu] = wrap_m ? Lmu - 1 : cmu - 1;
-        const uint32_t sm = c[0] + Lx * (c[1] + Ly * (c[2] + Lz * c[3]));
+        const int up = wrap_p ? 0 : cmu + 1, dn = wrap_m ? Lmu - 1 : cmu - 1;
+        const uint32_t sp = (mu == 0 ? up : x) + Lx * ((mu == 1 ? up : y) + Ly * ((mu == 2 ? up : z) + Lz * (mu == 3 ? up : t)));
+        const uint32_t sm = (mu == 0 ? dn : x) + Lx * ((mu == 1 ? dn : y) + Ly * ((mu == 2 ? dn : z) + Lz * (mu == 3 ? dn : t)));
         const double php = (mu == 3 && wrap_p) ? (double)g.t_bc : 1.0;
         const double phm = (mu == 3 && wrap_m) ? (double)g.t_bc : 1.0;
-        cx<double> f[6], gg[12];
-        {
-            // forward hop: U_mu(x) applied to s(x+mu) (rows of half h) and eta(x+mu)
-            cx<double> U[3][3], p[6];
-            load_link<GF64, double>(a.gauge64, g.Vs, mu, s0, U);
-            load_half_spinor<S>(sol, g.Vs, sp, h, p);
-            su3_apply_d(U, true, php, p, f);
-            su3_apply_d(U, true, php, p + 3, f + 3);
-            const uint64_t bp = noise_bits(a.seed_mixed, id, V, (uint64_t)sp);
+        cx<double> S8[8];
 #pragma unroll
-            for (int al = 0; al < 4; al++) {
-                cx<double> e[3];
-#pragma unroll
-                for (int k = 0; k < 3; k++) e[k] = z4_value<double>((uint32_t)(bp >> (2 * (3 * al + k))) & 3u);
-                su3_apply_d(U, true, php, e, gg + 3 * al);
-            }
-        }
-        {
-            // backward hop: U_mu(x-mu)^dag applied to s(x-mu) and eta(x-mu), subtracted
-            cx<double> U[3][3], p[6], o[3];
-            load_link<GF64, double>(a.gauge64, g.Vs, mu, sm, U);
-            load_half_spinor<S>(sol, g.Vs, sm, h, p);
-#pragma unroll
-            for (int b = 0; b < 2; b++) {
-                su3_apply_d(U, false, phm, p + 3 * b, o);
-#pragma unroll
-                for (int k = 0; k < 3; k++) f[3 * b + k] = f[3 * b + k] - o[k];
-            }
-            const uint64_t bm = noise_bits(a.seed_mixed, id, V, (uint64_t)sm);
-#pragma unroll
-            for (int al = 0; al < 4; al++) {
-                cx<double> e[3];
-#pragma unroll
-                for (int k = 0; k < 3; k++) e[k] = z4_value<double>((uint32_t)(bm >> (2 * (3 * al + k))) & 3u);
-                su3_apply_d(U, false, phm, e, o);
-#pragma unroll
-                for (int k = 0; k < 3; k++) gg[3 * al + k] = gg[3 * al + k] - o[k];
-            }
-        }
+        for (int e = 0; e < 8; e++) S8[e] = {0.0, 0.0};
         cx<double> p0[6];
         load_half_spinor<S>(sol, g.Vs, s0, h, p0);
         const uint64_t b0 = noise_bits(a.seed_mixed, id, V, (uint64_t)s0);
+        // S8[4b + al] += sum_k v[3b + k] conj(eta_{al k}) for the noise bits nb
+        auto add_z4 = [&](uint64_t nb, const cx<double> v[6], double sgn) {
 #pragma unroll
-        for (int b = 0; b < 2; b++)
+            for (int b = 0; b < 2; b++)
 #pragma unroll
-            for (int al = 0; al < 4; al++) {
-                cx<double> v = {0.0, 0.0};
+                for (int al = 0; al < 4; al++) {
+                    cx<double> w = {0.0, 0.0};
 #pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    v = v + z4_conj_times((uint32_t)(b0 >> (2 * (3 * al + k))) & 3u, f[3 * b + k]);
-                    v = v - cmulc(gg[3 * al + k], p0[3 * b + k]);
+                    for (int k = 0; k < 3; k++)
+                        w = w + z4_conj_times((uint32_t)(nb >> (2 * (3 * al + k))) & 3u, v[3 * b + k]);
+                    S8[4 * b + al] = S8[4 * b + al] + sgn * w;
                 }
-                v = 0.25 * v;
+        };
+        {
+            // forward hop through U_mu(x)
+            cx<double> U[3][3], p[6], v[6];
+            load_link<GF64, double>(a.gauge64, g.Vs, mu, s0, U);
+            load_half_spinor<S>(sol, g.Vs, sp, h, p);
+            su3_apply_d(U, true, php, p, v);
+            su3_apply_d(U, true, php, p + 3, v + 3);
+            add_z4(b0, v, 1.0);
+            su3_apply_d(U, false, php, p0, v);
+            su3_apply_d(U, false, php, p0 + 3, v + 3);
+            add_z4(noise_bits(a.seed_mixed, id, V, (uint64_t)sp), v, -1.0);
+        }
+        {
+            // backward hop through U_mu(x - mu)
+            cx<double> U[3][3], p[6], v[6];
+            load_link<GF64, double>(a.gauge64, g.Vs, mu, sm, U);
+            load_half_spinor<S>(sol, g.Vs, sm, h, p);
+            su3_apply_d(U, false, phm, p, v);
+            su3_apply_d(U, false, phm, p + 3, v + 3);
+            add_z4(b0, v, -1.0);
+            su3_apply_d(U, true, phm, p0, v);
+            su3_apply_d(U, true, phm, p0 + 3, v + 3);
+            add_z4(noise_bits(a.seed_mixed, id, V, (uint64_t)sm), v, 1.0);
+        }
 #pragma unroll
-                for (int i = 0; i < 3; i++) {
-                    if (i < npy) {
-                        const double2 ph = a.phy[i * Ly + y];
-                        acc[i][4 * b + al] = acc[i][4 * b + al] + cx<double>{ph.x, ph.y} * v;
-                    }
-                }
+        for (int i = 0; i < 3; i++) {
+            if (i < npy) {
+                const double2 ph = a.phy[i * Ly + y];
+                const cx<double> w = {0.25 * ph.x, 0.25 * ph.y};
+#pragma unroll
+                for (int e = 0; e < 8; e++) acc[i][e] = acc[i][e] + w * S8[e];
             }
+        }
     }
     const int rs = r * 4 + mu;
 #pragma unroll
@@ -349,7 +348,7 @@ void launch_contract(hipStream_t st, const ContractArgs& a0, int xprec) {
     ContractArgs a = a0;
     a.nrhs = a0.nrhs * a0.nmu;
     if (a0.est == 3) {
-        dim3 gd(ga.x, ga.y, 4);
+        dim3 gd(ga.y, ga.x, 4);
         if (xprec == P_F64)
             hipLaunchKernelGGL((k_contract_d<SF64>), gd, dim3(256), 0, st, a0);
         else
