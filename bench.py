@@ -254,8 +254,10 @@ def main():
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     prec_name = {v: k for k, v in PREC_NAMES.items()}
     dom_name = "%s %s NR=%d tseg=%d" % (kname(d), prec_name[d["prec"]], d["lane_rhs"], d["tseg"])
+    copy_gbs = copy_bandwidth(torch)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dom_name, wl.name),
+                "torch_copy_GBps": round(copy_gbs, 1), "frac_of_torch_copy": round(achieved / copy_gbs, 4),
                 "kernel": dom_name,
                 "launches": d["launches"], "avg_launch_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": avg_bytes}
@@ -315,6 +317,28 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_threads)
     print(json.dumps(out), flush=True)
+
+
+def copy_bandwidth(torch, nbytes=4 << 30, reps=5):
+    """Measured bandwidth of torch's device-to-device copy of nbytes (read +
+    write bytes per second, best of reps): a streaming reference next to the
+    8 TB/s peak, not a ceiling (the library's own streaming kernels run
+    faster)."""
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return 2.0 * 4 * n / (best * 1e-3) / 1e9
 
 
 def estimators(args, tq, torch, ctx, wl, lp, hp, mom):
