@@ -212,22 +212,30 @@ __global__ __launch_bounds__(256) void k_contract_d(ContractArgs a) {
         for (int e = 0; e < 8; e++) S8[e] = {0.0, 0.0};
         cx<double> p0[6];
         load_half_spinor<S>(sol, g.Vs, s0, h, p0);
-        const uint64_t b0 = noise_bits(a.seed_mixed, id, V, (uint64_t)s0);
-        // S8[4b + al] += sum_k v[3b + k] conj(eta_{al k}) for the noise bits nb
+        // S8[4b + al] += sgn sum_k conj(eta_{al k}) v[3b + k] for the noise
+        // bits nb: each Z4 code becomes the unit (c, d) = conj(i^k) once and
+        // serves both spin rows as two FP64 products
         auto add_z4 = [&](uint64_t nb, const cx<double> v[6], double sgn) {
 #pragma unroll
-            for (int b = 0; b < 2; b++)
+            for (int al = 0; al < 4; al++)
 #pragma unroll
-                for (int al = 0; al < 4; al++) {
-                    cx<double> w = {0.0, 0.0};
+                for (int k = 0; k < 3; k++) {
+                    const uint32_t code = (uint32_t)(nb >> (2 * (3 * al + k))) & 3u;
+                    // conj(i^code): 1, -i, -1, i
+                    const double c = code == 0u ? sgn : (code == 2u ? -sgn : 0.0);
+                    const double d = code == 1u ? -sgn : (code == 3u ? sgn : 0.0);
 #pragma unroll
-                    for (int k = 0; k < 3; k++)
-                        w = w + z4_conj_times((uint32_t)(nb >> (2 * (3 * al + k))) & 3u, v[3 * b + k]);
-                    S8[4 * b + al] = S8[4 * b + al] + sgn * w;
+                    for (int b = 0; b < 2; b++) {
+                        const cx<double> x0 = v[3 * b + k];
+                        S8[4 * b + al] = {S8[4 * b + al].re + (c * x0.re - d * x0.im),
+                                          S8[4 * b + al].im + (c * x0.im + d * x0.re)};
+                    }
                 }
         };
+        const uint64_t b0 = noise_bits(a.seed_mixed, id, V, (uint64_t)s0);
         {
-            // forward hop through U_mu(x)
+            // forward hop through U_mu(x): +ph+ (U s(x+mu)) conj(eta(x)) and
+            // -ph+ (U^dag s(x)) conj(eta(x+mu))
             cx<double> U[3][3], p[6], v[6];
             load_link<GF64, double>(a.gauge64, g.Vs, mu, s0, U);
             load_half_spinor<S>(sol, g.Vs, sp, h, p);
@@ -239,7 +247,8 @@ __global__ __launch_bounds__(256) void k_contract_d(ContractArgs a) {
             add_z4(noise_bits(a.seed_mixed, id, V, (uint64_t)sp), v, -1.0);
         }
         {
-            // backward hop through U_mu(x - mu)
+            // backward hop through U_mu(x - mu): -ph- (U^dag s(x-mu)) conj(eta(x))
+            // and +ph- (U s(x)) conj(eta(x-mu))
             cx<double> U[3][3], p[6], v[6];
             load_link<GF64, double>(a.gauge64, g.Vs, mu, sm, U);
             load_half_spinor<S>(sol, g.Vs, sm, h, p);
