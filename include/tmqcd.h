@@ -256,6 +256,13 @@ tm_status tsm_solve_batch(tm_ctx* ctx, const tsm_solve_params* params, uint64_t 
 tm_status tsm_contract(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* ids_host,
                        const double* sol_dev, int32_t n_mom, const int32_t* mom_host, double* loops_host);
 
+/* n_mom value of tsm_contract / tsm_contract_est asking for every momentum
+   of the lattice (the Fourier transform of section 3): p = 2 pi n / L with
+   0 <= n_i < L_i, momentum index n_x + Lx (n_y + Ly n_z), mom_host ignored;
+   standard loop only (TM_ENOTSUP otherwise).  loops_host is then complex128
+   [nsrc][16][Lx*Ly*Lz][Lt]. */
+#define TM_ALL_MOMENTA (-1)
+
 /* tsm_contract with the loop estimator chosen (tm_loop_estimator; section
    2.3, Eqs. 5 and 6, and the derivative loops of section 3).  The one-end
    estimators use the solutions alone: seed and ids_host are ignored and

@@ -23,6 +23,7 @@ LAYOUT_CANONICAL, LAYOUT_NATIVE = 0, 1
 STOP_NORMAL, STOP_TRUE = 0, 1
 SOLVER_CG, SOLVER_FCG_LEARNED = 0, 1
 LOOP_STANDARD, LOOP_ONEEND_ISOVECTOR, LOOP_ONEEND_GENERALIZED, LOOP_DERIVATIVE = 0, 1, 2, 3
+ALL_MOMENTA = -1
 KC_NAMES = ["dslash", "dslash_upd", "blas", "contract", "other", "apply"]
 
 
@@ -236,18 +237,25 @@ def tsm_solve_batch(ctx: Context, params: SolveParams, seed, ids, want_solutions
 def tsm_contract(ctx: Context, seed, ids, sol, mom, estimator=LOOP_STANDARD):
     """Loops of given solutions, complex128 [n][16][n_mom][Lt] (host).  The
     one-end estimators ignore seed and ids (pass ids=None and the count comes
-    from sol)."""
+    from sol).  mom=None projects the standard loop onto every momentum of
+    the lattice: [n][16][Lx*Ly*Lz][Lt]."""
     import torch
     n = len(ids) if ids is not None else int(sol.shape[0])
     ids_a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64)) if ids is not None else None
-    mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
-    el = (4, 16, mom.shape[0], ctx.dims[3]) if estimator == LOOP_DERIVATIVE else (16, mom.shape[0], ctx.dims[3])
+    if mom is None:
+        # every momentum of the lattice, index nx + Lx (ny + Ly nz)
+        n_mom, mom_p = ALL_MOMENTA, None
+        el = (16, ctx.dims[0] * ctx.dims[1] * ctx.dims[2], ctx.dims[3])
+    else:
+        mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+        n_mom, mom_p = mom.shape[0], _ptr(mom)
+        el = (4, 16, n_mom, ctx.dims[3]) if estimator == LOOP_DERIVATIVE else (16, n_mom, ctx.dims[3])
     out = np.zeros((n,) + el, dtype=np.complex128)
     assert sol.is_cuda and sol.is_contiguous() and tuple(sol.shape) == (n, ctx.V, 4, 3)
     assert sol.dtype == torch.complex128
     ctx.check(ctx.lib.tsm_contract_est(ctx.h, int(estimator), int(seed), n,
                                        _ptr(ids_a) if ids_a is not None else None,
-                                       ctypes.c_void_p(sol.data_ptr()), mom.shape[0], _ptr(mom), _ptr(out)))
+                                       ctypes.c_void_p(sol.data_ptr()), n_mom, mom_p, _ptr(out)))
     return out
 
 

@@ -382,6 +382,109 @@ void launch_contract(hipStream_t st, const ContractArgs& a0, int xprec) {
     hipLaunchKernelGGL(k_contract_c, dim3((unsigned)((nc + 255) / 256), (unsigned)a.nrhs), dim3(256), 0, st, a);
 }
 
+// ---------------------------------------------------------------------------
+// Projection onto all L^3 momenta (the paper's FFT step): the site matrices
+// S_{ba}(x) = sum_c s_{bc}(x) conj(eta_{ac}(x)) of the standard loop are
+// written out, transformed along x, y and z by direct DFTs of length L
+// (phases from a table exp(-2 pi i m / L)), then traced with each Gamma_n.
+// Layout of the site and spectrum buffers: [r][t][z][y][x][16], entry
+// 4 b + a.
+// ---------------------------------------------------------------------------
+template <class S>
+__global__ __launch_bounds__(256) void k_site_matrix(ContractArgs a, double2* out) {
+    const Geom& g = a.geo;
+    const long tid = (long)blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (tid >= 2 * g.V) return;
+    const int h = tid >= g.V ? 1 : 0;
+    const uint32_t s = (uint32_t)(tid - h * g.V);
+    cx<double> p[6];
+    load_half_spinor<S>(field_rhs<S>(a.sol, g.Vs, r), g.Vs, s, h, p);
+    const uint64_t bits = noise_bits(a.seed_mixed, a.ids[r], (uint64_t)g.V, (uint64_t)s);
+    double2* o = out + ((size_t)r * g.V + s) * 16 + 8 * h;
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+        for (int al = 0; al < 4; al++) {
+            cx<double> v = {0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+                v = v + z4_conj_times((uint32_t)(bits >> (2 * (3 * al + c))) & 3u, p[3 * b + c]);
+            o[4 * b + al] = make_double2(v.re, v.im);
+        }
+}
+
+// out[.., k, ..] = sum_j in[.., j, ..] tw[(k j) mod L] along one axis of
+// length L whose elements are `stride` double2 apart; one lane per output
+// element, lanes of consecutive entries and frequencies share the reads.
+__global__ __launch_bounds__(256) void k_dft_axis(const double2* in, double2* out, long total, int L, long stride,
+                                                  const double2* tw) {
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const long inner = i % stride;
+    const long rest = i / stride;
+    const int k = (int)(rest % L);
+    const long outer = rest / L;
+    const double2* src = in + outer * L * stride + inner;
+    cx<double> acc = {0.0, 0.0};
+    int m = 0;
+    for (int j = 0; j < L; j++) {
+        const double2 v = src[(long)j * stride];
+        const double2 w = tw[m];
+        acc = acc + cx<double>{w.x, w.y} * cx<double>{v.x, v.y};
+        m += k;
+        if (m >= L) m -= L;
+    }
+    out[i] = make_double2(acc.re, acc.im);
+}
+
+// loops[r][n][m][t] = sum_a Gamma_n[a][col] S~_{col a}(t, m), m = kx + Lx (ky + Ly kz)
+__global__ __launch_bounds__(256) void k_trace_all(ContractArgs a, const double2* spec, double2* out) {
+    const Geom& g = a.geo;
+    const long V3 = (long)g.L[0] * g.L[1] * g.L[2];
+    const int Lt = g.L[3];
+    const long n_el = 16L * V3 * Lt;
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= n_el) return;
+    const int t = (int)(i % Lt);
+    const long q = i / Lt;
+    const long m = q % V3;
+    const int gn = (int)(q / V3);
+    const double2* e = spec + (((size_t)r * Lt + t) * V3 + m) * 16;
+    cx<double> tr = {0.0, 0.0};
+#pragma unroll
+    for (int al = 0; al < 4; al++) {
+        const int be = a.gam_col[gn * 4 + al];
+        const double2 v = e[be * 4 + al];
+        tr = tr + z4_value<double>((uint32_t)a.gam_ph[gn * 4 + al]) * cx<double>{v.x, v.y};
+    }
+    out[(size_t)a.out_slot[r] * a.out_stride + i] = make_double2(tr.re, tr.im);
+}
+
+void launch_contract_all_momenta(hipStream_t st, const ContractArgs& a, int xprec, double2* buf0, double2* buf1,
+                                 const double2* tw) {
+    const Geom& g = a.geo;
+    const long nsite = 2L * g.V;
+    dim3 gs((unsigned)((nsite + 255) / 256), (unsigned)a.nrhs);
+    if (xprec == P_F64)
+        hipLaunchKernelGGL(k_site_matrix<SF64>, gs, dim3(256), 0, st, a, buf0);
+    else
+        hipLaunchKernelGGL(k_site_matrix<SF32>, gs, dim3(256), 0, st, a, buf0);
+    const long total = (long)a.nrhs * g.V * 16;
+    const unsigned nb = (unsigned)((total + 255) / 256);
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
+    // twiddle tables back to back: x, y, z
+    hipLaunchKernelGGL(k_dft_axis, dim3(nb), dim3(256), 0, st, (const double2*)buf0, buf1, total, Lx, 16L, tw);
+    hipLaunchKernelGGL(k_dft_axis, dim3(nb), dim3(256), 0, st, (const double2*)buf1, buf0, total, Ly, 16L * Lx,
+                       tw + Lx);
+    hipLaunchKernelGGL(k_dft_axis, dim3(nb), dim3(256), 0, st, (const double2*)buf0, buf1, total, Lz,
+                       16L * Lx * Ly, tw + Lx + Ly);
+    const long n_el = 16L * Lx * Ly * Lz * g.L[3];
+    hipLaunchKernelGGL(k_trace_all, dim3((unsigned)((n_el + 255) / 256), (unsigned)a.nrhs), dim3(256), 0, st, a,
+                       (const double2*)buf1, a.out);
+}
+
 // TSM combination of Eq. 4 from the per-source loops ps[j][slot][k]
 // (slot 0 LP, 1 HP), k over nl = 16 * n_mom * Lt elements.  Two passes in
 // source order: means, then the spread.  out/err: [3][nl] (C, B, T).

@@ -138,6 +138,11 @@ void launch_noise_c128(hipStream_t st, const Geom& g, uint64_t seed_mixed, const
 
 // loops
 void launch_contract(hipStream_t st, const ContractArgs& a, int xprec);
+// standard loops at all Lx*Ly*Lz momenta: site matrices into buf0, DFTs
+// ping-ponging buf0/buf1 (each nrhs * V * 16 double2), tw the x, y, z
+// phase tables exp(-2 pi i m / L) back to back
+void launch_contract_all_momenta(hipStream_t st, const ContractArgs& a, int xprec, double2* buf0, double2* buf1,
+                                 const double2* tw);
 void launch_tsm_final(hipStream_t st, const double* ps, long nl, int n_hp, int n_lp, double* out, double* err);
 
 }  // namespace tmq

@@ -584,6 +584,66 @@ static void contract_block(tm_ctx* ctx, Contractor* c, const uint64_t* ids_dev, 
                         : (a.est == 3 ? sb + (double)ctx->geo.V * 4 * 18 * 8 : sb));
 }
 
+// Standard loops of given solutions at all Lx*Ly*Lz momenta (n_mom =
+// TM_ALL_MOMENTA): site matrices, three DFT stages, Gamma traces; blocks of
+// up to four sources (each block holds two buffers of V * 16 complex per
+// source).
+static tm_status contract_all_momenta(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* ids_host,
+                                      const double* sol_dev, double* loops_host) {
+    const Geom& g = ctx->geo;
+    hipStream_t st = ctx->stream;
+    tm_status s = TM_OK;
+    const int blk = std::min(nsrc, 4);
+    const long V3 = (long)g.L[0] * g.L[1] * g.L[2];
+    const long nl = 16L * V3 * g.L[3];
+    std::vector<double> tw;
+    const double twopi = 2.0 * std::acos(-1.0);
+    for (int d = 0; d < 3; d++)
+        for (int m = 0; m < g.L[d]; m++) {
+            tw.push_back(std::cos(twopi * m / g.L[d]));
+            tw.push_back(-std::sin(twopi * m / g.L[d]));
+        }
+    double* twd = (double*)ws_get(ctx, "fft_tw", sizeof(double) * tw.size(), &s);
+    double2* buf0 = (double2*)ws_get(ctx, "fft_buf0", sizeof(double2) * 16 * (size_t)g.V * blk, &s);
+    double2* buf1 = (double2*)ws_get(ctx, "fft_buf1", sizeof(double2) * 16 * (size_t)g.V * blk, &s);
+    uint64_t* ids_dev = (uint64_t*)ws_get(ctx, "contract_ids", sizeof(uint64_t) * nsrc, &s);
+    int* slots = (int*)ws_get(ctx, "contract_slots", sizeof(int) * nsrc, &s);
+    void* nat = ws_get(ctx, "contract_nat", field_bytes(g, P_F64, blk), &s);
+    double* out = (double*)ws_get(ctx, "fft_out", sizeof(double) * 2 * nl * nsrc, &s);
+    if (s != TM_OK) return s;
+    std::vector<int> sl(nsrc);
+    for (int i = 0; i < nsrc; i++) sl[i] = i;
+    TM_COPY(twd, tw.data(), sizeof(double) * tw.size(), hipMemcpyHostToDevice);
+    TM_COPY(ids_dev, ids_host, sizeof(uint64_t) * nsrc, hipMemcpyHostToDevice);
+    TM_COPY(slots, sl.data(), sizeof(int) * nsrc, hipMemcpyHostToDevice);
+    ContractArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geo = g;
+    a.seed_mixed = seed_mix(seed);
+    a.gam_col = ctx->gam_dev;
+    a.gam_ph = ctx->gam_dev + 64;
+    a.out = (double2*)out;
+    a.out_stride = nl;
+    a.nmu = 1;
+    for (int j0 = 0; j0 < nsrc; j0 += blk) {
+        const int nb = std::min(blk, nsrc - j0);
+        launch_field_convert(st, g, P_F64, nb, true, sol_dev + (size_t)j0 * g.V * 24, nat);
+        a.ids = ids_dev + j0;
+        a.sol = nat;
+        a.nrhs = nb;
+        a.out_slot = slots + j0;
+        prof_begin(ctx, TM_KC_CONTRACT);
+        launch_contract_all_momenta(st, a, P_F64, buf0, buf1, (const double2*)twd);
+        // site matrices written once, three DFT passes read and write
+        // V * 16 complex each, the traces read them once more
+        prof_end(ctx, TM_KC_CONTRACT, (double)g.V * nb * (24.0 * 8 + 16 * 16 * 8.0));
+        TM_HIP(hipGetLastError());
+    }
+    TM_HIP(hipMemcpyAsync(loops_host, out, sizeof(double) * 2 * nl * nsrc, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    return TM_OK;
+}
+
 }  // namespace tmq
 
 using namespace tmq;
@@ -647,6 +707,11 @@ tm_status tsm_contract_est(tm_ctx* ctx, int32_t estimator, uint64_t seed, int32_
         return set_error(ctx, TM_EINVAL, "tsm_contract: bad argument");
     if ((estimator == TM_LOOP_ONEEND_GENERALIZED || estimator == TM_LOOP_DERIVATIVE) && !ctx->gauge_loaded)
         return set_error(ctx, TM_ESTATE, "tsm_contract: this loop needs the gauge field");
+    if (n_mom == TM_ALL_MOMENTA) {
+        if (estimator != TM_LOOP_STANDARD)
+            return set_error(ctx, TM_ENOTSUP, "tsm_contract: all momenta only for the standard loop");
+        return contract_all_momenta(ctx, seed, nsrc, ids_host, sol_dev, loops_host);
+    }
     const Geom& g = ctx->geo;
     MomPlan mp;
     tm_status s = plan_momenta(ctx, n_mom, mom_host, &mp);

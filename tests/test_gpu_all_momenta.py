@@ -1,0 +1,70 @@
+"""GPU parity of the projection of the standard loop onto every momentum of
+the lattice (site matrices, three DFT stages, Gamma traces) against the
+oracle's direct phase sums, and against the separable 27-momentum path on a
+larger lattice."""
+
+import numpy as np
+import pytest
+
+from lattice_inputs import make_gauge
+from lattice_inputs.workloads import momenta_27
+
+pytestmark = pytest.mark.gpu
+
+KAPPA, MU = 0.1632, 0.004
+
+
+def all_momenta(dims):
+    return np.array([(nx, ny, nz) for nz in range(dims[2]) for ny in range(dims[1]) for nx in range(dims[0])],
+                    dtype=np.int32)
+
+
+@pytest.mark.parametrize("dims,kind", [((4, 4, 4, 4), "cg"), ((6, 4, 8, 4), "rand"), ((2, 6, 4, 6), "rand")])
+def test_all_momenta_match_oracle(orc, dims, kind):
+    import torch
+    import paper_1211_0126_amd as tq
+    U = make_gauge(dims, 0.3, 29)
+    ctx = tq.tm_create(dims, KAPPA, MU, -1)
+    tq.tm_gauge_load(ctx, U)
+    ids = [0, 3, 4, 7, 11]
+    v = int(np.prod(dims))
+    if kind == "cg":
+        sols = np.stack([orc.cgnr(dims, -1, KAPPA, MU, U, orc.noise_z4(dims, 9, j), 1e-3)[0] for j in ids])
+    else:
+        rng = np.random.default_rng(99)
+        sols = rng.standard_normal((len(ids), v, 4, 3)) + 1j * rng.standard_normal((len(ids), v, 4, 3))
+    print("all momenta dims=%s kind=%s" % (dims, kind), flush=True)
+    got = tq.tsm_contract(ctx, 9, ids, torch.from_numpy(sols).cuda(), None)
+    ctx.close()
+    mom = all_momenta(dims)
+    assert got.shape == (len(ids), 16, len(mom), dims[3])
+    for i, j in enumerate(ids):
+        ref = orc.loops(dims, orc.noise_z4(dims, 9, j), sols[i], mom)
+        assert np.max(np.abs(got[i] - ref)) <= 1e-10 * np.max(np.abs(ref)), i
+
+
+def test_all_momenta_agree_with_separable_path():
+    """On 16x8x8x16 the 27 momenta with |n_i| <= 1 of the full projection
+    (n = -1 is n = L - 1) equal the separable path's."""
+    import torch
+    import paper_1211_0126_amd as tq
+    dims = (16, 8, 8, 16)
+    U = make_gauge(dims, 0.25, 31)
+    ctx = tq.tm_create(dims, KAPPA, MU, -1)
+    tq.tm_gauge_load(ctx, U)
+    rng = np.random.default_rng(7)
+    v = int(np.prod(dims))
+    sols = rng.standard_normal((6, v, 4, 3)) + 1j * rng.standard_normal((6, v, 4, 3))
+    ids = list(range(20, 26))
+    sol = torch.from_numpy(sols).cuda()
+    print("all momenta vs separable", flush=True)
+    full = tq.tsm_contract(ctx, 4, ids, sol, None)
+    m27 = momenta_27()
+    sep = tq.tsm_contract(ctx, 4, ids, sol, m27)
+    with pytest.raises(tq.TmError) as e:
+        tq.tsm_contract(ctx, 4, ids, sol, None, estimator=tq.LOOP_ONEEND_ISOVECTOR)
+    assert e.value.code == -5
+    ctx.close()
+    idx = [(nx % dims[0]) + dims[0] * ((ny % dims[1]) + dims[1] * (nz % dims[2])) for nx, ny, nz in m27]
+    picked = full[:, :, idx, :]
+    assert np.max(np.abs(picked - sep)) <= 1e-10 * np.max(np.abs(sep))
