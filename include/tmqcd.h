@@ -259,7 +259,8 @@ tm_status tsm_contract(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t*
 /* n_mom value of tsm_contract / tsm_contract_est asking for every momentum
    of the lattice (the Fourier transform of section 3): p = 2 pi n / L with
    0 <= n_i < L_i, momentum index n_x + Lx (n_y + Ly n_z), mom_host ignored;
-   standard loop only (TM_ENOTSUP otherwise).  loops_host is then complex128
+   standard loop and spatial extents <= 128 only (TM_ENOTSUP otherwise).
+   loops_host is then complex128
    [nsrc][16][Lx*Ly*Lz][Lt]. */
 #define TM_ALL_MOMENTA (-1)
 

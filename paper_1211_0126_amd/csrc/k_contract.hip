@@ -415,27 +415,36 @@ __global__ __launch_bounds__(256) void k_site_matrix(ContractArgs a, double2* ou
 }
 
 // out[.., k, ..] = sum_j in[.., j, ..] tw[(k j) mod L] along one axis of
-// length L whose elements are `stride` double2 apart; one lane per output
-// element, lanes of consecutive entries and frequencies share the reads.
-__global__ __launch_bounds__(256) void k_dft_axis(const double2* in, double2* out, long total, int L, long stride,
+// length L <= kDftMaxL whose elements are `stride` double2 apart (stride a
+// multiple of 16).  A block takes one line group of 16 consecutive inner
+// elements: it stages the L x 16 tile and the phases in LDS (each element
+// read once from memory), then each lane forms outputs (k, c) from LDS.
+constexpr int kDftMaxL = 128;  // 34 KB of LDS at the largest L
+__global__ __launch_bounds__(256) void k_dft_axis(const double2* in, double2* out, int L, long stride,
                                                   const double2* tw) {
-    const long i = (long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= total) return;
-    const long inner = i % stride;
-    const long rest = i / stride;
-    const int k = (int)(rest % L);
-    const long outer = rest / L;
-    const double2* src = in + outer * L * stride + inner;
-    cx<double> acc = {0.0, 0.0};
-    int m = 0;
-    for (int j = 0; j < L; j++) {
-        const double2 v = src[(long)j * stride];
-        const double2 w = tw[m];
-        acc = acc + cx<double>{w.x, w.y} * cx<double>{v.x, v.y};
-        m += k;
-        if (m >= L) m -= L;
+    extern __shared__ double2 lds[];  // L * 16 tile entries, then L phases
+    double2* tile = lds;
+    double2* ph = lds + L * 16;
+    const long nchunk = stride / 16;
+    const long outer = (long)blockIdx.x / nchunk;
+    const long base = outer * L * stride + ((long)blockIdx.x % nchunk) * 16;
+    const int n = L * 16;
+    for (int idx = threadIdx.x; idx < n; idx += 256) tile[idx] = in[base + (long)(idx >> 4) * stride + (idx & 15)];
+    for (int idx = threadIdx.x; idx < L; idx += 256) ph[idx] = tw[idx];
+    __syncthreads();
+    for (int o = threadIdx.x; o < n; o += 256) {
+        const int k = o >> 4, c = o & 15;
+        cx<double> acc = {0.0, 0.0};
+        int m = 0;
+        for (int jj = 0; jj < L; jj++) {
+            const double2 v = tile[jj * 16 + c];
+            const double2 w = ph[m];
+            acc = acc + cx<double>{w.x, w.y} * cx<double>{v.x, v.y};
+            m += k;
+            if (m >= L) m -= L;
+        }
+        out[base + (long)k * stride + c] = make_double2(acc.re, acc.im);
     }
-    out[i] = make_double2(acc.re, acc.im);
 }
 
 // loops[r][n][m][t] = sum_a Gamma_n[a][col] S~_{col a}(t, m), m = kx + Lx (ky + Ly kz)
@@ -471,14 +480,15 @@ void launch_contract_all_momenta(hipStream_t st, const ContractArgs& a, int xpre
         hipLaunchKernelGGL(k_site_matrix<SF64>, gs, dim3(256), 0, st, a, buf0);
     else
         hipLaunchKernelGGL(k_site_matrix<SF32>, gs, dim3(256), 0, st, a, buf0);
-    const long total = (long)a.nrhs * g.V * 16;
-    const unsigned nb = (unsigned)((total + 255) / 256);
     const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
-    // twiddle tables back to back: x, y, z
-    hipLaunchKernelGGL(k_dft_axis, dim3(nb), dim3(256), 0, st, (const double2*)buf0, buf1, total, Lx, 16L, tw);
-    hipLaunchKernelGGL(k_dft_axis, dim3(nb), dim3(256), 0, st, (const double2*)buf1, buf0, total, Ly, 16L * Lx,
+    // one block per line group of 16 inner elements: nrhs * V / L blocks per
+    // axis; phase tables back to back: x, y, z
+    auto blocks = [&](int L) { return dim3((unsigned)((long)a.nrhs * g.V / L)); };
+    auto lds = [](int L) { return (unsigned)(sizeof(double2) * 17 * L); };
+    hipLaunchKernelGGL(k_dft_axis, blocks(Lx), dim3(256), lds(Lx), st, (const double2*)buf0, buf1, Lx, 16L, tw);
+    hipLaunchKernelGGL(k_dft_axis, blocks(Ly), dim3(256), lds(Ly), st, (const double2*)buf1, buf0, Ly, 16L * Lx,
                        tw + Lx);
-    hipLaunchKernelGGL(k_dft_axis, dim3(nb), dim3(256), 0, st, (const double2*)buf0, buf1, total, Lz,
+    hipLaunchKernelGGL(k_dft_axis, blocks(Lz), dim3(256), lds(Lz), st, (const double2*)buf0, buf1, Lz,
                        16L * Lx * Ly, tw + Lx + Ly);
     const long n_el = 16L * Lx * Ly * Lz * g.L[3];
     hipLaunchKernelGGL(k_trace_all, dim3((unsigned)((n_el + 255) / 256), (unsigned)a.nrhs), dim3(256), 0, st, a,

@@ -593,6 +593,8 @@ static tm_status contract_all_momenta(tm_ctx* ctx, uint64_t seed, int32_t nsrc, 
     const Geom& g = ctx->geo;
     hipStream_t st = ctx->stream;
     tm_status s = TM_OK;
+    if (g.L[0] > 128 || g.L[1] > 128 || g.L[2] > 128)
+        return set_error(ctx, TM_ENOTSUP, "tsm_contract: all momenta need spatial extents <= 128");
     const int blk = std::min(nsrc, 4);
     const long V3 = (long)g.L[0] * g.L[1] * g.L[2];
     const long nl = 16L * V3 * g.L[3];
