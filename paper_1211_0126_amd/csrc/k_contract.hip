@@ -418,7 +418,9 @@ __global__ __launch_bounds__(256) void k_site_matrix(ContractArgs a, double2* ou
 // length L <= kDftMaxL whose elements are `stride` double2 apart (stride a
 // multiple of 16).  A block takes one line group of 16 consecutive inner
 // elements: it stages the L x 16 tile and the phases in LDS (each element
-// read once from memory), then each lane forms outputs (k, c) from LDS.
+// read once from memory); power-of-two lengths are transformed in place by
+// radix-2 passes, other lengths by direct sums, each lane forming outputs
+// (k, c) from LDS.
 constexpr int kDftMaxL = 128;  // 34 KB of LDS at the largest L
 __global__ __launch_bounds__(256) void k_dft_axis(const double2* in, double2* out, int L, long stride,
                                                   const double2* tw) {
@@ -429,9 +431,36 @@ __global__ __launch_bounds__(256) void k_dft_axis(const double2* in, double2* ou
     const long outer = (long)blockIdx.x / nchunk;
     const long base = outer * L * stride + ((long)blockIdx.x % nchunk) * 16;
     const int n = L * 16;
-    for (int idx = threadIdx.x; idx < n; idx += 256) tile[idx] = in[base + (long)(idx >> 4) * stride + (idx & 15)];
+    const bool pow2 = (L & (L - 1)) == 0;
+    int lg = 0;
+    while ((1 << lg) < L) lg++;
+    for (int idx = threadIdx.x; idx < n; idx += 256) {
+        const int jj = idx >> 4;
+        // power-of-two lengths: stored in bit-reversed order for the radix-2 passes
+        const int at = pow2 ? (int)(__brev((unsigned)jj) >> (32 - lg)) : jj;
+        tile[(lg == 0 ? jj : at) * 16 + (idx & 15)] = in[base + (long)jj * stride + (idx & 15)];
+    }
     for (int idx = threadIdx.x; idx < L; idx += 256) ph[idx] = tw[idx];
     __syncthreads();
+    if (pow2) {
+        // iterative radix-2 decimation in time: log2 L passes of L/2 x 16
+        // butterflies, twiddle exp(-2 pi i pos / len) = ph[pos * L / len]
+        for (int len = 2; len <= L; len <<= 1) {
+            const int half = len >> 1, step = L / len;
+            for (int b = threadIdx.x; b < (L >> 1) * 16; b += 256) {
+                const int c = b & 15, qb = b >> 4;
+                const int i0 = (qb / half) * len + qb % half, i1 = i0 + half;
+                const double2 w = ph[(qb % half) * step];
+                const double2 u = tile[i0 * 16 + c], v = tile[i1 * 16 + c];
+                const cx<double> wv = cx<double>{w.x, w.y} * cx<double>{v.x, v.y};
+                tile[i0 * 16 + c] = make_double2(u.x + wv.re, u.y + wv.im);
+                tile[i1 * 16 + c] = make_double2(u.x - wv.re, u.y - wv.im);
+            }
+            __syncthreads();
+        }
+        for (int o = threadIdx.x; o < n; o += 256) out[base + (long)(o >> 4) * stride + (o & 15)] = tile[o];
+        return;
+    }
     for (int o = threadIdx.x; o < n; o += 256) {
         const int k = o >> 4, c = o & 15;
         cx<double> acc = {0.0, 0.0};
@@ -447,28 +476,32 @@ __global__ __launch_bounds__(256) void k_dft_axis(const double2* in, double2* ou
     }
 }
 
-// loops[r][n][m][t] = sum_a Gamma_n[a][col] S~_{col a}(t, m), m = kx + Lx (ky + Ly kz)
+// loops[r][n][m][t] = sum_a Gamma_n[a][col] S~_{col a}(t, m), m = kx + Lx (ky + Ly kz):
+// one lane per (m, t) with t fastest reads its 16 spectrum entries (one
+// contiguous 256-byte block) and writes all 16 Gamma traces, so each write
+// instruction of a wave covers consecutive t
 __global__ __launch_bounds__(256) void k_trace_all(ContractArgs a, const double2* spec, double2* out) {
     const Geom& g = a.geo;
     const long V3 = (long)g.L[0] * g.L[1] * g.L[2];
     const int Lt = g.L[3];
-    const long n_el = 16L * V3 * Lt;
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     const int r = blockIdx.y;
-    if (i >= n_el) return;
+    if (i >= V3 * Lt) return;
     const int t = (int)(i % Lt);
-    const long q = i / Lt;
-    const long m = q % V3;
-    const int gn = (int)(q / V3);
+    const long m = i / Lt;
     const double2* e = spec + (((size_t)r * Lt + t) * V3 + m) * 16;
-    cx<double> tr = {0.0, 0.0};
+    double2* o = out + (size_t)a.out_slot[r] * a.out_stride + m * Lt + t;
 #pragma unroll
-    for (int al = 0; al < 4; al++) {
-        const int be = a.gam_col[gn * 4 + al];
-        const double2 v = e[be * 4 + al];
-        tr = tr + z4_value<double>((uint32_t)a.gam_ph[gn * 4 + al]) * cx<double>{v.x, v.y};
+    for (int gn = 0; gn < 16; gn++) {
+        cx<double> tr = {0.0, 0.0};
+#pragma unroll
+        for (int al = 0; al < 4; al++) {
+            // the lane's 256-byte block stays in the caches across the 16 traces
+            const double2 v = e[a.gam_col[gn * 4 + al] * 4 + al];
+            tr = tr + z4_value<double>((uint32_t)a.gam_ph[gn * 4 + al]) * cx<double>{v.x, v.y};
+        }
+        o[(size_t)gn * V3 * Lt] = make_double2(tr.re, tr.im);
     }
-    out[(size_t)a.out_slot[r] * a.out_stride + i] = make_double2(tr.re, tr.im);
 }
 
 void launch_contract_all_momenta(hipStream_t st, const ContractArgs& a, int xprec, double2* buf0, double2* buf1,
@@ -490,7 +523,7 @@ void launch_contract_all_momenta(hipStream_t st, const ContractArgs& a, int xpre
                        tw + Lx);
     hipLaunchKernelGGL(k_dft_axis, blocks(Lz), dim3(256), lds(Lz), st, (const double2*)buf0, buf1, Lz,
                        16L * Lx * Ly, tw + Lx + Ly);
-    const long n_el = 16L * Lx * Ly * Lz * g.L[3];
+    const long n_el = (long)Lx * Ly * Lz * g.L[3];
     hipLaunchKernelGGL(k_trace_all, dim3((unsigned)((n_el + 255) / 256), (unsigned)a.nrhs), dim3(256), 0, st, a,
                        (const double2*)buf1, a.out);
 }
