@@ -6,9 +6,11 @@ momenta per timeslice, the Eq. 4 combination) over one synthetic gauge
 field, by default the 32^3x64 workload (N_HP = 32, N_LP = 2048).
 
 value = N_LP / (wall time of the whole step): LP TSM sources per second,
-HP correction included.  Per-kernel durations come from HIP events recorded
-on the library's stream around every launch during the timed steps; the
-roofline entry is the kernel class with the largest total time.
+HP correction included.  The timed steps run the CG iterations as replays of
+captured HIP graphs (no per-launch instrumentation).  One further step, not
+timed for `value`, records HIP events on the library's stream around every
+launch; the roofline entry is the kernel variant with the largest total time
+in that step.
 
 After the timed steps (not part of them): plain FP32 single-RHS CG on the
 same GPU, and the LP configuration of the step (and, with --learned, flexible
@@ -69,6 +71,10 @@ def parse():
     ap.add_argument("--lp-config", default=None, metavar="NR,TSEG",
                     help="fix the LP kernels' right-hand sides per lane and time slices per lane (default: autotune)")
     ap.add_argument("--hp-config", default=None, metavar="NR,TSEG", help="same for the HP kernels")
+    ap.add_argument("--error-lp", type=int, default=128,
+                    help="LP sources of the per-loop error report against an FP64 run of the same sources "
+                         "(-1: the workload's N_LP; 0: skip)")
+    ap.add_argument("--error-hp", type=int, default=8, help="HP sources of the error report (-1: the workload's)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory once (calibrates the HBM byte counters) and exit")
     return ap.parse_args()
@@ -219,8 +225,10 @@ def main():
     # LP configuration in the equal-residual comparison after the timed steps.
     lp = tq.solve_params(prec=lp_prec, tol=wl.lp_tol, max_iter=wl.lp_maxit, rhs_block=args.lp_block,
                          true_resid=int(args.lp_true_resid))
+    # HP: FP32 iterations with FP64 reliable updates, stopped on the FP64
+    # true residual |eta - M s| / |eta| (taken at the reliable updates)
     hp = tq.solve_params(prec=tq.PREC_F32, tol=wl.hp_tol, max_iter=-1, reliable=1, delta=0.1,
-                         rhs_block=args.hp_block, true_resid=1)
+                         rhs_block=args.hp_block, true_resid=1, stop=tq.STOP_TRUE)
 
     def step():
         return tq.tsm_loops(ctx, wl.noise_seed, n_hp, n_lp, lp, hp, mom, stats=True)
@@ -231,7 +239,10 @@ def main():
         log("warmup step %d: %.1f ms (LP iters %d, HP iters %d)" % (w, 1e3 * (time.time() - t0),
                                                                       r["run"]["lp_iters"], r["run"]["hp_iters"]))
 
-    tq.tm_profile_enable(ctx, True)
+    # timed steps: graph replays of the CG chunks, no per-launch events
+    tq.tm_profile_enable(ctx, False)
+    tq.tm_set_graphs(ctx, True)
+    replays0 = tq.tm_set_graphs(ctx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = None
@@ -240,11 +251,21 @@ def main():
         log("timed step %d done" % k)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    graph_replays = tq.tm_set_graphs(ctx) - replays0
+    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    value = n_lp / (ms_per_step / 1e3)
+    log("timed: %.1f ms per step, %d graph replays" % (ms_per_step, graph_replays))
+
+    # one instrumented step (eager launches with HIP events around each) for
+    # the per-kernel figures and the roofline
+    tq.tm_profile_enable(ctx, True)
+    t2 = time.perf_counter()
+    step()
+    torch.cuda.synchronize()
+    ms_profiled_step = 1e3 * (time.perf_counter() - t2)
     prof = tq.tm_profile_read(ctx)
     variants = tq.tm_profile_entries(ctx)
     tq.tm_profile_enable(ctx, False)
-    ms_per_step = 1e3 * (t1 - t0) / args.steps
-    value = n_lp / (ms_per_step / 1e3)
 
     # dominant kernel: the variant (class, storage, RHS per lane, solver) with
     # the largest total time; it is one compiled kernel in the rocprofv3 trace
@@ -293,6 +314,8 @@ def main():
             "hp_rhs_block": args.hp_block,
         },
         "autotune": tune,
+        "graph_replays_timed": graph_replays,
+        "ms_profiled_step": round(ms_profiled_step, 1),
         "lp_phase_sources_per_s": round(n_lp / (run["ms_lp_phase"] / 1e3), 2),
         "hp_phase_ms": round(run["ms_hp_phase"], 1),
         "lp_iters_mean": round(float(np.mean(lp_iters)), 2),
@@ -308,6 +331,8 @@ def main():
         "roofline": roofline,
     }
 
+    if args.error_lp != 0:
+        out["loop_error_vs_fp64"] = loop_errors(args, tq, ctx, wl, lp, hp, mom)
     if not args.no_compare:
         out["equal_residual"] = compare(args, tq, torch, ctx, wl, n_hp, lp_prec)
     if not args.no_estimators:
@@ -339,6 +364,37 @@ def copy_bandwidth(torch, nbytes=4 << 30, reps=5):
         best = ms if best is None else min(best, ms)
     del a, b
     return 2.0 * 4 * n / (best * 1e-3) / 1e9
+
+
+def loop_errors(args, tq, ctx, wl, lp, hp, mom):
+    """The error of each loop of the benchmark's estimate: the TSM step on a
+    sample of the same sources once with the benchmark's LP solver and once
+    with FP64 LP solves (the FP64 GPU path equals the FP64 oracle to 1e-12),
+    the HP solves as in the step.  For every (part, Gamma, p, t) the
+    deviation |L - L_FP64| in units of the FP64 estimate's standard error,
+    real and imaginary parts separately."""
+    n_lp = wl.n_lp if args.error_lp < 0 else min(args.error_lp, wl.n_lp)
+    n_hp = wl.n_hp if args.error_hp < 0 else min(args.error_hp, wl.n_hp)
+    lp64 = tq.solve_params(prec=tq.PREC_F64, tol=lp.tol, max_iter=lp.max_iter, rhs_block=8, true_resid=0)
+    log("loop error report: N_HP %d, N_LP %d" % (n_hp, n_lp))
+    a = tq.tsm_loops(ctx, wl.noise_seed, n_hp, n_lp, lp, hp, mom, per_source=True, stats=True)
+    b = tq.tsm_loops(ctx, wl.noise_seed, n_hp, n_lp, lp64, hp, mom, per_source=True, stats=True)
+    out = {"sample": "N_HP %d, N_LP %d of the step's sources" % (n_hp, n_lp),
+           "reference": "the same TSM step with FP64 LP solves (FP64 arithmetic and storage)"}
+    for part, name in ((0, "C"), (1, "B"), (2, "T")):
+        d, e = a["loops"][part] - b["loops"][part], b["err"][part]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            z = np.concatenate([np.abs(d.real / e.real).ravel(), np.abs(d.imag / e.imag).ravel()])
+        z = z[np.isfinite(z)]
+        out[name] = {"max_dev_over_sigma": float(z.max()), "median_dev_over_sigma": float(np.median(z)),
+                     "max_abs_dev": float(np.abs(d).max()), "max_abs_loop": float(np.abs(b["loops"][part]).max())}
+    ps_a, ps_b = a["per_source"][:, 0], b["per_source"][:, 0]
+    rel = np.abs(ps_a - ps_b).max(axis=(1, 2, 3)) / np.abs(ps_b).max(axis=(1, 2, 3))
+    out["per_source_lp_rel_dev"] = {"max": float(rel.max()), "median": float(np.median(rel))}
+    out["lp_iters_mean"] = float(np.mean([s[0]["iters"] for s in a["stats"]]))
+    out["lp64_iters_mean"] = float(np.mean([s[0]["iters"] for s in b["stats"]]))
+    log("loop errors: %s" % out)
+    return out
 
 
 def estimators(args, tq, torch, ctx, wl, lp, hp, mom):

@@ -94,7 +94,9 @@ typedef enum {
 
 typedef enum {
     TM_STOP_NORMAL = 0, /* |M^dag eta - M^dag M s| / |M^dag eta| <= tol (CG's own residual) */
-    TM_STOP_TRUE = 1    /* recursively tracked |eta - M s| / |eta| <= tol */
+    TM_STOP_TRUE = 1    /* |eta - M s| / |eta| <= tol: tracked recursively, or with reliable
+                           updates the FP64 value taken at each update (an update is also made
+                           at every iteration whose normal-equation residual is below tol) */
 } tm_stop;
 
 typedef enum {

@@ -79,7 +79,7 @@ __device__ inline void cg_finish_step(CgScal& q, double rrn, double rhon) {
         q.rflag = 0;
         return;
     }
-    if (q.stop == 1) q.rho2 = rhon;
+    if (q.stop == 1 && !q.reliable) q.rho2 = rhon;
     if (q.reliable) {
         if (rrn > q.maxrr) q.maxrr = rrn;
         if (rrn <= q.tol2 * q.bb || rrn < q.delta2 * q.maxrr) {
@@ -391,7 +391,8 @@ __global__ __launch_bounds__(256) void k_rel_flush(CgArgs a, void* x64, int forc
 }
 
 // r64 = b64 - M^dag t64 (t64 = M x64), r32 = r64, block partials of |r64|^2
-// (grid: kGatedBlocks x nrhs, striding over site blocks)
+// and, when the solve stops on the true residual (a.eta64 set), of
+// |eta - t64|^2 (grid: kGatedBlocks x nrhs, striding over site blocks)
 __global__ TM_STENCIL_R(1, double) void k_rel_resid(CgArgs a, const void* gauge64, const void* b64, const void* t64) {
     __shared__ double sh[4];
     const int r = blockIdx.y;
@@ -399,7 +400,7 @@ __global__ TM_STENCIL_R(1, double) void k_rel_resid(CgArgs a, const void* gauge6
     const long Vs = a.geo.Vs;
     const uint32_t nsb = (uint32_t)((a.geo.V + 255) / 256);
     const void* t0 = field_rhs<SF64>(t64, Vs, r);
-    double pr = 0;
+    double pr = 0, pt = 0;
     for (uint32_t sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
         const uint32_t s = sb * 256u + threadIdx.x;
         if (s >= a.geo.V) continue;
@@ -418,18 +419,31 @@ __global__ TM_STENCIL_R(1, double) void k_rel_resid(CgArgs a, const void* gauge6
         }
         store_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r), Vs, s, rf);
         pr += spinor_norm2(bv);
+        if (a.eta64) {
+            cx<double> ev[12];
+            load_spinor<SF64, double>(field_rhs<SF64>(a.eta64, Vs, r), Vs, s, ev);
+#pragma unroll
+            for (int k = 0; k < 12; k++) ev[k] = ev[k] - tc[k];
+            pt += spinor_norm2(ev);
+        }
     }
     double v = block_sum256(pr, sh);
     if (threadIdx.x == 0) a.partials[(size_t)r * gridDim.x + blockIdx.x] = v;
+    if (a.eta64) {
+        double w = block_sum256(pt, sh);
+        if (threadIdx.x == 0) a.partials2[(size_t)r * gridDim.x + blockIdx.x] = w;
+    }
 }
 
 // one block per right-hand side with the reliable flag set: restart the
-// recursion from the recomputed residual, stop test on it
+// recursion from the recomputed residual, stop test on it (or on the FP64
+// true residual |eta - M x| when the solve stops on that)
 __global__ __launch_bounds__(256) void k_rel_fin(CgArgs a, uint32_t nb) {
     __shared__ double sh[4];
     const int r = blockIdx.x;
     if (!a.scal[r].rflag) return;
     const double rrn = sum_block_partials(a.partials + (size_t)r * nb, nb, sh);
+    const double rho2 = a.eta64 ? sum_block_partials(a.partials2 + (size_t)r * nb, nb, sh) : 0.0;
     if (threadIdx.x == 0) {
         CgScal& q = a.scal[r];
         q.beta = rrn / q.rr;
@@ -437,7 +451,8 @@ __global__ __launch_bounds__(256) void k_rel_fin(CgArgs a, uint32_t nb) {
         q.maxrr = rrn;
         q.rflag = 0;
         q.n_reliable += 1;
-        if (rrn <= q.tol2 * q.bb) {
+        if (q.stop == 1) q.rho2 = rho2;
+        if (q.stop == 1 ? rho2 <= q.tol2 * q.ee : rrn <= q.tol2 * q.bb) {
             q.status = 1;
             q.active = 0;
         } else if (q.maxit >= 0 && q.iters >= q.maxit) {

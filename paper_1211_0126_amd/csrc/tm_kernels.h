@@ -18,6 +18,7 @@ struct CgArgs {
     void* r;
     void* x;
     void* rho;          // recursive true residual (stop on |eta - M x|)
+    const void* eta64;  // reliable updates stopping on |eta - M x|: the FP64 sources
     CgScal* scal;
     double* partials;   // [nrhs][nblocks]
     double* partials2;  // [nrhs][nblocks]

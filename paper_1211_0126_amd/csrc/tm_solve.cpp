@@ -40,8 +40,6 @@ static tm_status check_solve_params(tm_ctx* ctx, const tsm_solve_params* p) {
     if (p->reliable) {
         if (p->prec != TM_PREC_F32)
             return set_error(ctx, TM_ENOTSUP, "solve: reliable updates need FP32 iterations");
-        if (p->stop != TM_STOP_NORMAL)
-            return set_error(ctx, TM_ENOTSUP, "solve: reliable updates stop on the normal-equation residual");
         if (!(p->delta > 0 && p->delta < 1)) return set_error(ctx, TM_EINVAL, "solve: delta must be in (0, 1)");
     }
     if (p->rhs_block < 0 || p->rhs_block > kMaxBlock) return set_error(ctx, TM_EINVAL, "solve: rhs_block in 0..32");
@@ -57,7 +55,7 @@ static int default_block(const tsm_solve_params* p) {
 // right-hand sides per lane in the stencil kernels: the tuned choice when it
 // divides the block, else the largest of 4, 2, 1 that does
 static int lane_rhs(const tm_ctx* ctx, const tsm_solve_params* p, int block) {
-    if (p->prec == TM_PREC_F64 || p->stop == TM_STOP_TRUE) return 1;
+    if (p->prec == TM_PREC_F64 || (p->stop == TM_STOP_TRUE && !p->reliable)) return 1;
     const int t = ctx->lane_rhs[p->prec];
     if (t > 0 && block % t == 0) return t;
     if (block % 4 == 0) return 4;
@@ -296,7 +294,9 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
     tm_status s = TM_OK;
     const int prec = p->prec;
     const bool rel = p->reliable != 0;
-    const bool track = p->stop == TM_STOP_TRUE;
+    // the recursively tracked true residual; with reliable updates the FP64
+    // true residual is taken at each update instead
+    const bool track = p->stop == TM_STOP_TRUE && !rel;
     const size_t nblk = (size_t)((g.V + 255) / 256);
     const size_t fb = field_bytes(g, prec, nrhs);
     const size_t fx = field_bytes(g, prec == P_F64 ? P_F64 : P_F32, nrhs);
@@ -325,6 +325,7 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
     void *b64 = nullptr, *x64 = nullptr, *t64 = nullptr;
     if (rel) {
         eta = ws_get(ctx, tag + "_eta64", f64, &s);
+        if (p->stop == TM_STOP_TRUE) a.eta64 = eta;
         b64 = ws_get(ctx, tag + "_b64", f64, &s);
         x64 = ws_get(ctx, tag + "_x64", f64, &s);
         t64 = ws_get(ctx, tag + "_t64", f64, &s);

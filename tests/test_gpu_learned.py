@@ -102,8 +102,10 @@ def test_loss_gradient_matches_oracle(orc, U):
     e = random_spinor(DIMS, 6, 3)
     loss, grad = tq.tm_precond_loss_grad(ctx, torch.from_numpy(r).cuda(), torch.from_numpy(e).cuda())
     loss_o, grad_o = orc.pt_loss_grad(DIMS, -1, U, WIDTHS, W, r, e)
-    assert abs(loss - loss_o) < 2e-2 * loss_o
-    assert _rel(grad, grad_o) < 2e-2, _rel(grad, grad_o)
+    # bfloat16 network: the gradient to 1e-2 relative
+    print("loss rel. deviation %.3g, gradient rel. deviation %.3g" % (abs(loss - loss_o) / loss_o, _rel(grad, grad_o)))
+    assert abs(loss - loss_o) < 1e-2 * loss_o
+    assert _rel(grad, grad_o) < 1e-2, _rel(grad, grad_o)
     ctx.close()
 
 
@@ -141,6 +143,30 @@ def test_fcg_with_network_matches_oracle(orc, U):
         assert abs(st[i]["iters"] - so["iters"]) <= 0.3 * so["iters"], (st[i]["iters"], so["iters"])
         assert _rel(sol[i], x) < 1e-4
         assert st[i]["resid_true"] < 1e-4
+    ctx.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_fcg_fixed_iterations_match_oracle(orc, U, k):
+    """Flexible CG stopped after k iterations (tol 0) against the oracle's
+    k-th iterate, so the step length, the direction update and the order of
+    N and N^dag in the preconditioner are compared step by step (the oracle
+    iterates are pinned as the Krylov-optimal points of preconditioned CG).
+    The network runs in bfloat16, so 2e-2."""
+    import paper_1211_0126_amd as tq
+    ctx = _ctx(DIMS, U)
+    W = _net(orc, 5, scale=0.08)
+    tq.tm_precond_set(ctx, WIDTHS, W)
+    p = tq.solve_params(prec=tq.PREC_F32, tol=0.0, max_iter=k, solver=tq.SOLVER_FCG_LEARNED, rhs_block=2)
+    sol, st, rc = tq.tsm_solve_batch(ctx, p, 8, [0, 1])
+    sol = sol.cpu().numpy()
+    for i in range(2):
+        eta = orc.noise_z4(DIMS, 8, i)
+        x, so = orc.fcg(DIMS, -1, KAPPA, MU, U, WIDTHS, W, eta, 0.0, k)
+        assert st[i]["iters"] == k == so["iters"] and st[i]["truncated"]
+        assert not st[i]["fell_back"] and not so["fell_back"]
+        print("k %d source %d: iterate rel. deviation %.3g" % (k, i, _rel(sol[i], x)))
+        assert _rel(sol[i], x) < 2e-2, _rel(sol[i], x)
     ctx.close()
 
 

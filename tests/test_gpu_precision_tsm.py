@@ -1,0 +1,61 @@
+"""The TSM estimate (Eq. 4) with reduced-precision LP solves (FP16 and BF16
+storage, FP32 arithmetic) and FP32 HP solves with FP64 reliable updates,
+against the FP64 oracle's estimate from the same sources.
+
+Both sides use the same Z4 sources, so the difference of the totals is only
+what the LP map changes (the HP solves agree to their tolerance); it must be
+far inside the statistical error of the estimate, and every per-source LP
+loop is compared with the oracle's FP64 LP loop of the same source."""
+
+import numpy as np
+import pytest
+
+from lattice_inputs import make_gauge
+from lattice_inputs.workloads import momenta_zero
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (8, 8, 8, 8)
+KAPPA, MU = 0.1632, 0.004
+N_HP, N_LP = 8, 256
+SEED = 2007
+
+
+@pytest.fixture(scope="module")
+def oracle_tsm(orc):
+    U = make_gauge(DIMS, 0.25, 1009)
+    mom = momenta_zero()
+    print("oracle TSM 8^4, N_HP %d, N_LP %d" % (N_HP, N_LP), flush=True)
+    ref = orc.tsm(DIMS, -1, KAPPA, MU, U, SEED, N_HP, N_LP, 1e-2, -1, 1e-10, -1, mom, per_source=True)
+    return U, mom, ref
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+def test_reduced_precision_tsm_against_fp64_oracle(oracle_tsm, prec):
+    import paper_1211_0126_amd as tq
+    U, mom, ref = oracle_tsm
+    ctx = tq.tm_create(DIMS, KAPPA, MU, -1)
+    tq.tm_gauge_load(ctx, U)
+    lp = tq.solve_params(prec=prec, tol=1e-2, max_iter=-1, rhs_block=16, true_resid=0)
+    hp = tq.solve_params(prec=tq.PREC_F32, tol=1e-10, max_iter=-1, reliable=1, delta=0.1, rhs_block=8)
+    res = tq.tsm_loops(ctx, SEED, N_HP, N_LP, lp, hp, mom, per_source=True)
+    ctx.close()
+    T, T_ref = res["loops"][2], ref["loops"][2]
+    sig = ref["err"][2]
+    # deviation of the total in units of the combined standard error, real
+    # and imaginary parts separately, over every (Gamma, p, t)
+    dr = np.abs(T.real - T_ref.real) / sig.real
+    di = np.abs(T.imag - T_ref.imag) / sig.imag
+    dev = np.concatenate([dr.ravel(), di.ravel()])
+    print("storage %d: |dT|/sigma max %.3g median %.3g" % (prec, dev.max(), np.median(dev)))
+    assert dev.max() < 3.0
+    # per-source LP loops: the reduced-precision truncated solve against the
+    # FP64 one of the same source (both stop at the LP tolerance)
+    lp_gpu, lp_ref = res["per_source"][:, 0], ref["per_source"][:, 0]
+    scale = np.max(np.abs(lp_ref), axis=(1, 2, 3))
+    per = np.max(np.abs(lp_gpu - lp_ref), axis=(1, 2, 3)) / scale
+    print("storage %d: per-source LP loop deviation max %.3g median %.3g" % (prec, per.max(), np.median(per)))
+    assert per.max() < 0.1
+    # the HP loops match the oracle's to the HP tolerance
+    hp_dev = np.max(np.abs(res["per_source"][:N_HP, 1] - ref["per_source"][:N_HP, 1]))
+    assert hp_dev < 1e-6 * np.max(np.abs(ref["per_source"][:N_HP, 1]))

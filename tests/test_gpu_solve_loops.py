@@ -121,6 +121,34 @@ def test_fp32_reliable_hp_solve(orc):
     ctx.close()
 
 
+def test_fp32_reliable_hp_true_residual_stop(orc):
+    """FP32 iterations with FP64 reliable updates stopping on the FP64 true
+    residual |eta - M x| / |eta| <= 1e-10 (taken at the updates): the
+    reported and the independently recomputed true residuals meet the
+    target, and the iteration count is the FP64 oracle's with the same stop
+    to within a few iterations."""
+    import paper_1211_0126_amd as tq
+    dims = (8, 8, 8, 8)
+    U = make_gauge(dims, 0.25, 1002)
+    ctx = _ctx(dims, 0.1632, 0.004, U)
+    ids = [0, 1, 2, 3]
+    p = tq.solve_params(prec=tq.PREC_F32, tol=1e-10, max_iter=-1, reliable=1, delta=0.1, rhs_block=4,
+                        stop=tq.STOP_TRUE)
+    sol, st, rc = tq.tsm_solve_batch(ctx, p, 9, ids)
+    sol = sol.cpu().numpy()
+    for i, j in enumerate(ids):
+        eta = orc.noise_z4(dims, 9, j)
+        x, so = orc.cgnr(dims, -1, 0.1632, 0.004, U, eta, 1e-10, -1, orc.STOP_TRUE)
+        mx = orc.apply_op(dims, -1, 0.1632, 0.004, orc.OP_M, U, sol[i])
+        true = np.linalg.norm((eta - mx).ravel()) / np.linalg.norm(eta.ravel())
+        print("source %d: iters %d (oracle %d), true residual %.3g (reported %.3g)"
+              % (j, st[i]["iters"], so["iters"], true, st[i]["resid_true"]))
+        assert st[i]["converged"], st[i]
+        assert st[i]["resid_iterated"] <= 1e-10 and st[i]["resid_true"] <= 1e-10 and true <= 1.01e-10
+        assert abs(st[i]["iters"] - so["iters"]) <= 3
+    ctx.close()
+
+
 def test_batching_does_not_change_a_source(c0):
     """Per-source arithmetic is independent of the other sources of a block:
     the same source solved in different blocks is bitwise identical."""

@@ -167,3 +167,65 @@ def test_fcg_zero_net_falls_back(orc):
     assert st["fell_back"] and st["converged"]
     assert st["iters"] == st2["iters"]
     assert np.linalg.norm(x - x2) / np.linalg.norm(x2) < 1e-12
+
+
+def _dense_precond(orc, dims, U, W, adjoint_first=True):
+    """P = N N^dag (adjoint_first) or N^dag N as a dense matrix, column by
+    column from the oracle's network."""
+    v = int(np.prod(dims))
+    n = 12 * v
+    P = np.zeros((n, n), dtype=np.complex128)
+    e = np.zeros((1, v, 4, 3), dtype=np.complex128)
+    flat = e.reshape(-1)
+    for i in range(n):
+        flat[:] = 0
+        flat[i] = 1.0
+        a = orc.pt_net(dims, -1, U, WIDTHS, W, e, adjoint=adjoint_first)
+        P[:, i] = orc.pt_net(dims, -1, U, WIDTHS, W, a, adjoint=not adjoint_first).reshape(-1)
+    return P
+
+
+def _pcg_optimal_iterate(A, P, b, k):
+    """The A-norm-optimal approximation to A^{-1} b over the Krylov space
+    K_k(PA, Pb) (what preconditioned CG from x = 0 reaches after k steps),
+    from an orthonormal basis of that space and a dense solve."""
+    cols = [P @ b]
+    for _ in range(k - 1):
+        cols.append(P @ (A @ cols[-1]))
+    Q, _ = np.linalg.qr(np.stack(cols, axis=1))
+    y = np.linalg.solve(Q.conj().T @ A @ Q, Q.conj().T @ b)
+    return Q @ y
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 2, 2, 4)])
+def test_fcg_iterates_are_pcg_krylov_optimal(orc, dims):
+    """For a fixed network N, flexible CG's preconditioner z = N N^dag r is a
+    fixed Hermitian positive definite P, and its k-th iterate is the
+    A-norm-optimal point of K_k(PA, Pb) with A = M^dag M, b = M^dag eta
+    (the defining property of preconditioned CG).  The reference comes from
+    dense matrices of M and of N N^dag and an orthonormal Krylov basis, so a
+    wrong step length (<r, r> for <z, r>), a wrong ordering (N^dag N) or a
+    dropped preconditioner fails it."""
+    U = make_gauge(dims, 0.3, 61)
+    kappa, mu = 0.16, 0.03125
+    W = identity_net(orc) + random_net(orc, 12, scale=0.08)
+    M = dense_op(dims, -1, kappa, mu, U, orc.OP_M)
+    A = M.conj().T @ M
+    eta = orc.noise_z4(dims, 31, 0)
+    b = M.conj().T @ eta.reshape(-1)
+    P = _dense_precond(orc, dims, U, W, adjoint_first=True)
+    assert np.max(np.abs(P - P.conj().T)) < 1e-12 * np.max(np.abs(P))
+    assert np.min(np.linalg.eigvalsh(P)) > 0
+    # the alternatives a mistake would produce are far from the right answer
+    # for this network, so the pin can tell them apart
+    P_wrong = _dense_precond(orc, dims, U, W, adjoint_first=False)
+    x1 = _pcg_optimal_iterate(A, P, b, 1)
+    assert np.linalg.norm(_pcg_optimal_iterate(A, P_wrong, b, 1) - x1) > 1e-3 * np.linalg.norm(x1)
+    z0 = P @ b
+    assert abs(np.vdot(z0, b) - np.vdot(b, b)) > 1e-3 * abs(np.vdot(b, b))
+    for k in range(1, 7):
+        x, st = orc.fcg(dims, -1, kappa, mu, U, WIDTHS, W, eta, 0.0, k)
+        assert st["iters"] == k and not st["fell_back"]
+        ref = _pcg_optimal_iterate(A, P, b, k)
+        dev = np.linalg.norm(x.reshape(-1) - ref) / np.linalg.norm(ref)
+        assert dev < 1e-9, (k, dev)
