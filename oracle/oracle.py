@@ -61,7 +61,13 @@ def load_oracle():
     lib.orc_loops_deriv.argtypes = [P, i32, P, P, P, i32, P, P]
     lib.orc_loops_est.argtypes = [P, i32, f64, f64, P, i32, P, P, i32, P, P]
     lib.orc_tsm.argtypes = [P, i32, f64, f64, P, u64, i32, i32, f64, i32, i32, f64, i32, i32,
-                            i32, P, i32, P, P, P, P]
+                            i32, P, i32, P, P, P, P, i32, i32]
+    lib.orc_eo_apply.argtypes = [P, i32, f64, f64, i32, P, P, P]
+    lib.orc_eo_apply.restype = i32
+    lib.orc_eo_source.argtypes = [P, i32, f64, f64, P, P, P]
+    lib.orc_eo_reconstruct.argtypes = [P, i32, f64, f64, P, P, P]
+    lib.orc_cgnr_eo.argtypes = [P, i32, f64, f64, P, P, f64, i32, i32, P, P]
+    lib.orc_cgnr_eo.restype = i32
     lib.orc_tsm.restype = i32
     lib.orc_pt_layer.argtypes = [P, i32, P, i32, i32, P, P, P]
     lib.orc_pt_layer_adj.argtypes = [P, i32, P, i32, i32, P, P, P]
@@ -157,6 +163,56 @@ def cgnr(dims, t_bc, kappa, mu, U, eta, tol, maxit=-1, stop=STOP_NORMAL):
                "converged": bool(st[3]), "truncated": bool(st[4])}
 
 
+def eo_apply(dims, t_bc, kappa, mu, op, U, psi) -> np.ndarray:
+    """The even-odd Schur complement Mhat = M_oo - M_oe M_ee^{-1} M_eo (op 0),
+    its adjoint (op 1) or Mhat^dag Mhat (op 2) on a full-size field whose odd
+    sites are used; the result is zero on the even sites.  Every extent must
+    be even."""
+    d = _dims(dims)
+    psi = _c128(psi)
+    out = np.zeros_like(psi)
+    rc = load_oracle().orc_eo_apply(_ptr(d), int(t_bc), float(kappa), float(mu), int(op), _ptr(_c128(U)),
+                                    _ptr(psi), _ptr(out))
+    if rc != 0:
+        raise ValueError("even-odd reduction needs even extents")
+    return out
+
+
+def eo_source(dims, t_bc, kappa, mu, U, eta) -> np.ndarray:
+    """etahat_o = eta_o - M_oe M_ee^{-1} eta_e (zero on the even sites)."""
+    d = _dims(dims)
+    eta = _c128(eta)
+    out = np.zeros_like(eta)
+    load_oracle().orc_eo_source(_ptr(d), int(t_bc), float(kappa), float(mu), _ptr(_c128(U)), _ptr(eta), _ptr(out))
+    return out
+
+
+def eo_reconstruct(dims, t_bc, kappa, mu, U, eta, x_odd) -> np.ndarray:
+    """The whole solution from its odd half: x_e = M_ee^{-1}(eta_e - M_eo x_o)."""
+    d = _dims(dims)
+    x = np.array(_c128(x_odd), copy=True)
+    load_oracle().orc_eo_reconstruct(_ptr(d), int(t_bc), float(kappa), float(mu), _ptr(_c128(U)),
+                                     _ptr(_c128(eta)), _ptr(x))
+    return x
+
+
+def cgnr_eo(dims, t_bc, kappa, mu, U, eta, tol, maxit=-1, stop=STOP_NORMAL):
+    """CG on the normal equations of the even-odd Schur complement, then the
+    even half reconstructed.  Returns (solution, stats dict); resid_normal is
+    that of the Schur normal equations."""
+    d = _dims(dims)
+    U = _c128(U)
+    eta = _c128(eta)
+    x = np.zeros_like(eta)
+    st = np.zeros(5, dtype=np.float64)
+    rc = load_oracle().orc_cgnr_eo(_ptr(d), int(t_bc), float(kappa), float(mu), _ptr(U), _ptr(eta), float(tol),
+                                   int(maxit), int(stop), _ptr(x), _ptr(st))
+    if rc < 0:
+        raise ValueError("even-odd reduction needs even extents")
+    return x, {"iters": int(st[0]), "resid_normal": st[1], "resid_true": st[2],
+               "converged": bool(st[3]), "truncated": bool(st[4])}
+
+
 def loops(dims, eta, s, mom) -> np.ndarray:
     """complex128 [16][n_mom][Lt]."""
     d = _dims(dims)
@@ -196,9 +252,10 @@ def loops_est(dims, t_bc, kappa, mu, U, est, s, mom, eta=None) -> np.ndarray:
 
 
 def tsm(dims, t_bc, kappa, mu, U, seed, n_hp, n_lp, lp_tol, lp_maxit, hp_tol, hp_maxit, mom,
-        lp_stop=STOP_NORMAL, hp_stop=STOP_NORMAL, per_source=False, estimator=LOOP_STD):
+        lp_stop=STOP_NORMAL, hp_stop=STOP_NORMAL, per_source=False, estimator=LOOP_STD, lp_eo=False, hp_eo=False):
     """Returns dict with 'loops' [3][16][n_mom][Lt] (C, B, T), 'err', optional
-    'per_source' [N][2][16][n_mom][Lt] and 'stats' [N][2][5]."""
+    'per_source' [N][2][16][n_mom][Lt] and 'stats' [N][2][5].  lp_eo / hp_eo
+    solve that set on the even-odd Schur complement."""
     d = _dims(dims)
     U = _c128(U)
     mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
@@ -213,7 +270,7 @@ def tsm(dims, t_bc, kappa, mu, U, seed, n_hp, n_lp, lp_tol, lp_maxit, hp_tol, hp
     load_oracle().orc_tsm(_ptr(d), int(t_bc), float(kappa), float(mu), _ptr(U), int(seed), int(n_hp), int(n_lp),
                           float(lp_tol), int(lp_maxit), int(lp_stop), float(hp_tol), int(hp_maxit), int(hp_stop),
                           nm, _ptr(mom), int(estimator), _ptr(out), _ptr(err), _ptr(ps) if ps is not None else None,
-                          _ptr(st))
+                          _ptr(st), int(bool(lp_eo)), int(bool(hp_eo)))
     res = {"loops": out, "err": err, "stats": st[:n]}
     if ps is not None:
         res["per_source"] = ps[:n]

@@ -211,7 +211,7 @@ static void hop(const int *L, int t_bc, const cplx *U, const cplx *in, cplx *out
     cplx gm[4][4][4];
     for (int mu = 0; mu < 4; mu++) gamma_mu(mu, gm[mu]);
 
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (V >= 8192)
     for (long s = 0; s < V; s++) {
         cplx acc[NSPIN][NCOL];
         memset(acc, 0, sizeof(acc));
@@ -364,6 +364,209 @@ int orc_cgnr(const int *L, int t_bc, double kappa, double mu, const double *U_,
         stats[4] = trunc;
     }
     free(b); free(r); free(p); free(t); free(q); free(rho);
+    return it;
+}
+
+/* ------------------------------------------------------------------ */
+/* even-odd (Schur-complement) reduction of M                          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Not in the paper: the standard even-odd reduction of the twisted-mass
+ * operator, here an alternative inverter for the LP (and HP) solves.  The
+ * TSM combination of Eq. 4 stays unbiased for any fixed LP map, so the
+ * estimator is unchanged; only the truncated solutions differ.
+ *
+ * A site is even or odd by the parity of x + y + z + t.  With every extent
+ * even, each hop of H changes the parity, so with the sites split by parity
+ *     A = [[A_ee, A_eo], [A_oe, A_oo]]        (A = M or A = M^dag)
+ * has diagonal blocks that act site by site (the twisted-mass term) and the
+ * Schur complement on the odd sites is
+ *     Ahat = A_oo - A_oe A_ee^{-1} A_eo.
+ * M x = eta is solved as Mhat x_o = etahat_o with
+ *     etahat_o = eta_o - M_oe M_ee^{-1} eta_e,
+ * and the even half follows as x_e = M_ee^{-1} (eta_e - M_eo x_o).  Then
+ * (eta - M x)_e = 0 and (eta - M x)_o = etahat_o - Mhat x_o.  (Mhat)^dag is
+ * the same construction on A = M^dag.
+ *
+ * Fields are full size [V][4][3]; a field of one parity has zeros on the
+ * sites of the other.
+ */
+
+static int parity_of(const int *L, long s)
+{
+    int c[4];
+    site_coords(L, s, c);
+    return (c[0] + c[1] + c[2] + c[3]) & 1;
+}
+
+static int all_even(const int *L)
+{
+    for (int d = 0; d < 4; d++)
+        if (L[d] % 2) return 0;
+    return 1;
+}
+
+/* out = in on the sites of parity par, zero elsewhere */
+static void mask_parity(const int *L, const cplx *in, cplx *out, int par)
+{
+    long V = volume(L);
+    for (long s = 0; s < V; s++)
+        for (int k = 0; k < NCOMP; k++)
+            out[s * NCOMP + k] = parity_of(L, s) == par ? in[s * NCOMP + k] : 0;
+}
+
+/* v <- A_pp^{-1} v on the sites of parity par.  The diagonal block of M is
+   1 + i tw gamma_5 on every site (tw = 2 kappa mu; H has no on-site term),
+   that of M^dag is 1 - i tw gamma_5; gamma_5 = diag(1, 1, -1, -1), so the
+   inverse divides spin component a by 1 +- i tw g5[a][a]. */
+static void diag_block_inverse(const int *L, double kappa, double mu, int dagger, cplx *v, int par)
+{
+    long V = volume(L);
+    cplx g5[4][4];
+    gamma5(g5);
+    double tw = (dagger ? -1.0 : 1.0) * 2.0 * kappa * mu;
+    for (long s = 0; s < V; s++) {
+        if (parity_of(L, s) != par) continue;
+        for (int a = 0; a < NSPIN; a++)
+            for (int i = 0; i < NCOL; i++) v[s * NCOMP + a * NCOL + i] /= (1.0 + I * tw * g5[a][a]);
+    }
+}
+
+/* out = Ahat in (odd sites of in used, even sites of out zero), A = M or M^dag */
+static void schur_apply(const int *L, int t_bc, double kappa, double mu, const cplx *U,
+                        const cplx *in, cplx *out, int dagger)
+{
+    long n = volume(L) * NCOMP;
+    cplx *a = malloc(sizeof(cplx) * n), *b = malloc(sizeof(cplx) * n);
+    cplx *c = malloc(sizeof(cplx) * n), *f = malloc(sizeof(cplx) * n);
+    mask_parity(L, in, a, 1);                          /* a = x_o */
+    apply_m(L, t_bc, kappa, mu, U, a, b, dagger);      /* b_o = A_oo x_o, b_e = A_eo x_o */
+    mask_parity(L, b, c, 0);                           /* c = A_eo x_o */
+    diag_block_inverse(L, kappa, mu, dagger, c, 0);    /* c = A_ee^{-1} A_eo x_o */
+    apply_m(L, t_bc, kappa, mu, U, c, f, dagger);      /* f_o = A_oe c_e */
+    for (long i = 0; i < n; i++) f[i] = b[i] - f[i];
+    mask_parity(L, f, out, 1);
+    free(a); free(b); free(c); free(f);
+}
+
+/* Mhat (op 0), Mhat^dag (op 1), Mhat^dag Mhat (op 2) on odd-site fields;
+   returns -1 (nothing written) unless every extent is even */
+int orc_eo_apply(const int *L, int t_bc, double kappa, double mu, int op,
+                 const double *U_, const double *in_, double *out_)
+{
+    if (!all_even(L)) return -1;
+    const cplx *U = (const cplx *)U_;
+    const cplx *in = (const cplx *)in_;
+    cplx *out = (cplx *)out_;
+    long n = volume(L) * NCOMP;
+    if (op == 2) {
+        cplx *tmp = malloc(sizeof(cplx) * n);
+        schur_apply(L, t_bc, kappa, mu, U, in, tmp, 0);
+        schur_apply(L, t_bc, kappa, mu, U, tmp, out, 1);
+        free(tmp);
+    } else {
+        schur_apply(L, t_bc, kappa, mu, U, in, out, op == 1);
+    }
+    return 0;
+}
+
+/* etahat = eta_o - M_oe M_ee^{-1} eta_e (odd-site field) */
+void orc_eo_source(const int *L, int t_bc, double kappa, double mu, const double *U_,
+                   const double *eta_, double *out_)
+{
+    const cplx *U = (const cplx *)U_;
+    const cplx *eta = (const cplx *)eta_;
+    cplx *out = (cplx *)out_;
+    long n = volume(L) * NCOMP;
+    cplx *e = malloc(sizeof(cplx) * n), *f = malloc(sizeof(cplx) * n);
+    mask_parity(L, eta, e, 0);
+    diag_block_inverse(L, kappa, mu, 0, e, 0);
+    apply_m(L, t_bc, kappa, mu, U, e, f, 0);           /* f_o = M_oe M_ee^{-1} eta_e */
+    for (long i = 0; i < n; i++) f[i] = eta[i] - f[i];
+    mask_parity(L, f, out, 1);
+    free(e); free(f);
+}
+
+/* x_e = M_ee^{-1} (eta_e - M_eo x_o): x holds x_o on entry and the whole
+   solution on return */
+void orc_eo_reconstruct(const int *L, int t_bc, double kappa, double mu, const double *U_,
+                        const double *eta_, double *x_)
+{
+    const cplx *U = (const cplx *)U_;
+    const cplx *eta = (const cplx *)eta_;
+    cplx *x = (cplx *)x_;
+    long n = volume(L) * NCOMP;
+    cplx *a = malloc(sizeof(cplx) * n), *g = malloc(sizeof(cplx) * n), *h = malloc(sizeof(cplx) * n);
+    mask_parity(L, x, a, 1);
+    apply_m(L, t_bc, kappa, mu, U, a, g, 0);           /* g_e = M_eo x_o */
+    for (long i = 0; i < n; i++) g[i] = eta[i] - g[i];
+    mask_parity(L, g, h, 0);
+    diag_block_inverse(L, kappa, mu, 0, h, 0);
+    for (long i = 0; i < n; i++) x[i] = a[i] + h[i];
+    free(a); free(g); free(h);
+}
+
+/*
+ * Solve M x = eta by CG on the normal equations of the Schur complement,
+ * Mhat^dag Mhat x_o = Mhat^dag etahat_o, from x_o = 0, then reconstruct
+ * x_e.  Stop (checked before every iteration) when the relative residual is
+ * <= tol or after maxit iterations (maxit < 0: no cap).  The residual is
+ * that of these normal equations (stop = 0), or the recursively tracked
+ * etahat_o - Mhat x_o, which is the residual eta - M x of the whole system,
+ * relative to |eta| (stop = 1).  stats as orc_cgnr, with stats[1] the final
+ * relative residual of the Schur normal equations.  Returns -1 unless
+ * every extent is even.
+ */
+int orc_cgnr_eo(const int *L, int t_bc, double kappa, double mu, const double *U_,
+                const double *eta_, double tol, int maxit, int stop,
+                double *x_, double *stats)
+{
+    if (!all_even(L)) return -1;
+    const cplx *U = (const cplx *)U_;
+    const cplx *eta = (const cplx *)eta_;
+    cplx *x = (cplx *)x_;
+    long n = volume(L) * NCOMP;
+    cplx *eh = malloc(sizeof(cplx) * n), *b = malloc(sizeof(cplx) * n), *r = malloc(sizeof(cplx) * n);
+    cplx *p = malloc(sizeof(cplx) * n), *t = malloc(sizeof(cplx) * n);
+    cplx *q = malloc(sizeof(cplx) * n), *rho = malloc(sizeof(cplx) * n);
+
+    orc_eo_source(L, t_bc, kappa, mu, U_, eta_, (double *)eh);
+    schur_apply(L, t_bc, kappa, mu, U, eh, b, 1);
+    for (long i = 0; i < n; i++) { x[i] = 0; r[i] = b[i]; p[i] = b[i]; rho[i] = eh[i]; }
+    double rr = norm2(r, n), bb = rr, ee = norm2(eta, n), rhorho = norm2(eh, n);
+    int it = 0, conv = 0, trunc = 0;
+    for (;;) {
+        double rel = (stop == ORC_STOP_TRUE) ? sqrt(rhorho / ee) : sqrt(rr / bb);
+        if (rel <= tol) { conv = 1; break; }
+        if (maxit >= 0 && it >= maxit) { trunc = 1; break; }
+        schur_apply(L, t_bc, kappa, mu, U, p, t, 0);
+        double tt = norm2(t, n);
+        double alpha = rr / tt;
+        for (long i = 0; i < n; i++) x[i] += alpha * p[i];
+        if (stop == ORC_STOP_TRUE) {
+            for (long i = 0; i < n; i++) rho[i] -= alpha * t[i];
+            rhorho = norm2(rho, n);
+        }
+        schur_apply(L, t_bc, kappa, mu, U, t, q, 1);
+        for (long i = 0; i < n; i++) r[i] -= alpha * q[i];
+        double rr_new = norm2(r, n);
+        double beta = rr_new / rr;
+        for (long i = 0; i < n; i++) p[i] = r[i] + beta * p[i];
+        rr = rr_new;
+        it++;
+    }
+    orc_eo_reconstruct(L, t_bc, kappa, mu, U_, eta_, x_);
+    if (stats) {
+        apply_m(L, t_bc, kappa, mu, U, x, t, 0);
+        for (long i = 0; i < n; i++) t[i] = eta[i] - t[i];
+        stats[0] = it;
+        stats[1] = sqrt(rr / bb);
+        stats[2] = sqrt(norm2(t, n) / ee);
+        stats[3] = conv;
+        stats[4] = trunc;
+    }
+    free(eh); free(b); free(r); free(p); free(t); free(q); free(rho);
     return it;
 }
 
@@ -591,13 +794,16 @@ void orc_loops_deriv(const int *L, int t_bc, const double *U_, const double *eta
  * per_src (nullable): complex128 [n_hp+n_lp][2][16][n_mom][Lt]: slot 0 the
  *   LP loops, slot 1 the HP loops (zero for LP ids).
  * src_stats (nullable): double [n_hp+n_lp][2][5] CG stats (slot 0 LP, 1 HP).
+ * lp_eo, hp_eo: 1 solves that set with CG on the even-odd Schur complement
+ *   (orc_cgnr_eo), 0 with CG on M^dag M (orc_cgnr).
  */
 int orc_tsm(const int *L, int t_bc, double kappa, double mu, const double *U,
             uint64_t seed, int n_hp, int n_lp,
             double lp_tol, int lp_maxit, int lp_stop,
             double hp_tol, int hp_maxit, int hp_stop,
             int n_mom, const int *mom, int est,
-            double *out_, double *err_, double *per_src_, double *src_stats)
+            double *out_, double *err_, double *per_src_, double *src_stats,
+            int lp_eo, int hp_eo)
 {
     long V = volume(L);
     long n = V * NCOMP;
@@ -617,13 +823,19 @@ int orc_tsm(const int *L, int t_bc, double kappa, double mu, const double *U,
     for (int j = 0; j < n_hp + n_lp; j++) {
         int is_hp = j < n_hp;
         orc_noise_z4(L, seed, (uint64_t)j, (double *)eta);
-        orc_cgnr(L, t_bc, kappa, mu, U, (double *)eta, lp_tol, lp_maxit, lp_stop, (double *)s, st);
+        if (lp_eo)
+            orc_cgnr_eo(L, t_bc, kappa, mu, U, (double *)eta, lp_tol, lp_maxit, lp_stop, (double *)s, st);
+        else
+            orc_cgnr(L, t_bc, kappa, mu, U, (double *)eta, lp_tol, lp_maxit, lp_stop, (double *)s, st);
         if (src_stats) memcpy(src_stats + (j * 2 + 0) * 5, st, sizeof(st));
         memset(l_lp, 0, sizeof(cplx) * nl);
         orc_loops_est(L, t_bc, kappa, mu, U, est, (double *)eta, (double *)s, n_mom, mom, (double *)l_lp);
         memset(l_hp, 0, sizeof(cplx) * nl);
         if (is_hp) {
-            orc_cgnr(L, t_bc, kappa, mu, U, (double *)eta, hp_tol, hp_maxit, hp_stop, (double *)s, st);
+            if (hp_eo)
+                orc_cgnr_eo(L, t_bc, kappa, mu, U, (double *)eta, hp_tol, hp_maxit, hp_stop, (double *)s, st);
+            else
+                orc_cgnr(L, t_bc, kappa, mu, U, (double *)eta, hp_tol, hp_maxit, hp_stop, (double *)s, st);
             if (src_stats) memcpy(src_stats + (j * 2 + 1) * 5, st, sizeof(st));
             orc_loops_est(L, t_bc, kappa, mu, U, est, (double *)eta, (double *)s, n_mom, mom, (double *)l_hp);
             for (long k = 0; k < nl; k++) {
@@ -710,7 +922,7 @@ static void transport(const int *L, int t_bc, const cplx *U, int p, const cplx *
     }
     int mu = (p - 1) / 2;
     int dir = (p % 2 == 1) ? 1 : -1;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (V >= 8192)
     for (long s = 0; s < V; s++) {
         double ph;
         long y = neighbour(L, t_bc, s, mu, dir, &ph);
