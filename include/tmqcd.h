@@ -233,6 +233,21 @@ tm_status tm_field_convert(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t to_n
 tm_status tm_dslash(tm_ctx* ctx, int32_t op, int32_t prec, int32_t nrhs, int32_t layout,
                     const void* in_dev, void* out_dev);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): tm_dslash
+   with the same arguments, results and kernels, which allocates nothing.
+   Its scratch (the native staging of a canonical input and output, and the
+   intermediate M in of M^dag M) lives in a device array of 128 MiB that the
+   library holds on every GPU it runs on until the process ends; tm_create
+   looks up its address.  Needs (canonical: 2 fields, M^dag M: 1 field, each
+   tm_field_bytes(ctx, prec, nrhs, TM_LAYOUT_NATIVE) rounded up to 256 B)
+   beyond 128 MiB return TM_EINVAL before anything is enqueued.  Every call
+   on one GPU shares that array: calls that overlap in time on one GPU (two
+   streams, two host threads) race on it.  Not recorded by tm_profile_*.
+   Asynchronous. */
+tm_status tm_dslash_noalloc(tm_ctx* ctx, int32_t op, int32_t prec, int32_t nrhs, int32_t layout,
+                            const void* in_dev, void* out_dev);
+
 /* ---- noise -------------------------------------------------------------- */
 
 /* Write the Z4 sources (Eq. 1) of the given ids as canonical complex128

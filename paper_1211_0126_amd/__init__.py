@@ -17,6 +17,7 @@ from .binding import (  # noqa: F401
     tm_create,
     tm_gauge_load,
     tm_dslash,
+    tm_dslash_noalloc,
     tm_field_bytes,
     tm_field_convert,
     tm_noise_z4,

@@ -65,7 +65,7 @@ class RunStats(ctypes.Structure):
 
 EXPORTS = [
     "tm_abi_version", "tm_create", "tm_destroy", "tm_last_error", "tm_gauge_load", "tm_field_bytes",
-    "tm_field_convert", "tm_dslash", "tm_noise_z4", "tsm_solve_batch", "tsm_contract", "tsm_contract_est",
+    "tm_field_convert", "tm_dslash", "tm_dslash_noalloc", "tm_noise_z4", "tsm_solve_batch", "tsm_contract", "tsm_contract_est",
     "tsm_loops",
     "tm_profile_enable", "tm_profile_read",
 ]
@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH):
     lib.tm_field_bytes.restype = ctypes.c_size_t
     lib.tm_field_convert.argtypes = [P, i32, i32, i32, P, P]
     lib.tm_dslash.argtypes = [P, i32, i32, i32, i32, P, P]
+    lib.tm_dslash_noalloc.argtypes = [P, i32, i32, i32, i32, P, P]
     lib.tm_noise_z4.argtypes = [P, u64, i32, P, P]
     lib.tsm_solve_batch.argtypes = [P, ctypes.POINTER(SolveParams), u64, i32, P, P, P]
     lib.tsm_contract.argtypes = [P, u64, i32, P, P, i32, P, P]
@@ -204,6 +205,21 @@ def tm_dslash(ctx: Context, op, prec, x, out=None, layout=LAYOUT_CANONICAL, nrhs
         assert nrhs is not None and out is not None
     ctx.check(ctx.lib.tm_dslash(ctx.h, op, prec, nrhs, layout, ctypes.c_void_p(x.data_ptr()),
                                 ctypes.c_void_p(out.data_ptr())))
+    return out
+
+
+def tm_dslash_noalloc(ctx: Context, op, prec, x, out, layout=LAYOUT_CANONICAL, nrhs=None):
+    """out = op(x) through the allocation-free entry point; out is the
+    caller's tensor (nothing is allocated here either)."""
+    if layout == LAYOUT_CANONICAL:
+        nrhs = x.shape[0]
+        assert tuple(x.shape) == canonical_shape(ctx, prec, nrhs) and x.dtype == _canon_dtype(prec)
+        assert tuple(out.shape) == tuple(x.shape) and out.dtype == x.dtype
+        assert x.is_cuda and x.is_contiguous() and out.is_cuda and out.is_contiguous()
+    else:
+        assert nrhs is not None
+    ctx.check(ctx.lib.tm_dslash_noalloc(ctx.h, op, prec, nrhs, layout, ctypes.c_void_p(x.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr())))
     return out
 
 

@@ -4,12 +4,44 @@
 #include <cstring>
 #include <array>
 #include <complex>
+#include <mutex>
 #include <vector>
 
 #include "tm_ctx.h"
 #include "tm_learn.h"
 
 namespace tmq {
+
+// Scratch of tm_dslash_noalloc, for callers that cannot allocate device
+// memory (code under graph capture, serving loops): a file-scope device
+// array of kScratchBytes, one copy on every GPU the library runs on, held
+// until the process ends.  Host code never passes the array's name to a
+// kernel or a copy: it uses the per-device address that tm_create obtains
+// with hipGetSymbolAddress (the name is only a host-side stand-in).
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// with device dev current: look up (once per device) the address of scratch
+static hipError_t scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+    return hipSuccess;
+}
+
+static void* scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
 
 // error text of the last failed tm_create on this thread (tm_last_error(NULL))
 static thread_local std::string g_create_error = "no error";
@@ -150,6 +182,62 @@ static void gamma_tables(int col[3][16][4], int ph[3][16][4]) {
         }
 }
 
+// ---------------------------------------------------------------------------
+// operator application shared by tm_dslash and tm_dslash_noalloc
+// ---------------------------------------------------------------------------
+static tm_status dslash_check(tm_ctx* ctx, int32_t op, int32_t prec, int32_t nrhs, int32_t layout, const void* in_dev,
+                              void* out_dev, const char* who) {
+    if (!ctx) return TM_EINVAL;
+    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, std::string(who) + ": no gauge field loaded");
+    if (op < 0 || op > 3 || prec < 0 || prec > 3 || nrhs < 1 || nrhs > 65535 || !in_dev || !out_dev ||
+        in_dev == out_dev || (layout != TM_LAYOUT_CANONICAL && layout != TM_LAYOUT_NATIVE))
+        return set_error(ctx, TM_EINVAL, std::string(who) + ": bad argument");
+    return TM_OK;
+}
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// scratch of one application: native staging of a canonical input and output,
+// and the intermediate M in of M^dag M
+static size_t dslash_scratch_bytes(const Geom& g, int op, int prec, int nrhs, int layout) {
+    const size_t fb = align256(field_bytes(g, prec, nrhs));
+    return (layout == TM_LAYOUT_CANONICAL ? 2 * fb : 0) + (op == TM_OP_MDAGM ? fb : 0);
+}
+
+// stage_in / stage_out: native buffers for a canonical layout (else unused);
+// tmp: the intermediate field of M^dag M (else unused)
+static tm_status dslash_run(tm_ctx* ctx, int op, int prec, int nrhs, int layout, const void* in_dev, void* out_dev,
+                            void* stage_in, void* stage_out, void* tmp, bool prof) {
+    const Geom& g = ctx->geo;
+    const void* gauge = prec == TM_PREC_F64 ? ctx->gauge64 : ctx->gauge32;
+    const int nr = (prec == TM_PREC_F64) ? 1 : (nrhs % 4 == 0 ? 4 : (nrhs % 2 == 0 ? 2 : 1));
+    const void* in = in_dev;
+    void* out = out_dev;
+    if (layout == TM_LAYOUT_CANONICAL) {
+        launch_field_convert(ctx->stream, g, prec, nrhs, true, in_dev, stage_in);
+        in = stage_in;
+        out = stage_out;
+    }
+    const double bs = prec == TM_PREC_F64 ? 8 : (prec == TM_PREC_F32 ? 4 : 2);
+    const double gb = prec == TM_PREC_F64 ? 4 * 18 * 8 : 4 * 12 * 4;
+    const double bytes_one = (double)g.V * (nrhs * 48.0 * bs + gb);
+    auto apply = [&](int o, const void* src, void* dst) {
+        if (prof) prof_begin(ctx, TM_KC_APPLY);
+        launch_apply(ctx->stream, g, prec, gauge, ctx->lat.kappa, ctx->twist, o, nrhs, src, dst, nr, nullptr);
+        if (prof) prof_end(ctx, TM_KC_APPLY, bytes_one);
+    };
+    if (op == TM_OP_MDAGM) {
+        apply(TM_OP_M, in, tmp);
+        apply(TM_OP_MDAG, tmp, out);
+    } else {
+        apply(op, in, out);
+    }
+    if (layout == TM_LAYOUT_CANONICAL) launch_field_convert(ctx->stream, g, prec, nrhs, false, out, out_dev);
+    TM_HIP(hipGetLastError());
+    return TM_OK;
+}
+
 }  // namespace tmq
 
 using namespace tmq;
@@ -211,6 +299,13 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
     hipError_t e = hipGetDevice(&ctx->device);
     if (e != hipSuccess) {
         g_create_error = std::string("tm_create: hipGetDevice: ") + hipGetErrorString(e);
+        delete ctx;
+        return TM_EDEVICE;
+    }
+    e = scratch_setup(ctx->device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("tm_create: address of the device scratch: ") + hipGetErrorString(e);
+        (void)hipGetLastError();
         delete ctx;
         return TM_EDEVICE;
     }
@@ -294,48 +389,44 @@ tm_status tm_field_convert(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t to_n
 
 tm_status tm_dslash(tm_ctx* ctx, int32_t op, int32_t prec, int32_t nrhs, int32_t layout, const void* in_dev,
                     void* out_dev) {
-    if (!ctx) return TM_EINVAL;
-    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
-    if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tm_dslash: no gauge field loaded");
-    if (op < 0 || op > 3 || prec < 0 || prec > 3 || nrhs < 1 || nrhs > 65535 || !in_dev || !out_dev ||
-        in_dev == out_dev || (layout != TM_LAYOUT_CANONICAL && layout != TM_LAYOUT_NATIVE))
-        return set_error(ctx, TM_EINVAL, "tm_dslash: bad argument");
-    const Geom& g = ctx->geo;
-    const void* gauge = prec == TM_PREC_F64 ? ctx->gauge64 : ctx->gauge32;
-    const int nr = (prec == TM_PREC_F64) ? 1 : (nrhs % 4 == 0 ? 4 : (nrhs % 2 == 0 ? 2 : 1));
-    const size_t fb = field_bytes(g, prec, nrhs);
-    const void* in = in_dev;
-    void* out = out_dev;
-    tm_status st = TM_OK;
+    tm_status st = dslash_check(ctx, op, prec, nrhs, layout, in_dev, out_dev, "tm_dslash");
+    if (st != TM_OK) return st;
+    const size_t fb = field_bytes(ctx->geo, prec, nrhs);
+    void *a = nullptr, *b = nullptr, *tmp = nullptr;
     if (layout == TM_LAYOUT_CANONICAL) {
-        void* a = ws_get(ctx, "dslash_in", fb, &st);
+        a = ws_get(ctx, "dslash_in", fb, &st);
         if (!a) return st;
-        void* b = ws_get(ctx, "dslash_out", fb, &st);
+        b = ws_get(ctx, "dslash_out", fb, &st);
         if (!b) return st;
-        launch_field_convert(ctx->stream, g, prec, nrhs, true, in_dev, a);
-        in = a;
-        out = b;
     }
-    const double bs = prec == TM_PREC_F64 ? 8 : (prec == TM_PREC_F32 ? 4 : 2);
-    const double gb = prec == TM_PREC_F64 ? 4 * 18 * 8 : 4 * 12 * 4;
-    const double bytes_one = (double)g.V * (nrhs * 48.0 * bs + gb);
     if (op == TM_OP_MDAGM) {
-        void* tmp = ws_get(ctx, "dslash_tmp", fb, &st);
+        tmp = ws_get(ctx, "dslash_tmp", fb, &st);
         if (!tmp) return st;
-        prof_begin(ctx, TM_KC_APPLY);
-        launch_apply(ctx->stream, g, prec, gauge, ctx->lat.kappa, ctx->twist, 0, nrhs, in, tmp, nr, nullptr);
-        prof_end(ctx, TM_KC_APPLY, bytes_one);
-        prof_begin(ctx, TM_KC_APPLY);
-        launch_apply(ctx->stream, g, prec, gauge, ctx->lat.kappa, ctx->twist, 1, nrhs, tmp, out, nr, nullptr);
-        prof_end(ctx, TM_KC_APPLY, bytes_one);
-    } else {
-        prof_begin(ctx, TM_KC_APPLY);
-        launch_apply(ctx->stream, g, prec, gauge, ctx->lat.kappa, ctx->twist, op, nrhs, in, out, nr, nullptr);
-        prof_end(ctx, TM_KC_APPLY, bytes_one);
     }
-    if (layout == TM_LAYOUT_CANONICAL) launch_field_convert(ctx->stream, g, prec, nrhs, false, out, out_dev);
-    TM_HIP(hipGetLastError());
-    return TM_OK;
+    return dslash_run(ctx, op, prec, nrhs, layout, in_dev, out_dev, a, b, tmp, true);
+}
+
+tm_status tm_dslash_noalloc(tm_ctx* ctx, int32_t op, int32_t prec, int32_t nrhs, int32_t layout, const void* in_dev,
+                            void* out_dev) {
+    tm_status st = dslash_check(ctx, op, prec, nrhs, layout, in_dev, out_dev, "tm_dslash_noalloc");
+    if (st != TM_OK) return st;
+    const size_t need = dslash_scratch_bytes(ctx->geo, op, prec, nrhs, layout);
+    if (need > kScratchBytes)
+        return set_error(ctx, TM_EINVAL, "tm_dslash_noalloc: this call needs " + std::to_string(need) +
+                                             " bytes of scratch; the maximum is " + std::to_string(kScratchBytes) +
+                                             " (use tm_dslash)");
+    char* base = (char*)scratch_ptr(ctx->device);
+    if (!base) return set_error(ctx, TM_ESTATE, "tm_dslash_noalloc: no scratch address for this device");
+    const size_t fb = align256(field_bytes(ctx->geo, prec, nrhs));
+    void *a = nullptr, *b = nullptr, *tmp = nullptr;
+    size_t off = 0;
+    if (layout == TM_LAYOUT_CANONICAL) {
+        a = base;
+        b = base + fb;
+        off = 2 * fb;
+    }
+    if (op == TM_OP_MDAGM) tmp = base + off;
+    return dslash_run(ctx, op, prec, nrhs, layout, in_dev, out_dev, a, b, tmp, false);
 }
 
 tm_status tm_noise_z4(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* ids_host, double* out_dev) {
