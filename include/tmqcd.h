@@ -101,7 +101,14 @@ typedef enum {
 
 typedef enum {
     TM_SOLVER_CG = 0,          /* conjugate gradients on M^dag M */
-    TM_SOLVER_FCG_LEARNED = 1  /* flexible CG preconditioned by the learned network */
+    TM_SOLVER_FCG_LEARNED = 1, /* flexible CG preconditioned by the learned network */
+    TM_SOLVER_CG_EO = 2        /* conjugate gradients on Mhat^dag Mhat, Mhat = D - kappa^2 H_oe D^{-1} H_eo
+                                  the even-odd Schur complement of M on the odd sites (D = 1 + 2i kappa mu g5);
+                                  the even half of s is reconstructed.  Not in the paper; a different LP map
+                                  than TM_SOLVER_CG (Eq. 4 stays unbiased for any fixed one).  Needs every
+                                  extent even (TM_ENOTSUP otherwise); tol, max_iter and TM_STOP_NORMAL refer
+                                  to the Schur system, TM_STOP_TRUE to |eta - M s| / |eta| of the whole
+                                  system (which equals that of the Schur system) */
 } tm_solver;
 
 typedef struct {
@@ -443,13 +450,17 @@ tm_status tm_set_graphs(tm_ctx* ctx, int32_t on, int64_t* replays);
 /* Kernel classes timed with HIP events on the context stream when profiling
    is enabled. */
 enum {
-    TM_KC_DSLASH = 0,     /* t = M p (+ |t|^2): the CG operator application */
-    TM_KC_DSLASH_UPD = 1, /* q = M^dag t fused with x, r updates (+ |r|^2) */
+    TM_KC_DSLASH = 0,     /* t = M p (+ |t|^2): the CG operator application (even-odd: its second
+                             half t = D p - kappa^2 H_oe y) */
+    TM_KC_DSLASH_UPD = 1, /* q = M^dag t fused with x, r updates (+ |r|^2) (even-odd: the second half
+                             of Mhat^dag t) */
     TM_KC_BLAS = 2,       /* p = r + beta p */
     TM_KC_CONTRACT = 3,   /* loop contraction */
     TM_KC_OTHER = 4,      /* noise, initialisation, CG scalar reductions, reliable updates, residuals */
     TM_KC_APPLY = 5,      /* tm_dslash applications */
-    TM_KC_COUNT = 6
+    TM_KC_EO_HOP = 6,     /* even-odd CG: y = D^{-1} H_eo p (the first half of Mhat p) */
+    TM_KC_EO_HOP_DAG = 7, /* even-odd CG: y = D^{-dag} H_eo^dag t (the first half of Mhat^dag t) */
+    TM_KC_COUNT = 8
 };
 
 /* Enable (1) or disable (0) per-launch event timing; enabling clears the

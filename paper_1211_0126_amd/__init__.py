@@ -36,6 +36,7 @@ from .binding import (  # noqa: F401
     tm_set_lane_rhs,
     SOLVER_CG,
     SOLVER_FCG_LEARNED,
+    SOLVER_CG_EO,
     EXPORTS,
     LIB_PATH,
     PREC_F64,

@@ -21,10 +21,10 @@ PREC_F64, PREC_F32, PREC_F16, PREC_BF16 = 0, 1, 2, 3
 OP_M, OP_MDAG, OP_MDAGM, OP_HOP = 0, 1, 2, 3
 LAYOUT_CANONICAL, LAYOUT_NATIVE = 0, 1
 STOP_NORMAL, STOP_TRUE = 0, 1
-SOLVER_CG, SOLVER_FCG_LEARNED = 0, 1
+SOLVER_CG, SOLVER_FCG_LEARNED, SOLVER_CG_EO = 0, 1, 2
 LOOP_STANDARD, LOOP_ONEEND_ISOVECTOR, LOOP_ONEEND_GENERALIZED, LOOP_DERIVATIVE = 0, 1, 2, 3
 ALL_MOMENTA = -1
-KC_NAMES = ["dslash", "dslash_upd", "blas", "contract", "other", "apply"]
+KC_NAMES = ["dslash", "dslash_upd", "blas", "contract", "other", "apply", "eo_hop", "eo_hop_dag"]
 
 
 class TmError(RuntimeError):

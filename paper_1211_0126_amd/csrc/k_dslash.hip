@@ -319,12 +319,13 @@ __device__ inline void cg_start(CgScal& q, double bb, double ee) {
     q.active = q.status == 0;
 }
 
-// one block per right-hand side; with_ee = 0: |eta|^2 of a Z4 source (12 V)
-__global__ __launch_bounds__(256) void k_cg_init_fin(CgArgs a, uint32_t nb, int with_ee) {
+// one block per right-hand side; with_ee = 0: |eta|^2 = ee_z4 (12 per site
+// of a Z4 source on the whole lattice)
+__global__ __launch_bounds__(256) void k_cg_init_fin(CgArgs a, uint32_t nb, int with_ee, double ee_z4) {
     __shared__ double sh[4];
     const int r = blockIdx.x;
     const double bb = sum_block_partials(a.partials + (size_t)r * nb, nb, sh);
-    const double ee = with_ee ? sum_block_partials(a.partials2 + (size_t)r * nb, nb, sh) : (double)a.geo.V * 12.0;
+    const double ee = with_ee ? sum_block_partials(a.partials2 + (size_t)r * nb, nb, sh) : ee_z4;
     if (threadIdx.x == 0) cg_start(a.scal[r], bb, ee);
 }
 
@@ -686,7 +687,7 @@ void launch_cg_p(hipStream_t st, const CgArgs& a, int prec) {
     }
 }
 
-void launch_cg_init(hipStream_t st, const CgArgs& a, int prec, bool track, const void* eta) {
+void launch_cg_init(hipStream_t st, const CgArgs& a, int prec, bool track, const void* eta, double ee_z4) {
     dim3 grid = site_grid(a.geo, a.nrhs);
     switch (prec) {
     case P_F64:
@@ -714,7 +715,8 @@ void launch_cg_init(hipStream_t st, const CgArgs& a, int prec, bool track, const
             hipLaunchKernelGGL((k_cg_init<float, SBF16, SF32, float, false>), grid, dim3(256), 0, st, a, eta);
         break;
     }
-    hipLaunchKernelGGL(k_cg_init_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, site_blocks(a.geo), 1);
+    hipLaunchKernelGGL(k_cg_init_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, site_blocks(a.geo),
+                       ee_z4 > 0 ? 0 : 1, ee_z4);
 }
 
 void launch_scal_init(hipStream_t st, CgScal* sc, int n, double tol2, int maxit, int stop, int reliable,
@@ -723,9 +725,13 @@ void launch_scal_init(hipStream_t st, CgScal* sc, int n, double tol2, int maxit,
                        delta2);
 }
 
-void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64) {
+void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64, double ee_z4) {
     hipLaunchKernelGGL(k_rel_init, site_grid(a.geo, a.nrhs), dim3(256), 0, st, a, b64, x64);
-    hipLaunchKernelGGL(k_cg_init_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, site_blocks(a.geo), 0);
+    hipLaunchKernelGGL(k_cg_init_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, site_blocks(a.geo), 0,
+                       ee_z4 > 0 ? ee_z4 : 12.0 * (double)a.geo.V);
+}
+void launch_rel_fin(hipStream_t st, const CgArgs& a, uint32_t nb) {
+    hipLaunchKernelGGL(k_rel_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, nb);
 }
 void launch_rel_flush(hipStream_t st, const CgArgs& a, void* x64, int force) {
     hipLaunchKernelGGL(k_rel_flush, dim3(gated_blocks(a.geo), (unsigned)a.nrhs), dim3(256), 0, st, a, x64, force);

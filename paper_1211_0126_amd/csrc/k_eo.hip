@@ -1,0 +1,584 @@
+// Even-odd (Schur complement) form of the twisted-mass operator (gfx950).
+//
+// A site is even or odd by the parity of x + y + z + t.  With every extent
+// even each hop of H joins sites of opposite parity, so M = 1 - kappa H +
+// i tw g5 (tw = 2 kappa mu) splits into the site-local blocks D = 1 + i tw g5
+// on either parity and the hops H_eo, H_oe.  CG runs on the normal
+// equations of the Schur complement on the odd sites,
+//   Mhat = D - kappa^2 H_oe D^{-1} H_eo,
+// whose source is etahat_o = eta_o + kappa H_oe D^{-1} eta_e; the even half
+// of the solution follows as x_e = D^{-1} (eta_e + kappa H_eo x_o).  Mhat^dag
+// is the same construction on M^dag (D^dag = 1 - i tw g5, H^dag = g5 H g5:
+// the two projectors swapped).  This reduction is not in the paper: it is an
+// alternative inverter for the LP and HP solves of the TSM (section 2.2,
+// Eq. 4), whose combination is unbiased for any fixed LP map.
+//
+// Half fields: the sites of one parity, indexed h = x/2 + (Lx/2)(y + Ly(z +
+// Lz t)), stored like full native fields (component planes of 16-byte
+// vectors) with their own plane stride.  The links are split the same way:
+// each parity's copy holds the forward links U_mu(x) of its sites, so a
+// half-hop reads the forward links from the output parity's copy and the
+// backward links U_mu(x - mu) from the input parity's copy at the neighbour,
+// and every link is read once per half-hop.
+//
+// Per CG iteration (k_eo_lin, k_eo_mp, k_eo_lin, k_eo_upd; the alpha and beta
+// reductions and p = r + beta p are the full-lattice kernels on the half
+// geometry):
+//   y = D^{-1} H_eo p          t = D p - kappa^2 H_oe y,  |t|^2
+//   y = D^{-dag} H_eo^dag t    q = D^dag t - kappa^2 H_oe^dag y,
+//                              r -= alpha q, x += alpha p, |r|^2
+
+#include <algorithm>
+
+#include "tm_device.h"
+#include "tm_kernels.h"
+#include "tm_stencil.h"
+
+namespace tmq {
+
+struct EoSite {
+    int xh, x, y, z, t;
+};
+
+// coordinates of half-site h of parity par (hg.m[0] divides by Lx/2; it is
+// 0 for Lx = 2, where the row is h itself)
+__device__ __forceinline__ EoSite eo_coords(const Geom& hg, uint32_t h, int par) {
+    const uint32_t Lxh = (uint32_t)hg.L[0] >> 1;
+    const uint32_t q0 = hg.m[0] ? fdiv(h, hg.m[0]) : h;
+    const uint32_t q1 = fdiv(q0, hg.m[1]);
+    const uint32_t q2 = fdiv(q1, hg.m[2]);
+    EoSite c;
+    c.xh = (int)(h - q0 * Lxh);
+    c.y = (int)(q0 - q1 * (uint32_t)hg.L[1]);
+    c.z = (int)(q1 - q2 * (uint32_t)hg.L[2]);
+    c.t = (int)q2;
+    c.x = 2 * c.xh + ((c.y + c.z + c.t + par) & 1);
+    return c;
+}
+
+// half index of the neighbour (opposite parity) in direction mu
+__device__ __forceinline__ uint32_t eo_nb(const Geom& hg, uint32_t h, const EoSite& c, int mu, bool fwd) {
+    const uint32_t L0 = hg.L[0], L1 = hg.L[1], L2 = hg.L[2], L3 = hg.L[3];
+    const uint32_t Lxh = L0 >> 1;
+    switch (mu) {
+    case 0: {
+        const int xn = fwd ? ((c.x + 1 == (int)L0) ? 0 : c.x + 1) : ((c.x == 0) ? (int)L0 - 1 : c.x - 1);
+        return h - (uint32_t)c.xh + (uint32_t)(xn >> 1);
+    }
+    case 1:
+        return fwd ? ((c.y + 1 == (int)L1) ? h - (L1 - 1) * Lxh : h + Lxh)
+                   : ((c.y == 0) ? h + (L1 - 1) * Lxh : h - Lxh);
+    case 2:
+        return fwd ? ((c.z + 1 == (int)L2) ? h - (L2 - 1) * Lxh * L1 : h + Lxh * L1)
+                   : ((c.z == 0) ? h + (L2 - 1) * Lxh * L1 : h - Lxh * L1);
+    default:
+        return fwd ? ((c.t + 1 == (int)L3) ? h - (L3 - 1) * Lxh * L1 * L2 : h + Lxh * L1 * L2)
+                   : ((c.t == 0) ? h + (L3 - 1) * Lxh * L1 * L2 : h - Lxh * L1 * L2);
+    }
+}
+
+// full-lattice site index of half-site h (parity par)
+__device__ __forceinline__ uint32_t eo_full_site(uint32_t h, const EoSite& c) {
+    return (h - (uint32_t)c.xh) * 2u + (uint32_t)c.x;  // x + Lx row with row = (h - xh) / (Lx/2)
+}
+
+// both hops in direction MU into half-site h: forward links from gout (the
+// output parity's copy, at h), backward links from gin at the neighbour
+template <int MU, bool DAG, typename R, class S, class G, int NR>
+__device__ __forceinline__ void eo_hop_mu(const Geom& hg, const void* gout, const void* gin, const void* in,
+                                          uint32_t h, const EoSite& c, cx<R> (&acc)[NR][12]) {
+    constexpr int SF = DAG ? -1 : 1;
+    const long Vs = hg.Vs;
+    {
+        const uint32_t y = eo_nb(hg, h, c, MU, true);
+        const bool flip = (MU == 3) && (c.t + 1 == hg.L[3]) && (hg.t_bc < 0);
+        cx<R> U[3][3];
+        load_link<G, R>(gout, Vs, MU, h, U);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<R> p[12], hh[6], g[6];
+            load_spinor<S, R>(field_rhs<S>(in, Vs, r), Vs, y, p);
+            proj<MU, SF>(p, hh);
+            if (flip) negate6(hh);
+            su3_mul(U, hh, g);
+            recon<MU, SF>(g, acc[r]);
+        }
+    }
+    if (sizeof(R) == 8) {
+        pin_acc<R, NR>(acc);
+        TM_MEM_FENCE();
+    }
+    {
+        const uint32_t y = eo_nb(hg, h, c, MU, false);
+        const bool flip = (MU == 3) && (c.t == 0) && (hg.t_bc < 0);
+        cx<R> U[3][3];
+        load_link<G, R>(gin, Vs, MU, y, U);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<R> p[12], hh[6], g[6];
+            load_spinor<S, R>(field_rhs<S>(in, Vs, r), Vs, y, p);
+            proj<MU, -SF>(p, hh);
+            if (flip) negate6(hh);
+            su3_dag_mul(U, hh, g);
+            recon<MU, -SF>(g, acc[r]);
+        }
+    }
+}
+
+template <bool DAG, typename R, class S, class G, int NR>
+__device__ __forceinline__ void eo_hop_all(const Geom& hg, const void* gout, const void* gin, const void* in,
+                                           uint32_t h, const EoSite& c, cx<R> (&acc)[NR][12]) {
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[r][k] = {(R)0, (R)0};
+    eo_hop_mu<0, DAG, R, S, G, NR>(hg, gout, gin, in, h, c, acc);
+    pin_acc<R, NR>(acc);
+    TM_MEM_FENCE();
+    eo_hop_mu<1, DAG, R, S, G, NR>(hg, gout, gin, in, h, c, acc);
+    pin_acc<R, NR>(acc);
+    TM_MEM_FENCE();
+    eo_hop_mu<2, DAG, R, S, G, NR>(hg, gout, gin, in, h, c, acc);
+    pin_acc<R, NR>(acc);
+    TM_MEM_FENCE();
+    eo_hop_mu<3, DAG, R, S, G, NR>(hg, gout, gin, in, h, c, acc);
+}
+
+// v <- (1 + i tw g5) v, g5 = diag(1, 1, -1, -1) (components 0-5 upper spins)
+template <typename R>
+__device__ __forceinline__ void mul_diag(cx<R> v[12], R tw) {
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const R s = k < 6 ? tw : -tw;
+        v[k] = {v[k].re - s * v[k].im, v[k].im + s * v[k].re};
+    }
+}
+// v <- (1 + i tw g5)^{-1} v = (1 - i tw g5) v / (1 + tw^2)
+template <typename R>
+__device__ __forceinline__ void mul_diag_inv(cx<R> v[12], R tw, R inv) {
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        const R s = k < 6 ? -tw : tw;
+        v[k] = {inv * (v[k].re - s * v[k].im), inv * (v[k].im + s * v[k].re)};
+    }
+}
+
+// Z4 source at full site s (the same hash as the full-lattice noise)
+template <typename R>
+__device__ __forceinline__ void noise_at(uint64_t seed_mixed, uint64_t id, uint64_t V, uint64_t s, cx<R> e[12]) {
+    const uint64_t hb = noise_bits(seed_mixed, id, V, s);
+#pragma unroll
+    for (int k = 0; k < 12; k++) e[k] = z4_value<R>((uint32_t)(hb >> (2 * k)) & 3u);
+}
+
+// ---------------------------------------------------------------------------
+// linear half-hop: out = POST(PRE(b) + c acc), acc = H (or H^dag if DAG) in,
+// PRE = D (if PRE_D) or 1 applied to the centre term b (nullptr: none; with
+// a.bnoise the Z4 source of the output site), POST = D^{-1} (if POST_DINV)
+// or 1; D carries the twist of M (or M^dag if DAG).
+// gate (nullable): only right-hand sides whose reliable flag is set (NR = 1,
+// small grid striding over the site blocks).
+// ---------------------------------------------------------------------------
+template <bool DAG, bool PRE_D, bool POST_DINV, typename R, class Si, class So, class G, int NR>
+__global__ TM_STENCIL_R(NR, R) void k_eo_lin(EoArgs a) {
+    const Geom& hg = a.hg;
+    const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
+    const int r0 = bm.ch * NR;
+    if (a.gate != nullptr && !a.gate[r0].rflag) return;
+    const long Vs = hg.Vs;
+    const R tw = (R)(DAG ? -a.twist : a.twist);
+    const R inv = (R)(1.0 / (1.0 + a.twist * a.twist));
+    const R cf = (R)a.c;
+    const void* in0 = field_rhs<Si>(a.in, Vs, r0);
+    const uint32_t nsb_all = (uint32_t)((hg.V + 255) / 256);
+    for (uint32_t sb = bm.sb; sb < nsb_all; sb += bm.nsb) {
+        const uint32_t h = sb * 256u + threadIdx.x;
+        if (h >= hg.V) continue;
+        const EoSite c = eo_coords(hg, h, a.pout);
+        cx<R> acc[NR][12];
+        eo_hop_all<DAG, R, Si, G, NR>(hg, a.gout, a.gin, in0, h, c, acc);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<R> o[12];
+            if (a.bnoise) {
+                noise_at<R>(a.seed_mixed, a.ids[r0 + r], (uint64_t)(2 * hg.V), eo_full_site(h, c), o);
+                if (PRE_D) mul_diag(o, tw);
+#pragma unroll
+                for (int k = 0; k < 12; k++) o[k] = o[k] + cf * acc[r][k];
+            } else if (a.b != nullptr) {
+                load_spinor<So, R>(field_rhs<So>(a.b, Vs, r0 + r), Vs, h, o);
+                if (PRE_D) mul_diag(o, tw);
+#pragma unroll
+                for (int k = 0; k < 12; k++) o[k] = o[k] + cf * acc[r][k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; k++) o[k] = cf * acc[r][k];
+            }
+            if (POST_DINV) mul_diag_inv(o, tw, inv);
+            store_spinor<So, R>(field_rhs<So>(a.out, Vs, r0 + r), Vs, h, o);
+        }
+    }
+}
+
+// site-local out = D^{-1} in (D of M, or of M^dag if dag)
+template <typename R, class S>
+__global__ __launch_bounds__(256) void k_eo_dinv(Geom hg, double twist, int nrhs, const void* in, void* out) {
+    const uint32_t h = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (h >= hg.V || r >= nrhs) return;
+    cx<R> v[12];
+    load_spinor<S, R>(field_rhs<S>(in, hg.Vs, r), hg.Vs, h, v);
+    mul_diag_inv(v, (R)twist, (R)(1.0 / (1.0 + twist * twist)));
+    store_spinor<S, R>(field_rhs<S>(out, hg.Vs, r), hg.Vs, h, v);
+}
+
+// ---------------------------------------------------------------------------
+// CG steps on the odd sites (a.geo is the half geometry)
+// ---------------------------------------------------------------------------
+
+// K1b: t = D p - kappa^2 H_oe y, block partials of |t|^2
+template <typename R, class S, class G, int NR>
+__global__ TM_STENCIL_R(NR, R) void k_eo_mp(CgArgs a, EoCg e) {
+    __shared__ double sh[4];
+    const Geom& hg = a.geo;
+    const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
+    const uint32_t nb = bm.nsb;
+    const uint32_t h = bm.sb * 256u + threadIdx.x;
+    const int r0 = bm.ch * NR;
+    const long Vs = hg.Vs;
+    bool act[NR];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        act[r] = a.scal[r0 + r].active != 0;
+        any |= act[r];
+    }
+    if (!any) return;
+    double part[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) part[r] = 0;
+    if (h < hg.V) {
+        const EoSite c = eo_coords(hg, h, 1);
+        cx<R> acc[NR][12];
+        eo_hop_all<false, R, S, G, NR>(hg, e.godd, e.geven, field_rhs<S>(e.y, Vs, r0), h, c, acc);
+        const R tw = (R)a.twist, k2 = (R)(-a.kappa * a.kappa);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (!act[r]) continue;
+            cx<R> t[12];
+            load_spinor<S, R>(field_rhs<S>(a.p, Vs, r0 + r), Vs, h, t);
+            mul_diag(t, tw);
+#pragma unroll
+            for (int k = 0; k < 12; k++) t[k] = t[k] + k2 * acc[r][k];
+            round_storage<S, R>(t);
+            store_spinor_cp<S, R, TM_CP_K1T>(field_rhs<S>(a.t, Vs, r0 + r), Vs, h, t);
+            part[r] = spinor_norm2(t);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        double v = block_sum256(part[r], sh);
+        if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * nb + bm.sb] = v;
+    }
+}
+
+// K2b: q = D^dag t - kappa^2 H_oe^dag y, r -= alpha q, x += alpha p, |r|^2;
+// with TRACK rho -= alpha t (rho = etahat - Mhat x) and |rho|^2
+template <typename R, class S, class G, class X, typename RX, int NR, bool TRACK>
+__global__ TM_STENCIL_R(NR, R) void k_eo_upd(CgArgs a, EoCg e) {
+    __shared__ double sh[4];
+    const Geom& hg = a.geo;
+    const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
+    const uint32_t nb = bm.nsb;
+    const uint32_t h = bm.sb * 256u + threadIdx.x;
+    const int r0 = bm.ch * NR;
+    const long Vs = hg.Vs;
+    bool act[NR];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        act[r] = a.scal[r0 + r].active != 0;
+        any |= act[r];
+    }
+    if (!any) return;
+    double prr[NR], prho[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) prr[r] = prho[r] = 0;
+    if (h < hg.V) {
+        const EoSite c = eo_coords(hg, h, 1);
+        cx<R> acc[NR][12];
+        eo_hop_all<true, R, S, G, NR>(hg, e.godd, e.geven, field_rhs<S>(e.y, Vs, r0), h, c, acc);
+        const R tw = (R)(-a.twist), k2 = (R)(-a.kappa * a.kappa);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            if (!act[r]) continue;
+            const double alpha = a.scal[r0 + r].alpha;
+            cx<R> tc[12], q[12], rv[12], pv[12];
+            load_spinor<S, R>(field_rhs<S>(a.t, Vs, r0 + r), Vs, h, tc);
+#pragma unroll
+            for (int k = 0; k < 12; k++) q[k] = tc[k];
+            mul_diag(q, tw);
+#pragma unroll
+            for (int k = 0; k < 12; k++) q[k] = q[k] + k2 * acc[r][k];
+            void* rp = field_rhs<S>(a.r, Vs, r0 + r);
+            load_spinor_cp<S, R, TM_CP_K2>(rp, Vs, h, rv);
+            const R al = (R)alpha;
+#pragma unroll
+            for (int k = 0; k < 12; k++) rv[k] = rv[k] - al * q[k];
+            round_storage<S, R>(rv);
+            store_spinor_cp<S, R, TM_CP_K2>(rp, Vs, h, rv);
+            prr[r] = spinor_norm2(rv);
+            load_spinor_cp<S, R, TM_CP_K2>(field_rhs<S>(a.p, Vs, r0 + r), Vs, h, pv);
+            cx<RX> xv[12];
+            void* xp = field_rhs<X>(a.x, Vs, r0 + r);
+            load_spinor_cp<X, RX, TM_CP_K2>(xp, Vs, h, xv);
+            const RX alx = (RX)alpha;
+#pragma unroll
+            for (int k = 0; k < 12; k++) xv[k] = {xv[k].re + alx * (RX)pv[k].re, xv[k].im + alx * (RX)pv[k].im};
+            store_spinor_cp<X, RX, TM_CP_K2>(xp, Vs, h, xv);
+            if (TRACK) {
+                cx<R> rh[12];
+                void* hp = field_rhs<S>(a.rho, Vs, r0 + r);
+                load_spinor_cp<S, R, TM_CP_K2>(hp, Vs, h, rh);
+#pragma unroll
+                for (int k = 0; k < 12; k++) rh[k] = rh[k] - al * tc[k];
+                round_storage<S, R>(rh);
+                store_spinor_cp<S, R, TM_CP_K2>(hp, Vs, h, rh);
+                prho[r] = spinor_norm2(rh);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        double v = block_sum256(prr[r], sh);
+        if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * nb + bm.sb] = v;
+        if (TRACK) {
+            double w = block_sum256(prho[r], sh);
+            if (threadIdx.x == 0) a.partials2[(size_t)(r0 + r) * nb + bm.sb] = w;
+        }
+    }
+}
+
+// Reliable update (gated, FP64): r64 = b64 - (D^dag t64 - kappa^2 H_oe^dag
+// y64) with t64 = Mhat x64 and y64 = D^{-dag} H_eo^dag t64, r32 = r64, block
+// partials of |r64|^2 and (a.eta64 = etahat set) of |etahat - t64|^2
+__global__ TM_STENCIL_R(1, double) void k_eo_rel_resid(CgArgs a, EoCg e, const void* b64, const void* t64,
+                                                      const void* y64) {
+    __shared__ double sh[4];
+    const int r = blockIdx.y;
+    if (!a.scal[r].rflag) return;
+    const Geom& hg = a.geo;
+    const long Vs = hg.Vs;
+    const uint32_t nsb = (uint32_t)((hg.V + 255) / 256);
+    const void* t0 = field_rhs<SF64>(t64, Vs, r);
+    double pr = 0, pt = 0;
+    for (uint32_t sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
+        const uint32_t h = sb * 256u + threadIdx.x;
+        if (h >= hg.V) continue;
+        const EoSite c = eo_coords(hg, h, 1);
+        cx<double> acc[1][12];
+        eo_hop_all<true, double, SF64, GF64, 1>(hg, e.godd, e.geven, field_rhs<SF64>(y64, Vs, r), h, c, acc);
+        cx<double> tc[12], q[12], bv[12];
+        load_spinor<SF64, double>(t0, Vs, h, tc);
+#pragma unroll
+        for (int k = 0; k < 12; k++) q[k] = tc[k];
+        mul_diag(q, -a.twist);
+        const double k2 = -a.kappa * a.kappa;
+        load_spinor<SF64, double>(field_rhs<SF64>(b64, Vs, r), Vs, h, bv);
+        cx<float> rf[12];
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            bv[k] = bv[k] - (q[k] + k2 * acc[0][k]);
+            rf[k] = {(float)bv[k].re, (float)bv[k].im};
+        }
+        store_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r), Vs, h, rf);
+        pr += spinor_norm2(bv);
+        if (a.eta64) {
+            cx<double> ev[12];
+            load_spinor<SF64, double>(field_rhs<SF64>(a.eta64, Vs, r), Vs, h, ev);
+#pragma unroll
+            for (int k = 0; k < 12; k++) ev[k] = ev[k] - tc[k];
+            pt += spinor_norm2(ev);
+        }
+    }
+    double v = block_sum256(pr, sh);
+    if (threadIdx.x == 0) a.partials[(size_t)r * gridDim.x + blockIdx.x] = v;
+    if (a.eta64) {
+        double w = block_sum256(pt, sh);
+        if (threadIdx.x == 0) a.partials2[(size_t)r * gridDim.x + blockIdx.x] = w;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// layout: full native planes <-> the two half layouts (np planes per field
+// block, e.g. S::NV * nrhs for spinors, 12 or 36 for the links)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_eo_split(Geom g, Geom hg, const void* in, int np, void* out_e, void* out_o) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= g.V) return;
+    const Site c = site_coords(g, s);
+    const int par = (c.x + c.y + c.z + c.t) & 1;
+    const uint32_t h = s >> 1;  // (row * Lx + x) / 2 = row * Lx/2 + x/2 (Lx even)
+    void* out = par ? out_o : out_e;
+    for (int k = blockIdx.y; k < np; k += gridDim.y) {
+        const uint4 v = ld_plane<uint4>(in, g.Vs, k, s);
+        st_plane<uint4>(out, hg.Vs, k, h, v);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_eo_merge(Geom g, Geom hg, const void* in_e, const void* in_o, int np,
+                                                  void* out) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    if (s >= g.V) return;
+    const Site c = site_coords(g, s);
+    const int par = (c.x + c.y + c.z + c.t) & 1;
+    const uint32_t h = s >> 1;
+    const void* in = par ? in_o : in_e;
+    for (int k = blockIdx.y; k < np; k += gridDim.y) {
+        const uint4 v = ld_plane<uint4>(in, hg.Vs, k, h);
+        st_plane<uint4>(out, g.Vs, k, s, v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+static inline uint32_t eo_blocks(const Geom& hg) { return (uint32_t)((hg.V + 255) / 256); }
+constexpr uint32_t kEoGatedBlocks = 512;
+
+void launch_eo_split(hipStream_t st, const Geom& g, const Geom& hg, const void* in, int np, void* out_e,
+                     void* out_o) {
+    const unsigned gy = (unsigned)std::min(np, 64);
+    hipLaunchKernelGGL(k_eo_split, dim3((unsigned)((g.V + 255) / 256), gy), dim3(256), 0, st, g, hg, in, np, out_e,
+                       out_o);
+}
+void launch_eo_merge(hipStream_t st, const Geom& g, const Geom& hg, const void* in_e, const void* in_o, int np,
+                     void* out) {
+    const unsigned gy = (unsigned)std::min(np, 64);
+    hipLaunchKernelGGL(k_eo_merge, dim3((unsigned)((g.V + 255) / 256), gy), dim3(256), 0, st, g, hg, in_e, in_o, np,
+                       out);
+}
+
+void launch_eo_dinv(hipStream_t st, const Geom& hg, int prec, double twist, int nrhs, const void* in, void* out) {
+    const dim3 grid(eo_blocks(hg), (unsigned)nrhs);
+    switch (prec) {
+    case P_F64: hipLaunchKernelGGL((k_eo_dinv<double, SF64>), grid, dim3(256), 0, st, hg, twist, nrhs, in, out); break;
+    case P_F32: hipLaunchKernelGGL((k_eo_dinv<float, SF32>), grid, dim3(256), 0, st, hg, twist, nrhs, in, out); break;
+    case P_F16: hipLaunchKernelGGL((k_eo_dinv<float, SF16>), grid, dim3(256), 0, st, hg, twist, nrhs, in, out); break;
+    default: hipLaunchKernelGGL((k_eo_dinv<float, SBF16>), grid, dim3(256), 0, st, hg, twist, nrhs, in, out); break;
+    }
+}
+
+template <bool DAG, bool PRE, bool POST, typename R, class Si, class So, class G>
+static void eo_lin_nr(hipStream_t st, const EoArgs& a, int nr) {
+    const uint32_t nb = eo_blocks(a.hg);
+    if (a.gate != nullptr) {
+        const unsigned gb = std::min(nb, kEoGatedBlocks);
+        hipLaunchKernelGGL((k_eo_lin<DAG, PRE, POST, R, Si, So, G, 1>), dim3(gb * (unsigned)a.nrhs), dim3(256), 0, st,
+                           a);
+        return;
+    }
+    if constexpr (sizeof(R) == 8) nr = 1;
+    switch (nr) {
+    case 4:
+        hipLaunchKernelGGL((k_eo_lin<DAG, PRE, POST, R, Si, So, G, 4>), dim3(nb * (unsigned)(a.nrhs / 4)), dim3(256),
+                           0, st, a);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_eo_lin<DAG, PRE, POST, R, Si, So, G, 2>), dim3(nb * (unsigned)(a.nrhs / 2)), dim3(256),
+                           0, st, a);
+        break;
+    default:
+        hipLaunchKernelGGL((k_eo_lin<DAG, PRE, POST, R, Si, So, G, 1>), dim3(nb * (unsigned)a.nrhs), dim3(256), 0, st,
+                           a);
+        break;
+    }
+}
+
+template <bool DAG, bool PRE, bool POST>
+static void eo_lin_prec(hipStream_t st, const EoArgs& a, int prec, int nr) {
+    switch (prec) {
+    case P_F64: eo_lin_nr<DAG, PRE, POST, double, SF64, SF64, GF64>(st, a, 1); break;
+    case P_F32: eo_lin_nr<DAG, PRE, POST, float, SF32, SF32, GF32>(st, a, nr); break;
+    case P_F16: eo_lin_nr<DAG, PRE, POST, float, SF16, SF16, GF32>(st, a, nr); break;
+    default: eo_lin_nr<DAG, PRE, POST, float, SBF16, SBF16, GF32>(st, a, nr); break;
+    }
+}
+
+void launch_eo_lin(hipStream_t st, const EoArgs& a, int prec, int nr, int kind) {
+    switch (kind) {
+    case EO_Y: eo_lin_prec<false, false, true>(st, a, prec, nr); break;
+    case EO_Y_DAG: eo_lin_prec<true, false, true>(st, a, prec, nr); break;
+    case EO_T: eo_lin_prec<false, true, false>(st, a, prec, nr); break;
+    case EO_T_DAG: eo_lin_prec<true, true, false>(st, a, prec, nr); break;
+    case EO_SRC: eo_lin_prec<false, false, false>(st, a, prec, nr); break;
+    default: eo_lin_prec<false, false, true>(st, a, prec, nr); break;  // EO_REC
+    }
+}
+
+// reconstruction with an FP32 odd half (FP32 output); FP64 runs through launch_eo_lin
+void launch_eo_rec_f32(hipStream_t st, const EoArgs& a, int nr) {
+    eo_lin_nr<false, false, true, float, SF32, SF32, GF32>(st, a, nr);
+}
+
+template <typename R, class S, class G>
+static void eo_mp_typed(hipStream_t st, const CgArgs& a, const EoCg& e, int nr) {
+    const uint32_t nb = eo_blocks(a.geo);
+    if constexpr (sizeof(R) == 8) nr = 1;
+    switch (nr) {
+    case 4: hipLaunchKernelGGL((k_eo_mp<R, S, G, 4>), dim3(nb * (unsigned)(a.nrhs / 4)), dim3(256), 0, st, a, e); break;
+    case 2: hipLaunchKernelGGL((k_eo_mp<R, S, G, 2>), dim3(nb * (unsigned)(a.nrhs / 2)), dim3(256), 0, st, a, e); break;
+    default: hipLaunchKernelGGL((k_eo_mp<R, S, G, 1>), dim3(nb * (unsigned)a.nrhs), dim3(256), 0, st, a, e); break;
+    }
+}
+
+template <typename R, class S, class G, class X, typename RX>
+static void eo_upd_typed(hipStream_t st, const CgArgs& a, const EoCg& e, int nr, bool track) {
+    const uint32_t nb = eo_blocks(a.geo);
+    if (track) {
+        hipLaunchKernelGGL((k_eo_upd<R, S, G, X, RX, 1, true>), dim3(nb * (unsigned)a.nrhs), dim3(256), 0, st, a, e);
+        return;
+    }
+    if constexpr (sizeof(R) == 8) nr = 1;
+    switch (nr) {
+    case 4:
+        hipLaunchKernelGGL((k_eo_upd<R, S, G, X, RX, 4, false>), dim3(nb * (unsigned)(a.nrhs / 4)), dim3(256), 0, st,
+                           a, e);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_eo_upd<R, S, G, X, RX, 2, false>), dim3(nb * (unsigned)(a.nrhs / 2)), dim3(256), 0, st,
+                           a, e);
+        break;
+    default:
+        hipLaunchKernelGGL((k_eo_upd<R, S, G, X, RX, 1, false>), dim3(nb * (unsigned)a.nrhs), dim3(256), 0, st, a, e);
+        break;
+    }
+}
+
+void launch_eo_mp(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr) {
+    switch (prec) {
+    case P_F64: eo_mp_typed<double, SF64, GF64>(st, a, e, 1); break;
+    case P_F32: eo_mp_typed<float, SF32, GF32>(st, a, e, nr); break;
+    case P_F16: eo_mp_typed<float, SF16, GF32>(st, a, e, nr); break;
+    default: eo_mp_typed<float, SBF16, GF32>(st, a, e, nr); break;
+    }
+}
+
+void launch_eo_upd(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr, bool track) {
+    switch (prec) {
+    case P_F64: eo_upd_typed<double, SF64, GF64, SF64, double>(st, a, e, 1, track); break;
+    case P_F32: eo_upd_typed<float, SF32, GF32, SF32, float>(st, a, e, nr, track); break;
+    case P_F16: eo_upd_typed<float, SF16, GF32, SF32, float>(st, a, e, nr, track); break;
+    default: eo_upd_typed<float, SBF16, GF32, SF32, float>(st, a, e, nr, track); break;
+    }
+}
+
+uint32_t eo_gated_blocks(const Geom& hg) { return std::min(eo_blocks(hg), kEoGatedBlocks); }
+
+void launch_eo_rel_resid(hipStream_t st, const CgArgs& a, const EoCg& e, const void* b64, const void* t64,
+                         const void* y64) {
+    const uint32_t nb = eo_gated_blocks(a.geo);
+    hipLaunchKernelGGL(k_eo_rel_resid, dim3(nb, (unsigned)a.nrhs), dim3(256), 0, st, a, e, b64, t64, y64);
+}
+
+}  // namespace tmq

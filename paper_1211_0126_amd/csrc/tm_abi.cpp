@@ -295,6 +295,25 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
         }
         g.m[d] = (uint32_t)m;
     }
+    // even-odd half geometry: planes of V/2 sites with their own stride, and
+    // division by Lx/2 for the half index (exact for every n < V/2)
+    ctx->eo_ok = (g.L[0] % 2 == 0) && (g.L[1] % 2 == 0) && (g.L[2] % 2 == 0) && (g.L[3] % 2 == 0);
+    if (ctx->eo_ok) {
+        Geom& h = ctx->hgeo;
+        h = g;
+        h.V = V / 2;
+        h.Vs = (h.V + 255) / 256 * 256;
+        if ((h.Vs / 256) % 2 == 0) h.Vs += 256;
+        const uint64_t dd = (uint64_t)(g.L[0] / 2);
+        const uint64_t m = ((1ULL << 32) + dd - 1) / dd;
+        const uint64_t e = m * dd - (1ULL << 32);
+        if (dd == 1)
+            h.m[0] = 0;  // Lx = 2: the half index is the row
+        else if ((uint64_t)h.V * e >= (1ULL << 32))
+            ctx->eo_ok = false;
+        else
+            h.m[0] = (uint32_t)m;
+    }
     ctx->twist = 2.0 * lat->kappa * lat->mu;
     hipError_t e = hipGetDevice(&ctx->device);
     if (e != hipSuccess) {
@@ -333,6 +352,10 @@ tm_status tm_destroy(tm_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto& kv : ctx->ws)
         if (kv.second.p) (void)hipFree(kv.second.p);
+    for (int q = 0; q < 2; q++) {
+        if (ctx->gauge32eo[q]) (void)hipFree(ctx->gauge32eo[q]);
+        if (ctx->gauge64eo[q]) (void)hipFree(ctx->gauge64eo[q]);
+    }
     if (ctx->gauge64) (void)hipFree(ctx->gauge64);
     if (ctx->gauge32) (void)hipFree(ctx->gauge32);
     if (ctx->gaugebf) (void)hipFree(ctx->gaugebf);
@@ -361,6 +384,18 @@ tm_status tm_gauge_load(tm_ctx* ctx, const double* links_host) {
     if (e == hipSuccess) {
         launch_gauge_convert(ctx->stream, g, (const double*)tmp, ctx->gauge64, ctx->gauge32, ctx->gaugebf);
         e = hipGetLastError();
+    }
+    if (e == hipSuccess && ctx->eo_ok) {
+        const Geom& h = ctx->hgeo;
+        for (int q = 0; q < 2 && e == hipSuccess; q++) {
+            if (!ctx->gauge32eo[q]) e = hipMalloc(&ctx->gauge32eo[q], (size_t)4 * 3 * 16 * h.Vs);
+            if (e == hipSuccess && !ctx->gauge64eo[q]) e = hipMalloc(&ctx->gauge64eo[q], (size_t)4 * 9 * 16 * h.Vs);
+        }
+        if (e == hipSuccess) {
+            launch_eo_split(ctx->stream, g, h, ctx->gauge32, 12, ctx->gauge32eo[0], ctx->gauge32eo[1]);
+            launch_eo_split(ctx->stream, g, h, ctx->gauge64, 36, ctx->gauge64eo[0], ctx->gauge64eo[1]);
+            e = hipGetLastError();
+        }
     }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     (void)hipFree(tmp);

@@ -23,6 +23,14 @@ struct tm_ctx {
     void* gaugebf = nullptr;  // uint4   [4][3][Vs]: bfloat16 (re, im) pairs of the 9 entries, for the network
     bool gauge_loaded = false;
 
+    // even-odd form (every extent even): the half geometry (V = sites of one
+    // parity, Vs their plane stride, m[0] divides by Lx/2) and the links split
+    // by parity, each copy holding the forward links of its sites
+    bool eo_ok = false;
+    tmq::Geom hgeo;
+    void* gauge32eo[2] = {nullptr, nullptr};  // float4  [4][3][Vhs] per parity
+    void* gauge64eo[2] = {nullptr, nullptr};  // double2 [4][9][Vhs] per parity
+
     struct Buf {
         void* p = nullptr;
         size_t bytes = 0;

@@ -101,6 +101,43 @@ int pt_chunks(const Geom& g);
 void launch_make_pair(hipStream_t st, const Geom& g, uint64_t seed_mixed, const uint64_t* id, const void* xk,
                       const void* xstar, const void* mxk, void* r_out, void* e_out);
 
+// even-odd (Schur complement) kernels on half fields (hg: half geometry,
+// V = sites of one parity, Vs their plane stride, L the full extents)
+struct EoArgs {
+    Geom hg;
+    const void* gout;   // links of the output parity (native half layout)
+    const void* gin;    // links of the input parity
+    int pout;           // parity of the output sites
+    double kappa, twist;
+    const void* in;     // hop input (parity 1 - pout)
+    void* out;
+    const void* b;      // centre term (parity pout) or nullptr
+    double c;           // coefficient of the hop
+    int bnoise;         // 1: the centre term is the Z4 source of the output site
+    uint64_t seed_mixed;
+    const uint64_t* ids;
+    const CgScal* gate; // nullable: only right-hand sides with the reliable flag
+    int nrhs;
+};
+struct EoCg {
+    const void* geven;  // links of the even sites
+    const void* godd;   // links of the odd sites
+    const void* y;      // intermediate even half field
+};
+// kinds of launch_eo_lin: out = POST(PRE(b) + c H in)
+enum { EO_Y = 0, EO_Y_DAG = 1, EO_T = 2, EO_T_DAG = 3, EO_SRC = 4, EO_REC = 5 };
+void launch_eo_lin(hipStream_t st, const EoArgs& a, int prec, int nr, int kind);
+void launch_eo_rec_f32(hipStream_t st, const EoArgs& a, int nr);
+void launch_eo_dinv(hipStream_t st, const Geom& hg, int prec, double twist, int nrhs, const void* in, void* out);
+void launch_eo_mp(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr);
+void launch_eo_upd(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr, bool track);
+uint32_t eo_gated_blocks(const Geom& hg);
+void launch_eo_rel_resid(hipStream_t st, const CgArgs& a, const EoCg& e, const void* b64, const void* t64,
+                         const void* y64);
+void launch_eo_split(hipStream_t st, const Geom& g, const Geom& hg, const void* in, int np, void* out_e, void* out_o);
+void launch_eo_merge(hipStream_t st, const Geom& g, const Geom& hg, const void* in_e, const void* in_o, int np,
+                     void* out);
+
 // operator
 void launch_apply(hipStream_t st, const Geom& g, int prec, const void* gauge, double kappa, double twist, int op,
                   int nrhs, const void* in, void* out, int nr, const CgScal* gate);
@@ -110,7 +147,8 @@ void launch_apply_f32in_f64(hipStream_t st, const Geom& g, const void* gauge64, 
 // CG
 void launch_scal_init(hipStream_t st, CgScal* sc, int n, double tol2, int maxit, int stop, int reliable,
                       double delta2);
-void launch_cg_init(hipStream_t st, const CgArgs& a, int prec, bool track, const void* eta);
+// ee_z4 > 0: |eta|^2 of every source (12 V of a Z4 source); else measured from eta
+void launch_cg_init(hipStream_t st, const CgArgs& a, int prec, bool track, const void* eta, double ee_z4 = -1.0);
 void launch_cg_mp(hipStream_t st, const CgArgs& a, int prec, int nr);
 void launch_cg_upd(hipStream_t st, const CgArgs& a, int prec, int nr, bool track);
 // time-marching K1 / K2 (a.tseg time slices per lane); they write
@@ -121,7 +159,8 @@ void launch_tm_upd(hipStream_t st, const CgArgs& a, int prec, int nr, bool track
 void launch_cg_alpha(hipStream_t st, const CgArgs& a);              // after launch_cg_mp
 void launch_cg_beta(hipStream_t st, const CgArgs& a, bool track);   // after launch_cg_upd
 void launch_cg_p(hipStream_t st, const CgArgs& a, int prec);
-void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64);
+void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64, double ee_z4 = -1.0);
+void launch_rel_fin(hipStream_t st, const CgArgs& a, uint32_t nb);
 void launch_rel_flush(hipStream_t st, const CgArgs& a, void* x64, int force);
 void launch_rel_resid(hipStream_t st, const CgArgs& a, const void* gauge64, const void* b64, const void* t64);
 void launch_true_resid(hipStream_t st, const CgArgs& a, int xprec, const void* gauge64, uint64_t seed_mixed,

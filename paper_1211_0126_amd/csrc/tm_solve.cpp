@@ -26,8 +26,10 @@ static const int kIterCap = 20000;  // safety cap for max_iter = -1
 static tm_status check_solve_params(tm_ctx* ctx, const tsm_solve_params* p) {
     if (!p) return set_error(ctx, TM_EINVAL, "null solve parameters");
     if (p->prec < 0 || p->prec > 3) return set_error(ctx, TM_EINVAL, "solve: bad precision");
-    if (p->solver != TM_SOLVER_CG && p->solver != TM_SOLVER_FCG_LEARNED)
+    if (p->solver != TM_SOLVER_CG && p->solver != TM_SOLVER_FCG_LEARNED && p->solver != TM_SOLVER_CG_EO)
         return set_error(ctx, TM_EINVAL, "solve: unknown solver");
+    if (p->solver == TM_SOLVER_CG_EO && !ctx->eo_ok)
+        return set_error(ctx, TM_ENOTSUP, "solve: the even-odd solver needs every lattice extent even");
     if (p->solver == TM_SOLVER_FCG_LEARNED) {
         if (p->prec != TM_PREC_F32 || p->reliable || p->stop != TM_STOP_NORMAL)
             return set_error(ctx, TM_ENOTSUP, "solve: flexible CG runs FP32 vectors, normal-equation stop, no reliable updates");
@@ -283,12 +285,271 @@ tm_status solve_f64_history(tm_ctx* ctx, uint64_t seed_mixed, const uint64_t* id
     return TM_OK;
 }
 
+// Bytes of the even-odd CG kernels per launch (algorithmic, per half site:
+// each field touched once, every link once per half-hop)
+struct EoBytes {
+    double hop, mp, upd, p;
+};
+static EoBytes eo_bytes(const Geom& hg, int prec, int nrhs, bool track) {
+    const double bs = prec == P_F64 ? 8 : (prec == P_F32 ? 4 : 2);
+    const double bx = prec == P_F64 ? 8 : 4;
+    const double gb = prec == P_F64 ? 8 * 18 * 8 : 8 * 12 * 4;
+    const double V = (double)hg.V;
+    EoBytes b;
+    b.hop = V * (nrhs * 48.0 * bs + gb);
+    b.mp = V * (nrhs * 72.0 * bs + gb);
+    b.upd = V * (nrhs * (120.0 * bs + 48.0 * bx + (track ? 48.0 * bs : 0.0)) + gb);
+    b.p = V * nrhs * 72.0 * bs;
+    return b;
+}
+
+// CG on the normal equations of the even-odd Schur complement (solver
+// TM_SOLVER_CG_EO): the odd-site source etahat = eta_o + kappa H_oe D^{-1}
+// eta_e and b = Mhat^dag etahat, the CG chunks on half fields (four
+// half-hops per iteration), then x_e = D^{-1} (eta_e + kappa H_eo x_o) and
+// the full native solution in res.  Reliable updates recompute
+// r = b - Mhat^dag Mhat x in FP64 on the half lattice.
+static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t seed_mixed,
+                                const uint64_t* ids_dev, int nrhs, int nr, const std::string& tag,
+                                BlockResult* res) {
+    const Geom& g = ctx->geo;
+    const Geom& hg = ctx->hgeo;
+    hipStream_t st = ctx->stream;
+    tm_status s = TM_OK;
+    const int prec = p->prec;
+    const bool rel = p->reliable != 0;
+    const bool track = p->stop == TM_STOP_TRUE && !rel;
+    const int xprec = prec == P_F64 ? P_F64 : P_F32;
+    const int nv = prec == P_F64 ? 12 : (prec == P_F32 ? 6 : 3);
+    const size_t nblk_full = (size_t)((g.V + 255) / 256);
+    const uint32_t nblk = (uint32_t)((hg.V + 255) / 256);
+    const size_t fbh = field_bytes(hg, prec, nrhs);
+    const double kappa = ctx->lat.kappa, tw = ctx->twist;
+    const double ee_z4 = 12.0 * (double)g.V;
+
+    CgArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.geo = hg;
+    a.kappa = kappa;
+    a.twist = tw;
+    a.nrhs = nrhs;
+    a.npart = nblk;
+    a.p = ws_get(ctx, tag + "_eo_p", fbh, &s);
+    a.t = ws_get(ctx, tag + "_eo_t", fbh, &s);
+    a.r = ws_get(ctx, tag + "_eo_r", fbh, &s);
+    a.x = ws_get(ctx, tag + "_eo_x", field_bytes(hg, xprec, nrhs), &s);
+    void* y = ws_get(ctx, tag + "_eo_y", fbh, &s);
+    a.scal = (CgScal*)ws_get(ctx, tag + "_scal", sizeof(CgScal) * kMaxBlock, &s);
+    a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * nblk_full * kMaxBlock, &s);
+    a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * nblk_full * kMaxBlock, &s);
+    if (track) a.rho = ws_get(ctx, tag + "_eo_rho", fbh, &s);
+    // the full solution handed to the contraction
+    const int fprec = rel ? P_F64 : xprec;
+    void* xfull = ws_get(ctx, tag + "_eo_xfull", field_bytes(g, fprec, nrhs), &s);
+    void* xe = ws_get(ctx, tag + "_eo_xe", field_bytes(hg, fprec, nrhs), &s);
+    // source preparation at the iteration precision (FP64 with reliable updates)
+    const int sp = rel ? P_F64 : prec;
+    const int snv = rel ? 12 : nv;
+    void* etaf = ws_get(ctx, tag + "_eo_etaf", field_bytes(g, sp, nrhs), &s);
+    void* eta_e = ws_get(ctx, tag + "_eo_etae", field_bytes(hg, sp, nrhs), &s);
+    void* eta_o = ws_get(ctx, tag + "_eo_etao", field_bytes(hg, sp, nrhs), &s);
+    void* eh = ws_get(ctx, tag + "_eo_eh", field_bytes(hg, sp, nrhs), &s);
+    void *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *y64 = nullptr;
+    if (rel) {
+        b64 = ws_get(ctx, tag + "_eo_b64", field_bytes(hg, P_F64, nrhs), &s);
+        x64 = ws_get(ctx, tag + "_eo_x64", field_bytes(hg, P_F64, nrhs), &s);
+        t64 = ws_get(ctx, tag + "_eo_t64", field_bytes(hg, P_F64, nrhs), &s);
+        y64 = ws_get(ctx, tag + "_eo_y64", field_bytes(hg, P_F64, nrhs), &s);
+    }
+    if (s != TM_OK) return s;
+    if ((s = ensure_scal_host(ctx, nrhs)) != TM_OK) return s;
+
+    const void* g32e = ctx->gauge32eo[0];
+    const void* g32o = ctx->gauge32eo[1];
+    const void* g64e = ctx->gauge64eo[0];
+    const void* g64o = ctx->gauge64eo[1];
+    const void* ge = prec == P_F64 ? g64e : g32e;
+    const void* go = prec == P_F64 ? g64o : g32o;
+    // half-hop arguments: output parity q, input field, output field
+    auto lin = [&](int q, bool f64, const void* in, void* out, const void* b, double c, int n) {
+        EoArgs e;
+        std::memset(&e, 0, sizeof(e));
+        e.hg = hg;
+        e.gout = q == 0 ? (f64 ? g64e : ge) : (f64 ? g64o : go);
+        e.gin = q == 0 ? (f64 ? g64o : go) : (f64 ? g64e : ge);
+        e.pout = q;
+        e.kappa = kappa;
+        e.twist = tw;
+        e.in = in;
+        e.out = out;
+        e.b = b;
+        e.c = c;
+        e.seed_mixed = seed_mixed;
+        e.ids = ids_dev;
+        e.nrhs = n;
+        return e;
+    };
+    const double k2 = -kappa * kappa;
+
+    launch_scal_init(st, a.scal, nrhs, p->tol * p->tol, p->max_iter, p->stop, rel ? 1 : 0,
+                     rel ? p->delta * p->delta : 0.0);
+    // sources: eta split by parity, etahat = eta_o + kappa H_oe D^{-1} eta_e,
+    // b = Mhat^dag etahat = D^dag etahat - kappa^2 H_oe^dag D^{-dag} H_eo^dag etahat
+    prof_begin(ctx, TM_KC_OTHER);
+    launch_noise_native(st, g, sp, seed_mixed, ids_dev, nrhs, etaf);
+    launch_eo_split(st, g, hg, etaf, snv * nrhs, eta_e, eta_o);
+    void* ys = rel ? y64 : y;
+    launch_eo_dinv(st, hg, sp, tw, nrhs, eta_e, ys);
+    launch_eo_lin(st, lin(1, rel, ys, eh, eta_o, kappa, nrhs), sp, 1, EO_SRC);
+    launch_eo_lin(st, lin(0, rel, eh, ys, nullptr, 1.0, nrhs), sp, 1, EO_Y_DAG);
+    if (rel) {
+        launch_eo_lin(st, lin(1, true, ys, b64, eh, k2, nrhs), P_F64, 1, EO_T_DAG);
+        if (p->stop == TM_STOP_TRUE) a.eta64 = eh;
+        launch_rel_init(st, a, b64, x64, ee_z4);
+    } else {
+        launch_eo_lin(st, lin(1, false, ys, a.r, eh, k2, nrhs), prec, 1, EO_T_DAG);
+        launch_cg_init(st, a, prec, track, eh, ee_z4);
+    }
+    prof_end(ctx, TM_KC_OTHER, 0.0);
+    TM_HIP(hipGetLastError());
+
+    EoCg ec;
+    ec.geven = ge;
+    ec.godd = go;
+    ec.y = y;
+    EoCg ec64;
+    ec64.geven = g64e;
+    ec64.godd = g64o;
+    ec64.y = y64;
+    const EoBytes by = eo_bytes(hg, prec, nrhs, track);
+    const int vtag = prof_tag(prec, prec == P_F64 ? 1 : nr, TM_SOLVER_CG_EO, 0);
+    const int chunk = rel ? 16 : 8;
+    int done = 0;
+    for (;;) {
+        int k = chunk;
+        if (p->max_iter >= 0) k = std::max(1, std::min(chunk, p->max_iter - done));
+        auto steps = [&](int n) {
+            for (int i = 0; i < n; i++) {
+                prof_begin(ctx, TM_KC_EO_HOP, vtag);
+                launch_eo_lin(st, lin(0, false, a.p, y, nullptr, 1.0, nrhs), prec, nr, EO_Y);
+                prof_end(ctx, TM_KC_EO_HOP, by.hop);
+                prof_begin(ctx, TM_KC_DSLASH, vtag);
+                launch_eo_mp(st, a, ec, prec, nr);
+                prof_end(ctx, TM_KC_DSLASH, by.mp);
+                prof_begin(ctx, TM_KC_OTHER);
+                launch_cg_alpha(st, a);
+                prof_end(ctx, TM_KC_OTHER, 0.0);
+                prof_begin(ctx, TM_KC_EO_HOP_DAG, vtag);
+                launch_eo_lin(st, lin(0, false, a.t, y, nullptr, 1.0, nrhs), prec, nr, EO_Y_DAG);
+                prof_end(ctx, TM_KC_EO_HOP_DAG, by.hop);
+                const int utag = track ? prof_tag(prec, 1, TM_SOLVER_CG_EO, 0) : vtag;
+                prof_begin(ctx, TM_KC_DSLASH_UPD, utag);
+                launch_eo_upd(st, a, ec, prec, track ? 1 : nr, track);
+                prof_end(ctx, TM_KC_DSLASH_UPD, by.upd);
+                prof_begin(ctx, TM_KC_OTHER);
+                launch_cg_beta(st, a, track);
+                prof_end(ctx, TM_KC_OTHER, 0.0);
+                if (rel) {
+                    // gated on the reliable flag: x64 += x, t64 = Mhat x64,
+                    // r = b64 - Mhat^dag t64
+                    prof_begin(ctx, TM_KC_OTHER);
+                    launch_rel_flush(st, a, x64, 0);
+                    EoArgs e1 = lin(0, true, x64, y64, nullptr, 1.0, nrhs);
+                    e1.gate = a.scal;
+                    launch_eo_lin(st, e1, P_F64, 1, EO_Y);
+                    EoArgs e2 = lin(1, true, y64, t64, x64, k2, nrhs);
+                    e2.gate = a.scal;
+                    launch_eo_lin(st, e2, P_F64, 1, EO_T);
+                    EoArgs e3 = lin(0, true, t64, y64, nullptr, 1.0, nrhs);
+                    e3.gate = a.scal;
+                    launch_eo_lin(st, e3, P_F64, 1, EO_Y_DAG);
+                    launch_eo_rel_resid(st, a, ec64, b64, t64, y64);
+                    launch_rel_fin(st, a, eo_gated_blocks(hg));
+                    prof_end(ctx, TM_KC_OTHER, 0.0);
+                }
+                prof_begin(ctx, TM_KC_BLAS, prof_tag(prec, 1, TM_SOLVER_CG_EO));
+                launch_cg_p(st, a, prec);
+                prof_end(ctx, TM_KC_BLAS, by.p);
+            }
+        };
+        if (ctx->use_graphs && !ctx->prof && st != nullptr) {
+            char key[512];
+            std::snprintf(key, sizeof(key), "eo|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%d",
+                          a.p, a.t, a.r, a.x, y, a.rho, (void*)a.scal, (void*)a.partials, (void*)a.partials2,
+                          x64, t64, b64, y64, prec, nr, (int)track, (int)rel, nrhs, k);
+            auto it = ctx->graphs.find(key);
+            if (it == ctx->graphs.end()) {
+                hipGraph_t graph;
+                TM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                steps(k);
+                hipError_t ce = hipStreamEndCapture(st, &graph);
+                if (ce != hipSuccess) return dev_error(ctx, ce, "hipStreamEndCapture");
+                hipGraphExec_t exec;
+                ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ce != hipSuccess) return dev_error(ctx, ce, "hipGraphInstantiate");
+                it = ctx->graphs.emplace(key, exec).first;
+            }
+            TM_HIP(hipGraphLaunch(it->second, st));
+            ctx->graph_launches++;
+        } else {
+            steps(k);
+        }
+        TM_HIP(hipGetLastError());
+        done += k;
+        TM_HIP(hipMemcpyAsync(ctx->scal_host, a.scal, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        bool any = false;
+        for (int r = 0; r < nrhs; r++) any |= ctx->scal_host[r].active != 0;
+        if (!any) break;
+        if (done >= kIterCap) break;
+    }
+
+    // even half x_e = D^{-1} (eta_e + kappa H_eo x_o) with eta_e from the
+    // hash, then the full native solution
+    prof_begin(ctx, TM_KC_OTHER);
+    if (rel) {
+        launch_rel_flush(st, a, x64, 1);
+        EoArgs e = lin(0, true, x64, xe, nullptr, kappa, nrhs);
+        e.bnoise = 1;
+        launch_eo_lin(st, e, P_F64, 1, EO_REC);
+        launch_eo_merge(st, g, hg, xe, x64, 12 * nrhs, xfull);
+    } else {
+        EoArgs e = lin(0, prec == P_F64, a.x, xe, nullptr, kappa, nrhs);
+        e.bnoise = 1;
+        if (prec == P_F64) {
+            launch_eo_lin(st, e, P_F64, 1, EO_REC);
+        } else {
+            e.gout = g32e;
+            e.gin = g32o;
+            launch_eo_rec_f32(st, e, 1);
+        }
+        launch_eo_merge(st, g, hg, xe, a.x, (xprec == P_F64 ? 12 : 6) * nrhs, xfull);
+    }
+    prof_end(ctx, TM_KC_OTHER, 0.0);
+    res->x = xfull;
+    res->xprec = fprec;
+    if (p->true_resid) {
+        CgArgs at = a;
+        at.geo = g;
+        at.x = xfull;
+        prof_begin(ctx, TM_KC_OTHER);
+        launch_true_resid(st, at, fprec, ctx->gauge64, seed_mixed, ids_dev);
+        prof_end(ctx, TM_KC_OTHER, (double)g.V * (nrhs * 24.0 * (fprec == P_F64 ? 8 : 4) + 4 * 18 * 8.0));
+    }
+    TM_HIP(hipGetLastError());
+    TM_HIP(hipMemcpyAsync(ctx->scal_host, a.scal, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    return TM_OK;
+}
+
 // Solve nrhs sources (ids on the device) with the given settings.  On
 // return the stream is synchronised, ctx->scal_host[0..nrhs) holds the final
 // per-source state and res the native solutions.
 static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t seed_mixed, const uint64_t* ids_dev,
                              int nrhs, int nr, const std::string& tag, BlockResult* res) {
     if (p->solver == TM_SOLVER_FCG_LEARNED) return solve_block_fcg(ctx, p, seed_mixed, ids_dev, nrhs, nr, tag, res);
+    if (p->solver == TM_SOLVER_CG_EO) return solve_block_eo(ctx, p, seed_mixed, ids_dev, nrhs, nr, tag, res);
     const Geom& g = ctx->geo;
     hipStream_t st = ctx->stream;
     tm_status s = TM_OK;
