@@ -37,8 +37,9 @@ METRIC = "LP TSM sources/s + Dslash HBM GB/s, learned/mixed vs plain CG at equal
 HBM_PEAK_GBS = 8000.0
 PREC_NAMES = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 KERNEL_OF = {"dslash": "k_cg_mp", "dslash_upd": "k_cg_upd", "blas": "k_cg_p", "contract": "k_contract",
-             "other": "init/residual", "apply": "k_apply"}
+             "other": "init/residual", "apply": "k_apply", "eo_hop": "k_eo_lin", "eo_hop_dag": "k_eo_lin_dag"}
 MARCH_OF = {"k_cg_mp": "k_tm_mp", "k_cg_upd": "k_tm_upd"}
+EO_OF = {"k_cg_mp": "k_eo_mp", "k_cg_upd": "k_eo_upd"}
 
 
 def parse():
@@ -48,6 +49,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--lp-prec", default="f16", choices=list(PREC_NAMES))
+    ap.add_argument("--solver", default="eo", choices=["eo", "full"],
+                    help="CG on the even-odd Schur complement (eo) or on M^dag M of the whole lattice (full), "
+                         "for the LP and the HP solves")
     ap.add_argument("--lp-block", type=int, default=0,
                     help="LP sources per solver block (default: autotune over 8, 16, 32)")
     ap.add_argument("--hp-block", type=int, default=0,
@@ -69,7 +73,10 @@ def parse():
     ap.add_argument("--lp-true-resid", action="store_true",
                     help="also compute the FP64 true residual of every LP solve inside the timed step")
     ap.add_argument("--lp-config", default=None, metavar="NR,TSEG",
-                    help="fix the LP kernels' right-hand sides per lane and time slices per lane (default: autotune)")
+                    help="fix the LP kernels' right-hand sides per lane and time slices per lane, or with the "
+                         "even-odd solver LDS tiles 0/1 (default: autotune)")
+    ap.add_argument("--no-tune-cache", action="store_true",
+                    help="measure the kernel traversal even if the tuning cache holds a choice (and do not record it)")
     ap.add_argument("--hp-config", default=None, metavar="NR,TSEG", help="same for the HP kernels")
     ap.add_argument("--error-lp", type=int, default=128,
                     help="LP sources of the per-loop error report against an FP64 run of the same sources "
@@ -113,6 +120,8 @@ def kname(v):
     k = KERNEL_OF[v["kc"]]
     if v.get("solver") == 1:
         return k.replace("k_cg_", "k_fcg_")
+    if v.get("solver") == 2:
+        return EO_OF.get(k, k)
     return MARCH_OF.get(k, k) if v.get("tseg", 0) > 0 else k
 
 
@@ -187,48 +196,51 @@ def main():
     del U
     mom = wl.momenta()
     lp_prec = PREC_NAMES[args.lp_prec]
+    from paper_1211_0126_amd import tuning_cache
+    solver = tq.SOLVER_CG_EO if args.solver == "eo" else tq.SOLVER_CG
     tune = {}
     n_lp0 = args.n_lp if args.n_lp is not None else wl.n_lp
     n_hp0 = args.n_hp if args.n_hp is not None else wl.n_hp
     # block candidates and the block used with a fixed kernel configuration
     for role, prec, blk, fixed, cands, dflt, nsrc in (
-            ("lp", lp_prec, args.lp_block, args.lp_config, (8, 16, 32), 16, n_lp0),
+            ("lp", lp_prec, args.lp_block, args.lp_config, (4, 8, 16, 32), 16, n_lp0),
             ("hp", tq.PREC_F32, args.hp_block, args.hp_config, (8, 16), 8, n_hp0)):
         name = [k for k, v in PREC_NAMES.items() if v == prec][0]
         blocks = [blk] if blk else ([b for b in cands if b <= max(nsrc, 1)] or [cands[0]])
         if fixed:
+            # NR,TSEG (CG on M^dag M) or NR,TILES (even-odd)
             nr, ts = (int(v) for v in fixed.split(","))
-            tq.tm_set_lane_rhs(ctx, prec, nr)
-            tq.tm_set_march(ctx, prec, ts)
+            tuning_cache.apply(ctx, prec, solver, {"lane_rhs": nr, "tseg": ts, "tiles": ts})
             tune[role] = {"storage": name, "rhs_block": blk or dflt, "lane_rhs": nr, "tseg": ts, "fixed": True}
             continue
         # per block size: the best (right-hand sides per lane, time slices
         # per lane); keep the block with the lowest time per source-iteration
+        # (the choice is kept in the persisted tuning cache of the package)
         best = None
         per_block = {}
         for b in blocks:
-            nr, ts, ms = tq.tm_autotune_cg(ctx, prec, b)
-            per_source = ms[(nr, ts)] / b
-            per_block[b] = {"lane_rhs": nr, "tseg": ts, "ms_per_source_iteration": round(per_source, 5),
-                            "ms_per_cg_iteration": {"%d,%d" % c: round(m, 4) for c, m in ms.items()}}
-            if best is None or per_source < best[3]:
-                best = (b, nr, ts, per_source)
-        b, nr, ts, _ = best
-        tq.tm_set_lane_rhs(ctx, prec, nr)
-        tq.tm_set_march(ctx, prec, ts)
-        tune[role] = {"storage": name, "rhs_block": b, "lane_rhs": nr, "tseg": ts, "candidates": per_block}
+            rec = tuning_cache.tune(ctx, prec, solver, b, use_cache=not args.no_tune_cache)
+            per_source = rec["ms_per_cg_iteration"] / b
+            per_block[b] = dict(rec, ms_per_source_iteration=round(per_source, 5))
+            if best is None or per_source < best[1]:
+                best = (b, per_source, rec)
+        b, _, rec = best
+        tuning_cache.apply(ctx, prec, solver, rec)
+        tune[role] = {"storage": name, "rhs_block": b, "lane_rhs": rec["lane_rhs"], "tseg": rec.get("tseg", 0),
+                      "tiles": rec.get("tiles", 0), "candidates": per_block}
     args.lp_block = tune["lp"]["rhs_block"]
     args.hp_block = tune["hp"]["rhs_block"]
     log("autotune: %s" % tune)
     # The LP true residual is a diagnostic outside the method (the estimator
     # uses the truncated solutions as they are); it is measured on the same
     # LP configuration in the equal-residual comparison after the timed steps.
+    args.solver_id = solver
     lp = tq.solve_params(prec=lp_prec, tol=wl.lp_tol, max_iter=wl.lp_maxit, rhs_block=args.lp_block,
-                         true_resid=int(args.lp_true_resid))
+                         true_resid=int(args.lp_true_resid), solver=solver)
     # HP: FP32 iterations with FP64 reliable updates, stopped on the FP64
     # true residual |eta - M s| / |eta| (taken at the reliable updates)
     hp = tq.solve_params(prec=tq.PREC_F32, tol=wl.hp_tol, max_iter=-1, reliable=1, delta=0.1,
-                         rhs_block=args.hp_block, true_resid=1, stop=tq.STOP_TRUE)
+                         rhs_block=args.hp_block, true_resid=1, stop=tq.STOP_TRUE, solver=solver)
 
     def step():
         return tq.tsm_loops(ctx, wl.noise_seed, n_hp, n_lp, lp, hp, mom, stats=True)
@@ -269,7 +281,12 @@ def main():
 
     # dominant kernel: the variant (class, storage, RHS per lane, solver) with
     # the largest total time; it is one compiled kernel in the rocprofv3 trace
-    d = max((v for v in variants if v["bytes"] > 0), key=lambda v: v["ms"])
+    # (classes without a variant, such as the contraction, span several kernels)
+    for v in sorted(variants, key=lambda v: -v["ms"]):
+        log("profiled %-10s prec %2d nr %2d solver %2d tseg %2d: %6d launches, %9.1f ms, avg %8.1f us"
+            % (v["kc"], v["prec"], v["lane_rhs"], v["solver"], v["tseg"], v["launches"], v["ms"],
+               1e3 * v["ms"] / max(v["launches"], 1)))
+    d = max((v for v in variants if v["bytes"] > 0 and v["prec"] >= 0), key=lambda v: v["ms"])
     avg_ms = d["ms"] / max(d["launches"], 1)
     avg_bytes = d["bytes"] / max(d["launches"], 1)
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
@@ -312,6 +329,7 @@ def main():
             "lattice": "x".join(str(d) for d in wl.dims),
             "n_hp": n_hp, "n_lp": n_lp, "lp_storage": args.lp_prec, "lp_rhs_block": args.lp_block,
             "hp_rhs_block": args.hp_block,
+            "solver": "CG on the even-odd Schur complement" if args.solver == "eo" else "CG on M^dag M",
         },
         "autotune": tune,
         "graph_replays_timed": graph_replays,
@@ -375,7 +393,8 @@ def loop_errors(args, tq, ctx, wl, lp, hp, mom):
     real and imaginary parts separately."""
     n_lp = wl.n_lp if args.error_lp < 0 else min(args.error_lp, wl.n_lp)
     n_hp = wl.n_hp if args.error_hp < 0 else min(args.error_hp, wl.n_hp)
-    lp64 = tq.solve_params(prec=tq.PREC_F64, tol=lp.tol, max_iter=lp.max_iter, rhs_block=8, true_resid=0)
+    lp64 = tq.solve_params(prec=tq.PREC_F64, tol=lp.tol, max_iter=lp.max_iter, rhs_block=8, true_resid=0,
+                           solver=lp.solver)
     log("loop error report: N_HP %d, N_LP %d" % (n_hp, n_lp))
     a = tq.tsm_loops(ctx, wl.noise_seed, n_hp, n_lp, lp, hp, mom, per_source=True, stats=True)
     b = tq.tsm_loops(ctx, wl.noise_seed, n_hp, n_lp, lp64, hp, mom, per_source=True, stats=True)
@@ -453,10 +472,11 @@ def compare(args, tq, torch, ctx, wl, n_hp, lp_prec):
     log("plain FP32 1-RHS CG: %.2f sources/s, true residual %.4g" % (ns / t_ref, target))
 
     def mk_batched(tol):
-        return tq.solve_params(prec=lp_prec, tol=tol, max_iter=-1, rhs_block=args.lp_block, true_resid=1)
+        return tq.solve_params(prec=lp_prec, tol=tol, max_iter=-1, rhs_block=args.lp_block, true_resid=1,
+                               solver=args.solver_id)
     tol_b, _ = calibrate(tq, ctx, mk_batched, wl.noise_seed, cal_ids, target, wl.lp_tol)
     t_b, st_b = timed_solve(tq, torch, ctx, mk_batched(tol_b), wl.noise_seed, ids)
-    res["batched_mixed"] = {"storage": args.lp_prec, "rhs_block": args.lp_block, "tol": tol_b,
+    res["batched_mixed"] = {"storage": args.lp_prec, "rhs_block": args.lp_block, "solver": args.solver, "tol": tol_b,
                             "sources_per_s": round(ns / t_b, 2),
                             "iters_mean": float(np.mean([s["iters"] for s in st_b])),
                             "true_resid_median": median_true(st_b), "speedup": round(t_ref / t_b, 3)}

@@ -425,6 +425,19 @@ tm_status tm_autotune(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_nr,
 tm_status tm_autotune_cg(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_nr, int32_t* best_tseg,
                          double* ms_host);
 
+/* Autotuner for the even-odd solver (TM_SOLVER_CG_EO) in storage precision
+   prec (F32, F16 or BF16) on blocks of nrhs sources (1..32): times
+   truncated Schur-complement CG iterations on synthetic sources for each
+   candidate (right-hand sides per lane, half-hop traversal), in this order:
+   (1, lane per half-site) (2, lane) (4, lane) (1, LDS tiles) (2, tiles)
+   (4, tiles); lane widths that do not divide nrhs are skipped.  Keeps the
+   fastest for later solves in that precision (as tm_set_lane_rhs and
+   tm_set_eo_tiles would) and reports it; ms_host (nullable) receives 6
+   per-iteration milliseconds, negative where skipped.  TM_ENOTSUP unless
+   every extent is even.  Needs a loaded gauge field; synchronous. */
+tm_status tm_autotune_eo(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_nr, int32_t* best_tiles,
+                         double* ms_host);
+
 /* Set (nr = 1, 2 or 4) or reset to the built-in choice (nr = 0) the
    right-hand sides per lane used by solves in storage precision prec. */
 tm_status tm_set_lane_rhs(tm_ctx* ctx, int32_t prec, int32_t nr);
@@ -438,6 +451,14 @@ tm_status tm_set_lane_rhs(tm_ctx* ctx, int32_t prec, int32_t nr);
    terms of a site are summed in another order).  TM_EINVAL for prec
    outside 0..3 or tseg outside 0..65535. */
 tm_status tm_set_march(tm_ctx* ctx, int32_t prec, int32_t tseg);
+
+/* Traversal of the even-odd solver's half-hops in storage precision prec
+   (TM_SOLVER_CG_EO): on = 1 gives each block a tile of 64 half-sites and all
+   right-hand sides of the launch, with the tile's links staged once in LDS;
+   on = 0 (the default) one lane per half-site and one block per chunk of
+   right-hand sides.  Same arithmetic; FP64 always uses on = 0.  TM_EINVAL
+   for prec outside 0..3 or on outside 0..1. */
+tm_status tm_set_eo_tiles(tm_ctx* ctx, int32_t prec, int32_t on);
 
 /* CG iteration chunks are captured once into HIP graphs and replayed (on a
    non-null stream, while per-launch profiling is off).  on = 1 enables (the

@@ -127,6 +127,7 @@ class Context:
         import torch
         self.lib = load_library()
         self.dims = tuple(int(d) for d in dims)
+        self.kappa, self.mu, self.t_bc = float(kappa), float(mu), int(t_bc)
         self.V = int(np.prod(self.dims))
         lat = Lattice((ctypes.c_int32 * 4)(*self.dims), float(kappa), float(mu), int(t_bc))
         if stream is None:

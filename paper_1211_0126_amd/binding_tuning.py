@@ -71,3 +71,33 @@ def tm_autotune_cg(ctx: Context, prec, nrhs):
     ctx.check(ctx.lib.tm_autotune_cg(ctx.h, int(prec), int(nrhs), ctypes.byref(nr), ctypes.byref(ts),
                                      ms.ctypes.data_as(ctypes.c_void_p)))
     return int(nr.value), int(ts.value), {c: float(m) for c, m in zip(TUNE_CANDIDATES, ms) if m >= 0}
+
+
+EXPORTS += ["tm_set_eo_tiles"]
+
+
+def tm_set_eo_tiles(ctx: Context, prec, on):
+    """Even-odd half-hops: 1 = LDS-staged link tiles shared by all right-hand
+    sides, 0 = one lane per half-site (the default)."""
+    ctx.lib.tm_set_eo_tiles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+    ctx.lib.tm_set_eo_tiles.restype = ctypes.c_int32
+    ctx.check(ctx.lib.tm_set_eo_tiles(ctx.h, int(prec), int(on)))
+
+
+EXPORTS += ["tm_autotune_eo"]
+
+EO_TUNE_CANDIDATES = [(1, 0), (2, 0), (4, 0), (1, 1), (2, 1), (4, 1)]
+
+
+def tm_autotune_eo(ctx: Context, prec, nrhs):
+    """Even-odd solver: returns (right-hand sides per lane, tiles 0/1,
+    {(nr, tiles): ms per Schur-CG iteration}) and keeps the choice."""
+    import numpy as np
+    ctx.lib.tm_autotune_eo.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), ctypes.c_void_p]
+    ctx.lib.tm_autotune_eo.restype = ctypes.c_int32
+    nr, tl = ctypes.c_int32(), ctypes.c_int32()
+    ms = np.zeros(len(EO_TUNE_CANDIDATES), dtype=np.float64)
+    ctx.check(ctx.lib.tm_autotune_eo(ctx.h, int(prec), int(nrhs), ctypes.byref(nr), ctypes.byref(tl),
+                                     ms.ctypes.data_as(ctypes.c_void_p)))
+    return int(nr.value), int(tl.value), {c: float(m) for c, m in zip(EO_TUNE_CANDIDATES, ms) if m >= 0}

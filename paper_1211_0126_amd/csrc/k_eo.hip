@@ -33,143 +33,9 @@
 #include "tm_device.h"
 #include "tm_kernels.h"
 #include "tm_stencil.h"
+#include "tm_eo.h"
 
 namespace tmq {
-
-struct EoSite {
-    int xh, x, y, z, t;
-};
-
-// coordinates of half-site h of parity par (hg.m[0] divides by Lx/2; it is
-// 0 for Lx = 2, where the row is h itself)
-__device__ __forceinline__ EoSite eo_coords(const Geom& hg, uint32_t h, int par) {
-    const uint32_t Lxh = (uint32_t)hg.L[0] >> 1;
-    const uint32_t q0 = hg.m[0] ? fdiv(h, hg.m[0]) : h;
-    const uint32_t q1 = fdiv(q0, hg.m[1]);
-    const uint32_t q2 = fdiv(q1, hg.m[2]);
-    EoSite c;
-    c.xh = (int)(h - q0 * Lxh);
-    c.y = (int)(q0 - q1 * (uint32_t)hg.L[1]);
-    c.z = (int)(q1 - q2 * (uint32_t)hg.L[2]);
-    c.t = (int)q2;
-    c.x = 2 * c.xh + ((c.y + c.z + c.t + par) & 1);
-    return c;
-}
-
-// half index of the neighbour (opposite parity) in direction mu
-__device__ __forceinline__ uint32_t eo_nb(const Geom& hg, uint32_t h, const EoSite& c, int mu, bool fwd) {
-    const uint32_t L0 = hg.L[0], L1 = hg.L[1], L2 = hg.L[2], L3 = hg.L[3];
-    const uint32_t Lxh = L0 >> 1;
-    switch (mu) {
-    case 0: {
-        const int xn = fwd ? ((c.x + 1 == (int)L0) ? 0 : c.x + 1) : ((c.x == 0) ? (int)L0 - 1 : c.x - 1);
-        return h - (uint32_t)c.xh + (uint32_t)(xn >> 1);
-    }
-    case 1:
-        return fwd ? ((c.y + 1 == (int)L1) ? h - (L1 - 1) * Lxh : h + Lxh)
-                   : ((c.y == 0) ? h + (L1 - 1) * Lxh : h - Lxh);
-    case 2:
-        return fwd ? ((c.z + 1 == (int)L2) ? h - (L2 - 1) * Lxh * L1 : h + Lxh * L1)
-                   : ((c.z == 0) ? h + (L2 - 1) * Lxh * L1 : h - Lxh * L1);
-    default:
-        return fwd ? ((c.t + 1 == (int)L3) ? h - (L3 - 1) * Lxh * L1 * L2 : h + Lxh * L1 * L2)
-                   : ((c.t == 0) ? h + (L3 - 1) * Lxh * L1 * L2 : h - Lxh * L1 * L2);
-    }
-}
-
-// full-lattice site index of half-site h (parity par)
-__device__ __forceinline__ uint32_t eo_full_site(uint32_t h, const EoSite& c) {
-    return (h - (uint32_t)c.xh) * 2u + (uint32_t)c.x;  // x + Lx row with row = (h - xh) / (Lx/2)
-}
-
-// both hops in direction MU into half-site h: forward links from gout (the
-// output parity's copy, at h), backward links from gin at the neighbour
-template <int MU, bool DAG, typename R, class S, class G, int NR>
-__device__ __forceinline__ void eo_hop_mu(const Geom& hg, const void* gout, const void* gin, const void* in,
-                                          uint32_t h, const EoSite& c, cx<R> (&acc)[NR][12]) {
-    constexpr int SF = DAG ? -1 : 1;
-    const long Vs = hg.Vs;
-    {
-        const uint32_t y = eo_nb(hg, h, c, MU, true);
-        const bool flip = (MU == 3) && (c.t + 1 == hg.L[3]) && (hg.t_bc < 0);
-        cx<R> U[3][3];
-        load_link<G, R>(gout, Vs, MU, h, U);
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            cx<R> p[12], hh[6], g[6];
-            load_spinor<S, R>(field_rhs<S>(in, Vs, r), Vs, y, p);
-            proj<MU, SF>(p, hh);
-            if (flip) negate6(hh);
-            su3_mul(U, hh, g);
-            recon<MU, SF>(g, acc[r]);
-        }
-    }
-    if (sizeof(R) == 8) {
-        pin_acc<R, NR>(acc);
-        TM_MEM_FENCE();
-    }
-    {
-        const uint32_t y = eo_nb(hg, h, c, MU, false);
-        const bool flip = (MU == 3) && (c.t == 0) && (hg.t_bc < 0);
-        cx<R> U[3][3];
-        load_link<G, R>(gin, Vs, MU, y, U);
-#pragma unroll
-        for (int r = 0; r < NR; r++) {
-            cx<R> p[12], hh[6], g[6];
-            load_spinor<S, R>(field_rhs<S>(in, Vs, r), Vs, y, p);
-            proj<MU, -SF>(p, hh);
-            if (flip) negate6(hh);
-            su3_dag_mul(U, hh, g);
-            recon<MU, -SF>(g, acc[r]);
-        }
-    }
-}
-
-template <bool DAG, typename R, class S, class G, int NR>
-__device__ __forceinline__ void eo_hop_all(const Geom& hg, const void* gout, const void* gin, const void* in,
-                                           uint32_t h, const EoSite& c, cx<R> (&acc)[NR][12]) {
-#pragma unroll
-    for (int r = 0; r < NR; r++)
-#pragma unroll
-        for (int k = 0; k < 12; k++) acc[r][k] = {(R)0, (R)0};
-    eo_hop_mu<0, DAG, R, S, G, NR>(hg, gout, gin, in, h, c, acc);
-    pin_acc<R, NR>(acc);
-    TM_MEM_FENCE();
-    eo_hop_mu<1, DAG, R, S, G, NR>(hg, gout, gin, in, h, c, acc);
-    pin_acc<R, NR>(acc);
-    TM_MEM_FENCE();
-    eo_hop_mu<2, DAG, R, S, G, NR>(hg, gout, gin, in, h, c, acc);
-    pin_acc<R, NR>(acc);
-    TM_MEM_FENCE();
-    eo_hop_mu<3, DAG, R, S, G, NR>(hg, gout, gin, in, h, c, acc);
-}
-
-// v <- (1 + i tw g5) v, g5 = diag(1, 1, -1, -1) (components 0-5 upper spins)
-template <typename R>
-__device__ __forceinline__ void mul_diag(cx<R> v[12], R tw) {
-#pragma unroll
-    for (int k = 0; k < 12; k++) {
-        const R s = k < 6 ? tw : -tw;
-        v[k] = {v[k].re - s * v[k].im, v[k].im + s * v[k].re};
-    }
-}
-// v <- (1 + i tw g5)^{-1} v = (1 - i tw g5) v / (1 + tw^2)
-template <typename R>
-__device__ __forceinline__ void mul_diag_inv(cx<R> v[12], R tw, R inv) {
-#pragma unroll
-    for (int k = 0; k < 12; k++) {
-        const R s = k < 6 ? -tw : tw;
-        v[k] = {inv * (v[k].re - s * v[k].im), inv * (v[k].im + s * v[k].re)};
-    }
-}
-
-// Z4 source at full site s (the same hash as the full-lattice noise)
-template <typename R>
-__device__ __forceinline__ void noise_at(uint64_t seed_mixed, uint64_t id, uint64_t V, uint64_t s, cx<R> e[12]) {
-    const uint64_t hb = noise_bits(seed_mixed, id, V, s);
-#pragma unroll
-    for (int k = 0; k < 12; k++) e[k] = z4_value<R>((uint32_t)(hb >> (2 * k)) & 3u);
-}
 
 // ---------------------------------------------------------------------------
 // linear half-hop: out = POST(PRE(b) + c acc), acc = H (or H^dag if DAG) in,
@@ -185,6 +51,12 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_lin(EoArgs a) {
     const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
     const int r0 = bm.ch * NR;
     if (a.gate != nullptr && !a.gate[r0].rflag) return;
+    if (a.act != nullptr) {
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < NR; r++) any |= a.act[r0 + r].active != 0;
+        if (!any) return;  // uniform over the chunk's blocks
+    }
     const long Vs = hg.Vs;
     const R tw = (R)(DAG ? -a.twist : a.twist);
     const R inv = (R)(1.0 / (1.0 + a.twist * a.twist));
@@ -217,6 +89,61 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_lin(EoArgs a) {
             if (POST_DINV) mul_diag_inv(o, tw, inv);
             store_spinor<So, R>(field_rhs<So>(a.out, Vs, r0 + r), Vs, h, o);
         }
+    }
+}
+
+// Sources in the half layout: eta_o on the odd sites and D^{-1} eta_e on
+// the even sites (the input of the source's hop), from the hash
+template <typename R, class S>
+__global__ __launch_bounds__(256) void k_eo_noise(Geom hg, uint64_t seed_mixed, const uint64_t* ids, double twist,
+                                                  void* eta_o, void* ye) {
+    const uint32_t h = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (h >= hg.V) return;
+    const uint64_t Vf = (uint64_t)(2 * hg.V);
+    cx<R> e[12];
+    const EoSite co = eo_coords(hg, h, 1);
+    noise_at<R>(seed_mixed, ids[r], Vf, eo_full_site(h, co), e);
+    store_spinor<S, R>(field_rhs<S>(eta_o, hg.Vs, r), hg.Vs, h, e);
+    const EoSite ce = eo_coords(hg, h, 0);
+    noise_at<R>(seed_mixed, ids[r], Vf, eo_full_site(h, ce), e);
+    mul_diag_inv(e, (R)twist, (R)(1.0 / (1.0 + twist * twist)));
+    store_spinor<S, R>(field_rhs<S>(ye, hg.Vs, r), hg.Vs, h, e);
+}
+
+// The whole solution in the full native layout of X (stride g.Vs): the even
+// site of half index h gets D^{-1} (eta_e + kappa H_eo x_o) with eta_e from
+// the hash, the odd site of the same half index gets x_o(h); a.in = x_o
+template <typename R, class X, class G, int NR>
+__global__ TM_STENCIL_R(NR, R) void k_eo_rec_full(EoArgs a, Geom g, void* full) {
+    const Geom& hg = a.hg;
+    const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
+    const int r0 = bm.ch * NR;
+    const uint32_t h = bm.sb * 256u + threadIdx.x;
+    if (h >= hg.V) return;
+    const long Vs = hg.Vs;
+    const R tw = (R)a.twist;
+    const R inv = (R)(1.0 / (1.0 + a.twist * a.twist));
+    const R kap = (R)a.kappa;
+    const EoSite c = eo_coords(hg, h, 0);
+    const uint32_t se = eo_full_site(h, c);
+    const uint32_t so = se - (uint32_t)c.x + (uint32_t)(c.x ^ 1);
+    const void* in0 = field_rhs<X>(a.in, Vs, r0);
+    cx<R> acc[NR][12];
+    eo_hop_all<false, R, X, G, NR>(hg, a.gout, a.gin, in0, h, c, acc);
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        cx<R> o[12], xo[12];
+        noise_at<R>(a.seed_mixed, a.ids[r0 + r], (uint64_t)(2 * hg.V), se, o);
+#pragma unroll
+        for (int k = 0; k < 12; k++) o[k] = o[k] + kap * acc[r][k];
+        mul_diag_inv(o, tw, inv);
+        load_spinor<X, R>(field_rhs<X>(in0, Vs, r), Vs, h, xo);
+        void* f = field_rhs<X>(full, g.Vs, r0 + r);
+        if (c.x & 1)
+            store_site_pair<X, R>(f, g.Vs, so, xo, se, o);
+        else
+            store_site_pair<X, R>(f, g.Vs, se, o, so, xo);
     }
 }
 
@@ -411,7 +338,9 @@ __global__ TM_STENCIL_R(1, double) void k_eo_rel_resid(CgArgs a, EoCg e, const v
 
 // ---------------------------------------------------------------------------
 // layout: full native planes <-> the two half layouts (np planes per field
-// block, e.g. S::NV * nrhs for spinors, 12 or 36 for the links)
+// block, e.g. S::NV * nrhs for spinors, 12 or 36 for the links).  A block of
+// many right-hand sides spans more than the 4 GiB that a 32-bit buffer
+// offset reaches, so every plane gets its own 64-bit base.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_eo_split(Geom g, Geom hg, const void* in, int np, void* out_e, void* out_o) {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
@@ -419,10 +348,10 @@ __global__ __launch_bounds__(256) void k_eo_split(Geom g, Geom hg, const void* i
     const Site c = site_coords(g, s);
     const int par = (c.x + c.y + c.z + c.t) & 1;
     const uint32_t h = s >> 1;  // (row * Lx + x) / 2 = row * Lx/2 + x/2 (Lx even)
-    void* out = par ? out_o : out_e;
+    char* out = (char*)(par ? out_o : out_e);
     for (int k = blockIdx.y; k < np; k += gridDim.y) {
-        const uint4 v = ld_plane<uint4>(in, g.Vs, k, s);
-        st_plane<uint4>(out, hg.Vs, k, h, v);
+        const uint4 v = ld_plane<uint4>((const char*)in + (size_t)k * g.Vs * 16, g.Vs, 0, s);
+        st_plane<uint4>(out + (size_t)k * hg.Vs * 16, hg.Vs, 0, h, v);
     }
 }
 
@@ -433,10 +362,10 @@ __global__ __launch_bounds__(256) void k_eo_merge(Geom g, Geom hg, const void* i
     const Site c = site_coords(g, s);
     const int par = (c.x + c.y + c.z + c.t) & 1;
     const uint32_t h = s >> 1;
-    const void* in = par ? in_o : in_e;
+    const char* in = (const char*)(par ? in_o : in_e);
     for (int k = blockIdx.y; k < np; k += gridDim.y) {
-        const uint4 v = ld_plane<uint4>(in, hg.Vs, k, h);
-        st_plane<uint4>(out, g.Vs, k, s, v);
+        const uint4 v = ld_plane<uint4>(in + (size_t)k * hg.Vs * 16, hg.Vs, 0, h);
+        st_plane<uint4>((char*)out + (size_t)k * g.Vs * 16, g.Vs, 0, s, v);
     }
 }
 
@@ -445,6 +374,49 @@ __global__ __launch_bounds__(256) void k_eo_merge(Geom g, Geom hg, const void* i
 // ---------------------------------------------------------------------------
 static inline uint32_t eo_blocks(const Geom& hg) { return (uint32_t)((hg.V + 255) / 256); }
 constexpr uint32_t kEoGatedBlocks = 512;
+
+void launch_eo_noise(hipStream_t st, const Geom& hg, int prec, uint64_t seed_mixed, const uint64_t* ids, int nrhs,
+                     double twist, void* eta_o, void* ye) {
+    const dim3 grid(eo_blocks(hg), (unsigned)nrhs);
+    switch (prec) {
+    case P_F64:
+        hipLaunchKernelGGL((k_eo_noise<double, SF64>), grid, dim3(256), 0, st, hg, seed_mixed, ids, twist, eta_o, ye);
+        break;
+    case P_F32:
+        hipLaunchKernelGGL((k_eo_noise<float, SF32>), grid, dim3(256), 0, st, hg, seed_mixed, ids, twist, eta_o, ye);
+        break;
+    case P_F16:
+        hipLaunchKernelGGL((k_eo_noise<float, SF16>), grid, dim3(256), 0, st, hg, seed_mixed, ids, twist, eta_o, ye);
+        break;
+    default:
+        hipLaunchKernelGGL((k_eo_noise<float, SBF16>), grid, dim3(256), 0, st, hg, seed_mixed, ids, twist, eta_o, ye);
+        break;
+    }
+}
+
+// xprec: P_F64 (FP64 odd half and output) or P_F32
+void launch_eo_rec_full(hipStream_t st, const EoArgs& a, int xprec, int nr, const Geom& g, void* full) {
+    const uint32_t nb = eo_blocks(a.hg);
+    if (xprec == P_F64) {
+        hipLaunchKernelGGL((k_eo_rec_full<double, SF64, GF64, 1>), dim3(nb * (unsigned)a.nrhs), dim3(256), 0, st, a,
+                           g, full);
+        return;
+    }
+    switch (nr) {
+    case 4:
+        hipLaunchKernelGGL((k_eo_rec_full<float, SF32, GF32, 4>), dim3(nb * (unsigned)(a.nrhs / 4)), dim3(256), 0, st,
+                           a, g, full);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_eo_rec_full<float, SF32, GF32, 2>), dim3(nb * (unsigned)(a.nrhs / 2)), dim3(256), 0, st,
+                           a, g, full);
+        break;
+    default:
+        hipLaunchKernelGGL((k_eo_rec_full<float, SF32, GF32, 1>), dim3(nb * (unsigned)a.nrhs), dim3(256), 0, st, a, g,
+                           full);
+        break;
+    }
+}
 
 void launch_eo_split(hipStream_t st, const Geom& g, const Geom& hg, const void* in, int np, void* out_e,
                      void* out_o) {

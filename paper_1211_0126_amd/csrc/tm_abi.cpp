@@ -492,6 +492,13 @@ tm_status tm_set_march(tm_ctx* ctx, int32_t prec, int32_t tseg) {
     return TM_OK;
 }
 
+tm_status tm_set_eo_tiles(tm_ctx* ctx, int32_t prec, int32_t on) {
+    if (!ctx || prec < 0 || prec > 3 || on < 0 || on > 1)
+        return ctx ? set_error(ctx, TM_EINVAL, "tm_set_eo_tiles: bad argument") : TM_EINVAL;
+    ctx->eo_tiles[prec] = prec == TM_PREC_F64 ? 0 : on;
+    return TM_OK;
+}
+
 tm_status tm_set_lane_rhs(tm_ctx* ctx, int32_t prec, int32_t nr) {
     if (!ctx || prec < 0 || prec > 3 || !(nr == 0 || nr == 1 || nr == 2 || nr == 4))
         return set_error(ctx, TM_EINVAL, "tm_set_lane_rhs: bad argument");

@@ -53,11 +53,17 @@ struct tm_ctx {
     // time slices per lane of the time-marching CG stencils, per storage
     // precision (0: one lane per site)
     int march[4] = {0, 0, 0, 0};
+    // even-odd CG half-hops per storage precision: 1 the tile kernels (links
+    // staged in LDS and shared by all right-hand sides), 0 a lane per site
+    int eo_tiles[4] = {0, 0, 0, 0};
 
     // captured CG chunks (replayed with hipGraphLaunch), keyed by buffers and
     // launch configuration; used on a non-null stream when profiling is off
     bool use_graphs = true;
     std::map<std::string, hipGraphExec_t> graphs;
+    // CG iterations of the last block solved with given settings (the first
+    // chunk of steps between host checks of the next such block)
+    std::map<std::string, int> chunk_hint;
     int64_t graph_launches = 0;
 
     std::string err;

@@ -330,11 +330,8 @@ __device__ __forceinline__ void load_link<GF64, double>(const void* g, long Vs, 
         U[k / 3][k % 3] = {v.x, v.y};
     }
 }
-template <>
-__device__ __forceinline__ void load_link<GF32, float>(const void* g, long Vs, int mu, uint32_t s, cx<float> U[3][3]) {
-    const float4 a0 = ld_plane<float4>(g, Vs, mu * 3 + 0, s);
-    const float4 a1 = ld_plane<float4>(g, Vs, mu * 3 + 1, s);
-    const float4 a2 = ld_plane<float4>(g, Vs, mu * 3 + 2, s);
+// the FP32 link from its two stored rows (three float4: row 0, then row 1)
+__device__ __forceinline__ void link_from_rows(float4 a0, float4 a1, float4 a2, cx<float> U[3][3]) {
     U[0][0] = {a0.x, a0.y};
     U[0][1] = {a0.z, a0.w};
     U[0][2] = {a1.x, a1.y};
@@ -357,6 +354,13 @@ __device__ __forceinline__ void load_link<GF32, float>(const void* g, long Vs, i
     U[2][0] = cof(U[0][1], U[1][2], U[0][2], U[1][1]);
     U[2][1] = cof(U[0][2], U[1][0], U[0][0], U[1][2]);
     U[2][2] = cof(U[0][0], U[1][1], U[0][1], U[1][0]);
+}
+template <>
+__device__ __forceinline__ void load_link<GF32, float>(const void* g, long Vs, int mu, uint32_t s, cx<float> U[3][3]) {
+    const float4 a0 = ld_plane<float4>(g, Vs, mu * 3 + 0, s);
+    const float4 a1 = ld_plane<float4>(g, Vs, mu * 3 + 1, s);
+    const float4 a2 = ld_plane<float4>(g, Vs, mu * 3 + 2, s);
+    link_from_rows(a0, a1, a2, U);
 }
 
 // ---------------------------------------------------------------------------

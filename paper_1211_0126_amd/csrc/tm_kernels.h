@@ -117,6 +117,7 @@ struct EoArgs {
     uint64_t seed_mixed;
     const uint64_t* ids;
     const CgScal* gate; // nullable: only right-hand sides with the reliable flag
+    const CgScal* act;  // nullable: skip chunks whose right-hand sides have all stopped
     int nrhs;
 };
 struct EoCg {
@@ -134,6 +135,21 @@ void launch_eo_upd(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int
 uint32_t eo_gated_blocks(const Geom& hg);
 void launch_eo_rel_resid(hipStream_t st, const CgArgs& a, const EoCg& e, const void* b64, const void* t64,
                          const void* y64);
+// the same half-hops with the links of a tile of 64 half-sites staged in LDS
+// and shared by all right-hand sides (FP32 links; FP32/FP16/BF16 storage);
+// reductions write eot_tiles(hg) partials per right-hand side
+uint32_t eot_tiles(const Geom& hg);
+void launch_eot_y(hipStream_t st, const EoArgs& a, int prec, int nr, bool dag, const CgScal* sc);
+void launch_eot_mp(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr, bool dag, const void* cin,
+                   void* cout);
+void launch_eot_upd(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr, bool track);
+void launch_eot_src(hipStream_t st, const EoArgs& a, int prec, int nr);
+void launch_eot_rec(hipStream_t st, const EoArgs& a, int nr, const Geom& g, void* full);
+// sources in the half layout: eta_o (odd sites) and D^{-1} eta_e (even)
+void launch_eo_noise(hipStream_t st, const Geom& hg, int prec, uint64_t seed_mixed, const uint64_t* ids, int nrhs,
+                     double twist, void* eta_o, void* ye);
+// the whole solution in the full native layout from the odd half a.in
+void launch_eo_rec_full(hipStream_t st, const EoArgs& a, int xprec, int nr, const Geom& g, void* full);
 void launch_eo_split(hipStream_t st, const Geom& g, const Geom& hg, const void* in, int np, void* out_e, void* out_o);
 void launch_eo_merge(hipStream_t st, const Geom& g, const Geom& hg, const void* in_e, const void* in_o, int np,
                      void* out);

@@ -87,6 +87,35 @@ static tm_status ensure_scal_host(tm_ctx* ctx, int n) {
     return TM_OK;
 }
 
+// CG steps between host checks.  The first chunk is the iteration count of
+// the previous block solved with the same settings (one graph replay then
+// covers a typical solve), else `dflt`; later chunks are shorter, so that few
+// launches run past convergence (such launches return at once).  With
+// per-launch profiling every step is checked, so that each timed launch has
+// active right-hand sides and its bytes count only those.
+static std::string chunk_key(const tsm_solve_params* p, const std::string& tag, int nrhs) {
+    char k[160];
+    std::snprintf(k, sizeof(k), "%s|%d|%d|%d|%d|%.6g|%d|%d", tag.c_str(), p->prec, p->solver, p->reliable, p->stop,
+                  p->tol, p->max_iter, nrhs);
+    return k;
+}
+static int first_chunk(const tm_ctx* ctx, const std::string& key, int dflt) {
+    if (ctx->prof) return 1;
+    auto it = ctx->chunk_hint.find(key);
+    return it == ctx->chunk_hint.end() ? dflt : std::max(1, it->second);
+}
+static int later_chunk(const tm_ctx* ctx, int dflt) { return ctx->prof ? 1 : std::max(1, dflt / 4); }
+static int active_count(const tm_ctx* ctx, int nrhs) {
+    int n = 0;
+    for (int r = 0; r < nrhs; r++) n += ctx->scal_host[r].active != 0;
+    return n;
+}
+static void remember_chunk(tm_ctx* ctx, const std::string& key, int nrhs) {
+    int m = 0;
+    for (int r = 0; r < nrhs; r++) m = std::max(m, (int)ctx->scal_host[r].iters);
+    if (m > 0) ctx->chunk_hint[key] = m;
+}
+
 // bytes of the CG kernels per launch (algorithmic: each field touched once,
 // each link once per site)
 struct CgBytes {
@@ -320,39 +349,40 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     const bool rel = p->reliable != 0;
     const bool track = p->stop == TM_STOP_TRUE && !rel;
     const int xprec = prec == P_F64 ? P_F64 : P_F32;
-    const int nv = prec == P_F64 ? 12 : (prec == P_F32 ? 6 : 3);
     const size_t nblk_full = (size_t)((g.V + 255) / 256);
     const uint32_t nblk = (uint32_t)((hg.V + 255) / 256);
     const size_t fbh = field_bytes(hg, prec, nrhs);
     const double kappa = ctx->lat.kappa, tw = ctx->twist;
     const double ee_z4 = 12.0 * (double)g.V;
 
+    // FP32 arithmetic runs the tile kernels (links staged in LDS, shared by
+    // the block's right-hand sides); FP64 the lane-per-site kernels
+    const bool tiles = prec != P_F64 && ctx->eo_tiles[prec] != 0;
     CgArgs a;
     std::memset(&a, 0, sizeof(a));
     a.geo = hg;
     a.kappa = kappa;
     a.twist = tw;
     a.nrhs = nrhs;
-    a.npart = nblk;
+    a.npart = tiles ? eot_tiles(hg) : nblk;
     a.p = ws_get(ctx, tag + "_eo_p", fbh, &s);
     a.t = ws_get(ctx, tag + "_eo_t", fbh, &s);
     a.r = ws_get(ctx, tag + "_eo_r", fbh, &s);
     a.x = ws_get(ctx, tag + "_eo_x", field_bytes(hg, xprec, nrhs), &s);
     void* y = ws_get(ctx, tag + "_eo_y", fbh, &s);
     a.scal = (CgScal*)ws_get(ctx, tag + "_scal", sizeof(CgScal) * kMaxBlock, &s);
-    a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * nblk_full * kMaxBlock, &s);
-    a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * nblk_full * kMaxBlock, &s);
+    const size_t npart_max = std::max<size_t>(nblk_full, (size_t)eot_tiles(hg));
+    a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * npart_max * kMaxBlock, &s);
+    a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * npart_max * kMaxBlock, &s);
     if (track) a.rho = ws_get(ctx, tag + "_eo_rho", fbh, &s);
     // the full solution handed to the contraction
     const int fprec = rel ? P_F64 : xprec;
     void* xfull = ws_get(ctx, tag + "_eo_xfull", field_bytes(g, fprec, nrhs), &s);
-    void* xe = ws_get(ctx, tag + "_eo_xe", field_bytes(hg, fprec, nrhs), &s);
-    // source preparation at the iteration precision (FP64 with reliable updates)
+    // source preparation at the iteration precision (FP64 with reliable
+    // updates); the tile kernels take the sources from the hash
     const int sp = rel ? P_F64 : prec;
-    const int snv = rel ? 12 : nv;
-    void* etaf = ws_get(ctx, tag + "_eo_etaf", field_bytes(g, sp, nrhs), &s);
-    void* eta_e = ws_get(ctx, tag + "_eo_etae", field_bytes(hg, sp, nrhs), &s);
-    void* eta_o = ws_get(ctx, tag + "_eo_etao", field_bytes(hg, sp, nrhs), &s);
+    const int snr = sp == P_F64 ? 1 : nr;
+    void* eta_o = tiles && !rel ? nullptr : ws_get(ctx, tag + "_eo_etao", field_bytes(hg, sp, nrhs), &s);
     void* eh = ws_get(ctx, tag + "_eo_eh", field_bytes(hg, sp, nrhs), &s);
     void *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *y64 = nullptr;
     if (rel) {
@@ -393,22 +423,37 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
 
     launch_scal_init(st, a.scal, nrhs, p->tol * p->tol, p->max_iter, p->stop, rel ? 1 : 0,
                      rel ? p->delta * p->delta : 0.0);
-    // sources: eta split by parity, etahat = eta_o + kappa H_oe D^{-1} eta_e,
+    // sources: etahat = eta_o + kappa H_oe D^{-1} eta_e,
     // b = Mhat^dag etahat = D^dag etahat - kappa^2 H_oe^dag D^{-dag} H_eo^dag etahat
     prof_begin(ctx, TM_KC_OTHER);
-    launch_noise_native(st, g, sp, seed_mixed, ids_dev, nrhs, etaf);
-    launch_eo_split(st, g, hg, etaf, snv * nrhs, eta_e, eta_o);
     void* ys = rel ? y64 : y;
-    launch_eo_dinv(st, hg, sp, tw, nrhs, eta_e, ys);
-    launch_eo_lin(st, lin(1, rel, ys, eh, eta_o, kappa, nrhs), sp, 1, EO_SRC);
-    launch_eo_lin(st, lin(0, rel, eh, ys, nullptr, 1.0, nrhs), sp, 1, EO_Y_DAG);
-    if (rel) {
-        launch_eo_lin(st, lin(1, true, ys, b64, eh, k2, nrhs), P_F64, 1, EO_T_DAG);
-        if (p->stop == TM_STOP_TRUE) a.eta64 = eh;
-        launch_rel_init(st, a, b64, x64, ee_z4);
-    } else {
-        launch_eo_lin(st, lin(1, false, ys, a.r, eh, k2, nrhs), prec, 1, EO_T_DAG);
+    if (tiles && !rel) {
+        EoArgs es = lin(1, false, nullptr, eh, nullptr, kappa, nrhs);
+        launch_eot_src(st, es, prec, nr);
+        launch_eot_y(st, lin(0, false, eh, y, nullptr, 1.0, nrhs), prec, nr, true, nullptr);
+        EoCg ei;
+        ei.geven = g32e;
+        ei.godd = g32o;
+        ei.y = y;
+        // r = b = D^dag etahat - kappa^2 H_oe^dag y (all sources active: no
+        // scalars yet)
+        CgArgs ai = a;
+        ai.scal = nullptr;
+        launch_eot_mp(st, ai, ei, prec, nr, true, eh, a.r);
         launch_cg_init(st, a, prec, track, eh, ee_z4);
+    } else {
+        // eta_o and D^{-1} eta_e, then etahat, y = D^{-dag} H_eo^dag etahat and b
+        launch_eo_noise(st, hg, sp, seed_mixed, ids_dev, nrhs, tw, eta_o, ys);
+        launch_eo_lin(st, lin(1, rel, ys, eh, eta_o, kappa, nrhs), sp, snr, EO_SRC);
+        launch_eo_lin(st, lin(0, rel, eh, ys, nullptr, 1.0, nrhs), sp, snr, EO_Y_DAG);
+        if (rel) {
+            launch_eo_lin(st, lin(1, true, ys, b64, eh, k2, nrhs), P_F64, 1, EO_T_DAG);
+            if (p->stop == TM_STOP_TRUE) a.eta64 = eh;
+            launch_rel_init(st, a, b64, x64, ee_z4);
+        } else {
+            launch_eo_lin(st, lin(1, false, ys, a.r, eh, k2, nrhs), prec, snr, EO_T_DAG);
+            launch_cg_init(st, a, prec, track, eh, ee_z4);
+        }
     }
     prof_end(ctx, TM_KC_OTHER, 0.0);
     TM_HIP(hipGetLastError());
@@ -421,30 +466,55 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     ec64.geven = g64e;
     ec64.godd = g64o;
     ec64.y = y64;
-    const EoBytes by = eo_bytes(hg, prec, nrhs, track);
     const int vtag = prof_tag(prec, prec == P_F64 ? 1 : nr, TM_SOLVER_CG_EO, 0);
-    const int chunk = rel ? 16 : 8;
+    const int dflt = rel ? 16 : 8;
+    const std::string ckey = chunk_key(p, tag, nrhs);
+    int chunk = first_chunk(ctx, ckey, dflt);
+    int n_active = nrhs;
+    if (ctx->prof) {
+        TM_HIP(hipMemcpyAsync(ctx->scal_host, a.scal, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        n_active = active_count(ctx, nrhs);
+    }
     int done = 0;
     for (;;) {
         int k = chunk;
         if (p->max_iter >= 0) k = std::max(1, std::min(chunk, p->max_iter - done));
+        chunk = later_chunk(ctx, dflt);
+        const EoBytes by = eo_bytes(hg, prec, n_active, track);
         auto steps = [&](int n) {
             for (int i = 0; i < n; i++) {
+                EoArgs ey = lin(0, false, a.p, y, nullptr, 1.0, nrhs);
+                ey.act = a.scal;
                 prof_begin(ctx, TM_KC_EO_HOP, vtag);
-                launch_eo_lin(st, lin(0, false, a.p, y, nullptr, 1.0, nrhs), prec, nr, EO_Y);
+                if (tiles)
+                    launch_eot_y(st, ey, prec, nr, false, a.scal);
+                else
+                    launch_eo_lin(st, ey, prec, nr, EO_Y);
                 prof_end(ctx, TM_KC_EO_HOP, by.hop);
                 prof_begin(ctx, TM_KC_DSLASH, vtag);
-                launch_eo_mp(st, a, ec, prec, nr);
+                if (tiles)
+                    launch_eot_mp(st, a, ec, prec, nr, false, a.p, a.t);
+                else
+                    launch_eo_mp(st, a, ec, prec, nr);
                 prof_end(ctx, TM_KC_DSLASH, by.mp);
                 prof_begin(ctx, TM_KC_OTHER);
                 launch_cg_alpha(st, a);
                 prof_end(ctx, TM_KC_OTHER, 0.0);
+                EoArgs ey2 = lin(0, false, a.t, y, nullptr, 1.0, nrhs);
+                ey2.act = a.scal;
                 prof_begin(ctx, TM_KC_EO_HOP_DAG, vtag);
-                launch_eo_lin(st, lin(0, false, a.t, y, nullptr, 1.0, nrhs), prec, nr, EO_Y_DAG);
+                if (tiles)
+                    launch_eot_y(st, ey2, prec, nr, true, a.scal);
+                else
+                    launch_eo_lin(st, ey2, prec, nr, EO_Y_DAG);
                 prof_end(ctx, TM_KC_EO_HOP_DAG, by.hop);
                 const int utag = track ? prof_tag(prec, 1, TM_SOLVER_CG_EO, 0) : vtag;
                 prof_begin(ctx, TM_KC_DSLASH_UPD, utag);
-                launch_eo_upd(st, a, ec, prec, track ? 1 : nr, track);
+                if (tiles)
+                    launch_eot_upd(st, a, ec, prec, track ? 1 : nr, track);
+                else
+                    launch_eo_upd(st, a, ec, prec, track ? 1 : nr, track);
                 prof_end(ctx, TM_KC_DSLASH_UPD, by.upd);
                 prof_begin(ctx, TM_KC_OTHER);
                 launch_cg_beta(st, a, track);
@@ -499,32 +569,27 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
         done += k;
         TM_HIP(hipMemcpyAsync(ctx->scal_host, a.scal, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st));
         TM_HIP(hipStreamSynchronize(st));
-        bool any = false;
-        for (int r = 0; r < nrhs; r++) any |= ctx->scal_host[r].active != 0;
-        if (!any) break;
+        n_active = active_count(ctx, nrhs);
+        if (n_active == 0) break;
         if (done >= kIterCap) break;
     }
+    remember_chunk(ctx, ckey, nrhs);
 
     // even half x_e = D^{-1} (eta_e + kappa H_eo x_o) with eta_e from the
     // hash, then the full native solution
     prof_begin(ctx, TM_KC_OTHER);
     if (rel) {
         launch_rel_flush(st, a, x64, 1);
-        EoArgs e = lin(0, true, x64, xe, nullptr, kappa, nrhs);
-        e.bnoise = 1;
-        launch_eo_lin(st, e, P_F64, 1, EO_REC);
-        launch_eo_merge(st, g, hg, xe, x64, 12 * nrhs, xfull);
+        launch_eo_rec_full(st, lin(0, true, x64, nullptr, nullptr, kappa, nrhs), P_F64, 1, g, xfull);
+    } else if (tiles) {
+        launch_eot_rec(st, lin(0, false, a.x, nullptr, nullptr, kappa, nrhs), nr, g, xfull);
     } else {
-        EoArgs e = lin(0, prec == P_F64, a.x, xe, nullptr, kappa, nrhs);
-        e.bnoise = 1;
-        if (prec == P_F64) {
-            launch_eo_lin(st, e, P_F64, 1, EO_REC);
-        } else {
+        EoArgs e = lin(0, prec == P_F64, a.x, nullptr, nullptr, kappa, nrhs);
+        if (prec != P_F64) {
             e.gout = g32e;
             e.gin = g32o;
-            launch_eo_rec_f32(st, e, 1);
         }
-        launch_eo_merge(st, g, hg, xe, a.x, (xprec == P_F64 ? 12 : 6) * nrhs, xfull);
+        launch_eo_rec_full(st, e, xprec, prec == P_F64 ? 1 : nr, g, xfull);
     }
     prof_end(ctx, TM_KC_OTHER, 0.0);
     res->x = xfull;
@@ -600,7 +665,6 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
     const double delta2 = rel ? p->delta * p->delta : 0.0;
     launch_scal_init(st, a.scal, nrhs, tol2, p->max_iter, p->stop, rel ? 1 : 0, delta2);
 
-    const CgBytes by = cg_bytes(g, prec, nrhs, rel, track);
     const double gb64 = 4 * 18 * 8.0;
 
     // sources and right-hand side b = M^dag eta
@@ -617,12 +681,22 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
     prof_end(ctx, TM_KC_OTHER, 0.0);
     TM_HIP(hipGetLastError());
 
-    const int chunk = rel ? 16 : 8;
     const int vtag = prof_tag(prec, prec == P_F64 ? 1 : nr, TM_SOLVER_CG, a.tseg);
+    const int dflt = rel ? 16 : 8;
+    const std::string ckey = chunk_key(p, tag, nrhs);
+    int chunk = first_chunk(ctx, ckey, dflt);
+    int n_active = nrhs;
+    if (ctx->prof) {
+        TM_HIP(hipMemcpyAsync(ctx->scal_host, a.scal, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        n_active = active_count(ctx, nrhs);
+    }
     int done = 0;
     for (;;) {
         int k = chunk;
         if (p->max_iter >= 0) k = std::max(1, std::min(chunk, p->max_iter - done));
+        chunk = later_chunk(ctx, dflt);
+        const CgBytes by = cg_bytes(g, prec, n_active, rel, track);
         auto steps = [&](int n) {
             for (int i = 0; i < n; i++) {
                 prof_begin(ctx, TM_KC_DSLASH, vtag);
@@ -685,11 +759,11 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
         done += k;
         TM_HIP(hipMemcpyAsync(ctx->scal_host, a.scal, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st));
         TM_HIP(hipStreamSynchronize(st));
-        bool any = false;
-        for (int r = 0; r < nrhs; r++) any |= ctx->scal_host[r].active != 0;
-        if (!any) break;
+        n_active = active_count(ctx, nrhs);
+        if (n_active == 0) break;
         if (done >= kIterCap) break;
     }
+    remember_chunk(ctx, ckey, nrhs);
     if (rel) {
         launch_rel_flush(st, a, x64, 1);
         res->x = x64;
@@ -1178,6 +1252,75 @@ tm_status tm_autotune_cg(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_
     ctx->march[prec] = bts;
     *best_nr = bnr;
     *best_tseg = bts;
+    return TM_OK;
+}
+
+tm_status tm_autotune_eo(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_nr, int32_t* best_tiles,
+                         double* ms_host) {
+    if (!ctx || prec < 1 || prec > 3 || nrhs < 1 || nrhs > kMaxBlock || !best_nr || !best_tiles)
+        return ctx ? set_error(ctx, TM_EINVAL, "tm_autotune_eo: bad argument") : TM_EINVAL;
+    if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tm_autotune_eo: no gauge field loaded");
+    if (!ctx->eo_ok) return set_error(ctx, TM_ENOTSUP, "tm_autotune_eo: the even-odd solver needs even extents");
+    tm_status s = TM_OK;
+    uint64_t* ids = (uint64_t*)ws_get(ctx, "tune_ids", sizeof(uint64_t) * nrhs, &s);
+    if (!ids) return s;
+    std::vector<uint64_t> idh(nrhs);
+    for (int i = 0; i < nrhs; i++) idh[i] = (uint64_t)i;
+    TM_COPY(ids, idh.data(), sizeof(uint64_t) * nrhs, hipMemcpyHostToDevice);
+    const int keep_nr = ctx->lane_rhs[prec], keep_tiles = ctx->eo_tiles[prec];
+    tsm_solve_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.prec = prec;
+    p.solver = TM_SOLVER_CG_EO;
+    p.tol = 0.0;  // runs max_iter steps
+    p.stop = TM_STOP_NORMAL;
+    p.rhs_block = nrhs;
+    p.true_resid = 0;
+    constexpr int kNrEo[6] = {1, 2, 4, 1, 2, 4};
+    constexpr int kTilesEo[6] = {0, 0, 0, 1, 1, 1};
+    double best = 1e300;
+    int bnr = 1, bt = 0;
+    for (int c = 0; c < 6; c++) {
+        const int nr = kNrEo[c], tl = kTilesEo[c];
+        if (ms_host) ms_host[c] = -1.0;
+        if (nrhs % nr != 0) continue;
+        ctx->lane_rhs[prec] = nr;
+        ctx->eo_tiles[prec] = tl;
+        // per-iteration time: difference of a long and a short truncated
+        // solve (set-up and reconstruction cancel), best of two after a warm-up
+        double per = 1e300;
+        for (int rep = 0; rep < 3; rep++) {
+            double t[2];
+            for (int j = 0; j < 2; j++) {
+                p.max_iter = j == 0 ? 2 : 8;
+                BlockResult res;
+                const auto t0 = std::chrono::steady_clock::now();
+                s = solve_block(ctx, &p, seed_mix(12345), ids, nrhs, nr, "tune", &res);
+                const auto t1 = std::chrono::steady_clock::now();
+                if (s != TM_OK) break;
+                t[j] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+            }
+            if (s != TM_OK) break;
+            if (rep > 0) per = std::min(per, (t[1] - t[0]) / 6.0);
+        }
+        if (s != TM_OK) break;
+        if (ms_host) ms_host[c] = per;
+        if (per < best) {
+            best = per;
+            bnr = nr;
+            bt = tl;
+        }
+    }
+    if (s != TM_OK) {
+        ctx->lane_rhs[prec] = keep_nr;
+        ctx->eo_tiles[prec] = keep_tiles;
+        return s;
+    }
+    ctx->lane_rhs[prec] = bnr;
+    ctx->eo_tiles[prec] = bt;
+    *best_nr = bnr;
+    *best_tiles = bt;
     return TM_OK;
 }
 

@@ -52,3 +52,49 @@ def test_bench_launch_shape_full_lattice(orc):
         assert abs(st_a[i]["resid_true"] / so["resid_true"] - 1) < 1e-2
     del a, b
     torch.cuda.empty_cache()
+
+
+def test_evenodd_blocks_of_32_full_lattice(orc):
+    """The even-odd solver at 32^3x64 with blocks of 32 FP16 sources: the
+    split and merge of a block move fields larger than 4 GiB, the solution
+    of each source is bitwise that of blocks of 16, and three Schur-CG
+    iterations agree with the FP64 oracle's for two sources."""
+    import torch
+    import paper_1211_0126_amd as tq
+    print("generating the 32^3x64 gauge field", flush=True)
+    U = make_gauge(C3.dims, C3.eps, C3.gauge_seed)
+    ctx = tq.tm_create(C3.dims, C3.kappa, C3.mu, -1)
+    tq.tm_gauge_load(ctx, U)
+    ids = list(range(200, 232))
+    tq.tm_set_lane_rhs(ctx, tq.PREC_F16, 2)
+    out = []
+    for blk, tiles in ((32, 0), (16, 0), (32, 1)):
+        tq.tm_set_eo_tiles(ctx, tq.PREC_F16, tiles)
+        p = tq.solve_params(prec=tq.PREC_F16, tol=0.0, max_iter=3, rhs_block=blk, true_resid=1,
+                            solver=tq.SOLVER_CG_EO)
+        print("even-odd FP16 CG, blocks of %d, tiles %d" % (blk, tiles), flush=True)
+        sol, st, _ = tq.tsm_solve_batch(ctx, p, C3.noise_seed, ids)
+        out.append((sol, st))
+    ctx.close()
+    (a, sa), (b, sb), (c, sc) = out
+    assert torch.equal(a, b)
+    # the tile kernels hash the sources in FP32 where the others store them
+    # in FP16 first: the same iterate up to FP16 rounding
+    d = torch.linalg.vector_norm((c - a).reshape(32, -1), dim=1) / torch.linalg.vector_norm(a.reshape(32, -1), dim=1)
+    print("tiles vs lane per half-site: normwise max %.3g" % d.max().item())
+    assert d.max().item() < 2e-3
+    del c
+    for s in sa:
+        assert s["iters"] == 3 and 0.01 < s["resid_true"] < 0.5, s
+    for i in (0, 31):
+        eta = orc.noise_z4(C3.dims, C3.noise_seed, ids[i])
+        print("oracle even-odd CG source %d" % ids[i], flush=True)
+        x, so = orc.cgnr_eo(C3.dims, -1, C3.kappa, C3.mu, U, eta, 0.0, 3)
+        got = a[i].cpu().numpy()
+        rel = np.linalg.norm((got - x).ravel()) / np.linalg.norm(x.ravel())
+        print("source %d: FP16 even-odd vs FP64 oracle, normwise %.3g, true residual %.4g vs %.4g"
+              % (ids[i], rel, sa[i]["resid_true"], so["resid_true"]))
+        assert rel < 5e-3
+        assert abs(sa[i]["resid_true"] / so["resid_true"] - 1) < 1e-2
+    del a, b
+    torch.cuda.empty_cache()

@@ -110,15 +110,17 @@ def test_eo_fp32_reliable_hp(orc):
     ctx.close()
 
 
+@pytest.mark.parametrize("tiles", [0, 1])
 @pytest.mark.parametrize("prec", [1, 2, 3])
-def test_eo_reduced_precision_lp(orc, prec):
-    """FP32 / FP16 / BF16 storage on the Schur system: converged at the LP
-    tolerance within an iteration or two of the FP64 oracle, with an FP64
-    true residual close to the oracle's."""
+def test_eo_reduced_precision_lp(orc, prec, tiles):
+    """FP32 / FP16 / BF16 storage on the Schur system, both traversals of
+    the half-hops: converged at the LP tolerance within an iteration of the
+    FP64 oracle, with an FP64 true residual close to the oracle's."""
     import paper_1211_0126_amd as tq
     dims, kappa, mu, eps = LATTICES[3]
     U = make_gauge(dims, eps, 1002)
     ctx = _ctx(dims, kappa, mu, U)
+    tq.tm_set_eo_tiles(ctx, prec, tiles)
     ids = list(range(8))
     p = tq.solve_params(prec=prec, tol=1e-2, max_iter=-1, rhs_block=8, solver=tq.SOLVER_CG_EO)
     sol, st, _ = tq.tsm_solve_batch(ctx, p, 7, ids)
@@ -133,28 +135,33 @@ def test_eo_reduced_precision_lp(orc, prec):
 
 @pytest.mark.parametrize("prec", [1, 2])
 def test_eo_lane_rhs_variants_agree(prec):
-    """1, 2 and 4 right-hand sides per lane give the same solutions."""
+    """1, 2 and 4 right-hand sides per lane, a lane per half-site or tiles
+    with LDS-staged links: the same solutions."""
     import paper_1211_0126_amd as tq
     dims, kappa, mu, eps = LATTICES[1]
     U = make_gauge(dims, eps, 5)
     ctx = _ctx(dims, kappa, mu, U)
     p = tq.solve_params(prec=prec, tol=0.0, max_iter=5, rhs_block=8, solver=tq.SOLVER_CG_EO)
     out = []
-    for nr in (1, 2, 4):
-        tq.tm_set_lane_rhs(ctx, prec, nr)
-        sol, _, _ = tq.tsm_solve_batch(ctx, p, 3, list(range(8)))
-        out.append(sol.cpu().numpy())
+    for tiles in (0, 1):
+        tq.tm_set_eo_tiles(ctx, prec, tiles)
+        for nr in (1, 2, 4):
+            tq.tm_set_lane_rhs(ctx, prec, nr)
+            sol, _, _ = tq.tsm_solve_batch(ctx, p, 3, list(range(8)))
+            out.append(sol.cpu().numpy())
     for o in out[1:]:
         assert _rel(o, out[0]) < (1e-6 if prec == 1 else 1e-3)
     ctx.close()
 
 
-def test_eo_batching_does_not_change_a_source():
+@pytest.mark.parametrize("tiles", [0, 1])
+def test_eo_batching_does_not_change_a_source(tiles):
     import torch
     import paper_1211_0126_amd as tq
     dims = (4, 4, 4, 8)
     U = make_gauge(dims, 0.25, 77)
     ctx = _ctx(dims, 0.1632, 0.004, U)
+    tq.tm_set_eo_tiles(ctx, tq.PREC_F16, tiles)
     p = tq.solve_params(prec=tq.PREC_F16, tol=1e-2, max_iter=-1, rhs_block=8, solver=tq.SOLVER_CG_EO)
     a, _, _ = tq.tsm_solve_batch(ctx, p, 3, list(range(8)))
     b, _, _ = tq.tsm_solve_batch(ctx, p, 3, [4, 5, 6, 7, 0, 1, 2, 3])
@@ -195,7 +202,8 @@ def test_eo_tsm_config0_matches_oracle(orc):
     ctx.close()
 
 
-def test_eo_tsm_27_momenta_fp32(orc):
+@pytest.mark.parametrize("tiles", [0, 1])
+def test_eo_tsm_27_momenta_fp32(orc, tiles):
     """Even-odd FP32 LP and reliable HP solves through the whole estimate on
     an anisotropic lattice at 27 momenta, against the oracle's even-odd
     FP64 TSM (LP truncated by iteration count, so both sides take the same
@@ -204,6 +212,7 @@ def test_eo_tsm_27_momenta_fp32(orc):
     dims, kappa, mu = (4, 6, 4, 8), 0.1632, 0.004
     U = make_gauge(dims, 0.25, 88)
     ctx = _ctx(dims, kappa, mu, U)
+    tq.tm_set_eo_tiles(ctx, tq.PREC_F32, tiles)
     lp = tq.solve_params(prec=tq.PREC_F32, tol=0.0, max_iter=6, rhs_block=4, solver=tq.SOLVER_CG_EO)
     hp = tq.solve_params(prec=tq.PREC_F32, tol=1e-10, max_iter=-1, reliable=1, delta=0.1, rhs_block=4,
                          solver=tq.SOLVER_CG_EO)
