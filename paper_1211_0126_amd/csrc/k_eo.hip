@@ -369,6 +369,26 @@ __global__ __launch_bounds__(256) void k_eo_merge(Geom g, Geom hg, const void* i
     }
 }
 
+// FP16 links of one parity from its FP64 links ([mu][9][Vs] double2 ->
+// [mu][3][Vs] uint4 of (re, im) binary16 pairs, entry 8 then padding)
+__global__ __launch_bounds__(256) void k_eo_links_h16(Geom hg, const void* g64, void* g16) {
+    const uint32_t h = blockIdx.x * 256u + threadIdx.x;
+    if (h >= hg.V) return;
+#pragma unroll
+    for (int mu = 0; mu < 4; mu++) {
+        uint32_t w[12];
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            const double2 v = ld_plane<double2>(g64, hg.Vs, mu * 9 + k, h);
+            w[k] = pack2_f16((float)v.x, (float)v.y);
+        }
+        w[9] = w[10] = w[11] = 0;
+#pragma unroll
+        for (int q = 0; q < 3; q++)
+            st_plane<uint4>(g16, hg.Vs, mu * 3 + q, h, make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
@@ -418,6 +438,9 @@ void launch_eo_rec_full(hipStream_t st, const EoArgs& a, int xprec, int nr, cons
     }
 }
 
+void launch_eo_links_h16(hipStream_t st, const Geom& hg, const void* g64, void* g16) {
+    hipLaunchKernelGGL(k_eo_links_h16, dim3(eo_blocks(hg)), dim3(256), 0, st, hg, g64, g16);
+}
 void launch_eo_split(hipStream_t st, const Geom& g, const Geom& hg, const void* in, int np, void* out_e,
                      void* out_o) {
     const unsigned gy = (unsigned)std::min(np, 64);
@@ -472,7 +495,7 @@ static void eo_lin_prec(hipStream_t st, const EoArgs& a, int prec, int nr) {
     switch (prec) {
     case P_F64: eo_lin_nr<DAG, PRE, POST, double, SF64, SF64, GF64>(st, a, 1); break;
     case P_F32: eo_lin_nr<DAG, PRE, POST, float, SF32, SF32, GF32>(st, a, nr); break;
-    case P_F16: eo_lin_nr<DAG, PRE, POST, float, SF16, SF16, GF32>(st, a, nr); break;
+    case P_F16: eo_lin_nr<DAG, PRE, POST, float, SF16, SF16, GH16>(st, a, nr); break;
     default: eo_lin_nr<DAG, PRE, POST, float, SBF16, SBF16, GF32>(st, a, nr); break;
     }
 }
@@ -531,7 +554,7 @@ void launch_eo_mp(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int 
     switch (prec) {
     case P_F64: eo_mp_typed<double, SF64, GF64>(st, a, e, 1); break;
     case P_F32: eo_mp_typed<float, SF32, GF32>(st, a, e, nr); break;
-    case P_F16: eo_mp_typed<float, SF16, GF32>(st, a, e, nr); break;
+    case P_F16: eo_mp_typed<float, SF16, GH16>(st, a, e, nr); break;
     default: eo_mp_typed<float, SBF16, GF32>(st, a, e, nr); break;
     }
 }
@@ -540,7 +563,7 @@ void launch_eo_upd(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int
     switch (prec) {
     case P_F64: eo_upd_typed<double, SF64, GF64, SF64, double>(st, a, e, 1, track); break;
     case P_F32: eo_upd_typed<float, SF32, GF32, SF32, float>(st, a, e, nr, track); break;
-    case P_F16: eo_upd_typed<float, SF16, GF32, SF32, float>(st, a, e, nr, track); break;
+    case P_F16: eo_upd_typed<float, SF16, GH16, SF32, float>(st, a, e, nr, track); break;
     default: eo_upd_typed<float, SBF16, GF32, SF32, float>(st, a, e, nr, track); break;
     }
 }

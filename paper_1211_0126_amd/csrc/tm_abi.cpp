@@ -355,6 +355,7 @@ tm_status tm_destroy(tm_ctx* ctx) {
     for (int q = 0; q < 2; q++) {
         if (ctx->gauge32eo[q]) (void)hipFree(ctx->gauge32eo[q]);
         if (ctx->gauge64eo[q]) (void)hipFree(ctx->gauge64eo[q]);
+        if (ctx->gauge16eo[q]) (void)hipFree(ctx->gauge16eo[q]);
     }
     if (ctx->gauge64) (void)hipFree(ctx->gauge64);
     if (ctx->gauge32) (void)hipFree(ctx->gauge32);
@@ -390,10 +391,12 @@ tm_status tm_gauge_load(tm_ctx* ctx, const double* links_host) {
         for (int q = 0; q < 2 && e == hipSuccess; q++) {
             if (!ctx->gauge32eo[q]) e = hipMalloc(&ctx->gauge32eo[q], (size_t)4 * 3 * 16 * h.Vs);
             if (e == hipSuccess && !ctx->gauge64eo[q]) e = hipMalloc(&ctx->gauge64eo[q], (size_t)4 * 9 * 16 * h.Vs);
+            if (e == hipSuccess && !ctx->gauge16eo[q]) e = hipMalloc(&ctx->gauge16eo[q], (size_t)4 * 3 * 16 * h.Vs);
         }
         if (e == hipSuccess) {
             launch_eo_split(ctx->stream, g, h, ctx->gauge32, 12, ctx->gauge32eo[0], ctx->gauge32eo[1]);
             launch_eo_split(ctx->stream, g, h, ctx->gauge64, 36, ctx->gauge64eo[0], ctx->gauge64eo[1]);
+            for (int q = 0; q < 2; q++) launch_eo_links_h16(ctx->stream, h, ctx->gauge64eo[q], ctx->gauge16eo[q]);
             e = hipGetLastError();
         }
     }

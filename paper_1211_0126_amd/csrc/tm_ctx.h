@@ -30,6 +30,7 @@ struct tm_ctx {
     tmq::Geom hgeo;
     void* gauge32eo[2] = {nullptr, nullptr};  // float4  [4][3][Vhs] per parity
     void* gauge64eo[2] = {nullptr, nullptr};  // double2 [4][9][Vhs] per parity
+    void* gauge16eo[2] = {nullptr, nullptr};  // uint4 [4][3][Vhs] per parity: binary16 pairs (FP16 storage hops)
 
     struct Buf {
         void* p = nullptr;

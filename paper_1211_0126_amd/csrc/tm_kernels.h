@@ -150,6 +150,8 @@ void launch_eo_noise(hipStream_t st, const Geom& hg, int prec, uint64_t seed_mix
                      double twist, void* eta_o, void* ye);
 // the whole solution in the full native layout from the odd half a.in
 void launch_eo_rec_full(hipStream_t st, const EoArgs& a, int xprec, int nr, const Geom& g, void* full);
+// FP16 links of one parity (the FP16-storage hops) from its FP64 links
+void launch_eo_links_h16(hipStream_t st, const Geom& hg, const void* g64, void* g16);
 void launch_eo_split(hipStream_t st, const Geom& g, const Geom& hg, const void* in, int np, void* out_e, void* out_o);
 void launch_eo_merge(hipStream_t st, const Geom& g, const Geom& hg, const void* in_e, const void* in_o, int np,
                      void* out);

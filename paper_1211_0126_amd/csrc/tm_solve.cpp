@@ -398,8 +398,11 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     const void* g32o = ctx->gauge32eo[1];
     const void* g64e = ctx->gauge64eo[0];
     const void* g64o = ctx->gauge64eo[1];
-    const void* ge = prec == P_F64 ? g64e : g32e;
-    const void* go = prec == P_F64 ? g64o : g32o;
+    // links of the iteration: FP64, FP32, or FP16 for the FP16-storage hops
+    // of the lane-per-site kernels
+    const bool h16 = prec == P_F16 && !tiles;
+    const void* ge = prec == P_F64 ? g64e : (h16 ? ctx->gauge16eo[0] : g32e);
+    const void* go = prec == P_F64 ? g64o : (h16 ? ctx->gauge16eo[1] : g32o);
     // half-hop arguments: output parity q, input field, output field
     auto lin = [&](int q, bool f64, const void* in, void* out, const void* b, double c, int n) {
         EoArgs e;
