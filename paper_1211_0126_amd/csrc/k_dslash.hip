@@ -167,6 +167,7 @@ __global__ __launch_bounds__(256) void k_cg_alpha(CgArgs a, uint32_t nb) {
         CgScal& q = a.scal[r];
         q.tt = tt;
         q.alpha = tt > 0 ? q.rr / tt : 0.0;
+        if (a.ahist) a.ahist[(size_t)r * a.ring + (q.iters % a.ring)] = q.alpha;
     }
 }
 
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(256) void k_cg_p(CgArgs a) {
     load_spinor_cp<S, R, TM_CP_K3>(pp, a.geo.Vs, s, pv);
 #pragma unroll
     for (int k = 0; k < 12; k++) pv[k] = rv[k] + beta * pv[k];
-    store_spinor<S, R>(pp, a.geo.Vs, s, pv);
+    store_spinor<S, R>(a.pn ? field_rhs<S>(a.pn, a.geo.Vs, r) : pp, a.geo.Vs, s, pv);
 }
 
 // Initialisation: r holds b = M^dag eta.  p = r, x = 0, (rho = eta), block

@@ -210,8 +210,9 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_mp(CgArgs a, EoCg e) {
 }
 
 // K2b: q = D^dag t - kappa^2 H_oe^dag y, r -= alpha q, x += alpha p, |r|^2;
-// with TRACK rho -= alpha t (rho = etahat - Mhat x) and |rho|^2
-template <typename R, class S, class G, class X, typename RX, int NR, bool TRACK>
+// with TRACK rho -= alpha t (rho = etahat - Mhat x) and |rho|^2; with XFREE
+// no x update (the directions are kept, k_eo_xflush forms x)
+template <typename R, class S, class G, class X, typename RX, int NR, bool TRACK, bool XFREE = false>
 __global__ TM_STENCIL_R(NR, R) void k_eo_upd(CgArgs a, EoCg e) {
     __shared__ double sh[4];
     const Geom& hg = a.geo;
@@ -255,14 +256,17 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_upd(CgArgs a, EoCg e) {
             round_storage<S, R>(rv);
             store_spinor_cp<S, R, TM_CP_K2>(rp, Vs, h, rv);
             prr[r] = spinor_norm2(rv);
-            load_spinor_cp<S, R, TM_CP_K2>(field_rhs<S>(a.p, Vs, r0 + r), Vs, h, pv);
-            cx<RX> xv[12];
-            void* xp = field_rhs<X>(a.x, Vs, r0 + r);
-            load_spinor_cp<X, RX, TM_CP_K2>(xp, Vs, h, xv);
-            const RX alx = (RX)alpha;
+            if (!XFREE) {
+                load_spinor_cp<S, R, TM_CP_K2>(field_rhs<S>(a.p, Vs, r0 + r), Vs, h, pv);
+                cx<RX> xv[12];
+                void* xp = field_rhs<X>(a.x, Vs, r0 + r);
+                load_spinor_cp<X, RX, TM_CP_K2>(xp, Vs, h, xv);
+                const RX alx = (RX)alpha;
 #pragma unroll
-            for (int k = 0; k < 12; k++) xv[k] = {xv[k].re + alx * (RX)pv[k].re, xv[k].im + alx * (RX)pv[k].im};
-            store_spinor_cp<X, RX, TM_CP_K2>(xp, Vs, h, xv);
+                for (int k = 0; k < 12; k++)
+                    xv[k] = {xv[k].re + alx * (RX)pv[k].re, xv[k].im + alx * (RX)pv[k].im};
+                store_spinor_cp<X, RX, TM_CP_K2>(xp, Vs, h, xv);
+            }
             if (TRACK) {
                 cx<R> rh[12];
                 void* hp = field_rhs<S>(a.rho, Vs, r0 + r);
@@ -284,6 +288,30 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_upd(CgArgs a, EoCg e) {
             if (threadIdx.x == 0) a.partials2[(size_t)(r0 + r) * nb + bm.sb] = w;
         }
     }
+}
+
+// x += sum over iterations k0 <= k < min(k1, iterations done) of alpha_k p_k,
+// p_k in slot k % ring of dirs (FP32 x, directions of storage S)
+template <class S>
+__global__ __launch_bounds__(256) void k_eo_xflush(CgArgs a, const void* dirs, size_t slot_bytes, int k0, int k1) {
+    const uint32_t h = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (h >= a.geo.V) return;
+    const int kend = min(k1, (int)a.scal[r].iters);
+    if (kend <= k0) return;
+    const long Vs = a.geo.Vs;
+    cx<float> xv[12];
+    void* xp = field_rhs<SF32>(a.x, Vs, r);
+    load_spinor_cp<SF32, float, kStream>(xp, Vs, h, xv);
+    for (int k = k0; k < kend; k++) {
+        const float al = (float)a.ahist[(size_t)r * a.ring + (k % a.ring)];
+        const void* pk = field_rhs<S>((const char*)dirs + (size_t)(k % a.ring) * slot_bytes, Vs, r);
+        cx<float> pv[12];
+        load_spinor_cp<S, float, kStream>(pk, Vs, h, pv);
+#pragma unroll
+        for (int c = 0; c < 12; c++) xv[c] = {xv[c].re + al * pv[c].re, xv[c].im + al * pv[c].im};
+    }
+    store_spinor_cp<SF32, float, kStream>(xp, Vs, h, xv);
 }
 
 // Reliable update (gated, FP64): r64 = b64 - (D^dag t64 - kappa^2 H_oe^dag
@@ -547,6 +575,47 @@ static void eo_upd_typed(hipStream_t st, const CgArgs& a, const EoCg& e, int nr,
     default:
         hipLaunchKernelGGL((k_eo_upd<R, S, G, X, RX, 1, false>), dim3(nb * (unsigned)a.nrhs), dim3(256), 0, st, a, e);
         break;
+    }
+}
+
+template <typename R, class S, class G>
+static void eo_upd_xfree_typed(hipStream_t st, const CgArgs& a, const EoCg& e, int nr, bool track) {
+    const uint32_t nb = eo_blocks(a.geo);
+    if (track) {
+        hipLaunchKernelGGL((k_eo_upd<R, S, G, SF32, float, 1, true, true>), dim3(nb * (unsigned)a.nrhs), dim3(256), 0,
+                           st, a, e);
+        return;
+    }
+    switch (nr) {
+    case 4:
+        hipLaunchKernelGGL((k_eo_upd<R, S, G, SF32, float, 4, false, true>), dim3(nb * (unsigned)(a.nrhs / 4)),
+                           dim3(256), 0, st, a, e);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_eo_upd<R, S, G, SF32, float, 2, false, true>), dim3(nb * (unsigned)(a.nrhs / 2)),
+                           dim3(256), 0, st, a, e);
+        break;
+    default:
+        hipLaunchKernelGGL((k_eo_upd<R, S, G, SF32, float, 1, false, true>), dim3(nb * (unsigned)a.nrhs), dim3(256),
+                           0, st, a, e);
+        break;
+    }
+}
+
+void launch_eo_upd_xfree(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr, bool track) {
+    switch (prec) {
+    case P_F32: eo_upd_xfree_typed<float, SF32, GF32>(st, a, e, nr, track); break;
+    case P_F16: eo_upd_xfree_typed<float, SF16, GH16>(st, a, e, nr, track); break;
+    default: eo_upd_xfree_typed<float, SBF16, GF32>(st, a, e, nr, track); break;
+    }
+}
+
+void launch_eo_xflush(hipStream_t st, const CgArgs& a, int prec, const void* dirs, size_t slot_bytes, int k0, int k1) {
+    const dim3 grid(eo_blocks(a.geo), (unsigned)a.nrhs);
+    switch (prec) {
+    case P_F32: hipLaunchKernelGGL(k_eo_xflush<SF32>, grid, dim3(256), 0, st, a, dirs, slot_bytes, k0, k1); break;
+    case P_F16: hipLaunchKernelGGL(k_eo_xflush<SF16>, grid, dim3(256), 0, st, a, dirs, slot_bytes, k0, k1); break;
+    default: hipLaunchKernelGGL(k_eo_xflush<SBF16>, grid, dim3(256), 0, st, a, dirs, slot_bytes, k0, k1); break;
     }
 }
 

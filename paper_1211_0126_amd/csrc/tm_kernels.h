@@ -25,6 +25,12 @@ struct CgArgs {
     int nrhs;
     uint32_t npart;     // block partials per right-hand side written by K1 / K2
     int tseg;           // time slices per lane of the time-marching K1 / K2
+    // search directions in a ring (even-odd CG without reduced-precision
+    // reliable updates): K3 writes p_{k+1} to pn instead of over p, the step
+    // lengths go to ahist[r][k % ring], and x is formed from them afterwards
+    void* pn;           // nullable: p = r + beta p in place
+    double* ahist;      // nullable: [nrhs][ring]
+    int ring;
 };
 
 struct ContractArgs {
@@ -132,6 +138,11 @@ void launch_eo_rec_f32(hipStream_t st, const EoArgs& a, int nr);
 void launch_eo_dinv(hipStream_t st, const Geom& hg, int prec, double twist, int nrhs, const void* in, void* out);
 void launch_eo_mp(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr);
 void launch_eo_upd(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr, bool track);
+// K2b without the solution update (directions kept in a ring), and the
+// update x += sum_k alpha_k p_k over iterations k0 <= k < min(k1, iterations
+// of the source), p_k in slot k % ring of `dirs` (slot_bytes apart)
+void launch_eo_upd_xfree(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr, bool track);
+void launch_eo_xflush(hipStream_t st, const CgArgs& a, int prec, const void* dirs, size_t slot_bytes, int k0, int k1);
 uint32_t eo_gated_blocks(const Geom& hg);
 void launch_eo_rel_resid(hipStream_t st, const CgArgs& a, const EoCg& e, const void* b64, const void* t64,
                          const void* y64);

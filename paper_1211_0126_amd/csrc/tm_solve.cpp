@@ -319,15 +319,16 @@ tm_status solve_f64_history(tm_ctx* ctx, uint64_t seed_mixed, const uint64_t* id
 struct EoBytes {
     double hop, mp, upd, p;
 };
-static EoBytes eo_bytes(const Geom& hg, int prec, int nrhs, bool track) {
+static EoBytes eo_bytes(const Geom& hg, int prec, int nrhs, bool track, bool xfree) {
     const double bs = prec == P_F64 ? 8 : (prec == P_F32 ? 4 : 2);
     const double bx = prec == P_F64 ? 8 : 4;
-    const double gb = prec == P_F64 ? 8 * 18 * 8 : 8 * 12 * 4;
+    const double gb = prec == P_F64 ? 8 * 18 * 8 : 8 * 12 * 4;  // the FP16 copy holds 9 of 12 words
     const double V = (double)hg.V;
     EoBytes b;
     b.hop = V * (nrhs * 48.0 * bs + gb);
     b.mp = V * (nrhs * 72.0 * bs + gb);
-    b.upd = V * (nrhs * (120.0 * bs + 48.0 * bx + (track ? 48.0 * bs : 0.0)) + gb);
+    // y, t, r read and r written; without the ring also p and x read, x written
+    b.upd = V * (nrhs * (96.0 * bs + (xfree ? 0.0 : 24.0 * bs + 48.0 * bx) + (track ? 48.0 * bs : 0.0)) + gb);
     b.p = V * nrhs * 72.0 * bs;
     return b;
 }
@@ -365,7 +366,21 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     a.twist = tw;
     a.nrhs = nrhs;
     a.npart = tiles ? eot_tiles(hg) : nblk;
-    a.p = ws_get(ctx, tag + "_eo_p", fbh, &s);
+    // search directions in a ring (CgArgs::pn): without reliable updates, on
+    // the lane-per-site kernels; x is formed from the step lengths every
+    // kRing - 1 iterations and at the end
+    const bool ringm = !rel && prec != P_F64 && !tiles;
+    constexpr int kRing = 8;
+    void* dirs = nullptr;
+    if (ringm) {
+        dirs = ws_get(ctx, tag + "_eo_dirs", fbh * kRing, &s);
+        a.ahist = (double*)ws_get(ctx, tag + "_eo_ahist", sizeof(double) * kMaxBlock * kRing, &s);
+        a.ring = kRing;
+        a.p = dirs;  // p_0, written by the CG start
+    } else {
+        a.p = ws_get(ctx, tag + "_eo_p", fbh, &s);
+    }
+    auto slot = [&](int k) { return (void*)((char*)dirs + (size_t)(k % kRing) * fbh); };
     a.t = ws_get(ctx, tag + "_eo_t", fbh, &s);
     a.r = ws_get(ctx, tag + "_eo_r", fbh, &s);
     a.x = ws_get(ctx, tag + "_eo_x", field_bytes(hg, xprec, nrhs), &s);
@@ -469,6 +484,7 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     ec64.geven = g64e;
     ec64.godd = g64o;
     ec64.y = y64;
+    const CgArgs a0 = a;
     const int vtag = prof_tag(prec, prec == P_F64 ? 1 : nr, TM_SOLVER_CG_EO, 0);
     const int dflt = rel ? 16 : 8;
     const std::string ckey = chunk_key(p, tag, nrhs);
@@ -480,13 +496,31 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
         n_active = active_count(ctx, nrhs);
     }
     int done = 0;
+    int k0 = 0;  // ring: first iteration not yet added to x
+    auto flush = [&](int k1) {
+        if (k1 > k0) {
+            prof_begin(ctx, TM_KC_OTHER);
+            launch_eo_xflush(st, a, prec, dirs, fbh, k0, k1);
+            prof_end(ctx, TM_KC_OTHER, 0.0);
+        }
+        k0 = k1;
+    };
     for (;;) {
         int k = chunk;
         if (p->max_iter >= 0) k = std::max(1, std::min(chunk, p->max_iter - done));
         chunk = later_chunk(ctx, dflt);
-        const EoBytes by = eo_bytes(hg, prec, n_active, track);
+        if (ringm) {
+            if (done - k0 >= kRing - 1) flush(done);
+            k = std::min(k, kRing - 1 - (done - k0));
+        }
+        const EoBytes by = eo_bytes(hg, prec, n_active, track, ringm);
         auto steps = [&](int n) {
             for (int i = 0; i < n; i++) {
+                CgArgs a = a0;  // this iteration's direction slots
+                if (ringm) {
+                    a.p = slot(done + i);
+                    a.pn = slot(done + i + 1);
+                }
                 EoArgs ey = lin(0, false, a.p, y, nullptr, 1.0, nrhs);
                 ey.act = a.scal;
                 prof_begin(ctx, TM_KC_EO_HOP, vtag);
@@ -516,6 +550,8 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
                 prof_begin(ctx, TM_KC_DSLASH_UPD, utag);
                 if (tiles)
                     launch_eot_upd(st, a, ec, prec, track ? 1 : nr, track);
+                else if (ringm)
+                    launch_eo_upd_xfree(st, a, ec, prec, track ? 1 : nr, track);
                 else
                     launch_eo_upd(st, a, ec, prec, track ? 1 : nr, track);
                 prof_end(ctx, TM_KC_DSLASH_UPD, by.upd);
@@ -547,9 +583,10 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
         };
         if (ctx->use_graphs && !ctx->prof && st != nullptr) {
             char key[512];
-            std::snprintf(key, sizeof(key), "eo|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%d",
-                          a.p, a.t, a.r, a.x, y, a.rho, (void*)a.scal, (void*)a.partials, (void*)a.partials2,
-                          x64, t64, b64, y64, prec, nr, (int)track, (int)rel, nrhs, k);
+            std::snprintf(key, sizeof(key), "eo|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%d|%d",
+                          a0.p, a0.t, a0.r, a0.x, y, a0.rho, (void*)a0.scal, (void*)a0.partials, (void*)a0.partials2,
+                          x64, t64, b64, y64, (void*)a0.ahist, prec, nr, (int)track, (int)rel, nrhs, k,
+                          ringm ? done % kRing : -1);
             auto it = ctx->graphs.find(key);
             if (it == ctx->graphs.end()) {
                 hipGraph_t graph;
@@ -577,6 +614,7 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
         if (done >= kIterCap) break;
     }
     remember_chunk(ctx, ckey, nrhs);
+    if (ringm) flush(done);
 
     // even half x_e = D^{-1} (eta_e + kappa H_eo x_o) with eta_e from the
     // hash, then the full native solution

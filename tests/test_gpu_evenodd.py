@@ -224,3 +224,34 @@ def test_eo_tsm_27_momenta_fp32(orc, tiles):
     assert np.max(np.abs(res["per_source"] - ref["per_source"])) < 1e-4 * scale
     assert np.max(np.abs(res["loops"] - ref["loops"])) < 1e-4 * np.max(np.abs(ref["loops"]))
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_eo_long_truncated_solve_ring_flushes(orc, prec):
+    """FP32 / FP16 Schur CG truncated at 20 iterations (the search
+    directions sit in a ring of 8 and the solution is formed from them every
+    7 iterations): the same iterate as the FP64 oracle's to FP32 / FP16
+    rounding, for sources of a block that stop at different counts."""
+    import paper_1211_0126_amd as tq
+    dims, kappa, mu, eps = LATTICES[1]
+    U = make_gauge(dims, eps, 61)
+    ctx = _ctx(dims, kappa, mu, U)
+    ids = [0, 1, 2, 3]
+    p = tq.solve_params(prec=prec, tol=0.0, max_iter=20, rhs_block=4, solver=tq.SOLVER_CG_EO)
+    sol, st, _ = tq.tsm_solve_batch(ctx, p, 23, ids)
+    sol = sol.cpu().numpy()
+    for i, j in enumerate(ids):
+        eta = orc.noise_z4(dims, 23, j)
+        x, so = orc.cgnr_eo(dims, -1, kappa, mu, U, eta, 0.0, 20)
+        assert st[i]["iters"] == 20
+        assert _rel(sol[i], x) < (1e-4 if prec == 1 else 2e-2), (prec, j, _rel(sol[i], x))
+    # sources that stop early (tolerance) next to ones that run on
+    p2 = tq.solve_params(prec=prec, tol=1e-4, max_iter=-1, rhs_block=4, solver=tq.SOLVER_CG_EO)
+    sol2, st2, _ = tq.tsm_solve_batch(ctx, p2, 23, ids)
+    sol2 = sol2.cpu().numpy()
+    for i, j in enumerate(ids):
+        eta = orc.noise_z4(dims, 23, j)
+        x, so = orc.cgnr_eo(dims, -1, kappa, mu, U, eta, 1e-4)
+        assert st2[i]["converged"] and abs(st2[i]["iters"] - so["iters"]) <= 1
+        assert st2[i]["resid_true"] < 2 * so["resid_true"] + (0 if prec == 1 else 1e-3)
+    ctx.close()
