@@ -287,10 +287,12 @@ __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const void* eta) {
         cx<R> rv[12], ev[12];
         load_spinor<S, R>(field_rhs<S>(a.r, Vs, r), Vs, s, rv);
         store_spinor<S, R>(field_rhs<S>(a.p, Vs, r), Vs, s, rv);
-        cx<RX> z[12];
+        if (a.x) {  // (a solve that forms x from kept directions passes none)
+            cx<RX> z[12];
 #pragma unroll
-        for (int k = 0; k < 12; k++) z[k] = {(RX)0, (RX)0};
-        store_spinor<X, RX>(field_rhs<X>(a.x, Vs, r), Vs, s, z);
+            for (int k = 0; k < 12; k++) z[k] = {(RX)0, (RX)0};
+            store_spinor<X, RX>(field_rhs<X>(a.x, Vs, r), Vs, s, z);
+        }
         pb = spinor_norm2(rv);
         load_spinor<S, R>(field_rhs<S>(eta, Vs, r), Vs, s, ev);
         pe = spinor_norm2(ev);

@@ -50,7 +50,12 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_lin(EoArgs a) {
     const Geom& hg = a.hg;
     const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
     const int r0 = bm.ch * NR;
-    if (a.gate != nullptr && !a.gate[r0].rflag) return;
+    if (a.gate != nullptr) {
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < NR; r++) any |= a.gate[r0 + r].rflag != 0;
+        if (!any) return;  // (sources of the chunk without the flag are computed and not used)
+    }
     if (a.act != nullptr) {
         bool any = false;
 #pragma unroll
@@ -291,18 +296,24 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_upd(CgArgs a, EoCg e) {
 }
 
 // x += sum over iterations k0 <= k < min(k1, iterations done) of alpha_k p_k,
-// p_k in slot k % ring of dirs (FP32 x, directions of storage S)
+// p_k in slot k % ring of dirs (FP32 x, directions of storage S); the first
+// pass (k0 = 0) writes x = the sum (x is not initialised before)
 template <class S>
 __global__ __launch_bounds__(256) void k_eo_xflush(CgArgs a, const void* dirs, size_t slot_bytes, int k0, int k1) {
     const uint32_t h = blockIdx.x * 256u + threadIdx.x;
     const int r = blockIdx.y;
     if (h >= a.geo.V) return;
     const int kend = min(k1, (int)a.scal[r].iters);
-    if (kend <= k0) return;
+    if (kend <= k0 && k0 > 0) return;
     const long Vs = a.geo.Vs;
     cx<float> xv[12];
     void* xp = field_rhs<SF32>(a.x, Vs, r);
-    load_spinor_cp<SF32, float, kStream>(xp, Vs, h, xv);
+    if (k0 > 0) {
+        load_spinor_cp<SF32, float, kStream>(xp, Vs, h, xv);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 12; c++) xv[c] = {0.f, 0.f};
+    }
     for (int k = k0; k < kend; k++) {
         const float al = (float)a.ahist[(size_t)r * a.ring + (k % a.ring)];
         const void* pk = field_rhs<S>((const char*)dirs + (size_t)(k % a.ring) * slot_bytes, Vs, r);
@@ -316,51 +327,68 @@ __global__ __launch_bounds__(256) void k_eo_xflush(CgArgs a, const void* dirs, s
 
 // Reliable update (gated, FP64): r64 = b64 - (D^dag t64 - kappa^2 H_oe^dag
 // y64) with t64 = Mhat x64 and y64 = D^{-dag} H_eo^dag t64, r32 = r64, block
-// partials of |r64|^2 and (a.eta64 = etahat set) of |etahat - t64|^2
-__global__ TM_STENCIL_R(1, double) void k_eo_rel_resid(CgArgs a, EoCg e, const void* b64, const void* t64,
-                                                      const void* y64) {
+// partials of |r64|^2 and (a.eta64 = etahat set) of |etahat - t64|^2; NR
+// sources per lane, a chunk runs if any of its sources has the flag
+template <int NR>
+__global__ TM_STENCIL_R(NR, double) void k_eo_rel_resid(CgArgs a, EoCg e, const void* b64, const void* t64,
+                                                       const void* y64) {
     __shared__ double sh[4];
-    const int r = blockIdx.y;
-    if (!a.scal[r].rflag) return;
+    const int r0 = blockIdx.y * NR;
+    bool flag[NR];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        flag[r] = a.scal[r0 + r].rflag != 0;
+        any |= flag[r];
+    }
+    if (!any) return;
     const Geom& hg = a.geo;
     const long Vs = hg.Vs;
     const uint32_t nsb = (uint32_t)((hg.V + 255) / 256);
-    const void* t0 = field_rhs<SF64>(t64, Vs, r);
-    double pr = 0, pt = 0;
+    double pr[NR], pt[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) pr[r] = pt[r] = 0;
+    const double k2 = -a.kappa * a.kappa;
     for (uint32_t sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
         const uint32_t h = sb * 256u + threadIdx.x;
         if (h >= hg.V) continue;
         const EoSite c = eo_coords(hg, h, 1);
-        cx<double> acc[1][12];
-        eo_hop_all<true, double, SF64, GF64, 1>(hg, e.godd, e.geven, field_rhs<SF64>(y64, Vs, r), h, c, acc);
-        cx<double> tc[12], q[12], bv[12];
-        load_spinor<SF64, double>(t0, Vs, h, tc);
+        cx<double> acc[NR][12];
+        eo_hop_all<true, double, SF64, GF64, NR>(hg, e.godd, e.geven, field_rhs<SF64>(y64, Vs, r0), h, c, acc);
 #pragma unroll
-        for (int k = 0; k < 12; k++) q[k] = tc[k];
-        mul_diag(q, -a.twist);
-        const double k2 = -a.kappa * a.kappa;
-        load_spinor<SF64, double>(field_rhs<SF64>(b64, Vs, r), Vs, h, bv);
-        cx<float> rf[12];
+        for (int r = 0; r < NR; r++) {
+            if (!flag[r]) continue;
+            cx<double> tc[12], q[12], bv[12];
+            load_spinor<SF64, double>(field_rhs<SF64>(t64, Vs, r0 + r), Vs, h, tc);
 #pragma unroll
-        for (int k = 0; k < 12; k++) {
-            bv[k] = bv[k] - (q[k] + k2 * acc[0][k]);
-            rf[k] = {(float)bv[k].re, (float)bv[k].im};
-        }
-        store_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r), Vs, h, rf);
-        pr += spinor_norm2(bv);
-        if (a.eta64) {
-            cx<double> ev[12];
-            load_spinor<SF64, double>(field_rhs<SF64>(a.eta64, Vs, r), Vs, h, ev);
+            for (int k = 0; k < 12; k++) q[k] = tc[k];
+            mul_diag(q, -a.twist);
+            load_spinor<SF64, double>(field_rhs<SF64>(b64, Vs, r0 + r), Vs, h, bv);
+            cx<float> rf[12];
 #pragma unroll
-            for (int k = 0; k < 12; k++) ev[k] = ev[k] - tc[k];
-            pt += spinor_norm2(ev);
+            for (int k = 0; k < 12; k++) {
+                bv[k] = bv[k] - (q[k] + k2 * acc[r][k]);
+                rf[k] = {(float)bv[k].re, (float)bv[k].im};
+            }
+            store_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r0 + r), Vs, h, rf);
+            pr[r] += spinor_norm2(bv);
+            if (a.eta64) {
+                cx<double> ev[12];
+                load_spinor<SF64, double>(field_rhs<SF64>(a.eta64, Vs, r0 + r), Vs, h, ev);
+#pragma unroll
+                for (int k = 0; k < 12; k++) ev[k] = ev[k] - tc[k];
+                pt[r] += spinor_norm2(ev);
+            }
         }
     }
-    double v = block_sum256(pr, sh);
-    if (threadIdx.x == 0) a.partials[(size_t)r * gridDim.x + blockIdx.x] = v;
-    if (a.eta64) {
-        double w = block_sum256(pt, sh);
-        if (threadIdx.x == 0) a.partials2[(size_t)r * gridDim.x + blockIdx.x] = w;
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        double v = block_sum256(pr[r], sh);
+        if (threadIdx.x == 0) a.partials[(size_t)(r0 + r) * gridDim.x + blockIdx.x] = v;
+        if (a.eta64) {
+            double w = block_sum256(pt[r], sh);
+            if (threadIdx.x == 0) a.partials2[(size_t)(r0 + r) * gridDim.x + blockIdx.x] = w;
+        }
     }
 }
 
@@ -446,8 +474,12 @@ void launch_eo_noise(hipStream_t st, const Geom& hg, int prec, uint64_t seed_mix
 void launch_eo_rec_full(hipStream_t st, const EoArgs& a, int xprec, int nr, const Geom& g, void* full) {
     const uint32_t nb = eo_blocks(a.hg);
     if (xprec == P_F64) {
-        hipLaunchKernelGGL((k_eo_rec_full<double, SF64, GF64, 1>), dim3(nb * (unsigned)a.nrhs), dim3(256), 0, st, a,
-                           g, full);
+        if (nr >= 2)
+            hipLaunchKernelGGL((k_eo_rec_full<double, SF64, GF64, 2>), dim3(nb * (unsigned)(a.nrhs / 2)), dim3(256), 0,
+                               st, a, g, full);
+        else
+            hipLaunchKernelGGL((k_eo_rec_full<double, SF64, GF64, 1>), dim3(nb * (unsigned)a.nrhs), dim3(256), 0, st,
+                               a, g, full);
         return;
     }
     switch (nr) {
@@ -495,13 +527,17 @@ void launch_eo_dinv(hipStream_t st, const Geom& hg, int prec, double twist, int 
 template <bool DAG, bool PRE, bool POST, typename R, class Si, class So, class G>
 static void eo_lin_nr(hipStream_t st, const EoArgs& a, int nr) {
     const uint32_t nb = eo_blocks(a.hg);
+    if constexpr (sizeof(R) == 8) nr = std::min(nr, 2);
     if (a.gate != nullptr) {
         const unsigned gb = std::min(nb, kEoGatedBlocks);
-        hipLaunchKernelGGL((k_eo_lin<DAG, PRE, POST, R, Si, So, G, 1>), dim3(gb * (unsigned)a.nrhs), dim3(256), 0, st,
-                           a);
+        if (nr == 2)
+            hipLaunchKernelGGL((k_eo_lin<DAG, PRE, POST, R, Si, So, G, 2>), dim3(gb * (unsigned)(a.nrhs / 2)),
+                               dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_eo_lin<DAG, PRE, POST, R, Si, So, G, 1>), dim3(gb * (unsigned)a.nrhs), dim3(256),
+                               0, st, a);
         return;
     }
-    if constexpr (sizeof(R) == 8) nr = 1;
     switch (nr) {
     case 4:
         hipLaunchKernelGGL((k_eo_lin<DAG, PRE, POST, R, Si, So, G, 4>), dim3(nb * (unsigned)(a.nrhs / 4)), dim3(256),
@@ -640,9 +676,12 @@ void launch_eo_upd(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int
 uint32_t eo_gated_blocks(const Geom& hg) { return std::min(eo_blocks(hg), kEoGatedBlocks); }
 
 void launch_eo_rel_resid(hipStream_t st, const CgArgs& a, const EoCg& e, const void* b64, const void* t64,
-                         const void* y64) {
+                         const void* y64, int nr) {
     const uint32_t nb = eo_gated_blocks(a.geo);
-    hipLaunchKernelGGL(k_eo_rel_resid, dim3(nb, (unsigned)a.nrhs), dim3(256), 0, st, a, e, b64, t64, y64);
+    if (nr == 2)
+        hipLaunchKernelGGL(k_eo_rel_resid<2>, dim3(nb, (unsigned)(a.nrhs / 2)), dim3(256), 0, st, a, e, b64, t64, y64);
+    else
+        hipLaunchKernelGGL(k_eo_rel_resid<1>, dim3(nb, (unsigned)a.nrhs), dim3(256), 0, st, a, e, b64, t64, y64);
 }
 
 }  // namespace tmq

@@ -145,7 +145,7 @@ void launch_eo_upd_xfree(hipStream_t st, const CgArgs& a, const EoCg& e, int pre
 void launch_eo_xflush(hipStream_t st, const CgArgs& a, int prec, const void* dirs, size_t slot_bytes, int k0, int k1);
 uint32_t eo_gated_blocks(const Geom& hg);
 void launch_eo_rel_resid(hipStream_t st, const CgArgs& a, const EoCg& e, const void* b64, const void* t64,
-                         const void* y64);
+                         const void* y64, int nr);
 // the same half-hops with the links of a tile of 64 half-sites staged in LDS
 // and shared by all right-hand sides (FP32 links; FP32/FP16/BF16 storage);
 // reductions write eot_tiles(hg) partials per right-hand side

@@ -396,7 +396,9 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     // source preparation at the iteration precision (FP64 with reliable
     // updates); the tile kernels take the sources from the hash
     const int sp = rel ? P_F64 : prec;
-    const int snr = sp == P_F64 ? 1 : nr;
+    // FP64 half-hops: two sources per lane (the links are read once per pair)
+    const int nr64 = nrhs % 2 == 0 ? 2 : 1;
+    const int snr = sp == P_F64 ? nr64 : nr;
     void* eta_o = tiles && !rel ? nullptr : ws_get(ctx, tag + "_eo_etao", field_bytes(hg, sp, nrhs), &s);
     void* eh = ws_get(ctx, tag + "_eo_eh", field_bytes(hg, sp, nrhs), &s);
     void *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *y64 = nullptr;
@@ -458,19 +460,21 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
         CgArgs ai = a;
         ai.scal = nullptr;
         launch_eot_mp(st, ai, ei, prec, nr, true, eh, a.r);
-        launch_cg_init(st, a, prec, track, eh, ee_z4);
+        launch_cg_init(st, a, prec, track, eh, ee_z4);  // (the tile path updates x: no ring)
     } else {
         // eta_o and D^{-1} eta_e, then etahat, y = D^{-dag} H_eo^dag etahat and b
         launch_eo_noise(st, hg, sp, seed_mixed, ids_dev, nrhs, tw, eta_o, ys);
         launch_eo_lin(st, lin(1, rel, ys, eh, eta_o, kappa, nrhs), sp, snr, EO_SRC);
         launch_eo_lin(st, lin(0, rel, eh, ys, nullptr, 1.0, nrhs), sp, snr, EO_Y_DAG);
         if (rel) {
-            launch_eo_lin(st, lin(1, true, ys, b64, eh, k2, nrhs), P_F64, 1, EO_T_DAG);
+            launch_eo_lin(st, lin(1, true, ys, b64, eh, k2, nrhs), P_F64, nr64, EO_T_DAG);
             if (p->stop == TM_STOP_TRUE) a.eta64 = eh;
             launch_rel_init(st, a, b64, x64, ee_z4);
         } else {
             launch_eo_lin(st, lin(1, false, ys, a.r, eh, k2, nrhs), prec, snr, EO_T_DAG);
-            launch_cg_init(st, a, prec, track, eh, ee_z4);
+            CgArgs ai = a;
+            if (ringm) ai.x = nullptr;  // x is written by the first pass over the kept directions
+            launch_cg_init(st, ai, prec, track, eh, ee_z4);
         }
     }
     prof_end(ctx, TM_KC_OTHER, 0.0);
@@ -565,14 +569,14 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
                     launch_rel_flush(st, a, x64, 0);
                     EoArgs e1 = lin(0, true, x64, y64, nullptr, 1.0, nrhs);
                     e1.gate = a.scal;
-                    launch_eo_lin(st, e1, P_F64, 1, EO_Y);
+                    launch_eo_lin(st, e1, P_F64, nr64, EO_Y);
                     EoArgs e2 = lin(1, true, y64, t64, x64, k2, nrhs);
                     e2.gate = a.scal;
-                    launch_eo_lin(st, e2, P_F64, 1, EO_T);
+                    launch_eo_lin(st, e2, P_F64, nr64, EO_T);
                     EoArgs e3 = lin(0, true, t64, y64, nullptr, 1.0, nrhs);
                     e3.gate = a.scal;
-                    launch_eo_lin(st, e3, P_F64, 1, EO_Y_DAG);
-                    launch_eo_rel_resid(st, a, ec64, b64, t64, y64);
+                    launch_eo_lin(st, e3, P_F64, nr64, EO_Y_DAG);
+                    launch_eo_rel_resid(st, a, ec64, b64, t64, y64, nr64);
                     launch_rel_fin(st, a, eo_gated_blocks(hg));
                     prof_end(ctx, TM_KC_OTHER, 0.0);
                 }
@@ -621,7 +625,7 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     prof_begin(ctx, TM_KC_OTHER);
     if (rel) {
         launch_rel_flush(st, a, x64, 1);
-        launch_eo_rec_full(st, lin(0, true, x64, nullptr, nullptr, kappa, nrhs), P_F64, 1, g, xfull);
+        launch_eo_rec_full(st, lin(0, true, x64, nullptr, nullptr, kappa, nrhs), P_F64, nr64, g, xfull);
     } else if (tiles) {
         launch_eot_rec(st, lin(0, false, a.x, nullptr, nullptr, kappa, nrhs), nr, g, xfull);
     } else {
@@ -630,7 +634,7 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
             e.gout = g32e;
             e.gin = g32o;
         }
-        launch_eo_rec_full(st, e, xprec, prec == P_F64 ? 1 : nr, g, xfull);
+        launch_eo_rec_full(st, e, xprec, prec == P_F64 ? nr64 : nr, g, xfull);
     }
     prof_end(ctx, TM_KC_OTHER, 0.0);
     res->x = xfull;
