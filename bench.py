@@ -191,16 +191,33 @@ def main():
     log("gauge generated in %.1f s" % (time.time() - t0))
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
-    ctx = tq.tm_create(wl.dims, wl.kappa, wl.mu, wl.t_bc, stream=stream)
-    tq.tm_gauge_load(ctx, U)
-    del U
     mom = wl.momenta()
     lp_prec = PREC_NAMES[args.lp_prec]
-    from paper_1211_0126_amd import tuning_cache
     solver = tq.SOLVER_CG_EO if args.solver == "eo" else tq.SOLVER_CG
-    tune = {}
     n_lp0 = args.n_lp if args.n_lp is not None else wl.n_lp
     n_hp0 = args.n_hp if args.n_hp is not None else wl.n_hp
+    # the workspace (caller-owned, torch memory) sized for what this run does:
+    # LP blocks up to 32 (also with the tracked true residual of the
+    # equal-residual comparison), HP blocks up to 16 with reliable updates,
+    # the FP64 LP comparison, the learned flexible CG and its training, every
+    # estimator, four sources at all momenta
+    solves = [tq.solve_params(prec=lp_prec, stop=tq.STOP_TRUE, rhs_block=args.lp_block or 32, solver=solver),
+              tq.solve_params(prec=tq.PREC_F32, reliable=1, stop=tq.STOP_TRUE, rhs_block=args.hp_block or 16,
+                              solver=solver),
+              tq.solve_params(prec=tq.PREC_F64, rhs_block=8, solver=solver)]
+    if not args.no_learned:
+        solves.append(tq.solve_params(prec=tq.PREC_F32, stop=tq.STOP_TRUE, rhs_block=8,
+                                      solver=tq.SOLVER_FCG_LEARNED))
+    caps = tq.caps(solves, max_sources=max(n_hp0 + n_lp0, 64), max_mom=len(mom), mom_distinct=3,
+                   estimators=(0, 1, 2, 3), all_mom_sources=4, field_rhs=1,
+                   train_pairs=0 if args.no_learned else args.train_pairs,
+                   train_sources=0 if args.no_learned else args.train_sources)
+    ctx = tq.tm_create(wl.dims, wl.kappa, wl.mu, wl.t_bc, stream=stream, caps=caps)
+    log("workspace: %.2f GB (torch tensor, caller-owned)" % (ctx.workspace.numel() / 1e9))
+    tq.tm_gauge_load(ctx, U)
+    del U
+    from paper_1211_0126_amd import tuning_cache
+    tune = {}
     # block candidates and the block used with a fixed kernel configuration
     for role, prec, blk, fixed, cands, dflt, nsrc in (
             ("lp", lp_prec, args.lp_block, args.lp_config, (4, 8, 16, 32), 16, n_lp0),
@@ -332,6 +349,7 @@ def main():
             "solver": "CG on the even-odd Schur complement" if args.solver == "eo" else "CG on M^dag M",
         },
         "autotune": tune,
+        "workspace": ctx.workspace_usage(),
         "graph_replays_timed": graph_replays,
         "ms_profiled_step": round(ms_profiled_step, 1),
         "lp_phase_sources_per_s": round(n_lp / (run["ms_lp_phase"] / 1e3), 2),

@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define TM_ABI_VERSION 2
+#define TM_ABI_VERSION 3
 
 typedef int32_t tm_status;
 enum {
@@ -70,7 +70,7 @@ enum {
     TM_WARN_NOT_CONVERGED = 1, /* a solve with no iteration cap missed its tolerance */
     TM_WARN_FALLBACK = 2,      /* the learned preconditioner fell back to plain CG */
     TM_EINVAL = -1,            /* invalid argument */
-    TM_ENOMEM = -2,            /* device allocation failed */
+    TM_ENOMEM = -2,            /* the workspace cannot hold the call's buffers (tm_workspace_bytes) */
     TM_EDEVICE = -3,           /* HIP runtime error (sticky) */
     TM_ESTATE = -4,            /* call out of order (e.g. no gauge field loaded) */
     TM_ENOTSUP = -5            /* combination not supported */
@@ -131,6 +131,11 @@ typedef struct {
     double delta;       /* reliable-update trigger: |r| < delta * max |r| since the last update */
     int32_t rhs_block;  /* sources per launch, 1..32; 0 = library default */
     int32_t true_resid; /* 1: compute the FP64 true residual of every solve (one FP64 M) */
+    int32_t out_layout; /* tm_layout of the solutions tsm_solve_batch writes: TM_LAYOUT_CANONICAL
+                           [nsrc][V][4][3] complex, or TM_LAYOUT_NATIVE (tm_field_bytes(ctx,
+                           out_prec, nsrc, TM_LAYOUT_NATIVE), the input of a native tm_dslash) */
+    int32_t out_prec;   /* tm_prec of those solutions (F64: complex128, F32: complex64, F16 /
+                           BF16: pairs of binary16 / bfloat16), rounded from the solve's own */
 } tsm_solve_params;
 
 /* Per-source solve record. */
@@ -193,20 +198,66 @@ typedef struct {
     int32_t reserved;
 } tsm_run_stats;
 
+/* What a context will be asked to do, for tm_workspace_bytes.  Every count
+   is a maximum over the calls the context will see. */
+#define TM_CAPS_MAX_SOLVES 4
+typedef struct {
+    int32_t n_solves;       /* entries of solves[] */
+    tsm_solve_params solves[TM_CAPS_MAX_SOLVES]; /* the solve settings of the tsm_solve_batch calls,
+                               of both the lp and the hp of tsm_loops (any two entries may pair), and
+                               the precision and block (rhs_block; 0: its default) of the autotuners */
+    int32_t max_sources;    /* sources of one tsm_solve_batch, tsm_loops or tsm_contract call */
+    int32_t max_mom;        /* momenta of one loop call */
+    int32_t mom_distinct;   /* distinct values of one momentum component among them (0: max_mom;
+                               3 for the 27 momenta with components in -1..1) */
+    uint32_t estimators;    /* loop estimators used: bits 1 << tm_loop_estimator (0: standard only) */
+    int32_t all_mom_sources;/* sources of one tsm_contract call at TM_ALL_MOMENTA (0: none) */
+    int32_t field_rhs;      /* right-hand sides of one canonical-layout tm_dslash or of one
+                               tm_precond_apply call */
+    int32_t train_pairs;    /* pairs of one tm_precond_train call (0: no training) */
+    int32_t train_sources;  /* sources of one tm_precond_train call */
+    int32_t loss_pairs;     /* pairs of one tm_precond_loss_grad call */
+} tm_caps;
+
 /* ---- lifecycle ---------------------------------------------------------- */
 
 /* ABI version (TM_ABI_VERSION). */
 int32_t tm_abi_version(void);
 
-/* Create a context for one lattice on the current HIP device.  hip_stream is
-   a hipStream_t (NULL: the null stream).  TM_EINVAL for dims < 2 or for
-   lattices whose volume, padded to the plane stride (an odd multiple of
-   256), exceeds 7,456,512 sites (planes are addressed with 32-bit byte
-   offsets: 48^3 x 64 fits, 48^3 x 96 does not); tm_last_error(NULL) says
-   why. */
-tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out);
+/* Bytes of device workspace a context of this lattice needs for the calls
+   caps describes (caps NULL: every solver and storage precision, with and
+   without reliable updates and true-residual stops, at 32 sources per block;
+   256 sources and 27 momenta with components in 3 values per call, every
+   estimator, 4 sources at all momenta, 32 right-hand sides per operator
+   call, 64 training and loss pairs from 64 sources).  The links, tables and network weights the
+   context keeps, plus the largest scratch of one call, each buffer rounded
+   to 256 B.  0 for a lattice tm_create refuses. */
+size_t tm_workspace_bytes(const tm_lattice* lat, const tm_caps* caps);
 
-/* Release every device buffer and the context. */
+/* Create a context for one lattice on the current HIP device.  dev_ws is
+   the caller's device workspace of ws_bytes (256-byte aligned; e.g. a torch
+   uint8 tensor of tm_workspace_bytes(lat, caps)); it must stay allocated,
+   and untouched by the caller, until tm_destroy.  Every device buffer of
+   the context is carved from it: the links, tables and network weights
+   from its top, the scratch of each call from its bottom (released when the
+   next call begins).  The library allocates no device memory after
+   tm_create; a call whose buffers do not fit returns TM_ENOMEM before it
+   enqueues work.  dev_ws NULL: tm_create allocates ws_bytes itself (once;
+   tm_destroy releases it).  tm_create zeroes the workspace and allocates a
+   small pinned host buffer.  hip_stream is a hipStream_t (NULL: the null
+   stream).  TM_EINVAL for dims < 2 or for lattices whose volume, padded to
+   the plane stride (an odd multiple of 256), exceeds 7,456,512 sites
+   (planes are addressed with 32-bit byte offsets: 48^3 x 64 fits, 48^3 x
+   96 does not), TM_ENOMEM for a workspace below the context's own tables;
+   tm_last_error(NULL) says why. */
+tm_status tm_create(const tm_lattice* lat, void* dev_ws, size_t ws_bytes, void* hip_stream, tm_ctx** out);
+
+/* Bytes of the workspace the context holds until tm_destroy (persistent),
+   the most scratch one call has used since tm_create (peak_scratch), and
+   the workspace size (total).  Any pointer may be NULL. */
+tm_status tm_workspace_usage(const tm_ctx* ctx, size_t* persistent, size_t* peak_scratch, size_t* total);
+
+/* Release the context (and the workspace if tm_create allocated it). */
 tm_status tm_destroy(tm_ctx* ctx);
 
 /* Text of the last error on this context (never NULL). */
@@ -264,12 +315,14 @@ tm_status tm_noise_z4(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* 
 /* ---- solves ------------------------------------------------------------- */
 
 /* Solve M s_j = eta_j (section 2.2) for the Z4 sources of the given ids with
-   CG on M^dag M from s = 0.  sol_dev (nullable) receives the solutions as
-   canonical complex128 [nsrc][V][4][3]; stats_host receives nsrc records.
-   Synchronous.  Returns TM_WARN_NOT_CONVERGED if a solve with max_iter = -1
-   stopped without reaching tol (cannot happen with an iteration cap). */
+   CG on M^dag M from s = 0.  sol_dev (nullable, caller-owned device memory)
+   receives the solutions in params->out_layout and params->out_prec
+   (canonical complex128 [nsrc][V][4][3] for zeroed fields); stats_host
+   receives nsrc records.  Synchronous.  Returns TM_WARN_NOT_CONVERGED if a
+   solve with max_iter = -1 stopped without reaching tol (cannot happen with
+   an iteration cap). */
 tm_status tsm_solve_batch(tm_ctx* ctx, const tsm_solve_params* params, uint64_t seed, int32_t nsrc,
-                          const uint64_t* ids_host, double* sol_dev, tsm_solve_stats* stats_host);
+                          const uint64_t* ids_host, void* sol_dev, tsm_solve_stats* stats_host);
 
 /* ---- loops -------------------------------------------------------------- */
 

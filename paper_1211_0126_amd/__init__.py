@@ -9,8 +9,11 @@ and a thin ctypes binding with the same entry-point names.
 
 from .binding_tuning import tm_set_graphs, tm_profile_entries, tm_set_march, tm_autotune_cg, tm_set_eo_tiles, tm_autotune_eo  # noqa: F401
 from .binding import (  # noqa: F401
+    Caps,
     Context,
     TmError,
+    caps,
+    tm_workspace_bytes,
     load_library,
     solve_params,
     tm_abi_version,

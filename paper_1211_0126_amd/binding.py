@@ -1,8 +1,9 @@
 """Thin ctypes binding of libtmqcd.so (the C ABI in include/tmqcd.h).
 
 Argument marshalling only: every step of the computation runs in the HIP
-library.  torch supplies device memory and the stream.  There is no CPU
-fallback: if the library is not built, loading it raises.
+library.  torch supplies device memory (the context's workspace, sized by
+tm_workspace_bytes, and every input and output field) and the stream.
+There is no CPU fallback: if the library is not built, loading it raises.
 """
 
 from __future__ import annotations
@@ -41,7 +42,8 @@ class Lattice(ctypes.Structure):
 class SolveParams(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("solver", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("stop", ctypes.c_int32), ("reliable", ctypes.c_int32),
-                ("delta", ctypes.c_double), ("rhs_block", ctypes.c_int32), ("true_resid", ctypes.c_int32)]
+                ("delta", ctypes.c_double), ("rhs_block", ctypes.c_int32), ("true_resid", ctypes.c_int32),
+                ("out_layout", ctypes.c_int32), ("out_prec", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -56,6 +58,33 @@ class TsmParams(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+CAPS_MAX_SOLVES = 4
+
+
+class Caps(ctypes.Structure):
+    _fields_ = [("n_solves", ctypes.c_int32), ("solves", SolveParams * CAPS_MAX_SOLVES),
+                ("max_sources", ctypes.c_int32), ("max_mom", ctypes.c_int32), ("mom_distinct", ctypes.c_int32),
+                ("estimators", ctypes.c_uint32), ("all_mom_sources", ctypes.c_int32), ("field_rhs", ctypes.c_int32),
+                ("train_pairs", ctypes.c_int32), ("train_sources", ctypes.c_int32), ("loss_pairs", ctypes.c_int32)]
+
+
+def caps(solves=(), max_sources=64, max_mom=27, mom_distinct=3, estimators=(LOOP_STANDARD,), all_mom_sources=0,
+         field_rhs=1, train_pairs=0, train_sources=0, loss_pairs=0) -> Caps:
+    """What a context will be asked to do (tm_caps): the solve settings (at
+    most four SolveParams), and the per-call maxima of the other calls."""
+    solves = list(solves)
+    assert len(solves) <= CAPS_MAX_SOLVES
+    c = Caps()
+    c.n_solves = len(solves)
+    for i, sp in enumerate(solves):
+        c.solves[i] = sp
+    c.max_sources, c.max_mom, c.mom_distinct = int(max_sources), int(max_mom), int(mom_distinct)
+    c.estimators = sum(1 << int(e) for e in estimators)
+    c.all_mom_sources, c.field_rhs = int(all_mom_sources), int(field_rhs)
+    c.train_pairs, c.train_sources, c.loss_pairs = int(train_pairs), int(train_sources), int(loss_pairs)
+    return c
+
+
 class RunStats(ctypes.Structure):
     _fields_ = [("ms_hp_phase", ctypes.c_double), ("ms_lp_phase", ctypes.c_double), ("lp_iters", ctypes.c_int64),
                 ("hp_iters", ctypes.c_int64), ("max_lp_resid_true", ctypes.c_double),
@@ -67,7 +96,7 @@ EXPORTS = [
     "tm_abi_version", "tm_create", "tm_destroy", "tm_last_error", "tm_gauge_load", "tm_field_bytes",
     "tm_field_convert", "tm_dslash", "tm_dslash_noalloc", "tm_noise_z4", "tsm_solve_batch", "tsm_contract", "tsm_contract_est",
     "tsm_loops",
-    "tm_profile_enable", "tm_profile_read",
+    "tm_profile_enable", "tm_profile_read", "tm_workspace_bytes", "tm_workspace_usage",
 ]
 
 _lib = None
@@ -87,7 +116,10 @@ def load_library(path: str = LIB_PATH):
     lib = ctypes.CDLL(path)
     P, i32, u64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_double
     lib.tm_abi_version.restype = i32
-    lib.tm_create.argtypes = [ctypes.POINTER(Lattice), P, ctypes.POINTER(P)]
+    lib.tm_create.argtypes = [ctypes.POINTER(Lattice), P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+    lib.tm_workspace_bytes.argtypes = [ctypes.POINTER(Lattice), ctypes.POINTER(Caps)]
+    lib.tm_workspace_bytes.restype = ctypes.c_size_t
+    lib.tm_workspace_usage.argtypes = [P, P, P, P]
     lib.tm_destroy.argtypes = [P]
     lib.tm_last_error.argtypes = [P]
     lib.tm_last_error.restype = ctypes.c_char_p
@@ -105,7 +137,7 @@ def load_library(path: str = LIB_PATH):
     lib.tm_profile_enable.argtypes = [P, i32]
     lib.tm_profile_read.argtypes = [P, P, P, P]
     for name in EXPORTS:
-        if name != "tm_abi_version" and name != "tm_last_error" and name != "tm_field_bytes":
+        if name not in ("tm_abi_version", "tm_last_error", "tm_field_bytes", "tm_workspace_bytes"):
             getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -116,33 +148,66 @@ def _ptr(a: np.ndarray):
 
 
 def solve_params(prec=PREC_F64, tol=1e-10, max_iter=-1, stop=STOP_NORMAL, reliable=0, delta=0.1, rhs_block=0,
-                 true_resid=1, solver=SOLVER_CG) -> SolveParams:
-    return SolveParams(prec, solver, tol, max_iter, stop, reliable, delta, rhs_block, true_resid)
+                 true_resid=1, solver=SOLVER_CG, out_layout=LAYOUT_CANONICAL, out_prec=PREC_F64) -> SolveParams:
+    return SolveParams(prec, solver, tol, max_iter, stop, reliable, delta, rhs_block, true_resid, out_layout,
+                       out_prec)
+
+
+def _lattice(dims, kappa, mu, t_bc) -> Lattice:
+    return Lattice((ctypes.c_int32 * 4)(*[int(d) for d in dims]), float(kappa), float(mu), int(t_bc))
+
+
+def tm_workspace_bytes(dims, kappa=0.1, mu=0.0, t_bc=-1, caps_=None) -> int:
+    """Workspace bytes for a context of this lattice doing what caps_ (a
+    Caps; None: every solver and precision at 32 sources per block)
+    describes; 0 for a lattice tm_create refuses."""
+    lat = _lattice(dims, kappa, mu, t_bc)
+    return int(load_library().tm_workspace_bytes(ctypes.byref(lat), ctypes.byref(caps_) if caps_ is not None
+                                                 else None))
 
 
 class Context:
-    """One lattice on the current device; wraps a tm_ctx*."""
+    """One lattice on the current device; wraps a tm_ctx* and owns its
+    workspace (a torch uint8 tensor of tm_workspace_bytes(caps) bytes, or of
+    workspace_bytes if given)."""
 
-    def __init__(self, dims, kappa, mu, t_bc=-1, stream=None):
+    def __init__(self, dims, kappa, mu, t_bc=-1, stream=None, caps=None, workspace_bytes=None):
         import torch
         self.lib = load_library()
         self.dims = tuple(int(d) for d in dims)
         self.kappa, self.mu, self.t_bc = float(kappa), float(mu), int(t_bc)
         self.V = int(np.prod(self.dims))
-        lat = Lattice((ctypes.c_int32 * 4)(*self.dims), float(kappa), float(mu), int(t_bc))
+        lat = _lattice(self.dims, kappa, mu, t_bc)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        if workspace_bytes is None:
+            workspace_bytes = int(self.lib.tm_workspace_bytes(ctypes.byref(lat),
+                                                              ctypes.byref(caps) if caps is not None else None))
+            if workspace_bytes == 0:
+                self.lib.tm_create(ctypes.byref(lat), None, 0, None, ctypes.byref(ctypes.c_void_p()))
+                raise TmError(TM_EINVAL, self.lib.tm_last_error(None).decode())
+        self.workspace = torch.empty(max(int(workspace_bytes), 1), dtype=torch.uint8, device="cuda")
         h = ctypes.c_void_p()
-        rc = self.lib.tm_create(ctypes.byref(lat), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
+        rc = self.lib.tm_create(ctypes.byref(lat), ctypes.c_void_p(self.workspace.data_ptr()),
+                                int(workspace_bytes), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h))
         if rc != TM_OK:
+            self.workspace = None
             raise TmError(rc, self.lib.tm_last_error(None).decode())
         self.h = h
 
     def close(self):
         if getattr(self, "h", None):
-            self.lib.tm_destroy(self.h)
+            self.lib.tm_destroy(self.h)  # waits for the context's stream
             self.h = None
+        self.workspace = None
+
+    def workspace_usage(self) -> dict:
+        """Bytes held until close (persistent), the most scratch one call has
+        used (peak_scratch), and the workspace size (total)."""
+        v = [ctypes.c_size_t() for _ in range(3)]
+        self.check(self.lib.tm_workspace_usage(self.h, *[ctypes.byref(x) for x in v]))
+        return {"persistent": v[0].value, "peak_scratch": v[1].value, "total": v[2].value}
 
     def __del__(self):
         try:
@@ -160,8 +225,8 @@ def tm_abi_version() -> int:
     return int(load_library().tm_abi_version())
 
 
-def tm_create(dims, kappa, mu, t_bc=-1, stream=None) -> Context:
-    return Context(dims, kappa, mu, t_bc, stream)
+def tm_create(dims, kappa, mu, t_bc=-1, stream=None, caps=None, workspace_bytes=None) -> Context:
+    return Context(dims, kappa, mu, t_bc, stream, caps, workspace_bytes)
 
 
 def tm_gauge_load(ctx: Context, links: np.ndarray) -> None:
@@ -239,11 +304,21 @@ def _stats_list(st):
 
 
 def tsm_solve_batch(ctx: Context, params: SolveParams, seed, ids, want_solutions=True):
-    """Returns (solutions complex128 [n][V][4][3] on the device or None, stats list, status)."""
+    """Returns (solutions on the device or None, stats list, status).  The
+    solutions follow params.out_layout / out_prec: canonical [n][V][4][3]
+    complex128 / complex64 (or [n][V][4][3][2] binary16 / bfloat16 pairs),
+    or a native uint8 buffer of tm_field_bytes(ctx, out_prec, n, NATIVE)."""
     import torch
     ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64))
     n = len(ids)
-    sol = torch.empty((n, ctx.V, 4, 3), dtype=torch.complex128, device="cuda") if want_solutions else None
+    sol = None
+    if want_solutions:
+        if params.out_layout == LAYOUT_NATIVE:
+            sol = torch.empty(max(tm_field_bytes(ctx, params.out_prec, n, LAYOUT_NATIVE), 1), dtype=torch.uint8,
+                              device="cuda")
+        else:
+            sol = torch.empty(canonical_shape(ctx, params.out_prec, n), dtype=_canon_dtype(params.out_prec),
+                              device="cuda")
     st = (SolveStats * max(n, 1))()
     rc = ctx.lib.tsm_solve_batch(ctx.h, ctypes.byref(params), int(seed), n, _ptr(ids),
                                  ctypes.c_void_p(sol.data_ptr()) if sol is not None else None, st)

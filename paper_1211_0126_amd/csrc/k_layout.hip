@@ -88,6 +88,66 @@ void launch_native_to_c128(hipStream_t st, const Geom& g, int prec, int nrhs, co
         hipLaunchKernelGGL((k_native_to_c128<SF32>), grid, dim3(256), 0, st, g, nrhs, in, out);
 }
 
+// Solutions (native, F64 or F32 storage, rhs 0..nrhs-1) -> right-hand sides
+// r0.. of the caller's field: canonical [rhs][site][12] complex of out_prec
+// (complex128, complex64, or (re, im) pairs of binary16 / bfloat16 as the
+// native half planes hold them), or native planes of out_prec
+template <class S, typename R>
+__global__ __launch_bounds__(256) void k_sol_out(Geom geo, const void* in, void* out, int out_prec, int native,
+                                                 int r0) {
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= geo.V) return;
+    cx<R> p[12];
+    load_spinor<S, R>(field_rhs<S>(in, geo.Vs, r), geo.Vs, s, p);
+    if (native) {
+        if (out_prec == P_F64) {
+            cx<double> q[12];
+#pragma unroll
+            for (int k = 0; k < 12; k++) q[k] = {(double)p[k].re, (double)p[k].im};
+            store_spinor<SF64, double>(field_rhs<SF64>(out, geo.Vs, r0 + r), geo.Vs, s, q);
+        } else {
+            cx<float> q[12];
+#pragma unroll
+            for (int k = 0; k < 12; k++) q[k] = {(float)p[k].re, (float)p[k].im};
+            if (out_prec == P_F32)
+                store_spinor<SF32, float>(field_rhs<SF32>(out, geo.Vs, r0 + r), geo.Vs, s, q);
+            else if (out_prec == P_F16)
+                store_spinor<SF16, float>(field_rhs<SF16>(out, geo.Vs, r0 + r), geo.Vs, s, q);
+            else
+                store_spinor<SBF16, float>(field_rhs<SBF16>(out, geo.Vs, r0 + r), geo.Vs, s, q);
+        }
+        return;
+    }
+    const size_t base = ((size_t)(r0 + r) * geo.V + s) * 12;
+    if (out_prec == P_F64) {
+        double2* o = (double2*)out + base;
+#pragma unroll
+        for (int k = 0; k < 12; k++) o[k] = make_double2((double)p[k].re, (double)p[k].im);
+    } else if (out_prec == P_F32) {
+        float2* o = (float2*)out + base;
+#pragma unroll
+        for (int k = 0; k < 12; k++) o[k] = make_float2((float)p[k].re, (float)p[k].im);
+    } else {
+        uint32_t* o = (uint32_t*)out + base;
+        const bool bf = out_prec == P_BF16;
+#pragma unroll
+        for (int k = 0; k < 12; k++)
+            o[k] = bf ? pack2_bf16((float)p[k].re, (float)p[k].im) : pack2_f16((float)p[k].re, (float)p[k].im);
+    }
+}
+
+void launch_sol_out(hipStream_t st, const Geom& g, int prec, int nrhs, const void* in, void* out, int out_prec,
+                    bool native, int r0) {
+    dim3 grid((unsigned)((g.V + 255) / 256), (unsigned)nrhs);
+    if (prec == P_F64)
+        hipLaunchKernelGGL((k_sol_out<SF64, double>), grid, dim3(256), 0, st, g, in, out, out_prec, native ? 1 : 0,
+                           r0);
+    else
+        hipLaunchKernelGGL((k_sol_out<SF32, float>), grid, dim3(256), 0, st, g, in, out, out_prec, native ? 1 : 0,
+                           r0);
+}
+
 // canonical complex128 -> native storage S (values rounded to S)
 template <class S, typename R>
 __global__ __launch_bounds__(256) void k_c128_to_native(Geom geo, int nrhs, const double* in, void* out) {

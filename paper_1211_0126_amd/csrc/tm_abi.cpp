@@ -1,5 +1,6 @@
 // C ABI: lifecycle, gauge load, operator application, noise, instrumentation.
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <array>
@@ -59,35 +60,48 @@ tm_status dev_error(tm_ctx* ctx, hipError_t e, const char* what) {
     return TM_EDEVICE;
 }
 
+static uint64_t digest_mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9E3779B97F4A7C15ULL + (h << 6) + (h >> 2);
+    return seed_mix(h);
+}
+
 void* ws_get(tm_ctx* ctx, const std::string& name, size_t bytes, tm_status* st) {
-    auto& b = ctx->ws[name];
-    if (b.bytes >= bytes && b.p) return b.p;
-    if (b.p) {
-        hipError_t e = hipStreamSynchronize(ctx->stream);
-        if (e != hipSuccess) {
-            *st = dev_error(ctx, e, "hipStreamSynchronize");
-            return nullptr;
-        }
-        (void)hipFree(b.p);
-        b.p = nullptr;
-        b.bytes = 0;
-    }
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        *st = set_error(ctx, TM_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes for " + name +
-                                            " failed");
+    auto it = ctx->ws.find(name);
+    if (it != ctx->ws.end() && it->second.bytes >= bytes) return ctx->arena.base + it->second.off;
+    auto& A = ctx->arena;
+    const size_t need = align256(bytes > 0 ? bytes : 1);
+    size_t off = A.sp;
+    // a name that grows in place when it is the last buffer carved
+    if (it != ctx->ws.end() && it->second.off + align256(it->second.bytes) == A.sp) off = it->second.off;
+    if (off + need > A.top) {
+        *st = set_error(ctx, TM_ENOMEM,
+                        "workspace too small: " + name + " needs " + std::to_string(need) + " bytes at offset " +
+                            std::to_string(off) + " with " + std::to_string(A.bytes - A.top) +
+                            " bytes persistent in a workspace of " + std::to_string(A.bytes) +
+                            " (size it with tm_workspace_bytes)");
         return nullptr;
     }
-    e = hipMemsetAsync(p, 0, bytes, ctx->stream);
-    if (e != hipSuccess) {
-        *st = dev_error(ctx, e, "hipMemsetAsync");
+    A.sp = off + need;
+    A.peak_sp = std::max(A.peak_sp, A.sp);
+    ctx->ws[name] = {off, need};
+    uint64_t h = ctx->ws_digest;
+    for (char c : name) h = digest_mix(h, (uint64_t)(unsigned char)c);
+    ctx->ws_digest = digest_mix(h, off ^ (need << 1));
+    return A.base + off;
+}
+
+void* ws_persist(tm_ctx* ctx, size_t bytes, const char* what, tm_status* st) {
+    auto& A = ctx->arena;
+    const size_t need = align256(bytes > 0 ? bytes : 1);
+    if (A.top < need || A.top - need < A.sp) {
+        *st = set_error(ctx, TM_ENOMEM,
+                        std::string("workspace too small: ") + what + " needs " + std::to_string(need) +
+                            " persistent bytes; " + std::to_string(A.top - A.sp) + " of " + std::to_string(A.bytes) +
+                            " are free (size it with tm_workspace_bytes)");
         return nullptr;
     }
-    b.p = p;
-    b.bytes = bytes;
-    return p;
+    A.top -= need;
+    return A.base + A.top;
 }
 
 size_t field_bytes(const Geom& g, int prec, int nrhs) {
@@ -196,7 +210,6 @@ static tm_status dslash_check(tm_ctx* ctx, int32_t op, int32_t prec, int32_t nrh
     return TM_OK;
 }
 
-static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 // scratch of one application: native staging of a canonical input and output,
 // and the intermediate M in of M^dag M
@@ -238,32 +251,24 @@ static tm_status dslash_run(tm_ctx* ctx, int op, int prec, int nrhs, int layout,
     return TM_OK;
 }
 
-}  // namespace tmq
-
-using namespace tmq;
-
-extern "C" {
-
-int32_t tm_abi_version(void) { return TM_ABI_VERSION; }
-
-tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
-    if (!lat || !out) return TM_EINVAL;
-    *out = nullptr;
+bool geom_setup(const tm_lattice* lat, Geom* gp, Geom* hp, bool* eo_ok, std::string* why) {
     long V = 1;
     for (int d = 0; d < 4; d++) {
-        if (lat->dims[d] < 2 || lat->dims[d] > 4096) return TM_EINVAL;
+        if (lat->dims[d] < 2 || lat->dims[d] > 4096) {
+            *why = "every extent must be in 2..4096";
+            return false;
+        }
         V *= lat->dims[d];
     }
     if (V >= (1L << 26)) {
-        g_create_error = "lattice too large";
-        return TM_EINVAL;
+        *why = "lattice too large";
+        return false;
     }
-    if (lat->t_bc != 1 && lat->t_bc != -1) return TM_EINVAL;
-    if (!std::isfinite(lat->kappa) || !std::isfinite(lat->mu)) return TM_EINVAL;
-    tm_ctx* ctx = new tm_ctx();
-    ctx->lat = *lat;
-    ctx->stream = (hipStream_t)hip_stream;
-    Geom& g = ctx->geo;
+    if (lat->t_bc != 1 && lat->t_bc != -1) {
+        *why = "t_bc must be +1 or -1";
+        return false;
+    }
+    Geom& g = *gp;
     for (int d = 0; d < 4; d++) g.L[d] = lat->dims[d];
     g.t_bc = lat->t_bc;
     g.V = V;
@@ -280,9 +285,8 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
     // from one base; the most planes behind one base are the FP64 links'
     // 4 x 9, so 36 planes of 16 Vs bytes must stay below 4 GiB.
     if (g.Vs * 16 * 36 > 0xFFFFFFFFL) {
-        g_create_error = "lattice too large: 576 * (volume padded to 256) must stay below 2^32 bytes";
-        delete ctx;
-        return TM_EINVAL;
+        *why = "lattice too large: 576 * (volume padded to 256) must stay below 2^32 bytes";
+        return false;
     }
     for (int d = 0; d < 3; d++) {
         uint64_t dd = (uint64_t)g.L[d];
@@ -290,17 +294,17 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
         // exactness of floor(n * m / 2^32) = n / d for every n < V
         uint64_t e = m * dd - (1ULL << 32);
         if ((uint64_t)V * e >= (1ULL << 32)) {
-            delete ctx;
-            return TM_EINVAL;
+            *why = "no exact 32-bit division for these extents";
+            return false;
         }
         g.m[d] = (uint32_t)m;
     }
     // even-odd half geometry: planes of V/2 sites with their own stride, and
     // division by Lx/2 for the half index (exact for every n < V/2)
-    ctx->eo_ok = (g.L[0] % 2 == 0) && (g.L[1] % 2 == 0) && (g.L[2] % 2 == 0) && (g.L[3] % 2 == 0);
-    if (ctx->eo_ok) {
-        Geom& h = ctx->hgeo;
-        h = g;
+    *eo_ok = (g.L[0] % 2 == 0) && (g.L[1] % 2 == 0) && (g.L[2] % 2 == 0) && (g.L[3] % 2 == 0);
+    Geom& h = *hp;
+    h = g;
+    if (*eo_ok) {
         h.V = V / 2;
         h.Vs = (h.V + 255) / 256 * 256;
         if ((h.Vs / 256) % 2 == 0) h.Vs += 256;
@@ -310,39 +314,123 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
         if (dd == 1)
             h.m[0] = 0;  // Lx = 2: the half index is the row
         else if ((uint64_t)h.V * e >= (1ULL << 32))
-            ctx->eo_ok = false;
+            *eo_ok = false;
         else
             h.m[0] = (uint32_t)m;
     }
+    return true;
+}
+
+size_t partials_per_rhs(const Geom& g, const Geom& hg, bool eo_ok) {
+    size_t n = (size_t)((g.V + 255) / 256);
+    // time-marching kernels: a partial per 256 sites of a time slice and per
+    // segment (at most one segment per slice)
+    n = std::max(n, (size_t)((g.V / g.L[3] + 255) / 256) * (size_t)g.L[3]);
+    if (eo_ok) n = std::max(n, (size_t)eot_tiles(hg));
+    return n;
+}
+
+static size_t create_bytes() { return align256(sizeof(int) * 384) + align256(kNetFragPoolBytes); }
+
+size_t ws_persistent(const Geom& g, const Geom& hg, bool eo_ok) {
+    // the links: FP64, FP32 and bfloat16 copies, and the parity-split FP32,
+    // FP64 and binary16 copies of the even-odd solver
+    size_t b = align256((size_t)4 * 9 * 16 * g.Vs) + 2 * align256((size_t)4 * 3 * 16 * g.Vs);
+    if (eo_ok) b += 2 * (2 * align256((size_t)4 * 3 * 16 * hg.Vs) + align256((size_t)4 * 9 * 16 * hg.Vs));
+    return create_bytes() + b;
+}
+
+size_t ws_abi_scratch(const Geom& g, int field_rhs, int tune_rhs) {
+    size_t b = align256((size_t)g.V * 4 * 9 * 16);                                   // gauge upload
+    b = std::max(b, 3 * align256(field_bytes(g, P_F64, field_rhs)));                  // canonical M^dag M
+    b = std::max(b, align256(sizeof(uint64_t) * 65535));                              // noise ids
+    b = std::max(b, 2 * align256(field_bytes(g, P_F64, tune_rhs)) + align256(sizeof(uint64_t) * tune_rhs));
+    return b;
+}
+
+}  // namespace tmq
+
+using namespace tmq;
+
+extern "C" {
+
+int32_t tm_abi_version(void) { return TM_ABI_VERSION; }
+
+tm_status tm_create(const tm_lattice* lat, void* dev_ws, size_t ws_bytes, void* hip_stream, tm_ctx** out) {
+    if (!lat || !out) return TM_EINVAL;
+    *out = nullptr;
+    Geom g, h;
+    bool eo_ok = false;
+    std::string why;
+    if (!geom_setup(lat, &g, &h, &eo_ok, &why)) {
+        g_create_error = "tm_create: " + why;
+        return TM_EINVAL;
+    }
+    if (!std::isfinite(lat->kappa) || !std::isfinite(lat->mu)) {
+        g_create_error = "tm_create: kappa and mu must be finite";
+        return TM_EINVAL;
+    }
+    if (dev_ws && ((uintptr_t)dev_ws % 256 != 0)) {
+        g_create_error = "tm_create: the workspace must be 256-byte aligned";
+        return TM_EINVAL;
+    }
+    ws_bytes = ws_bytes / 256 * 256;
+    if (ws_bytes < create_bytes()) {
+        g_create_error = "tm_create: a workspace of " + std::to_string(ws_bytes) + " bytes is below the " +
+                         std::to_string(create_bytes()) + " the context itself holds (size it with tm_workspace_bytes)";
+        return TM_ENOMEM;
+    }
+    tm_ctx* ctx = new tm_ctx();
+    ctx->lat = *lat;
+    ctx->stream = (hipStream_t)hip_stream;
+    ctx->geo = g;
+    ctx->hgeo = h;
+    ctx->eo_ok = eo_ok;
     ctx->twist = 2.0 * lat->kappa * lat->mu;
-    hipError_t e = hipGetDevice(&ctx->device);
-    if (e != hipSuccess) {
-        g_create_error = std::string("tm_create: hipGetDevice: ") + hipGetErrorString(e);
-        delete ctx;
-        return TM_EDEVICE;
-    }
-    e = scratch_setup(ctx->device);
-    if (e != hipSuccess) {
-        g_create_error = std::string("tm_create: address of the device scratch: ") + hipGetErrorString(e);
+    auto fail = [&](tm_status code, const std::string& msg) {
+        g_create_error = "tm_create: " + msg;
         (void)hipGetLastError();
+        if (ctx->arena.owned && ctx->arena.base) (void)hipFree(ctx->arena.base);
+        if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
         delete ctx;
-        return TM_EDEVICE;
+        return code;
+    };
+    hipError_t e = hipGetDevice(&ctx->device);
+    if (e != hipSuccess) return fail(TM_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    e = scratch_setup(ctx->device);
+    if (e != hipSuccess) return fail(TM_EDEVICE, std::string("address of the device scratch: ") + hipGetErrorString(e));
+    // the workspace: the caller's, or (null dev_ws) one allocation made here
+    // and released by tm_destroy; zeroed once
+    ctx->arena.bytes = ws_bytes;
+    ctx->arena.top = ws_bytes;
+    if (dev_ws) {
+        ctx->arena.base = (char*)dev_ws;
+    } else {
+        e = hipMalloc((void**)&ctx->arena.base, ws_bytes);
+        if (e != hipSuccess) return fail(TM_ENOMEM, "allocation of " + std::to_string(ws_bytes) + " bytes failed");
+        ctx->arena.owned = true;
     }
+    e = hipMemsetAsync(ctx->arena.base, 0, ws_bytes, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(TM_EDEVICE, std::string("clearing the workspace: ") + hipGetErrorString(e));
+    // pinned host mirror of the per-source CG scalars
+    e = hipHostMalloc((void**)&ctx->scal_host, sizeof(CgScal) * kScalHostEntries);
+    if (e != hipSuccess) return fail(TM_EDEVICE, std::string("pinned host buffer: ") + hipGetErrorString(e));
+    ctx->scal_host_n = kScalHostEntries;
     int col[3][16][4], ph[3][16][4];
     gamma_tables(col, ph);
     int tab[384];  // per table e: [16][4] columns, then [16][4] phases
-    for (int e = 0; e < 3; e++) {
-        std::memcpy(tab + 128 * e, col[e], sizeof(col[e]));
-        std::memcpy(tab + 128 * e + 64, ph[e], sizeof(ph[e]));
+    for (int t = 0; t < 3; t++) {
+        std::memcpy(tab + 128 * t, col[t], sizeof(col[t]));
+        std::memcpy(tab + 128 * t + 64, ph[t], sizeof(ph[t]));
     }
-    e = hipMalloc(&ctx->gam_dev, sizeof(tab));
-    if (e == hipSuccess) e = hipMemcpy(ctx->gam_dev, tab, sizeof(tab), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        g_create_error = std::string("tm_create: device set-up: ") + hipGetErrorString(e);
-        (void)hipGetLastError();
-        delete ctx;
-        return TM_EDEVICE;
-    }
+    tm_status st = TM_OK;
+    ctx->gam_dev = (int*)ws_persist(ctx, sizeof(tab), "insertion tables", &st);
+    ctx->net_frag_pool = (short*)ws_persist(ctx, kNetFragPoolBytes, "network fragments", &st);
+    if (st != TM_OK) return fail(st, ctx->err);
+    e = hipMemcpyAsync(ctx->gam_dev, tab, sizeof(tab), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(TM_EDEVICE, std::string("device set-up: ") + hipGetErrorString(e));
     *out = ctx;
     return TM_OK;
 }
@@ -350,22 +438,20 @@ tm_status tm_create(const tm_lattice* lat, void* hip_stream, tm_ctx** out) {
 tm_status tm_destroy(tm_ctx* ctx) {
     if (!ctx) return TM_EINVAL;
     (void)hipStreamSynchronize(ctx->stream);
-    for (auto& kv : ctx->ws)
-        if (kv.second.p) (void)hipFree(kv.second.p);
-    for (int q = 0; q < 2; q++) {
-        if (ctx->gauge32eo[q]) (void)hipFree(ctx->gauge32eo[q]);
-        if (ctx->gauge64eo[q]) (void)hipFree(ctx->gauge64eo[q]);
-        if (ctx->gauge16eo[q]) (void)hipFree(ctx->gauge16eo[q]);
-    }
-    if (ctx->gauge64) (void)hipFree(ctx->gauge64);
-    if (ctx->gauge32) (void)hipFree(ctx->gauge32);
-    if (ctx->gaugebf) (void)hipFree(ctx->gaugebf);
-    if (ctx->gam_dev) (void)hipFree(ctx->gam_dev);
-    if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
     net_release(ctx);
     for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
+    if (ctx->arena.owned && ctx->arena.base) (void)hipFree(ctx->arena.base);
     delete ctx;
+    return TM_OK;
+}
+
+tm_status tm_workspace_usage(const tm_ctx* ctx, size_t* persistent, size_t* peak_scratch, size_t* total) {
+    if (!ctx) return TM_EINVAL;
+    if (persistent) *persistent = ctx->arena.bytes - ctx->arena.top;
+    if (peak_scratch) *peak_scratch = ctx->arena.peak_sp;
+    if (total) *total = ctx->arena.bytes;
     return TM_OK;
 }
 
@@ -374,34 +460,40 @@ const char* tm_last_error(const tm_ctx* ctx) { return ctx ? ctx->err.c_str() : g
 tm_status tm_gauge_load(tm_ctx* ctx, const double* links_host) {
     if (!ctx || !links_host) return set_error(ctx, TM_EINVAL, "null argument");
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    WsScope scope(ctx);
     const Geom& g = ctx->geo;
+    const Geom& h = ctx->hgeo;
+    tm_status st = TM_OK;
+    // the link copies: carved from the top at the first load, kept after
+    if (!ctx->gauge64) {
+        ctx->gauge64 = ws_persist(ctx, (size_t)4 * 9 * 16 * g.Vs, "FP64 links", &st);
+        ctx->gauge32 = ws_persist(ctx, (size_t)4 * 3 * 16 * g.Vs, "FP32 links", &st);
+        ctx->gaugebf = ws_persist(ctx, (size_t)4 * 3 * 16 * g.Vs, "bfloat16 links", &st);
+        for (int q = 0; q < 2 && ctx->eo_ok; q++) {
+            ctx->gauge32eo[q] = ws_persist(ctx, (size_t)4 * 3 * 16 * h.Vs, "FP32 parity links", &st);
+            ctx->gauge64eo[q] = ws_persist(ctx, (size_t)4 * 9 * 16 * h.Vs, "FP64 parity links", &st);
+            ctx->gauge16eo[q] = ws_persist(ctx, (size_t)4 * 3 * 16 * h.Vs, "binary16 parity links", &st);
+        }
+        if (st != TM_OK) {
+            ctx->gauge64 = ctx->gauge32 = ctx->gaugebf = nullptr;
+            return st;
+        }
+    }
     const size_t canon_bytes = (size_t)g.V * 4 * 9 * 16;
-    if (!ctx->gauge64) TM_HIP(hipMalloc(&ctx->gauge64, (size_t)4 * 9 * 16 * g.Vs));
-    if (!ctx->gauge32) TM_HIP(hipMalloc(&ctx->gauge32, (size_t)4 * 3 * 16 * g.Vs));
-    if (!ctx->gaugebf) TM_HIP(hipMalloc(&ctx->gaugebf, (size_t)4 * 3 * 16 * g.Vs));
-    void* tmp = nullptr;
-    TM_HIP(hipMalloc(&tmp, canon_bytes));
+    void* tmp = ws_get(ctx, "gauge_upload", canon_bytes, &st);
+    if (!tmp) return st;
     hipError_t e = hipMemcpyAsync(tmp, links_host, canon_bytes, hipMemcpyHostToDevice, ctx->stream);
     if (e == hipSuccess) {
         launch_gauge_convert(ctx->stream, g, (const double*)tmp, ctx->gauge64, ctx->gauge32, ctx->gaugebf);
         e = hipGetLastError();
     }
     if (e == hipSuccess && ctx->eo_ok) {
-        const Geom& h = ctx->hgeo;
-        for (int q = 0; q < 2 && e == hipSuccess; q++) {
-            if (!ctx->gauge32eo[q]) e = hipMalloc(&ctx->gauge32eo[q], (size_t)4 * 3 * 16 * h.Vs);
-            if (e == hipSuccess && !ctx->gauge64eo[q]) e = hipMalloc(&ctx->gauge64eo[q], (size_t)4 * 9 * 16 * h.Vs);
-            if (e == hipSuccess && !ctx->gauge16eo[q]) e = hipMalloc(&ctx->gauge16eo[q], (size_t)4 * 3 * 16 * h.Vs);
-        }
-        if (e == hipSuccess) {
-            launch_eo_split(ctx->stream, g, h, ctx->gauge32, 12, ctx->gauge32eo[0], ctx->gauge32eo[1]);
-            launch_eo_split(ctx->stream, g, h, ctx->gauge64, 36, ctx->gauge64eo[0], ctx->gauge64eo[1]);
-            for (int q = 0; q < 2; q++) launch_eo_links_h16(ctx->stream, h, ctx->gauge64eo[q], ctx->gauge16eo[q]);
-            e = hipGetLastError();
-        }
+        launch_eo_split(ctx->stream, g, h, ctx->gauge32, 12, ctx->gauge32eo[0], ctx->gauge32eo[1]);
+        launch_eo_split(ctx->stream, g, h, ctx->gauge64, 36, ctx->gauge64eo[0], ctx->gauge64eo[1]);
+        for (int q = 0; q < 2; q++) launch_eo_links_h16(ctx->stream, h, ctx->gauge64eo[q], ctx->gauge16eo[q]);
+        e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-    (void)hipFree(tmp);
     if (e != hipSuccess) return dev_error(ctx, e, "gauge load");
     ctx->gauge_loaded = true;
     return TM_OK;
@@ -429,6 +521,7 @@ tm_status tm_dslash(tm_ctx* ctx, int32_t op, int32_t prec, int32_t nrhs, int32_t
                     void* out_dev) {
     tm_status st = dslash_check(ctx, op, prec, nrhs, layout, in_dev, out_dev, "tm_dslash");
     if (st != TM_OK) return st;
+    WsScope scope(ctx);
     const size_t fb = field_bytes(ctx->geo, prec, nrhs);
     void *a = nullptr, *b = nullptr, *tmp = nullptr;
     if (layout == TM_LAYOUT_CANONICAL) {
@@ -470,6 +563,7 @@ tm_status tm_dslash_noalloc(tm_ctx* ctx, int32_t op, int32_t prec, int32_t nrhs,
 tm_status tm_noise_z4(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* ids_host, double* out_dev) {
     if (!ctx) return TM_EINVAL;
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    WsScope scope(ctx);
     if (nsrc < 1 || nsrc > 65535 || !ids_host || !out_dev) return set_error(ctx, TM_EINVAL, "tm_noise_z4: bad argument");
     tm_status st = TM_OK;
     uint64_t* ids = (uint64_t*)ws_get(ctx, "noise_ids", sizeof(uint64_t) * nsrc, &st);
@@ -513,6 +607,7 @@ tm_status tm_autotune(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_nr,
     if (!ctx || prec < 0 || prec > 3 || nrhs < 1 || nrhs > 32 || !best_nr)
         return set_error(ctx, TM_EINVAL, "tm_autotune: bad argument");
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    WsScope scope(ctx);
     if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tm_autotune: no gauge field loaded");
     const Geom& g = ctx->geo;
     tm_status s = TM_OK;

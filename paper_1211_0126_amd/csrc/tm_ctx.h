@@ -32,14 +32,36 @@ struct tm_ctx {
     void* gauge64eo[2] = {nullptr, nullptr};  // double2 [4][9][Vhs] per parity
     void* gauge16eo[2] = {nullptr, nullptr};  // uint4 [4][3][Vhs] per parity: binary16 pairs (FP16 storage hops)
 
+    // The caller's device workspace.  Every device buffer of the context is
+    // carved from it: buffers that live until tm_destroy (links, tables,
+    // network fragments) from the top down, the scratch of one API call from
+    // the bottom up, released when the next call begins.
+    struct Arena {
+        char* base = nullptr;
+        size_t bytes = 0;
+        bool owned = false;   // allocated by tm_create (null dev_ws)
+        size_t top = 0;       // persistent buffers occupy [top, bytes)
+        size_t sp = 0;        // scratch of the current call occupies [0, sp)
+        size_t peak_sp = 0;   // largest sp since tm_create
+        int depth = 0;        // nesting of API scopes (the outermost resets sp)
+    } arena;
     struct Buf {
-        void* p = nullptr;
+        size_t off = 0;
         size_t bytes = 0;
     };
-    std::map<std::string, Buf> ws;  // grow-only named device workspace
+    std::map<std::string, Buf> ws;  // named scratch of the current call
+    // right-hand sides the buffers of a solve tag are sized for in this call
+    // (at least the block being solved)
+    std::map<std::string, int> ws_cap;
+    // digest of the names and offsets of the current call's scratch (part of
+    // the keys of captured graphs, which hold buffer addresses)
+    uint64_t ws_digest = 0;
 
     tmq::CgScal* scal_host = nullptr;  // pinned mirror for stop checks
     int scal_host_n = 0;
+    // device memory of the network weight fragments (TM_NET_MAX_LAYERS layers,
+    // forward and adjoint), carved at tm_create
+    short* net_frag_pool = nullptr;
 
     // insertion tables on the device (row a -> column, phase i^k): [3][2][16][4]
     // for Gamma_n, g5 Gamma_n, g5 Gamma_n g5
@@ -93,9 +115,42 @@ struct tm_ctx {
 
 namespace tmq {
 
+// most right-hand sides of one solve block
+constexpr int kMaxBlock = 32;
+// entries of the pinned host mirror of the CG scalars (two blocks of 32)
+constexpr int kScalHostEntries = 64;
+// device bytes of one layer's weight fragments in one direction, for widths
+// up to 2 (144 padded K rows: 9 MFMA K-steps of 64 lanes x 4 bfloat16), and
+// of the pool holding every layer in both directions
+constexpr size_t kNetFragBytes = 9 * 64 * 4 * 2;
+constexpr size_t kNetFragPoolBytes = (size_t)TM_NET_MAX_LAYERS * 2 * kNetFragBytes;
+
 tm_status set_error(tm_ctx* ctx, tm_status code, const std::string& msg);
 tm_status dev_error(tm_ctx* ctx, hipError_t e, const char* what);
+// Named scratch of the current API call (sized for bytes; a name asked for
+// again in the same call returns its buffer if it is large enough).  Null and
+// *st = TM_ENOMEM if the workspace cannot hold it.
 void* ws_get(tm_ctx* ctx, const std::string& name, size_t bytes, tm_status* st);
+// A buffer that lives until tm_destroy, from the top of the workspace.
+void* ws_persist(tm_ctx* ctx, size_t bytes, const char* what, tm_status* st);
+// right-hand sides to size the buffers of a solve tag for in this call
+inline int ws_rhs(const tm_ctx* ctx, const std::string& tag, int nrhs) {
+    auto it = ctx->ws_cap.find(tag);
+    return it == ctx->ws_cap.end() ? nrhs : (it->second > nrhs ? it->second : nrhs);
+}
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+// reduction partials per right-hand side, the most any CG or FCG kernel
+// writes (lane-per-site, time-marching and even-odd tile traversals)
+size_t partials_per_rhs(const Geom& g, const Geom& hg, bool eo_ok);
+// geometry of a lattice (plane strides, divisors) and of its even-odd half;
+// false with the reason in *why for an unsupported lattice
+bool geom_setup(const tm_lattice* lat, Geom* g, Geom* hg, bool* eo_ok, std::string* why);
+// workspace bounds: the buffers kept until tm_destroy (tables, network
+// fragments, links), and the scratch of the calls of the lifecycle and
+// operator part (gauge upload, canonical tm_dslash with field_rhs
+// right-hand sides, noise ids, tm_autotune with tune_rhs)
+size_t ws_persistent(const Geom& g, const Geom& hg, bool eo_ok);
+size_t ws_abi_scratch(const Geom& g, int field_rhs, int tune_rhs);
 size_t field_bytes(const Geom& g, int prec, int nrhs);
 uint64_t seed_mix(uint64_t seed);
 
@@ -118,6 +173,26 @@ inline int prof_tag(int prec, int lane_rhs, int solver, int tseg = 0) {
 void prof_end(tm_ctx* ctx, int kc, double bytes);
 
 }  // namespace tmq
+
+// Scope of one API call: the outermost scope on a context starts a fresh
+// scratch region (the previous call's scratch is dead: every use of it was
+// enqueued on the context's stream before this call's work).
+struct WsScope {
+    tm_ctx* c;
+    explicit WsScope(tm_ctx* ctx) : c(ctx) {
+        if (c && c->arena.depth++ == 0) {
+            c->arena.sp = 0;
+            c->ws.clear();
+            c->ws_cap.clear();
+            c->ws_digest = 0;
+        }
+    }
+    ~WsScope() {
+        if (c) c->arena.depth--;
+    }
+    WsScope(const WsScope&) = delete;
+    WsScope& operator=(const WsScope&) = delete;
+};
 
 #define TM_HIP(call)                                             \
     do {                                                         \

@@ -198,6 +198,10 @@ void launch_true_resid(hipStream_t st, const CgArgs& a, int xprec, const void* g
 // layout and noise
 void launch_field_convert(hipStream_t st, const Geom& g, int prec, int nrhs, bool to_native, const void* in,
                           void* out);
+// solutions (native, F64 or F32 storage) -> right-hand sides r0.. of a
+// caller's field in out_prec, canonical or native
+void launch_sol_out(hipStream_t st, const Geom& g, int prec, int nrhs, const void* in, void* out, int out_prec,
+                    bool native, int r0);
 void launch_native_to_c128(hipStream_t st, const Geom& g, int prec, int nrhs, const void* in, double* out);
 void launch_c128_to_native(hipStream_t st, const Geom& g, int prec, int nrhs, const double* in, void* out);
 void launch_gauge_convert(hipStream_t st, const Geom& g, const double* canon, void* g64, void* g32, void* gbf);

@@ -19,12 +19,8 @@ struct NetState {
     int widths[TM_NET_MAX_LAYERS + 1] = {0};
     std::vector<cplx> W;
     std::vector<size_t> off;              // complex offset of each layer
-    std::vector<short*> frag_fwd, frag_adj;
+    std::vector<short*> frag_fwd, frag_adj;  // in the context's fragment pool
     std::vector<int> kpad_fwd, kpad_adj;
-    ~NetState() {
-        for (auto p : frag_fwd) (void)hipFree(p);
-        for (auto p : frag_adj) (void)hipFree(p);
-    }
 };
 
 namespace tmq {
@@ -98,10 +94,11 @@ static tm_status upload_fragments(tm_ctx* ctx) {
         int kf, ka;
         auto ff = layer_fragments(ns->W.data() + ns->off[l], ns->widths[l], ns->widths[l + 1], false, &kf);
         auto fa = layer_fragments(ns->W.data() + ns->off[l], ns->widths[l], ns->widths[l + 1], true, &ka);
+        if (ff.size() * 2 > kNetFragBytes || fa.size() * 2 > kNetFragBytes || l >= TM_NET_MAX_LAYERS)
+            return set_error(ctx, TM_ENOTSUP, "network layer larger than its fragment slot");
         if ((int)ns->frag_fwd.size() <= l) {
-            short *a = nullptr, *b = nullptr;
-            TM_HIP(hipMalloc(&a, ff.size() * 2));
-            TM_HIP(hipMalloc(&b, fa.size() * 2));
+            short* a = (short*)((char*)ctx->net_frag_pool + (size_t)(2 * l) * kNetFragBytes);
+            short* b = (short*)((char*)ctx->net_frag_pool + (size_t)(2 * l + 1) * kNetFragBytes);
             ns->frag_fwd.push_back(a);
             ns->frag_adj.push_back(b);
             ns->kpad_fwd.push_back(kf);
@@ -155,10 +152,10 @@ static void layer_launch(tm_ctx* ctx, int l, bool adjoint, const void* in, int i
 // them in) in the layers' half-split plane order (P_BH); out is written in
 // out_prec (FP32 or P_BH).
 tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_prec, void* out, int out_prec,
-                    const FcgScal* gate) {
+                    const FcgScal* gate, int cap) {
     NetState* ns = ctx->net;
     tm_status s = TM_OK;
-    const size_t fb = field_bytes(ctx->geo, P_BH, 2 * nrhs);
+    const size_t fb = field_bytes(ctx->geo, P_BH, 2 * std::max(nrhs, cap));
     void* A = ws_get(ctx, "net_a", fb, &s);
     void* B = ws_get(ctx, "net_b", fb, &s);
     if (s != TM_OK) return s;
@@ -181,12 +178,12 @@ tm_status net_apply(tm_ctx* ctx, bool adjoint, int nrhs, const void* in, int in_
 
 // z = N(N^dag(r)), r and z FP32, the middle field bfloat16 (P_BH); right-hand sides
 // that gate marks converged or fallen back are skipped (z keeps its values)
-tm_status net_precondition(tm_ctx* ctx, int nrhs, const void* r, void* z, const FcgScal* gate) {
+tm_status net_precondition(tm_ctx* ctx, int nrhs, const void* r, void* z, const FcgScal* gate, int cap) {
     tm_status s = TM_OK;
-    void* tmp = ws_get(ctx, "net_mid", field_bytes(ctx->geo, P_BH, nrhs), &s);
+    void* tmp = ws_get(ctx, "net_mid", field_bytes(ctx->geo, P_BH, std::max(nrhs, cap)), &s);
     if (s != TM_OK) return s;
-    if ((s = net_apply(ctx, true, nrhs, r, P_F32, tmp, P_BH, gate)) != TM_OK) return s;
-    return net_apply(ctx, false, nrhs, tmp, P_BH, z, P_F32, gate);
+    if ((s = net_apply(ctx, true, nrhs, r, P_F32, tmp, P_BH, gate, cap)) != TM_OK) return s;
+    return net_apply(ctx, false, nrhs, tmp, P_BH, z, P_F32, gate, cap);
 }
 
 bool net_installed(const tm_ctx* ctx) { return ctx->net != nullptr; }
@@ -302,6 +299,35 @@ static tm_status read_grads(tm_ctx* ctx, std::vector<double*>& grads, std::vecto
     return TM_OK;
 }
 
+// ---- workspace bounds (the buffers the paths above carve) ----
+
+// the loss-gradient buffers of loss_grad_pairs and the per-layer gradients,
+// for the largest network (TM_NET_MAX_LAYERS layers of width 2)
+static size_t ws_loss_buffers(const Geom& g) {
+    const size_t f2 = align256(field_bytes(g, P_F32, 2));
+    size_t b = (size_t)(TM_NET_MAX_LAYERS + 4) * f2;  // activations, g0, g1, mw, gd
+    b += align256(sizeof(float) * (size_t)pt_blocks(g) * 16 * 144);
+    b += align256(sizeof(double) * (size_t)pt_chunks(g) * 16 * 144);
+    b += align256(sizeof(double) * 2 * (size_t)((g.V + 255) / 256));
+    b += (size_t)TM_NET_MAX_LAYERS * align256(sizeof(double) * 16 * kpad_of(2));
+    return b;
+}
+
+size_t ws_net_apply(const Geom& g, int nrhs) { return 2 * align256(field_bytes(g, P_BH, 2 * nrhs)); }
+
+size_t ws_loss_grad(const Geom& g, int npairs) {
+    return 2 * align256(field_bytes(g, P_F32, 1) * npairs) + align256(sizeof(double) * 4) + ws_loss_buffers(g);
+}
+
+size_t ws_train(const Geom& g, const Geom& hg, bool eo_ok, int npairs, int nsrc) {
+    const size_t f64 = align256(field_bytes(g, P_F64, 1));
+    size_t b = 2 * align256(field_bytes(g, P_BF16, 1) * npairs) + align256(sizeof(uint64_t) * nsrc) + f64;
+    // the FP64 history solve: six fields, its scalars, the two partial arrays
+    b += 6 * f64 + align256(sizeof(CgScal) * kMaxBlock) +
+         2 * align256(sizeof(double) * partials_per_rhs(g, hg, eo_ok) * kMaxBlock);
+    return b + align256(sizeof(double) * 4) + ws_loss_buffers(g);
+}
+
 }  // namespace tmq
 
 using namespace tmq;
@@ -330,6 +356,7 @@ tm_status tm_precond_apply(tm_ctx* ctx, int32_t adjoint, int32_t nrhs, const dou
     if (!ctx || !in_dev || !out_dev || nrhs < 1 || nrhs > 65535)
         return set_error(ctx, TM_EINVAL, "tm_precond_apply: bad argument");
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    WsScope scope(ctx);
     if (!ctx->gauge_loaded || !ctx->net) return set_error(ctx, TM_ESTATE, "tm_precond_apply: gauge or network missing");
     tm_status s = TM_OK;
     const size_t fb = field_bytes(ctx->geo, P_F32, nrhs);
@@ -348,6 +375,7 @@ tm_status tm_precond_loss_grad(tm_ctx* ctx, int32_t npairs, const double* r_dev,
     if (!ctx || npairs < 1 || !r_dev || !e_dev || !loss_host || !grad_host)
         return set_error(ctx, TM_EINVAL, "tm_precond_loss_grad: bad argument");
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    WsScope scope(ctx);
     if (!ctx->gauge_loaded || !ctx->net) return set_error(ctx, TM_ESTATE, "gauge or network missing");
     const Geom& g = ctx->geo;
     tm_status s = TM_OK;
@@ -441,6 +469,7 @@ tm_status tm_precond_train(tm_ctx* ctx, const tm_train_params* P, tm_train_stats
     using clk = std::chrono::steady_clock;
     if (!ctx || !P) return set_error(ctx, TM_EINVAL, "tm_precond_train: null argument");
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    WsScope scope(ctx);
     if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tm_precond_train: no gauge field loaded");
     const bool init_only = P->n_pairs == 0 && P->epochs == 0;
     if ((!init_only && (P->n_sources < 1 || P->n_pairs < 1 || P->epochs < 0 || P->batch < 1 || !(P->lr > 0) ||

@@ -20,8 +20,9 @@
 
 namespace tmq {
 
-static const int kMaxBlock = 32;
 static const int kIterCap = 20000;  // safety cap for max_iter = -1
+// search directions kept by the even-odd CG without reliable updates
+constexpr int kEoRing = 8;
 
 static tm_status check_solve_params(tm_ctx* ctx, const tsm_solve_params* p) {
     if (!p) return set_error(ctx, TM_EINVAL, "null solve parameters");
@@ -77,14 +78,10 @@ static int march_tseg(const tm_ctx* ctx, const tsm_solve_params* p, int nr) {
     return std::min(t, ctx->geo.L[3]);
 }
 
+// the pinned mirror (allocated by tm_create) holds a block's scalars
 static tm_status ensure_scal_host(tm_ctx* ctx, int n) {
     if (ctx->scal_host_n >= n) return TM_OK;
-    if (ctx->scal_host) (void)hipHostFree(ctx->scal_host);
-    ctx->scal_host = nullptr;
-    ctx->scal_host_n = 0;
-    TM_HIP(hipHostMalloc((void**)&ctx->scal_host, sizeof(CgScal) * kMaxBlock * 2));
-    ctx->scal_host_n = kMaxBlock * 2;
-    return TM_OK;
+    return set_error(ctx, TM_EINVAL, "block larger than the scalar mirror");
 }
 
 // CG steps between host checks.  The first chunk is the iteration count of
@@ -146,8 +143,8 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
     const Geom& g = ctx->geo;
     hipStream_t st = ctx->stream;
     tm_status s = TM_OK;
-    const size_t nblk = (size_t)((g.V + 255) / 256);
-    const size_t fb = field_bytes(g, P_F32, nrhs);
+    const size_t fb = field_bytes(g, P_F32, ws_rhs(ctx, tag, nrhs));
+    const size_t npart = partials_per_rhs(g, ctx->hgeo, ctx->eo_ok);
     FcgArgs a;
     std::memset(&a, 0, sizeof(a));
     a.geo = g;
@@ -163,10 +160,10 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
     a.z = ws_get(ctx, tag + "_fz", fb, &s);
     void* eta = ws_get(ctx, tag + "_feta", fb, &s);
     a.scal = (FcgScal*)ws_get(ctx, tag + "_fscal", sizeof(FcgScal) * kMaxBlock, &s);
-    a.partials = (double*)ws_get(ctx, "fpartials", sizeof(double) * nblk * kMaxBlock * 4, &s);
+    a.partials = (double*)ws_get(ctx, "fpartials", sizeof(double) * npart * kMaxBlock * 4, &s);
     CgScal* tscal = (CgScal*)ws_get(ctx, tag + "_ftscal", sizeof(CgScal) * kMaxBlock, &s);
-    double* part1 = (double*)ws_get(ctx, "partials", sizeof(double) * nblk * kMaxBlock, &s);
-    double* part2 = (double*)ws_get(ctx, "partials2", sizeof(double) * nblk * kMaxBlock, &s);
+    double* part1 = (double*)ws_get(ctx, "partials", sizeof(double) * npart * kMaxBlock, &s);
+    double* part2 = (double*)ws_get(ctx, "partials2", sizeof(double) * npart * kMaxBlock, &s);
     if (s != TM_OK) return s;
     if ((s = ensure_scal_host(ctx, nrhs)) != TM_OK) return s;
 
@@ -175,7 +172,7 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
     launch_apply(st, g, P_F32, ctx->gauge32, ctx->lat.kappa, ctx->twist, 1, nrhs, eta, a.r, 1, nullptr);
     launch_fcg_init(st, a, p->tol * p->tol, p->max_iter, 0);
     prof_end(ctx, TM_KC_OTHER, 0.0);
-    if ((s = net_precondition(ctx, nrhs, a.r, a.z, nullptr)) != TM_OK) return s;
+    if ((s = net_precondition(ctx, nrhs, a.r, a.z, nullptr, ws_rhs(ctx, tag, nrhs))) != TM_OK) return s;
     launch_fcg_dot(st, a, 1);
     launch_fcg_p(st, a);
     TM_HIP(hipGetLastError());
@@ -203,7 +200,7 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
             else
                 launch_fcg_upd(st, a);
             prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
-            if ((s = net_precondition(ctx, nrhs, a.r, a.z, a.scal)) != TM_OK) return s;
+            if ((s = net_precondition(ctx, nrhs, a.r, a.z, a.scal, ws_rhs(ctx, tag, nrhs))) != TM_OK) return s;
             launch_fcg_dot(st, a, 0);
             prof_begin(ctx, TM_KC_BLAS, prof_tag(P_F32, 1, TM_SOLVER_FCG_LEARNED));
             launch_fcg_p(st, a);
@@ -273,8 +270,8 @@ tm_status solve_f64_history(tm_ctx* ctx, uint64_t seed_mixed, const uint64_t* id
     void* eta = ws_get(ctx, "h_eta", fb, &s);
     void* mx = ws_get(ctx, "h_mx", fb, &s);
     a.scal = (CgScal*)ws_get(ctx, "h_scal", sizeof(CgScal) * kMaxBlock, &s);
-    a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * nblk * kMaxBlock, &s);
-    a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * nblk * kMaxBlock, &s);
+    a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * partials_per_rhs(g, ctx->hgeo, ctx->eo_ok) * kMaxBlock, &s);
+    a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * partials_per_rhs(g, ctx->hgeo, ctx->eo_ok) * kMaxBlock, &s);
     if (s != TM_OK) return s;
     launch_scal_init(st, a.scal, 1, tol * tol, maxit, 0, 0, 0.0);
     launch_noise_native(st, g, P_F64, seed_mixed, id_dev, 1, eta);
@@ -353,6 +350,9 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     const size_t nblk_full = (size_t)((g.V + 255) / 256);
     const uint32_t nblk = (uint32_t)((hg.V + 255) / 256);
     const size_t fbh = field_bytes(hg, prec, nrhs);
+    // buffers sized for the tag's capacity (at least nrhs)
+    const int nc = ws_rhs(ctx, tag, nrhs);
+    const size_t fbc = field_bytes(hg, prec, nc);
     const double kappa = ctx->lat.kappa, tw = ctx->twist;
     const double ee_z4 = 12.0 * (double)g.V;
 
@@ -370,43 +370,43 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     // the lane-per-site kernels; x is formed from the step lengths every
     // kRing - 1 iterations and at the end
     const bool ringm = !rel && prec != P_F64 && !tiles;
-    constexpr int kRing = 8;
+    constexpr int kRing = kEoRing;
     void* dirs = nullptr;
     if (ringm) {
-        dirs = ws_get(ctx, tag + "_eo_dirs", fbh * kRing, &s);
+        dirs = ws_get(ctx, tag + "_eo_dirs", fbc * kRing, &s);
         a.ahist = (double*)ws_get(ctx, tag + "_eo_ahist", sizeof(double) * kMaxBlock * kRing, &s);
         a.ring = kRing;
         a.p = dirs;  // p_0, written by the CG start
     } else {
-        a.p = ws_get(ctx, tag + "_eo_p", fbh, &s);
+        a.p = ws_get(ctx, tag + "_eo_p", fbc, &s);
     }
     auto slot = [&](int k) { return (void*)((char*)dirs + (size_t)(k % kRing) * fbh); };
-    a.t = ws_get(ctx, tag + "_eo_t", fbh, &s);
-    a.r = ws_get(ctx, tag + "_eo_r", fbh, &s);
-    a.x = ws_get(ctx, tag + "_eo_x", field_bytes(hg, xprec, nrhs), &s);
-    void* y = ws_get(ctx, tag + "_eo_y", fbh, &s);
+    a.t = ws_get(ctx, tag + "_eo_t", fbc, &s);
+    a.r = ws_get(ctx, tag + "_eo_r", fbc, &s);
+    a.x = ws_get(ctx, tag + "_eo_x", field_bytes(hg, xprec, nc), &s);
+    void* y = ws_get(ctx, tag + "_eo_y", fbc, &s);
     a.scal = (CgScal*)ws_get(ctx, tag + "_scal", sizeof(CgScal) * kMaxBlock, &s);
-    const size_t npart_max = std::max<size_t>(nblk_full, (size_t)eot_tiles(hg));
+    const size_t npart_max = partials_per_rhs(g, hg, ctx->eo_ok);
     a.partials = (double*)ws_get(ctx, "partials", sizeof(double) * npart_max * kMaxBlock, &s);
     a.partials2 = (double*)ws_get(ctx, "partials2", sizeof(double) * npart_max * kMaxBlock, &s);
-    if (track) a.rho = ws_get(ctx, tag + "_eo_rho", fbh, &s);
+    if (track) a.rho = ws_get(ctx, tag + "_eo_rho", fbc, &s);
     // the full solution handed to the contraction
     const int fprec = rel ? P_F64 : xprec;
-    void* xfull = ws_get(ctx, tag + "_eo_xfull", field_bytes(g, fprec, nrhs), &s);
+    void* xfull = ws_get(ctx, tag + "_eo_xfull", field_bytes(g, fprec, nc), &s);
     // source preparation at the iteration precision (FP64 with reliable
     // updates); the tile kernels take the sources from the hash
     const int sp = rel ? P_F64 : prec;
     // FP64 half-hops: two sources per lane (the links are read once per pair)
     const int nr64 = nrhs % 2 == 0 ? 2 : 1;
     const int snr = sp == P_F64 ? nr64 : nr;
-    void* eta_o = tiles && !rel ? nullptr : ws_get(ctx, tag + "_eo_etao", field_bytes(hg, sp, nrhs), &s);
-    void* eh = ws_get(ctx, tag + "_eo_eh", field_bytes(hg, sp, nrhs), &s);
+    void* eta_o = tiles && !rel ? nullptr : ws_get(ctx, tag + "_eo_etao", field_bytes(hg, sp, nc), &s);
+    void* eh = ws_get(ctx, tag + "_eo_eh", field_bytes(hg, sp, nc), &s);
     void *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *y64 = nullptr;
     if (rel) {
-        b64 = ws_get(ctx, tag + "_eo_b64", field_bytes(hg, P_F64, nrhs), &s);
-        x64 = ws_get(ctx, tag + "_eo_x64", field_bytes(hg, P_F64, nrhs), &s);
-        t64 = ws_get(ctx, tag + "_eo_t64", field_bytes(hg, P_F64, nrhs), &s);
-        y64 = ws_get(ctx, tag + "_eo_y64", field_bytes(hg, P_F64, nrhs), &s);
+        b64 = ws_get(ctx, tag + "_eo_b64", field_bytes(hg, P_F64, nc), &s);
+        x64 = ws_get(ctx, tag + "_eo_x64", field_bytes(hg, P_F64, nc), &s);
+        t64 = ws_get(ctx, tag + "_eo_t64", field_bytes(hg, P_F64, nc), &s);
+        y64 = ws_get(ctx, tag + "_eo_y64", field_bytes(hg, P_F64, nc), &s);
     }
     if (s != TM_OK) return s;
     if ((s = ensure_scal_host(ctx, nrhs)) != TM_OK) return s;
@@ -587,10 +587,11 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
         };
         if (ctx->use_graphs && !ctx->prof && st != nullptr) {
             char key[512];
-            std::snprintf(key, sizeof(key), "eo|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%d|%d",
-                          a0.p, a0.t, a0.r, a0.x, y, a0.rho, (void*)a0.scal, (void*)a0.partials, (void*)a0.partials2,
-                          x64, t64, b64, y64, (void*)a0.ahist, prec, nr, (int)track, (int)rel, nrhs, k,
-                          ringm ? done % kRing : -1);
+            std::snprintf(key, sizeof(key),
+                          "eo|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%d|%llx", a0.p, a0.t,
+                          a0.r, a0.x, y, a0.rho, (void*)a0.scal, (void*)a0.partials, (void*)a0.partials2, x64, t64,
+                          b64, y64, (void*)a0.ahist, prec, nr, (int)track, (int)rel, nrhs, k,
+                          ringm ? done % kRing : -1, (int)tiles, (unsigned long long)ctx->ws_digest);
             auto it = ctx->graphs.find(key);
             if (it == ctx->graphs.end()) {
                 hipGraph_t graph;
@@ -669,9 +670,11 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
     // true residual is taken at each update instead
     const bool track = p->stop == TM_STOP_TRUE && !rel;
     const size_t nblk = (size_t)((g.V + 255) / 256);
-    const size_t fb = field_bytes(g, prec, nrhs);
-    const size_t fx = field_bytes(g, prec == P_F64 ? P_F64 : P_F32, nrhs);
-    const size_t f64 = field_bytes(g, P_F64, nrhs);
+    // buffers sized for the tag's capacity (at least nrhs)
+    const int nc = ws_rhs(ctx, tag, nrhs);
+    const size_t fb = field_bytes(g, prec, nc);
+    const size_t fx = field_bytes(g, prec == P_F64 ? P_F64 : P_F32, nc);
+    const size_t f64 = field_bytes(g, P_F64, nc);
 
     CgArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -683,7 +686,7 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
     // time-marching K1 / K2 when a segment length is set for this precision
     a.tseg = march_tseg(ctx, p, nr);
     a.npart = a.tseg > 0 ? march_partials(g, a.tseg) : (uint32_t)nblk;
-    const size_t npart_max = std::max<size_t>(nblk, a.npart);
+    const size_t npart_max = partials_per_rhs(g, ctx->hgeo, ctx->eo_ok);
     a.p = ws_get(ctx, tag + "_p", fb, &s);
     a.t = ws_get(ctx, tag + "_t", fb, &s);
     a.r = ws_get(ctx, tag + "_r", fb, &s);
@@ -779,9 +782,10 @@ static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t se
             // the chunk's launches depend only on the buffers and the launch
             // configuration, so one captured graph serves every chunk
             char key[512];
-            std::snprintf(key, sizeof(key), "cg|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%d|%d", a.p, a.t, a.r,
-                          a.x, a.rho, (void*)a.scal, (void*)a.partials, (void*)a.partials2, x64, t64, b64, prec, nr,
-                          a.tseg, (int)track, (int)rel, nrhs, k);
+            std::snprintf(key, sizeof(key), "cg|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%p|%d|%d|%d|%d|%d|%d|%d|%llx", a.p,
+                          a.t, a.r, a.x, a.rho, (void*)a.scal, (void*)a.partials, (void*)a.partials2, x64, t64, b64,
+                          (void*)a.eta64, prec, nr, a.tseg, (int)track, (int)rel, nrhs, k,
+                          (unsigned long long)ctx->ws_digest);
             auto it = ctx->graphs.find(key);
             if (it == ctx->graphs.end()) {
                 hipGraph_t graph;
@@ -1027,6 +1031,127 @@ static tm_status contract_all_momenta(tm_ctx* ctx, uint64_t seed, int32_t nsrc, 
     return TM_OK;
 }
 
+// ---- workspace bounds (tm_workspace_bytes) ----
+
+// Scratch of one solve_block call for nc right-hand sides under settings p,
+// whatever lane width, tile or time-marching choice the context makes: the
+// buffers of the solver path, each rounded to 256 B.  The partial arrays
+// shared by every solve of a call are counted by ws_partials.
+static size_t ws_block(const Geom& g, const Geom& hg, const tsm_solve_params* p, int nc) {
+    const size_t scal = align256(sizeof(CgScal) * kMaxBlock);
+    const int prec = p->prec;
+    const bool rel = p->reliable != 0;
+    const bool track = p->stop == TM_STOP_TRUE && !rel;
+    if (p->solver == TM_SOLVER_FCG_LEARNED) {
+        const size_t fb = align256(field_bytes(g, P_F32, nc));
+        return 7 * fb + align256(sizeof(FcgScal) * kMaxBlock) + scal + align256(field_bytes(g, P_BH, nc)) +
+               ws_net_apply(g, nc);
+    }
+    if (p->solver == TM_SOLVER_CG_EO) {
+        const int xprec = prec == P_F64 ? P_F64 : P_F32;
+        const size_t fb = align256(field_bytes(hg, prec, nc));
+        const bool ring = !rel && prec != P_F64;
+        size_t b = ring ? align256(field_bytes(hg, prec, nc) * kEoRing) + align256(sizeof(double) * kMaxBlock * kEoRing)
+                        : fb;
+        b += 3 * fb + align256(field_bytes(hg, xprec, nc)) + scal + (track ? fb : 0);
+        b += align256(field_bytes(g, rel ? P_F64 : xprec, nc));
+        b += 2 * align256(field_bytes(hg, rel ? P_F64 : prec, nc));
+        if (rel) b += 4 * align256(field_bytes(hg, P_F64, nc));
+        return b;
+    }
+    const size_t fb = align256(field_bytes(g, prec, nc));
+    size_t b = 3 * fb + align256(field_bytes(g, prec == P_F64 ? P_F64 : P_F32, nc)) + scal + (track ? fb : 0);
+    b += rel ? 4 * align256(field_bytes(g, P_F64, nc)) : fb;
+    return b;
+}
+
+static size_t ws_partials(const Geom& g, const Geom& hg, bool eo_ok, bool fcg) {
+    const size_t n = partials_per_rhs(g, hg, eo_ok) * kMaxBlock;
+    return 2 * align256(sizeof(double) * n) + (fcg ? align256(sizeof(double) * n * 4) : 0);
+}
+
+// setup_contract for maxr sources: phase tables, momentum indices, the two
+// stage buffers (nd distinct values per momentum component) and, for the
+// generalized one-end loop, D s
+static size_t ws_contract_setup(const Geom& g, int n_mom, int nd, int maxr, uint32_t est_mask) {
+    const int nmu = (est_mask & (1u << TM_LOOP_DERIVATIVE)) ? 4 : 1;
+    size_t b = align256(sizeof(double) * 2 * (size_t)nd * (g.L[0] + g.L[1] + g.L[2])) +
+               align256(sizeof(int) * 3 * (size_t)n_mom);
+    b += align256((size_t)maxr * nmu * g.L[3] * g.L[2] * nd * g.L[0] * 256);
+    b += align256((size_t)maxr * nmu * g.L[3] * g.L[2] * nd * nd * 256);
+    if (est_mask & (1u << TM_LOOP_ONEEND_GENERALIZED)) b += align256(field_bytes(g, P_F64, maxr));
+    return b;
+}
+
+static size_t ws_bound(const tm_lattice* lat, const Geom& g, const Geom& hg, bool eo_ok,
+                       const std::vector<tsm_solve_params>& sv, int max_sources, int max_mom, int nd,
+                       uint32_t est_mask, int all_mom, int field_rhs, int train_pairs, int train_sources,
+                       int loss_pairs) {
+    (void)lat;
+    const int N = std::max(max_sources, 1);
+    const int nmu = (est_mask & (1u << TM_LOOP_DERIVATIVE)) ? 4 : 1;
+    std::vector<int> blk(sv.size());
+    bool fcg = false;
+    int bmax = 1;
+    for (size_t i = 0; i < sv.size(); i++) {
+        blk[i] = std::min(default_block(&sv[i]), kMaxBlock);
+        bmax = std::max(bmax, blk[i]);
+        fcg = fcg || sv[i].solver == TM_SOLVER_FCG_LEARNED;
+    }
+    const size_t parts = ws_partials(g, hg, eo_ok, fcg);
+    size_t best = ws_abi_scratch(g, field_rhs, bmax);
+    // tsm_solve_batch
+    for (size_t i = 0; i < sv.size(); i++)
+        best = std::max(best, align256(sizeof(uint64_t) * (N + 4)) + ws_block(g, hg, &sv[i], blk[i]) + parts);
+    // autotuners: a truncated solve at each listed precision and block
+    for (size_t i = 0; i < sv.size(); i++) {
+        tsm_solve_params t = sv[i];
+        t.reliable = 0;
+        t.stop = TM_STOP_NORMAL;
+        const size_t ids = align256(sizeof(uint64_t) * blk[i]);
+        t.solver = TM_SOLVER_CG;
+        best = std::max(best, ids + ws_block(g, hg, &t, blk[i]) + parts);
+        if (eo_ok) {
+            t.solver = TM_SOLVER_CG_EO;
+            best = std::max(best, ids + ws_block(g, hg, &t, blk[i]) + parts);
+        }
+    }
+    // tsm_contract / tsm_contract_est at max_mom
+    {
+        const int b = std::min(N, kMaxBlock);
+        const size_t nl = (size_t)16 * nmu * max_mom * g.L[3];
+        best = std::max(best, ws_contract_setup(g, max_mom, nd, b, est_mask) + align256(sizeof(uint64_t) * N) +
+                                  align256(sizeof(int) * N) + align256(field_bytes(g, P_F64, b)) +
+                                  align256(sizeof(double) * 2 * nl * N));
+    }
+    // tsm_contract at all momenta
+    if (all_mom > 0) {
+        const int b = std::min(all_mom, 4);
+        best = std::max(best, align256(sizeof(double) * 2 * (g.L[0] + g.L[1] + g.L[2])) +
+                                  2 * align256(sizeof(double) * 2 * 16 * (size_t)g.V * b) +
+                                  align256(sizeof(uint64_t) * all_mom) + align256(sizeof(int) * all_mom) +
+                                  align256(field_bytes(g, P_F64, b)) +
+                                  align256(sizeof(double) * 2 * 16 * (size_t)g.V * all_mom));
+    }
+    // tsm_loops: any two listed settings as lp and hp
+    if (!sv.empty()) {
+        const size_t nl = (size_t)16 * nmu * max_mom * g.L[3];
+        const size_t fixed = ws_contract_setup(g, max_mom, nd, bmax + 4, est_mask) +
+                             align256(sizeof(double) * 4 * nl * N) + 2 * align256(sizeof(uint64_t) * (N + 8)) +
+                             align256(sizeof(double) * 12 * nl) + parts;
+        size_t pair = 0;
+        for (size_t i = 0; i < sv.size(); i++)
+            for (size_t j = 0; j < sv.size(); j++)
+                pair = std::max(pair, ws_block(g, hg, &sv[i], blk[i]) + ws_block(g, hg, &sv[j], blk[j]));
+        best = std::max(best, fixed + pair);
+    }
+    // network calls
+    best = std::max(best, 2 * align256(field_bytes(g, P_F32, field_rhs)) + ws_net_apply(g, field_rhs));
+    if (loss_pairs > 0) best = std::max(best, ws_loss_grad(g, loss_pairs));
+    if (train_pairs > 0) best = std::max(best, ws_train(g, hg, eo_ok, train_pairs, std::max(train_sources, 1)));
+    return ws_persistent(g, hg, eo_ok) + best + (size_t(1) << 20);
+}
+
 }  // namespace tmq
 
 using namespace tmq;
@@ -1034,14 +1159,19 @@ using namespace tmq;
 extern "C" {
 
 tm_status tsm_solve_batch(tm_ctx* ctx, const tsm_solve_params* params, uint64_t seed, int32_t nsrc,
-                          const uint64_t* ids_host, double* sol_dev, tsm_solve_stats* stats_host) {
+                          const uint64_t* ids_host, void* sol_dev, tsm_solve_stats* stats_host) {
     if (!ctx) return TM_EINVAL;
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    WsScope scope(ctx);
     if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tsm_solve_batch: no gauge field loaded");
     tm_status s = check_solve_params(ctx, params);
     if (s != TM_OK) return s;
     if (nsrc < 0 || (nsrc > 0 && (!ids_host || !stats_host)))
         return set_error(ctx, TM_EINVAL, "tsm_solve_batch: bad source list");
+    if (params->out_layout != TM_LAYOUT_CANONICAL && params->out_layout != TM_LAYOUT_NATIVE)
+        return set_error(ctx, TM_EINVAL, "tsm_solve_batch: bad out_layout");
+    if (params->out_prec < TM_PREC_F64 || params->out_prec > TM_PREC_BF16)
+        return set_error(ctx, TM_EINVAL, "tsm_solve_batch: bad out_prec");
     if (nsrc == 0) return TM_OK;
     const Geom& g = ctx->geo;
     const int blk = default_block(params);
@@ -1066,7 +1196,8 @@ tm_status tsm_solve_batch(tm_ctx* ctx, const tsm_solve_params* params, uint64_t 
             if (params->max_iter < 0 && ctx->scal_host[r].status != 1) warn = true;
         }
         if (sol_dev) {
-            launch_native_to_c128(ctx->stream, g, res.xprec, nb, res.x, sol_dev + (size_t)j0 * g.V * 24);
+            launch_sol_out(ctx->stream, g, res.xprec, nb, res.x, sol_dev, params->out_prec,
+                           params->out_layout == TM_LAYOUT_NATIVE, j0);
             TM_HIP(hipGetLastError());
         }
     }
@@ -1083,6 +1214,7 @@ tm_status tsm_contract_est(tm_ctx* ctx, int32_t estimator, uint64_t seed, int32_
                            const double* sol_dev, int32_t n_mom, const int32_t* mom_host, double* loops_host) {
     if (!ctx) return TM_EINVAL;
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    WsScope scope(ctx);
     if (estimator < TM_LOOP_STANDARD || estimator > TM_LOOP_DERIVATIVE)
         return set_error(ctx, TM_EINVAL, "tsm_contract: unknown estimator");
     const bool needs_eta = estimator == TM_LOOP_STANDARD || estimator == TM_LOOP_DERIVATIVE;
@@ -1131,6 +1263,7 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double
     using clk = std::chrono::steady_clock;
     if (!ctx) return TM_EINVAL;
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    WsScope scope(ctx);
     if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tsm_loops: no gauge field loaded");
     if (!P || !loops_host) return set_error(ctx, TM_EINVAL, "tsm_loops: null argument");
     if (P->n_hp < 0 || P->n_lp < 0) return set_error(ctx, TM_EINVAL, "tsm_loops: negative source count");
@@ -1149,6 +1282,13 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double
 
     const int blp = default_block(&P->lp), bhp = default_block(&P->hp);
     const int nr_lp = lane_rhs(ctx, &P->lp, blp), nr_hp = lane_rhs(ctx, &P->hp, bhp);
+    // LP buffers sized for the LP blocks from the first (smaller) HP-set
+    // block on, HP buffers for the padded HP-set blocks
+    {
+        const int bh0 = std::min(blp, bhp);
+        ctx->ws_cap["lp"] = blp;
+        ctx->ws_cap["hp"] = (bh0 + nr_hp - 1) / nr_hp * nr_hp;
+    }
     Contractor c;
     if ((s = setup_contract(ctx, mp, P->n_mom, std::max(blp, bhp) + 4, sm, P->estimator, &c)) != TM_OK) return s;
 
@@ -1239,6 +1379,7 @@ tm_status tm_autotune_cg(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_
     if (!ctx || prec < 0 || prec > 3 || nrhs < 1 || nrhs > kMaxBlock || !best_nr || !best_tseg)
         return ctx ? set_error(ctx, TM_EINVAL, "tm_autotune_cg: bad argument") : TM_EINVAL;
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    WsScope scope(ctx);
     if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tm_autotune_cg: no gauge field loaded");
     tm_status s = TM_OK;
     uint64_t* ids = (uint64_t*)ws_get(ctx, "tune_ids", sizeof(uint64_t) * nrhs, &s);
@@ -1305,6 +1446,7 @@ tm_status tm_autotune_eo(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_
     if (!ctx || prec < 1 || prec > 3 || nrhs < 1 || nrhs > kMaxBlock || !best_nr || !best_tiles)
         return ctx ? set_error(ctx, TM_EINVAL, "tm_autotune_eo: bad argument") : TM_EINVAL;
     if (ctx->sticky) return set_error(ctx, TM_EDEVICE, "context has a sticky device error");
+    WsScope scope(ctx);
     if (!ctx->gauge_loaded) return set_error(ctx, TM_ESTATE, "tm_autotune_eo: no gauge field loaded");
     if (!ctx->eo_ok) return set_error(ctx, TM_ENOTSUP, "tm_autotune_eo: the even-odd solver needs even extents");
     tm_status s = TM_OK;
@@ -1367,6 +1509,47 @@ tm_status tm_autotune_eo(tm_ctx* ctx, int32_t prec, int32_t nrhs, int32_t* best_
     *best_nr = bnr;
     *best_tiles = bt;
     return TM_OK;
+}
+
+size_t tm_workspace_bytes(const tm_lattice* lat, const tm_caps* caps) {
+    if (!lat) return 0;
+    Geom g, hg;
+    bool eo_ok = false;
+    std::string why;
+    if (!geom_setup(lat, &g, &hg, &eo_ok, &why)) return 0;
+    std::vector<tsm_solve_params> sv;
+    if (!caps) {
+        // every solver and storage precision at 32 sources per block
+        for (int solver : {TM_SOLVER_CG, TM_SOLVER_CG_EO, TM_SOLVER_FCG_LEARNED})
+            for (int prec = TM_PREC_F64; prec <= TM_PREC_BF16; prec++)
+                for (int rel = 0; rel <= 1; rel++)
+                    for (int stop : {TM_STOP_NORMAL, TM_STOP_TRUE}) {
+                        if ((rel && prec != TM_PREC_F32) || (solver == TM_SOLVER_FCG_LEARNED && (prec != TM_PREC_F32 || rel)) ||
+                            (solver == TM_SOLVER_CG_EO && !eo_ok))
+                            continue;
+                        tsm_solve_params p;
+                        std::memset(&p, 0, sizeof(p));
+                        p.prec = prec;
+                        p.solver = solver;
+                        p.reliable = rel;
+                        p.stop = stop;
+                        p.rhs_block = kMaxBlock;
+                        sv.push_back(p);
+                    }
+        const uint32_t all_est = (1u << TM_LOOP_STANDARD) | (1u << TM_LOOP_ONEEND_ISOVECTOR) |
+                                 (1u << TM_LOOP_ONEEND_GENERALIZED) | (1u << TM_LOOP_DERIVATIVE);
+        return ws_bound(lat, g, hg, eo_ok, sv, 256, 27, 3, all_est, 4, kMaxBlock, 64, 64, 64);
+    }
+    if (caps->n_solves < 0 || caps->n_solves > TM_CAPS_MAX_SOLVES || caps->max_sources < 0 || caps->max_mom < 0 ||
+        caps->mom_distinct < 0 || caps->all_mom_sources < 0 || caps->field_rhs < 0 || caps->train_pairs < 0 ||
+        caps->train_sources < 0 || caps->loss_pairs < 0)
+        return 0;
+    for (int i = 0; i < caps->n_solves; i++) sv.push_back(caps->solves[i]);
+    const int max_mom = std::max(caps->max_mom, 1);
+    const int nd = caps->mom_distinct > 0 ? std::min(caps->mom_distinct, max_mom) : max_mom;
+    const uint32_t est = caps->estimators ? caps->estimators : (1u << TM_LOOP_STANDARD);
+    return ws_bound(lat, g, hg, eo_ok, sv, caps->max_sources, max_mom, nd, est, caps->all_mom_sources,
+                    std::max(caps->field_rhs, 1), caps->train_pairs, caps->train_sources, caps->loss_pairs);
 }
 
 }  // extern "C"

@@ -46,7 +46,7 @@ def test_binding_covers_header():
 
 
 def test_abi_version(lib):
-    assert lib.tm_abi_version() == 2
+    assert lib.tm_abi_version() == 3
 
 
 def test_product_path_has_no_oracle_dependency():
@@ -74,16 +74,24 @@ def test_too_large_lattices_are_rejected_before_any_device_call(lib):
     """tm_create refuses volumes whose 36 planes of FP64 links would need
     byte offsets of 2^32 or more (checked before any HIP call)."""
     from paper_1211_0126_amd.binding import Lattice
-    lib.tm_create.argtypes = [ctypes.POINTER(Lattice), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
-    lib.tm_create.restype = ctypes.c_int32
-    lib.tm_last_error.argtypes = [ctypes.c_void_p]
-    lib.tm_last_error.restype = ctypes.c_char_p
     for dims in ((48, 48, 48, 96), (64, 64, 64, 64), (256, 256, 256, 16)):
         lat = Lattice((ctypes.c_int32 * 4)(*dims), 0.16, 0.01, -1)
         out = ctypes.c_void_p()
-        assert lib.tm_create(ctypes.byref(lat), None, ctypes.byref(out)) == -1, dims
+        assert lib.tm_create(ctypes.byref(lat), None, 1 << 30, None, ctypes.byref(out)) == -1, dims
         assert not out.value
         assert b"too large" in lib.tm_last_error(None)
+        assert lib.tm_workspace_bytes(ctypes.byref(lat), None) == 0
+
+
+def test_undersized_workspace_is_rejected_before_any_device_call(lib):
+    """A workspace below what the context itself holds is TM_ENOMEM from
+    tm_create, before any HIP call."""
+    from paper_1211_0126_amd.binding import Lattice
+    lat = Lattice((ctypes.c_int32 * 4)(4, 4, 4, 4), 0.16, 0.01, -1)
+    out = ctypes.c_void_p()
+    assert lib.tm_create(ctypes.byref(lat), None, 4096, None, ctypes.byref(out)) == -2
+    assert not out.value
+    assert b"workspace" in lib.tm_last_error(None)
 
 
 def test_struct_layouts_match_binding(tmp_path):
@@ -94,7 +102,7 @@ def test_struct_layouts_match_binding(tmp_path):
     from paper_1211_0126_amd import binding as b
     structs = {"tm_lattice": b.Lattice, "tsm_solve_params": b.SolveParams, "tsm_solve_stats": b.SolveStats,
                "tsm_params": b.TsmParams, "tsm_run_stats": b.RunStats, "tm_net_shape": b.NetShape,
-               "tm_train_params": b.TrainParams, "tm_train_stats": b.TrainStats}
+               "tm_train_params": b.TrainParams, "tm_train_stats": b.TrainStats, "tm_caps": b.Caps}
     lines = []
     for cname, cls in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))

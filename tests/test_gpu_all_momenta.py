@@ -27,7 +27,7 @@ def test_all_momenta_match_oracle(orc, dims, kind):
     import torch
     import paper_1211_0126_amd as tq
     U = make_gauge(dims, 0.3, 29)
-    ctx = tq.tm_create(dims, KAPPA, MU, -1)
+    ctx = tq.tm_create(dims, KAPPA, MU, -1, caps=tq.caps([], max_sources=8, all_mom_sources=8))
     tq.tm_gauge_load(ctx, U)
     ids = [0, 3, 4, 7, 11]
     v = int(np.prod(dims))
@@ -53,7 +53,7 @@ def test_all_momenta_agree_with_separable_path():
     import paper_1211_0126_amd as tq
     dims = (16, 8, 8, 16)
     U = make_gauge(dims, 0.25, 31)
-    ctx = tq.tm_create(dims, KAPPA, MU, -1)
+    ctx = tq.tm_create(dims, KAPPA, MU, -1, caps=tq.caps([], max_sources=8, all_mom_sources=8))
     tq.tm_gauge_load(ctx, U)
     rng = np.random.default_rng(7)
     v = int(np.prod(dims))

@@ -20,7 +20,8 @@ def test_bench_launch_shape_full_lattice(orc):
     import paper_1211_0126_amd as tq
     print("generating the 32^3x64 gauge field", flush=True)
     U = make_gauge(C3.dims, C3.eps, C3.gauge_seed)
-    ctx = tq.tm_create(C3.dims, C3.kappa, C3.mu, -1)
+    caps = tq.caps([tq.solve_params(prec=tq.PREC_F16, rhs_block=16)], max_sources=16)
+    ctx = tq.tm_create(C3.dims, C3.kappa, C3.mu, -1, caps=caps)
     tq.tm_gauge_load(ctx, U)
     ids = list(range(100, 116))
     p = tq.solve_params(prec=tq.PREC_F16, tol=0.0, max_iter=3, rhs_block=16, true_resid=1)
@@ -63,7 +64,8 @@ def test_evenodd_blocks_of_32_full_lattice(orc):
     import paper_1211_0126_amd as tq
     print("generating the 32^3x64 gauge field", flush=True)
     U = make_gauge(C3.dims, C3.eps, C3.gauge_seed)
-    ctx = tq.tm_create(C3.dims, C3.kappa, C3.mu, -1)
+    caps = tq.caps([tq.solve_params(prec=tq.PREC_F16, rhs_block=32, solver=tq.SOLVER_CG_EO)], max_sources=32)
+    ctx = tq.tm_create(C3.dims, C3.kappa, C3.mu, -1, caps=caps)
     tq.tm_gauge_load(ctx, U)
     ids = list(range(200, 232))
     tq.tm_set_lane_rhs(ctx, tq.PREC_F16, 2)

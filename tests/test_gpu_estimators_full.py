@@ -36,7 +36,7 @@ def test_one_end_loops_full_lattice(orc, gauge, est):
     fields = np.zeros((len(slices), DIMS[3], vs, 4, 3), dtype=np.complex128)
     for i, t0 in enumerate(slices):
         fields[i, t0] = rng.standard_normal((vs, 4, 3)) + 1j * rng.standard_normal((vs, 4, 3))
-    ctx = tq.tm_create(DIMS, KAPPA, MU, -1)
+    ctx = tq.tm_create(DIMS, KAPPA, MU, -1, caps=tq.caps([], max_sources=len(slices), estimators=(est,)))
     tq.tm_gauge_load(ctx, gauge)
     mom = momenta_27()
     print("full-lattice one-end est=%d" % est, flush=True)

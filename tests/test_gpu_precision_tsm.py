@@ -34,10 +34,10 @@ def oracle_tsm(orc):
 def test_reduced_precision_tsm_against_fp64_oracle(oracle_tsm, prec):
     import paper_1211_0126_amd as tq
     U, mom, ref = oracle_tsm
-    ctx = tq.tm_create(DIMS, KAPPA, MU, -1)
-    tq.tm_gauge_load(ctx, U)
     lp = tq.solve_params(prec=prec, tol=1e-2, max_iter=-1, rhs_block=16, true_resid=0)
     hp = tq.solve_params(prec=tq.PREC_F32, tol=1e-10, max_iter=-1, reliable=1, delta=0.1, rhs_block=8)
+    ctx = tq.tm_create(DIMS, KAPPA, MU, -1, caps=tq.caps([lp, hp], max_sources=N_HP + N_LP, max_mom=len(mom)))
+    tq.tm_gauge_load(ctx, U)
     res = tq.tsm_loops(ctx, SEED, N_HP, N_LP, lp, hp, mom, per_source=True)
     ctx.close()
     T, T_ref = res["loops"][2], ref["loops"][2]
