@@ -69,7 +69,7 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_lin(EoArgs a) {
     const void* in0 = field_rhs<Si>(a.in, Vs, r0);
     const uint32_t nsb_all = (uint32_t)((hg.V + 255) / 256);
     for (uint32_t sb = bm.sb; sb < nsb_all; sb += bm.nsb) {
-        const uint32_t h = sb * 256u + threadIdx.x;
+        const uint32_t h = eo_site(hg, sb, threadIdx.x);
         if (h >= hg.V) continue;
         const EoSite c = eo_coords(hg, h, a.pout);
         cx<R> acc[NR][12];
@@ -124,7 +124,7 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_rec_full(EoArgs a, Geom g, void* full) 
     const Geom& hg = a.hg;
     const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
     const int r0 = bm.ch * NR;
-    const uint32_t h = bm.sb * 256u + threadIdx.x;
+    const uint32_t h = eo_site(hg, bm.sb, threadIdx.x);
     if (h >= hg.V) return;
     const long Vs = hg.Vs;
     const R tw = (R)a.twist;
@@ -175,7 +175,7 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_mp(CgArgs a, EoCg e) {
     const Geom& hg = a.geo;
     const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
     const uint32_t nb = bm.nsb;
-    const uint32_t h = bm.sb * 256u + threadIdx.x;
+    const uint32_t h = eo_site(hg, bm.sb, threadIdx.x);
     const int r0 = bm.ch * NR;
     const long Vs = hg.Vs;
     bool act[NR];
@@ -223,7 +223,7 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_upd(CgArgs a, EoCg e) {
     const Geom& hg = a.geo;
     const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
     const uint32_t nb = bm.nsb;
-    const uint32_t h = bm.sb * 256u + threadIdx.x;
+    const uint32_t h = eo_site(hg, bm.sb, threadIdx.x);
     const int r0 = bm.ch * NR;
     const long Vs = hg.Vs;
     bool act[NR];
@@ -350,7 +350,7 @@ __global__ TM_STENCIL_R(NR, double) void k_eo_rel_resid(CgArgs a, EoCg e, const 
     for (int r = 0; r < NR; r++) pr[r] = pt[r] = 0;
     const double k2 = -a.kappa * a.kappa;
     for (uint32_t sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
-        const uint32_t h = sb * 256u + threadIdx.x;
+        const uint32_t h = eo_site(hg, sb, threadIdx.x);
         if (h >= hg.V) continue;
         const EoSite c = eo_coords(hg, h, 1);
         cx<double> acc[NR][12];

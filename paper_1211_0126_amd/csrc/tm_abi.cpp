@@ -269,6 +269,7 @@ bool geom_setup(const tm_lattice* lat, Geom* gp, Geom* hp, bool* eo_ok, std::str
         return false;
     }
     Geom& g = *gp;
+    g.brick = 0;
     for (int d = 0; d < 4; d++) g.L[d] = lat->dims[d];
     g.t_bc = lat->t_bc;
     g.V = V;
@@ -318,6 +319,14 @@ bool geom_setup(const tm_lattice* lat, Geom* gp, Geom* hp, bool* eo_ok, std::str
         else
             h.m[0] = (uint32_t)m;
     }
+#ifndef TM_EO_NATURAL
+    // brick order of the half-lattice site blocks: a wave is 64 / (Lx/2)
+    // whole rows, a block four z planes of them
+    if (*eo_ok) {
+        const int Lxh = g.L[0] / 2;
+        if (64 % Lxh == 0 && g.L[1] % (64 / Lxh) == 0 && g.L[2] % 4 == 0) h.brick = (uint32_t)(64 / Lxh);
+    }
+#endif
     return true;
 }
 

@@ -34,6 +34,25 @@ __device__ __forceinline__ EoSite eo_coords(const Geom& hg, uint32_t h, int par)
     return c;
 }
 
+// Half-site of thread tid in site block sb.  Natural order: 256 consecutive
+// half-sites.  Brick order (hg.brick = rows per wave, Lx/2 * hg.brick = 64):
+// a wave covers hg.brick consecutive rows of one z plane (1 KiB per plane of
+// an FP32 field, as in the natural order), the block's four waves four
+// consecutive z planes of one time slice, and the blocks run time slice
+// fastest, so the time neighbours a block gathers belong to the blocks
+// dispatched just before and after it on the same XCD (served from its L2
+// instead of HBM).
+__device__ __forceinline__ uint32_t eo_site(const Geom& hg, uint32_t sb, uint32_t tid) {
+    if (hg.brick == 0) return sb * 256u + tid;
+    const uint32_t Lxh = (uint32_t)hg.L[0] >> 1, by = hg.brick;
+    const uint32_t Lt = (uint32_t)hg.L[3], nty = (uint32_t)hg.L[1] / by;
+    const uint32_t t = sb % Lt, col = sb / Lt;
+    const uint32_t ty = col % nty, tz = col / nty;
+    const uint32_t lane = tid & 63u;
+    const uint32_t y = ty * by + lane / Lxh, z = tz * 4u + (tid >> 6);
+    return lane % Lxh + Lxh * (y + (uint32_t)hg.L[1] * (z + (uint32_t)hg.L[2] * t));
+}
+
 // half index of the neighbour (opposite parity) in direction mu
 __device__ __forceinline__ uint32_t eo_nb(const Geom& hg, uint32_t h, const EoSite& c, int mu, bool fwd) {
     const uint32_t L0 = hg.L[0], L1 = hg.L[1], L2 = hg.L[2], L3 = hg.L[3];

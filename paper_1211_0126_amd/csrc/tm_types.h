@@ -52,6 +52,7 @@ struct Geom {
     int64_t V;
     int64_t Vs;     // padded plane stride of native fields (multiple of 256)
     uint32_t m[3];  // ceil(2^32 / L[d]) for exact division of site indices
+    uint32_t brick; // half lattice: rows per wave of the brick order of site blocks (0: natural order)
 };
 
 enum SPrec { P_F64 = 0, P_F32 = 1, P_F16 = 2, P_BF16 = 3, P_BH = 4 /* network-internal bfloat16, half-split planes */ };

@@ -13,12 +13,15 @@ from lattice_inputs.workloads import get_workload, momenta_27
 pytestmark = pytest.mark.gpu
 
 # (dims, kappa, a*mu, eps): single partial block of half sites (2x4x6x8:
-# 192 per parity), ragged (6x4x8x10: 960), the 4^4 workload, several tiles
+# 192 per parity), ragged (6x4x8x10: 960), the 4^4 workload, several tiles,
+# and a lattice whose half-site blocks run in the brick order (Lx/2 = 8: a
+# wave is 8 rows, a block 4 z planes; 2 x 2 bricks per time slice)
 LATTICES = [
     ((2, 4, 6, 8), 0.1632, 0.004, 0.3),
     ((6, 4, 8, 10), 0.1632, 0.003, 0.25),
     ((4, 4, 4, 4), 0.160, 0.03125, 0.3),
     ((8, 8, 8, 8), 0.1632, 0.004, 0.25),
+    ((16, 16, 8, 4), 0.1632, 0.004, 0.25),
 ]
 
 
@@ -131,6 +134,34 @@ def test_eo_reduced_precision_lp(orc, prec, tiles):
         assert abs(st[i]["iters"] - so["iters"]) <= 1, (st[i], so)
         assert abs(st[i]["resid_true"] - so["resid_true"]) < 0.05 * so["resid_true"] + 1e-3
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_eo_brick_order_lp_and_reliable_hp(orc, prec):
+    """On the brick-order lattice: reduced-precision LP solves (the ring of
+    directions) within an iteration of the FP64 oracle, and FP32 HP solves
+    with FP64 reliable updates to 1e-8 of the oracle's solution."""
+    import paper_1211_0126_amd as tq
+    dims, kappa, mu, eps = LATTICES[4]
+    U = make_gauge(dims, eps, 47)
+    ctx = _ctx(dims, kappa, mu, U)
+    ids = list(range(4))
+    p = tq.solve_params(prec=prec, tol=1e-2, max_iter=-1, rhs_block=4, solver=tq.SOLVER_CG_EO)
+    _, st, _ = tq.tsm_solve_batch(ctx, p, 5, ids)
+    hp = tq.solve_params(prec=tq.PREC_F32, tol=1e-10, max_iter=-1, reliable=1, delta=0.1, rhs_block=2,
+                         stop=tq.STOP_TRUE, solver=tq.SOLVER_CG_EO)
+    sol, sth, _ = tq.tsm_solve_batch(ctx, hp, 5, ids[:2])
+    sol = sol.cpu().numpy()
+    ctx.close()
+    for i, j in enumerate(ids):
+        eta = orc.noise_z4(dims, 5, j)
+        x, so = orc.cgnr_eo(dims, -1, kappa, mu, U, eta, 1e-2)
+        assert st[i]["converged"] and abs(st[i]["iters"] - so["iters"]) <= 1, (st[i], so)
+        assert abs(st[i]["resid_true"] - so["resid_true"]) < 0.05 * so["resid_true"] + 1e-3
+        if i < 2:
+            x, so = orc.cgnr_eo(dims, -1, kappa, mu, U, eta, 1e-10, -1, tq.STOP_TRUE)
+            assert sth[i]["converged"] and sth[i]["resid_true"] <= 1e-10
+            assert _rel(sol[i], x) < 1e-8, _rel(sol[i], x)
 
 
 @pytest.mark.parametrize("prec", [1, 2])
