@@ -1,5 +1,8 @@
 // Flexible CG on M^dag M with the network preconditioner z = N(N^dag(r))
-// (Notay 2000; Golub & Ye 1999), FP32 vectors, FP64 complex scalars.
+// (Notay 2000; Golub & Ye 1999), FP64 complex scalars.  The stencil inputs
+// p and t are stored in a.prec (FP32, FP16 or BF16: the search direction
+// and M p as the stored values, so q = M^dag M p and the updates of x and r
+// use the same rounded p); q, r, x and z are FP32.
 //   F1  t = M p, |t|^2                         -> alpha = <z,r> / |t|^2
 //   F2  q = M^dag t (kept), x += alpha p, r -= alpha q, |r|^2 -> stop tests,
 //       stagnation test (|r| not below its value five steps earlier)
@@ -15,20 +18,22 @@
 
 namespace tmq {
 
-// out = M in (DAG: M^dag in), single right-hand side, FP32
-template <bool DAG>
+// out = M in (DAG: M^dag in), single right-hand side stored as S, FP32
+// arithmetic
+template <bool DAG, class S>
 __device__ __forceinline__ void fop(const Geom& geo, const void* gauge, float kappa, float tw, const void* in,
                                     uint32_t s, cx<float> out[12]) {
     const Site c = site_coords(geo, s);
     cx<float> acc[1][12], p[12];
-    hop_all<DAG, float, SF32, GF32, 1>(geo, gauge, in, s, c, acc);
-    load_spinor<SF32, float>(in, geo.Vs, s, p);
+    hop_all<DAG, float, S, GF32, 1>(geo, gauge, in, s, c, acc);
+    load_spinor<S, float>(in, geo.Vs, s, p);
     diag_combine(p, acc[0], kappa, DAG ? -tw : tw, out);
 }
 
 __device__ __forceinline__ bool finite_d(double v) { return v == v && v < 1e300 && v > -1e300; }
 
-// F1: t = M p, alpha = <z,r> / |t|^2
+// F1: t = M p, alpha = <z,r> / |t|^2 (|t|^2 of t as stored)
+template <class S>
 __global__ TM_STENCIL(1) void k_fcg_mp(FcgArgs a) {
     __shared__ double sh[4];
     const uint32_t nb = gridDim.x, b = xcd_block(blockIdx.x, nb);
@@ -39,8 +44,9 @@ __global__ TM_STENCIL(1) void k_fcg_mp(FcgArgs a) {
     double part = 0;
     if (s < a.geo.V) {
         cx<float> t[12];
-        fop<false>(a.geo, a.gauge, (float)a.kappa, (float)a.twist, field_rhs<SF32>(a.p, Vs, r), s, t);
-        store_spinor<SF32, float>(field_rhs<SF32>(a.t, Vs, r), Vs, s, t);
+        fop<false, S>(a.geo, a.gauge, (float)a.kappa, (float)a.twist, field_rhs<S>(a.p, Vs, r), s, t);
+        round_storage<S, float>(t);
+        store_spinor<S, float>(field_rhs<S>(a.t, Vs, r), Vs, s, t);
 #pragma unroll
         for (int k = 0; k < 12; k++) part += (double)t[k].re * t[k].re + (double)t[k].im * t[k].im;
     }
@@ -70,6 +76,7 @@ __global__ __launch_bounds__(256) void k_fcg_mp_fin(FcgArgs a, uint32_t nb) {
 }
 
 // F2: q = M^dag t, x += alpha p, r -= alpha q, |r|^2, stop and stagnation tests
+template <class S>
 __global__ TM_STENCIL(1) void k_fcg_upd(FcgArgs a) {
     __shared__ double sh[4];
     const uint32_t nb = gridDim.x, b = xcd_block(blockIdx.x, nb);
@@ -81,12 +88,12 @@ __global__ TM_STENCIL(1) void k_fcg_upd(FcgArgs a) {
     if (s < a.geo.V) {
         const float ar = (float)a.scal[r].alpha_re, ai = (float)a.scal[r].alpha_im;
         cx<float> q[12], rv[12], pv[12], xv[12];
-        fop<true>(a.geo, a.gauge, (float)a.kappa, (float)a.twist, field_rhs<SF32>(a.t, Vs, r), s, q);
+        fop<true, S>(a.geo, a.gauge, (float)a.kappa, (float)a.twist, field_rhs<S>(a.t, Vs, r), s, q);
         store_spinor<SF32, float>(field_rhs<SF32>(a.q, Vs, r), Vs, s, q);
         void* rp = field_rhs<SF32>(a.r, Vs, r);
         void* xp = field_rhs<SF32>(a.x, Vs, r);
         load_spinor<SF32, float>(rp, Vs, s, rv);
-        load_spinor<SF32, float>(field_rhs<SF32>(a.p, Vs, r), Vs, s, pv);
+        load_spinor<S, float>(field_rhs<S>(a.p, Vs, r), Vs, s, pv);
         load_spinor<SF32, float>(xp, Vs, s, xv);
         const cx<float> al = {ar, ai};
 #pragma unroll
@@ -220,7 +227,8 @@ __global__ __launch_bounds__(256) void k_fcg_dot_fin(FcgArgs a, uint32_t nb, int
     }
 }
 
-// F4: p = z + beta p (mode 0), r + beta p (1), r (2), z (3)
+// F4: p = z + beta p (mode 0), r + beta p (1), r (2), z (3); p stored as S
+template <class S>
 __global__ __launch_bounds__(256) void k_fcg_p(FcgArgs a) {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     const int r = blockIdx.y;
@@ -230,15 +238,15 @@ __global__ __launch_bounds__(256) void k_fcg_p(FcgArgs a) {
     const long Vs = a.geo.Vs;
     cx<float> src[12], pv[12];
     load_spinor<SF32, float>(field_rhs<SF32>((q.mode == 0 || q.mode == 3) ? a.z : a.r, Vs, r), Vs, s, src);
-    void* pp = field_rhs<SF32>(a.p, Vs, r);
+    void* pp = field_rhs<S>(a.p, Vs, r);
     if (q.mode <= 1) {
         const cx<float> be = {(float)q.beta_re, (float)q.beta_im};
-        load_spinor<SF32, float>(pp, Vs, s, pv);
+        load_spinor<S, float>(pp, Vs, s, pv);
 #pragma unroll
         for (int k = 0; k < 12; k++) pv[k] = src[k] + be * pv[k];
-        store_spinor<SF32, float>(pp, Vs, s, pv);
+        store_spinor<S, float>(pp, Vs, s, pv);
     } else {
-        store_spinor<SF32, float>(pp, Vs, s, src);
+        store_spinor<S, float>(pp, Vs, s, src);
     }
 }
 
@@ -295,11 +303,23 @@ void launch_fcg_init(hipStream_t st, const FcgArgs& a, double tol2, int maxit, i
     hipLaunchKernelGGL(k_fcg_init_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, fblocks(a.geo), tol2, maxit, fell);
 }
 void launch_fcg_mp(hipStream_t st, const FcgArgs& a) {
-    hipLaunchKernelGGL(k_fcg_mp, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a);
+    const dim3 gr = fgrid(a.geo, a.nrhs);
+    if (a.prec == P_F16)
+        hipLaunchKernelGGL(k_fcg_mp<SF16>, gr, dim3(256), 0, st, a);
+    else if (a.prec == P_BF16)
+        hipLaunchKernelGGL(k_fcg_mp<SBF16>, gr, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_fcg_mp<SF32>, gr, dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_fcg_mp_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, fblocks(a.geo));
 }
 void launch_fcg_upd(hipStream_t st, const FcgArgs& a) {
-    hipLaunchKernelGGL(k_fcg_upd, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a);
+    const dim3 gr = fgrid(a.geo, a.nrhs);
+    if (a.prec == P_F16)
+        hipLaunchKernelGGL(k_fcg_upd<SF16>, gr, dim3(256), 0, st, a);
+    else if (a.prec == P_BF16)
+        hipLaunchKernelGGL(k_fcg_upd<SBF16>, gr, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_fcg_upd<SF32>, gr, dim3(256), 0, st, a);
     hipLaunchKernelGGL(k_fcg_upd_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, fblocks(a.geo));
 }
 void launch_fcg_mp_fin(hipStream_t st, const FcgArgs& a, uint32_t nb) {
@@ -313,7 +333,13 @@ void launch_fcg_dot(hipStream_t st, const FcgArgs& a, int init) {
     hipLaunchKernelGGL(k_fcg_dot_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, fblocks(a.geo), init);
 }
 void launch_fcg_p(hipStream_t st, const FcgArgs& a) {
-    hipLaunchKernelGGL(k_fcg_p, fgrid(a.geo, a.nrhs), dim3(256), 0, st, a);
+    const dim3 gr = fgrid(a.geo, a.nrhs);
+    if (a.prec == P_F16)
+        hipLaunchKernelGGL(k_fcg_p<SF16>, gr, dim3(256), 0, st, a);
+    else if (a.prec == P_BF16)
+        hipLaunchKernelGGL(k_fcg_p<SBF16>, gr, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_fcg_p<SF32>, gr, dim3(256), 0, st, a);
 }
 
 }  // namespace tmq

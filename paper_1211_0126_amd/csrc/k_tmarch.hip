@@ -264,10 +264,11 @@ __global__ TM_MARCH_R(NR, R) void k_tm_upd(CgArgs a) {
     }
 }
 
-// Flexible CG with the marching stencils (FP32 fields, complex alpha):
-// F1 t = M p with block partials of |t|^2; F2 q = M^dag t (kept for the
-// direction update), x += alpha p, r -= alpha q, block partials of |r|^2.
-template <int NR>
+// Flexible CG with the marching stencils (p and t stored as S, the other
+// fields FP32, complex alpha): F1 t = M p with block partials of |t|^2 (of
+// t as stored); F2 q = M^dag t (kept for the direction update), x += alpha
+// p, r -= alpha q, block partials of |r|^2.
+template <int NR, class S>
 __global__ TM_MARCH_R(NR, float) void k_fcg_tm_mp(FcgArgs a, int tseg, uint32_t npart) {
     __shared__ double sh[4];
     const Geom& g = a.geo;
@@ -291,16 +292,16 @@ __global__ TM_MARCH_R(NR, float) void k_fcg_tm_mp(FcgArgs a, int tseg, uint32_t 
     const int t1 = min(t0 + tseg, Lt);
     if (s3 < V3) {
         const long Vs = g.Vs;
-        march<false, float, SF32, GF32, NR>(g, a.gauge, field_rhs<SF32>(a.p, Vs, r0), a.kappa, a.twist, s3, V3, t0,
-                                            t1, [&](int, uint32_t s, cx<float> (&out)[NR][12]) {
+        march<false, float, S, GF32, NR>(g, a.gauge, field_rhs<S>(a.p, Vs, r0), a.kappa, a.twist, s3, V3, t0, t1,
+                                         [&](int, uint32_t s, cx<float> (&out)[NR][12]) {
 #pragma unroll
-                                                for (int r = 0; r < NR; r++) {
-                                                    if (!act[r]) continue;
-                                                    store_spinor<SF32, float>(field_rhs<SF32>(a.t, Vs, r0 + r), Vs, s,
-                                                                              out[r]);
-                                                    part[r] += spinor_norm2(out[r]);
-                                                }
-                                            });
+                                             for (int r = 0; r < NR; r++) {
+                                                 if (!act[r]) continue;
+                                                 round_storage<S, float>(out[r]);
+                                                 store_spinor<S, float>(field_rhs<S>(a.t, Vs, r0 + r), Vs, s, out[r]);
+                                                 part[r] += spinor_norm2(out[r]);
+                                             }
+                                         });
     }
     const uint32_t blk = m.tile + m.ntile * m.seg;
 #pragma unroll
@@ -310,7 +311,7 @@ __global__ TM_MARCH_R(NR, float) void k_fcg_tm_mp(FcgArgs a, int tseg, uint32_t 
     }
 }
 
-template <int NR>
+template <int NR, class S>
 __global__ TM_MARCH_R(NR, float) void k_fcg_tm_upd(FcgArgs a, int tseg, uint32_t npart) {
     __shared__ double sh[4];
     const Geom& g = a.geo;
@@ -335,8 +336,8 @@ __global__ TM_MARCH_R(NR, float) void k_fcg_tm_upd(FcgArgs a, int tseg, uint32_t
     const int t1 = min(t0 + tseg, Lt);
     if (s3 < V3) {
         const long Vs = g.Vs;
-        march<true, float, SF32, GF32, NR>(
-            g, a.gauge, field_rhs<SF32>(a.t, Vs, r0), a.kappa, a.twist, s3, V3, t0, t1,
+        march<true, float, S, GF32, NR>(
+            g, a.gauge, field_rhs<S>(a.t, Vs, r0), a.kappa, a.twist, s3, V3, t0, t1,
             [&](int, uint32_t s, cx<float> (&q)[NR][12]) {
 #pragma unroll
                 for (int r = 0; r < NR; r++) {
@@ -351,7 +352,7 @@ __global__ TM_MARCH_R(NR, float) void k_fcg_tm_upd(FcgArgs a, int tseg, uint32_t
                     prr[r] += spinor_norm2(rv);
                     void* xp = field_rhs<SF32>(a.x, Vs, r0 + r);
                     cx<float> pv[12], xv[12];
-                    load_spinor_cp<SF32, float, TM_CP_K2>(field_rhs<SF32>(a.p, Vs, r0 + r), Vs, s, pv);
+                    load_spinor_cp<S, float, TM_CP_K2>(field_rhs<S>(a.p, Vs, r0 + r), Vs, s, pv);
                     load_spinor_cp<SF32, float, TM_CP_K2>(xp, Vs, s, xv);
 #pragma unroll
                     for (int k = 0; k < 12; k++) xv[k] = xv[k] + al[r] * pv[k];
@@ -405,22 +406,34 @@ static void tm_upd_typed(hipStream_t st, const CgArgs& a, int nr, bool track) {
     }
 }
 
-void launch_fcg_tm_mp(hipStream_t st, const FcgArgs& a, int nr, int tseg) {
+template <class S>
+static void fcg_tm_typed(hipStream_t st, const FcgArgs& a, int nr, int tseg, bool upd) {
     const uint32_t np = march_partials(a.geo, tseg);
-    if (nr == 2)
-        hipLaunchKernelGGL(k_fcg_tm_mp<2>, dim3(np * (unsigned)(a.nrhs / 2)), dim3(256), 0, st, a, tseg, np);
-    else
-        hipLaunchKernelGGL(k_fcg_tm_mp<1>, dim3(np * (unsigned)a.nrhs), dim3(256), 0, st, a, tseg, np);
-    launch_fcg_mp_fin(st, a, np);
+    const dim3 gr(np * (unsigned)(nr == 2 ? a.nrhs / 2 : a.nrhs));
+    if (upd) {
+        if (nr == 2)
+            hipLaunchKernelGGL((k_fcg_tm_upd<2, S>), gr, dim3(256), 0, st, a, tseg, np);
+        else
+            hipLaunchKernelGGL((k_fcg_tm_upd<1, S>), gr, dim3(256), 0, st, a, tseg, np);
+        launch_fcg_upd_fin(st, a, np);
+    } else {
+        if (nr == 2)
+            hipLaunchKernelGGL((k_fcg_tm_mp<2, S>), gr, dim3(256), 0, st, a, tseg, np);
+        else
+            hipLaunchKernelGGL((k_fcg_tm_mp<1, S>), gr, dim3(256), 0, st, a, tseg, np);
+        launch_fcg_mp_fin(st, a, np);
+    }
 }
-void launch_fcg_tm_upd(hipStream_t st, const FcgArgs& a, int nr, int tseg) {
-    const uint32_t np = march_partials(a.geo, tseg);
-    if (nr == 2)
-        hipLaunchKernelGGL(k_fcg_tm_upd<2>, dim3(np * (unsigned)(a.nrhs / 2)), dim3(256), 0, st, a, tseg, np);
+static void fcg_tm(hipStream_t st, const FcgArgs& a, int nr, int tseg, bool upd) {
+    if (a.prec == P_F16)
+        fcg_tm_typed<SF16>(st, a, nr, tseg, upd);
+    else if (a.prec == P_BF16)
+        fcg_tm_typed<SBF16>(st, a, nr, tseg, upd);
     else
-        hipLaunchKernelGGL(k_fcg_tm_upd<1>, dim3(np * (unsigned)a.nrhs), dim3(256), 0, st, a, tseg, np);
-    launch_fcg_upd_fin(st, a, np);
+        fcg_tm_typed<SF32>(st, a, nr, tseg, upd);
 }
+void launch_fcg_tm_mp(hipStream_t st, const FcgArgs& a, int nr, int tseg) { fcg_tm(st, a, nr, tseg, false); }
+void launch_fcg_tm_upd(hipStream_t st, const FcgArgs& a, int nr, int tseg) { fcg_tm(st, a, nr, tseg, true); }
 
 void launch_tm_mp(hipStream_t st, const CgArgs& a, int prec, int nr) {
     switch (prec) {

@@ -63,10 +63,11 @@ struct FcgArgs {
     Geom geo;
     const void* gauge;  // FP32 native links
     double kappa, twist;
-    void *p, *t, *q, *r, *x, *z;  // FP32 native fields, nrhs each
+    void *p, *t, *q, *r, *x, *z;  // native fields, nrhs each: p and t in prec, the rest FP32
     FcgScal* scal;
     double* partials;   // [nrhs][4][nblocks]
     int nrhs;
+    int prec;           // storage of p and t (P_F32, P_F16 or P_BF16)
 };
 
 void launch_fcg_init(hipStream_t st, const FcgArgs& a, double tol2, int maxit, int fell);

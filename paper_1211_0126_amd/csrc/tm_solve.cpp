@@ -32,8 +32,10 @@ static tm_status check_solve_params(tm_ctx* ctx, const tsm_solve_params* p) {
     if (p->solver == TM_SOLVER_CG_EO && !ctx->eo_ok)
         return set_error(ctx, TM_ENOTSUP, "solve: the even-odd solver needs every lattice extent even");
     if (p->solver == TM_SOLVER_FCG_LEARNED) {
-        if (p->prec != TM_PREC_F32 || p->reliable || p->stop != TM_STOP_NORMAL)
-            return set_error(ctx, TM_ENOTSUP, "solve: flexible CG runs FP32 vectors, normal-equation stop, no reliable updates");
+        if (p->prec == TM_PREC_F64 || p->reliable || p->stop != TM_STOP_NORMAL)
+            return set_error(ctx, TM_ENOTSUP,
+                             "solve: flexible CG stores its directions in FP32/FP16/BF16, stops on the normal "
+                             "equations, has no reliable updates");
         if (!net_installed(ctx)) return set_error(ctx, TM_ESTATE, "solve: no network installed (tm_precond_set/train)");
     }
     if (!(p->tol >= 0) || !std::isfinite(p->tol)) return set_error(ctx, TM_EINVAL, "solve: bad tolerance");
@@ -144,6 +146,9 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
     hipStream_t st = ctx->stream;
     tm_status s = TM_OK;
     const size_t fb = field_bytes(g, P_F32, ws_rhs(ctx, tag, nrhs));
+    // the stencil inputs p and t in the storage precision
+    const int prec = p->prec;
+    const size_t fbs = field_bytes(g, prec, ws_rhs(ctx, tag, nrhs));
     const size_t npart = partials_per_rhs(g, ctx->hgeo, ctx->eo_ok);
     FcgArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -152,8 +157,9 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
     a.kappa = ctx->lat.kappa;
     a.twist = ctx->twist;
     a.nrhs = nrhs;
-    a.p = ws_get(ctx, tag + "_fp", fb, &s);
-    a.t = ws_get(ctx, tag + "_ft", fb, &s);
+    a.prec = prec;
+    a.p = ws_get(ctx, tag + "_fp", fbs, &s);
+    a.t = ws_get(ctx, tag + "_ft", fbs, &s);
     a.q = ws_get(ctx, tag + "_fq", fb, &s);
     a.r = ws_get(ctx, tag + "_fr", fb, &s);
     a.x = ws_get(ctx, tag + "_fx", fb, &s);
@@ -176,7 +182,7 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
     launch_fcg_dot(st, a, 1);
     launch_fcg_p(st, a);
     TM_HIP(hipGetLastError());
-    const CgBytes by = cg_bytes(g, P_F32, nrhs, false, false);
+    const CgBytes by = cg_bytes(g, prec, nrhs, false, false);
     std::vector<FcgScal> fs(nrhs);
     int done = 0;
     // the stencil steps march in time when a segment length is set for FP32
@@ -188,13 +194,13 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
         int k = 2;
         if (p->max_iter >= 0) k = std::max(1, std::min(k, p->max_iter - done));
         for (int i = 0; i < k; i++) {
-            prof_begin(ctx, TM_KC_DSLASH, prof_tag(P_F32, tseg > 0 ? nr : 1, TM_SOLVER_FCG_LEARNED, tseg));
+            prof_begin(ctx, TM_KC_DSLASH, prof_tag(prec, tseg > 0 ? nr : 1, TM_SOLVER_FCG_LEARNED, tseg));
             if (tseg > 0)
                 launch_fcg_tm_mp(st, a, nr, tseg);
             else
                 launch_fcg_mp(st, a);
             prof_end(ctx, TM_KC_DSLASH, by.k1);
-            prof_begin(ctx, TM_KC_DSLASH_UPD, prof_tag(P_F32, tseg > 0 ? nr : 1, TM_SOLVER_FCG_LEARNED, tseg));
+            prof_begin(ctx, TM_KC_DSLASH_UPD, prof_tag(prec, tseg > 0 ? nr : 1, TM_SOLVER_FCG_LEARNED, tseg));
             if (tseg > 0)
                 launch_fcg_tm_upd(st, a, nr, tseg);
             else
@@ -202,7 +208,7 @@ static tm_status solve_block_fcg(tm_ctx* ctx, const tsm_solve_params* p, uint64_
             prof_end(ctx, TM_KC_DSLASH_UPD, by.k2);
             if ((s = net_precondition(ctx, nrhs, a.r, a.z, a.scal, ws_rhs(ctx, tag, nrhs))) != TM_OK) return s;
             launch_fcg_dot(st, a, 0);
-            prof_begin(ctx, TM_KC_BLAS, prof_tag(P_F32, 1, TM_SOLVER_FCG_LEARNED));
+            prof_begin(ctx, TM_KC_BLAS, prof_tag(prec, 1, TM_SOLVER_FCG_LEARNED));
             launch_fcg_p(st, a);
             prof_end(ctx, TM_KC_BLAS, by.k3);
         }
@@ -1524,7 +1530,7 @@ size_t tm_workspace_bytes(const tm_lattice* lat, const tm_caps* caps) {
             for (int prec = TM_PREC_F64; prec <= TM_PREC_BF16; prec++)
                 for (int rel = 0; rel <= 1; rel++)
                     for (int stop : {TM_STOP_NORMAL, TM_STOP_TRUE}) {
-                        if ((rel && prec != TM_PREC_F32) || (solver == TM_SOLVER_FCG_LEARNED && (prec != TM_PREC_F32 || rel)) ||
+                        if ((rel && prec != TM_PREC_F32) || (solver == TM_SOLVER_FCG_LEARNED && (prec == TM_PREC_F64 || rel)) ||
                             (solver == TM_SOLVER_CG_EO && !eo_ok))
                             continue;
                         tsm_solve_params p;

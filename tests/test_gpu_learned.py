@@ -211,6 +211,40 @@ def test_fcg_marching_stencils_match_lane_per_site(orc, U, nr, tseg):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("nr,tseg", [(1, 0), (2, 4)])
+def test_fcg_half_storage_directions(orc, U, prec, nr, tseg):
+    """Flexible CG with the directions p and M p stored as FP16 / BF16 (lane
+    per site and marching stencils): at the LP tolerance it converges within
+    an iteration of the FP64 oracle's flexible CG, with an FP64 true residual
+    close to the oracle's; after k = 2 fixed iterations the iterate is the
+    oracle's to the storage rounding."""
+    import paper_1211_0126_amd as tq
+    ctx = _ctx(DIMS, U)
+    # the third-order Neumann network (the starting point of training)
+    tq.tm_precond_train(ctx, seed=0, n_sources=0, n_pairs=0, epochs=0, batch=1, init_scale=0.0, init_mode=1)
+    _, W = tq.tm_precond_get(ctx)
+    tq.tm_set_lane_rhs(ctx, prec, nr)
+    tq.tm_set_march(ctx, prec, tseg)
+    ids = [0, 1, 2, 3]
+    p = tq.solve_params(prec=prec, tol=1e-2, max_iter=-1, solver=tq.SOLVER_FCG_LEARNED, rhs_block=4)
+    _, st, _ = tq.tsm_solve_batch(ctx, p, 8, ids)
+    pk = tq.solve_params(prec=prec, tol=0.0, max_iter=2, solver=tq.SOLVER_FCG_LEARNED, rhs_block=4)
+    solk, stk, _ = tq.tsm_solve_batch(ctx, pk, 8, ids)
+    solk = solk.cpu().numpy()
+    ctx.close()
+    for i, j in enumerate(ids):
+        eta = orc.noise_z4(DIMS, 8, j)
+        x, so = orc.fcg(DIMS, -1, KAPPA, MU, U, WIDTHS, W, eta, 1e-2)
+        print("prec %d source %d: iters %d (oracle %d), true residual %.4g (oracle %.4g), fell back %d"
+              % (prec, j, st[i]["iters"], so["iters"], st[i]["resid_true"], so["resid_true"], st[i]["fell_back"]))
+        assert st[i]["converged"] and not st[i]["fell_back"] and abs(st[i]["iters"] - so["iters"]) <= 1, (st[i], so)
+        assert abs(st[i]["resid_true"] - so["resid_true"]) < 0.1 * so["resid_true"] + 2e-3
+        xk, _ = orc.fcg(DIMS, -1, KAPPA, MU, U, WIDTHS, W, eta, 0.0, 2)
+        assert stk[i]["iters"] == 2
+        assert _rel(solk[i], xk) < (3e-2 if prec == 2 else 6e-2), _rel(solk[i], xk)
+
+
 def test_training_reduces_loss_and_solves(orc):
     """Training on harvested pairs lowers the loss; the trained network
     preconditions flexible CG to the same solution as plain CG."""
