@@ -383,45 +383,183 @@ void launch_contract(hipStream_t st, const ContractArgs& a0, int xprec) {
 }
 
 // ---------------------------------------------------------------------------
-// Projection onto all L^3 momenta (the paper's FFT step): the site matrices
-// S_{ba}(x) = sum_c s_{bc}(x) conj(eta_{ac}(x)) of the standard loop are
-// written out, transformed along x, y and z by direct DFTs of length L
-// (phases from a table exp(-2 pi i m / L)), then traced with each Gamma_n.
-// Layout of the site and spectrum buffers: [r][t][z][y][x][16], entry
-// 4 b + a.
+// Projection onto all L^3 momenta (the paper's FFT step) in three passes.
+// The Gamma traces are linear, so they are taken at each site, before the
+// Fourier transform: T_n(x) = sum_a Gamma_n[a][col] S_{col a}(x) with the
+// site matrix S_{ba} = sum_c s_{bc} conj(eta_{ac}) (eta regenerated from the
+// hash), and the 16 T_n are transformed along x, y and z by DFTs of length L
+// (phases exp(-2 pi i m / L) from a table; radix-2 passes in LDS for powers
+// of two, direct sums otherwise):
+//   X: traces of a few x lines and their x transform, written as
+//      [r][t][z][y][kx][16];
+//   Y: the y transform in place of that layout (k_dft_axis);
+//   Z: the z transform of T consecutive time slices of one (kx, ky) column,
+//      written straight into loops[slot][n][m][t], m = kx + Lx (ky + Ly kz).
+// HBM traffic per source: the solution once, three writes and two reads of
+// 16 complex per site.
 // ---------------------------------------------------------------------------
-template <class S>
-__global__ __launch_bounds__(256) void k_site_matrix(ContractArgs a, double2* out) {
-    const Geom& g = a.geo;
-    const long tid = (long)blockIdx.x * 256 + threadIdx.x;
-    const int r = blockIdx.y;
-    if (tid >= 2 * g.V) return;
-    const int h = tid >= g.V ? 1 : 0;
-    const uint32_t s = (uint32_t)(tid - h * g.V);
-    cx<double> p[6];
-    load_half_spinor<S>(field_rhs<S>(a.sol, g.Vs, r), g.Vs, s, h, p);
-    const uint64_t bits = noise_bits(a.seed_mixed, a.ids[r], (uint64_t)g.V, (uint64_t)s);
-    double2* o = out + ((size_t)r * g.V + s) * 16 + 8 * h;
-#pragma unroll
-    for (int b = 0; b < 2; b++)
-#pragma unroll
-        for (int al = 0; al < 4; al++) {
-            cx<double> v = {0.0, 0.0};
-#pragma unroll
-            for (int c = 0; c < 3; c++)
-                v = v + z4_conj_times((uint32_t)(bits >> (2 * (3 * al + c))) & 3u, p[3 * b + c]);
-            o[4 * b + al] = make_double2(v.re, v.im);
+
+// LDS tiles [L][W] of W lines (W a power of two >= 16): entry (j, w) at
+// j * W + lds_pos(w), the low four bits of w swizzled with the next four so
+// that lanes walking either of them hit distinct banks
+__device__ __forceinline__ int lds_pos(int w) { return (w & ~15) | ((w ^ (w >> 4)) & 15); }
+
+__device__ __forceinline__ int ilog2(int L) {
+    int lg = 0;
+    while ((1 << lg) < L) lg++;
+    return lg;
+}
+
+// In-place radix-2 DFT (decimation in time) along the slow index of a tile
+// [L][W] (L and W powers of two) whose rows were stored bit-reversed; ph[m] =
+// exp(-2 pi i m / L) (in LDS).
+__device__ void lds_dft_pow2(double2* tile, int W, int L, const double2* ph) {
+    const int lgW = ilog2(W), lgL = ilog2(L);
+    for (int lgl = 1; lgl <= lgL; lgl++) {
+        const int half = 1 << (lgl - 1);
+        for (int b = threadIdx.x; b < (L >> 1) << lgW; b += blockDim.x) {
+            const int c = b & (W - 1), qb = b >> lgW;
+            const int j = qb & (half - 1);
+            const int i0 = ((qb >> (lgl - 1)) << lgl) + j, i1 = i0 + half;
+            const double2 w = ph[j << (lgL - lgl)];
+            double2* pu = tile + i0 * W + lds_pos(c);
+            double2* pv = tile + i1 * W + lds_pos(c);
+            const double2 u = *pu, v = *pv;
+            const cx<double> wv = cx<double>{w.x, w.y} * cx<double>{v.x, v.y};
+            *pu = make_double2(u.x + wv.re, u.y + wv.im);
+            *pv = make_double2(u.x - wv.re, u.y - wv.im);
         }
+        __syncthreads();
+    }
+}
+
+// output k of line c: the transformed tile entry (power of two), else the
+// direct sum over the untransformed tile
+__device__ __forceinline__ double2 lds_dft_out(const double2* tile, int W, int L, bool pow2, const double2* ph,
+                                               int k, int c) {
+    const int lc = lds_pos(c);
+    if (pow2) return tile[k * W + lc];
+    cx<double> acc = {0.0, 0.0};
+    int m = 0;
+    for (int j = 0; j < L; j++) {
+        const double2 v = tile[j * W + lc];
+        const double2 w = ph[m];
+        acc = acc + cx<double>{w.x, w.y} * cx<double>{v.x, v.y};
+        m += k;
+        if (m >= L) m -= L;
+    }
+    return make_double2(acc.re, acc.im);
+}
+
+// row of element j in a tile of L rows: bit-reversed for the radix-2 passes
+__device__ __forceinline__ int dft_row(int j, bool pow2, int lg) {
+    return pow2 && lg > 0 ? (int)(__brev((unsigned)j) >> (32 - lg)) : j;
+}
+
+// Gamma_n = g1^b0 g2^b1 g3^b2 g4^b3 of the Euclidean chiral basis as the
+// column and phase i^k of each row's one nonzero, built at compile time from
+// the four gammas (each a phase-signed permutation, so a product's row a has
+// column colB(colA(a)) and phase phA(a) + phB(colA(a)))
+struct GammaTable {
+    int col[16][4];
+    int ph[16][4];
+};
+constexpr GammaTable gamma_table() {
+    // gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = [[0, 1], [1, 0]]
+    constexpr int gc[4][4] = {{3, 2, 1, 0}, {3, 2, 1, 0}, {2, 3, 0, 1}, {2, 3, 0, 1}};
+    constexpr int gp[4][4] = {{3, 3, 1, 1}, {2, 0, 0, 2}, {3, 1, 1, 3}, {0, 0, 0, 0}};
+    GammaTable t{};
+    for (int n = 0; n < 16; n++) {
+        for (int a = 0; a < 4; a++) {
+            t.col[n][a] = a;
+            t.ph[n][a] = 0;
+        }
+        for (int mu = 0; mu < 4; mu++)
+            if ((n >> mu) & 1)
+                for (int a = 0; a < 4; a++) {
+                    const int k = t.col[n][a];
+                    t.col[n][a] = gc[mu][k];
+                    t.ph[n][a] = (t.ph[n][a] + gp[mu][k]) & 3;
+                }
+    }
+    return t;
+}
+
+// i^k p: a permutation and signs
+__device__ __forceinline__ cx<double> z4_times(int k, cx<double> p) {
+    const double re = (k & 1) ? -p.im : p.re;
+    const double im = (k & 1) ? p.re : p.im;
+    return (k & 2) ? cx<double>{-re, -im} : cx<double>{re, im};
+}
+
+// X pass: block (r, t, z, y0 .. y0 + NL - 1); its sites' 16 Gamma traces
+// into the tile [x][NL * 16] (line 16 l + n), the x transform, rows written
+// line by line
+template <class S>
+__global__ __launch_bounds__(256) void k_allmom_x(ContractArgs a, double2* out, const double2* tw, int NL) {
+    extern __shared__ double2 lds[];
+    const Geom& g = a.geo;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
+    const int W = 16 * NL;
+    double2* tile = lds;
+    double2* ph = lds + Lx * W;
+    for (int i = threadIdx.x; i < Lx; i += blockDim.x) ph[i] = tw[i];
+    const int r = blockIdx.y;
+    const int nyb = Ly / NL;
+    const long plane = (long)blockIdx.x / nyb;  // t * Lz + z
+    const int y0 = (int)(blockIdx.x % nyb) * NL;
+    const bool pow2 = (Lx & (Lx - 1)) == 0;
+    const int lg = ilog2(Lx);
+    const void* sol = field_rhs<S>(a.sol, g.Vs, r);
+    const uint64_t id = a.ids[r];
+    for (int i = threadIdx.x; i < Lx * NL; i += blockDim.x) {
+        const int x = pow2 ? (i & (Lx - 1)) : i % Lx, l = pow2 ? (i >> lg) : i / Lx;
+        const uint32_t s = (uint32_t)(x + (long)Lx * (y0 + l + (long)Ly * plane));
+        cx<double> p[12];
+        load_half_spinor<S>(sol, g.Vs, s, 0, p);
+        load_half_spinor<S>(sol, g.Vs, s, 1, p + 6);
+        const uint64_t bits = noise_bits(a.seed_mixed, id, (uint64_t)g.V, (uint64_t)s);
+        cx<double> Sm[16];
+#pragma unroll
+        for (int b = 0; b < 4; b++)
+#pragma unroll
+            for (int al = 0; al < 4; al++) {
+                cx<double> v = {0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+                    v = v + z4_conj_times((uint32_t)(bits >> (2 * (3 * al + c))) & 3u, p[3 * b + c]);
+                Sm[4 * b + al] = v;
+            }
+        // the basis is fixed at compile time: each trace is a sum of four
+        // entries of S with signs and swaps
+        constexpr GammaTable G = gamma_table();
+        double2* o = tile + dft_row(x, pow2, lg) * W;
+#pragma unroll
+        for (int n = 0; n < 16; n++) {
+            cx<double> tr = {0.0, 0.0};
+#pragma unroll
+            for (int al = 0; al < 4; al++) tr = tr + z4_times(G.ph[n][al], Sm[4 * G.col[n][al] + al]);
+            o[lds_pos(16 * l + n)] = make_double2(tr.re, tr.im);
+        }
+    }
+    __syncthreads();
+    if (pow2) lds_dft_pow2(tile, W, Lx, ph);
+    double2* ob = out + (((size_t)r * g.L[3] * Lz + plane) * Ly + y0) * Lx * 16;
+    for (int o = threadIdx.x; o < Lx * W; o += blockDim.x) {
+        const int n = o & 15, rest = o >> 4;
+        const int kx = pow2 ? (rest & (Lx - 1)) : rest % Lx, l = pow2 ? (rest >> lg) : rest / Lx;
+        ob[((size_t)l * Lx + kx) * 16 + n] = lds_dft_out(tile, W, Lx, pow2, ph, kx, 16 * l + n);
+    }
 }
 
 // out[.., k, ..] = sum_j in[.., j, ..] tw[(k j) mod L] along one axis of
 // length L <= kDftMaxL whose elements are `stride` double2 apart (stride a
 // multiple of 16).  A block takes one line group of 16 consecutive inner
-// elements: it stages the L x 16 tile and the phases in LDS (each element
-// read once from memory); power-of-two lengths are transformed in place by
-// radix-2 passes, other lengths by direct sums, each lane forming outputs
-// (k, c) from LDS.
-constexpr int kDftMaxL = 128;  // 34 KB of LDS at the largest L
+// elements: it stages the L x 16 tile in LDS (each element read once from
+// memory); power-of-two lengths are transformed in place by radix-2 passes,
+// other lengths by direct sums, each lane forming outputs (k, c) from LDS.
+// in may equal out (each block reads its lines before writing them).
+constexpr int kDftMaxL = 128;  // 32 KB of LDS at the largest L
 __global__ __launch_bounds__(256) void k_dft_axis(const double2* in, double2* out, int L, long stride,
                                                   const double2* tw) {
     extern __shared__ double2 lds[];  // L * 16 tile entries, then L phases
@@ -430,102 +568,87 @@ __global__ __launch_bounds__(256) void k_dft_axis(const double2* in, double2* ou
     const long nchunk = stride / 16;
     const long outer = (long)blockIdx.x / nchunk;
     const long base = outer * L * stride + ((long)blockIdx.x % nchunk) * 16;
-    const int n = L * 16;
     const bool pow2 = (L & (L - 1)) == 0;
-    int lg = 0;
-    while ((1 << lg) < L) lg++;
-    for (int idx = threadIdx.x; idx < n; idx += 256) {
+    const int lg = ilog2(L);
+    for (int idx = threadIdx.x; idx < L * 16; idx += 256) {
         const int jj = idx >> 4;
-        // power-of-two lengths: stored in bit-reversed order for the radix-2 passes
-        const int at = pow2 ? (int)(__brev((unsigned)jj) >> (32 - lg)) : jj;
-        tile[(lg == 0 ? jj : at) * 16 + (idx & 15)] = in[base + (long)jj * stride + (idx & 15)];
+        tile[dft_row(jj, pow2, lg) * 16 + (idx & 15)] = in[base + (long)jj * stride + (idx & 15)];
     }
     for (int idx = threadIdx.x; idx < L; idx += 256) ph[idx] = tw[idx];
     __syncthreads();
-    if (pow2) {
-        // iterative radix-2 decimation in time: log2 L passes of L/2 x 16
-        // butterflies, twiddle exp(-2 pi i pos / len) = ph[pos * L / len]
-        for (int len = 2; len <= L; len <<= 1) {
-            const int half = len >> 1, step = L / len;
-            for (int b = threadIdx.x; b < (L >> 1) * 16; b += 256) {
-                const int c = b & 15, qb = b >> 4;
-                const int i0 = (qb / half) * len + qb % half, i1 = i0 + half;
-                const double2 w = ph[(qb % half) * step];
-                const double2 u = tile[i0 * 16 + c], v = tile[i1 * 16 + c];
-                const cx<double> wv = cx<double>{w.x, w.y} * cx<double>{v.x, v.y};
-                tile[i0 * 16 + c] = make_double2(u.x + wv.re, u.y + wv.im);
-                tile[i1 * 16 + c] = make_double2(u.x - wv.re, u.y - wv.im);
-            }
-            __syncthreads();
-        }
-        for (int o = threadIdx.x; o < n; o += 256) out[base + (long)(o >> 4) * stride + (o & 15)] = tile[o];
-        return;
+    if (pow2) lds_dft_pow2(tile, 16, L, ph);
+    for (int o = threadIdx.x; o < L * 16; o += 256)
+        out[base + (long)(o >> 4) * stride + (o & 15)] = lds_dft_out(tile, 16, L, pow2, ph, o >> 4, o & 15);
+}
+
+// Z pass: block (r, channel half, t0 .. t0 + T - 1, ky, kx) of the
+// [r][t][z][ky][kx][16] spectrum; the z transform of its T * 8 lines (line
+// 8 tt + c), written with t fastest into loops[slot][n][m][t] (runs of T
+// consecutive t)
+__global__ __launch_bounds__(256) void k_allmom_z(ContractArgs a, const double2* in, const double2* tw, int T) {
+    extern __shared__ double2 lds[];
+    const Geom& g = a.geo;
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+    const long V3 = (long)Lx * Ly * Lz;
+    const int W = std::max(16, 8 * T);  // lines, padded to the swizzle's group of 16
+    double2* tile = lds;
+    double2* ph = lds + Lz * W;
+    const int r = blockIdx.y;
+    const long XY = (long)Lx * Ly;
+    const long col = blockIdx.x % XY;  // kx + Lx ky
+    const int t0 = (int)((blockIdx.x / XY) % (Lt / T)) * T;
+    const int c0 = (int)(blockIdx.x / (XY * (Lt / T))) * 8;
+    const bool pow2 = (Lz & (Lz - 1)) == 0;
+    const int lg = ilog2(Lz), lgT = ilog2(T);
+    for (int i = threadIdx.x; i < Lz; i += blockDim.x) ph[i] = tw[i];
+    const double2* ib = in + ((size_t)r * Lt * Lz * XY + col) * 16 + c0;
+    for (int i = threadIdx.x; i < Lz * 8 * T; i += blockDim.x) {
+        const int c = i & 7, rest = i >> 3;
+        const int tt = rest & (T - 1), z = rest >> lgT;
+        tile[dft_row(z, pow2, lg) * W + lds_pos(8 * tt + c)] = ib[(((size_t)(t0 + tt) * Lz + z) * XY) * 16 + c];
     }
-    for (int o = threadIdx.x; o < n; o += 256) {
-        const int k = o >> 4, c = o & 15;
-        cx<double> acc = {0.0, 0.0};
-        int m = 0;
-        for (int jj = 0; jj < L; jj++) {
-            const double2 v = tile[jj * 16 + c];
-            const double2 w = ph[m];
-            acc = acc + cx<double>{w.x, w.y} * cx<double>{v.x, v.y};
-            m += k;
-            if (m >= L) m -= L;
-        }
-        out[base + (long)k * stride + c] = make_double2(acc.re, acc.im);
+    __syncthreads();
+    if (pow2) lds_dft_pow2(tile, W, Lz, ph);
+    double2* ob = a.out + (size_t)a.out_slot[r] * a.out_stride + col * Lt + t0;
+    for (int o = threadIdx.x; o < Lz * 8 * T; o += blockDim.x) {
+        const int tt = o & (T - 1), rest = o >> lgT;
+        const int c = rest & 7, kz = rest >> 3;
+        ob[(size_t)(c0 + c) * V3 * Lt + (size_t)kz * XY * Lt + tt] =
+            lds_dft_out(tile, W, Lz, pow2, ph, kz, 8 * tt + c);
     }
 }
 
-// loops[r][n][m][t] = sum_a Gamma_n[a][col] S~_{col a}(t, m), m = kx + Lx (ky + Ly kz):
-// one lane per (m, t) with t fastest reads its 16 spectrum entries (one
-// contiguous 256-byte block) and writes all 16 Gamma traces, so each write
-// instruction of a wave covers consecutive t
-__global__ __launch_bounds__(256) void k_trace_all(ContractArgs a, const double2* spec, double2* out) {
-    const Geom& g = a.geo;
-    const long V3 = (long)g.L[0] * g.L[1] * g.L[2];
-    const int Lt = g.L[3];
-    const long i = (long)blockIdx.x * 256 + threadIdx.x;
-    const int r = blockIdx.y;
-    if (i >= V3 * Lt) return;
-    const int t = (int)(i % Lt);
-    const long m = i / Lt;
-    const double2* e = spec + (((size_t)r * Lt + t) * V3 + m) * 16;
-    double2* o = out + (size_t)a.out_slot[r] * a.out_stride + m * Lt + t;
-#pragma unroll
-    for (int gn = 0; gn < 16; gn++) {
-        cx<double> tr = {0.0, 0.0};
-#pragma unroll
-        for (int al = 0; al < 4; al++) {
-            // the lane's 256-byte block stays in the caches across the 16 traces
-            const double2 v = e[a.gam_col[gn * 4 + al] * 4 + al];
-            tr = tr + z4_value<double>((uint32_t)a.gam_ph[gn * 4 + al]) * cx<double>{v.x, v.y};
-        }
-        o[(size_t)gn * V3 * Lt] = make_double2(tr.re, tr.im);
-    }
+// largest power of two <= cap dividing n with a tile of L rows x w k lines
+// within 32 KB of LDS (several blocks per CU)
+static int pick_lines(int n, int L, int w, int cap) {
+    int k = 1;
+    while (k * 2 <= cap && n % (k * 2) == 0 && (size_t)L * w * (k * 2) * sizeof(double2) <= (32u << 10)) k *= 2;
+    return k;
 }
 
 void launch_contract_all_momenta(hipStream_t st, const ContractArgs& a, int xprec, double2* buf0, double2* buf1,
                                  const double2* tw) {
     const Geom& g = a.geo;
-    const long nsite = 2L * g.V;
-    dim3 gs((unsigned)((nsite + 255) / 256), (unsigned)a.nrhs);
+    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
+    const int NL = pick_lines(Ly, Lx, 16, 8);
+    const unsigned lds_x = (unsigned)(sizeof(double2) * (Lx * 16 * NL + Lx));
+    const dim3 gx((unsigned)((long)Lt * Lz * (Ly / NL)), (unsigned)a.nrhs);
+    // one thread per site of the block's lines (at least a wave, at most 256)
+    const unsigned bx = (unsigned)std::min(256, std::max(64, (Lx * NL + 63) / 64 * 64));
     if (xprec == P_F64)
-        hipLaunchKernelGGL(k_site_matrix<SF64>, gs, dim3(256), 0, st, a, buf0);
+        hipLaunchKernelGGL(k_allmom_x<SF64>, gx, dim3(bx), lds_x, st, a, buf0, tw, NL);
     else
-        hipLaunchKernelGGL(k_site_matrix<SF32>, gs, dim3(256), 0, st, a, buf0);
-    const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2];
-    // one block per line group of 16 inner elements: nrhs * V / L blocks per
-    // axis; phase tables back to back: x, y, z
-    auto blocks = [&](int L) { return dim3((unsigned)((long)a.nrhs * g.V / L)); };
-    auto lds = [](int L) { return (unsigned)(sizeof(double2) * 17 * L); };
-    hipLaunchKernelGGL(k_dft_axis, blocks(Lx), dim3(256), lds(Lx), st, (const double2*)buf0, buf1, Lx, 16L, tw);
-    hipLaunchKernelGGL(k_dft_axis, blocks(Ly), dim3(256), lds(Ly), st, (const double2*)buf1, buf0, Ly, 16L * Lx,
-                       tw + Lx);
-    hipLaunchKernelGGL(k_dft_axis, blocks(Lz), dim3(256), lds(Lz), st, (const double2*)buf0, buf1, Lz,
-                       16L * Lx * Ly, tw + Lx + Ly);
-    const long n_el = (long)Lx * Ly * Lz * g.L[3];
-    hipLaunchKernelGGL(k_trace_all, dim3((unsigned)((n_el + 255) / 256), (unsigned)a.nrhs), dim3(256), 0, st, a,
-                       (const double2*)buf1, a.out);
+        hipLaunchKernelGGL(k_allmom_x<SF32>, gx, dim3(bx), lds_x, st, a, buf0, tw, NL);
+    // y transform in place: one block per (r, t, z, kx) line group
+    hipLaunchKernelGGL(k_dft_axis, dim3((unsigned)((long)a.nrhs * g.V / Ly)), dim3(256),
+                       (unsigned)(sizeof(double2) * 17 * Ly), st, (const double2*)buf0, buf0, Ly, 16L * Lx, tw + Lx);
+    // half the channels per block, T = 8 consecutive time slices: 128-byte
+    // runs of the output
+    const int T = pick_lines(Lt, Lz, 8, 8);
+    const unsigned lds_z = (unsigned)(sizeof(double2) * (Lz * std::max(16, 8 * T) + Lz));
+    hipLaunchKernelGGL(k_allmom_z, dim3((unsigned)((long)Lx * Ly * (Lt / T) * 2), (unsigned)a.nrhs), dim3(256),
+                       lds_z, st, a, (const double2*)buf0, tw + Lx + Ly, T);
+    (void)buf1;
 }
 
 // TSM combination of Eq. 4 from the per-source loops ps[j][slot][k]

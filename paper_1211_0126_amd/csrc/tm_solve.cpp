@@ -976,8 +976,8 @@ static void contract_block(tm_ctx* ctx, Contractor* c, const uint64_t* ids_dev, 
 }
 
 // Standard loops of given solutions at all Lx*Ly*Lz momenta (n_mom =
-// TM_ALL_MOMENTA): site matrices, three DFT stages, Gamma traces; blocks of
-// up to four sources (each block holds two buffers of V * 16 complex per
+// TM_ALL_MOMENTA): Gamma traces at each site and three DFT passes; blocks of
+// up to four sources (each block holds one buffer of V * 16 complex per
 // source).
 static tm_status contract_all_momenta(tm_ctx* ctx, uint64_t seed, int32_t nsrc, const uint64_t* ids_host,
                                       const double* sol_dev, double* loops_host) {
@@ -998,7 +998,6 @@ static tm_status contract_all_momenta(tm_ctx* ctx, uint64_t seed, int32_t nsrc, 
         }
     double* twd = (double*)ws_get(ctx, "fft_tw", sizeof(double) * tw.size(), &s);
     double2* buf0 = (double2*)ws_get(ctx, "fft_buf0", sizeof(double2) * 16 * (size_t)g.V * blk, &s);
-    double2* buf1 = (double2*)ws_get(ctx, "fft_buf1", sizeof(double2) * 16 * (size_t)g.V * blk, &s);
     uint64_t* ids_dev = (uint64_t*)ws_get(ctx, "contract_ids", sizeof(uint64_t) * nsrc, &s);
     int* slots = (int*)ws_get(ctx, "contract_slots", sizeof(int) * nsrc, &s);
     void* nat = ws_get(ctx, "contract_nat", field_bytes(g, P_F64, blk), &s);
@@ -1026,10 +1025,11 @@ static tm_status contract_all_momenta(tm_ctx* ctx, uint64_t seed, int32_t nsrc, 
         a.nrhs = nb;
         a.out_slot = slots + j0;
         prof_begin(ctx, TM_KC_CONTRACT);
-        launch_contract_all_momenta(st, a, P_F64, buf0, buf1, (const double2*)twd);
-        // site matrices written once, three DFT passes read and write
-        // V * 16 complex each, the traces read them once more
-        prof_end(ctx, TM_KC_CONTRACT, (double)g.V * nb * (24.0 * 8 + 16 * 16 * 8.0));
+        launch_contract_all_momenta(st, a, P_F64, buf0, nullptr, (const double2*)twd);
+        // the three passes: the solution read once (24 FP64), 16 complex per
+        // site written by the x pass, read and written by the y pass, read
+        // by the z pass, and the loops written
+        prof_end(ctx, TM_KC_CONTRACT, (double)g.V * nb * (24.0 * 8 + 5 * 16 * 16.0));
         TM_HIP(hipGetLastError());
     }
     TM_HIP(hipMemcpyAsync(loops_host, out, sizeof(double) * 2 * nl * nsrc, hipMemcpyDeviceToHost, st));
@@ -1134,7 +1134,7 @@ static size_t ws_bound(const tm_lattice* lat, const Geom& g, const Geom& hg, boo
     if (all_mom > 0) {
         const int b = std::min(all_mom, 4);
         best = std::max(best, align256(sizeof(double) * 2 * (g.L[0] + g.L[1] + g.L[2])) +
-                                  2 * align256(sizeof(double) * 2 * 16 * (size_t)g.V * b) +
+                                  align256(sizeof(double) * 2 * 16 * (size_t)g.V * b) +
                                   align256(sizeof(uint64_t) * all_mom) + align256(sizeof(int) * all_mom) +
                                   align256(field_bytes(g, P_F64, b)) +
                                   align256(sizeof(double) * 2 * 16 * (size_t)g.V * all_mom));

@@ -20,7 +20,8 @@ def all_momenta(dims):
 
 
 @pytest.mark.parametrize("dims,kind", [((4, 4, 4, 4), "cg"), ((6, 4, 8, 4), "rand"), ((2, 6, 4, 6), "rand"),
-                                       ((32, 4, 2, 2), "rand"), ((16, 16, 2, 2), "rand"), ((2, 2, 32, 2), "rand")])
+                                       ((32, 4, 2, 2), "rand"), ((16, 16, 2, 2), "rand"), ((2, 2, 32, 2), "rand"),
+                                       ((4, 2, 2, 16), "rand"), ((6, 4, 2, 12), "rand")])
 def test_all_momenta_match_oracle(orc, dims, kind):
     """Every momentum against direct phase sums; extents 16 and 32 run the
     radix-2 passes with four and five butterfly stages on each axis."""
