@@ -66,11 +66,13 @@ def parse():
                     help="training pairs of the learned preconditioner (default: 2000 for the learned-preconditioner "
                          "workload c4, 256 otherwise)")
     ap.add_argument("--train-sources", type=int, default=None,
-                    help="training sources the pairs are harvested from (default: 96 for c4, 16 otherwise)")
+                    help="training sources the pairs are harvested from (default: 1000 for c4, 16 otherwise)")
+    ap.add_argument("--train-loss", default=None, choices=["error", "residual", "both"],
+                    help="training loss: |N r - e|^2 / |e|^2 (error), |M N r - r|^2 / |r|^2 (residual), or one "
+                         "trained leg with each (default: both for c4, error otherwise)")
     ap.add_argument("--train-epochs", type=int, default=None, help="(default: 3 for c4, 6 otherwise)")
-    ap.add_argument("--min-rel-err", type=float, default=None,
-                    help="pairs are cut from the iterates whose relative error exceeds this (default: 0.05 for c4, "
-                         "0.3 otherwise)")
+    ap.add_argument("--min-rel-err", type=float, default=0.3,
+                    help="pairs are cut from the iterates whose relative error exceeds this")
     ap.add_argument("--fcg-prec", default="f16", choices=list(PREC_NAMES),
                     help="storage of the flexible CG's directions in the learned leg")
     ap.add_argument("--fcg-block", type=int, default=16, help="sources per flexible-CG block in the learned leg")
@@ -183,11 +185,11 @@ def main():
     if args.train_pairs is None:
         args.train_pairs = 2000 if c4 else 256
     if args.train_sources is None:
-        args.train_sources = 96 if c4 else 16
+        args.train_sources = 1000 if c4 else 16
+    if args.train_loss is None:
+        args.train_loss = "both" if c4 else "error"
     if args.train_epochs is None:
         args.train_epochs = 3 if c4 else 6
-    if args.min_rel_err is None:
-        args.min_rel_err = 0.05 if c4 else 0.3
     args.learned_tsm = args.learned_tsm or (c4 and not args.no_learned)
     if args.gpus != 1:
         print("bench.py runs on one GPU only (--gpus 1): the estimator shards by source, so N GPUs would each run "
@@ -506,7 +508,7 @@ def compare(args, tq, torch, ctx, wl, n_hp, lp_prec):
     (and optionally learned flexible CG) at equal median true residual."""
     ns = args.compare_sources
     ids = list(range(n_hp, n_hp + ns))
-    cal_ids = ids[:16]
+    cal_ids = ids
     ref_p = tq.solve_params(prec=tq.PREC_F32, tol=wl.lp_tol, max_iter=-1, rhs_block=1, true_resid=1)
     tq.tsm_solve_batch(ctx, ref_p, wl.noise_seed, ids[:2], want_solutions=False)  # warm
     t_ref, st_ref = timed_solve(tq, torch, ctx, ref_p, wl.noise_seed, ids)
@@ -557,15 +559,21 @@ def compare(args, tq, torch, ctx, wl, n_hp, lp_prec):
         # trained from there on (residual, error) pairs from the early
         # iterates of FP64 solves of training sources disjoint from the
         # estimator's
-        tr = tq.tm_precond_train(ctx, seed=0x5EED0000 + wl.noise_seed, n_sources=args.train_sources,
-                                 n_pairs=args.train_pairs, epochs=args.train_epochs, batch=8, lr=1e-4,
-                                 hp_tol=wl.hp_tol, min_rel_err=args.min_rel_err, init_seed=7, init_scale=0.0,
-                                 init_mode=1, loss_mode=0)
-        log("trained: %s" % tr)
-        leg("learned_fcg", {"train": dict(tr, pairs_requested=args.train_pairs, sources=args.train_sources,
-                                          epochs=args.train_epochs, min_rel_err=args.min_rel_err)})
-        res["learned_fcg"]["speedup_vs_untrained"] = round(
-            res["learned_fcg"]["sources_per_s"] / res["fcg_neumann_untrained"]["sources_per_s"], 3)
+        losses = ["error", "residual"] if args.train_loss == "both" else [args.train_loss]
+        for i, loss in enumerate(losses):
+            if i > 0:  # each training starts from the Neumann network
+                tq.tm_precond_train(ctx, seed=0, n_sources=0, n_pairs=0, epochs=0, batch=1, init_seed=7,
+                                    init_scale=0.0, init_mode=1)
+            tr = tq.tm_precond_train(ctx, seed=0x5EED0000 + wl.noise_seed, n_sources=args.train_sources,
+                                     n_pairs=args.train_pairs, epochs=args.train_epochs, batch=8, lr=1e-4,
+                                     hp_tol=wl.hp_tol, min_rel_err=args.min_rel_err, init_seed=7, init_scale=0.0,
+                                     init_mode=1, loss_mode=1 if loss == "residual" else 0)
+            log("trained (%s loss): %s" % (loss, tr))
+            name = "learned_fcg" if i == 0 else "learned_fcg_" + loss + "_loss"
+            leg(name, {"train": dict(tr, pairs_requested=args.train_pairs, sources=args.train_sources,
+                                     epochs=args.train_epochs, min_rel_err=args.min_rel_err, loss=loss)})
+            res[name]["speedup_vs_untrained"] = round(
+                res[name]["sources_per_s"] / res["fcg_neumann_untrained"]["sources_per_s"], 3)
     return res
 
 
