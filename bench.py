@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--lp-block", type=int, default=0,
                     help="LP sources per solver block (default: autotune over 8, 16, 32)")
     ap.add_argument("--hp-block", type=int, default=0,
-                    help="HP sources per solver block (default: autotune over 8, 16)")
+                    help="HP sources per solver block (default: autotune over 8, 16, 32)")
     ap.add_argument("--n-lp", type=int, default=None, help="override N_LP (default: the workload's)")
     ap.add_argument("--n-hp", type=int, default=None)
     ap.add_argument("--compare-sources", type=int, default=64)
@@ -230,7 +230,7 @@ def main():
     # the FP64 LP comparison, the learned flexible CG and its training, every
     # estimator, four sources at all momenta
     solves = [tq.solve_params(prec=lp_prec, stop=tq.STOP_TRUE, rhs_block=args.lp_block or 32, solver=solver),
-              tq.solve_params(prec=tq.PREC_F32, reliable=1, stop=tq.STOP_TRUE, rhs_block=args.hp_block or 16,
+              tq.solve_params(prec=tq.PREC_F32, reliable=1, stop=tq.STOP_TRUE, rhs_block=args.hp_block or 32,
                               solver=solver),
               tq.solve_params(prec=tq.PREC_F64, rhs_block=8, solver=solver)]
     if not args.no_learned:
@@ -249,7 +249,7 @@ def main():
     # block candidates and the block used with a fixed kernel configuration
     for role, prec, blk, fixed, cands, dflt, nsrc in (
             ("lp", lp_prec, args.lp_block, args.lp_config, (4, 8, 16, 32), 16, n_lp0),
-            ("hp", tq.PREC_F32, args.hp_block, args.hp_config, (8, 16), 8, n_hp0)):
+            ("hp", tq.PREC_F32, args.hp_block, args.hp_config, (8, 16, 32), 8, n_hp0)):
         name = [k for k, v in PREC_NAMES.items() if v == prec][0]
         blocks = [blk] if blk else ([b for b in cands if b <= max(nsrc, 1)] or [cands[0]])
         if fixed:
