@@ -557,7 +557,7 @@ static void eo_lin_nr(hipStream_t st, const EoArgs& a, int nr) {
 template <bool DAG, bool PRE, bool POST>
 static void eo_lin_prec(hipStream_t st, const EoArgs& a, int prec, int nr) {
     switch (prec) {
-    case P_F64: eo_lin_nr<DAG, PRE, POST, double, SF64, SF64, GF64>(st, a, 1); break;
+    case P_F64: eo_lin_nr<DAG, PRE, POST, double, SF64, SF64, GF64>(st, a, nr); break;  // (at most 2)
     case P_F32: eo_lin_nr<DAG, PRE, POST, float, SF32, SF32, GF32>(st, a, nr); break;
     case P_F16: eo_lin_nr<DAG, PRE, POST, float, SF16, SF16, GH16>(st, a, nr); break;
     default: eo_lin_nr<DAG, PRE, POST, float, SBF16, SBF16, GF32>(st, a, nr); break;
