@@ -38,16 +38,17 @@ __device__ __forceinline__ EoSite eo_coords(const Geom& hg, uint32_t h, int par)
 // half-sites.  Brick order (hg.brick = rows per wave, Lx/2 * hg.brick = 64):
 // a wave covers hg.brick consecutive rows of one z plane (1 KiB per plane of
 // an FP32 field, as in the natural order), the block's four waves four
-// consecutive z planes of one time slice, and the blocks run time slice
-// fastest, so the time neighbours a block gathers belong to the blocks
-// dispatched just before and after it on the same XCD (served from its L2
-// instead of HBM).
+// consecutive z planes of one time slice; the blocks run through the bricks
+// of one z slab y-brick fastest, then time slice, so that the y neighbours
+// of a block belong to the blocks dispatched just before and after it on the
+// same XCD and its time neighbours to blocks a y row of bricks away (both
+// served from that XCD's L2 instead of HBM).
 __device__ __forceinline__ uint32_t eo_site(const Geom& hg, uint32_t sb, uint32_t tid) {
     if (hg.brick == 0) return sb * 256u + tid;
     const uint32_t Lxh = (uint32_t)hg.L[0] >> 1, by = hg.brick;
     const uint32_t Lt = (uint32_t)hg.L[3], nty = (uint32_t)hg.L[1] / by;
-    const uint32_t t = sb % Lt, col = sb / Lt;
-    const uint32_t ty = col % nty, tz = col / nty;
+    const uint32_t ty = sb % nty, rest = sb / nty;
+    const uint32_t t = rest % Lt, tz = rest / Lt;
     const uint32_t lane = tid & 63u;
     const uint32_t y = ty * by + lane / Lxh, z = tz * 4u + (tid >> 6);
     return lane % Lxh + Lxh * (y + (uint32_t)hg.L[1] * (z + (uint32_t)hg.L[2] * t));
