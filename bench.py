@@ -91,6 +91,9 @@ def parse():
     ap.add_argument("--no-tune-cache", action="store_true",
                     help="measure the kernel traversal even if the tuning cache holds a choice (and do not record it)")
     ap.add_argument("--hp-config", default=None, metavar="NR,TSEG", help="same for the HP kernels")
+    ap.add_argument("--hp-delta", type=float, default=0.0,
+                    help="reliable-update trigger of the HP solves (0: the fastest of a few candidates, timed on "
+                         "the first HP block before the warmup)")
     ap.add_argument("--error-lp", type=int, default=128,
                     help="LP sources of the per-loop error report against an FP64 run of the same sources "
                          "(-1: the workload's N_LP; 0: skip)")
@@ -112,10 +115,11 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE
-    counter runs recorded in profiles/hbm_traffic.json (scaled by the copy
-    probe), or None if absent or taken on other kernel sources."""
+def recorded_traffic(kernel, workload, rhs_block):
+    """HBM bytes per launch of `kernel` run on blocks of `rhs_block` sources,
+    from the FETCH_SIZE / WRITE_SIZE counter runs recorded in
+    profiles/hbm_traffic.json (scaled by the copy probe), or None if absent,
+    taken on other kernel sources or on another block size."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
@@ -123,7 +127,7 @@ def recorded_traffic(kernel, workload):
         rec = json.load(fh)
     if rec.get("kernel_source_sha") != kernel_source_sha() or rec.get("workload") != workload:
         return None
-    k = rec.get("kernels", {}).get(kernel)
+    k = rec.get("kernels", {}).get("%s block=%d" % (kernel, rhs_block))
     if not k:
         return None
     return k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
@@ -284,8 +288,32 @@ def main():
                          true_resid=int(args.lp_true_resid), solver=solver)
     # HP: FP32 iterations with FP64 reliable updates, stopped on the FP64
     # true residual |eta - M s| / |eta| (taken at the reliable updates)
-    hp = tq.solve_params(prec=tq.PREC_F32, tol=wl.hp_tol, max_iter=-1, reliable=1, delta=0.1,
-                         rhs_block=args.hp_block, true_resid=1, stop=tq.STOP_TRUE, solver=solver)
+    def hp_params(delta):
+        return tq.solve_params(prec=tq.PREC_F32, tol=wl.hp_tol, max_iter=-1, reliable=1, delta=delta,
+                               rhs_block=args.hp_block, true_resid=1, stop=tq.STOP_TRUE, solver=solver)
+
+    # The HP solve stops on the FP64 true residual whatever the trigger delta
+    # is, so delta only trades FP64 updates (each about three FP32 iterations)
+    # against the drift of the FP32 residual; keep the fastest candidate.
+    if args.hp_delta > 0:
+        tune["hp"]["delta"] = args.hp_delta
+    elif n_hp > 0:
+        ids = list(range(min(args.hp_block, n_hp)))
+        cands = {}
+        for delta in (0.1, 1e-2, 1e-3, 3e-4, 1e-4):
+            for _ in range(2):  # the first run may capture graphs
+                ms, st = timed_solve(tq, torch, ctx, hp_params(delta), wl.noise_seed, ids)
+            cands[delta] = {"ms": round(1e3 * ms, 1), "iters_mean": float(np.mean([s["iters"] for s in st])),
+                            "resid_true_max": max(s["resid_true"] for s in st),
+                            "converged": all(s["converged"] for s in st)}
+        ok = [d for d in cands if cands[d]["converged"]] or [0.1]
+        tune["hp"]["delta"] = min(ok, key=lambda d: cands[d]["ms"])
+        tune["hp"]["delta_candidates"] = {"%g" % d: v for d, v in cands.items()}
+        log("HP delta: %s" % tune["hp"]["delta_candidates"])
+    else:
+        tune["hp"]["delta"] = 0.1
+    args.hp_delta = tune["hp"]["delta"]
+    hp = hp_params(args.hp_delta)
 
     def step():
         return tq.tsm_loops(ctx, wl.noise_seed, n_hp, n_lp, lp, hp, mom, stats=True)
@@ -337,11 +365,12 @@ def main():
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     prec_name = {v: k for k, v in PREC_NAMES.items()}
     dom_name = "%s %s NR=%d tseg=%d" % (kname(d), prec_name[d["prec"]], d["lane_rhs"], d["tseg"])
+    dom_block = args.lp_block if d["prec"] == lp_prec else args.hp_block
     copy_gbs = copy_bandwidth(torch)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dom_name, wl.name),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dom_name, wl.name, dom_block),
                 "torch_copy_GBps": round(copy_gbs, 1), "frac_of_torch_copy": round(achieved / copy_gbs, 4),
-                "kernel": dom_name,
+                "kernel": dom_name, "rhs_block": dom_block,
                 "launches": d["launches"], "avg_launch_us": round(avg_ms * 1e3, 2),
                 "algorithmic_bytes_per_launch": avg_bytes}
     per_class = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["ms"] / max(v["launches"], 1), 2),
@@ -373,7 +402,7 @@ def main():
                            len(mom)),
             "lattice": "x".join(str(d) for d in wl.dims),
             "n_hp": n_hp, "n_lp": n_lp, "lp_storage": args.lp_prec, "lp_rhs_block": args.lp_block,
-            "hp_rhs_block": args.hp_block,
+            "hp_rhs_block": args.hp_block, "hp_delta": args.hp_delta,
             "solver": "CG on the even-odd Schur complement" if args.solver == "eo" else "CG on M^dag M",
         },
         "autotune": tune,

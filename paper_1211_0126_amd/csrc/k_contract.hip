@@ -136,14 +136,14 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
             }
         }
     }
-    // A[r][t][z][iy][entry][x]: lanes of consecutive x write consecutive
-    // elements
+    // A[r][t][z][iy][x][entry]: a lane writes its eight entries in one run,
+    // and stage B reads the 16 entries of an x as one run
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         if (i < npy) {
-            double2* o = a.A + ((((((size_t)r * Lt + t) * Lz + z) * npy + i) * 16 + 8 * h) * Lx + x);
+            double2* o = a.A + (((((size_t)r * Lt + t) * Lz + z) * npy + i) * Lx + x) * 16 + 8 * h;
 #pragma unroll
-            for (int e = 0; e < 8; e++) o[(size_t)e * Lx] = make_double2(acc[i][e].re, acc[i][e].im);
+            for (int e = 0; e < 8; e++) o[e] = make_double2(acc[i][e].re, acc[i][e].im);
         }
     }
 }
@@ -273,9 +273,9 @@ __global__ __launch_bounds__(256) void k_contract_d(ContractArgs a) {
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         if (i < npy) {
-            double2* o = a.A + ((((((size_t)rs * Lt + t) * Lz + z) * npy + i) * 16 + 8 * h) * Lx + x);
+            double2* o = a.A + (((((size_t)rs * Lt + t) * Lz + z) * npy + i) * Lx + x) * 16 + 8 * h;
 #pragma unroll
-            for (int e = 0; e < 8; e++) o[(size_t)e * Lx] = make_double2(acc[i][e].re, acc[i][e].im);
+            for (int e = 0; e < 8; e++) o[e] = make_double2(acc[i][e].re, acc[i][e].im);
         }
     }
 }
@@ -297,9 +297,10 @@ __global__ __launch_bounds__(256) void k_contract_b(ContractArgs a) {
     cx<double> acc[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) acc[i] = {0.0, 0.0};
-    const double2* in = a.A + (((((size_t)r * Lt + t) * Lz + z) * npy + iy) * 16 + e) * Lx;
+    // the 16 lanes of one (iy, z, t) read the 16 entries of an x together
+    const double2* in = a.A + ((((size_t)r * Lt + t) * Lz + z) * npy + iy) * Lx * 16 + e;
     for (int x = 0; x < Lx; x++) {
-        const double2 v = in[x];
+        const double2 v = in[(size_t)x * 16];
         const cx<double> vv = {v.x, v.y};
 #pragma unroll
         for (int i = 0; i < 3; i++) {

@@ -23,14 +23,17 @@ def test_recorded_traffic_follows_the_kernel_sources():
     import bench
     with open(os.path.join(ROOT, "profiles", "hbm_traffic.json")) as fh:
         rec = json.load(fh)
-    name, k = next(iter(rec["kernels"].items()))
-    got = bench.recorded_traffic(name, rec["workload"])
+    key, k = next(iter(rec["kernels"].items()))
+    name, blk = key.rsplit(" block=", 1)
+    blk = int(blk)
+    got = bench.recorded_traffic(name, rec["workload"], blk)
     if rec["kernel_source_sha"] == bench.kernel_source_sha():
         assert got == k["fetch_bytes_per_launch"] + k["write_bytes_per_launch"]
     else:
         assert got is None
-    assert bench.recorded_traffic(name, "another workload") is None
-    assert bench.recorded_traffic("no such kernel", rec["workload"]) is None
+    assert bench.recorded_traffic(name, rec["workload"], blk + 1) is None
+    assert bench.recorded_traffic(name, "another workload", blk) is None
+    assert bench.recorded_traffic("no such kernel", rec["workload"], blk) is None
 
 
 def test_source_hash_depends_on_contents(tmp_path, monkeypatch):

@@ -85,16 +85,18 @@ def test_eo_fp64_converged_and_true_stop(orc):
     ctx.close()
 
 
-def test_eo_fp32_reliable_hp(orc):
+@pytest.mark.parametrize("delta", [0.1, 1e-4])
+def test_eo_fp32_reliable_hp(orc, delta):
     """FP32 iterations with FP64 reliable updates on the Schur system, to
-    1e-10 on the normal equations and on the true residual."""
+    1e-10 on the normal equations and on the true residual, with updates
+    every decade of the residual or every four decades."""
     import paper_1211_0126_amd as tq
     dims, kappa, mu, eps = LATTICES[3]
     U = make_gauge(dims, eps, 1002)
     ctx = _ctx(dims, kappa, mu, U)
     ids = [0, 1, 2, 3]
     for stop in (tq.STOP_NORMAL, tq.STOP_TRUE):
-        p = tq.solve_params(prec=tq.PREC_F32, tol=1e-10, max_iter=-1, reliable=1, delta=0.1, rhs_block=4,
+        p = tq.solve_params(prec=tq.PREC_F32, tol=1e-10, max_iter=-1, reliable=1, delta=delta, rhs_block=4,
                             stop=stop, solver=tq.SOLVER_CG_EO)
         sol, st, _ = tq.tsm_solve_batch(ctx, p, 9, ids)
         sol = sol.cpu().numpy()
