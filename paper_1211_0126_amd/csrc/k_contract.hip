@@ -86,6 +86,8 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int e = 0; e < 8; e++) acc[i][e] = {0.0, 0.0};
+    // four sites of the row in flight per lane
+#pragma unroll 4
     for (int y = 0; y < Ly; y++) {
         const uint32_t s = x + Lx * (y + Ly * (z + Lz * t));
         cx<double> S8[8];

@@ -274,7 +274,8 @@ __global__ __launch_bounds__(256) void k_cg_p(CgArgs a) {
 }
 
 // Initialisation: r holds b = M^dag eta.  p = r, x = 0, (rho = eta), block
-// partials of |b|^2 and |eta|^2 (k_cg_init_fin finishes).
+// partials of |b|^2 and, if eta is given, of |eta|^2 (k_cg_init_fin
+// finishes).
 template <typename R, class S, class X, typename RX, bool TRACK>
 __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const void* eta) {
     __shared__ double sh[4];
@@ -294,9 +295,11 @@ __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const void* eta) {
             store_spinor<X, RX>(field_rhs<X>(a.x, Vs, r), Vs, s, z);
         }
         pb = spinor_norm2(rv);
-        load_spinor<S, R>(field_rhs<S>(eta, Vs, r), Vs, s, ev);
-        pe = spinor_norm2(ev);
-        if (TRACK) store_spinor<S, R>(field_rhs<S>(a.rho, Vs, r), Vs, s, ev);
+        if (eta) {  // (none when |eta|^2 is known and nothing is tracked)
+            load_spinor<S, R>(field_rhs<S>(eta, Vs, r), Vs, s, ev);
+            pe = spinor_norm2(ev);
+            if (TRACK) store_spinor<S, R>(field_rhs<S>(a.rho, Vs, r), Vs, s, ev);
+        }
     }
     double v = block_sum256(pb, sh);
     if (threadIdx.x == 0) a.partials[(size_t)r * nb + blockIdx.x] = v;
@@ -692,6 +695,7 @@ void launch_cg_p(hipStream_t st, const CgArgs& a, int prec) {
 
 void launch_cg_init(hipStream_t st, const CgArgs& a, int prec, bool track, const void* eta, double ee_z4) {
     dim3 grid = site_grid(a.geo, a.nrhs);
+    if (!track && ee_z4 > 0) eta = nullptr;  // |eta|^2 given, no rho
     switch (prec) {
     case P_F64:
         if (track)

@@ -97,23 +97,110 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_lin(EoArgs a) {
     }
 }
 
-// Sources in the half layout: eta_o on the odd sites and D^{-1} eta_e on
-// the even sites (the input of the source's hop), from the hash
-template <typename R, class S>
-__global__ __launch_bounds__(256) void k_eo_noise(Geom hg, uint64_t seed_mixed, const uint64_t* ids, double twist,
-                                                  void* eta_o, void* ye) {
-    const uint32_t h = blockIdx.x * 256u + threadIdx.x;
-    const int r = blockIdx.y;
+// Full-lattice index of the neighbour in direction MU of half-site h (the
+// Z4 source of a site is a hash of its full index)
+template <int MU>
+__device__ __forceinline__ uint32_t eo_nb_full(const Geom& hg, uint32_t h, const EoSite& c, bool fwd) {
+    const uint32_t L0 = hg.L[0], L1 = hg.L[1], L2 = hg.L[2], L3 = hg.L[3];
+    const uint32_t row = (h - (uint32_t)c.xh) * 2u;  // Lx (y + Ly (z + Lz t))
+    if (MU == 0) {
+        const uint32_t xn = fwd ? ((c.x + 1 == (int)L0) ? 0u : (uint32_t)c.x + 1u)
+                                : ((c.x == 0) ? L0 - 1u : (uint32_t)c.x - 1u);
+        return row + xn;
+    }
+    const uint32_t s = row + (uint32_t)c.x;
+    if (MU == 1) return fwd ? ((c.y + 1 == (int)L1) ? s - (L1 - 1u) * L0 : s + L0) : ((c.y == 0) ? s + (L1 - 1u) * L0 : s - L0);
+    if (MU == 2)
+        return fwd ? ((c.z + 1 == (int)L2) ? s - (L2 - 1u) * L0 * L1 : s + L0 * L1)
+                   : ((c.z == 0) ? s + (L2 - 1u) * L0 * L1 : s - L0 * L1);
+    return fwd ? ((c.t + 1 == (int)L3) ? s - (L3 - 1u) * L0 * L1 * L2 : s + L0 * L1 * L2)
+               : ((c.t == 0) ? s + (L3 - 1u) * L0 * L1 * L2 : s - L0 * L1 * L2);
+}
+
+// Both hops of H (not H^dag) in direction MU into odd half-site h with the
+// input D^{-1} eta generated at the even neighbours from the hash
+template <int MU, typename R, class G, int NR>
+__device__ __forceinline__ void src_hop_mu(const EoArgs& a, const uint64_t* ids, uint32_t h, const EoSite& c, R tw,
+                                           R inv, cx<R> (&acc)[NR][12]) {
+    const Geom& hg = a.hg;
+    const long Vs = hg.Vs;
+    const uint64_t Vf = 2 * (uint64_t)hg.V;
+    {
+        const uint32_t sy = eo_nb_full<MU>(hg, h, c, true);
+        const bool flip = (MU == 3) && (c.t + 1 == hg.L[3]) && (hg.t_bc < 0);
+        cx<R> U[3][3];
+        load_link<G, R>(a.gout, Vs, MU, h, U);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<R> p[12], hh[6], g[6];
+            noise_at<R>(a.seed_mixed, ids[r], Vf, sy, p);
+            mul_diag_inv(p, tw, inv);
+            proj<MU, 1>(p, hh);
+            if (flip) negate6(hh);
+            su3_mul(U, hh, g);
+            recon<MU, 1>(g, acc[r]);
+        }
+    }
+    {
+        const uint32_t y = eo_nb(hg, h, c, MU, false);
+        const uint32_t sy = eo_nb_full<MU>(hg, h, c, false);
+        const bool flip = (MU == 3) && (c.t == 0) && (hg.t_bc < 0);
+        cx<R> U[3][3];
+        load_link<G, R>(a.gin, Vs, MU, y, U);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            cx<R> p[12], hh[6], g[6];
+            noise_at<R>(a.seed_mixed, ids[r], Vf, sy, p);
+            mul_diag_inv(p, tw, inv);
+            proj<MU, -1>(p, hh);
+            if (flip) negate6(hh);
+            su3_dag_mul(U, hh, g);
+            recon<MU, -1>(g, acc[r]);
+        }
+    }
+}
+
+// Source of the Schur system on the odd sites, etahat = eta_o + kappa H_oe
+// D^{-1} eta_e, with the Z4 source generated from the hash at each site it
+// needs: no source field is written or read.  The chunk of right-hand sides
+// r0 .. r0 + NR - 1 takes the ids a.ids[r0 ..].
+template <typename R, class So, class G, int NR>
+__global__ __launch_bounds__(256) void k_eo_src(EoArgs a) {
+    const Geom& hg = a.hg;
+    const BlockMap bm = stencil_block((uint32_t)(a.nrhs / NR));
+    const int r0 = bm.ch * NR;
+    const uint32_t h = eo_site(hg, bm.sb, threadIdx.x);
     if (h >= hg.V) return;
-    const uint64_t Vf = (uint64_t)(2 * hg.V);
-    cx<R> e[12];
-    const EoSite co = eo_coords(hg, h, 1);
-    noise_at<R>(seed_mixed, ids[r], Vf, eo_full_site(h, co), e);
-    store_spinor<S, R>(field_rhs<S>(eta_o, hg.Vs, r), hg.Vs, h, e);
-    const EoSite ce = eo_coords(hg, h, 0);
-    noise_at<R>(seed_mixed, ids[r], Vf, eo_full_site(h, ce), e);
-    mul_diag_inv(e, (R)twist, (R)(1.0 / (1.0 + twist * twist)));
-    store_spinor<S, R>(field_rhs<S>(ye, hg.Vs, r), hg.Vs, h, e);
+    const long Vs = hg.Vs;
+    const R tw = (R)a.twist;
+    const R inv = (R)(1.0 / (1.0 + a.twist * a.twist));
+    const R kap = (R)a.kappa;
+    const EoSite c = eo_coords(hg, h, 1);
+    const uint64_t* ids = a.ids + r0;
+    cx<R> acc[NR][12];
+#pragma unroll
+    for (int r = 0; r < NR; r++)
+#pragma unroll
+        for (int k = 0; k < 12; k++) acc[r][k] = {(R)0, (R)0};
+    src_hop_mu<0, R, G, NR>(a, ids, h, c, tw, inv, acc);
+    pin_acc<R, NR>(acc);
+    TM_MEM_FENCE();
+    src_hop_mu<1, R, G, NR>(a, ids, h, c, tw, inv, acc);
+    pin_acc<R, NR>(acc);
+    TM_MEM_FENCE();
+    src_hop_mu<2, R, G, NR>(a, ids, h, c, tw, inv, acc);
+    pin_acc<R, NR>(acc);
+    TM_MEM_FENCE();
+    src_hop_mu<3, R, G, NR>(a, ids, h, c, tw, inv, acc);
+    const uint32_t so = eo_full_site(h, c);
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        cx<R> o[12];
+        noise_at<R>(a.seed_mixed, ids[r], 2 * (uint64_t)hg.V, so, o);
+#pragma unroll
+        for (int k = 0; k < 12; k++) o[k] = o[k] + kap * acc[r][k];
+        store_spinor<So, R>(field_rhs<So>(a.out, Vs, r0 + r), Vs, h, o);
+    }
 }
 
 // The whole solution in the full native layout of X (stride g.Vs): the even
@@ -451,22 +538,24 @@ __global__ __launch_bounds__(256) void k_eo_links_h16(Geom hg, const void* g64, 
 static inline uint32_t eo_blocks(const Geom& hg) { return (uint32_t)((hg.V + 255) / 256); }
 constexpr uint32_t kEoGatedBlocks = 512;
 
-void launch_eo_noise(hipStream_t st, const Geom& hg, int prec, uint64_t seed_mixed, const uint64_t* ids, int nrhs,
-                     double twist, void* eta_o, void* ye) {
-    const dim3 grid(eo_blocks(hg), (unsigned)nrhs);
+
+template <typename R, class So, class G>
+static void eo_src_nr(hipStream_t st, const EoArgs& a, int nr) {
+    const uint32_t nb = eo_blocks(a.hg);
+    if (nr >= 2 && a.nrhs % 2 == 0)
+        hipLaunchKernelGGL((k_eo_src<R, So, G, 2>), dim3(nb * (unsigned)(a.nrhs / 2)), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_eo_src<R, So, G, 1>), dim3(nb * (unsigned)a.nrhs), dim3(256), 0, st, a);
+}
+
+// etahat into a.out in storage prec (FP64 arithmetic and links for P_F64,
+// FP32 otherwise)
+void launch_eo_src(hipStream_t st, const EoArgs& a, int prec, int nr) {
     switch (prec) {
-    case P_F64:
-        hipLaunchKernelGGL((k_eo_noise<double, SF64>), grid, dim3(256), 0, st, hg, seed_mixed, ids, twist, eta_o, ye);
-        break;
-    case P_F32:
-        hipLaunchKernelGGL((k_eo_noise<float, SF32>), grid, dim3(256), 0, st, hg, seed_mixed, ids, twist, eta_o, ye);
-        break;
-    case P_F16:
-        hipLaunchKernelGGL((k_eo_noise<float, SF16>), grid, dim3(256), 0, st, hg, seed_mixed, ids, twist, eta_o, ye);
-        break;
-    default:
-        hipLaunchKernelGGL((k_eo_noise<float, SBF16>), grid, dim3(256), 0, st, hg, seed_mixed, ids, twist, eta_o, ye);
-        break;
+    case P_F64: eo_src_nr<double, SF64, GF64>(st, a, nr); break;
+    case P_F32: eo_src_nr<float, SF32, GF32>(st, a, nr); break;
+    case P_F16: eo_src_nr<float, SF16, GF32>(st, a, nr); break;
+    default: eo_src_nr<float, SBF16, GF32>(st, a, nr); break;
     }
 }
 

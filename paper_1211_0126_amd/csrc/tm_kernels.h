@@ -134,6 +134,10 @@ struct EoCg {
 };
 // kinds of launch_eo_lin: out = POST(PRE(b) + c H in)
 enum { EO_Y = 0, EO_Y_DAG = 1, EO_T = 2, EO_T_DAG = 3, EO_SRC = 4, EO_REC = 5 };
+// etahat = eta_o + kappa H_oe D^{-1} eta_e on the odd sites from the Z4 hash
+// (a.out, a.ids, a.nrhs, a.twist, a.kappa, a.seed_mixed; a.gout / a.gin the
+// odd / even links of the arithmetic's precision)
+void launch_eo_src(hipStream_t st, const EoArgs& a, int prec, int nr);
 void launch_eo_lin(hipStream_t st, const EoArgs& a, int prec, int nr, int kind);
 void launch_eo_rec_f32(hipStream_t st, const EoArgs& a, int nr);
 void launch_eo_dinv(hipStream_t st, const Geom& hg, int prec, double twist, int nrhs, const void* in, void* out);
@@ -157,9 +161,6 @@ void launch_eot_mp(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int
 void launch_eot_upd(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr, bool track);
 void launch_eot_src(hipStream_t st, const EoArgs& a, int prec, int nr);
 void launch_eot_rec(hipStream_t st, const EoArgs& a, int nr, const Geom& g, void* full);
-// sources in the half layout: eta_o (odd sites) and D^{-1} eta_e (even)
-void launch_eo_noise(hipStream_t st, const Geom& hg, int prec, uint64_t seed_mixed, const uint64_t* ids, int nrhs,
-                     double twist, void* eta_o, void* ye);
 // the whole solution in the full native layout from the odd half a.in
 void launch_eo_rec_full(hipStream_t st, const EoArgs& a, int xprec, int nr, const Geom& g, void* full);
 // FP16 links of one parity (the FP16-storage hops) from its FP64 links

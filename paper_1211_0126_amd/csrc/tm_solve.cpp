@@ -23,6 +23,9 @@ namespace tmq {
 static const int kIterCap = 20000;  // safety cap for max_iter = -1
 // search directions kept by the even-odd CG without reliable updates
 constexpr int kEoRing = 8;
+// sources per launch of the FP32 solution reconstruction (a multiple of every
+// right-hand-sides-per-lane setting)
+constexpr int kRecSub = 8;
 
 static tm_status check_solve_params(tm_ctx* ctx, const tsm_solve_params* p) {
     if (!p) return set_error(ctx, TM_EINVAL, "null solve parameters");
@@ -405,7 +408,6 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     // FP64 half-hops: two sources per lane (the links are read once per pair)
     const int nr64 = nrhs % 2 == 0 ? 2 : 1;
     const int snr = sp == P_F64 ? nr64 : nr;
-    void* eta_o = tiles && !rel ? nullptr : ws_get(ctx, tag + "_eo_etao", field_bytes(hg, sp, nc), &s);
     void* eh = ws_get(ctx, tag + "_eo_eh", field_bytes(hg, sp, nc), &s);
     void *b64 = nullptr, *x64 = nullptr, *t64 = nullptr, *y64 = nullptr;
     if (rel) {
@@ -468,9 +470,13 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
         launch_eot_mp(st, ai, ei, prec, nr, true, eh, a.r);
         launch_cg_init(st, a, prec, track, eh, ee_z4);  // (the tile path updates x: no ring)
     } else {
-        // eta_o and D^{-1} eta_e, then etahat, y = D^{-dag} H_eo^dag etahat and b
-        launch_eo_noise(st, hg, sp, seed_mixed, ids_dev, nrhs, tw, eta_o, ys);
-        launch_eo_lin(st, lin(1, rel, ys, eh, eta_o, kappa, nrhs), sp, snr, EO_SRC);
+        // etahat from the hash, then y = D^{-dag} H_eo^dag etahat and b
+        EoArgs es = lin(1, sp == P_F64, nullptr, eh, nullptr, kappa, nrhs);
+        if (sp != P_F64) {  // FP32 arithmetic with FP32 links
+            es.gout = g32o;
+            es.gin = g32e;
+        }
+        launch_eo_src(st, es, sp, snr);
         launch_eo_lin(st, lin(0, rel, eh, ys, nullptr, 1.0, nrhs), sp, snr, EO_Y_DAG);
         if (rel) {
             launch_eo_lin(st, lin(1, true, ys, b64, eh, k2, nrhs), P_F64, nr64, EO_T_DAG);
@@ -640,8 +646,19 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
         if (prec != P_F64) {
             e.gout = g32e;
             e.gin = g32o;
+            // FP32 halves of at most kRecSub sources per launch: the
+            // neighbours a block gathers are then still in L2 when the blocks
+            // of the next time slice need them
+            for (int j0 = 0; j0 < nrhs; j0 += kRecSub) {
+                EoArgs es = e;
+                es.in = (const char*)a.x + field_bytes(hg, xprec, j0);
+                es.ids = ids_dev + j0;
+                es.nrhs = std::min(kRecSub, nrhs - j0);
+                launch_eo_rec_full(st, es, xprec, nr, g, (char*)xfull + field_bytes(g, fprec, j0));
+            }
+        } else {
+            launch_eo_rec_full(st, e, xprec, nr64, g, xfull);
         }
-        launch_eo_rec_full(st, e, xprec, prec == P_F64 ? nr64 : nr, g, xfull);
     }
     prof_end(ctx, TM_KC_OTHER, 0.0);
     res->x = xfull;
@@ -1061,7 +1078,7 @@ static size_t ws_block(const Geom& g, const Geom& hg, const tsm_solve_params* p,
                         : fb;
         b += 3 * fb + align256(field_bytes(hg, xprec, nc)) + scal + (track ? fb : 0);
         b += align256(field_bytes(g, rel ? P_F64 : xprec, nc));
-        b += 2 * align256(field_bytes(hg, rel ? P_F64 : prec, nc));
+        b += align256(field_bytes(hg, rel ? P_F64 : prec, nc));  // etahat
         if (rel) b += 4 * align256(field_bytes(hg, P_F64, nc));
         return b;
     }
