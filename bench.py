@@ -91,6 +91,9 @@ def parse():
     ap.add_argument("--no-tune-cache", action="store_true",
                     help="measure the kernel traversal even if the tuning cache holds a choice (and do not record it)")
     ap.add_argument("--hp-config", default=None, metavar="NR,TSEG", help="same for the HP kernels")
+    ap.add_argument("--hp-prec", default="f16", choices=["f32", "f16", "bf16"],
+                    help="storage of the HP iteration vectors (FP32 arithmetic, FP64 reliable updates; the stored "
+                         "residual is rescaled at each update)")
     ap.add_argument("--hp-delta", type=float, default=0.0,
                     help="reliable-update trigger of the HP solves (0: the fastest of a few candidates, timed on "
                          "the first HP block before the warmup)")
@@ -225,6 +228,7 @@ def main():
     torch.cuda.set_stream(stream)
     mom = wl.momenta()
     lp_prec = PREC_NAMES[args.lp_prec]
+    hp_prec = PREC_NAMES[args.hp_prec]
     solver = tq.SOLVER_CG_EO if args.solver == "eo" else tq.SOLVER_CG
     n_lp0 = args.n_lp if args.n_lp is not None else wl.n_lp
     n_hp0 = args.n_hp if args.n_hp is not None else wl.n_hp
@@ -234,7 +238,7 @@ def main():
     # the FP64 LP comparison, the learned flexible CG and its training, every
     # estimator, four sources at all momenta
     solves = [tq.solve_params(prec=lp_prec, stop=tq.STOP_TRUE, rhs_block=args.lp_block or 32, solver=solver),
-              tq.solve_params(prec=tq.PREC_F32, reliable=1, stop=tq.STOP_TRUE, rhs_block=args.hp_block or 32,
+              tq.solve_params(prec=hp_prec, reliable=1, stop=tq.STOP_TRUE, rhs_block=args.hp_block or 32,
                               solver=solver),
               tq.solve_params(prec=tq.PREC_F64, rhs_block=8, solver=solver)]
     if not args.no_learned:
@@ -253,14 +257,15 @@ def main():
     # block candidates and the block used with a fixed kernel configuration
     for role, prec, blk, fixed, cands, dflt, nsrc in (
             ("lp", lp_prec, args.lp_block, args.lp_config, (4, 8, 16, 32), 16, n_lp0),
-            ("hp", tq.PREC_F32, args.hp_block, args.hp_config, (8, 16, 32), 8, n_hp0)):
+            ("hp", hp_prec, args.hp_block, args.hp_config, (8, 16, 32), 8, n_hp0)):
         name = [k for k, v in PREC_NAMES.items() if v == prec][0]
         blocks = [blk] if blk else ([b for b in cands if b <= max(nsrc, 1)] or [cands[0]])
         if fixed:
             # NR,TSEG (CG on M^dag M) or NR,TILES (even-odd)
             nr, ts = (int(v) for v in fixed.split(","))
             tuning_cache.apply(ctx, prec, solver, {"lane_rhs": nr, "tseg": ts, "tiles": ts})
-            tune[role] = {"storage": name, "rhs_block": blk or dflt, "lane_rhs": nr, "tseg": ts, "fixed": True}
+            tune[role] = {"storage": name, "rhs_block": blk or dflt, "lane_rhs": nr, "tseg": ts, "fixed": True,
+                          "rec": {"lane_rhs": nr, "tseg": ts, "tiles": ts}}
             continue
         # per block size: the best (right-hand sides per lane, time slices
         # per lane); keep the block with the lowest time per source-iteration
@@ -276,7 +281,12 @@ def main():
         b, _, rec = best
         tuning_cache.apply(ctx, prec, solver, rec)
         tune[role] = {"storage": name, "rhs_block": b, "lane_rhs": rec["lane_rhs"], "tseg": rec.get("tseg", 0),
-                      "tiles": rec.get("tiles", 0), "candidates": per_block}
+                      "tiles": rec.get("tiles", 0), "candidates": per_block, "rec": rec}
+    if hp_prec == lp_prec and "rec" in tune["lp"]:
+        # one kernel configuration per storage: the LP's, which runs most
+        tuning_cache.apply(ctx, lp_prec, solver, tune["lp"]["rec"])
+    for role in tune:
+        tune[role].pop("rec", None)
     args.lp_block = tune["lp"]["rhs_block"]
     args.hp_block = tune["hp"]["rhs_block"]
     log("autotune: %s" % tune)
@@ -288,21 +298,23 @@ def main():
                          true_resid=int(args.lp_true_resid), solver=solver)
     # HP: FP32 iterations with FP64 reliable updates, stopped on the FP64
     # true residual |eta - M s| / |eta| (taken at the reliable updates)
-    def hp_params(delta):
-        return tq.solve_params(prec=tq.PREC_F32, tol=wl.hp_tol, max_iter=-1, reliable=1, delta=delta,
+    def hp_params(delta, max_iter=-1):
+        return tq.solve_params(prec=hp_prec, tol=wl.hp_tol, max_iter=max_iter, reliable=1, delta=delta,
                                rhs_block=args.hp_block, true_resid=1, stop=tq.STOP_TRUE, solver=solver)
 
     # The HP solve stops on the FP64 true residual whatever the trigger delta
     # is, so delta only trades FP64 updates (each about three FP32 iterations)
-    # against the drift of the FP32 residual; keep the fastest candidate.
+    # against the drift of the recursively updated residual in the storage
+    # precision; keep the fastest candidate.
     if args.hp_delta > 0:
         tune["hp"]["delta"] = args.hp_delta
     elif n_hp > 0:
         ids = list(range(min(args.hp_block, n_hp)))
         cands = {}
-        for delta in (0.1, 1e-2, 1e-3, 3e-4, 1e-4):
+        for delta in (0.1, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4):
             for _ in range(2):  # the first run may capture graphs
-                ms, st = timed_solve(tq, torch, ctx, hp_params(delta), wl.noise_seed, ids)
+                # (a bounded trial: a trigger too small for the storage stalls)
+                ms, st = timed_solve(tq, torch, ctx, hp_params(delta, 400), wl.noise_seed, ids)
             cands[delta] = {"ms": round(1e3 * ms, 1), "iters_mean": float(np.mean([s["iters"] for s in st])),
                             "resid_true_max": max(s["resid_true"] for s in st),
                             "converged": all(s["converged"] for s in st)}
@@ -356,16 +368,17 @@ def main():
     # the largest total time; it is one compiled kernel in the rocprofv3 trace
     # (classes without a variant, such as the contraction, span several kernels)
     for v in sorted(variants, key=lambda v: -v["ms"]):
-        log("profiled %-10s prec %2d nr %2d solver %2d tseg %2d: %6d launches, %9.1f ms, avg %8.1f us"
-            % (v["kc"], v["prec"], v["lane_rhs"], v["solver"], v["tseg"], v["launches"], v["ms"],
+        log("profiled %-10s prec %2d nr %2d solver %2d tseg %2d rel %2d: %6d launches, %9.1f ms, avg %8.1f us"
+            % (v["kc"], v["prec"], v["lane_rhs"], v["solver"], v["tseg"], v["reliable"], v["launches"], v["ms"],
                1e3 * v["ms"] / max(v["launches"], 1)))
     d = max((v for v in variants if v["bytes"] > 0 and v["prec"] >= 0), key=lambda v: v["ms"])
     avg_ms = d["ms"] / max(d["launches"], 1)
     avg_bytes = d["bytes"] / max(d["launches"], 1)
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9
     prec_name = {v: k for k, v in PREC_NAMES.items()}
-    dom_name = "%s %s NR=%d tseg=%d" % (kname(d), prec_name[d["prec"]], d["lane_rhs"], d["tseg"])
-    dom_block = args.lp_block if d["prec"] == lp_prec else args.hp_block
+    dom_name = "%s %s NR=%d tseg=%d%s" % (kname(d), prec_name[d["prec"]], d["lane_rhs"], d["tseg"],
+                                          " reliable" if d["reliable"] == 1 else "")
+    dom_block = args.hp_block if d["reliable"] == 1 or d["prec"] != lp_prec else args.lp_block
     copy_gbs = copy_bandwidth(torch)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dom_name, wl.name, dom_block),
@@ -396,13 +409,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "%s: %dx%dx%dx%d twisted-mass Wilson, kappa %.4f, a*mu %.4f, N_HP %d (FP32 + FP64 reliable "
-                        "updates to %.0e), N_LP %d (%s storage, FP32 arithmetic, to %.0e), 16 Gamma x %d momenta"
-                        % (wl.name, *wl.dims, wl.kappa, wl.mu, n_hp, wl.hp_tol, n_lp, args.lp_prec, wl.lp_tol,
-                           len(mom)),
+            "workload": "%s: %dx%dx%dx%d twisted-mass Wilson, kappa %.4f, a*mu %.4f, N_HP %d (%s storage, FP32 "
+                        "arithmetic, FP64 reliable updates, to %.0e), N_LP %d (%s storage, FP32 arithmetic, to %.0e), "
+                        "16 Gamma x %d momenta"
+                        % (wl.name, *wl.dims, wl.kappa, wl.mu, n_hp, args.hp_prec, wl.hp_tol, n_lp, args.lp_prec,
+                           wl.lp_tol, len(mom)),
             "lattice": "x".join(str(d) for d in wl.dims),
             "n_hp": n_hp, "n_lp": n_lp, "lp_storage": args.lp_prec, "lp_rhs_block": args.lp_block,
-            "hp_rhs_block": args.hp_block, "hp_delta": args.hp_delta,
+            "hp_storage": args.hp_prec, "hp_rhs_block": args.hp_block, "hp_delta": args.hp_delta,
             "solver": "CG on the even-odd Schur complement" if args.solver == "eo" else "CG on M^dag M",
         },
         "autotune": tune,
@@ -417,6 +431,7 @@ def main():
         "hp_true_resid_max": run["max_hp_resid_true"],
         "kernels": per_class,
         "kernel_variants": [{"kernel": kname(v), "prec": v["prec"], "lane_rhs": v["lane_rhs"], "tseg": v["tseg"],
+                             "reliable": v["reliable"],
                              "launches": v["launches"], "avg_us": round(1e3 * v["ms"] / max(v["launches"], 1), 2),
                              "GBps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1) if v["bytes"] > 0 else None}
                             for v in variants if v["prec"] >= 0],

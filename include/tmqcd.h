@@ -127,7 +127,8 @@ typedef struct {
     double tol;         /* relative residual target; 0 = run to max_iter */
     int32_t max_iter;   /* iteration cap, -1 = none; 0 returns s = 0 */
     int32_t stop;       /* tm_stop */
-    int32_t reliable;   /* 1: FP32 iterations with FP64 reliable updates (prec must be F32) */
+    int32_t reliable;   /* 1: FP32 iterations with FP64 reliable updates (prec F32; also F16 or BF16
+                           storage with TM_SOLVER_CG_EO) */
     double delta;       /* reliable-update trigger: |r| < delta * max |r| since the last update */
     int32_t rhs_block;  /* sources per launch, 1..32; 0 = library default */
     int32_t true_resid; /* 1: compute the FP64 true residual of every solve (one FP64 M) */
@@ -547,7 +548,8 @@ tm_status tm_profile_enable(tm_ctx* ctx, int32_t on);
 tm_status tm_profile_read(tm_ctx* ctx, int64_t* launches, double* ms, double* bytes);
 
 /* The same figures split by kernel variant: one entry per (kernel class,
-   storage precision, right-hand sides per lane, solver) seen since the last
+   storage precision, right-hand sides per lane, solver, reliable-update
+   mode) seen since the last
    tm_profile_enable, so that an entry corresponds to one compiled kernel.
    Launches that carry no variant (initialisation, residuals, contraction,
    tm_dslash) have prec = lane_rhs = solver = -1.  Writes at most `cap`
@@ -560,7 +562,8 @@ typedef struct {
     int32_t solver;   /* tm_solver, or -1 */
     int32_t tseg;     /* time slices per lane of a time-marching kernel, 0 if
                          one lane per site, -1 if not a CG stencil */
-    int32_t reserved;
+    int32_t reliable; /* 1: launched by a solve with reliable updates, else 0
+                         (-1 if not a CG stencil) */
     int64_t launches;
     double ms;
     double bytes;

@@ -23,7 +23,7 @@ def tm_set_graphs(ctx: Context, on=None):
 
 class ProfileEntry(ctypes.Structure):
     _fields_ = [("kc", ctypes.c_int32), ("prec", ctypes.c_int32), ("lane_rhs", ctypes.c_int32),
-                ("solver", ctypes.c_int32), ("tseg", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("solver", ctypes.c_int32), ("tseg", ctypes.c_int32), ("reliable", ctypes.c_int32),
                 ("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
@@ -41,7 +41,7 @@ def tm_profile_entries(ctx: Context, cap=256):
     n = ctypes.c_int32()
     ctx.check(ctx.lib.tm_profile_entries(ctx.h, buf, int(cap), ctypes.byref(n)))
     return [{"kc": KC_NAMES[e.kc], "prec": e.prec, "lane_rhs": e.lane_rhs, "solver": e.solver, "tseg": e.tseg,
-             "launches": int(e.launches), "ms": float(e.ms), "bytes": float(e.bytes)} for e in buf[:n.value]]
+             "reliable": e.reliable, "launches": int(e.launches), "ms": float(e.ms), "bytes": float(e.bytes)} for e in buf[:n.value]]
 
 
 EXPORTS += ["tm_set_march"]

@@ -82,8 +82,11 @@ __device__ inline void cg_finish_step(CgScal& q, double rrn, double rhon) {
     if (q.stop == 1 && !q.reliable) q.rho2 = rhon;
     if (q.reliable) {
         if (rrn > q.maxrr) q.maxrr = rrn;
-        if (rrn <= q.tol2 * q.bb || rrn < q.delta2 * q.maxrr) {
+        if (rrn * q.sigma * q.sigma <= q.tol2 * q.bb || rrn < q.delta2 * q.maxrr) {
             q.rflag = 1;  // the reliable-update kernels finish this step
+            // the recomputed residual is stored at the source's scale
+            const double s = (rrn > 0 && q.bb > 0) ? q.sigma * sqrt(rrn / q.bb) : q.sigma;
+            q.sigma_next = (s > 0 && s < 1e300) ? exp2(rint(log2(s))) : q.sigma;
             return;
         }
         q.beta = rrn / q.rr;
@@ -311,6 +314,7 @@ __global__ __launch_bounds__(256) void k_cg_init(CgArgs a, const void* eta) {
 __device__ inline void cg_start(CgScal& q, double bb, double ee) {
     q.bb = q.rr = q.maxrr = bb;
     q.ee = q.rho2 = ee;
+    q.sigma = q.sigma_next = 1.0;
     q.iters = 0;
     q.rflag = 0;
     q.n_reliable = 0;
@@ -339,7 +343,9 @@ __global__ __launch_bounds__(256) void k_cg_init_fin(CgArgs a, uint32_t nb, int 
 // reliable updates (FP32 iterations, FP64 solution and true residual)
 // ---------------------------------------------------------------------------
 
-// init: r32 = b64, p32 = r32, x32 = 0, x64 = 0, block partials of |b64|^2
+// init: r = b64, p = r (stored as S), x32 = 0, x64 = 0, block partials of
+// |b64|^2
+template <class S>
 __global__ __launch_bounds__(256) void k_rel_init(CgArgs a, const void* b64, void* x64) {
     __shared__ double sh[4];
     const uint32_t nb = gridDim.x;
@@ -358,8 +364,8 @@ __global__ __launch_bounds__(256) void k_rel_init(CgArgs a, const void* b64, voi
             zf[k] = {0.f, 0.f};
             z[k] = {0.0, 0.0};
         }
-        store_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r), Vs, s, rf);
-        store_spinor<SF32, float>(field_rhs<SF32>(a.p, Vs, r), Vs, s, rf);
+        store_spinor<S, float>(field_rhs<S>(a.r, Vs, r), Vs, s, rf);
+        store_spinor<S, float>(field_rhs<S>(a.p, Vs, r), Vs, s, rf);
         store_spinor<SF32, float>(field_rhs<SF32>(a.x, Vs, r), Vs, s, zf);
         store_spinor<SF64, double>(field_rhs<SF64>(x64, Vs, r), Vs, s, z);
     }
@@ -380,6 +386,7 @@ __global__ __launch_bounds__(256) void k_rel_flush(CgArgs a, void* x64, int forc
     const uint32_t nsb = (uint32_t)((a.geo.V + 255) / 256);
     void* xdp = field_rhs<SF64>(x64, Vs, r);
     void* xsp = field_rhs<SF32>(a.x, Vs, r);
+    const double sg = a.scal[r].sigma;
     for (uint32_t sb = blockIdx.x; sb < nsb; sb += gridDim.x) {
         const uint32_t s = sb * 256u + threadIdx.x;
         if (s >= a.geo.V) continue;
@@ -389,7 +396,7 @@ __global__ __launch_bounds__(256) void k_rel_flush(CgArgs a, void* x64, int forc
         load_spinor<SF32, double>(xsp, Vs, s, xs);
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            xd[k] = xd[k] + xs[k];
+            xd[k] = xd[k] + sg * xs[k];
             z[k] = {0.f, 0.f};
         }
         store_spinor<SF64, double>(xdp, Vs, s, xd);
@@ -419,10 +426,11 @@ __global__ TM_STENCIL_R(1, double) void k_rel_resid(CgArgs a, const void* gauge6
         diag_combine(tc, acc[0], a.kappa, -a.twist, q);
         load_spinor<SF64, double>(field_rhs<SF64>(b64, Vs, r), Vs, s, bv);
         cx<float> rf[12];
+        const double isg = 1.0 / a.scal[r].sigma_next;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
             bv[k] = bv[k] - q[k];
-            rf[k] = {(float)bv[k].re, (float)bv[k].im};
+            rf[k] = {(float)(isg * bv[k].re), (float)(isg * bv[k].im)};
         }
         store_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r), Vs, s, rf);
         pr += spinor_norm2(bv);
@@ -453,9 +461,13 @@ __global__ __launch_bounds__(256) void k_rel_fin(CgArgs a, uint32_t nb) {
     const double rho2 = a.eta64 ? sum_block_partials(a.partials2 + (size_t)r * nb, nb, sh) : 0.0;
     if (threadIdx.x == 0) {
         CgScal& q = a.scal[r];
-        q.beta = rrn / q.rr;
-        q.rr = rrn;
-        q.maxrr = rrn;
+        // rrn is the true |r|^2; the next p = r + beta p in the new scale
+        // takes the old p times sigma / sigma_next
+        const double so = q.sigma, sn = q.sigma_next;
+        q.beta = rrn / (q.rr * so * so) * (so / sn);
+        q.rr = rrn / (sn * sn);
+        q.maxrr = q.rr;
+        q.sigma = sn;
         q.rflag = 0;
         q.n_reliable += 1;
         if (q.stop == 1) q.rho2 = rho2;
@@ -732,8 +744,13 @@ void launch_scal_init(hipStream_t st, CgScal* sc, int n, double tol2, int maxit,
                        delta2);
 }
 
-void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64, double ee_z4) {
-    hipLaunchKernelGGL(k_rel_init, site_grid(a.geo, a.nrhs), dim3(256), 0, st, a, b64, x64);
+void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64, double ee_z4, int prec) {
+    const dim3 grid = site_grid(a.geo, a.nrhs);
+    switch (prec) {
+    case P_F16: hipLaunchKernelGGL(k_rel_init<SF16>, grid, dim3(256), 0, st, a, b64, x64); break;
+    case P_BF16: hipLaunchKernelGGL(k_rel_init<SBF16>, grid, dim3(256), 0, st, a, b64, x64); break;
+    default: hipLaunchKernelGGL(k_rel_init<SF32>, grid, dim3(256), 0, st, a, b64, x64); break;
+    }
     hipLaunchKernelGGL(k_cg_init_fin, dim3((unsigned)a.nrhs), dim3(256), 0, st, a, site_blocks(a.geo), 0,
                        ee_z4 > 0 ? ee_z4 : 12.0 * (double)a.geo.V);
 }

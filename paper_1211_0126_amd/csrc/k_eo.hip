@@ -415,8 +415,9 @@ __global__ __launch_bounds__(256) void k_eo_xflush(CgArgs a, const void* dirs, s
 // Reliable update (gated, FP64): r64 = b64 - (D^dag t64 - kappa^2 H_oe^dag
 // y64) with t64 = Mhat x64 and y64 = D^{-dag} H_eo^dag t64, r32 = r64, block
 // partials of |r64|^2 and (a.eta64 = etahat set) of |etahat - t64|^2; NR
-// sources per lane, a chunk runs if any of its sources has the flag
-template <int NR>
+// sources per lane, a chunk runs if any of its sources has the flag; r is
+// stored as S (the iteration's storage)
+template <int NR, class S>
 __global__ TM_STENCIL_R(NR, double) void k_eo_rel_resid(CgArgs a, EoCg e, const void* b64, const void* t64,
                                                        const void* y64) {
     __shared__ double sh[4];
@@ -452,12 +453,13 @@ __global__ TM_STENCIL_R(NR, double) void k_eo_rel_resid(CgArgs a, EoCg e, const 
             mul_diag(q, -a.twist);
             load_spinor<SF64, double>(field_rhs<SF64>(b64, Vs, r0 + r), Vs, h, bv);
             cx<float> rf[12];
+            const double isg = 1.0 / a.scal[r0 + r].sigma_next;  // (a power of two)
 #pragma unroll
             for (int k = 0; k < 12; k++) {
                 bv[k] = bv[k] - (q[k] + k2 * acc[r][k]);
-                rf[k] = {(float)bv[k].re, (float)bv[k].im};
+                rf[k] = {(float)(isg * bv[k].re), (float)(isg * bv[k].im)};
             }
-            store_spinor<SF32, float>(field_rhs<SF32>(a.r, Vs, r0 + r), Vs, h, rf);
+            store_spinor<S, float>(field_rhs<S>(a.r, Vs, r0 + r), Vs, h, rf);
             pr[r] += spinor_norm2(bv);
             if (a.eta64) {
                 cx<double> ev[12];
@@ -764,13 +766,24 @@ void launch_eo_upd(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int
 
 uint32_t eo_gated_blocks(const Geom& hg) { return std::min(eo_blocks(hg), kEoGatedBlocks); }
 
-void launch_eo_rel_resid(hipStream_t st, const CgArgs& a, const EoCg& e, const void* b64, const void* t64,
-                         const void* y64, int nr) {
+template <class S>
+static void eo_rel_resid_typed(hipStream_t st, const CgArgs& a, const EoCg& e, const void* b64, const void* t64,
+                               const void* y64, int nr) {
     const uint32_t nb = eo_gated_blocks(a.geo);
     if (nr == 2)
-        hipLaunchKernelGGL(k_eo_rel_resid<2>, dim3(nb, (unsigned)(a.nrhs / 2)), dim3(256), 0, st, a, e, b64, t64, y64);
+        hipLaunchKernelGGL((k_eo_rel_resid<2, S>), dim3(nb, (unsigned)(a.nrhs / 2)), dim3(256), 0, st, a, e, b64, t64,
+                           y64);
     else
-        hipLaunchKernelGGL(k_eo_rel_resid<1>, dim3(nb, (unsigned)a.nrhs), dim3(256), 0, st, a, e, b64, t64, y64);
+        hipLaunchKernelGGL((k_eo_rel_resid<1, S>), dim3(nb, (unsigned)a.nrhs), dim3(256), 0, st, a, e, b64, t64, y64);
+}
+
+void launch_eo_rel_resid(hipStream_t st, const CgArgs& a, const EoCg& e, const void* b64, const void* t64,
+                         const void* y64, int nr, int prec) {
+    switch (prec) {
+    case P_F16: eo_rel_resid_typed<SF16>(st, a, e, b64, t64, y64, nr); break;
+    case P_BF16: eo_rel_resid_typed<SBF16>(st, a, e, b64, t64, y64, nr); break;
+    default: eo_rel_resid_typed<SF32>(st, a, e, b64, t64, y64, nr); break;
+    }
 }
 
 }  // namespace tmq

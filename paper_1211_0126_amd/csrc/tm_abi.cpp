@@ -717,8 +717,8 @@ tm_status tm_profile_entries(tm_ctx* ctx, tm_profile_entry* out, int32_t cap, in
         e.prec = tag < 0 ? -1 : (tag & 15);
         e.lane_rhs = tag < 0 ? -1 : ((tag >> 4) & 15);
         e.solver = tag < 0 ? -1 : ((tag >> 8) & 15);
-        e.tseg = tag < 0 ? -1 : (tag >> 12);
-        e.reserved = 0;
+        e.tseg = tag < 0 ? -1 : ((tag >> 12) & 255);
+        e.reliable = tag < 0 ? -1 : ((tag >> 20) & 1);
         e.launches = kv.second.launches;
         e.ms = kv.second.ms;
         e.bytes = kv.second.bytes;

@@ -167,8 +167,8 @@ tm_status copy_sync(tm_ctx* ctx, void* dst, const void* src, size_t bytes, hipMe
 // instrumentation around a launch of kernel class kc moving `bytes`
 // tag: prof_tag(prec, lane_rhs, solver) of the launched kernel, -1 if none
 void prof_begin(tm_ctx* ctx, int kc, int tag = -1);
-inline int prof_tag(int prec, int lane_rhs, int solver, int tseg = 0) {
-    return prec | (lane_rhs << 4) | (solver << 8) | (tseg << 12);
+inline int prof_tag(int prec, int lane_rhs, int solver, int tseg = 0, bool reliable = false) {
+    return prec | (lane_rhs << 4) | (solver << 8) | (tseg << 12) | ((int)reliable << 20);
 }
 void prof_end(tm_ctx* ctx, int kc, double bytes);
 

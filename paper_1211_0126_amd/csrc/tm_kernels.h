@@ -150,7 +150,7 @@ void launch_eo_upd_xfree(hipStream_t st, const CgArgs& a, const EoCg& e, int pre
 void launch_eo_xflush(hipStream_t st, const CgArgs& a, int prec, const void* dirs, size_t slot_bytes, int k0, int k1);
 uint32_t eo_gated_blocks(const Geom& hg);
 void launch_eo_rel_resid(hipStream_t st, const CgArgs& a, const EoCg& e, const void* b64, const void* t64,
-                         const void* y64, int nr);
+                         const void* y64, int nr, int prec = P_F32);
 // the same half-hops with the links of a tile of 64 half-sites staged in LDS
 // and shared by all right-hand sides (FP32 links; FP32/FP16/BF16 storage);
 // reductions write eot_tiles(hg) partials per right-hand side
@@ -190,7 +190,9 @@ void launch_tm_upd(hipStream_t st, const CgArgs& a, int prec, int nr, bool track
 void launch_cg_alpha(hipStream_t st, const CgArgs& a);              // after launch_cg_mp
 void launch_cg_beta(hipStream_t st, const CgArgs& a, bool track);   // after launch_cg_upd
 void launch_cg_p(hipStream_t st, const CgArgs& a, int prec);
-void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64, double ee_z4 = -1.0);
+// (prec: storage of r and p; x stays FP32)
+void launch_rel_init(hipStream_t st, const CgArgs& a, const void* b64, void* x64, double ee_z4 = -1.0,
+                     int prec = P_F32);
 void launch_rel_fin(hipStream_t st, const CgArgs& a, uint32_t nb);
 void launch_rel_flush(hipStream_t st, const CgArgs& a, void* x64, int force);
 void launch_rel_resid(hipStream_t st, const CgArgs& a, const void* gauge64, const void* b64, const void* t64);

@@ -46,8 +46,11 @@ static tm_status check_solve_params(tm_ctx* ctx, const tsm_solve_params* p) {
     if (p->stop != TM_STOP_NORMAL && p->stop != TM_STOP_TRUE) return set_error(ctx, TM_EINVAL, "solve: bad stop");
     if (p->reliable != 0 && p->reliable != 1) return set_error(ctx, TM_EINVAL, "solve: bad reliable flag");
     if (p->reliable) {
-        if (p->prec != TM_PREC_F32)
-            return set_error(ctx, TM_ENOTSUP, "solve: reliable updates need FP32 iterations");
+        // FP32 iterations; FP32, FP16 or BF16 storage on the even-odd solver
+        if (p->prec == TM_PREC_F64 || (p->prec != TM_PREC_F32 && p->solver != TM_SOLVER_CG_EO))
+            return set_error(ctx, TM_ENOTSUP,
+                             "solve: reliable updates need FP32 iterations (FP32 storage, or FP32/FP16/BF16 on the "
+                             "even-odd solver)");
         if (!(p->delta > 0 && p->delta < 1)) return set_error(ctx, TM_EINVAL, "solve: delta must be in (0, 1)");
     }
     if (p->rhs_block < 0 || p->rhs_block > kMaxBlock) return set_error(ctx, TM_EINVAL, "solve: rhs_block in 0..32");
@@ -481,7 +484,7 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
         if (rel) {
             launch_eo_lin(st, lin(1, true, ys, b64, eh, k2, nrhs), P_F64, nr64, EO_T_DAG);
             if (p->stop == TM_STOP_TRUE) a.eta64 = eh;
-            launch_rel_init(st, a, b64, x64, ee_z4);
+            launch_rel_init(st, a, b64, x64, ee_z4, prec);
         } else {
             launch_eo_lin(st, lin(1, false, ys, a.r, eh, k2, nrhs), prec, snr, EO_T_DAG);
             CgArgs ai = a;
@@ -501,7 +504,7 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     ec64.godd = g64o;
     ec64.y = y64;
     const CgArgs a0 = a;
-    const int vtag = prof_tag(prec, prec == P_F64 ? 1 : nr, TM_SOLVER_CG_EO, 0);
+    const int vtag = prof_tag(prec, prec == P_F64 ? 1 : nr, TM_SOLVER_CG_EO, 0, rel);
     const int dflt = rel ? 16 : 8;
     const std::string ckey = chunk_key(p, tag, nrhs);
     int chunk = first_chunk(ctx, ckey, dflt);
@@ -588,11 +591,11 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
                     EoArgs e3 = lin(0, true, t64, y64, nullptr, 1.0, nrhs);
                     e3.gate = a.scal;
                     launch_eo_lin(st, e3, P_F64, nr64, EO_Y_DAG);
-                    launch_eo_rel_resid(st, a, ec64, b64, t64, y64, nr64);
+                    launch_eo_rel_resid(st, a, ec64, b64, t64, y64, nr64, prec);
                     launch_rel_fin(st, a, eo_gated_blocks(hg));
                     prof_end(ctx, TM_KC_OTHER, 0.0);
                 }
-                prof_begin(ctx, TM_KC_BLAS, prof_tag(prec, 1, TM_SOLVER_CG_EO));
+                prof_begin(ctx, TM_KC_BLAS, prof_tag(prec, 1, TM_SOLVER_CG_EO, 0, rel));
                 launch_cg_p(st, a, prec);
                 prof_end(ctx, TM_KC_BLAS, by.p);
             }
@@ -865,7 +868,7 @@ static void fill_stats(const CgScal& q, tsm_solve_stats* o) {
     if (q.stop == 1)
         o->resid_iterated = q.ee > 0 ? std::sqrt(q.rho2 / q.ee) : 0.0;
     else
-        o->resid_iterated = q.bb > 0 ? std::sqrt(q.rr / q.bb) : 0.0;
+        o->resid_iterated = q.bb > 0 ? std::sqrt(q.rr / q.bb) * (q.reliable ? q.sigma : 1.0) : 0.0;
     o->resid_true = q.resid_true;
 }
 

@@ -20,6 +20,14 @@ struct CgScal {
     double tol2;    // tol^2
     double delta2;  // reliable-update threshold squared
     double resid_true;  // FP64 |eta - M x| / |eta| (filled at the end)
+    // Reliable mode: the stored r and p are the true ones divided by sigma,
+    // a power of two chosen at each reliable update so that the stored
+    // residual starts every cycle at the scale of the source (the recursion
+    // is invariant under a common scale of r and p; x32 accumulates alpha p
+    // of the stored p and is added to x64 times sigma).  rr and maxrr are in
+    // stored units, bb, rho2 and ee in true units.
+    double sigma;
+    double sigma_next;  // the scale of the residual stored by the pending update
     int32_t maxit;  // -1: no cap
     int32_t iters;
     int32_t active;     // 1 while iterating

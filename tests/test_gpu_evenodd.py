@@ -115,6 +115,36 @@ def test_eo_fp32_reliable_hp(orc, delta):
     ctx.close()
 
 
+@pytest.mark.parametrize("delta", [0.1, 1e-2])
+@pytest.mark.parametrize("prec", [2, 3])
+def test_eo_half_storage_reliable_hp(orc, prec, delta):
+    """FP16 / BF16 storage of the iteration vectors (FP32 arithmetic) with
+    FP64 reliable updates, stopped on the FP64 true residual: converged to
+    1e-10 (checked with the oracle's operator), the oracle's solution to
+    1e-8, at most half again the oracle's iterations."""
+    import paper_1211_0126_amd as tq
+    dims, kappa, mu, eps = LATTICES[3]
+    U = make_gauge(dims, eps, 1002)
+    ctx = _ctx(dims, kappa, mu, U)
+    ids = [0, 1, 2, 3]
+    p = tq.solve_params(prec=prec, tol=1e-10, max_iter=400, reliable=1, delta=delta, rhs_block=4,
+                        stop=tq.STOP_TRUE, solver=tq.SOLVER_CG_EO)
+    sol, st, _ = tq.tsm_solve_batch(ctx, p, 9, ids)
+    sol = sol.cpu().numpy()
+    for i, j in enumerate(ids):
+        eta = orc.noise_z4(dims, 9, j)
+        x, so = orc.cgnr_eo(dims, -1, kappa, mu, U, eta, 1e-10, -1, tq.STOP_TRUE)
+        mx = orc.apply_op(dims, -1, kappa, mu, orc.OP_M, U, sol[i])
+        true = np.linalg.norm((eta - mx).ravel()) / np.linalg.norm(eta.ravel())
+        print("prec %d delta %g source %d: iters %d (oracle %d), true residual %.3g (reported %.3g)"
+              % (prec, delta, j, st[i]["iters"], so["iters"], true, st[i]["resid_true"]))
+        assert st[i]["converged"], st[i]
+        assert st[i]["iters"] <= 1.5 * so["iters"] + 2
+        assert st[i]["resid_true"] <= 1e-10 and true <= 1.01e-10
+        assert _rel(sol[i], x) < 1e-8
+    ctx.close()
+
+
 @pytest.mark.parametrize("tiles", [0, 1])
 @pytest.mark.parametrize("prec", [1, 2, 3])
 def test_eo_reduced_precision_lp(orc, prec, tiles):
