@@ -23,7 +23,11 @@
 //   B: sum over x with the x phases
 //   C: sum over z with the z phases and the Gamma traces (each Gamma_n is
 //      a phase-signed permutation: 4 terms)
-// All sums are in FP64 and in a fixed order (bitwise reproducible).
+// The sums are in FP64, except stage A of the standard loop of an FP32
+// solution: its products with the noise are exact in FP32 and its y sums
+// (Ly terms) are taken in FP32, about 1e-7 relative, far below the FP32
+// solution's own rounding.  Every sum runs in a fixed order (bitwise
+// reproducible).
 
 #include <type_traits>
 
@@ -54,13 +58,31 @@ __device__ __forceinline__ void load_half_spinor<SF32>(const void* base, long Vs
     }
 }
 
+// the six components of spin rows 2h, 2h+1 in arithmetic A (FP32 only from
+// an FP32 field)
+template <class S, typename A>
+__device__ __forceinline__ void load_half_spinor_as(const void* base, long Vs, uint32_t s, int h, cx<A> p[6]) {
+    if constexpr (std::is_same<A, double>::value) {
+        load_half_spinor<S>(base, Vs, s, h, p);
+    } else {
+        static_assert(std::is_same<S, SF32>::value, "FP32 sums read FP32 solutions");
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            float4 v = ld_plane<float4>(base, Vs, 3 * h + k, s);
+            p[2 * k] = {v.x, v.y};
+            p[2 * k + 1] = {v.z, v.w};
+        }
+    }
+}
+
 // conj(i^k) p for a Z4 noise component i^k: a permutation and signs
-__device__ __forceinline__ cx<double> z4_conj_times(uint32_t k, cx<double> p) {
-    const double re = (k & 1u) ? p.im : p.re;
-    const double im = (k & 1u) ? p.re : p.im;
+template <typename A>
+__device__ __forceinline__ cx<A> z4_conj_times(uint32_t k, cx<A> p) {
+    const A re = (k & 1u) ? p.im : p.re;
+    const A im = (k & 1u) ? p.re : p.im;
     // k = 0: (re, im); 1: (im, -re); 2: (-re, -im); 3: (-im, re)
-    const double sr = (k == 2u || k == 3u) ? -1.0 : 1.0;
-    const double si = (k == 1u || k == 2u) ? -1.0 : 1.0;
+    const A sr = (k == 2u || k == 3u) ? (A)-1 : (A)1;
+    const A si = (k == 1u || k == 2u) ? (A)-1 : (A)1;
     return {sr * re, si * im};
 }
 
@@ -81,25 +103,27 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
     const int npy = a.npy;
     const void* sol = field_rhs<S>(a.sol, g.Vs, r);
     const uint64_t id = a.ids[r];
-    cx<double> acc[3][8];
+    // the y sums of the standard loop of an FP32 solution in FP32
+    using A = typename std::conditional<E == 0 && std::is_same<S, SF32>::value, float, double>::type;
+    cx<A> acc[3][8];
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
-        for (int e = 0; e < 8; e++) acc[i][e] = {0.0, 0.0};
+        for (int e = 0; e < 8; e++) acc[i][e] = {(A)0, (A)0};
     // four sites of the row in flight per lane
 #pragma unroll 4
     for (int y = 0; y < Ly; y++) {
         const uint32_t s = x + Lx * (y + Ly * (z + Lz * t));
-        cx<double> S8[8];
+        cx<A> S8[8];
         if constexpr (E == 0) {
-            cx<double> p[6];
-            load_half_spinor<S>(sol, g.Vs, s, h, p);
+            cx<A> p[6];
+            load_half_spinor_as<S, A>(sol, g.Vs, s, h, p);
             const uint64_t bits = noise_bits(a.seed_mixed, id, (uint64_t)g.V, (uint64_t)s);
 #pragma unroll
             for (int b = 0; b < 2; b++)
 #pragma unroll
                 for (int al = 0; al < 4; al++) {
-                    cx<double> v = {0.0, 0.0};
+                    cx<A> v = {(A)0, (A)0};
 #pragma unroll
                     for (int c = 0; c < 3; c++)
                         v = v + z4_conj_times((uint32_t)(bits >> (2 * (3 * al + c))) & 3u, p[3 * b + c]);
@@ -132,7 +156,7 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
         for (int i = 0; i < 3; i++) {
             if (i < npy) {
                 const double2 ph = a.phy[i * Ly + y];
-                const cx<double> w = {ph.x, ph.y};
+                const cx<A> w = {(A)ph.x, (A)ph.y};
 #pragma unroll
                 for (int e = 0; e < 8; e++) acc[i][e] = acc[i][e] + w * S8[e];
             }
@@ -145,7 +169,7 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
         if (i < npy) {
             double2* o = a.A + (((((size_t)r * Lt + t) * Lz + z) * npy + i) * Lx + x) * 16 + 8 * h;
 #pragma unroll
-            for (int e = 0; e < 8; e++) o[e] = make_double2(acc[i][e].re, acc[i][e].im);
+            for (int e = 0; e < 8; e++) o[e] = make_double2((double)acc[i][e].re, (double)acc[i][e].im);
         }
     }
 }
