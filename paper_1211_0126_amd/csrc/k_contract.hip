@@ -86,7 +86,9 @@ __device__ __forceinline__ cx<A> z4_conj_times(uint32_t k, cx<A> p) {
     return {sr * re, si * im};
 }
 
-template <class S, int E>
+// With HALVES (standard loop of an FP32 solution only): a.sol and a.sol_e
+// hold the odd and even half of each solution in the half layout of a.hgeo.
+template <class S, int E, bool HALVES = false>
 __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
     const Geom& g = a.geo;
     const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
@@ -101,7 +103,9 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
     const int z = (int)(q2 % Lz);
     const int t = (int)(q2 / Lz);
     const int npy = a.npy;
-    const void* sol = field_rhs<S>(a.sol, g.Vs, r);
+    static_assert(!HALVES || (E == 0 && std::is_same<S, SF32>::value), "halves: standard loop, FP32");
+    const void* sol = field_rhs<S>(a.sol, HALVES ? a.hgeo.Vs : g.Vs, r);
+    const void* sol_e = HALVES ? field_rhs<S>(a.sol_e, a.hgeo.Vs, r) : nullptr;
     const uint64_t id = a.ids[r];
     // the y sums of the standard loop of an FP32 solution in FP32
     using A = typename std::conditional<E == 0 && std::is_same<S, SF32>::value, float, double>::type;
@@ -117,7 +121,12 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
         cx<A> S8[8];
         if constexpr (E == 0) {
             cx<A> p[6];
-            load_half_spinor_as<S, A>(sol, g.Vs, s, h, p);
+            if constexpr (HALVES) {
+                const uint32_t hs = s >> 1;  // x/2 + (Lx/2)(y + Ly(z + Lz t)): Lx is even
+                load_half_spinor_as<S, A>(((x + y + z + t) & 1) ? sol : sol_e, a.hgeo.Vs, hs, h, p);
+            } else {
+                load_half_spinor_as<S, A>(sol, g.Vs, s, h, p);
+            }
             const uint64_t bits = noise_bits(a.seed_mixed, id, (uint64_t)g.V, (uint64_t)s);
 #pragma unroll
             for (int b = 0; b < 2; b++)
@@ -401,6 +410,8 @@ void launch_contract(hipStream_t st, const ContractArgs& a0, int xprec) {
         run_a(std::integral_constant<int, 1>{});
     else if (a.est == 2)
         run_a(std::integral_constant<int, 2>{});
+    else if (a.est == 0 && a0.sol_e != nullptr)
+        hipLaunchKernelGGL((k_contract_a<SF32, 0, true>), ga, dim3(256), 0, st, a0);
     else if (a.est == 0)
         run_a(std::integral_constant<int, 0>{});
     const long nb = 16L * a.npy * g.L[2] * g.L[3];

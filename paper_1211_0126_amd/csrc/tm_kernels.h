@@ -37,7 +37,9 @@ struct ContractArgs {
     Geom geo;
     uint64_t seed_mixed;
     const uint64_t* ids;  // [nrhs] source ids (device)
-    const void* sol;      // native solutions (F64 or F32 storage)
+    const void* sol;      // native solutions (F64 or F32 storage), or with sol_e the FP32 odd halves
+    const void* sol_e;    // (nullable) the FP32 even halves: the solutions in the half layout of hgeo
+    Geom hgeo;            // the half-lattice geometry (with sol_e)
     const void* dsol;     // est 2: native FP64 D s = (1 - kappa H) s of the same sources
     int est;              // 0 eta^dag Gamma s; 1, 2 the one-end loops (Eqs. 5, 6)
     double2 coef;         // factor of every loop element (1; -2i 2 kappa mu; 2)

@@ -139,8 +139,9 @@ static CgBytes cg_bytes(const Geom& g, int prec, int nrhs, bool reliable_x64, bo
 }
 
 struct BlockResult {
-    void* x;
+    void* x;             // the native solutions, or with xe their FP32 odd halves
     int xprec;
+    void* xe = nullptr;  // (halves only) the FP32 even halves
 };
 
 // Flexible CG with the network preconditioner for a block of sources; the
@@ -348,9 +349,11 @@ static EoBytes eo_bytes(const Geom& hg, int prec, int nrhs, bool track, bool xfr
 // half-hops per iteration), then x_e = D^{-1} (eta_e + kappa H_eo x_o) and
 // the full native solution in res.  Reliable updates recompute
 // r = b - Mhat^dag Mhat x in FP64 on the half lattice.
+// halves: the caller can take the solution as its two FP32 halves (the
+// standard loop's contraction), which saves writing the full native field
 static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t seed_mixed,
                                 const uint64_t* ids_dev, int nrhs, int nr, const std::string& tag,
-                                BlockResult* res) {
+                                BlockResult* res, bool halves) {
     const Geom& g = ctx->geo;
     const Geom& hg = ctx->hgeo;
     hipStream_t st = ctx->stream;
@@ -637,8 +640,32 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
     if (ringm) flush(done);
 
     // even half x_e = D^{-1} (eta_e + kappa H_eo x_o) with eta_e from the
-    // hash, then the full native solution
+    // hash, then the full native solution (or, for a caller that takes the
+    // halves, x_e alone beside the odd half x)
     prof_begin(ctx, TM_KC_OTHER);
+    const bool to_halves = halves && !rel && !tiles && prec != P_F64 && !p->true_resid;
+    if (to_halves) {
+        EoArgs e = lin(0, false, a.x, xfull, nullptr, kappa, nrhs);
+        e.gout = g32e;
+        e.gin = g32o;
+        e.bnoise = 1;
+        for (int j0 = 0; j0 < nrhs; j0 += kRecSub) {
+            EoArgs es = e;
+            es.in = (const char*)a.x + field_bytes(hg, P_F32, j0);
+            es.out = (char*)xfull + field_bytes(hg, P_F32, j0);
+            es.ids = ids_dev + j0;
+            es.nrhs = std::min(kRecSub, nrhs - j0);
+            launch_eo_lin(st, es, P_F32, nr, EO_REC);
+        }
+        prof_end(ctx, TM_KC_OTHER, 0.0);
+        res->x = a.x;
+        res->xe = xfull;  // (the even halves fill the front of the full buffer)
+        res->xprec = P_F32;
+        TM_HIP(hipGetLastError());
+        TM_HIP(hipMemcpyAsync(ctx->scal_host, a.scal, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        return TM_OK;
+    }
     if (rel) {
         launch_rel_flush(st, a, x64, 1);
         launch_eo_rec_full(st, lin(0, true, x64, nullptr, nullptr, kappa, nrhs), P_F64, nr64, g, xfull);
@@ -684,9 +711,9 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
 // return the stream is synchronised, ctx->scal_host[0..nrhs) holds the final
 // per-source state and res the native solutions.
 static tm_status solve_block(tm_ctx* ctx, const tsm_solve_params* p, uint64_t seed_mixed, const uint64_t* ids_dev,
-                             int nrhs, int nr, const std::string& tag, BlockResult* res) {
+                             int nrhs, int nr, const std::string& tag, BlockResult* res, bool halves = false) {
     if (p->solver == TM_SOLVER_FCG_LEARNED) return solve_block_fcg(ctx, p, seed_mixed, ids_dev, nrhs, nr, tag, res);
-    if (p->solver == TM_SOLVER_CG_EO) return solve_block_eo(ctx, p, seed_mixed, ids_dev, nrhs, nr, tag, res);
+    if (p->solver == TM_SOLVER_CG_EO) return solve_block_eo(ctx, p, seed_mixed, ids_dev, nrhs, nr, tag, res, halves);
     const Geom& g = ctx->geo;
     hipStream_t st = ctx->stream;
     tm_status s = TM_OK;
@@ -964,10 +991,12 @@ static tm_status setup_contract(tm_ctx* ctx, const MomPlan& mp, int n_mom, int m
 }
 
 static void contract_block(tm_ctx* ctx, Contractor* c, const uint64_t* ids_dev, const void* x, int xprec, int nrhs,
-                           double2* out, const int* slots_dev, long out_stride) {
+                           double2* out, const int* slots_dev, long out_stride, const void* xe = nullptr) {
     ContractArgs a = c->a;
     a.ids = ids_dev;
     a.sol = x;
+    a.sol_e = xe;  // (x and xe the FP32 halves; standard loop only)
+    a.hgeo = ctx->hgeo;
     a.nrhs = nrhs;
     a.out = out;
     a.out_slot = slots_dev;
@@ -1358,6 +1387,8 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double
     };
     if (stats_host) std::memset(stats_host, 0, sizeof(tsm_solve_stats) * 2 * N);
 
+    // the standard loop takes the LP solutions as their two halves
+    const bool halves = P->estimator == TM_LOOP_STANDARD;
     auto t0 = clk::now();
     // HP set: LP and HP solves of ids 0..n_hp-1
     const int bh = std::min(blp, bhp);
@@ -1365,9 +1396,9 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double
         const int nb = std::min(bh, P->n_hp - j0);
         BlockResult res;
         const int nbl = (nb + nr_lp - 1) / nr_lp * nr_lp;
-        if ((s = solve_block(ctx, &P->lp, sm, ids_dev + j0, nbl, nr_lp, "lp", &res)) != TM_OK) return s;
+        if ((s = solve_block(ctx, &P->lp, sm, ids_dev + j0, nbl, nr_lp, "lp", &res, halves)) != TM_OK) return s;
         record(j0, nb, 0, false);
-        contract_block(ctx, &c, ids_dev + j0, res.x, res.xprec, nb, (double2*)ps, slots_dev + j0, nl);
+        contract_block(ctx, &c, ids_dev + j0, res.x, res.xprec, nb, (double2*)ps, slots_dev + j0, nl, res.xe);
         const int nbh = (nb + nr_hp - 1) / nr_hp * nr_hp;
         if ((s = solve_block(ctx, &P->hp, sm, ids_dev + j0, nbh, nr_hp, "hp", &res)) != TM_OK) return s;
         record(j0, nb, 1, true);
@@ -1381,9 +1412,9 @@ tm_status tsm_loops(tm_ctx* ctx, const tsm_params* P, double* loops_host, double
         const int nb = std::min(blp, N - j0);
         const int nbl = (nb + nr_lp - 1) / nr_lp * nr_lp;
         BlockResult res;
-        if ((s = solve_block(ctx, &P->lp, sm, ids_dev + j0, nbl, nr_lp, "lp", &res)) != TM_OK) return s;
+        if ((s = solve_block(ctx, &P->lp, sm, ids_dev + j0, nbl, nr_lp, "lp", &res, halves)) != TM_OK) return s;
         record(j0, nb, 0, false);
-        contract_block(ctx, &c, ids_dev + j0, res.x, res.xprec, nb, (double2*)ps, slots_dev + j0, nl);
+        contract_block(ctx, &c, ids_dev + j0, res.x, res.xprec, nb, (double2*)ps, slots_dev + j0, nl, res.xe);
         TM_HIP(hipGetLastError());
     }
     launch_tsm_final(st, ps, nl, P->n_hp, P->n_lp, fin, fin + 2 * 3 * nl);
