@@ -64,8 +64,20 @@ template <class S, typename A>
 __device__ __forceinline__ void load_half_spinor_as(const void* base, long Vs, uint32_t s, int h, cx<A> p[6]) {
     if constexpr (std::is_same<A, double>::value) {
         load_half_spinor<S>(base, Vs, s, h, p);
+    } else if constexpr (std::is_same<S, SF16>::value) {
+        // components 6h .. 6h + 5 of the planes of four packed pairs
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const uint4 v = ld_plane<uint4>(base, Vs, (6 * h) / 4 + k, s);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int c = 4 * ((6 * h) / 4 + k) + j - 6 * h;
+                if (c >= 0 && c < 6) p[c] = {f16_to_f32(w[j] & 0xFFFFu), f16_to_f32(w[j] >> 16)};
+            }
+        }
     } else {
-        static_assert(std::is_same<S, SF32>::value, "FP32 sums read FP32 solutions");
+        static_assert(std::is_same<S, SF32>::value, "FP32 sums read FP32 or FP16 solutions");
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             float4 v = ld_plane<float4>(base, Vs, 3 * h + k, s);
@@ -86,8 +98,9 @@ __device__ __forceinline__ cx<A> z4_conj_times(uint32_t k, cx<A> p) {
     return {sr * re, si * im};
 }
 
-// With HALVES (standard loop of an FP32 solution only): a.sol and a.sol_e
-// hold the odd and even half of each solution in the half layout of a.hgeo.
+// With HALVES (standard loop of an FP32 or FP16 solution only): a.sol and
+// a.sol_e hold the odd and even half of each solution in the half layout of
+// a.hgeo.
 template <class S, int E, bool HALVES = false>
 __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
     const Geom& g = a.geo;
@@ -103,12 +116,14 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
     const int z = (int)(q2 % Lz);
     const int t = (int)(q2 / Lz);
     const int npy = a.npy;
-    static_assert(!HALVES || (E == 0 && std::is_same<S, SF32>::value), "halves: standard loop, FP32");
+    static_assert(!HALVES || (E == 0 && (std::is_same<S, SF32>::value || std::is_same<S, SF16>::value)),
+                  "halves: standard loop, FP32 or FP16");
     const void* sol = field_rhs<S>(a.sol, HALVES ? a.hgeo.Vs : g.Vs, r);
     const void* sol_e = HALVES ? field_rhs<S>(a.sol_e, a.hgeo.Vs, r) : nullptr;
     const uint64_t id = a.ids[r];
     // the y sums of the standard loop of an FP32 solution in FP32
-    using A = typename std::conditional<E == 0 && std::is_same<S, SF32>::value, float, double>::type;
+    using A = typename std::conditional<E == 0 && (std::is_same<S, SF32>::value || std::is_same<S, SF16>::value),
+                                        float, double>::type;
     cx<A> acc[3][8];
 #pragma unroll
     for (int i = 0; i < 3; i++)
@@ -410,6 +425,8 @@ void launch_contract(hipStream_t st, const ContractArgs& a0, int xprec) {
         run_a(std::integral_constant<int, 1>{});
     else if (a.est == 2)
         run_a(std::integral_constant<int, 2>{});
+    else if (a.est == 0 && a0.sol_e != nullptr && xprec == P_F16)
+        hipLaunchKernelGGL((k_contract_a<SF16, 0, true>), ga, dim3(256), 0, st, a0);
     else if (a.est == 0 && a0.sol_e != nullptr)
         hipLaunchKernelGGL((k_contract_a<SF32, 0, true>), ga, dim3(256), 0, st, a0);
     else if (a.est == 0)

@@ -384,14 +384,16 @@ __global__ TM_STENCIL_R(NR, R) void k_eo_upd(CgArgs a, EoCg e) {
 
 // x += sum over iterations k0 <= k < min(k1, iterations done) of alpha_k p_k,
 // p_k in slot k % ring of dirs (FP32 x, directions of storage S); the first
-// pass (k0 = 0) writes x = the sum (x is not initialised before)
-template <class S>
-__global__ __launch_bounds__(256) void k_eo_xflush(CgArgs a, const void* dirs, size_t slot_bytes, int k0, int k1) {
+// pass (k0 = 0) writes x = the sum (x is not initialised before).  The
+// result goes to out as XO (the last pass may hand x over in FP16).
+template <class S, class XO>
+__global__ __launch_bounds__(256) void k_eo_xflush(CgArgs a, const void* dirs, size_t slot_bytes, int k0, int k1,
+                                                   void* out) {
     const uint32_t h = blockIdx.x * 256u + threadIdx.x;
     const int r = blockIdx.y;
     if (h >= a.geo.V) return;
     const int kend = min(k1, (int)a.scal[r].iters);
-    if (kend <= k0 && k0 > 0) return;
+    if (kend <= k0 && k0 > 0 && out == a.x) return;  // (nothing to add in place)
     const long Vs = a.geo.Vs;
     cx<float> xv[12];
     void* xp = field_rhs<SF32>(a.x, Vs, r);
@@ -409,7 +411,7 @@ __global__ __launch_bounds__(256) void k_eo_xflush(CgArgs a, const void* dirs, s
 #pragma unroll
         for (int c = 0; c < 12; c++) xv[c] = {xv[c].re + al * pv[c].re, xv[c].im + al * pv[c].im};
     }
-    store_spinor_cp<SF32, float, kStream>(xp, Vs, h, xv);
+    store_spinor_cp<XO, float, kStream>(field_rhs<XO>(out, Vs, r), Vs, h, xv);
 }
 
 // Reliable update (gated, FP64): r64 = b64 - (D^dag t64 - kappa^2 H_oe^dag
@@ -737,13 +739,30 @@ void launch_eo_upd_xfree(hipStream_t st, const CgArgs& a, const EoCg& e, int pre
     }
 }
 
-void launch_eo_xflush(hipStream_t st, const CgArgs& a, int prec, const void* dirs, size_t slot_bytes, int k0, int k1) {
+template <class XO>
+static void eo_xflush_out(hipStream_t st, const CgArgs& a, int prec, const void* dirs, size_t slot_bytes, int k0,
+                          int k1, void* out) {
     const dim3 grid(eo_blocks(a.geo), (unsigned)a.nrhs);
     switch (prec) {
-    case P_F32: hipLaunchKernelGGL(k_eo_xflush<SF32>, grid, dim3(256), 0, st, a, dirs, slot_bytes, k0, k1); break;
-    case P_F16: hipLaunchKernelGGL(k_eo_xflush<SF16>, grid, dim3(256), 0, st, a, dirs, slot_bytes, k0, k1); break;
-    default: hipLaunchKernelGGL(k_eo_xflush<SBF16>, grid, dim3(256), 0, st, a, dirs, slot_bytes, k0, k1); break;
+    case P_F32:
+        hipLaunchKernelGGL((k_eo_xflush<SF32, XO>), grid, dim3(256), 0, st, a, dirs, slot_bytes, k0, k1, out);
+        break;
+    case P_F16:
+        hipLaunchKernelGGL((k_eo_xflush<SF16, XO>), grid, dim3(256), 0, st, a, dirs, slot_bytes, k0, k1, out);
+        break;
+    default:
+        hipLaunchKernelGGL((k_eo_xflush<SBF16, XO>), grid, dim3(256), 0, st, a, dirs, slot_bytes, k0, k1, out);
+        break;
     }
+}
+
+void launch_eo_xflush(hipStream_t st, const CgArgs& a, int prec, const void* dirs, size_t slot_bytes, int k0, int k1,
+                      void* out, int out_prec) {
+    if (out == nullptr) out = a.x;
+    if (out_prec == P_F16)
+        eo_xflush_out<SF16>(st, a, prec, dirs, slot_bytes, k0, k1, out);
+    else
+        eo_xflush_out<SF32>(st, a, prec, dirs, slot_bytes, k0, k1, out);
 }
 
 void launch_eo_mp(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr) {

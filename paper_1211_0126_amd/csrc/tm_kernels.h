@@ -37,8 +37,8 @@ struct ContractArgs {
     Geom geo;
     uint64_t seed_mixed;
     const uint64_t* ids;  // [nrhs] source ids (device)
-    const void* sol;      // native solutions (F64 or F32 storage), or with sol_e the FP32 odd halves
-    const void* sol_e;    // (nullable) the FP32 even halves: the solutions in the half layout of hgeo
+    const void* sol;      // native solutions (F64 or F32 storage), or with sol_e the odd halves
+    const void* sol_e;    // (nullable) the even halves (FP32 or FP16): the solutions in the half layout of hgeo
     Geom hgeo;            // the half-lattice geometry (with sol_e)
     const void* dsol;     // est 2: native FP64 D s = (1 - kappa H) s of the same sources
     int est;              // 0 eta^dag Gamma s; 1, 2 the one-end loops (Eqs. 5, 6)
@@ -149,7 +149,9 @@ void launch_eo_upd(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int
 // update x += sum_k alpha_k p_k over iterations k0 <= k < min(k1, iterations
 // of the source), p_k in slot k % ring of `dirs` (slot_bytes apart)
 void launch_eo_upd_xfree(hipStream_t st, const CgArgs& a, const EoCg& e, int prec, int nr, bool track);
-void launch_eo_xflush(hipStream_t st, const CgArgs& a, int prec, const void* dirs, size_t slot_bytes, int k0, int k1);
+// (the sum is written to out in out_prec, P_F32 or P_F16; out nullptr: a.x)
+void launch_eo_xflush(hipStream_t st, const CgArgs& a, int prec, const void* dirs, size_t slot_bytes, int k0, int k1,
+                      void* out = nullptr, int out_prec = P_F32);
 uint32_t eo_gated_blocks(const Geom& hg);
 void launch_eo_rel_resid(hipStream_t st, const CgArgs& a, const EoCg& e, const void* b64, const void* t64,
                          const void* y64, int nr, int prec = P_F32);

@@ -637,13 +637,37 @@ static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t
         if (done >= kIterCap) break;
     }
     remember_chunk(ctx, ckey, nrhs);
-    if (ringm) flush(done);
+    // a caller that takes the halves of an FP16 solve gets them in FP16: the
+    // last pass over the kept directions writes x_o in FP16 into y (free now)
+    const bool to_halves = halves && !rel && !tiles && prec != P_F64 && !p->true_resid;
+    const bool halves16 = to_halves && ringm && prec == P_F16;
+    if (halves16) {
+        prof_begin(ctx, TM_KC_OTHER);
+        launch_eo_xflush(st, a, prec, dirs, fbh, k0, done, y, P_F16);
+        prof_end(ctx, TM_KC_OTHER, 0.0);
+        k0 = done;
+    } else if (ringm) {
+        flush(done);
+    }
 
     // even half x_e = D^{-1} (eta_e + kappa H_eo x_o) with eta_e from the
     // hash, then the full native solution (or, for a caller that takes the
     // halves, x_e alone beside the odd half x)
     prof_begin(ctx, TM_KC_OTHER);
-    const bool to_halves = halves && !rel && !tiles && prec != P_F64 && !p->true_resid;
+    if (halves16) {
+        // x_e in FP16 by the FP16 half-hop, both halves handed over in FP16
+        EoArgs e = lin(0, false, y, xfull, nullptr, kappa, nrhs);
+        e.bnoise = 1;
+        launch_eo_lin(st, e, P_F16, nr, EO_REC);
+        prof_end(ctx, TM_KC_OTHER, 0.0);
+        res->x = y;
+        res->xe = xfull;
+        res->xprec = P_F16;
+        TM_HIP(hipGetLastError());
+        TM_HIP(hipMemcpyAsync(ctx->scal_host, a.scal, sizeof(CgScal) * nrhs, hipMemcpyDeviceToHost, st));
+        TM_HIP(hipStreamSynchronize(st));
+        return TM_OK;
+    }
     if (to_halves) {
         EoArgs e = lin(0, false, a.x, xfull, nullptr, kappa, nrhs);
         e.gout = g32e;
@@ -1001,7 +1025,7 @@ static void contract_block(tm_ctx* ctx, Contractor* c, const uint64_t* ids_dev, 
     a.out = out;
     a.out_slot = slots_dev;
     a.out_stride = out_stride;
-    const double sb = (double)ctx->geo.V * nrhs * 24.0 * (xprec == P_F64 ? 8 : 4);
+    const double sb = (double)ctx->geo.V * nrhs * 24.0 * (xprec == P_F64 ? 8 : (xprec == P_F32 ? 4 : 2));
     if (a.est == 2) {
         // D s = (1 - kappa H) s: the operator at zero twist, FP64 arithmetic
         // and output on the FP64 links (FP32 solutions promote exactly)

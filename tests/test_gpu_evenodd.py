@@ -289,21 +289,24 @@ def test_eo_tsm_27_momenta_fp32(orc, tiles):
     ctx.close()
 
 
-def test_eo_tsm_fp16_lp_brick_lattice(orc):
+@pytest.mark.parametrize("lp_iters", [6, 20])
+def test_eo_tsm_fp16_lp_brick_lattice(orc, lp_iters):
     """FP16 LP solves on the brick-order lattice through the whole estimate:
-    the standard loop then contracts the two FP32 halves of each LP solution
-    (no full field is formed); against the oracle's even-odd FP64 TSM with
-    the same truncation, to FP16 storage rounding."""
+    the standard loop then contracts the two FP16 halves of each LP solution
+    (no full field is formed; with 20 iterations the solution is formed from
+    the kept directions twice in FP32 before the last pass writes it in
+    FP16); against the oracle's even-odd FP64 TSM with the same truncation,
+    to FP16 storage rounding."""
     import paper_1211_0126_amd as tq
     dims, kappa, mu, eps = LATTICES[4]
     U = make_gauge(dims, eps, 91)
     ctx = _ctx(dims, kappa, mu, U)
-    lp = tq.solve_params(prec=tq.PREC_F16, tol=0.0, max_iter=6, rhs_block=4, solver=tq.SOLVER_CG_EO)
+    lp = tq.solve_params(prec=tq.PREC_F16, tol=0.0, max_iter=lp_iters, rhs_block=4, solver=tq.SOLVER_CG_EO)
     hp = tq.solve_params(prec=tq.PREC_F16, tol=1e-10, max_iter=-1, reliable=1, delta=1e-2, rhs_block=2,
                          solver=tq.SOLVER_CG_EO)
     mom = momenta_27()
     res = tq.tsm_loops(ctx, 7, 2, 6, lp, hp, mom, per_source=True)
-    ref = orc.tsm(dims, -1, kappa, mu, U, 7, 2, 6, 0.0, 6, 1e-10, -1, mom, per_source=True, lp_eo=True,
+    ref = orc.tsm(dims, -1, kappa, mu, U, 7, 2, 6, 0.0, lp_iters, 1e-10, -1, mom, per_source=True, lp_eo=True,
                   hp_eo=True)
     scale = np.max(np.abs(ref["per_source"]))
     dev = np.max(np.abs(res["per_source"] - ref["per_source"])) / scale
