@@ -199,11 +199,11 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
 }
 
 // U psi (fwd) or U^dag psi (!fwd) of one colour vector, times ph
-__device__ __forceinline__ void su3_apply_d(const cx<double> U[3][3], bool fwd, double ph, const cx<double> v[3],
-                                            cx<double> o[3]) {
+template <typename A>
+__device__ __forceinline__ void su3_apply_d(const cx<A> U[3][3], bool fwd, A ph, const cx<A> v[3], cx<A> o[3]) {
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-        cx<double> acc = {0.0, 0.0};
+        cx<A> acc = {(A)0, (A)0};
 #pragma unroll
         for (int k = 0; k < 3; k++) acc = acc + (fwd ? U[i][k] * v[k] : cmulc(U[k][i], v[k]));
         o[i] = ph * acc;
@@ -219,8 +219,13 @@ __device__ __forceinline__ void su3_apply_d(const cx<double> U[3][3], bool fwd, 
 //                      - ph+ (U_mu(x)^dag s(x))_{bk} conj(eta_{ak}(x+mu))
 //                      + ph- (U_mu(x-mu) s(x))_{bk} conj(eta_{ak}(x-mu)) ],
 //   f = ph+ U_mu(x) s(x+mu) - ph- U_mu(x-mu)^dag s(x-mu).
+// An FP32 solution takes FP32 links and FP32 arithmetic (its y sums too,
+// about 1e-6 relative); an FP64 one FP64 throughout.
 template <class S>
 __global__ __launch_bounds__(256) void k_contract_d(ContractArgs a) {
+    using A = typename std::conditional<std::is_same<S, SF64>::value, double, float>::type;
+    using GL = typename std::conditional<std::is_same<S, SF64>::value, GF64, GF32>::type;
+    const void* gl = std::is_same<S, SF64>::value ? a.gauge64 : a.gauge32;
     const Geom& g = a.geo;
     const int Lx = g.L[0], Ly = g.L[1], Lz = g.L[2], Lt = g.L[3];
     const long nrow = (long)Lx * Lz * Lt;
@@ -240,11 +245,11 @@ __global__ __launch_bounds__(256) void k_contract_d(ContractArgs a) {
     const void* sol = field_rhs<S>(a.sol, g.Vs, r);
     const uint64_t id = a.ids[r];
     const uint64_t V = (uint64_t)g.V;
-    cx<double> acc[3][8];
+    cx<A> acc[3][8];
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
-        for (int e = 0; e < 8; e++) acc[i][e] = {0.0, 0.0};
+        for (int e = 0; e < 8; e++) acc[i][e] = {(A)0, (A)0};
     for (int y = 0; y < Ly; y++) {
         // neighbour coordinates by selects (a coordinate array indexed by mu
         // would live in scratch memory)
@@ -255,28 +260,28 @@ __global__ __launch_bounds__(256) void k_contract_d(ContractArgs a) {
         const int up = wrap_p ? 0 : cmu + 1, dn = wrap_m ? Lmu - 1 : cmu - 1;
         const uint32_t sp = (mu == 0 ? up : x) + Lx * ((mu == 1 ? up : y) + Ly * ((mu == 2 ? up : z) + Lz * (mu == 3 ? up : t)));
         const uint32_t sm = (mu == 0 ? dn : x) + Lx * ((mu == 1 ? dn : y) + Ly * ((mu == 2 ? dn : z) + Lz * (mu == 3 ? dn : t)));
-        const double php = (mu == 3 && wrap_p) ? (double)g.t_bc : 1.0;
-        const double phm = (mu == 3 && wrap_m) ? (double)g.t_bc : 1.0;
-        cx<double> S8[8];
+        const A php = (mu == 3 && wrap_p) ? (A)g.t_bc : (A)1;
+        const A phm = (mu == 3 && wrap_m) ? (A)g.t_bc : (A)1;
+        cx<A> S8[8];
 #pragma unroll
-        for (int e = 0; e < 8; e++) S8[e] = {0.0, 0.0};
-        cx<double> p0[6];
-        load_half_spinor<S>(sol, g.Vs, s0, h, p0);
+        for (int e = 0; e < 8; e++) S8[e] = {(A)0, (A)0};
+        cx<A> p0[6];
+        load_half_spinor_as<S, A>(sol, g.Vs, s0, h, p0);
         // S8[4b + al] += sgn sum_k conj(eta_{al k}) v[3b + k] for the noise
         // bits nb: each Z4 code becomes the unit (c, d) = conj(i^k) once and
         // serves both spin rows as two FP64 products
-        auto add_z4 = [&](uint64_t nb, const cx<double> v[6], double sgn) {
+        auto add_z4 = [&](uint64_t nb, const cx<A> v[6], A sgn) {
 #pragma unroll
             for (int al = 0; al < 4; al++)
 #pragma unroll
                 for (int k = 0; k < 3; k++) {
                     const uint32_t code = (uint32_t)(nb >> (2 * (3 * al + k))) & 3u;
                     // conj(i^code): 1, -i, -1, i
-                    const double c = code == 0u ? sgn : (code == 2u ? -sgn : 0.0);
-                    const double d = code == 1u ? -sgn : (code == 3u ? sgn : 0.0);
+                    const A c = code == 0u ? sgn : (code == 2u ? -sgn : (A)0);
+                    const A d = code == 1u ? -sgn : (code == 3u ? sgn : (A)0);
 #pragma unroll
                     for (int b = 0; b < 2; b++) {
-                        const cx<double> x0 = v[3 * b + k];
+                        const cx<A> x0 = v[3 * b + k];
                         S8[4 * b + al] = {S8[4 * b + al].re + (c * x0.re - d * x0.im),
                                           S8[4 * b + al].im + (c * x0.im + d * x0.re)};
                     }
@@ -286,34 +291,34 @@ __global__ __launch_bounds__(256) void k_contract_d(ContractArgs a) {
         {
             // forward hop through U_mu(x): +ph+ (U s(x+mu)) conj(eta(x)) and
             // -ph+ (U^dag s(x)) conj(eta(x+mu))
-            cx<double> U[3][3], p[6], v[6];
-            load_link<GF64, double>(a.gauge64, g.Vs, mu, s0, U);
-            load_half_spinor<S>(sol, g.Vs, sp, h, p);
+            cx<A> U[3][3], p[6], v[6];
+            load_link<GL, A>(gl, g.Vs, mu, s0, U);
+            load_half_spinor_as<S, A>(sol, g.Vs, sp, h, p);
             su3_apply_d(U, true, php, p, v);
             su3_apply_d(U, true, php, p + 3, v + 3);
-            add_z4(b0, v, 1.0);
+            add_z4(b0, v, (A)1);
             su3_apply_d(U, false, php, p0, v);
             su3_apply_d(U, false, php, p0 + 3, v + 3);
-            add_z4(noise_bits(a.seed_mixed, id, V, (uint64_t)sp), v, -1.0);
+            add_z4(noise_bits(a.seed_mixed, id, V, (uint64_t)sp), v, (A)-1);
         }
         {
             // backward hop through U_mu(x - mu): -ph- (U^dag s(x-mu)) conj(eta(x))
             // and +ph- (U s(x)) conj(eta(x-mu))
-            cx<double> U[3][3], p[6], v[6];
-            load_link<GF64, double>(a.gauge64, g.Vs, mu, sm, U);
-            load_half_spinor<S>(sol, g.Vs, sm, h, p);
+            cx<A> U[3][3], p[6], v[6];
+            load_link<GL, A>(gl, g.Vs, mu, sm, U);
+            load_half_spinor_as<S, A>(sol, g.Vs, sm, h, p);
             su3_apply_d(U, false, phm, p, v);
             su3_apply_d(U, false, phm, p + 3, v + 3);
-            add_z4(b0, v, -1.0);
+            add_z4(b0, v, (A)-1);
             su3_apply_d(U, true, phm, p0, v);
             su3_apply_d(U, true, phm, p0 + 3, v + 3);
-            add_z4(noise_bits(a.seed_mixed, id, V, (uint64_t)sm), v, 1.0);
+            add_z4(noise_bits(a.seed_mixed, id, V, (uint64_t)sm), v, (A)1);
         }
 #pragma unroll
         for (int i = 0; i < 3; i++) {
             if (i < npy) {
                 const double2 ph = a.phy[i * Ly + y];
-                const cx<double> w = {0.25 * ph.x, 0.25 * ph.y};
+                const cx<A> w = {(A)(0.25 * ph.x), (A)(0.25 * ph.y)};
 #pragma unroll
                 for (int e = 0; e < 8; e++) acc[i][e] = acc[i][e] + w * S8[e];
             }
@@ -325,7 +330,7 @@ __global__ __launch_bounds__(256) void k_contract_d(ContractArgs a) {
         if (i < npy) {
             double2* o = a.A + (((((size_t)rs * Lt + t) * Lz + z) * npy + i) * Lx + x) * 16 + 8 * h;
 #pragma unroll
-            for (int e = 0; e < 8; e++) o[e] = make_double2(acc[i][e].re, acc[i][e].im);
+            for (int e = 0; e < 8; e++) o[e] = make_double2((double)acc[i][e].re, (double)acc[i][e].im);
         }
     }
 }

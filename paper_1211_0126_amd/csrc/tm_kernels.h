@@ -44,6 +44,7 @@ struct ContractArgs {
     int est;              // 0 eta^dag Gamma s; 1, 2 the one-end loops (Eqs. 5, 6)
     double2 coef;         // factor of every loop element (1; -2i 2 kappa mu; 2)
     const void* gauge64;  // est 3: FP64 links (double2 [4][9][Vs])
+    const void* gauge32;  // est 3 of FP32 solutions: FP32 links (rows 0 and 1, float4 [4][3][Vs])
     int nmu;              // loop sets per source: 4 for est 3 (one per direction), else 1
     int nrhs;
     int npx, npy, npz;    // distinct momentum components per axis (<= 3)

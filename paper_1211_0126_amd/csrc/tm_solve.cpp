@@ -978,6 +978,7 @@ static tm_status setup_contract(tm_ctx* ctx, const MomPlan& mp, int n_mom, int m
     a.coef = est == 1 ? make_double2(0.0, -2.0 * ctx->twist) : make_double2(est == 2 ? 2.0 : 1.0, 0.0);
     a.nmu = loop_sets(est);
     a.gauge64 = ctx->gauge64;
+    a.gauge32 = ctx->gauge32;
     a.npx = mp.np[0];
     a.npy = mp.np[1];
     a.npz = mp.np[2];
