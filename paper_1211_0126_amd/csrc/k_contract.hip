@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
 #pragma unroll
                 for (int k = 0; k < 6; k++) u[k] = h ? q[6 + k] : q[k];
             } else {
-                load_half_spinor<SF64>(field_rhs<SF64>(a.dsol, g.Vs, r), g.Vs, s, h, u);
+                load_half_spinor<S>(field_rhs<S>(a.dsol, g.Vs, r), g.Vs, s, h, u);  // (D s in s's precision)
             }
 #pragma unroll
             for (int b = 0; b < 2; b++)

@@ -611,14 +611,6 @@ void launch_apply(hipStream_t st, const Geom& g, int prec, const void* gauge, do
         apply_prec<3>(st, g, prec, gauge, kappa, twist, nrhs, in, out, nr, gate);
 }
 
-void launch_apply_f32in_f64(hipStream_t st, const Geom& g, const void* gauge64, double kappa, double twist, int op,
-                            int nrhs, const void* in32, void* out64, const CgScal* gate) {
-    if (op == 0)
-        apply_nr<0, double, SF32, SF64, GF64>(st, g, gauge64, kappa, twist, nrhs, in32, out64, 1, gate);
-    else
-        apply_nr<1, double, SF32, SF64, GF64>(st, g, gauge64, kappa, twist, nrhs, in32, out64, 1, gate);
-}
-
 template <typename R, class S, class G>
 static void cg_mp_typed(hipStream_t st, const CgArgs& a, int nr) {
     const Geom& g = a.geo;

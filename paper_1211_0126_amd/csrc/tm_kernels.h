@@ -40,7 +40,7 @@ struct ContractArgs {
     const void* sol;      // native solutions (F64 or F32 storage), or with sol_e the odd halves
     const void* sol_e;    // (nullable) the even halves (FP32 or FP16): the solutions in the half layout of hgeo
     Geom hgeo;            // the half-lattice geometry (with sol_e)
-    const void* dsol;     // est 2: native FP64 D s = (1 - kappa H) s of the same sources
+    const void* dsol;     // est 2: native D s = (1 - kappa H) s of the same sources, in the solutions' precision
     int est;              // 0 eta^dag Gamma s; 1, 2 the one-end loops (Eqs. 5, 6)
     double2 coef;         // factor of every loop element (1; -2i 2 kappa mu; 2)
     const void* gauge64;  // est 3: FP64 links (double2 [4][9][Vs])
@@ -177,9 +177,6 @@ void launch_eo_merge(hipStream_t st, const Geom& g, const Geom& hg, const void* 
 // operator
 void launch_apply(hipStream_t st, const Geom& g, int prec, const void* gauge, double kappa, double twist, int op,
                   int nrhs, const void* in, void* out, int nr, const CgScal* gate);
-void launch_apply_f32in_f64(hipStream_t st, const Geom& g, const void* gauge64, double kappa, double twist, int op,
-                            int nrhs, const void* in32, void* out64, const CgScal* gate);
-
 // CG
 void launch_scal_init(hipStream_t st, CgScal* sc, int n, double tol2, int maxit, int stop, int reliable,
                       double delta2);

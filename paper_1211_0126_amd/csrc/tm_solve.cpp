@@ -1028,24 +1028,25 @@ static void contract_block(tm_ctx* ctx, Contractor* c, const uint64_t* ids_dev, 
     a.out_stride = out_stride;
     const double sb = (double)ctx->geo.V * nrhs * 24.0 * (xprec == P_F64 ? 8 : (xprec == P_F32 ? 4 : 2));
     if (a.est == 2) {
-        // D s = (1 - kappa H) s: the operator at zero twist, FP64 arithmetic
-        // and output on the FP64 links (FP32 solutions promote exactly)
+        // D s = (1 - kappa H) s: the operator at zero twist in the solution's
+        // precision (FP64 links and arithmetic, or FP32 ones)
         const Geom& g = ctx->geo;
         prof_begin(ctx, TM_KC_OTHER);
         if (xprec == P_F64)
             launch_apply(ctx->stream, g, P_F64, ctx->gauge64, ctx->lat.kappa, 0.0, 0, nrhs, x, (void*)a.dsol, 1,
                          nullptr);
         else
-            launch_apply_f32in_f64(ctx->stream, g, ctx->gauge64, ctx->lat.kappa, 0.0, 0, nrhs, x, (void*)a.dsol,
-                                   nullptr);
-        prof_end(ctx, TM_KC_OTHER, sb + (double)g.V * nrhs * 24.0 * 8 + (double)g.V * 144.0 * 8);
+            launch_apply(ctx->stream, g, P_F32, ctx->gauge32, ctx->lat.kappa, 0.0, 0, nrhs, x, (void*)a.dsol,
+                         nrhs % 2 == 0 ? 2 : 1, nullptr);
+        prof_end(ctx, TM_KC_OTHER,
+                 2 * sb + (xprec == P_F64 ? (double)g.V * 144.0 * 8 : (double)g.V * 48.0 * 8));
     }
     prof_begin(ctx, TM_KC_CONTRACT);
     launch_contract(ctx->stream, a, xprec);
     // est 3 reads s at x and its eight neighbours (each reused by eight
     // sites: counted once) and the FP64 links once
     prof_end(ctx, TM_KC_CONTRACT,
-             a.est == 2 ? sb + (double)ctx->geo.V * nrhs * 24.0 * 8
+             a.est == 2 ? 2 * sb
                         : (a.est == 3 ? sb + (double)ctx->geo.V * 4 * 18 * 8 : sb));
 }
 

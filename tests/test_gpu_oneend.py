@@ -79,8 +79,9 @@ def test_oneend_tsm_config0_matches_oracle(orc, est):
 def test_oneend_fp32_solutions(orc, est):
     """LP solves in FP32 storage and arithmetic, stopped after a fixed number
     of iterations, contracted from their FP32 solutions (the generalized loop
-    promotes them to FP64 for D s).  FP32 CG iterates differ from the FP64
-    ones by about k * 1e-7 * cond, so the per-source loops agree to 1e-4."""
+    forms D s in FP32 on the FP32 links).  FP32 CG iterates differ from the
+    FP64 ones by about k * 1e-7 * cond, so the per-source loops agree to
+    1e-4."""
     import paper_1211_0126_amd as tq
     dims = (8, 8, 8, 8)
     kappa, mu = 0.1632, 0.004
