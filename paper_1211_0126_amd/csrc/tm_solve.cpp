@@ -139,9 +139,9 @@ static CgBytes cg_bytes(const Geom& g, int prec, int nrhs, bool reliable_x64, bo
 }
 
 struct BlockResult {
-    void* x;             // the native solutions, or with xe their FP32 odd halves
+    void* x;             // the native solutions, or with xe their odd halves
     int xprec;
-    void* xe = nullptr;  // (halves only) the FP32 even halves
+    void* xe = nullptr;  // (halves only) the even halves, in xprec (FP32, or FP16 for FP16 solves)
 };
 
 // Flexible CG with the network preconditioner for a block of sources; the
@@ -349,8 +349,9 @@ static EoBytes eo_bytes(const Geom& hg, int prec, int nrhs, bool track, bool xfr
 // half-hops per iteration), then x_e = D^{-1} (eta_e + kappa H_eo x_o) and
 // the full native solution in res.  Reliable updates recompute
 // r = b - Mhat^dag Mhat x in FP64 on the half lattice.
-// halves: the caller can take the solution as its two FP32 halves (the
-// standard loop's contraction), which saves writing the full native field
+// halves: the caller can take the solution as its two halves (the standard
+// loop's contraction), FP32, or FP16 for an FP16 solve, which saves writing
+// the full native field
 static tm_status solve_block_eo(tm_ctx* ctx, const tsm_solve_params* p, uint64_t seed_mixed,
                                 const uint64_t* ids_dev, int nrhs, int nr, const std::string& tag,
                                 BlockResult* res, bool halves) {
@@ -1020,7 +1021,7 @@ static void contract_block(tm_ctx* ctx, Contractor* c, const uint64_t* ids_dev, 
     ContractArgs a = c->a;
     a.ids = ids_dev;
     a.sol = x;
-    a.sol_e = xe;  // (x and xe the FP32 halves; standard loop only)
+    a.sol_e = xe;  // (x and xe the two halves in xprec; standard loop only)
     a.hgeo = ctx->hgeo;
     a.nrhs = nrhs;
     a.out = out;
