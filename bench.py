@@ -145,6 +145,14 @@ def kname(v):
     return MARCH_OF.get(k, k) if v.get("tseg", 0) > 0 else k
 
 
+def pick_delta(cands, default=0.1):
+    """The fastest reliable-update trigger among the timed candidates whose
+    sources all converged ({delta: {"ms", "converged", ...}}); `default` if
+    none did."""
+    ok = [d for d, v in cands.items() if v["converged"]]
+    return min(ok, key=lambda d: cands[d]["ms"]) if ok else default
+
+
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -318,8 +326,7 @@ def main():
             cands[delta] = {"ms": round(1e3 * ms, 1), "iters_mean": float(np.mean([s["iters"] for s in st])),
                             "resid_true_max": max(s["resid_true"] for s in st),
                             "converged": all(s["converged"] for s in st)}
-        ok = [d for d in cands if cands[d]["converged"]] or [0.1]
-        tune["hp"]["delta"] = min(ok, key=lambda d: cands[d]["ms"])
+        tune["hp"]["delta"] = pick_delta(cands)
         tune["hp"]["delta_candidates"] = {"%g" % d: v for d, v in cands.items()}
         log("HP delta: %s" % tune["hp"]["delta_candidates"])
     else:

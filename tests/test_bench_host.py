@@ -1,6 +1,6 @@
-"""Host-side logic of bench.py (no GPU): the one-GPU guard, and the HBM
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the HBM
 traffic figures that are reported only for the kernel sources they were
-measured on."""
+measured on, and the choice of the HP reliable-update trigger."""
 
 import json
 import os
@@ -45,3 +45,11 @@ def test_source_hash_depends_on_contents(tmp_path, monkeypatch):
     h1 = bench.kernel_source_sha()
     (src / "a.hip").write_text("y")
     assert bench.kernel_source_sha() != h1
+
+
+def test_trigger_choice_skips_stalled_candidates():
+    import bench
+    cands = {0.1: {"ms": 300.0, "converged": True}, 3e-3: {"ms": 260.0, "converged": True},
+             1e-4: {"ms": 100.0, "converged": False}}
+    assert bench.pick_delta(cands) == 3e-3
+    assert bench.pick_delta({1e-4: {"ms": 1.0, "converged": False}}) == 0.1
