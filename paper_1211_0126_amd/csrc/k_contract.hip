@@ -87,6 +87,36 @@ __device__ __forceinline__ void load_half_spinor_as(const void* base, long Vs, u
     }
 }
 
+// The same from a base address that differs between the lanes of a wave
+// (the two half fields of the even-odd solver): plain global loads with
+// per-lane 64-bit addresses, since a buffer descriptor must be uniform.
+template <class S, typename A>
+__device__ __forceinline__ void load_half_spinor_lane(const void* base, long Vs, uint32_t s, int h, cx<A> p[6]) {
+    static_assert(std::is_same<A, float>::value, "FP32 sums");
+    const uint4* q = (const uint4*)base + s;
+    if constexpr (std::is_same<S, SF16>::value) {
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            const int pl = (6 * h) / 4 + k;
+            const uint4 v = q[(size_t)pl * Vs];
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const int c = 4 * pl + j - 6 * h;
+                if (c >= 0 && c < 6) p[c] = {f16_to_f32(w[j] & 0xFFFFu), f16_to_f32(w[j] >> 16)};
+            }
+        }
+    } else {
+        static_assert(std::is_same<S, SF32>::value, "FP32 or FP16 halves");
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            const float4 v = __builtin_bit_cast(float4, q[(size_t)(3 * h + k) * Vs]);
+            p[2 * k] = {v.x, v.y};
+            p[2 * k + 1] = {v.z, v.w};
+        }
+    }
+}
+
 // conj(i^k) p for a Z4 noise component i^k: a permutation and signs
 template <typename A>
 __device__ __forceinline__ cx<A> z4_conj_times(uint32_t k, cx<A> p) {
@@ -138,7 +168,7 @@ __global__ __launch_bounds__(256) void k_contract_a(ContractArgs a) {
             cx<A> p[6];
             if constexpr (HALVES) {
                 const uint32_t hs = s >> 1;  // x/2 + (Lx/2)(y + Ly(z + Lz t)): Lx is even
-                load_half_spinor_as<S, A>(((x + y + z + t) & 1) ? sol : sol_e, a.hgeo.Vs, hs, h, p);
+                load_half_spinor_lane<S, A>(((x + y + z + t) & 1) ? sol : sol_e, a.hgeo.Vs, hs, h, p);
             } else {
                 load_half_spinor_as<S, A>(sol, g.Vs, s, h, p);
             }
