@@ -36,6 +36,16 @@
 
 namespace tmq {
 
+// Plane `plane` of site s where the plane may differ between the lanes of a
+// wave (the spin half h of a lane): its offset goes into the per-lane
+// offset of the buffer load, not the scalar one (plane * Vs * 16 < 2^32, as
+// tm_create bounds Vs).
+template <typename T>
+__device__ __forceinline__ T ld_plane_lane(const void* base, long Vs, int plane, uint32_t s) {
+    const uint32_t off = (s << 4) + (uint32_t)plane * (uint32_t)Vs * 16u;
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(rsrc_of(base), off, 0u, 0));
+}
+
 // load the six components of spin rows 2h, 2h+1
 template <class S>
 __device__ __forceinline__ void load_half_spinor(const void* base, long Vs, uint32_t s, int h, cx<double> p[6]);
@@ -44,7 +54,7 @@ template <>
 __device__ __forceinline__ void load_half_spinor<SF64>(const void* base, long Vs, uint32_t s, int h, cx<double> p[6]) {
 #pragma unroll
     for (int k = 0; k < 6; k++) {
-        double2 v = ld_plane<double2>(base, Vs, 6 * h + k, s);
+        double2 v = ld_plane_lane<double2>(base, Vs, 6 * h + k, s);
         p[k] = {v.x, v.y};
     }
 }
@@ -52,7 +62,7 @@ template <>
 __device__ __forceinline__ void load_half_spinor<SF32>(const void* base, long Vs, uint32_t s, int h, cx<double> p[6]) {
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        float4 v = ld_plane<float4>(base, Vs, 3 * h + k, s);
+        float4 v = ld_plane_lane<float4>(base, Vs, 3 * h + k, s);
         p[2 * k] = {(double)v.x, (double)v.y};
         p[2 * k + 1] = {(double)v.z, (double)v.w};
     }
@@ -68,7 +78,7 @@ __device__ __forceinline__ void load_half_spinor_as(const void* base, long Vs, u
         // components 6h .. 6h + 5 of the planes of four packed pairs
 #pragma unroll
         for (int k = 0; k < 2; k++) {
-            const uint4 v = ld_plane<uint4>(base, Vs, (6 * h) / 4 + k, s);
+            const uint4 v = ld_plane_lane<uint4>(base, Vs, (6 * h) / 4 + k, s);
             const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
             for (int j = 0; j < 4; j++) {
@@ -80,7 +90,7 @@ __device__ __forceinline__ void load_half_spinor_as(const void* base, long Vs, u
         static_assert(std::is_same<S, SF32>::value, "FP32 sums read FP32 or FP16 solutions");
 #pragma unroll
         for (int k = 0; k < 3; k++) {
-            float4 v = ld_plane<float4>(base, Vs, 3 * h + k, s);
+            float4 v = ld_plane_lane<float4>(base, Vs, 3 * h + k, s);
             p[2 * k] = {v.x, v.y};
             p[2 * k + 1] = {v.z, v.w};
         }
